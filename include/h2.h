@@ -1,0 +1,168 @@
+/*
+ * h2.h - C ABI of libh2mi, an accuracy-controlled H^2 direct solver for AMD
+ * MI355X (gfx950).
+ *
+ * The solver implements the level-by-level factorization of a general
+ * H^2-matrix of Ma & Jiao, "Accuracy Directly Controlled Fast Direct
+ * Solutions of General H^2-Matrices and Its Application to Electrically
+ * Large Integral-Equation-Based Electromagnetic Analysis" (arXiv:1703.06155):
+ * at every tree level each cluster's basis is updated with the fill-ins to a
+ * prescribed accuracy (Sec. III-A-2, eqs. 16-18 / 25-27), zeros are
+ * introduced with [V_perp V]^H from both sides (eqs. 5-8 / 30), a partial LU
+ * of the rank-sized diagonal block is taken and its Schur complement is
+ * applied to the coupled blocks (eqs. 9-15 / 31-32), level after level up to
+ * the coarsest admissible level l0 (Alg. 1); the factors Z = L U of eq. 34
+ * are then applied by the substitution sweeps of Sec. IV (Algs. 5-6).
+ *
+ * The matrix is the one of a volume integral equation on N cells:
+ *   A_ij = k^2 chi_j h^3 e^{-jkr_ij} / (4 pi r_ij)   (i != j),
+ *   A_ii = 1 + chi_i ((1 + jka) e^{-jka} - 1),  a = (3 / (4 pi))^{1/3} h.
+ * A = Z D with D = diag(k^2 h^3 chi) and Z complex symmetric; the library
+ * factors Z, whose single cluster basis per cluster serves rows and columns
+ * as the paper's eqs. 2, 5, 7-8 and 16 require, and solves A x = b as
+ * Z y = b, x = D^-1 y.
+ *
+ * Conventions for every call:
+ *   - complex vectors are interleaved (re, im) doubles ("c128"), column-major
+ *     with leading dimension ld >= n, in the caller's point order;
+ *   - vector arguments (b, x, g, lam, y) are DEVICE pointers; points and
+ *     contrast are HOST pointers, copied during the call;
+ *   - hip_stream is a hipStream_t (NULL = the default stream); all device work
+ *     of a call is enqueued on it;
+ *   - no call throws; every call returns an h2_status and, on failure, sets a
+ *     thread-local message readable with h2_last_error();
+ *   - arguments are validated before any device work, so argument errors are
+ *     reported without touching a GPU;
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef H2MI_H
+#define H2MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct h2_ctx* h2_handle;
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_ARG = 1,       /* invalid argument (null pointer, size, range, non-finite) */
+  H2_ERR_OOM = 2,       /* device allocation failed */
+  H2_ERR_SINGULAR = 3,  /* zero pivot in a partial or final LU */
+  H2_ERR_STATE = 4,     /* call out of order (e.g. solve before factor) */
+  H2_ERR_DEVICE = 5,    /* no usable gfx950 device, or a HIP runtime error */
+  H2_ERR_NOCONV = 6,    /* refinement did not reach tol within max_iter */
+  H2_ERR_INTERNAL = 7   /* size beyond a kernel limit, or an internal invariant broke */
+} h2_status;
+
+enum { H2_FP64 = 0, H2_MIXED = 1 };
+enum { H2_ORDER_COLOR = 0 };
+
+typedef struct {
+  size_t struct_size;          /* sizeof(h2_options); guards ABI growth */
+  int32_t precision;           /* H2_FP64 (default) or H2_MIXED (complex64 Schur and
+                                  projection GEMMs, FP64 everything else) */
+  int32_t order;               /* H2_ORDER_COLOR: clusters of one colour of a level's
+                                  inadmissible graph are eliminated together */
+  double eps_fill;             /* Step 0 truncation (eqs. 17, 26); <= 0: use eps */
+  const int32_t* forced_ranks; /* optional host array pinning rank decisions, layout in
+                                  h2_forced_ranks_layout(); NULL: decide from eps */
+  int64_t forced_ranks_len;    /* number of int32 entries behind forced_ranks */
+} h2_options;
+
+typedef struct {
+  int32_t iterations;          /* refinement steps taken (0 for a plain solve) */
+  double rel_residual;         /* ||b - A_H2 x|| / ||b|| after the last step (column max) */
+  double rel_residual_first;   /* the same after the first solve */
+} h2_solve_info;
+
+/* Build the H^2 representation of Z (Sec. II, eqs. 1-3) on the device.
+ *   points   host, n x 3 row-major cell centres (distinct);
+ *   k, h     wavenumber and cell edge (> 0);
+ *   contrast host, n real values, each finite and > 0;
+ *   leaf     maximum leaf cluster size (>= 1); eta >= 0 admissibility
+ *            parameter of eq. 1; eps in (0,1) truncation of the nested bases
+ *            (sigma_j > eps * sigma_1 of each far-field block row).
+ * The cluster tree bisects every cluster at the midpoint of its bounding
+ * box's longest side until all leaves hold <= leaf points; eq. 1 is tested on
+ * cell-support boxes (centres +- h/2).  On success *out owns all device
+ * memory of the problem; release it with h2_destroy.  Synchronises the stream. */
+h2_status h2_build(const double* points, int64_t n, double k, double h, const double* contrast,
+                   int32_t leaf, double eta, double eps, const h2_options* opt,
+                   void* hip_stream, h2_handle* out);
+
+/* Factor Z = L U in the product form of eq. 34 (Alg. 1 with Steps 0-3 per
+ * cluster, Algs. 2-4; coupling/transfer updates eqs. 20-23 / 33; final LU of
+ * the level-(l0-1) block).  Synchronises once per level to size the next
+ * level's storage.  H2_ERR_SINGULAR leaves the handle unfactored. */
+h2_status h2_factor(h2_handle H, void* hip_stream);
+
+/* x = M^-1 b for nrhs columns (forward sweep Alg. 5, backward sweep Alg. 6;
+ * eqs. 37, 41), where M = L U D approximates A.  With tol > 0 iterative
+ * refinement x += M^-1 (b - A_H2 x) runs until the relative residual against
+ * the H^2-represented matrix A_H2 = Z_H2 D (the accuracy measure of the
+ * paper's Sec. VI-B) is <= tol for every column, at most max_iter steps
+ * (H2_ERR_NOCONV otherwise, x holding the last iterate).  b and x may alias.
+ * Without refinement the call is asynchronous; info may be NULL. */
+h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
+                   int32_t max_iter, void* hip_stream, h2_solve_info* info);
+
+/* lam = M^-H g: the conjugate transposes of the sweeps of eq. 35 applied in
+ * reverse order over the same factors (the exact adjoint of the computed
+ * solve).  g and lam may alias.  Asynchronous. */
+h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld,
+                           void* hip_stream);
+
+/* y = A_H2 x (conj_transpose = 0) or y = A_H2^H x (conj_transpose = 1), with
+ * the inadmissible leaf blocks and V_t S_ts V_s^T (eq. 2) applied through the
+ * nested bases (eq. 3).  x and y must not alias.  Asynchronous. */
+h2_status h2_matvec(h2_handle H, const void* x, void* y, int32_t nrhs, int64_t ld,
+                    int32_t conj_transpose, void* hip_stream);
+
+/* Release every resource of H (NULL is ignored). */
+void h2_destroy(h2_handle H);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* h2_last_error(void);
+
+/* Host-only structure query (no device is touched): builds the cluster tree,
+ * block partition and colouring exactly as h2_build does.  counts receives 8
+ * int64 values: N, L, l0 (-1 if no admissible block), leaves, leaf_min,
+ * leaf_max, admissible pairs at the leaf level, inadmissible pairs at the
+ * leaf level.  perm (nullable, n entries) receives the tree order of the
+ * points; colours (nullable, leaves entries) the leaf colours. */
+h2_status h2_structure(const double* points, int64_t n, double h, int32_t leaf, double eta,
+                       int64_t* counts, int64_t* perm, int32_t* colours);
+
+/* Per-level statistics after h2_factor, written as rows of int64:
+ *   level, clusters, sum n, max n, sum k, max k, sum k~, max k~, min k~, eliminated.
+ * rows_cap is the number of rows out can hold; *rows receives the count.
+ * The final dense block is reported as one more row with level = l0 - 1. */
+h2_status h2_stats(h2_handle H, int64_t* out, int32_t rows_cap, int32_t* rows);
+
+/* Rank decisions of the last build/factor as (level, cluster, k, k~) int32
+ * quadruples for every nonempty cluster of every factored level, finest level
+ * first; this array (length 4 * *count) is also the forced_ranks format:
+ * passing it back pins both the construction rank k and the factor rank k~
+ * of each listed cluster.  cap is in quadruples. */
+h2_status h2_forced_ranks_layout(h2_handle H, int32_t* out, int64_t cap, int64_t* count);
+
+/* Timing (milliseconds) of the phases of the last h2_factor, measured with
+ * HIP events on its stream: out[0] total, out[1] basis update and
+ * projection (Steps 0-2), out[2] partial LU and panels, out[3] Schur
+ * updates (eq. 12), out[4] level merges, out[5] final LU; n_out >= 6.
+ * With n_out >= 10 the algorithmic ledger follows, computed from the actual
+ * ranks: out[6] Schur flops (8 (sum m_a)^2 r per cluster, complex),
+ * out[7] number of Schur launches (one per colour and level), out[8] flops of
+ * the whole factorization, out[9] Schur bytes (blocks read and written once,
+ * panels read once). */
+h2_status h2_factor_timing(h2_handle H, double* out, int32_t n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2MI_H */

@@ -1,0 +1,245 @@
+"""Accuracy-controlled H^2 direct solver for AMD MI355X.
+
+Thin ctypes binding of ``libh2mi.so`` (the C ABI declared in ``include/h2.h``):
+argument marshalling only.  Every step of construction, factorization and the
+sweeps runs in the library's gfx950 kernels; PyTorch provides device memory and
+the stream.  The library is built in-tree by ``__graft_entry__.build()``; when
+it is missing the binding raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2mi.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "h2.h")
+
+H2_OK, H2_ERR_ARG, H2_ERR_OOM, H2_ERR_SINGULAR, H2_ERR_STATE, H2_ERR_DEVICE, H2_ERR_NOCONV, H2_ERR_INTERNAL = range(8)
+STATUS_NAMES = ["H2_OK", "H2_ERR_ARG", "H2_ERR_OOM", "H2_ERR_SINGULAR", "H2_ERR_STATE", "H2_ERR_DEVICE",
+                "H2_ERR_NOCONV", "H2_ERR_INTERNAL"]
+H2_FP64, H2_MIXED = 0, 1
+
+
+class H2Error(RuntimeError):
+    def __init__(self, status: int, message: str, call: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{call}: {name}: {message}")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("precision", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("eps_fill", ctypes.c_double), ("forced_ranks", ctypes.POINTER(ctypes.c_int32)),
+                ("forced_ranks_len", ctypes.c_int64)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("rel_residual_first", ctypes.c_double)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    """The loaded libh2mi; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.h2_build.argtypes = [_DP, ctypes.c_int64, ctypes.c_double, ctypes.c_double, _DP, ctypes.c_int32,
+                               ctypes.c_double, ctypes.c_double, ctypes.POINTER(Options), _P, ctypes.POINTER(_P)]
+        L.h2_factor.argtypes = [_P, _P]
+        L.h2_solve.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P,
+                               ctypes.POINTER(SolveInfo)]
+        L.h2_solve_adjoint.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, _P]
+        L.h2_matvec.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P]
+        L.h2_destroy.argtypes = [_P]
+        L.h2_destroy.restype = None
+        L.h2_last_error.argtypes = []
+        L.h2_last_error.restype = ctypes.c_char_p
+        L.h2_structure.argtypes = [_DP, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _I64P,
+                                   _I64P, _I32P]
+        L.h2_stats.argtypes = [_P, _I64P, ctypes.c_int32, _I32P]
+        L.h2_forced_ranks_layout.argtypes = [_P, _I32P, ctypes.c_int64, _I64P]
+        L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
+        for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
+                     "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> list:
+    """Function names declared by include/h2.h."""
+    with open(HEADER) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^\s*(?:h2_status|void|const char\*)\s+(h2_\w+)\s*\(", src, re.M)))
+
+
+def _check(status: int, call: str):
+    if status != H2_OK:
+        raise H2Error(status, lib().h2_last_error().decode(errors="replace"), call)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def structure(points, h: float, leaf: int, eta: float) -> dict:
+    """Host-only tree / partition / colouring summary (no device touched)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    counts = np.zeros(8, np.int64)
+    perm = np.zeros(n, np.int64)
+    _check(lib().h2_structure(_dptr(pts), n, float(h), int(leaf), float(eta), counts.ctypes.data_as(_I64P),
+                              perm.ctypes.data_as(_I64P), None), "h2_structure")
+    cols = np.zeros(int(counts[3]), np.int32)
+    _check(lib().h2_structure(_dptr(pts), n, float(h), int(leaf), float(eta), counts.ctypes.data_as(_I64P), None,
+                              cols.ctypes.data_as(_I32P)), "h2_structure")
+    keys = ["N", "L", "l0", "leaves", "leaf_min", "leaf_max", "adm_leaf", "near_leaf"]
+    out = {k: int(v) for k, v in zip(keys, counts)}
+    out["perm"] = perm
+    out["colours"] = cols
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_cols(x, n: int):
+    """complex128 device tensor -> (column-major buffer (nrhs, n) contiguous, nrhs, was_vector)."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.asarray(x))
+    x = x.to(device="cuda", dtype=torch.complex128)
+    vec = x.dim() == 1
+    if vec:
+        x = x.reshape(n, 1)
+    if x.shape[0] != n:
+        raise ValueError(f"expected {n} rows, got {tuple(x.shape)}")
+    return x.t().contiguous(), x.shape[1], vec
+
+
+def _from_cols(buf, vec: bool):
+    return buf[0] if vec else buf.t()
+
+
+class H2:
+    """An H^2 representation of the VIE matrix A = Z D on the device, and its factorization.
+
+    Parameters follow h2_build: cell centres ``points`` (N x 3), wavenumber ``k``,
+    cell size ``h``, per-cell contrast ``chi`` (> 0), leaf size, admissibility
+    ``eta`` and construction accuracy ``eps``; ``eps_fill`` (default eps) controls
+    the basis updates of the factorization; ``forced_ranks`` pins rank decisions
+    (the format of :meth:`forced_ranks`).
+    """
+
+    def __init__(self, points, k, h, chi, leaf, eta, eps, eps_fill=None, precision="fp64", forced_ranks=None,
+                 stream=None):
+        pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+        chi = np.ascontiguousarray(chi, dtype=np.float64).reshape(-1)
+        self.n = pts.shape[0]
+        self.k, self.h, self.leaf, self.eta, self.eps = float(k), float(h), int(leaf), float(eta), float(eps)
+        self.chi = chi.copy()
+        self._forced = None
+        opt = Options()
+        opt.struct_size = ctypes.sizeof(Options)
+        opt.precision = H2_MIXED if precision == "mixed" else H2_FP64
+        opt.order = 0
+        opt.eps_fill = float(eps_fill) if eps_fill else 0.0
+        if forced_ranks is not None:
+            self._forced = np.ascontiguousarray(forced_ranks, dtype=np.int32).reshape(-1)
+            opt.forced_ranks = self._forced.ctypes.data_as(_I32P)
+            opt.forced_ranks_len = self._forced.size
+        self._h = ctypes.c_void_p()
+        st = _stream_ptr(stream)
+        _check(lib().h2_build(_dptr(pts), self.n, self.k, self.h, _dptr(chi), self.leaf, self.eta, self.eps,
+                              ctypes.byref(opt), st, ctypes.byref(self._h)), "h2_build")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().h2_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self, stream=None):
+        _check(lib().h2_factor(self._h, _stream_ptr(stream)), "h2_factor")
+        return self
+
+    def solve(self, b, tol=0.0, max_iter=20, stream=None, info=False):
+        buf, nrhs, vec = _as_cols(b, self.n)
+        out = _torch().empty_like(buf)
+        si = SolveInfo()
+        _check(lib().h2_solve(self._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr()), nrhs,
+                              self.n, float(tol), int(max_iter), _stream_ptr(stream), ctypes.byref(si)), "h2_solve")
+        x = _from_cols(out, vec)
+        if info:
+            return x, {"iterations": si.iterations, "rel_residual": si.rel_residual,
+                       "rel_residual_first": si.rel_residual_first}
+        return x
+
+    def solve_adjoint(self, g, stream=None):
+        buf, nrhs, vec = _as_cols(g, self.n)
+        out = _torch().empty_like(buf)
+        _check(lib().h2_solve_adjoint(self._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      nrhs, self.n, _stream_ptr(stream)), "h2_solve_adjoint")
+        return _from_cols(out, vec)
+
+    def matvec(self, x, adjoint=False, stream=None):
+        buf, nrhs, vec = _as_cols(x, self.n)
+        out = _torch().empty_like(buf)
+        _check(lib().h2_matvec(self._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr()), nrhs,
+                               self.n, 1 if adjoint else 0, _stream_ptr(stream)), "h2_matvec")
+        return _from_cols(out, vec)
+
+    def stats(self) -> np.ndarray:
+        rows = ctypes.c_int32()
+        buf = np.zeros(64 * 10, np.int64)
+        _check(lib().h2_stats(self._h, buf.ctypes.data_as(_I64P), 64, ctypes.byref(rows)), "h2_stats")
+        return buf[:rows.value * 10].reshape(-1, 10)
+
+    def forced_ranks(self) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check(lib().h2_forced_ranks_layout(self._h, None, 0, ctypes.byref(cnt)), "h2_forced_ranks_layout")
+        out = np.zeros(4 * cnt.value, np.int32)
+        _check(lib().h2_forced_ranks_layout(self._h, out.ctypes.data_as(_I32P), cnt.value, ctypes.byref(cnt)),
+               "h2_forced_ranks_layout")
+        return out.reshape(-1, 4)
+
+    def timing(self) -> np.ndarray:
+        """[total, steps 0-2, LU + panels, Schur, merges, final LU] ms, then the ledger:
+        Schur flops, Schur launches, factor flops, Schur bytes."""
+        out = np.zeros(10)
+        _check(lib().h2_factor_timing(self._h, _dptr(out), 10), "h2_factor_timing")
+        return out
+
+
+def forced_ranks_from_oracle(construct_ranks: dict, factor_ranks: dict) -> np.ndarray:
+    """(level, cluster, k, k~) rows from {(l, t): k} and {(l, i): k~} dictionaries, in the
+    library's order (finest level first, clusters ascending)."""
+    keys = sorted(construct_ranks, key=lambda lt: (-lt[0], lt[1]))
+    rows = [(l, t, construct_ranks[(l, t)], factor_ranks.get((l, t), -1)) for (l, t) in keys]
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 4)

@@ -1,0 +1,259 @@
+// Device building blocks for gfx950: complex helpers, wavefront reductions and
+// the 64x64 complex MFMA tile engine used by every batched contraction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "h2_kernels.hpp"
+
+namespace h2 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct cplx_t;
+template <>
+struct cplx_t<double> {
+  typedef double2 type;
+};
+template <>
+struct cplx_t<float> {
+  typedef float2 type;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Workgroup-wide sum for 256 threads; `red` holds >= 4 doubles of LDS.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------------------
+// MFMA wrappers.  The operands are passed swapped (B fragment first) so that
+// the 16x16 accumulator holds C^T, i.e. 16 consecutive rows of a column-major
+// C per quarter wave: lane l, element v <-> C(row = l % 16, col = acc_col(l, v)).
+// The accumulator's row order differs between the two instructions (measured
+// on gfx950): f64 16x16x4 interleaves rows as l / 16 + 4 v, f32 16x16x4
+// blocks them as 4 (l / 16) + v.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename R>
+__device__ __forceinline__ int acc_col(int lane, int v);
+template <>
+__device__ __forceinline__ int acc_col<double>(int lane, int v) {
+  return (lane >> 4) + 4 * v;
+}
+template <>
+__device__ __forceinline__ int acc_col<float>(int lane, int v) {
+  return 4 * (lane >> 4) + v;
+}
+
+template <typename R>
+struct acc_t;
+template <>
+struct acc_t<double> {
+  typedef d4 type;
+};
+template <>
+struct acc_t<float> {
+  typedef f4 type;
+};
+
+
+constexpr int TM = 64;   // tile rows
+constexpr int TN = 64;   // tile cols
+constexpr int TK = 16;   // k step
+constexpr int TPAD = 1;  // LDS row padding (elements)
+
+template <typename R>
+struct TileSmem {
+  R are[TK][TM + TPAD];
+  R aim[TK][TM + TPAD];
+  R bre[TK][TN + TPAD];
+  R bim[TK][TN + TPAD];
+};
+
+template <typename R>
+struct TileAcc {
+  typename acc_t<R>::type re[2][2], im[2][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        re[t][u] = typename acc_t<R>::type{0, 0, 0, 0};
+        im[t][u] = typename acc_t<R>::type{0, 0, 0, 0};
+      }
+  }
+};
+
+// Load a 64 x TK tile of op(A) (rows [0, m), k in [k0, k0 + TK) of K) into LDS.
+// A points at element (0, 0) of op(A)'s row/col origin in storage.
+template <typename R, typename CT>
+__device__ __forceinline__ void load_a(TileSmem<R>& s, const CT* __restrict__ A, int64_t lda, int op,
+                                       int m, int K, int k0) {
+  const int t = threadIdx.x;
+  if (op == OP_N || op == OP_R) {
+    const int i = t & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = (t >> 6) + 4 * e;
+      const int k = k0 + kk;
+      CT v{0, 0};
+      if (i < m && k < K) v = A[i + (int64_t)k * lda];
+      s.are[kk][i] = v.x;
+      s.aim[kk][i] = (op == OP_R) ? -v.y : v.y;
+    }
+  } else {
+    const int kk = t & 15;
+    const int k = k0 + kk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = (t >> 4) + 16 * e;
+      CT v{0, 0};
+      if (i < m && k < K) v = A[k + (int64_t)i * lda];
+      s.are[kk][i] = v.x;
+      s.aim[kk][i] = (op == OP_C) ? -v.y : v.y;
+    }
+  }
+}
+
+// Load a TK x 64 tile of op(B) (k in [k0, k0 + TK), cols [0, n)) into LDS.
+template <typename R, typename CT>
+__device__ __forceinline__ void load_b(TileSmem<R>& s, const CT* __restrict__ B, int64_t ldb, int op,
+                                       int n, int K, int k0) {
+  const int t = threadIdx.x;
+  if (op == OP_N || op == OP_R) {
+    const int kk = t & 15;
+    const int k = k0 + kk;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = (t >> 4) + 16 * e;
+      CT v{0, 0};
+      if (j < n && k < K) v = B[k + (int64_t)j * ldb];
+      s.bre[kk][j] = v.x;
+      s.bim[kk][j] = (op == OP_R) ? -v.y : v.y;
+    }
+  } else {
+    const int j = t & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = (t >> 6) + 4 * e;
+      const int k = k0 + kk;
+      CT v{0, 0};
+      if (j < n && k < K) v = B[j + (int64_t)k * ldb];
+      s.bre[kk][j] = v.x;
+      s.bim[kk][j] = (op == OP_C) ? -v.y : v.y;
+    }
+  }
+}
+
+// acc += op(A_tile) * op(B_tile) for one TK slab resident in LDS.
+template <typename R>
+__device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kq = 0; kq < TK / 4; ++kq) {
+    const int kk = kq * 4 + lk;
+    R ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ar[t] = s.are[kk][wr * 32 + t * 16 + li];
+      ai[t] = s.aim[kk][wr * 32 + t * 16 + li];
+      nai[t] = -ai[t];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      br[u] = s.bre[kk][wc * 32 + u * 16 + li];
+      bi[u] = s.bim[kk][wc * 32 + u * 16 + li];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        // C^T = op(B)^T op(A)^T : pass the B fragment as the MFMA's first operand
+        acc.re[t][u] = mfma16(br[u], ar[t], acc.re[t][u]);
+        acc.re[t][u] = mfma16(bi[u], nai[t], acc.re[t][u]);
+        acc.im[t][u] = mfma16(br[u], ai[t], acc.im[t][u]);
+        acc.im[t][u] = mfma16(bi[u], ar[t], acc.im[t][u]);
+      }
+  }
+}
+
+// acc += op(A)[0:m, 0:K] * op(B)[0:K, 0:n] (m, n <= 64).
+template <typename R, typename CT>
+__device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const CT* A, int64_t lda,
+                                          int opA, const CT* B, int64_t ldb, int opB, int m, int n,
+                                          int K) {
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    __syncthreads();
+    load_a<R, CT>(s, A, lda, opA, m, K, k0);
+    load_b<R, CT>(s, B, ldb, opB, n, K, k0);
+    __syncthreads();
+    mma_slab<R>(s, acc);
+  }
+}
+
+
+// C[0:m, 0:n] (op)= acc, C column-major with leading dimension ldc.
+template <typename R, typename CT>
+__device__ __forceinline__ void store_tile(const TileAcc<R>& acc, CT* C, int64_t ldc, int m, int n,
+                                           int mode) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + t * 16 + (lane & 15);
+        const int j = wc * 32 + u * 16 + acc_col<R>(lane, v);
+        if (i < m && j < n) {
+          CT* p = C + i + (int64_t)j * ldc;
+          R xr = acc.re[t][u][v], xi = acc.im[t][u][v];
+          if (mode == ST_SET) {
+            *p = CT{xr, xi};
+          } else {
+            CT o = *p;
+            if (mode == ST_ADD)
+              *p = CT{o.x + xr, o.y + xi};
+            else
+              *p = CT{o.x - xr, o.y - xi};
+          }
+        }
+      }
+}
+
+}  // namespace h2

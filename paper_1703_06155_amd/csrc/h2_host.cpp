@@ -1,0 +1,1807 @@
+// Host orchestration and C ABI of libh2mi.
+//
+// h2_build: structure (tree, partition, colouring), task plans, and the H^2
+//   construction on the device (far-field Grams -> Hermitian eigensolver ->
+//   nested bases, couplings, inadmissible leaf blocks).
+// h2_factor: Alg. 1 level by level; within a level clusters of one colour
+//   take Steps 0-3 together; one host synchronisation per level reads the
+//   ranks k~ that size the next level.
+// h2_solve / h2_solve_adjoint / h2_matvec: the sweeps of Sec. IV, their
+//   adjoint, and the H^2 product, all on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <climits>
+#include <iterator>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/h2.h"
+#include "h2_kernels.hpp"
+#include "h2_structure.hpp"
+
+namespace h2 {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+struct Fail {
+  h2_status st;
+  std::string msg;
+};
+
+[[noreturn]] static void fail(h2_status st, const std::string& m) { throw Fail{st, m}; }
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) {                                                            \
+      if (e_ == hipErrorOutOfMemory) fail(H2_ERR_OOM, std::string("device allocation: ") + #x); \
+      fail(H2_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));             \
+    }                                                                                  \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DArr {
+  T* p = nullptr;
+  size_t n = 0;
+  DArr() = default;
+  DArr(const DArr&) = delete;
+  DArr& operator=(const DArr&) = delete;
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DArr& operator=(DArr&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DArr() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t cnt) {
+    release();
+    if (cnt == 0) cnt = 1;
+    HIPCHK(hipMalloc((void**)&p, cnt * sizeof(T)));
+    n = cnt;
+  }
+  // blocking: the host vector may be a temporary
+  void upload(const std::vector<T>& v, hipStream_t st) {
+    alloc(v.size());
+    if (!v.empty()) {
+      HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+struct ColourPlan {
+  std::vector<int32_t> cl, pj_slot, sc_slot, sc_cptr, sc_i, sc_ja, sc_jb, pn_i, pn_ja, sv_cl, sv_cptr, sv_i,
+      sv_ja;
+  DArr<int32_t> d_cl, d_pj_slot, d_sc_slot, d_sc_cptr, d_sc_i, d_sc_ja, d_sc_jb, d_pn_i, d_pn_ja, d_sv_cl,
+      d_sv_cptr, d_sv_i, d_sv_ja;
+  DArr<int64_t> d_pj_toff;
+  std::vector<int64_t> pj_toff;
+  int64_t temp_elems = 0;
+};
+
+struct MergeSrc {  // rank-independent part of a merge task
+  int32_t pslot;   // parent slot (or parent pair index for the final dense block)
+  int32_t ci, dj;  // which child of the parent row / column cluster
+  int32_t kind, slot, adm;  // kind 0 near / 1 admissible (adm = pair index) / 2 fill
+  int32_t ca, cb;
+};
+
+struct LevelPlan {
+  int l = 0, nc = 0, ncol = 0, nnear = 0, nslot = 0;
+  std::vector<int32_t> colour, nonempty, slot_a, slot_b, diag_slot;
+  std::vector<int32_t> np_ptr, np_cl, np_srow, np_scol;
+  std::vector<int32_t> fp_ptr, fp_cl, fp_srow;
+  std::vector<ColourPlan> cols;
+  std::vector<MergeSrc> merge;  // into level l-1 (slots) or the final dense block
+  // device copies of the static lists
+  DArr<int32_t> d_colour, d_nonempty, d_slot_a, d_slot_b, d_diag_slot, d_np_ptr, d_np_cl, d_np_srow, d_np_scol,
+      d_fp_ptr, d_fp_cl, d_fp_srow;
+  // row-wise slot lookup: for cluster a, (b, slot) sorted by b
+  std::vector<int32_t> rl_ptr, rl_b, rl_slot;
+  int slot_of(int a, int b) const {
+    auto beg = rl_b.begin() + rl_ptr[a], end = rl_b.begin() + rl_ptr[a + 1];
+    auto it = std::lower_bound(beg, end, b);
+    if (it == end || *it != b) return -1;
+    return rl_slot[it - rl_b.begin()];
+  }
+};
+
+// construction data of one level (l0 <= l <= L)
+struct BuildLevel {
+  std::vector<int32_t> k;       // ranks
+  std::vector<double> nu;       // sigma_1 of the far-field row
+  std::vector<double> margin;   // per cluster (sigma_k/thr, sigma_{k+1}/thr)
+  std::vector<int64_t> boff;    // basis (leaf V: #t x k; non-leaf T: (k1+k2) x k)
+  DArr<double2> basis;
+  std::vector<int64_t> voff;    // expanded basis #t x k
+  DArr<double2> V;
+  std::vector<int64_t> soff;    // couplings for S.adm[l] (k_t x k_s)
+  DArr<double2> S;
+  DArr<int64_t> d_voff, d_soff;
+  DArr<int32_t> d_k, d_rows;    // k per cluster, #t per cluster
+  DArr<int32_t> d_cptr, d_ccol; // admissible CSR by row cluster (into S.adm order)
+  DArr<int64_t> d_cstart, d_xoff;  // cluster starts (tree order), xhat offsets
+  DArr<double> d_nu;
+  int64_t ktot = 0;             // sum of k
+};
+
+// factor data of one level (kept for the sweeps)
+struct FactorLevel {
+  std::vector<int32_t> n, kt;
+  int64_t ntot = 0;
+  DArr<int32_t> d_n, d_k, d_kt, d_forced, d_np_off, d_prow, d_flags;
+  DArr<int64_t> d_slot_off, d_q_off, d_b_off, d_bp_off, d_lu_off, d_cp_off, d_rp_off, d_w_off, d_voff;
+  DArr<double> d_margins;
+  DArr<double2> Q, LU, CP, RP, B;
+  std::vector<int64_t> voff;
+  LevelView view{};
+  int tiles = 1;
+};
+
+}  // namespace h2
+
+struct h2_ctx {
+  h2::Structure S;
+  int64_t N = 0;
+  double k = 0, h = 0, eta = 0, eps = 0, eps_fill = 0;
+  int leaf = 0, precision = H2_FP64;
+  std::vector<double> chi_tree;
+  std::vector<int32_t> forced_k, forced_kt;  // flattened per level: offset lvl_base[l]
+  std::vector<int64_t> lvl_base;
+  bool has_forced = false;
+  // device geometry
+  h2::DArr<double> d_pts, d_chi, d_scale_solve, d_scale_mat;
+  h2::DArr<int32_t> d_leafid;
+  h2::DArr<int64_t> d_perm;
+  h2::GeomView geom{};
+  // plans and construction
+  std::vector<h2::LevelPlan> plans;        // index L - l
+  std::vector<h2::BuildLevel> build;       // index L - l
+  h2::DArr<double2> near_orig;             // inadmissible leaf blocks (S.near[L] order)
+  std::vector<int64_t> near_off;
+  h2::DArr<int64_t> d_near_off, d_leaf_start;
+  h2::DArr<int32_t> d_near_ptr, d_near_col, d_leaf_size;
+  // factorization
+  bool factored = false;
+  std::vector<h2::FactorLevel> flev;       // index L - l
+  int64_t nf = 0;
+  std::vector<int32_t> final_off;          // per cluster of level l0-1
+  h2::DArr<double2> Zf, Zinv;
+  std::vector<double> timing;
+  std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
+  // sweep workspace
+  std::vector<h2::DArr<double2>> vbuf;
+  h2::DArr<double2> vtmp, vtmp2, vtmp3;
+  int vbuf_nrhs = 0;
+  h2::DArr<double> d_norms;
+  std::vector<std::vector<int64_t>> stats_rows;
+};
+
+namespace h2 {
+
+static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
+  const Structure& S = H->S;
+  P.l = l;
+  P.nc = S.nclusters(l);
+  const int nc = P.nc;
+  P.colour.assign(S.colour[l].begin(), S.colour[l].end());
+  P.ncol = S.ncolours[l];
+  P.nonempty.resize(nc);
+  for (int t = 0; t < nc; ++t) P.nonempty[t] = S.size[l][t] > 0;
+  // near lists
+  P.np_ptr.assign(nc + 1, 0);
+  for (const Pair& p : S.near[l]) P.np_ptr[p.first + 1]++;
+  for (int t = 0; t < nc; ++t) P.np_ptr[t + 1] += P.np_ptr[t];
+  P.np_cl.resize(S.near[l].size());
+  {
+    std::vector<int32_t> fillp(P.np_ptr.begin(), P.np_ptr.end() - 1);
+    for (const Pair& p : S.near[l]) P.np_cl[fillp[p.first]++] = p.second;
+  }
+  // near slots, in S.near order
+  P.nnear = (int)S.near[l].size();
+  std::vector<int64_t> keys;
+  keys.reserve(S.near[l].size() * 4);
+  for (int i = 0; i < nc; ++i) {
+    for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
+      for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y) keys.push_back((int64_t)P.np_cl[x] * nc + P.np_cl[y]);
+  }
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  // remove near pairs from keys -> fill pairs
+  std::vector<int64_t> nearkeys(S.near[l].size());
+  for (size_t e = 0; e < S.near[l].size(); ++e)
+    nearkeys[e] = (int64_t)S.near[l][e].first * nc + S.near[l][e].second;
+  std::vector<int64_t> fillkeys;
+  std::set_difference(keys.begin(), keys.end(), nearkeys.begin(), nearkeys.end(), std::back_inserter(fillkeys));
+  // also every parent of a fill slot of the level below is a fill slot here (kept for safety)
+  P.nslot = P.nnear + (int)fillkeys.size();
+  P.slot_a.resize(P.nslot);
+  P.slot_b.resize(P.nslot);
+  for (int e = 0; e < P.nnear; ++e) {
+    P.slot_a[e] = S.near[l][e].first;
+    P.slot_b[e] = S.near[l][e].second;
+  }
+  for (size_t e = 0; e < fillkeys.size(); ++e) {
+    P.slot_a[P.nnear + e] = (int32_t)(fillkeys[e] / nc);
+    P.slot_b[P.nnear + e] = (int32_t)(fillkeys[e] % nc);
+  }
+  // row lookup
+  P.rl_ptr.assign(nc + 1, 0);
+  for (int s = 0; s < P.nslot; ++s) P.rl_ptr[P.slot_a[s] + 1]++;
+  for (int t = 0; t < nc; ++t) P.rl_ptr[t + 1] += P.rl_ptr[t];
+  {
+    std::vector<std::pair<int32_t, int32_t>> tmp(P.nslot);
+    std::vector<int32_t> fillp(P.rl_ptr.begin(), P.rl_ptr.end() - 1);
+    for (int s = 0; s < P.nslot; ++s) tmp[fillp[P.slot_a[s]]++] = {P.slot_b[s], s};
+    for (int t = 0; t < nc; ++t) std::sort(tmp.begin() + P.rl_ptr[t], tmp.begin() + P.rl_ptr[t + 1]);
+    P.rl_b.resize(P.nslot);
+    P.rl_slot.resize(P.nslot);
+    for (int s = 0; s < P.nslot; ++s) {
+      P.rl_b[s] = tmp[s].first;
+      P.rl_slot[s] = tmp[s].second;
+    }
+  }
+  P.np_srow.resize(P.np_cl.size());
+  P.np_scol.resize(P.np_cl.size());
+  P.diag_slot.assign(nc, -1);
+  for (int i = 0; i < nc; ++i)
+    for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
+      const int a = P.np_cl[x];
+      P.np_srow[x] = P.slot_of(i, a);
+      P.np_scol[x] = P.slot_of(a, i);
+      if (a == i) P.diag_slot[i] = P.np_srow[x];
+    }
+  // fill partner lists (row i, non-near b)
+  P.fp_ptr.assign(nc + 1, 0);
+  for (int s = P.nnear; s < P.nslot; ++s) P.fp_ptr[P.slot_a[s] + 1]++;
+  for (int t = 0; t < nc; ++t) P.fp_ptr[t + 1] += P.fp_ptr[t];
+  P.fp_cl.resize(P.nslot - P.nnear);
+  P.fp_srow.resize(P.nslot - P.nnear);
+  {
+    std::vector<int32_t> fillp(P.fp_ptr.begin(), P.fp_ptr.end() - 1);
+    for (int s = P.nnear; s < P.nslot; ++s) {
+      const int e = fillp[P.slot_a[s]]++;
+      P.fp_cl[e] = P.slot_b[s];
+      P.fp_srow[e] = s;
+    }
+  }
+  // colours
+  P.cols.clear();
+  P.cols.resize(P.ncol);
+  for (int i = 0; i < nc; ++i)
+    if (P.colour[i] >= 0) P.cols[P.colour[i]].cl.push_back(i);
+  for (int s = 0; s < P.nslot; ++s) {
+    const int cx = P.colour[P.slot_a[s]], cy = P.colour[P.slot_b[s]];
+    P.cols[cx].pj_slot.push_back(s);
+    if (cy != cx) P.cols[cy].pj_slot.push_back(s);
+  }
+  for (int c = 0; c < P.ncol; ++c) {
+    ColourPlan& C = P.cols[c];
+    // Schur targets grouped by slot
+    std::vector<std::array<int32_t, 4>> con;
+    for (int i : C.cl)
+      for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
+        for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y) {
+          const int s = P.slot_of(P.np_cl[x], P.np_cl[y]);
+          con.push_back({s, i, x, y});
+        }
+    std::sort(con.begin(), con.end());
+    C.sc_cptr.push_back(0);
+    for (size_t e = 0; e < con.size(); ++e) {
+      if (e == 0 || con[e][0] != con[e - 1][0]) {
+        if (e) C.sc_cptr.push_back((int32_t)e);
+        C.sc_slot.push_back(con[e][0]);
+      }
+      C.sc_i.push_back(con[e][1]);
+      C.sc_ja.push_back(con[e][2]);
+      C.sc_jb.push_back(con[e][3]);
+    }
+    C.sc_cptr.push_back((int32_t)con.size());
+    if (C.sc_slot.empty()) C.sc_cptr.assign(1, 0);
+    // panels and solve gathers
+    std::vector<std::array<int32_t, 3>> sv;
+    for (int i : C.cl)
+      for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
+        C.pn_i.push_back(i);
+        C.pn_ja.push_back(x);
+        sv.push_back({P.np_cl[x], i, x});
+      }
+    std::sort(sv.begin(), sv.end());
+    C.sv_cptr.push_back(0);
+    for (size_t e = 0; e < sv.size(); ++e) {
+      if (e == 0 || sv[e][0] != sv[e - 1][0]) {
+        if (e) C.sv_cptr.push_back((int32_t)e);
+        C.sv_cl.push_back(sv[e][0]);
+      }
+      C.sv_i.push_back(sv[e][1]);
+      C.sv_ja.push_back(sv[e][2]);
+    }
+    C.sv_cptr.push_back((int32_t)sv.size());
+    if (C.sv_cl.empty()) C.sv_cptr.assign(1, 0);
+  }
+}
+
+// merge plan from level l (plan P) into level l-1 (plan Pp, or the final block when l == l0)
+static void build_merge(h2_ctx* H, LevelPlan& P, const LevelPlan* Pp) {
+  const Structure& S = H->S;
+  const int l = P.l;
+  const int npar = S.nclusters(l - 1);
+  P.merge.clear();
+  auto parent_pos = [&](int a, int b) -> int {
+    if (Pp) return Pp->slot_of(a / 2, b / 2);
+    return (a / 2) * npar + (b / 2);  // final dense block: pair index
+  };
+  std::vector<char> is_adm_fill(P.nslot, 0);
+  for (size_t e = 0; e < S.adm[l].size(); ++e) {
+    const Pair& p = S.adm[l][e];
+    const int fs = P.slot_of(p.first, p.second);
+    if (fs >= 0) is_adm_fill[fs] = 1;
+    const int pp = parent_pos(p.first, p.second);
+    if (pp < 0) fail(H2_ERR_INTERNAL, "admissible pair without an inadmissible parent");
+    P.merge.push_back({pp, p.first & 1, p.second & 1, 1, fs, (int32_t)e, p.first, p.second});
+  }
+  for (int s = 0; s < P.nslot; ++s) {
+    const int a = P.slot_a[s], b = P.slot_b[s];
+    if (s < P.nnear) {
+      const int pp = parent_pos(a, b);
+      if (pp < 0) fail(H2_ERR_INTERNAL, "inadmissible pair without an inadmissible parent");
+      P.merge.push_back({pp, a & 1, b & 1, 0, s, -1, a, b});
+    } else if (!is_adm_fill[s]) {
+      const int pp = parent_pos(a, b);
+      if (pp < 0) {
+        if (!Pp) fail(H2_ERR_INTERNAL, "fill-in outside the final block");
+        fail(H2_ERR_INTERNAL, "carried fill-in without a parent slot");
+      }
+      P.merge.push_back({pp, a & 1, b & 1, 2, s, -1, a, b});
+    }
+  }
+}
+
+static void upload_plan(LevelPlan& P, hipStream_t st) {
+  P.d_colour.upload(P.colour, st);
+  P.d_nonempty.upload(P.nonempty, st);
+  P.d_slot_a.upload(P.slot_a, st);
+  P.d_slot_b.upload(P.slot_b, st);
+  P.d_diag_slot.upload(P.diag_slot, st);
+  P.d_np_ptr.upload(P.np_ptr, st);
+  P.d_np_cl.upload(P.np_cl, st);
+  P.d_np_srow.upload(P.np_srow, st);
+  P.d_np_scol.upload(P.np_scol, st);
+  P.d_fp_ptr.upload(P.fp_ptr, st);
+  P.d_fp_cl.upload(P.fp_cl, st);
+  P.d_fp_srow.upload(P.fp_srow, st);
+  for (ColourPlan& C : P.cols) {
+    C.d_cl.upload(C.cl, st);
+    C.d_pj_slot.upload(C.pj_slot, st);
+    C.d_sc_slot.upload(C.sc_slot, st);
+    C.d_sc_cptr.upload(C.sc_cptr, st);
+    C.d_sc_i.upload(C.sc_i, st);
+    C.d_sc_ja.upload(C.sc_ja, st);
+    C.d_sc_jb.upload(C.sc_jb, st);
+    C.d_pn_i.upload(C.pn_i, st);
+    C.d_pn_ja.upload(C.pn_ja, st);
+    C.d_sv_cl.upload(C.sv_cl, st);
+    C.d_sv_cptr.upload(C.sv_cptr, st);
+    C.d_sv_i.upload(C.sv_i, st);
+    C.d_sv_ja.upload(C.sv_ja, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched GEMM helper (host-resolved tasks)
+// ---------------------------------------------------------------------------
+static void run_gemms(const std::vector<GemmTask>& tasks, hipStream_t st) {
+  if (tasks.empty()) return;
+  std::vector<int32_t> tt, rc;
+  for (size_t i = 0; i < tasks.size(); ++i) {
+    const int tr = (tasks[i].m + 63) / 64, tc = (tasks[i].n + 63) / 64;
+    for (int a = 0; a < tr; ++a)
+      for (int b = 0; b < tc; ++b) {
+        tt.push_back((int32_t)i);
+        rc.push_back(a | (b << 16));
+      }
+  }
+  DArr<GemmTask> dt;
+  DArr<int32_t> dtt, drc;
+  dt.alloc(tasks.size());
+  HIPCHK(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(GemmTask), hipMemcpyHostToDevice, st));
+  dtt.upload(tt, st);
+  drc.upload(rc, st);
+  launch_gemm_batched(dt.p, dtt.p, drc.p, (int)tt.size(), st);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+static bool sync_debug() {
+  static const bool on = [] {
+    const char* e = std::getenv("H2MI_SYNC_CHECK");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+// After a group of launches: report launch errors; with H2MI_SYNC_CHECK=1 also
+// wait for the device and report execution errors at the group that caused them.
+static void check_launch(const char* where = "") {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(H2_ERR_DEVICE, std::string("kernel launch ") + where + ": " + hipGetErrorString(e));
+  if (sync_debug()) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) fail(H2_ERR_DEVICE, std::string("kernel execution ") + where + ": " + hipGetErrorString(e));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// construction (Sec. II): nested bases from the far-field block rows
+// ---------------------------------------------------------------------------
+static std::vector<uint32_t> near_mask(const Structure& S, int l) {
+  const int64_t nc = S.nclusters(l);
+  std::vector<uint32_t> m((size_t)((nc * nc + 31) / 32), 0u);
+  for (const Pair& p : S.near[l]) {
+    const int64_t bit = (int64_t)p.first * nc + p.second;
+    m[bit >> 5] |= 1u << (bit & 31);
+  }
+  return m;
+}
+
+static int forced_k_of(h2_ctx* H, int l, int t) {
+  if (!H->has_forced) return -1;
+  return H->forced_k[H->lvl_base[l] + t];
+}
+
+static void construct(h2_ctx* H, hipStream_t st) {
+  const Structure& S = H->S;
+  const int L = S.L, l0 = S.l0;
+  const int nlev = L - l0 + 1;
+  H->build.clear();
+  H->build.resize(nlev);
+  const GeomView& g = H->geom;
+  for (int l = L; l >= l0; --l) {
+    BuildLevel& B = H->build[L - l];
+    const int nc = S.nclusters(l);
+    B.k.assign(nc, 0);
+    B.nu.assign(nc, 0.0);
+    B.margin.assign(2 * nc, 0.0);
+    // Gram dimensions
+    std::vector<int32_t> dim(nc, 0);
+    for (int t = 0; t < nc; ++t) {
+      if (l == L)
+        dim[t] = (int32_t)S.size[l][t];
+      else
+        dim[t] = H->build[L - l - 1].k[2 * t] + H->build[L - l - 1].k[2 * t + 1];
+      if (S.size[l][t] == 0) dim[t] = 0;
+    }
+    std::vector<int64_t> goff(nc + 1, 0);
+    int dmax = 0;
+    for (int t = 0; t < nc; ++t) {
+      goff[t + 1] = goff[t] + (int64_t)dim[t] * dim[t];
+      dmax = std::max(dmax, dim[t]);
+    }
+    const int64_t gtot = goff[nc];
+    DArr<double2> G;
+    G.alloc(gtot);
+    DArr<int64_t> d_goff;
+    d_goff.upload(goff, st);
+    std::vector<uint32_t> mask = near_mask(S, l);
+    DArr<uint32_t> d_mask;
+    d_mask.upload(mask, st);
+    const int ntr = std::max(1, (dmax + 63) / 64);
+    if (l == L) {
+      std::vector<int64_t> cstart(S.start[l].begin(), S.start[l].end());
+      std::vector<int32_t> csize(nc);
+      for (int t = 0; t < nc; ++t) csize[t] = (int32_t)S.size[l][t];
+      DArr<int64_t> d_cs;
+      DArr<int32_t> d_sz;
+      d_cs.upload(cstart, st);
+      d_sz.upload(csize, st);
+      // split the columns so that the partial Grams stay below ~1 GiB
+      int64_t kchunk = 2048;
+      while ((H->N + kchunk - 1) / kchunk * gtot * 16 > (int64_t)1 << 30 && kchunk < H->N) kchunk *= 2;
+      const int nchunks = (int)((H->N + kchunk - 1) / kchunk);
+      DArr<double2> part;
+      part.alloc((size_t)nchunks * gtot);
+      launch_leaf_gram(g, d_mask.p, nc, l, d_cs.p, d_sz.p, kchunk, nchunks, part.p, gtot, d_goff.p, ntr, st);
+      check_launch("host.cpp:534");
+      launch_gram_reduce(part.p, G.p, nullptr, nullptr, nc, nchunks, gtot, st);
+      check_launch("host.cpp:536");
+      HIPCHK(hipStreamSynchronize(st));
+    } else {
+      const BuildLevel& C = H->build[L - l - 1];
+      const int ncc = S.nclusters(l + 1);
+      // stacked row blocks: child c of parent t writes rows [off, off + k_c) of Y_t (ld dim_t)
+      std::vector<int64_t> cstart(S.start[l + 1].begin(), S.start[l + 1].end());
+      std::vector<int32_t> csize(ncc), ck(ncc), yld(ncc);
+      int kmax = 0;
+      for (int c = 0; c < ncc; ++c) {
+        csize[c] = (int32_t)S.size[l + 1][c];
+        ck[c] = C.k[c];
+        yld[c] = dim[c / 2];
+        kmax = std::max(kmax, ck[c]);
+      }
+      std::vector<int64_t> ybase(nc + 1, 0);
+      int64_t rowsum = 0;
+      for (int t = 0; t < nc; ++t) rowsum += dim[t];
+      int64_t chunk = 8192;
+      while (chunk > 256 && rowsum * chunk * 16 > ((int64_t)1 << 31)) chunk /= 2;
+      chunk = std::min<int64_t>(chunk, H->N);
+      for (int t = 0; t < nc; ++t) ybase[t + 1] = ybase[t] + (int64_t)dim[t] * chunk;
+      std::vector<int64_t> yoff(ncc);
+      for (int c = 0; c < ncc; ++c) yoff[c] = ybase[c / 2] + ((c & 1) ? C.k[c - 1] : 0);
+      std::vector<int64_t> ytoff(nc);
+      for (int t = 0; t < nc; ++t) ytoff[t] = ybase[t];
+      DArr<int64_t> d_cs, d_yoff, d_ytoff;
+      DArr<int32_t> d_sz, d_ck, d_yld, d_dim;
+      d_cs.upload(cstart, st);
+      d_sz.upload(csize, st);
+      d_ck.upload(ck, st);
+      d_yld.upload(yld, st);
+      d_yoff.upload(yoff, st);
+      d_ytoff.upload(ytoff, st);
+      d_dim.upload(dim, st);
+      DArr<double2> Y;
+      Y.alloc(std::max<int64_t>(1, ybase[nc]));
+      launch_zero(G.p, gtot, st);
+      const int ktr = std::max(1, (kmax + 63) / 64);
+      for (int64_t c0 = 0; c0 < H->N; c0 += chunk) {
+        const int ncols = (int)std::min<int64_t>(chunk, H->N - c0);
+        launch_proj_rows(g, d_mask.p, l, ncc, d_cs.p, d_sz.p, d_ck.p, C.d_voff.p, C.V.p, d_yoff.p, d_yld.p, Y.p, c0,
+                         ncols, ktr, st);
+        check_launch("host.cpp:579");
+        launch_gram_acc(nc, d_dim.p, d_ytoff.p, Y.p, ncols, d_goff.p, G.p, ntr, st);
+        check_launch("host.cpp:581");
+      }
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    // eigen-decomposition of every Gram (relative-accuracy Jacobi)
+    std::vector<int64_t> uoff(goff.begin(), goff.end() - 1), loff(nc), soff(nc);
+    int64_t lt = 0, stt = 0;
+    for (int t = 0; t < nc; ++t) {
+      loff[t] = lt;
+      lt += dim[t];
+      soff[t] = stt;
+      if (dim[t] > 64) stt += 2 * (int64_t)(dim[t] + 1) * (dim[t] + 1);
+    }
+    DArr<double2> U, scratch;
+    DArr<double> lam;
+    U.alloc(gtot);
+    lam.alloc(std::max<int64_t>(1, lt));
+    scratch.alloc(std::max<int64_t>(1, stt));
+    DArr<int64_t> d_uoff, d_loff, d_soff;
+    DArr<int32_t> d_dim;
+    d_uoff.upload(uoff, st);
+    d_loff.upload(loff, st);
+    d_soff.upload(soff, st);
+    d_dim.upload(dim, st);
+    if (dmax > 255) fail(H2_ERR_INTERNAL, "construction Gram larger than 255 (eigensolver limit)");
+    launch_jacobi(nc, d_dim.p, d_goff.p, G.p, d_uoff.p, U.p, d_loff.p, lam.p, 1, scratch.p, d_soff.p, st);
+    check_launch("host.cpp:607");
+    std::vector<double> hl(std::max<int64_t>(1, lt));
+    HIPCHK(hipMemcpyAsync(hl.data(), lam.p, hl.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // ranks: sigma_j > eps * sigma_1
+    B.boff.assign(nc + 1, 0);
+    for (int t = 0; t < nc; ++t) {
+      int kt = 0;
+      double s1 = 0.0;
+      if (dim[t] > 0) {
+        s1 = std::sqrt(std::max(hl[loff[t]], 0.0));
+        const double thr = H->eps * s1;
+        if (s1 > 0.0) {
+          for (int j = 0; j < dim[t]; ++j)
+            if (std::sqrt(std::max(hl[loff[t] + j], 0.0)) > thr) kt = j + 1;
+          B.margin[2 * t] = kt > 0 ? std::sqrt(std::max(hl[loff[t] + kt - 1], 0.0)) / thr : 1e300;
+          B.margin[2 * t + 1] = kt < dim[t] ? std::sqrt(std::max(hl[loff[t] + kt], 0.0)) / thr : 0.0;
+        }
+      }
+      const int fk = forced_k_of(H, l, t);
+      if (fk >= 0) kt = std::min(fk, dim[t]);
+      B.k[t] = kt;
+      B.nu[t] = s1;
+      B.boff[t + 1] = B.boff[t] + (int64_t)dim[t] * kt;
+    }
+    // basis = leading k columns of the eigenvector matrix (contiguous in column-major)
+    B.basis.alloc(B.boff[nc]);
+    for (int t = 0; t < nc; ++t)
+      if (B.boff[t + 1] > B.boff[t])
+        HIPCHK(hipMemcpyAsync(B.basis.p + B.boff[t], U.p + uoff[t], (B.boff[t + 1] - B.boff[t]) * sizeof(double2),
+                              hipMemcpyDeviceToDevice, st));
+    // expanded bases
+    B.voff.assign(nc + 1, 0);
+    for (int t = 0; t < nc; ++t) B.voff[t + 1] = B.voff[t] + S.size[l][t] * (int64_t)B.k[t];
+    B.V.alloc(B.voff[nc]);
+    if (l == L) {
+      if (B.voff[nc] > 0)
+        HIPCHK(hipMemcpyAsync(B.V.p, B.basis.p, B.voff[nc] * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    } else {
+      const BuildLevel& C = H->build[L - l - 1];
+      std::vector<GemmTask> tasks;
+      for (int t = 0; t < nc; ++t) {
+        if (B.k[t] == 0 || S.size[l][t] == 0) continue;
+        const int k1 = C.k[2 * t], k2 = C.k[2 * t + 1];
+        const int64_t n1 = S.size[l + 1][2 * t], n2 = S.size[l + 1][2 * t + 1];
+        const int64_t nt = S.size[l][t];
+        const double2* T = B.basis.p + B.boff[t];
+        if (k1 > 0 && n1 > 0)
+          tasks.push_back({C.V.p + C.voff[2 * t], T, B.V.p + B.voff[t], n1, (int64_t)(k1 + k2), nt, (int32_t)n1,
+                           B.k[t], k1, OP_N, OP_N, ST_SET});
+        if (k2 > 0 && n2 > 0)
+          tasks.push_back({C.V.p + C.voff[2 * t + 1], T + k1, B.V.p + B.voff[t] + n1, n2, (int64_t)(k1 + k2), nt,
+                           (int32_t)n2, B.k[t], k2, OP_N, OP_N, ST_SET});
+      }
+      // rows of a child with k = 0 must read as zero
+      launch_zero(B.V.p, B.voff[nc], st);
+      run_gemms(tasks, st);
+    }
+    B.ktot = 0;
+    for (int t = 0; t < nc; ++t) B.ktot += B.k[t];
+    B.d_voff.upload(B.voff, st);
+    B.d_k.upload(B.k, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  // couplings S_ts = V_t^H Z(t, s) conj(V_s) for admissible pairs (t < s), S_st = S_ts^T
+  for (int l = l0; l <= L; ++l) {
+    BuildLevel& B = H->build[L - l];
+    const auto& adm = S.adm[l];
+    B.soff.assign(adm.size() + 1, 0);
+    for (size_t e = 0; e < adm.size(); ++e)
+      B.soff[e + 1] = B.soff[e] + (int64_t)B.k[adm[e].first] * B.k[adm[e].second];
+    B.S.alloc(B.soff[adm.size()]);
+    std::unordered_map<int64_t, int32_t> idx;
+    const int64_t nc = S.nclusters(l);
+    for (size_t e = 0; e < adm.size(); ++e) idx[(int64_t)adm[e].first * nc + adm[e].second] = (int32_t)e;
+    std::vector<int32_t> pt, ps;
+    std::vector<int64_t> xoff;
+    std::vector<size_t> pe;
+    int64_t xt = 0;
+    int kmax = 0, smax = 0;
+    std::vector<int64_t> cstart(S.start[l].begin(), S.start[l].end());
+    std::vector<int32_t> csize(nc), ck(nc);
+    for (int t = 0; t < nc; ++t) {
+      csize[t] = (int32_t)S.size[l][t];
+      ck[t] = B.k[t];
+    }
+    DArr<int64_t> d_cs;
+    DArr<int32_t> d_sz, d_ck;
+    d_cs.upload(cstart, st);
+    d_sz.upload(csize, st);
+    d_ck.upload(ck, st);
+    DArr<int64_t> d_voff;
+    d_voff.upload(B.voff, st);
+    auto flush = [&]() {
+      if (pt.empty()) return;
+      DArr<int32_t> d_pt, d_ps;
+      DArr<int64_t> d_xoff;
+      DArr<double2> X;
+      d_pt.upload(pt, st);
+      d_ps.upload(ps, st);
+      d_xoff.upload(xoff, st);
+      X.alloc(std::max<int64_t>(1, xt));
+      const int ntr = std::max(1, (kmax + 63) / 64), ntc = std::max(1, (smax + 63) / 64);
+      launch_coupling_x(g, (int)pt.size(), ntr, ntc, d_pt.p, d_ps.p, d_cs.p, d_sz.p, d_ck.p, d_voff.p, B.V.p,
+                        d_xoff.p, X.p, st);
+      check_launch("host.cpp:712");
+      std::vector<GemmTask> tasks, trans;
+      for (size_t q = 0; q < pt.size(); ++q) {
+        const int t = pt[q], s = ps[q];
+        const size_t e = pe[q];
+        tasks.push_back({X.p + xoff[q], B.V.p + B.voff[s], B.S.p + B.soff[e], (int64_t)std::max(1, B.k[t]),
+                         (int64_t)S.size[l][s], (int64_t)std::max(1, B.k[t]), B.k[t], B.k[s], (int32_t)S.size[l][s],
+                         OP_N, OP_R, ST_SET});
+        const size_t et = idx[(int64_t)s * nc + t];
+        trans.push_back({B.S.p + B.soff[e], nullptr, B.S.p + B.soff[et], (int64_t)std::max(1, B.k[t]), 0,
+                         (int64_t)std::max(1, B.k[s]), B.k[t], B.k[s], 0, 0, 0, 0});
+      }
+      run_gemms(tasks, st);
+      DArr<GemmTask> dtr;
+      dtr.alloc(trans.size());
+      HIPCHK(hipMemcpyAsync(dtr.p, trans.data(), trans.size() * sizeof(GemmTask), hipMemcpyHostToDevice, st));
+      launch_transpose_copy(dtr.p, (int)trans.size(), st);
+      check_launch("host.cpp:729");
+      HIPCHK(hipStreamSynchronize(st));
+      pt.clear();
+      ps.clear();
+      xoff.clear();
+      pe.clear();
+      xt = 0;
+      kmax = smax = 0;
+    };
+    for (size_t e = 0; e < adm.size(); ++e) {
+      const int t = adm[e].first, s = adm[e].second;
+      if (t >= s) continue;
+      if (B.k[t] == 0 || B.k[s] == 0) continue;
+      pt.push_back(t);
+      ps.push_back(s);
+      pe.push_back(e);
+      xoff.push_back(xt);
+      xt += (int64_t)B.k[t] * S.size[l][s];
+      kmax = std::max(kmax, B.k[t]);
+      smax = std::max<int>(smax, (int)S.size[l][s]);
+      if (xt * 16 > ((int64_t)1 << 30)) flush();
+    }
+    flush();
+    // device views for the H^2 product
+    B.d_soff.upload(B.soff, st);
+    B.d_nu.upload(B.nu, st);
+    std::vector<int32_t> rows(nc);
+    for (int t = 0; t < nc; ++t) rows[t] = (int32_t)S.size[l][t];
+    B.d_rows.upload(rows, st);
+    std::vector<int32_t> cptr(nc + 1, 0), ccol(adm.size());
+    for (const Pair& p : adm) cptr[p.first + 1]++;
+    for (int t = 0; t < nc; ++t) cptr[t + 1] += cptr[t];
+    for (size_t e = 0; e < adm.size(); ++e) ccol[e] = adm[e].second;  // adm sorted by row: CSR order = list order
+    B.d_cptr.upload(cptr, st);
+    B.d_ccol.upload(ccol, st);
+    B.d_cstart.upload(cstart, st);
+    std::vector<int64_t> xo(nc);
+    int64_t o = 0;
+    for (int t = 0; t < nc; ++t) {
+      xo[t] = o;
+      o += B.k[t];
+    }
+    B.d_xoff.upload(xo, st);
+  }
+  // inadmissible leaf blocks
+  const auto& nl = S.near[L];
+  H->near_off.assign(nl.size() + 1, 0);
+  for (size_t e = 0; e < nl.size(); ++e)
+    H->near_off[e + 1] = H->near_off[e] + S.size[L][nl[e].first] * S.size[L][nl[e].second];
+  H->near_orig.alloc(H->near_off[nl.size()]);
+  {
+    std::vector<int32_t> pr(nl.size()), pc(nl.size()), sz(S.nclusters(L));
+    for (size_t e = 0; e < nl.size(); ++e) {
+      pr[e] = nl[e].first;
+      pc[e] = nl[e].second;
+    }
+    for (int t = 0; t < S.nclusters(L); ++t) sz[t] = (int32_t)S.size[L][t];
+    std::vector<int64_t> cs(S.start[L].begin(), S.start[L].end());
+    DArr<int32_t> d_pr, d_pc;
+    d_pr.upload(pr, st);
+    d_pc.upload(pc, st);
+    H->d_leaf_size.upload(sz, st);
+    H->d_leaf_start.upload(cs, st);
+    H->d_near_off.upload(H->near_off, st);
+    launch_near_blocks(g, d_pr.p, d_pc.p, H->d_near_off.p, H->d_leaf_start.p, H->d_leaf_size.p,
+                       H->d_leaf_start.p, H->d_leaf_size.p, (int)nl.size(), H->near_orig.p, st);
+    check_launch("host.cpp:795");
+    std::vector<int32_t> nptr(S.nclusters(L) + 1, 0);
+    for (const Pair& p : nl) nptr[p.first + 1]++;
+    for (int t = 0; t < S.nclusters(L); ++t) nptr[t + 1] += nptr[t];
+    H->d_near_ptr.upload(nptr, st);
+    H->d_near_col.upload(pc, st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// factorization
+// ---------------------------------------------------------------------------
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipEvent_t next(hipStream_t st) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    hipEvent_t e = ev[used++];
+    HIPCHK(hipEventRecord(e, st));
+    return e;
+  }
+  ~EventPool() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
+static void dense_lu_inverse(h2_ctx* H, hipStream_t st);
+
+static void factor_impl(h2_ctx* H, hipStream_t st) {
+  const Structure& S = H->S;
+  const int L = S.L, l0 = S.l0;
+  H->factored = false;
+  H->flev.clear();
+  H->timing.assign(6, 0.0);
+  H->ledger.assign(10, 0.0);
+  H->stats_rows.clear();
+  EventPool ev;
+  std::vector<std::array<hipEvent_t, 4>> phase_ev;
+  hipEvent_t t_begin = ev.next(st);
+  if (l0 < 0) {
+    // no admissible block anywhere: LU of the whole matrix
+    H->nf = H->N;
+    H->Zf.alloc((size_t)H->N * H->N);
+    launch_zero(H->Zf.p, H->N * H->N, st);
+    const auto& nl = S.near[L];
+    for (size_t e = 0; e < nl.size(); ++e) {
+      const int a = nl[e].first, b = nl[e].second;
+      HIPCHK(hipMemcpy2DAsync(H->Zf.p + S.start[L][a] + S.start[L][b] * H->N, H->N * sizeof(double2),
+                              H->near_orig.p + H->near_off[e], S.size[L][a] * sizeof(double2),
+                              S.size[L][a] * sizeof(double2), S.size[L][b], hipMemcpyDeviceToDevice, st));
+    }
+    hipEvent_t t_m = ev.next(st);
+    dense_lu_inverse(H, st);
+    hipEvent_t t_end = ev.next(st);
+    HIPCHK(hipStreamSynchronize(st));
+    H->timing[0] = elapsed(t_begin, t_end);
+    H->timing[5] = elapsed(t_m, t_end);
+    H->factored = true;
+    return;
+  }
+  const int nlev = L - l0 + 1;
+  H->flev.resize(nlev);
+  DArr<double2> slots;  // current level's block arena
+  DArr<double2> parent_slots;
+  std::vector<int32_t> n_cur(S.nclusters(L));
+  for (int t = 0; t < S.nclusters(L); ++t) n_cur[t] = (int32_t)S.size[L][t];
+  for (int l = L; l >= l0; --l) {
+    const int j = L - l;
+    LevelPlan& P = H->plans[j];
+    BuildLevel& Bd = H->build[j];
+    FactorLevel& F = H->flev[j];
+    const int nc = P.nc;
+    F.n = n_cur;
+    std::vector<int32_t> kk(Bd.k.begin(), Bd.k.end());
+    for (int t = 0; t < nc; ++t)
+      if (!P.nonempty[t]) kk[t] = 0;
+    int nmax = 0;
+    for (int t = 0; t < nc; ++t) {
+      nmax = std::max(nmax, F.n[t]);
+      if (F.n[t] < kk[t]) fail(H2_ERR_INTERNAL, "basis wider than its cluster");
+      if (F.n[t] - kk[t] > 128) fail(H2_ERR_INTERNAL, "cluster complement dimension above 128 (kernel limit)");
+      if (kk[t] > 128) fail(H2_ERR_INTERNAL, "cluster basis wider than 128 (kernel limit)");
+    }
+    if (nmax > 512) fail(H2_ERR_INTERNAL, "cluster dimension above 512 (kernel limit)");
+    F.tiles = std::max(1, (nmax + 63) / 64);
+    // offsets
+    std::vector<int64_t> slot_off(P.nslot + 1, 0);
+    for (int s = 0; s < P.nslot; ++s)
+      slot_off[s + 1] = slot_off[s] + (int64_t)F.n[P.slot_a[s]] * F.n[P.slot_b[s]];
+    std::vector<int32_t> np_off(P.np_cl.size()), prow(nc, 0);
+    for (int i = 0; i < nc; ++i) {
+      int o = 0;
+      for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
+        np_off[x] = o;
+        o += F.n[P.np_cl[x]];
+      }
+      prow[i] = o;
+    }
+    std::vector<int64_t> q_off(nc + 1, 0), b_off(nc + 1, 0), bp_off(nc + 1, 0), lu_off(nc + 1, 0),
+        cp_off(nc + 1, 0), w_off(nc + 1, 0);
+    for (int i = 0; i < nc; ++i) {
+      const int64_t n = F.n[i], k = kk[i], d = n - k;
+      q_off[i + 1] = q_off[i] + n * n;
+      b_off[i + 1] = b_off[i] + n * k;
+      bp_off[i + 1] = bp_off[i] + n * d;
+      lu_off[i + 1] = lu_off[i] + 2 * d * d;
+      cp_off[i + 1] = cp_off[i] + (int64_t)prow[i] * d;
+      w_off[i + 1] = w_off[i] + n * n + n * d + 2 * d * d;
+    }
+    // per-colour projection temp offsets
+    int64_t temp_max = 0;
+    for (ColourPlan& C : P.cols) {
+      C.pj_toff.resize(C.pj_slot.size());
+      int64_t o = 0;
+      for (size_t e = 0; e < C.pj_slot.size(); ++e) {
+        C.pj_toff[e] = o;
+        const int s = C.pj_slot[e];
+        o += (int64_t)F.n[P.slot_a[s]] * F.n[P.slot_b[s]];
+      }
+      C.d_pj_toff.upload(C.pj_toff, st);
+      temp_max = std::max(temp_max, o);
+    }
+    F.ntot = 0;
+    F.voff.assign(nc + 1, 0);
+    for (int i = 0; i < nc; ++i) F.voff[i + 1] = F.voff[i] + F.n[i];
+    F.ntot = F.voff[nc];
+    // device arrays
+    F.d_n.upload(F.n, st);
+    F.d_k.upload(kk, st);
+    F.d_kt.upload(kk, st);
+    {
+      std::vector<int32_t> fk(nc, -1);
+      if (H->has_forced)
+        for (int i = 0; i < nc; ++i) fk[i] = H->forced_kt[H->lvl_base[l] + i];
+      F.d_forced.upload(fk, st);
+    }
+    F.d_np_off.upload(np_off, st);
+    F.d_prow.upload(prow, st);
+    F.d_flags.upload(std::vector<int32_t>(4, 0), st);
+    F.d_slot_off.upload(slot_off, st);
+    F.d_q_off.upload(q_off, st);
+    F.d_b_off.upload(b_off, st);
+    F.d_bp_off.upload(bp_off, st);
+    F.d_lu_off.upload(lu_off, st);
+    F.d_cp_off.upload(cp_off, st);
+    F.d_rp_off.upload(cp_off, st);
+    F.d_w_off.upload(w_off, st);
+    F.d_voff.upload(F.voff, st);
+    F.d_margins.alloc(2 * nc);
+    F.Q.alloc(q_off[nc]);
+    F.LU.alloc(lu_off[nc]);
+    F.CP.alloc(cp_off[nc]);
+    F.RP.alloc(cp_off[nc]);
+    DArr<double2> Bp, W, temp, lu_scr, eig_scr;
+    Bp.alloc(bp_off[nc]);
+    W.alloc(w_off[nc]);
+    temp.alloc(temp_max);
+    int maxcl = 1;
+    for (ColourPlan& C : P.cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
+    lu_scr.alloc((size_t)maxcl * 256 * 256 * (nmax > 64 ? 1 : 0) + 1);
+    eig_scr.alloc((size_t)maxcl * 2 * 130 * 130 * (nmax > 64 ? 1 : 0) + 1);
+    // blocks of this level
+    if (l == L) {
+      slots.alloc(slot_off[P.nslot]);
+      launch_zero(slots.p, slot_off[P.nslot], st);
+      // inadmissible leaf blocks first (same order as S.near[L] and same sizes)
+      HIPCHK(hipMemcpyAsync(slots.p, H->near_orig.p, H->near_off.back() * sizeof(double2), hipMemcpyDeviceToDevice,
+                            st));
+      F.B.alloc(b_off[nc]);
+      if (b_off[nc] > 0)
+        HIPCHK(hipMemcpyAsync(F.B.p, Bd.basis.p, b_off[nc] * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    } else {
+      slots = std::move(parent_slots);
+      // parent bases: transfer matrices padded with zero rows (eq. 23)
+      const FactorLevel& Fc = H->flev[j - 1];
+      const BuildLevel& Bc = H->build[j - 1];
+      std::vector<int32_t> k1(nc), k2(nc), off1(nc);
+      for (int p = 0; p < nc; ++p) {
+        k1[p] = Bc.k[2 * p];
+        k2[p] = Bc.k[2 * p + 1];
+        off1[p] = H->plans[j - 1].nonempty[2 * p] ? Fc.kt[2 * p] : 0;
+      }
+      std::vector<int64_t> toff(Bd.boff.begin(), Bd.boff.end() - 1);
+      DArr<int32_t> d_k1, d_k2, d_off1;
+      DArr<int64_t> d_toff;
+      d_k1.upload(k1, st);
+      d_k2.upload(k2, st);
+      d_off1.upload(off1, st);
+      d_toff.upload(toff, st);
+      F.B.alloc(b_off[nc]);
+      launch_parent_basis(nc, F.d_n.p, F.d_k.p, d_k1.p, d_k2.p, d_off1.p, d_toff.p, Bd.basis.p, F.d_b_off.p, F.B.p,
+                          st);
+      check_launch("host.cpp:997");
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    LevelView& v = F.view;
+    v.nc = nc;
+    v.n = F.d_n.p;
+    v.k = F.d_k.p;
+    v.kt = F.d_kt.p;
+    v.colour = P.d_colour.p;
+    v.nu = Bd.d_nu.p;
+    v.forced = H->has_forced ? F.d_forced.p : nullptr;
+    v.eps_fill = H->eps_fill;
+    v.slot_off = F.d_slot_off.p;
+    v.slot_a = P.d_slot_a.p;
+    v.slot_b = P.d_slot_b.p;
+    v.slots = slots.p;
+    v.diag_slot = P.d_diag_slot.p;
+    v.np_ptr = P.d_np_ptr.p;
+    v.np_cl = P.d_np_cl.p;
+    v.np_srow = P.d_np_srow.p;
+    v.np_scol = P.d_np_scol.p;
+    v.np_off = F.d_np_off.p;
+    v.fp_ptr = P.d_fp_ptr.p;
+    v.fp_cl = P.d_fp_cl.p;
+    v.fp_srow = P.d_fp_srow.p;
+    v.q_off = F.d_q_off.p;
+    v.Q = F.Q.p;
+    v.b_off = F.d_b_off.p;
+    v.B = F.B.p;
+    v.bp_off = F.d_bp_off.p;
+    v.Bp = Bp.p;
+    v.lu_off = F.d_lu_off.p;
+    v.LU = F.LU.p;
+    v.cp_off = F.d_cp_off.p;
+    v.CP = F.CP.p;
+    v.rp_off = F.d_rp_off.p;
+    v.RP = F.RP.p;
+    v.prow = F.d_prow.p;
+    v.w_off = F.d_w_off.p;
+    v.W = W.p;
+    v.flags = F.d_flags.p;
+    v.margins = F.d_margins.p;
+    launch_householder_perp(v, nc, st);
+    check_launch("host.cpp:1040");
+    hipEvent_t e_lev0 = ev.next(st);
+    for (int c = 0; c < P.ncol; ++c) {
+      ColourPlan& C = P.cols[c];
+      ColourTasks ct{};
+      ct.cl = C.d_cl.p;
+      ct.ncl = (int)C.cl.size();
+      ct.pj_slot = C.d_pj_slot.p;
+      ct.pj_toff = C.d_pj_toff.p;
+      ct.npj = (int)C.pj_slot.size();
+      ct.sc_slot = C.d_sc_slot.p;
+      ct.sc_cptr = C.d_sc_cptr.p;
+      ct.sc_i = C.d_sc_i.p;
+      ct.sc_ja = C.d_sc_ja.p;
+      ct.sc_jb = C.d_sc_jb.p;
+      ct.nsc = (int)C.sc_slot.size();
+      ct.pn_i = C.d_pn_i.p;
+      ct.pn_ja = C.d_pn_ja.p;
+      ct.npn = (int)C.pn_i.size();
+      ct.sv_cl = C.d_sv_cl.p;
+      ct.sv_cptr = C.d_sv_cptr.p;
+      ct.sv_i = C.d_sv_i.p;
+      ct.sv_ja = C.d_sv_ja.p;
+      ct.nsv = (int)C.sv_cl.size();
+      ct.colour = c;
+      ct.tiles = F.tiles;
+      hipEvent_t e0 = ev.next(st);
+      launch_gram_fill(v, ct, st);
+      check_launch("gram_fill");
+      launch_xform(v, ct, 0, st);
+      launch_xform(v, ct, 1, st);
+      check_launch("xform");
+      launch_step0_eig(v, ct, eig_scr.p, st);
+      check_launch("step0_eig");
+      launch_xform(v, ct, 2, st);
+      launch_proj(v, ct, temp.p, 0, st);
+      launch_proj(v, ct, temp.p, 1, st);
+      check_launch("projection");
+      hipEvent_t e1 = ev.next(st);
+      launch_lu(v, ct, lu_scr.p, st);
+      check_launch("lu");
+      launch_panels(v, ct, st);
+      check_launch("panels");
+      hipEvent_t e2 = ev.next(st);
+      launch_schur(v, ct, st);
+      hipEvent_t e3 = ev.next(st);
+      check_launch("schur");
+      phase_ev.push_back({e0, e1, e2, e3});
+    }
+    // one synchronisation per level: ranks k~ and pivot status
+    F.kt.assign(nc, 0);
+    HIPCHK(hipMemcpyAsync(F.kt.data(), F.d_kt.p, nc * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int32_t flags[4];
+    HIPCHK(hipMemcpyAsync(flags, F.d_flags.p, sizeof(flags), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (flags[0]) fail(H2_ERR_SINGULAR, "zero pivot in the partial LU of a cluster at level " + std::to_string(l));
+    for (int i = 0; i < nc; ++i)
+      if (!P.nonempty[i]) F.kt[i] = 0;
+    // flop / byte ledger of this level from the actual ranks
+    for (int c = 0; c < P.ncol; ++c) {
+      H->ledger[7] += 1.0;  // one Schur launch per colour
+      for (int i : P.cols[c].cl) {
+        const double n = F.n[i], kt = F.kt[i], r = n - kt, k = kk[i], d = n - k;
+        double M = 0.0, fillcols = 0.0;
+        for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
+          const int a = P.np_cl[x];
+          M += (a == i) ? kt : (P.colour[a] < c ? F.kt[a] : F.n[a]);
+        }
+        for (int x = P.fp_ptr[i]; x < P.fp_ptr[i + 1]; ++x) {
+          const int b = P.fp_cl[x];
+          fillcols += (P.colour[b] < c ? F.kt[b] : F.n[b]);
+        }
+        const double schur = 8.0 * M * M * r;
+        H->ledger[6] += schur;
+        H->ledger[9] += 16.0 * (2.0 * M * M + 2.0 * M * r);  // targets read+written, panels read
+        // Gram, B_perp transforms, projections (rows and columns of every touched block), LU, panels
+        const double gram = 8.0 * n * n * fillcols + 8.0 * (n * n * d + n * d * d + n * d * d);
+        const double proj = 8.0 * n * n * (M - kt + n + fillcols) * 2.0;
+        const double lu = 8.0 / 3.0 * r * r * r + 8.0 * r * r * (M + M);
+        H->ledger[8] += schur + gram + proj + lu;
+      }
+    }
+    // merge into the parent level (or the final dense block)
+    hipEvent_t e_m0 = ev.next(st);
+    const int npar = S.nclusters(l - 1);
+    std::vector<int32_t> n_par(npar, 0), off1(npar, 0);
+    for (int p = 0; p < npar; ++p) {
+      off1[p] = P.nonempty[2 * p] ? F.kt[2 * p] : 0;
+      n_par[p] = off1[p] + (P.nonempty[2 * p + 1] ? F.kt[2 * p + 1] : 0);
+    }
+    std::vector<MergeTask> mt(P.merge.size());
+    int64_t dst_total = 0;
+    std::vector<int64_t> pslot_off;
+    if (l > l0) {
+      const LevelPlan& Pp = H->plans[j + 1];
+      pslot_off.assign(Pp.nslot + 1, 0);
+      for (int s = 0; s < Pp.nslot; ++s)
+        pslot_off[s + 1] = pslot_off[s] + (int64_t)n_par[Pp.slot_a[s]] * n_par[Pp.slot_b[s]];
+      dst_total = pslot_off[Pp.nslot];
+      for (size_t e = 0; e < P.merge.size(); ++e) {
+        const MergeSrc& m = P.merge[e];
+        const int pa = Pp.slot_a[m.pslot], pb = Pp.slot_b[m.pslot];
+        const int64_t ld = n_par[pa];
+        const int64_t ro = m.ci ? off1[pa] : 0, co = m.dj ? off1[pb] : 0;
+        MergeTask& t = mt[e];
+        t.dst = pslot_off[m.pslot] + ro + co * ld;
+        t.ldd = ld;
+        t.kind = m.kind;
+        t.slot = m.slot;
+        t.ca = m.ca;
+        t.cb = m.cb;
+        t.soff = m.adm >= 0 ? Bd.soff[m.adm] : 0;
+        t.ska = m.adm >= 0 ? Bd.k[m.ca] : 0;
+        t.skb = m.adm >= 0 ? Bd.k[m.cb] : 0;
+      }
+    } else {
+      H->final_off.assign(npar + 1, 0);
+      for (int p = 0; p < npar; ++p) H->final_off[p + 1] = H->final_off[p] + n_par[p];
+      H->nf = H->final_off[npar];
+      dst_total = H->nf * H->nf;
+      for (size_t e = 0; e < P.merge.size(); ++e) {
+        const MergeSrc& m = P.merge[e];
+        const int pa = m.pslot / npar, pb = m.pslot % npar;
+        const int64_t ro = H->final_off[pa] + (m.ci ? off1[pa] : 0);
+        const int64_t co = H->final_off[pb] + (m.dj ? off1[pb] : 0);
+        MergeTask& t = mt[e];
+        t.dst = ro + co * H->nf;
+        t.ldd = H->nf;
+        t.kind = m.kind;
+        t.slot = m.slot;
+        t.ca = m.ca;
+        t.cb = m.cb;
+        t.soff = m.adm >= 0 ? Bd.soff[m.adm] : 0;
+        t.ska = m.adm >= 0 ? Bd.k[m.ca] : 0;
+        t.skb = m.adm >= 0 ? Bd.k[m.cb] : 0;
+      }
+    }
+    DArr<MergeTask> d_mt;
+    d_mt.alloc(mt.size());
+    if (!mt.empty())
+      HIPCHK(hipMemcpyAsync(d_mt.p, mt.data(), mt.size() * sizeof(MergeTask), hipMemcpyHostToDevice, st));
+    double2* dst;
+    if (l > l0) {
+      parent_slots.alloc(dst_total);
+      dst = parent_slots.p;
+    } else {
+      H->Zf.alloc(dst_total);
+      dst = H->Zf.p;
+    }
+    launch_zero(dst, dst_total, st);
+    launch_merge(v, d_mt.p, (int)mt.size(), Bd.S.p, dst, st);
+    check_launch("host.cpp:1167");
+    hipEvent_t e_m1 = ev.next(st);
+    HIPCHK(hipStreamSynchronize(st));
+    H->timing[4] += elapsed(e_m0, e_m1);
+    (void)e_lev0;
+    // stats row
+    {
+      int64_t sn = 0, mn = 0, sk = 0, mk = 0, skt = 0, mkt = 0, nkt = INT64_MAX, el = 0, ncl = 0;
+      for (int i = 0; i < nc; ++i) {
+        if (!P.nonempty[i]) continue;
+        ++ncl;
+        sn += F.n[i];
+        mn = std::max<int64_t>(mn, F.n[i]);
+        sk += kk[i];
+        mk = std::max<int64_t>(mk, kk[i]);
+        skt += F.kt[i];
+        mkt = std::max<int64_t>(mkt, F.kt[i]);
+        nkt = std::min<int64_t>(nkt, F.kt[i]);
+        el += F.n[i] - F.kt[i];
+      }
+      H->stats_rows.push_back({l, ncl, sn, mn, sk, mk, skt, mkt, ncl ? nkt : 0, el});
+    }
+    n_cur = n_par;
+    slots.release();
+  }
+  hipEvent_t e_f0 = ev.next(st);
+  dense_lu_inverse(H, st);
+  hipEvent_t t_end = ev.next(st);
+  HIPCHK(hipStreamSynchronize(st));
+  H->stats_rows.push_back({l0 - 1, (int64_t)S.nclusters(l0 - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
+  H->timing[5] = elapsed(e_f0, t_end);
+  for (auto& pe : phase_ev) {
+    H->timing[1] += elapsed(pe[0], pe[1]);
+    H->timing[2] += elapsed(pe[1], pe[2]);
+    H->timing[3] += elapsed(pe[2], pe[3]);
+  }
+  H->timing[0] = elapsed(t_begin, t_end);
+  H->ledger[8] += 8.0 / 3.0 * (double)H->nf * H->nf * H->nf + 8.0 * (double)H->nf * H->nf * H->nf;
+  H->factored = true;
+}
+
+// Z_f^-1 by blocked LU with partial pivoting followed by blocked substitution on the identity.
+static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
+  const int64_t n = H->nf;
+  H->Zinv.alloc(std::max<int64_t>(1, n * n));
+  if (n == 0) return;
+  double2* A = H->Zf.p;
+  DArr<int32_t> piv, flag;
+  piv.alloc(n);
+  flag.upload(std::vector<int32_t>(1, 0), st);
+  const int64_t nb = (n + 63) / 64;
+  DArr<double2> linv, uinv;
+  linv.alloc(nb * 64 * 64);
+  uinv.alloc(nb * 64 * 64);
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0), rest = n - j0 - w;
+    launch_dense_panel(A, n, j0, piv.p, linv.p + b * 4096, flag.p, st);
+    check_launch("host.cpp:1223");
+    if (rest > 0) {
+      // U12 = L11^-1 A12 (in place: one tile row owns all 64 rows of its columns)
+      std::vector<GemmTask> t1{{linv.p + b * 4096, A + j0 + (j0 + w) * n, A + j0 + (j0 + w) * n, 64, n, n, (int32_t)w,
+                                (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SET}};
+      run_gemms(t1, st);
+      // A22 -= L21 U12
+      std::vector<GemmTask> t2{{A + (j0 + w) + j0 * n, A + j0 + (j0 + w) * n, A + (j0 + w) + (j0 + w) * n, n, n, n,
+                                (int32_t)rest, (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SUB}};
+      run_gemms(t2, st);
+    }
+  }
+  int32_t hf = 0;
+  HIPCHK(hipMemcpyAsync(&hf, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hf) fail(H2_ERR_SINGULAR, "zero pivot in the final dense LU");
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0);
+    launch_tri_inv_upper(A + j0 + j0 * n, n, (int)w, uinv.p + b * 4096, st);
+  }
+  check_launch("host.cpp:1243");
+  // X = P, then X <- L^-1 X, X <- U^-1 X (block rows)
+  double2* X = H->Zinv.p;
+  launch_zero(X, n * n, st);
+  launch_apply_perm_cols(X, n, piv.p, st);
+  check_launch("host.cpp:1248");
+  DArr<double2> tmp;
+  tmp.alloc(64 * n);
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0);
+    std::vector<GemmTask> t;
+    if (j0 > 0)
+      t.push_back({A + j0, X, X + j0, n, n, n, (int32_t)w, (int32_t)n, (int32_t)j0, OP_N, OP_N, ST_SUB});
+    run_gemms(t, st);
+    std::vector<GemmTask> t2{{linv.p + b * 4096, X + j0, tmp.p, 64, n, 64, (int32_t)w, (int32_t)n, (int32_t)w, OP_N,
+                              OP_N, ST_SET}};
+    run_gemms(t2, st);
+    HIPCHK(hipMemcpy2DAsync(X + j0, n * sizeof(double2), tmp.p, 64 * sizeof(double2), w * sizeof(double2), n,
+                            hipMemcpyDeviceToDevice, st));
+  }
+  for (int64_t b = nb - 1; b >= 0; --b) {
+    const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0), rest = n - j0 - w;
+    std::vector<GemmTask> t;
+    if (rest > 0)
+      t.push_back({A + j0 + (j0 + w) * n, X + j0 + w, X + j0, n, n, n, (int32_t)w, (int32_t)n, (int32_t)rest, OP_N,
+                   OP_N, ST_SUB});
+    run_gemms(t, st);
+    std::vector<GemmTask> t2{{uinv.p + b * 4096, X + j0, tmp.p, 64, n, 64, (int32_t)w, (int32_t)n, (int32_t)w, OP_N,
+                              OP_N, ST_SET}};
+    run_gemms(t2, st);
+    HIPCHK(hipMemcpy2DAsync(X + j0, n * sizeof(double2), tmp.p, 64 * sizeof(double2), w * sizeof(double2), n,
+                            hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// sweeps
+// ---------------------------------------------------------------------------
+static void ensure_vbuf(h2_ctx* H, int nrhs) {
+  if (H->vbuf_nrhs >= nrhs && !H->vbuf.empty()) return;
+  H->vbuf.clear();
+  H->vbuf.resize(H->flev.size());
+  for (size_t j = 0; j < H->flev.size(); ++j) H->vbuf[j].alloc(std::max<int64_t>(1, H->flev[j].ntot) * nrhs);
+  H->vtmp.alloc(std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs);
+  H->vtmp2.alloc(std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs);
+  H->vtmp3.alloc(std::max<int64_t>(1, H->N) * nrhs);
+  H->vbuf_nrhs = nrhs;
+}
+
+static ColourTasks colour_tasks(const ColourPlan& C, int c, int tiles) {
+  ColourTasks ct{};
+  ct.cl = C.d_cl.p;
+  ct.ncl = (int)C.cl.size();
+  ct.sv_cl = C.d_sv_cl.p;
+  ct.sv_cptr = C.d_sv_cptr.p;
+  ct.sv_i = C.d_sv_i.p;
+  ct.sv_ja = C.d_sv_ja.p;
+  ct.nsv = (int)C.sv_cl.size();
+  ct.colour = c;
+  ct.tiles = tiles;
+  return ct;
+}
+
+// in (tree order, ld N) -> out (tree order, ld N): out = M^-1 in (adj = 0) or M^-H in (adj = 1), on Z
+static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj, hipStream_t st) {
+  const Structure& S = H->S;
+  const int64_t N = H->N;
+  ensure_vbuf(H, nrhs);
+  if (H->flev.empty()) {
+    launch_dense_gemv(H->Zinv.p, N, in, H->vtmp2.p, N, nrhs, adj, st);
+    HIPCHK(hipMemcpyAsync(out, H->vtmp2.p, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    check_launch("host.cpp:1314");
+    return;
+  }
+  const int nlev = (int)H->flev.size();
+  // level L vector = input
+  HIPCHK(hipMemcpyAsync(H->vbuf[0].p, in, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  for (int j = 0; j < nlev; ++j) {
+    FactorLevel& F = H->flev[j];
+    LevelPlan& P = H->plans[j];
+    for (int c = 0; c < P.ncol; ++c) {
+      ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
+      launch_fwd_local(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, st);
+      launch_fwd_gather(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, st);
+    }
+    const int npar = S.nclusters(P.l - 1);
+    if (j + 1 < nlev) {
+      FactorLevel& Fp = H->flev[j + 1];
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, H->vbuf[j].p, H->vbuf[j + 1].p, 1,
+                    P.d_nonempty.p, st);
+    } else {
+      std::vector<int64_t> po(H->final_off.begin(), H->final_off.end() - 1);
+      DArr<int64_t> d_po;
+      d_po.upload(po, st);
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, d_po.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp.p, 1,
+                    P.d_nonempty.p, st);
+      launch_dense_gemv(H->Zinv.p, H->nf, H->vtmp.p, H->vtmp2.p, H->nf, nrhs, adj, st);
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, d_po.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp2.p, 0,
+                    P.d_nonempty.p, st);
+      check_launch("host.cpp:1342");
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    check_launch("host.cpp:1345");
+  }
+  for (int j = nlev - 1; j >= 0; --j) {
+    FactorLevel& F = H->flev[j];
+    LevelPlan& P = H->plans[j];
+    if (j + 1 < nlev) {
+      FactorLevel& Fp = H->flev[j + 1];
+      launch_vmerge(S.nclusters(P.l - 1), F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, H->vbuf[j].p,
+                    H->vbuf[j + 1].p, 0, P.d_nonempty.p, st);
+    }
+    for (int c = P.ncol - 1; c >= 0; --c) {
+      ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
+      launch_bwd_local(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, st);
+    }
+    check_launch("host.cpp:1359");
+  }
+  HIPCHK(hipMemcpyAsync(out, H->vbuf[0].p, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+}
+
+// y (tree order) = Z_H2 v (tree order)
+static void matvec_tree(h2_ctx* H, const double2* v, double2* y, int nrhs, hipStream_t st) {
+  const Structure& S = H->S;
+  const int64_t N = H->N;
+  const int L = S.L;
+  launch_near_mv(S.nclusters(L), H->d_near_ptr.p, H->d_near_col.p, H->d_near_off.p, H->near_orig.p,
+                 H->d_leaf_start.p, H->d_leaf_size.p, v, y, N, nrhs, st);
+  check_launch("host.cpp:1371");
+  if (S.l0 < 0) return;
+  for (int l = S.l0; l <= L; ++l) {
+    BuildLevel& B = H->build[L - l];
+    const int nc = S.nclusters(l);
+    if (B.ktot == 0) continue;
+    DArr<double2> xh, yh;
+    xh.alloc(B.ktot * nrhs);
+    yh.alloc(B.ktot * nrhs);
+    launch_basis_mv(nc, B.d_rows.p, B.d_k.p, B.d_voff.p, B.V.p, B.d_cstart.p, v, B.d_xoff.p, xh.p, N, B.ktot, nrhs, 1,
+                    0, st);
+    launch_coupling_mv(nc, B.d_cptr.p, B.d_ccol.p, B.d_soff.p, B.d_k.p, B.d_k.p, B.S.p, B.d_xoff.p, xh.p, B.d_xoff.p,
+                       yh.p, B.ktot, nrhs, st);
+    launch_basis_mv(nc, B.d_rows.p, B.d_k.p, B.d_voff.p, B.V.p, B.d_xoff.p, yh.p, B.d_cstart.p, y, B.ktot, N, nrhs, 0,
+                    1, st);
+    check_launch("host.cpp:1386");
+    HIPCHK(hipStreamSynchronize(st));
+  }
+}
+
+}  // namespace h2
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace h2;
+
+template <typename Fn>
+static h2_status guarded(Fn&& fn) {
+  try {
+    g_err.clear();
+    fn();
+    return H2_OK;
+  } catch (const Fail& f) {
+    g_err = f.msg;
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return H2_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return H2_ERR_INTERNAL;
+  } catch (...) {
+    g_err = "unknown failure";
+    return H2_ERR_INTERNAL;
+  }
+}
+
+static void check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) fail(H2_ERR_DEVICE, "no HIP device available");
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    fail(H2_ERR_DEVICE, std::string("device is ") + prop.gcnArchName + ", the library is built for gfx950");
+  if (prop.sharedMemPerBlock < 140 * 1024)
+    fail(H2_ERR_DEVICE, "device reports " + std::to_string(prop.sharedMemPerBlock) +
+                            " bytes of LDS per workgroup; the eigensolver kernels need 137256");
+}
+
+static void validate_build(const double* points, int64_t n, double k, double h, const double* contrast, int32_t leaf,
+                           double eta, double eps, const h2_options* opt, h2_handle* out) {
+  if (!out) fail(H2_ERR_ARG, "out is NULL");
+  if (!points || !contrast) fail(H2_ERR_ARG, "points or contrast is NULL");
+  if (n < 1) fail(H2_ERR_ARG, "n < 1");
+  if (!(k > 0) || !std::isfinite(k)) fail(H2_ERR_ARG, "k must be finite and > 0");
+  if (!(h > 0) || !std::isfinite(h)) fail(H2_ERR_ARG, "h must be finite and > 0");
+  if (leaf < 1) fail(H2_ERR_ARG, "leaf < 1");
+  if (!(eta >= 0) || !std::isfinite(eta)) fail(H2_ERR_ARG, "eta must be finite and >= 0");
+  if (!(eps > 0 && eps < 1)) fail(H2_ERR_ARG, "eps must lie in (0, 1)");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(contrast[i] > 0) || !std::isfinite(contrast[i])) fail(H2_ERR_ARG, "contrast must be finite and > 0");
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(points[3 * i + d])) fail(H2_ERR_ARG, "points must be finite");
+  }
+  if (opt) {
+    if (opt->struct_size != sizeof(h2_options)) fail(H2_ERR_ARG, "h2_options.struct_size mismatch");
+    if (opt->precision != H2_FP64 && opt->precision != H2_MIXED) fail(H2_ERR_ARG, "unknown precision");
+    if (opt->order != H2_ORDER_COLOR) fail(H2_ERR_ARG, "unknown elimination order");
+    if (!std::isfinite(opt->eps_fill) || opt->eps_fill >= 1) fail(H2_ERR_ARG, "eps_fill must be < 1");
+    if (opt->forced_ranks && (opt->forced_ranks_len < 0 || opt->forced_ranks_len % 4))
+      fail(H2_ERR_ARG, "forced_ranks_len must be a multiple of 4");
+  }
+}
+
+extern "C" h2_status h2_structure(const double* points, int64_t n, double h, int32_t leaf, double eta, int64_t* counts,
+                                  int64_t* perm, int32_t* colours) {
+  return guarded([&] {
+    if (!points || !counts) fail(H2_ERR_ARG, "points or counts is NULL");
+    if (n < 1 || leaf < 1 || !(h > 0) || !(eta >= 0)) fail(H2_ERR_ARG, "invalid size or parameter");
+    Structure S;
+    std::vector<char> msg;
+    if (!build_structure(points, n, h, leaf, eta, S, msg)) fail(H2_ERR_ARG, msg.data());
+    const int L = S.L;
+    int64_t mn = INT64_MAX, mx = 0;
+    for (int64_t s : S.size[L]) {
+      mn = std::min(mn, s);
+      mx = std::max(mx, s);
+    }
+    counts[0] = n;
+    counts[1] = L;
+    counts[2] = S.l0;
+    counts[3] = S.nclusters(L);
+    counts[4] = mn;
+    counts[5] = mx;
+    counts[6] = (int64_t)S.adm[L].size();
+    counts[7] = (int64_t)S.near[L].size();
+    if (perm) std::memcpy(perm, S.perm.data(), n * sizeof(int64_t));
+    if (colours) std::memcpy(colours, S.colour[L].data(), S.colour[L].size() * sizeof(int32_t));
+  });
+}
+
+extern "C" h2_status h2_build(const double* points, int64_t n, double k, double h, const double* contrast, int32_t leaf,
+                              double eta, double eps, const h2_options* opt, void* hip_stream, h2_handle* out) {
+  return guarded([&] {
+    validate_build(points, n, k, h, contrast, leaf, eta, eps, opt, out);
+    *out = nullptr;
+    std::unique_ptr<h2_ctx> H(new h2_ctx());
+    std::vector<char> msg;
+    if (!build_structure(points, n, h, leaf, eta, H->S, msg)) fail(H2_ERR_ARG, msg.data());
+    check_device();
+    hipStream_t st = (hipStream_t)hip_stream;
+    H->N = n;
+    H->k = k;
+    H->h = h;
+    H->eta = eta;
+    H->eps = eps;
+    H->leaf = leaf;
+    H->eps_fill = (opt && opt->eps_fill > 0) ? opt->eps_fill : eps;
+    H->precision = opt ? opt->precision : H2_FP64;
+    const Structure& S = H->S;
+    const int L = S.L;
+    // forced ranks
+    H->lvl_base.assign(L + 2, 0);
+    for (int l = 0; l <= L; ++l) H->lvl_base[l + 1] = H->lvl_base[l] + S.nclusters(l);
+    if (opt && opt->forced_ranks && opt->forced_ranks_len > 0) {
+      H->has_forced = true;
+      H->forced_k.assign(H->lvl_base[L + 1], -1);
+      H->forced_kt.assign(H->lvl_base[L + 1], -1);
+      for (int64_t e = 0; e + 3 < opt->forced_ranks_len; e += 4) {
+        const int32_t l = opt->forced_ranks[e], t = opt->forced_ranks[e + 1];
+        if (l < 0 || l > L || t < 0 || t >= S.nclusters(l)) fail(H2_ERR_ARG, "forced rank entry out of range");
+        H->forced_k[H->lvl_base[l] + t] = opt->forced_ranks[e + 2];
+        H->forced_kt[H->lvl_base[l] + t] = opt->forced_ranks[e + 3];
+      }
+    }
+    // geometry in tree order
+    std::vector<double> pts(3 * n), chi(n), ssolve(n), smat(n);
+    const double h3 = std::pow(h, 3.0);
+    const double k2h3 = k * k * h3;
+    for (int64_t t = 0; t < n; ++t) {
+      const int64_t i = S.perm[t];
+      for (int d = 0; d < 3; ++d) pts[3 * t + d] = points[3 * i + d];
+      chi[t] = contrast[i];
+      smat[t] = k2h3 * contrast[i];
+      ssolve[t] = 1.0 / smat[t];
+    }
+    H->chi_tree = chi;
+    std::vector<int32_t> leafid(n);
+    for (int t = 0; t < S.nclusters(L); ++t)
+      for (int64_t e = 0; e < S.size[L][t]; ++e) leafid[S.start[L][t] + e] = t;
+    H->d_pts.upload(pts, st);
+    H->d_chi.upload(chi, st);
+    H->d_leafid.upload(leafid, st);
+    H->d_perm.upload(S.perm, st);
+    H->d_scale_solve.upload(ssolve, st);
+    H->d_scale_mat.upload(smat, st);
+    const double a = std::cbrt(3.0 / (4.0 * M_PI)) * h;
+    // c = (1 + jka) e^{-jka} - 1
+    const double ka = k * a;
+    const double cr = std::cos(ka), ci = -std::sin(ka);
+    const double self_re = (1.0 * cr - ka * ci) - 1.0;
+    const double self_im = (1.0 * ci + ka * cr);
+    GeomView& g = H->geom;
+    g.pts = H->d_pts.p;
+    g.chi = H->d_chi.p;
+    g.leafid = H->d_leafid.p;
+    g.N = n;
+    g.L = L;
+    g.k = k;
+    g.h = h;
+    g.diag_re_c = self_re;
+    g.diag_im_c = self_im;
+    g.k2h3 = k2h3;
+    if (S.l0 >= 0) {
+      // plans
+      H->plans.clear();
+      H->plans.resize(L - S.l0 + 1);
+      for (int l = L; l >= S.l0; --l) build_plan_level(H.get(), l, H->plans[L - l]);
+      for (int l = L; l >= S.l0; --l)
+        build_merge(H.get(), H->plans[L - l], l > S.l0 ? &H->plans[L - l + 1] : nullptr);
+      for (auto& P : H->plans) upload_plan(P, st);
+    }
+    if (S.l0 >= 0) {
+      construct(H.get(), st);
+    } else {
+      // no admissible block: only the inadmissible leaf blocks (the whole matrix)
+      const auto& nl = S.near[L];
+      H->near_off.assign(nl.size() + 1, 0);
+      for (size_t e = 0; e < nl.size(); ++e)
+        H->near_off[e + 1] = H->near_off[e] + S.size[L][nl[e].first] * S.size[L][nl[e].second];
+      H->near_orig.alloc(H->near_off[nl.size()]);
+      std::vector<int32_t> pr(nl.size()), pc(nl.size()), sz(S.nclusters(L));
+      for (size_t e = 0; e < nl.size(); ++e) {
+        pr[e] = nl[e].first;
+        pc[e] = nl[e].second;
+      }
+      for (int t = 0; t < S.nclusters(L); ++t) sz[t] = (int32_t)S.size[L][t];
+      std::vector<int64_t> cs(S.start[L].begin(), S.start[L].end());
+      DArr<int32_t> d_pr, d_pc;
+      d_pr.upload(pr, st);
+      d_pc.upload(pc, st);
+      H->d_leaf_size.upload(sz, st);
+      H->d_leaf_start.upload(cs, st);
+      H->d_near_off.upload(H->near_off, st);
+      launch_near_blocks(g, d_pr.p, d_pc.p, H->d_near_off.p, H->d_leaf_start.p, H->d_leaf_size.p, H->d_leaf_start.p,
+                         H->d_leaf_size.p, (int)nl.size(), H->near_orig.p, st);
+      check_launch("host.cpp:1590");
+      std::vector<int32_t> nptr(S.nclusters(L) + 1, 0);
+      for (const Pair& p : nl) nptr[p.first + 1]++;
+      for (int t = 0; t < S.nclusters(L); ++t) nptr[t + 1] += nptr[t];
+      H->d_near_ptr.upload(nptr, st);
+      H->d_near_col.upload(pc, st);
+    }
+    H->d_norms.alloc(4096);
+    HIPCHK(hipStreamSynchronize(st));
+    *out = H.release();
+  });
+}
+
+extern "C" h2_status h2_factor(h2_handle H, void* hip_stream) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    try {
+      factor_impl(H, (hipStream_t)hip_stream);
+    } catch (...) {
+      H->factored = false;
+      throw;
+    }
+  });
+}
+
+static void validate_vec(h2_handle H, const void* a, const void* b, int32_t nrhs, int64_t ld) {
+  if (!H) fail(H2_ERR_ARG, "handle is NULL");
+  if (!a || !b) fail(H2_ERR_ARG, "vector pointer is NULL");
+  if (nrhs < 1) fail(H2_ERR_ARG, "nrhs < 1");
+  if (ld < H->N) fail(H2_ERR_ARG, "ld < n");
+}
+
+extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
+                              int32_t max_iter, void* hip_stream, h2_solve_info* info) {
+  return guarded([&] {
+    validate_vec(H, b, x, nrhs, ld);
+    if (!(tol >= 0) || !std::isfinite(tol)) fail(H2_ERR_ARG, "tol must be finite and >= 0");
+    if (tol > 0 && max_iter < 1) fail(H2_ERR_ARG, "max_iter < 1 with tol > 0");
+    if (!H->factored) fail(H2_ERR_STATE, "h2_solve before a successful h2_factor");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t N = H->N;
+    ensure_vbuf(H, nrhs);
+    const double2* bb = (const double2*)b;
+    double2* xx = (double2*)x;
+    // copy of b (b and x may alias)
+    DArr<double2> b0;
+    b0.alloc(N * nrhs);
+    HIPCHK(hipMemcpy2DAsync(b0.p, N * sizeof(double2), bb, ld * sizeof(double2), N * sizeof(double2), nrhs,
+                            hipMemcpyDeviceToDevice, st));
+    auto solve_once = [&](const double2* rhs, int64_t ldr, double2* outx, int64_t ldo, int accumulate) {
+      launch_permute_in(rhs, ldr, H->d_perm.p, nullptr, 0, N, nrhs, H->vtmp3.p, N, st);
+      sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 0, st);
+      launch_permute_out(H->vtmp3.p, N, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, outx, ldo, accumulate, st);
+      check_launch("host.cpp:1643");
+    };
+    solve_once(b0.p, N, xx, ld, 0);
+    if (info) {
+      info->iterations = 0;
+      info->rel_residual = -1.0;
+      info->rel_residual_first = -1.0;
+    }
+    if (tol <= 0) return;
+    // iterative refinement against A_H2 = Z_H2 D
+    DArr<double2> r, ax, vt;
+    r.alloc(N * nrhs);
+    ax.alloc(N * nrhs);
+    vt.alloc(N * nrhs);
+    std::vector<double> nb(nrhs), nr(nrhs);
+    DArr<double> d_nb;
+    d_nb.alloc(nrhs);
+    launch_col_norms(b0.p, N, N, nrhs, d_nb.p, st);
+    HIPCHK(hipMemcpyAsync(nb.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    int it = 0;
+    double rel = 0, first = -1;
+    for (;;) {
+      launch_permute_in(xx, ld, H->d_perm.p, H->d_scale_mat.p, 0, N, nrhs, vt.p, N, st);
+      matvec_tree(H, vt.p, H->vtmp3.p, nrhs, st);
+      launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, ax.p, N, 0, st);
+      launch_residual(b0.p, N, ax.p, N, r.p, N, N, nrhs, st);
+      launch_col_norms(r.p, N, N, nrhs, d_nb.p, st);
+      check_launch("host.cpp:1670");
+      HIPCHK(hipMemcpyAsync(nr.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      rel = 0;
+      for (int c = 0; c < nrhs; ++c) rel = std::max(rel, nb[c] > 0 ? nr[c] / nb[c] : nr[c]);
+      if (first < 0) first = rel;
+      if (rel <= tol || it >= max_iter) break;
+      solve_once(r.p, N, xx, ld, 1);
+      ++it;
+    }
+    if (info) {
+      info->iterations = it;
+      info->rel_residual = rel;
+      info->rel_residual_first = first;
+    }
+    if (rel > tol) fail(H2_ERR_NOCONV, "refinement did not reach tol within max_iter");
+  });
+}
+
+extern "C" h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld,
+                                      void* hip_stream) {
+  return guarded([&] {
+    validate_vec(H, g, lam, nrhs, ld);
+    if (!H->factored) fail(H2_ERR_STATE, "h2_solve_adjoint before a successful h2_factor");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t N = H->N;
+    ensure_vbuf(H, nrhs);
+    launch_permute_in((const double2*)g, ld, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, H->vtmp3.p, N, st);
+    sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 1, st);
+    launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, (double2*)lam, ld, 0, st);
+    check_launch("host.cpp:1700");
+  });
+}
+
+extern "C" h2_status h2_matvec(h2_handle H, const void* x, void* y, int32_t nrhs, int64_t ld, int32_t conj_transpose,
+                               void* hip_stream) {
+  return guarded([&] {
+    validate_vec(H, x, y, nrhs, ld);
+    if (x == y) fail(H2_ERR_ARG, "x and y must not alias");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t N = H->N;
+    DArr<double2> v, w;
+    v.alloc(N * nrhs);
+    w.alloc(N * nrhs);
+    if (!conj_transpose) {
+      launch_permute_in((const double2*)x, ld, H->d_perm.p, H->d_scale_mat.p, 0, N, nrhs, v.p, N, st);
+      matvec_tree(H, v.p, w.p, nrhs, st);
+      launch_permute_out(w.p, N, H->d_perm.p, nullptr, 0, N, nrhs, (double2*)y, ld, 0, st);
+    } else {
+      launch_permute_in((const double2*)x, ld, H->d_perm.p, nullptr, 1, N, nrhs, v.p, N, st);
+      matvec_tree(H, v.p, w.p, nrhs, st);
+      launch_permute_out(w.p, N, H->d_perm.p, H->d_scale_mat.p, 1, N, nrhs, (double2*)y, ld, 0, st);
+    }
+    check_launch("host.cpp:1723");
+    HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+extern "C" void h2_destroy(h2_handle H) {
+  try {
+    delete H;
+  } catch (...) {
+  }
+}
+
+extern "C" const char* h2_last_error(void) { return g_err.c_str(); }
+
+extern "C" h2_status h2_stats(h2_handle H, int64_t* out, int32_t rows_cap, int32_t* rows) {
+  return guarded([&] {
+    if (!H || !out || !rows) fail(H2_ERR_ARG, "NULL argument");
+    if (!H->factored) fail(H2_ERR_STATE, "h2_stats before h2_factor");
+    const int nr = (int)H->stats_rows.size();
+    *rows = nr;
+    for (int r = 0; r < std::min(nr, (int)rows_cap); ++r)
+      for (int c = 0; c < 10; ++c) out[10 * r + c] = H->stats_rows[r][c];
+  });
+}
+
+extern "C" h2_status h2_forced_ranks_layout(h2_handle H, int32_t* out, int64_t cap, int64_t* count) {
+  return guarded([&] {
+    if (!H || !count) fail(H2_ERR_ARG, "NULL argument");
+    const Structure& S = H->S;
+    int64_t cnt = 0;
+    if (S.l0 >= 0) {
+      for (int l = S.L; l >= S.l0; --l) {
+        const int j = S.L - l;
+        for (int t = 0; t < S.nclusters(l); ++t) {
+          if (S.size[l][t] == 0) continue;
+          if (out && cnt < cap) {
+            out[4 * cnt] = l;
+            out[4 * cnt + 1] = t;
+            out[4 * cnt + 2] = H->build[j].k[t];
+            out[4 * cnt + 3] = (H->factored && j < (int)H->flev.size()) ? H->flev[j].kt[t] : -1;
+          }
+          ++cnt;
+        }
+      }
+    }
+    *count = cnt;
+  });
+}
+
+extern "C" h2_status h2_factor_timing(h2_handle H, double* out, int32_t n_out) {
+  return guarded([&] {
+    if (!H || !out || n_out < 6) fail(H2_ERR_ARG, "invalid argument");
+    if (!H->factored) fail(H2_ERR_STATE, "h2_factor_timing before h2_factor");
+    for (int i = 0; i < 6; ++i) out[i] = H->timing[i];
+    for (int i = 6; i < std::min<int32_t>(n_out, 10); ++i) out[i] = H->ledger.size() > (size_t)i ? H->ledger[i] : 0.0;
+  });
+}

@@ -1,0 +1,1515 @@
+// gfx950 kernels of the H^2 direct solver.
+//
+// Layout conventions: complex double ("double2") matrices are column-major;
+// every cluster / block / panel lives in a packed arena at an element offset
+// given per object.  Inside a cluster the coordinates after Steps 0-2 are
+// "kept first": Q~ = [B  B_add  B~perp], so the k~ kept coordinates occupy
+// rows [0, k~) and the r = n - k~ eliminated ones rows [k~, n).
+#include <hip/hip_runtime.h>
+
+#include "h2_device.hpp"
+#include "h2_kernels.hpp"
+
+namespace h2 {
+
+static inline __host__ __device__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+// ===========================================================================
+// VIE matrix entries Z = A D^-1 (generated on the fly)
+// ===========================================================================
+__device__ __forceinline__ double2 zentry(const GeomView& g, int64_t x, int64_t y) {
+  if (x == y) {
+    const double c = g.chi[x];
+    const double den = g.k2h3 * c;  // k^2 h^3 chi
+    return make_double2((1.0 + c * g.diag_re_c) / den, (c * g.diag_im_c) / den);
+  }
+  const double dx = g.pts[3 * x] - g.pts[3 * y];
+  const double dy = g.pts[3 * x + 1] - g.pts[3 * y + 1];
+  const double dz = g.pts[3 * x + 2] - g.pts[3 * y + 2];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double s, c;
+  sincos(g.k * r, &s, &c);
+  const double den = 4.0 * M_PI * r;
+  return make_double2(c / den, -s / den);
+}
+
+__device__ __forceinline__ bool near_bit(const uint32_t* mask, int64_t nc, int64_t a, int64_t b) {
+  const int64_t bit = a * nc + b;
+  return (mask[bit >> 5] >> (bit & 31)) & 1u;
+}
+
+// Entry of Z masked to the far field at `level`: zero where the level-`level`
+// clusters of x and y form an inadmissible pair.
+__device__ __forceinline__ double2 zmasked(const GeomView& g, const uint32_t* mask, int level, int64_t x,
+                                           int64_t y) {
+  const int sh = g.L - level;
+  const int64_t cx = g.leafid[x] >> sh, cy = g.leafid[y] >> sh;
+  if (near_bit(mask, (int64_t)1 << level, cx, cy)) return make_double2(0.0, 0.0);
+  return zentry(g, x, y);
+}
+
+__global__ void __launch_bounds__(256) k_near_blocks(GeomView g, const int32_t* pr, const int32_t* pc,
+                                                     const int64_t* off, const int64_t* rs,
+                                                     const int32_t* rn, const int64_t* cs,
+                                                     const int32_t* cn, double2* out) {
+  const int p = blockIdx.x;
+  const int a = pr[p], b = pc[p];
+  const int m = rn[a], n = cn[b];
+  const int64_t r0 = rs[a], c0 = cs[b];
+  double2* o = out + off[p];
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    o[e] = zentry(g, r0 + i, c0 + j);
+  }
+}
+
+void launch_near_blocks(const GeomView& g, const int32_t* pr, const int32_t* pc, const int64_t* off,
+                        const int64_t* rs, const int32_t* rn, const int64_t* cs, const int32_t* cn,
+                        int npairs, double2* out, hipStream_t st) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_near_blocks, dim3(npairs), dim3(256), 0, st, g, pr, pc, off, rs, rn, cs, cn, out);
+}
+
+// ---------------------------------------------------------------------------
+// Leaf far-field Gram G_t = sum_y Zm(t, y) Zm(t, y)^H, split over column chunks.
+// grid: (cluster, tile(2x2), chunk)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_leaf_gram(GeomView g, const uint32_t* mask, int level,
+                                                   const int64_t* cstart, const int32_t* csize,
+                                                   int64_t kchunk, double2* part, int64_t stride,
+                                                   const int64_t* goff, int ntr) {
+  __shared__ TileSmem<double> s;
+  const int t = blockIdx.x, tile = blockIdx.y, ch = blockIdx.z;
+  const int n = csize[t];
+  const int tr = tile % ntr, tc = tile / ntr;
+  if (tr * 64 >= n || tc * 64 >= n) return;
+  const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
+  const int64_t k_begin = (int64_t)ch * kchunk;
+  const int64_t k_end = min(g.N, k_begin + kchunk);
+  const int64_t row_a = cstart[t] + tr * 64, row_b = cstart[t] + tc * 64;
+  TileAcc<double> acc;
+  acc.zero();
+  for (int64_t k0 = k_begin; k0 < k_end; k0 += TK) {
+    __syncthreads();
+    {
+      const int th = threadIdx.x;
+      const int kk = th & 15;
+      const int64_t y = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = (th >> 4) + 16 * e;
+        double2 v = make_double2(0, 0);
+        if (i < m && y < k_end) v = zmasked(g, mask, level, row_a + i, y);
+        s.are[kk][i] = v.x;
+        s.aim[kk][i] = v.y;
+        double2 w = v;
+        if (tr != tc) {
+          w = make_double2(0, 0);
+          if (i < nn && y < k_end) w = zmasked(g, mask, level, row_b + i, y);
+        } else if (i >= nn) {
+          w = make_double2(0, 0);
+        }
+        s.bre[kk][i] = w.x;
+        s.bim[kk][i] = -w.y;
+      }
+    }
+    __syncthreads();
+    mma_slab<double>(s, acc);
+  }
+  double2* G = part + (int64_t)ch * stride + goff[t] + tr * 64 + (int64_t)tc * 64 * n;
+  store_tile<double, double2>(acc, G, n, m, nn, ST_SET);
+}
+
+void launch_leaf_gram(const GeomView& g, const uint32_t* mask, int ncl, int level, const int64_t* cstart,
+                      const int32_t* csize, int64_t kchunk, int nchunks, double2* part, int64_t stride,
+                      const int64_t* goff, int ntr, hipStream_t st) {
+  if (ncl <= 0) return;
+  hipLaunchKernelGGL(k_leaf_gram, dim3(ncl, ntr * ntr, nchunks), dim3(256), 0, st, g, mask, level, cstart,
+                     csize, kchunk, part, stride, goff, ntr);
+}
+
+__global__ void k_gram_reduce(const double2* part, double2* out, int64_t total, int nchunks,
+                              int64_t stride) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = part[e];
+    for (int c = 1; c < nchunks; ++c) a = cadd(a, part[(int64_t)c * stride + e]);
+    out[e] = a;
+  }
+}
+
+void launch_gram_reduce(const double2* part, double2* out, const int64_t* off, const int32_t* sz, int ncl,
+                        int nchunks, int64_t stride, hipStream_t st) {
+  (void)off;
+  (void)sz;
+  (void)ncl;
+  if (stride <= 0) return;
+  int blocks = (int)imin64(4096, (stride + 255) / 256);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(blocks), dim3(256), 0, st, part, out, stride, nchunks, stride);
+}
+
+// ---------------------------------------------------------------------------
+// Non-leaf construction rows: Y_c = V_c^H Zm(c, J) for children c (K = #c),
+// written into the stacked row block of the parent.  grid: (child, tiles)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_proj_rows(GeomView g, const uint32_t* mask, int level,
+                                                   const int64_t* cstart, const int32_t* csize,
+                                                   const int32_t* ck, const int64_t* voff,
+                                                   const double2* V, const int64_t* yoff,
+                                                   const int32_t* yld, double2* Y, int64_t col0,
+                                                   int ncols, int ntr) {
+  __shared__ TileSmem<double> s;
+  const int c = blockIdx.x;
+  const int kc = ck[c];
+  const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
+  if (tr * 64 >= kc || tc * 64 >= ncols) return;
+  const int m = min(64, kc - tr * 64), nn = min(64, ncols - tc * 64);
+  const int K = csize[c];
+  const double2* A = V + voff[c] + (int64_t)tr * 64 * K;  // op C of V_c (#c x k_c, ld #c)
+  const int64_t x0 = cstart[c];
+  const int64_t y0 = col0 + tc * 64;
+  TileAcc<double> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    __syncthreads();
+    load_a<double, double2>(s, A, K, OP_C, m, K, k0);
+    {
+      const int th = threadIdx.x;
+      const int kk = th & 15;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = (th >> 4) + 16 * e;
+        double2 v = make_double2(0, 0);
+        if (j < nn && k < K) v = zmasked(g, mask, level, x0 + k, y0 + j);
+        s.bre[kk][j] = v.x;
+        s.bim[kk][j] = v.y;
+      }
+    }
+    __syncthreads();
+    mma_slab<double>(s, acc);
+  }
+  double2* out = Y + yoff[c] + tr * 64 + (int64_t)tc * 64 * yld[c];
+  store_tile<double, double2>(acc, out, yld[c], m, nn, ST_SET);
+}
+
+void launch_proj_rows(const GeomView& g, const uint32_t* mask, int level, int nch, const int64_t* cstart,
+                      const int32_t* csize, const int32_t* ck, const int64_t* voff, const double2* V,
+                      const int64_t* yoff, const int32_t* yld, double2* Y, int64_t col0, int ncols,
+                      int ntr, hipStream_t st) {
+  if (nch <= 0) return;
+  const int tiles = ntr * ((ncols + 63) / 64);
+  hipLaunchKernelGGL(k_proj_rows, dim3(nch, tiles), dim3(256), 0, st, g, mask, level, cstart, csize, ck,
+                     voff, V, yoff, yld, Y, col0, ncols, ntr);
+}
+
+// G_t (d x d) += Y_t Y_t^H over ncols columns (Y_t ld = d).  grid: (cluster, 2x2 tiles)
+__global__ void __launch_bounds__(256) k_gram_acc(const int32_t* dim, const int64_t* yoff, const double2* Y,
+                                                  int ncols, const int64_t* goff, double2* G, int ntr) {
+  __shared__ TileSmem<double> s;
+  const int t = blockIdx.x;
+  const int d = dim[t];
+  const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
+  if (tr * 64 >= d || tc * 64 >= d) return;
+  const int m = min(64, d - tr * 64), nn = min(64, d - tc * 64);
+  const double2* Yt = Y + yoff[t];
+  TileAcc<double> acc;
+  acc.zero();
+  gemm_tile<double, double2>(s, acc, Yt + tr * 64, d, OP_N, Yt + tc * 64, d, OP_C, m, nn, ncols);
+  store_tile<double, double2>(acc, G + goff[t] + tr * 64 + (int64_t)tc * 64 * d, d, m, nn, ST_ADD);
+}
+
+void launch_gram_acc(int ncl, const int32_t* dim, const int64_t* yoff, const double2* Y, int ncols,
+                     const int64_t* goff, double2* G, int ntr, hipStream_t st) {
+  if (ncl <= 0) return;
+  hipLaunchKernelGGL(k_gram_acc, dim3(ncl, ntr * ntr), dim3(256), 0, st, dim, yoff, Y, ncols, goff, G, ntr);
+}
+
+// X_ts = V_t^H Z(t, s) (k_t x #s) for admissible pairs.  grid: (pair, tiles)
+__global__ void __launch_bounds__(256) k_coupling_x(GeomView g, const int32_t* pt, const int32_t* ps,
+                                                    const int64_t* tstart, const int32_t* tsz,
+                                                    const int32_t* tk, const int64_t* voff,
+                                                    const double2* V, const int64_t* xoff, double2* X,
+                                                    int ntr) {
+  __shared__ TileSmem<double> s;
+  const int p = blockIdx.x;
+  const int t = pt[p], u = ps[p];
+  const int kt = tk[t], K = tsz[t], ns = tsz[u];
+  const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
+  if (tr * 64 >= kt || tc * 64 >= ns) return;
+  const int m = min(64, kt - tr * 64), nn = min(64, ns - tc * 64);
+  const double2* A = V + voff[t] + (int64_t)tr * 64 * K;
+  const int64_t x0 = tstart[t], y0 = tstart[u] + tc * 64;
+  TileAcc<double> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < K; k0 += TK) {
+    __syncthreads();
+    load_a<double, double2>(s, A, K, OP_C, m, K, k0);
+    {
+      const int th = threadIdx.x;
+      const int kk = th & 15;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = (th >> 4) + 16 * e;
+        double2 v = make_double2(0, 0);
+        if (j < nn && k < K) v = zentry(g, x0 + k, y0 + j);
+        s.bre[kk][j] = v.x;
+        s.bim[kk][j] = v.y;
+      }
+    }
+    __syncthreads();
+    mma_slab<double>(s, acc);
+  }
+  store_tile<double, double2>(acc, X + xoff[p] + tr * 64 + (int64_t)tc * 64 * kt, kt, m, nn, ST_SET);
+}
+
+void launch_coupling_x(const GeomView& g, int npairs, int ntr, int ntc, const int32_t* pt, const int32_t* ps,
+                       const int64_t* tstart, const int32_t* tsz, const int32_t* tk, const int64_t* voff,
+                       const double2* V, const int64_t* xoff, double2* X, hipStream_t st) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_coupling_x, dim3(npairs, ntr * ntc), dim3(256), 0, st, g, pt, ps, tstart, tsz, tk, voff,
+                     V, xoff, X, ntr);
+}
+
+// ===========================================================================
+// Generic host-resolved batched GEMM
+// ===========================================================================
+__global__ void __launch_bounds__(256) k_gemm_batched(const GemmTask* tasks, const int32_t* tile_task,
+                                                      const int32_t* tile_rc) {
+  __shared__ TileSmem<double> s;
+  const GemmTask T = tasks[tile_task[blockIdx.x]];
+  const int rc = tile_rc[blockIdx.x];
+  const int tr = rc & 0xffff, tc = rc >> 16;
+  const int m = min(64, T.m - tr * 64), n = min(64, T.n - tc * 64);
+  if (m <= 0 || n <= 0) return;
+  const double2* A = (T.opA == OP_N || T.opA == OP_R) ? T.A + tr * 64 : T.A + (int64_t)tr * 64 * T.lda;
+  const double2* B = (T.opB == OP_N || T.opB == OP_R) ? T.B + (int64_t)tc * 64 * T.ldb : T.B + tc * 64;
+  TileAcc<double> acc;
+  acc.zero();
+  gemm_tile<double, double2>(s, acc, A, T.lda, T.opA, B, T.ldb, T.opB, m, n, T.K);
+  store_tile<double, double2>(acc, T.C + tr * 64 + (int64_t)tc * 64 * T.ldc, T.ldc, m, n, T.mode);
+}
+
+void launch_gemm_batched(const GemmTask* tasks, const int32_t* tile_task, const int32_t* tile_rc, int ntiles,
+                         hipStream_t st) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_gemm_batched, dim3(ntiles), dim3(256), 0, st, tasks, tile_task, tile_rc);
+}
+
+// C = A^T for each task (A m x n, ld lda -> C n x m, ld ldc)
+__global__ void k_transpose_copy(const GemmTask* tasks) {
+  const GemmTask T = tasks[blockIdx.x];
+  for (int e = threadIdx.x; e < T.m * T.n; e += blockDim.x) {
+    const int i = e % T.m, j = e / T.m;
+    T.C[j + (int64_t)i * T.ldc] = T.A[i + (int64_t)j * T.lda];
+  }
+}
+
+void launch_transpose_copy(const GemmTask* tasks, int ntasks, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_transpose_copy, dim3(ntasks), dim3(256), 0, st, tasks);
+}
+
+// ===========================================================================
+// Cyclic Jacobi eigensolver for small Hermitian matrices
+// ===========================================================================
+struct Rot {
+  double c, s;
+  double2 e;  // unit phase of the off-diagonal entry
+};
+
+__device__ __forceinline__ void rr_pair(int k, int round, int m, int& p, int& q) {
+  auto pl = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (m - 1)); };
+  const int a = pl(k), b = pl(m - 1 - k);
+  p = min(a, b);
+  q = max(a, b);
+}
+
+// Diagonalise the m x m (m even, padded) Hermitian matrix A (ld m) in place,
+// accumulating U (ld m, starts as identity).  256 threads.
+__device__ void jacobi_core(double2* A, double2* U, int m, int rel, Rot* rot, int* flag, double fro) {
+  const int tid = threadIdx.x;
+  const int h = m / 2;
+  const double tol_abs = 2e-17 * fro;
+  for (int sweep = 0; sweep < 24; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < h) {
+        int p, q;
+        rr_pair(tid, round, m, p, q);
+        const double a = A[p + p * m].x, d = A[q + q * m].x;
+        const double2 b = A[p + q * m];
+        const double bb = sqrt(cabs2(b));
+        bool go = rel ? (bb > 2.2e-16 * sqrt(fabs(a * d)) && bb > 1e-300) : (bb > tol_abs);
+        Rot R;
+        if (go) {
+          const double th = (d - a) / (2.0 * bb);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          R.c = 1.0 / sqrt(t * t + 1.0);
+          R.s = t * R.c;
+          R.e = make_double2(b.x / bb, b.y / bb);
+          *flag = 1;
+        } else {
+          R.c = 1.0;
+          R.s = 0.0;
+          R.e = make_double2(1.0, 0.0);
+        }
+        rot[tid] = R;
+      }
+      __syncthreads();
+      // two-sided update on 2x2 blocks (P <= Q); one block per work item
+      for (int w = tid; w < h * h; w += blockDim.x) {
+        const int P = w / h, Qi = w % h;
+        if (P > Qi) continue;
+        int p1, q1, p2, q2;
+        rr_pair(P, round, m, p1, q1);
+        rr_pair(Qi, round, m, p2, q2);
+        const Rot a = rot[P], b = rot[Qi];
+        const double2 x00 = A[p1 + p2 * m], x01 = A[p1 + q2 * m], x10 = A[q1 + p2 * m], x11 = A[q1 + q2 * m];
+        // left: J_P^H X ; J^H = [[c, -s e], [s, c e]]
+        const double2 se = make_double2(a.s * a.e.x, a.s * a.e.y), ce = make_double2(a.c * a.e.x, a.c * a.e.y);
+        double2 y00 = make_double2(a.c * x00.x, a.c * x00.y), y01 = make_double2(a.c * x01.x, a.c * x01.y);
+        y00 = csub(y00, cmul(se, x10));
+        y01 = csub(y01, cmul(se, x11));
+        double2 y10 = cadd(make_double2(a.s * x00.x, a.s * x00.y), cmul(ce, x10));
+        double2 y11 = cadd(make_double2(a.s * x01.x, a.s * x01.y), cmul(ce, x11));
+        // right: Y J_Q ; J = [[c, s], [-s conj(e), c conj(e)]]
+        const double2 sec = make_double2(b.s * b.e.x, -b.s * b.e.y), cec = make_double2(b.c * b.e.x, -b.c * b.e.y);
+        double2 z00 = csub(make_double2(b.c * y00.x, b.c * y00.y), cmul(sec, y01));
+        double2 z01 = cadd(make_double2(b.s * y00.x, b.s * y00.y), cmul(cec, y01));
+        double2 z10 = csub(make_double2(b.c * y10.x, b.c * y10.y), cmul(sec, y11));
+        double2 z11 = cadd(make_double2(b.s * y10.x, b.s * y10.y), cmul(cec, y11));
+        if (P == Qi) {
+          z00.y = 0.0;
+          z11.y = 0.0;
+          if (a.s != 0.0) {
+            z01 = make_double2(0.0, 0.0);
+            z10 = make_double2(0.0, 0.0);
+          } else {
+            z10 = cconj(z01);
+          }
+          A[p1 + p1 * m] = z00;
+          A[p1 + q1 * m] = z01;
+          A[q1 + p1 * m] = z10;
+          A[q1 + q1 * m] = z11;
+        } else {
+          A[p1 + p2 * m] = z00;
+          A[p1 + q2 * m] = z01;
+          A[q1 + p2 * m] = z10;
+          A[q1 + q2 * m] = z11;
+          A[p2 + p1 * m] = cconj(z00);
+          A[q2 + p1 * m] = cconj(z01);
+          A[p2 + q1 * m] = cconj(z10);
+          A[q2 + q1 * m] = cconj(z11);
+        }
+      }
+      // U <- U J for every row and pair
+      for (int w = tid; w < m * h; w += blockDim.x) {
+        const int row = w % m, Qi = w / m;
+        int p, q;
+        rr_pair(Qi, round, m, p, q);
+        const Rot b = rot[Qi];
+        if (b.s == 0.0) continue;
+        const double2 up = U[row + p * m], uq = U[row + q * m];
+        const double2 sec = make_double2(b.s * b.e.x, -b.s * b.e.y), cec = make_double2(b.c * b.e.x, -b.c * b.e.y);
+        U[row + p * m] = csub(make_double2(b.c * up.x, b.c * up.y), cmul(sec, uq));
+        U[row + q * m] = cadd(make_double2(b.s * up.x, b.s * up.y), cmul(cec, uq));
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (*flag == 0) break;
+    __syncthreads();
+  }
+}
+
+// Shared driver: copy G (d x d, ld ldg) into the padded work matrix, run Jacobi,
+// write sorted eigenvalues (descending) and eigenvectors (ld ldu).
+__device__ void jacobi_solve(const double2* G, int ldg, int d, double2* A, double2* Uw, double* lam,
+                             double2* Uout, int ldu, int rel, Rot* rot, int* flag, double* red) {
+  const int m = d + (d & 1);
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  for (int e = tid; e < m * m; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    double2 v = make_double2(0, 0);
+    if (i < d && j < d) v = G[i + (int64_t)j * ldg];
+    if (i == j) v.y = 0.0;
+    A[e] = v;
+    Uw[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    part += cabs2(v);
+  }
+  const double fro = sqrt(block_sum256(part, red));
+  __syncthreads();
+  if (m >= 2) jacobi_core(A, Uw, m, rel, rot, flag, fro);
+  __syncthreads();
+  // sort descending (stable by index)
+  for (int j = tid; j < d; j += blockDim.x) {
+    const double lj = A[j + j * m].x;
+    int pos = 0;
+    for (int i = 0; i < d; ++i) {
+      const double li = A[i + i * m].x;
+      pos += (li > lj) || (li == lj && i < j);
+    }
+    lam[pos] = lj;
+    for (int r = 0; r < d; ++r) Uout[r + (int64_t)pos * ldu] = Uw[r + j * m];
+  }
+  __syncthreads();
+}
+
+constexpr int JLDS = 64;  // matrices up to 64 x 64 are diagonalised in LDS
+
+__global__ void __launch_bounds__(256) k_jacobi(const int32_t* dims, const int64_t* goff, double2* G,
+                                                const int64_t* uoff, double2* U, const int64_t* loff,
+                                                double* lam, int rel, double2* scratch, const int64_t* soff) {
+  __shared__ double2 sA[JLDS * JLDS];
+  __shared__ double2 sU[JLDS * JLDS];
+  __shared__ Rot rot[JLDS];
+  __shared__ int flag;
+  __shared__ double red[4];
+  const int p = blockIdx.x;
+  const int d = dims[p];
+  if (d <= 0) return;
+  double2 *A = sA, *Uw = sU;
+  if (d > JLDS) {
+    A = scratch + soff[p];
+    Uw = A + (int64_t)(d + 1) * (d + 1);
+  }
+  Rot* rp = rot;
+  // rotations for m/2 pairs: for m > 64 reuse the LDS slot budget (m/2 <= 128 needs 128 entries)
+  __shared__ Rot rot_big[128];
+  if (d > JLDS) rp = rot_big;
+  jacobi_solve(G + goff[p], d, d, A, Uw, lam + loff[p], U + uoff[p], d, rel, rp, &flag, red);
+}
+
+void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2* G, const int64_t* uoff,
+                   double2* U, const int64_t* loff, double* lam, int rel, double2* scratch,
+                   const int64_t* soff, hipStream_t st) {
+  if (nprob <= 0) return;
+  hipLaunchKernelGGL(k_jacobi, dim3(nprob), dim3(256), 0, st, dims, goff, G, uoff, U, loff, lam, rel, scratch,
+                     soff);
+}
+
+// ===========================================================================
+// Factorization level kernels
+// ===========================================================================
+__device__ __forceinline__ int dim_before(const LevelView& v, int a, int c) {
+  return v.colour[a] < c ? v.kt[a] : v.n[a];
+}
+__device__ __forceinline__ int dim_after(const LevelView& v, int a, int c) {
+  return v.colour[a] <= c ? v.kt[a] : v.n[a];
+}
+
+// B_perp: orthonormal complement of the basis B (n x k) through Householder QR.
+__global__ void __launch_bounds__(256) k_householder_perp(LevelView v) {
+  __shared__ double2 sA[64 * 64];
+  __shared__ double2 tau[128];
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  const int n = v.n[i], k = v.k[i], d = n - k;
+  if (n == 0 || d == 0) return;
+  double2* E = v.Bp + v.bp_off[i];  // n x d output
+  double2* A = (n <= 64) ? sA : v.W + v.w_off[i];  // working copy of B (n x k)
+  const double2* B = v.B + v.b_off[i];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < n * k; e += blockDim.x) A[e] = B[e];
+  for (int e = tid; e < n * d; e += blockDim.x) {
+    const int r = e % n, c = e / n;
+    E[e] = make_double2(r == k + c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double part = 0.0;
+    for (int r = j + 1 + tid; r < n; r += blockDim.x) part += cabs2(A[r + j * n]);
+    const double sigma = block_sum256(part, red);
+    const double2 alpha = A[j + j * n];
+    double2 t = make_double2(0, 0);
+    if (sigma > 0.0 || alpha.y != 0.0) {
+      const double beta = -copysign(sqrt(cabs2(alpha) + sigma), alpha.x);
+      t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      // scale = 1 / (alpha - beta)
+      const double2 den = make_double2(alpha.x - beta, alpha.y);
+      const double dd = cabs2(den);
+      const double2 sc = make_double2(den.x / dd, -den.y / dd);
+      __syncthreads();
+      for (int r = j + 1 + tid; r < n; r += blockDim.x) A[r + j * n] = cmul(A[r + j * n], sc);
+      if (tid == 0) A[j + j * n] = make_double2(beta, 0.0);
+    }
+    if (tid == 0) tau[j] = t;
+    __syncthreads();
+    // apply H^H = I - conj(tau) v v^H to the trailing columns
+    if (t.x != 0.0 || t.y != 0.0) {
+      for (int c = j + 1 + wv; c < k; c += 4) {
+        double2 w = make_double2(0, 0);
+        for (int r = j + lane; r < n; r += 64) {
+          const double2 vr = (r == j) ? make_double2(1, 0) : A[r + j * n];
+          w = cadd(w, cmulc(vr, A[r + c * n]));
+        }
+        w.x = wave_sum(w.x);
+        w.y = wave_sum(w.y);
+        const double2 f = cmul(cconj(t), w);
+        for (int r = j + lane; r < n; r += 64) {
+          const double2 vr = (r == j) ? make_double2(1, 0) : A[r + j * n];
+          A[r + c * n] = csub(A[r + c * n], cmul(vr, f));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // E <- H_0 ... H_{k-1} [0; I]
+  for (int j = k - 1; j >= 0; --j) {
+    const double2 t = tau[j];
+    if (t.x == 0.0 && t.y == 0.0) continue;
+    for (int c = wv; c < d; c += 4) {
+      double2 w = make_double2(0, 0);
+      for (int r = j + lane; r < n; r += 64) {
+        const double2 vr = (r == j) ? make_double2(1, 0) : A[r + j * n];
+        w = cadd(w, cmulc(vr, E[r + c * n]));
+      }
+      w.x = wave_sum(w.x);
+      w.y = wave_sum(w.y);
+      const double2 f = cmul(t, w);
+      for (int r = j + lane; r < n; r += 64) {
+        const double2 vr = (r == j) ? make_double2(1, 0) : A[r + j * n];
+        E[r + c * n] = csub(E[r + c * n], cmul(vr, f));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_householder_perp(const LevelView& v, int nc, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_householder_perp, dim3(nc), dim3(256), 0, st, v);
+}
+
+// Step 0 Gram of the fill-ins in block row i: H_i = sum_b F_ib F_ib^H.
+__global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c) {
+  __shared__ TileSmem<double> s;
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i];
+  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  if (tr * 64 >= n || tc * 64 >= n) return;
+  const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
+  TileAcc<double> acc;
+  acc.zero();
+  for (int j = v.fp_ptr[i]; j < v.fp_ptr[i + 1]; ++j) {
+    const int b = v.fp_cl[j];
+    const double2* F = v.slots + v.slot_off[v.fp_srow[j]];
+    const int mb = dim_before(v, b, c.colour);
+    gemm_tile<double, double2>(s, acc, F + tr * 64, n, OP_N, F + tc * 64, n, OP_C, m, nn, mb);
+  }
+  store_tile<double, double2>(acc, v.W + v.w_off[i] + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
+}
+
+void launch_gram_fill(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_gram_fill, dim3(c.ncl, c.tiles * c.tiles), dim3(256), 0, st, v, c);
+}
+
+// phase 0: X = H B_perp ; phase 1: G' = B_perp^H X ; phase 2: Q~[:, k:n] = B_perp U'
+__global__ void __launch_bounds__(256) k_xform(LevelView v, ColourTasks c, int phase) {
+  __shared__ TileSmem<double> s;
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], k = v.k[i], d = n - k;
+  if (d <= 0) return;
+  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  double2* W = v.W + v.w_off[i];
+  const double2* H = W;
+  double2* X = W + (int64_t)n * n;
+  double2* Gp = X + (int64_t)n * d;
+  double2* Up = Gp + (int64_t)d * d;
+  const double2* Bp = v.Bp + v.bp_off[i];
+  TileAcc<double> acc;
+  acc.zero();
+  if (phase == 0) {
+    if (tr * 64 >= n || tc * 64 >= d) return;
+    const int m = min(64, n - tr * 64), nn = min(64, d - tc * 64);
+    gemm_tile<double, double2>(s, acc, H + tr * 64, n, OP_N, Bp + (int64_t)tc * 64 * n, n, OP_N, m, nn, n);
+    store_tile<double, double2>(acc, X + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
+  } else if (phase == 1) {
+    if (tr * 64 >= d || tc * 64 >= d) return;
+    const int m = min(64, d - tr * 64), nn = min(64, d - tc * 64);
+    gemm_tile<double, double2>(s, acc, Bp + (int64_t)tr * 64 * n, n, OP_C, X + (int64_t)tc * 64 * n, n, OP_N, m,
+                               nn, n);
+    store_tile<double, double2>(acc, Gp + tr * 64 + (int64_t)tc * 64 * d, d, m, nn, ST_SET);
+  } else {
+    if (tr * 64 >= n || tc * 64 >= d) return;
+    const int m = min(64, n - tr * 64), nn = min(64, d - tc * 64);
+    gemm_tile<double, double2>(s, acc, Bp + tr * 64, n, OP_N, Up + (int64_t)tc * 64 * d, d, OP_N, m, nn, d);
+    double2* Qc = v.Q + v.q_off[i] + (int64_t)k * n;
+    store_tile<double, double2>(acc, Qc + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
+  }
+}
+
+void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_xform, dim3(c.ncl, c.tiles * c.tiles), dim3(256), 0, st, v, c, phase);
+}
+
+// Step 0 eigen-decomposition of G' = B_perp^H H B_perp, rank decision, Q~[:, 0:k] = B.
+__global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, double2* scratch) {
+  __shared__ double2 sA[JLDS * JLDS];
+  __shared__ double2 sU[JLDS * JLDS];
+  __shared__ Rot rot[128];
+  __shared__ double lam[256];
+  __shared__ int flag;
+  __shared__ double red[4];
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], k = v.k[i], d = n - k;
+  const int tid = threadIdx.x;
+  double2* Q = v.Q + v.q_off[i];
+  const double2* B = v.B + v.b_off[i];
+  for (int e = tid; e < n * k; e += blockDim.x) Q[e] = B[e];
+  int p = 0;
+  if (d > 0) {
+    double2* W = v.W + v.w_off[i];
+    double2* Gp = W + (int64_t)n * n + (int64_t)n * d;
+    double2* Up = Gp + (int64_t)d * d;
+    double2 *A = sA, *Uw = sU;
+    if (d > JLDS) {
+      A = scratch + (int64_t)blockIdx.x * 2 * 130 * 130;
+      Uw = A + 130 * 130;
+    }
+    jacobi_solve(Gp, d, d, A, Uw, lam, Up, d, 0, rot, &flag, red);
+    const double s1 = sqrt(fmax(lam[0], 0.0));
+    const double tau = v.eps_fill * fmax(v.nu[i], s1);
+    if (tau > 0.0) {
+      for (int j = 0; j < d; ++j)
+        if (sqrt(fmax(lam[j], 0.0)) > tau) p = j + 1;
+    }
+    if (tid == 0 && v.margins) {
+      v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(lam[p - 1], 0.0)) / tau : 1e300;
+      v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(lam[p], 0.0)) / tau : 0.0;
+    }
+  }
+  if (v.forced && v.forced[i] >= 0) p = min(max(v.forced[i] - k, 0), d);
+  if (tid == 0) v.kt[i] = k + p;
+}
+
+void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_step0_eig, dim3(c.ncl), dim3(256), 0, st, v, c, scratch);
+}
+
+// Step 2 projections.  side 0: T = (x in colour ? Q~_x^H : I) Z ; side 1: Z = T (y in colour ? conj(Q~_y) : I)
+__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side) {
+  __shared__ TileSmem<double> s;
+  const int task = blockIdx.x;
+  const int sl = c.pj_slot[task];
+  const int x = v.slot_a[sl], y = v.slot_b[sl];
+  const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
+  const int nx = v.n[x], ny = v.n[y];
+  // rows of the output: for blocks whose row cluster is eliminated now and that
+  // are fill-only (not inadmissible), the eliminated rows are dropped
+  const int rows_in = cx ? nx : dim_before(v, x, c.colour);
+  const int cols_in = cy ? ny : dim_before(v, y, c.colour);
+  double2* Z = v.slots + v.slot_off[sl];
+  double2* T = temp + c.pj_toff[task];
+  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  if (side == 0) {
+    if (tr * 64 >= rows_in || tc * 64 >= cols_in) return;
+    const int m = min(64, rows_in - tr * 64), nn = min(64, cols_in - tc * 64);
+    if (!cx) {
+      for (int e = threadIdx.x; e < m * nn; e += blockDim.x) {
+        const int i = e % m, j = e / m;
+        T[tr * 64 + i + (int64_t)(tc * 64 + j) * nx] = Z[tr * 64 + i + (int64_t)(tc * 64 + j) * nx];
+      }
+      return;
+    }
+    TileAcc<double> acc;
+    acc.zero();
+    const double2* Q = v.Q + v.q_off[x];
+    gemm_tile<double, double2>(s, acc, Q + (int64_t)tr * 64 * nx, nx, OP_C, Z + (int64_t)tc * 64 * nx, nx, OP_N, m,
+                               nn, nx);
+    store_tile<double, double2>(acc, T + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
+  } else {
+    const int rows = rows_in;
+    if (tr * 64 >= rows || tc * 64 >= cols_in) return;
+    const int m = min(64, rows - tr * 64), nn = min(64, cols_in - tc * 64);
+    if (!cy) {
+      for (int e = threadIdx.x; e < m * nn; e += blockDim.x) {
+        const int i = e % m, j = e / m;
+        Z[tr * 64 + i + (int64_t)(tc * 64 + j) * nx] = T[tr * 64 + i + (int64_t)(tc * 64 + j) * nx];
+      }
+      return;
+    }
+    TileAcc<double> acc;
+    acc.zero();
+    const double2* Q = v.Q + v.q_off[y];
+    gemm_tile<double, double2>(s, acc, T + tr * 64, nx, OP_N, Q + (int64_t)tc * 64 * ny, ny, OP_R, m, nn, ny);
+    store_tile<double, double2>(acc, Z + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
+  }
+}
+
+void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, hipStream_t st) {
+  if (c.npj <= 0) return;
+  hipLaunchKernelGGL(k_proj, dim3(c.npj, c.tiles * c.tiles), dim3(256), 0, st, v, c, temp, side);
+}
+
+// Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n]; explicit
+// L^-1 P and U^-1 (ld rmax = n - k).
+__global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2* scratch) {
+  __shared__ double2 sF[64 * 64];
+  __shared__ int perm[256];
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  if (r <= 0) return;
+  const int tid = threadIdx.x;
+  const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
+  double2* F = (r <= 64) ? sF : scratch + (int64_t)blockIdx.x * 256 * 256;
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int a = e % r, b = e / r;
+    F[e] = Z[kt + a + (int64_t)(kt + b) * n];
+  }
+  for (int a = tid; a < r; a += blockDim.x) perm[a] = a;
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    // pivot search: max |re| + |im| in column j, rows j..r-1, first index on ties
+    double best = -1.0;
+    int bi = r;
+    for (int a = j + tid; a < r; a += blockDim.x) {
+      const double val = fabs(F[a + j * r].x) + fabs(F[a + j * r].y);
+      if (val > best) {
+        best = val;
+        bi = a;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double v2 = rv[tid + o];
+        const int i2 = ri[tid + o];
+        if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) {
+          rv[tid] = v2;
+          ri[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int pj = ri[0];
+    const double pv = rv[0];
+    __syncthreads();
+    if (!(pv > 0.0)) {
+      if (tid == 0) atomicMax(v.flags, i + 1);
+      return;
+    }
+    if (pj != j) {
+      for (int b = tid; b < r; b += blockDim.x) {
+        const double2 t = F[j + b * r];
+        F[j + b * r] = F[pj + b * r];
+        F[pj + b * r] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[j];
+        perm[j] = perm[pj];
+        perm[pj] = t;
+      }
+    }
+    __syncthreads();
+    const double2 piv = F[j + j * r];
+    const double pd = cabs2(piv);
+    const double2 pinv = make_double2(piv.x / pd, -piv.y / pd);
+    for (int a = j + 1 + tid; a < r; a += blockDim.x) F[a + j * r] = cmul(F[a + j * r], pinv);
+    __syncthreads();
+    const int rem = r - j - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int a = j + 1 + e % rem, b = j + 1 + e / rem;
+      F[a + b * r] = csub(F[a + b * r], cmul(F[a + j * r], F[j + b * r]));
+    }
+    __syncthreads();
+  }
+  double2* Li = v.LU + v.lu_off[i];
+  double2* Ui = Li + (int64_t)rmax * rmax;
+  // column-wise triangular inverses
+  for (int col = tid; col < r; col += blockDim.x) {
+    // U^-1 column col
+    for (int a = col; a >= 0; --a) {
+      double2 acc = make_double2(a == col ? 1.0 : 0.0, 0.0);
+      for (int mm = a + 1; mm <= col; ++mm) acc = csub(acc, cmul(F[a + mm * r], Ui[mm + (int64_t)col * rmax]));
+      const double2 u = F[a + a * r];
+      const double ud = cabs2(u);
+      Ui[a + (int64_t)col * rmax] = cmul(acc, make_double2(u.x / ud, -u.y / ud));
+    }
+    for (int a = col + 1; a < r; ++a) Ui[a + (int64_t)col * rmax] = make_double2(0, 0);
+    // (L^-1)[:, col] placed at column perm[col] of L^-1 P
+    double2* Lc = Li + (int64_t)perm[col] * rmax;
+    for (int a = 0; a < col; ++a) Lc[a] = make_double2(0, 0);
+    Lc[col] = make_double2(1, 0);
+    for (int a = col + 1; a < r; ++a) {
+      double2 acc = make_double2(0, 0);
+      for (int mm = col; mm < a; ++mm) acc = cadd(acc, cmul(F[a + mm * r], Lc[mm]));
+      Lc[a] = make_double2(-acc.x, -acc.y);
+    }
+  }
+}
+
+void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_lu, dim3(c.ncl), dim3(256), 0, st, v, c, scratch);
+}
+
+// Step 3a panels: R_i[:, a] = (L^-1 P) Z_ia[k~:n, 0:m_a]; C_i[a, :] = Z_ai[0:m_a, k~:n] U^-1.
+// grid: (panel task, 2x2 tiles, which)
+__global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
+  __shared__ TileSmem<double> s;
+  const int task = blockIdx.x;
+  const int i = c.pn_i[task], ja = c.pn_ja[task];
+  const int a = v.np_cl[ja];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  if (r <= 0) return;
+  const int ma = (a == i) ? kt : dim_before(v, a, c.colour);
+  const int na = v.n[a];
+  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const double2* Li = v.LU + v.lu_off[i];
+  const double2* Ui = Li + (int64_t)rmax * rmax;
+  const int off = v.np_off[ja];
+  TileAcc<double> acc;
+  acc.zero();
+  if (blockIdx.z == 0) {
+    // R: r x ma
+    if (tr * 64 >= r || tc * 64 >= ma) return;
+    const int m = min(64, r - tr * 64), nn = min(64, ma - tc * 64);
+    const double2* Zia = v.slots + v.slot_off[v.np_srow[ja]] + kt;  // rows k~.. of slot (i, a), ld n
+    gemm_tile<double, double2>(s, acc, Li + tr * 64, rmax, OP_N, Zia + (int64_t)tc * 64 * n, n, OP_N, m, nn, r);
+    double2* R = v.RP + v.rp_off[i] + (int64_t)off * rmax;
+    store_tile<double, double2>(acc, R + tr * 64 + (int64_t)tc * 64 * rmax, rmax, m, nn, ST_SET);
+  } else {
+    // C: ma x r
+    if (tr * 64 >= ma || tc * 64 >= r) return;
+    const int m = min(64, ma - tr * 64), nn = min(64, r - tc * 64);
+    const double2* Zai = v.slots + v.slot_off[v.np_scol[ja]] + (int64_t)kt * na;  // cols k~.. of slot (a, i)
+    gemm_tile<double, double2>(s, acc, Zai + tr * 64, na, OP_N, Ui + (int64_t)tc * 64 * rmax, rmax, OP_N, m, nn,
+                               r);
+    const int pr = v.prow[i];
+    double2* C = v.CP + v.cp_off[i] + off;
+    store_tile<double, double2>(acc, C + tr * 64 + (int64_t)tc * 64 * pr, pr, m, nn, ST_SET);
+  }
+}
+
+void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+  if (c.npn <= 0) return;
+  hipLaunchKernelGGL(k_panels, dim3(c.npn, c.tiles * c.tiles, 2), dim3(256), 0, st, v, c);
+}
+
+// Step 3b: Z_ab[0:m_a, 0:m_b] -= sum_i C_i[a] R_i[b] (gather over the colour's clusters)
+__global__ void __launch_bounds__(256) k_schur(LevelView v, ColourTasks c) {
+  __shared__ TileSmem<double> s;
+  const int task = blockIdx.x;
+  const int sl = c.sc_slot[task];
+  const int a = v.slot_a[sl], b = v.slot_b[sl];
+  const int ma = dim_after(v, a, c.colour), mb = dim_after(v, b, c.colour);
+  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  if (tr * 64 >= ma || tc * 64 >= mb) return;
+  const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
+  TileAcc<double> acc;
+  acc.zero();
+  for (int e = c.sc_cptr[task]; e < c.sc_cptr[task + 1]; ++e) {
+    const int i = c.sc_i[e];
+    const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+    if (r <= 0) continue;
+    const int pr = v.prow[i];
+    const double2* C = v.CP + v.cp_off[i] + v.np_off[c.sc_ja[e]] + tr * 64;
+    const double2* R = v.RP + v.rp_off[i] + (int64_t)(v.np_off[c.sc_jb[e]] + tc * 64) * rmax;
+    gemm_tile<double, double2>(s, acc, C, pr, OP_N, R, rmax, OP_N, m, nn, r);
+  }
+  const int na = v.n[a];
+  double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
+  store_tile<double, double2>(acc, Z, na, m, nn, ST_SUB);
+}
+
+void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+  if (c.nsc <= 0) return;
+  hipLaunchKernelGGL(k_schur, dim3(c.nsc, c.tiles * c.tiles), dim3(256), 0, st, v, c);
+}
+
+// ===========================================================================
+// Level end
+// ===========================================================================
+__global__ void k_zero(double2* p, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = make_double2(0, 0);
+}
+
+void launch_zero(double2* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  int blocks = (int)imin64(8192, (n + 255) / 256);
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, p, n);
+}
+
+__global__ void k_merge(LevelView v, const MergeTask* tasks, const double2* S, double2* dst) {
+  const MergeTask t = tasks[blockIdx.x];
+  const int ka = v.kt[t.ca], kb = v.kt[t.cb];
+  double2* D = dst + t.dst;
+  if (t.kind == 0 || t.kind == 2) {
+    const double2* Z = v.slots + v.slot_off[t.slot];
+    const int ld = v.n[t.ca];
+    for (int e = threadIdx.x; e < ka * kb; e += blockDim.x) {
+      const int i = e % ka, j = e / ka;
+      D[i + j * t.ldd] = Z[i + (int64_t)j * ld];
+    }
+  } else {
+    const double2* F = t.slot >= 0 ? v.slots + v.slot_off[t.slot] : nullptr;
+    const int ld = v.n[t.ca];
+    for (int e = threadIdx.x; e < ka * kb; e += blockDim.x) {
+      const int i = e % ka, j = e / ka;
+      double2 val = make_double2(0, 0);
+      if (i < t.ska && j < t.skb) val = S[t.soff + i + (int64_t)j * t.ska];
+      if (F) val = cadd(val, F[i + (int64_t)j * ld]);
+      D[i + j * t.ldd] = val;
+    }
+  }
+}
+
+void launch_merge(const LevelView& v, const MergeTask* t, int nt, const double2* S, double2* dst,
+                  hipStream_t st) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_merge, dim3(nt), dim3(256), 0, st, v, t, S, dst);
+}
+
+// B_p (n_p x k_p) = transfer matrix T_p with zero rows for the children's added columns (eq. 23)
+__global__ void k_parent_basis(const int32_t* pn, const int32_t* pk, const int32_t* k1, const int32_t* k2,
+                               const int32_t* off1, const int64_t* toff, const double2* T,
+                               const int64_t* boff, double2* B) {
+  const int p = blockIdx.x;
+  const int n = pn[p], k = pk[p];
+  const double2* Tp = T + toff[p];
+  const int ld = k1[p] + k2[p];
+  double2* Bp = B + boff[p];
+  for (int e = threadIdx.x; e < n * k; e += blockDim.x) {
+    const int r = e % n, col = e / n;
+    double2 val = make_double2(0, 0);
+    if (r < k1[p])
+      val = Tp[r + (int64_t)col * ld];
+    else if (r >= off1[p] && r < off1[p] + k2[p])
+      val = Tp[k1[p] + (r - off1[p]) + (int64_t)col * ld];
+    Bp[e] = val;
+  }
+}
+
+void launch_parent_basis(int np, const int32_t* pn, const int32_t* pk, const int32_t* k1, const int32_t* k2,
+                         const int32_t* off1, const int64_t* toff, const double2* T, const int64_t* boff,
+                         double2* B, hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_parent_basis, dim3(np), dim3(256), 0, st, pn, pk, k1, k2, off1, toff, T, boff, B);
+}
+
+// ===========================================================================
+// Dense final LU (blocked right-looking, panel width 64)
+// ===========================================================================
+__global__ void __launch_bounds__(1024) k_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv,
+                                                      double2* linv, int32_t* flag) {
+  __shared__ double rv[1024];
+  __shared__ int64_t ri[1024];
+  const int tid = threadIdx.x;
+  const int w = (int)imin64(64, n - j0);
+  for (int jj = 0; jj < w; ++jj) {
+    const int64_t j = j0 + jj;
+    double best = -1.0;
+    int64_t bi = n;
+    for (int64_t a = j + tid; a < n; a += blockDim.x) {
+      const double2 x = A[a + j * n];
+      const double val = fabs(x.x) + fabs(x.y);
+      if (val > best) {
+        best = val;
+        bi = a;
+      }
+    }
+    rv[tid] = best;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if (tid < o) {
+        if (rv[tid + o] > rv[tid] || (rv[tid + o] == rv[tid] && ri[tid + o] < ri[tid])) {
+          rv[tid] = rv[tid + o];
+          ri[tid] = ri[tid + o];
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t pj = ri[0];
+    const double pv = rv[0];
+    __syncthreads();
+    if (!(pv > 0.0)) {
+      if (tid == 0) *flag = 1;
+      return;
+    }
+    if (tid == 0) piv[j] = (int32_t)pj;
+    if (pj != j)
+      for (int64_t b = tid; b < n; b += blockDim.x) {
+        const double2 t = A[j + b * n];
+        A[j + b * n] = A[pj + b * n];
+        A[pj + b * n] = t;
+      }
+    __syncthreads();
+    const double2 p = A[j + j * n];
+    const double pd = cabs2(p);
+    const double2 pinv = make_double2(p.x / pd, -p.y / pd);
+    for (int64_t a = j + 1 + tid; a < n; a += blockDim.x) A[a + j * n] = cmul(A[a + j * n], pinv);
+    __syncthreads();
+    // update the remaining columns of the panel only
+    const int64_t rows = n - j - 1;
+    const int cols = w - jj - 1;
+    for (int64_t e = tid; e < rows * cols; e += blockDim.x) {
+      const int64_t a = j + 1 + e % rows, b = j + 1 + e / rows;
+      A[a + b * n] = csub(A[a + b * n], cmul(A[a + j * n], A[j + b * n]));
+    }
+    __syncthreads();
+  }
+  // explicit inverse of the unit-lower diagonal block
+  for (int col = tid; col < w; col += blockDim.x) {
+    for (int a = 0; a < w; ++a) {
+      double2 val;
+      if (a < col)
+        val = make_double2(0, 0);
+      else if (a == col)
+        val = make_double2(1, 0);
+      else {
+        double2 acc = make_double2(0, 0);
+        for (int mm = col; mm < a; ++mm)
+          acc = cadd(acc, cmul(A[j0 + a + (j0 + mm) * n], linv[mm + col * 64]));
+        val = make_double2(-acc.x, -acc.y);
+      }
+      linv[a + col * 64] = val;
+    }
+  }
+}
+
+void launch_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv, double2* linv, int32_t* flag,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_panel, dim3(1), dim3(1024), 0, st, A, n, j0, piv, linv, flag);
+}
+
+// inverse of the upper-triangular 64 x 64 (or smaller) diagonal block at A (ld n) -> Uinv (ld 64)
+__global__ void k_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv) {
+  const int col = threadIdx.x;
+  if (col >= w) return;
+  for (int a = col; a >= 0; --a) {
+    double2 acc = make_double2(a == col ? 1.0 : 0.0, 0.0);
+    for (int mm = a + 1; mm <= col; ++mm) acc = csub(acc, cmul(A[a + mm * n], Uinv[mm + col * 64]));
+    const double2 u = A[a + a * n];
+    const double ud = cabs2(u);
+    Uinv[a + col * 64] = cmul(acc, make_double2(u.x / ud, -u.y / ud));
+  }
+  for (int a = col + 1; a < 64; ++a) Uinv[a + col * 64] = make_double2(0, 0);
+}
+
+void launch_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv, hipStream_t st) {
+  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(64), 0, st, A, n, w, Uinv);
+}
+
+// X (n x n) = P: the permutation produced by the recorded row interchanges
+__global__ void k_perm_matrix(double2* X, int64_t n, const int32_t* piv) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t pos = c;
+    for (int64_t j = 0; j < n; ++j) {
+      const int64_t pj = piv[j];
+      if (pos == j)
+        pos = pj;
+      else if (pos == pj)
+        pos = j;
+    }
+    X[pos + c * n] = make_double2(1, 0);
+  }
+}
+
+void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream_t st) {
+  int blocks = (int)imin64(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_perm_matrix, dim3(blocks), dim3(256), 0, st, X, n, piv);
+}
+
+// ===========================================================================
+// Substitution sweeps (nrhs columns)
+// ===========================================================================
+// Forward (adj = 0): b_i <- Q~^H b_i ; b_i' <- (L^-1 P) b_i'.
+// Adjoint phase A (adj = 1): g_i <- Q~^T g_i ; g_i' <- U^-H g_i'.
+__global__ void __launch_bounds__(256) k_fwd_local(LevelView v, ColourTasks c, double2* vec,
+                                                   const int64_t* voff, int64_t ldv, int nrhs, int adj) {
+  __shared__ double2 xs[512];
+  __shared__ double2 ys[512];
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  const double2* Q = v.Q + v.q_off[i];
+  const double2* Li = v.LU + v.lu_off[i];
+  const double2* Ui = Li + (int64_t)rmax * rmax;
+  for (int col = 0; col < nrhs; ++col) {
+    double2* b = vec + voff[i] + col * ldv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) xs[e] = b[e];
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      const double2* qc = Q + (int64_t)row * n;  // column `row` of Q~
+      if (!adj)
+        for (int e = 0; e < n; ++e) acc = cadd(acc, cmulc(qc[e], xs[e]));
+      else
+        for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(qc[e], xs[e]));
+      ys[row] = acc;
+    }
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+      if (row < kt) {
+        b[row] = ys[row];
+      } else {
+        const int q = row - kt;
+        double2 acc = make_double2(0, 0);
+        if (!adj)
+          for (int e = 0; e < r; ++e) acc = cadd(acc, cmul(Li[q + (int64_t)e * rmax], ys[kt + e]));
+        else
+          for (int e = 0; e < r; ++e) acc = cadd(acc, cmulc(Ui[e + (int64_t)q * rmax], ys[kt + e]));
+        b[row] = acc;
+      }
+    }
+  }
+}
+
+void launch_fwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                      int nrhs, int adj, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_fwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+}
+
+// b_a[0:m_a] -= sum_i C_i[a] b_i'   (adj: g_a -= R_i[:, a]^H g_i')
+__global__ void __launch_bounds__(256) k_fwd_gather(LevelView v, ColourTasks c, double2* vec,
+                                                    const int64_t* voff, int64_t ldv, int nrhs, int adj) {
+  const int task = blockIdx.x;
+  const int a = c.sv_cl[task];
+  const int ma = dim_after(v, a, c.colour);
+  for (int col = 0; col < nrhs; ++col) {
+    for (int row = threadIdx.x; row < ma; row += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      for (int e = c.sv_cptr[task]; e < c.sv_cptr[task + 1]; ++e) {
+        const int i = c.sv_i[e];
+        const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+        const double2* bi = vec + voff[i] + col * ldv + kt;
+        const int off = v.np_off[c.sv_ja[e]];
+        if (!adj) {
+          const int pr = v.prow[i];
+          const double2* C = v.CP + v.cp_off[i] + off + row;
+          for (int q = 0; q < r; ++q) acc = cadd(acc, cmul(C[(int64_t)q * pr], bi[q]));
+        } else {
+          const double2* R = v.RP + v.rp_off[i] + (int64_t)(off + row) * rmax;
+          for (int q = 0; q < r; ++q) acc = cadd(acc, cmulc(R[q], bi[q]));
+        }
+      }
+      double2* ba = vec + voff[a] + col * ldv;
+      ba[row] = csub(ba[row], acc);
+    }
+  }
+}
+
+void launch_fwd_gather(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                       int nrhs, int adj, hipStream_t st) {
+  if (c.nsv <= 0) return;
+  hipLaunchKernelGGL(k_fwd_gather, dim3(c.nsv), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+}
+
+// Backward (adj = 0): y_i' <- U^-1 (y_i' - sum_a R_i[a] y_a) ; y_i <- conj(Q~) y_i.
+// Adjoint phase B (adj = 1): g_i' <- (L^-1 P)^H (g_i' - sum_a C_i[a]^H g_a) ; g_i <- Q~ g_i.
+__global__ void __launch_bounds__(256) k_bwd_local(LevelView v, ColourTasks c, double2* vec,
+                                                   const int64_t* voff, int64_t ldv, int nrhs, int adj) {
+  __shared__ double2 xs[512];
+  __shared__ double2 ys[512];
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  const double2* Q = v.Q + v.q_off[i];
+  const double2* Li = v.LU + v.lu_off[i];
+  const double2* Ui = Li + (int64_t)rmax * rmax;
+  const int pr = v.prow[i];
+  for (int col = 0; col < nrhs; ++col) {
+    double2* y = vec + voff[i] + col * ldv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) xs[e] = y[e];
+    __syncthreads();
+    // acc_q = y'_q - sum over partners
+    for (int q = threadIdx.x; q < r; q += blockDim.x) {
+      double2 acc = xs[kt + q];
+      for (int j = v.np_ptr[i]; j < v.np_ptr[i + 1]; ++j) {
+        const int a = v.np_cl[j];
+        const int ma = (a == i) ? kt : dim_before(v, a, c.colour);
+        const double2* ya = (a == i) ? nullptr : vec + voff[a] + col * ldv;
+        const int off = v.np_off[j];
+        if (!adj) {
+          const double2* R = v.RP + v.rp_off[i] + q + (int64_t)off * rmax;
+          for (int e = 0; e < ma; ++e) acc = csub(acc, cmul(R[(int64_t)e * rmax], (a == i) ? xs[e] : ya[e]));
+        } else {
+          const double2* C = v.CP + v.cp_off[i] + off + (int64_t)q * pr;
+          for (int e = 0; e < ma; ++e) acc = csub(acc, cmulc(C[e], (a == i) ? xs[e] : ya[e]));
+        }
+      }
+      ys[q] = acc;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < r; q += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      if (!adj)
+        for (int e = q; e < r; ++e) acc = cadd(acc, cmul(Ui[q + (int64_t)e * rmax], ys[e]));
+      else
+        for (int e = 0; e < r; ++e) acc = cadd(acc, cmulc(Li[e + (int64_t)q * rmax], ys[e]));
+      xs[kt + q] = acc;
+    }
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      if (!adj)
+        for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(cconj(Q[row + (int64_t)e * n]), xs[e]));
+      else
+        for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(Q[row + (int64_t)e * n], xs[e]));
+      y[row] = acc;
+    }
+  }
+}
+
+void launch_bwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                      int nrhs, int adj, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_bwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+}
+
+// up = 1: parent vector = [kept(c1); kept(c2)] ; up = 0: children's kept parts from the parent
+__global__ void k_vmerge(const int32_t* kt, const int64_t* cvoff, const int64_t* pvoff, int64_t ldc,
+                         int64_t ldp, int nrhs, double2* cvec, double2* pvec, int up, const int32_t* nonempty) {
+  const int p = blockIdx.x;
+  const int c1 = 2 * p, c2 = 2 * p + 1;
+  const int k1 = nonempty[c1] ? kt[c1] : 0, k2 = nonempty[c2] ? kt[c2] : 0;
+  for (int col = 0; col < nrhs; ++col) {
+    for (int e = threadIdx.x; e < k1 + k2; e += blockDim.x) {
+      const int64_t ci = (e < k1) ? cvoff[c1] + e : cvoff[c2] + (e - k1);
+      double2* cp = cvec + ci + col * ldc;
+      double2* pp = pvec + pvoff[p] + e + col * ldp;
+      if (up)
+        *pp = *cp;
+      else
+        *cp = *pp;
+    }
+  }
+}
+
+void launch_vmerge(int np, const int32_t* kt, const int64_t* cvoff, const int64_t* pvoff, int64_t ldc,
+                   int64_t ldp, int nrhs, double2* cvec, double2* pvec, int up, const int32_t* nonempty,
+                   hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_vmerge, dim3(np), dim3(128), 0, st, kt, cvoff, pvoff, ldc, ldp, nrhs, cvec, pvec, up,
+                     nonempty);
+}
+
+__global__ void k_permute_in(const double2* x, int64_t ldx, const int64_t* perm, const double* scale,
+                             int conj_in, int64_t N, int nrhs, double2* out, int64_t ldo) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e % N, col = e / N;
+    double2 val = x[perm[t] + col * ldx];
+    if (conj_in) val.y = -val.y;
+    if (scale) {
+      val.x *= scale[t];
+      val.y *= scale[t];
+    }
+    out[t + col * ldo] = val;
+  }
+}
+
+void launch_permute_in(const double2* x, int64_t ldx, const int64_t* perm, const double* scale, int conj_in,
+                       int64_t N, int nrhs, double2* out, int64_t ldo, hipStream_t st) {
+  const int64_t tot = N * nrhs;
+  if (tot <= 0) return;
+  int blocks = (int)imin64(4096, (tot + 255) / 256);
+  hipLaunchKernelGGL(k_permute_in, dim3(blocks), dim3(256), 0, st, x, ldx, perm, scale, conj_in, N, nrhs, out,
+                     ldo);
+}
+
+__global__ void k_permute_out(const double2* in, int64_t ldi, const int64_t* perm, const double* scale,
+                              int conj_out, int64_t N, int nrhs, double2* y, int64_t ldy, int accumulate) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e % N, col = e / N;
+    double2 val = in[t + col * ldi];
+    if (conj_out) val.y = -val.y;
+    if (scale) {
+      val.x *= scale[t];
+      val.y *= scale[t];
+    }
+    double2* p = y + perm[t] + col * ldy;
+    *p = accumulate ? cadd(*p, val) : val;
+  }
+}
+
+void launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, const double* scale, int conj_out,
+                        int64_t N, int nrhs, double2* y, int64_t ldy, int accumulate, hipStream_t st) {
+  const int64_t tot = N * nrhs;
+  if (tot <= 0) return;
+  int blocks = (int)imin64(4096, (tot + 255) / 256);
+  hipLaunchKernelGGL(k_permute_out, dim3(blocks), dim3(256), 0, st, in, ldi, perm, scale, conj_out, N, nrhs, y,
+                     ldy, accumulate);
+}
+
+// y = M x (conj_trans = 0) or M^H x (1) for an n x n dense M; x and y distinct, ld for both
+__global__ void k_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
+                             int conj_trans) {
+  const int col = blockIdx.y;
+  for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n; row += (int64_t)gridDim.x * blockDim.x) {
+    double2 acc = make_double2(0, 0);
+    const double2* xc = x + col * ld;
+    if (!conj_trans)
+      for (int64_t e = 0; e < n; ++e) acc = cadd(acc, cmul(M[row + e * n], xc[e]));
+    else
+      for (int64_t e = 0; e < n; ++e) acc = cadd(acc, cmulc(M[e + row * n], xc[e]));
+    y[row + col * ld] = acc;
+  }
+}
+
+void launch_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
+                       int conj_trans, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
+  int blocks = (int)imin64(1024, (n + 127) / 128);
+  hipLaunchKernelGGL(k_dense_gemv, dim3(blocks, nrhs), dim3(128), 0, st, M, n, x, y, ld, nrhs, conj_trans);
+}
+
+// ===========================================================================
+// H^2 matrix-vector product pieces
+// ===========================================================================
+// y_t = sum_{s in near(t)} Z_ts x_s for leaf clusters (row-cluster CSR)
+__global__ void __launch_bounds__(256) k_near_mv(const int32_t* rptr, const int32_t* rcol, const int64_t* boff,
+                                                 const double2* blocks, const int64_t* cstart,
+                                                 const int32_t* csize, const double2* x, double2* y, int64_t ld,
+                                                 int nrhs) {
+  const int t = blockIdx.x;
+  const int m = csize[t];
+  for (int col = 0; col < nrhs; ++col) {
+    for (int row = threadIdx.x; row < m; row += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      for (int e = rptr[t]; e < rptr[t + 1]; ++e) {
+        const int s = rcol[e];
+        const int ns = csize[s];
+        const double2* Bk = blocks + boff[e] + row;
+        const double2* xs = x + cstart[s] + col * ld;
+        for (int q = 0; q < ns; ++q) acc = cadd(acc, cmul(Bk[(int64_t)q * m], xs[q]));
+      }
+      y[cstart[t] + row + col * ld] = acc;
+    }
+  }
+}
+
+void launch_near_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* boff, const double2* blocks,
+                    const int64_t* cstart, const int32_t* csize, const double2* x, double2* y, int64_t ld, int nrhs,
+                    hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_near_mv, dim3(nc), dim3(128), 0, st, rptr, rcol, boff, blocks, cstart, csize, x, y, ld,
+                     nrhs);
+}
+
+// trans = 1: y_t = M_t^T x_t (M_t rows x cols) ; trans = 0: y_t (+)= M_t x_t
+__global__ void k_basis_mv(const int32_t* rows, const int32_t* cols, const int64_t* moff, const double2* M,
+                           const int64_t* xoff, const double2* x, const int64_t* yoff, double2* y, int64_t ldx,
+                           int64_t ldy, int nrhs, int trans, int accumulate) {
+  const int t = blockIdx.x;
+  const int m = rows[t], n = cols[t];
+  const double2* Mt = M + moff[t];
+  for (int col = 0; col < nrhs; ++col) {
+    const double2* xt = x + xoff[t] + col * ldx;
+    double2* yt = y + yoff[t] + col * ldy;
+    if (trans) {
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double2 acc = make_double2(0, 0);
+        for (int i = 0; i < m; ++i) acc = cadd(acc, cmul(Mt[i + (int64_t)j * m], xt[i]));
+        yt[j] = accumulate ? cadd(yt[j], acc) : acc;
+      }
+    } else {
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        double2 acc = make_double2(0, 0);
+        for (int j = 0; j < n; ++j) acc = cadd(acc, cmul(Mt[i + (int64_t)j * m], xt[j]));
+        yt[i] = accumulate ? cadd(yt[i], acc) : acc;
+      }
+    }
+  }
+}
+
+void launch_basis_mv(int nc, const int32_t* rows, const int32_t* cols, const int64_t* moff, const double2* M,
+                     const int64_t* xoff, const double2* x, const int64_t* yoff, double2* y, int64_t ldx,
+                     int64_t ldy, int nrhs, int trans, int accumulate, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_basis_mv, dim3(nc), dim3(128), 0, st, rows, cols, moff, M, xoff, x, yoff, y, ldx, ldy, nrhs,
+                     trans, accumulate);
+}
+
+// yhat_t = sum_{s in adm(t)} S_ts xhat_s
+__global__ void k_coupling_mv(const int32_t* rptr, const int32_t* rcol, const int64_t* soff, const int32_t* kr,
+                              const int32_t* kc, const double2* S, const int64_t* xoff, const double2* x,
+                              const int64_t* yoff, double2* y, int64_t ld, int nrhs) {
+  const int t = blockIdx.x;
+  const int m = kr[t];
+  for (int col = 0; col < nrhs; ++col) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      for (int e = rptr[t]; e < rptr[t + 1]; ++e) {
+        const int s = rcol[e];
+        const int n = kc[s];
+        const double2* St = S + soff[e] + i;
+        const double2* xs = x + xoff[s] + col * ld;
+        for (int j = 0; j < n; ++j) acc = cadd(acc, cmul(St[(int64_t)j * m], xs[j]));
+      }
+      y[yoff[t] + i + col * ld] = acc;
+    }
+  }
+}
+
+void launch_coupling_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* soff, const int32_t* kr,
+                        const int32_t* kc, const double2* S, const int64_t* xoff, const double2* x,
+                        const int64_t* yoff, double2* y, int64_t ld, int nrhs, hipStream_t st) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_coupling_mv, dim3(nc), dim3(128), 0, st, rptr, rcol, soff, kr, kc, S, xoff, x, yoff, y, ld,
+                     nrhs);
+}
+
+// ===========================================================================
+// Refinement helpers
+// ===========================================================================
+__global__ void k_residual(const double2* b, int64_t ldb, const double2* ax, int64_t lda, double2* r, int64_t ldr,
+                           int64_t N, int nrhs) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % N, c = e / N;
+    r[i + c * ldr] = csub(b[i + c * ldb], ax[i + c * lda]);
+  }
+}
+
+void launch_residual(const double2* b, int64_t ldb, const double2* ax, int64_t lda, double2* r, int64_t ldr,
+                     int64_t N, int nrhs, hipStream_t st) {
+  int blocks = (int)imin64(4096, (N * nrhs + 255) / 256);
+  hipLaunchKernelGGL(k_residual, dim3(blocks), dim3(256), 0, st, b, ldb, ax, lda, r, ldr, N, nrhs);
+}
+
+__global__ void k_axpy_cols(const double2* d, int64_t ldd, double2* x, int64_t ldx, int64_t N, int nrhs) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % N, c = e / N;
+    x[i + c * ldx] = cadd(x[i + c * ldx], d[i + c * ldd]);
+  }
+}
+
+void launch_axpy_cols(const double2* d, int64_t ldd, double2* x, int64_t ldx, int64_t N, int nrhs,
+                      hipStream_t st) {
+  int blocks = (int)imin64(4096, (N * nrhs + 255) / 256);
+  hipLaunchKernelGGL(k_axpy_cols, dim3(blocks), dim3(256), 0, st, d, ldd, x, ldx, N, nrhs);
+}
+
+__global__ void __launch_bounds__(256) k_col_norms(const double2* x, int64_t ld, int64_t N, double* out) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  double part = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) part += cabs2(x[i + c * ld]);
+  const double s = block_sum256(part, red);
+  if (threadIdx.x == 0) out[c] = sqrt(s);
+}
+
+void launch_col_norms(const double2* x, int64_t ld, int64_t N, int nrhs, double* out, hipStream_t st) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(k_col_norms, dim3(nrhs), dim3(256), 0, st, x, ld, N, out);
+}
+
+}  // namespace h2

@@ -1,0 +1,196 @@
+// Device-side data views and kernel launchers (host interface of h2_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace h2 {
+
+// Operand access modes: element (i, k) of op(A) / (k, j) of op(B).
+enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2, OP_R = 3 };  // R = conjugate, not transposed
+// Epilogue of a tile: C = acc, C += acc, C -= acc.
+enum StoreMode : int { ST_SET = 0, ST_ADD = 1, ST_SUB = 2 };
+
+// Geometry and kernel constants of the VIE matrix Z = A D^-1 (tree order).
+struct GeomView {
+  const double* pts;       // N x 3, tree order
+  const double* chi;       // N, tree order
+  const int32_t* leafid;   // N: leaf cluster of each tree-ordered point
+  int64_t N;
+  int L;
+  double k, h;
+  double diag_re_c, diag_im_c;  // self term c = (1 + jka) e^{-jka} - 1
+  double k2h3;                  // k^2 h^3
+};
+
+// One factorization level; every array is indexed by cluster (nc entries),
+// slot, or partner-list position.  Dimensions written during the level (kt)
+// are read back by later kernels of the same level on the device.
+struct LevelView {
+  int nc;
+  const int32_t* n;        // current size n_i
+  const int32_t* k;        // basis columns k_i
+  int32_t* kt;             // k~_i (Step 0 result)
+  const int32_t* colour;
+  const double* nu;        // construction sigma_1
+  const int32_t* forced;   // forced k~ or -1 (nullable)
+  double eps_fill;
+  // blocks ("slots"): inadmissible pairs and fill-receiving admissible pairs
+  const int64_t* slot_off;
+  const int32_t* slot_a;
+  const int32_t* slot_b;
+  double2* slots;
+  const int32_t* diag_slot;
+  // inadmissible partners N+(i) (incl. i), CSR
+  const int32_t* np_ptr;
+  const int32_t* np_cl;
+  const int32_t* np_srow;  // slot (i, a)
+  const int32_t* np_scol;  // slot (a, i)
+  const int32_t* np_off;   // offset of a inside the panels (sum of n over earlier partners)
+  // fill partners (admissible / ancestor-admissible pairs reached by fill-ins), CSR
+  const int32_t* fp_ptr;
+  const int32_t* fp_cl;
+  const int32_t* fp_srow;
+  // per-cluster storage
+  const int64_t* q_off;  double2* Q;     // Q~ (n x n), kept-first: [B B_add B~perp]
+  const int64_t* b_off;  double2* B;     // B (n x k)
+  const int64_t* bp_off; double2* Bp;    // B_perp (n x (n-k))
+  const int64_t* lu_off; double2* LU;    // L^-1 P (rmax x rmax) then U^-1 (rmax x rmax)
+  const int64_t* cp_off; double2* CP;    // C panel (prow x rmax)
+  const int64_t* rp_off; double2* RP;    // R panel (rmax x prow)
+  const int32_t* prow;                   // sum of n_a over N+(i)
+  const int64_t* w_off;  double2* W;     // workspace: H (n x n), X (n x d), G' (d x d), U' (d x d)
+  int32_t* flags;                        // [0]: 1 + cluster of a zero pivot
+  double* margins;                       // per cluster (sigma_p / tau, sigma_{p+1} / tau)
+};
+
+// Per-colour task lists (device arrays).
+struct ColourTasks {
+  const int32_t* cl; int ncl;            // clusters of the colour
+  const int32_t* pj_slot; const int64_t* pj_toff; int npj;   // projection slots, temp offsets
+  const int32_t* sc_slot; const int32_t* sc_cptr; const int32_t* sc_i; const int32_t* sc_ja;
+  const int32_t* sc_jb; int nsc;          // Schur targets and their contributions
+  const int32_t* pn_i; const int32_t* pn_ja; int npn;          // panel tasks (i, partner pos)
+  const int32_t* sv_cl; const int32_t* sv_cptr; const int32_t* sv_i; const int32_t* sv_ja;
+  int nsv;                                // solve gather targets and contributions
+  int colour;
+  int tiles;                              // 64-wide tiles per block side (ceil(max n / 64))
+};
+
+// Generic host-resolved batched GEMM task: C (op)= op(A) op(B).
+struct GemmTask {
+  const double2* A;
+  const double2* B;
+  double2* C;
+  int64_t lda, ldb, ldc;
+  int32_t m, n, K;
+  int32_t opA, opB, mode;
+};
+
+// ---- construction ----
+void launch_near_blocks(const GeomView& g, const int32_t* pr, const int32_t* pc, const int64_t* off,
+                        const int64_t* rs, const int32_t* rn, const int64_t* cs, const int32_t* cn,
+                        int npairs, double2* out, hipStream_t st);
+void launch_leaf_gram(const GeomView& g, const uint32_t* mask, int ncl, int level, const int64_t* cstart,
+                      const int32_t* csize, int64_t kchunk, int nchunks, double2* part, int64_t stride,
+                      const int64_t* goff, int ntr, hipStream_t st);
+void launch_gram_reduce(const double2* part, double2* out, const int64_t* off, const int32_t* sz,
+                        int ncl, int nchunks, int64_t stride, hipStream_t st);
+void launch_proj_rows(const GeomView& g, const uint32_t* mask, int level, int nch, const int64_t* cstart,
+                      const int32_t* csize, const int32_t* ck, const int64_t* voff, const double2* V,
+                      const int64_t* yoff, const int32_t* yld, double2* Y, int64_t col0, int ncols,
+                      int ntr, hipStream_t st);
+void launch_gram_acc(int ncl, const int32_t* dim, const int64_t* yoff, const double2* Y, int ncols,
+                     const int64_t* goff, double2* G, int ntr, hipStream_t st);
+void launch_coupling_x(const GeomView& g, int npairs, int ntr, int ntc, const int32_t* pt, const int32_t* ps,
+                       const int64_t* tstart, const int32_t* tsz, const int32_t* tk, const int64_t* voff,
+                       const double2* V, const int64_t* xoff, double2* X, hipStream_t st);
+void launch_gemm_batched(const GemmTask* tasks, const int32_t* tile_task, const int32_t* tile_rc,
+                         int ntiles, hipStream_t st);
+void launch_transpose_copy(const GemmTask* tasks, int ntasks, hipStream_t st);
+
+// Batched Hermitian eigensolver (cyclic Jacobi): G (d x d, ld d) per problem at
+// goff; writes eigenvalues descending (lam at loff) and eigenvectors (U at uoff,
+// ld d).  rel != 0: rotate until |g_pq| <= 1e-17 sqrt(|g_pp g_qq|) (relative
+// accuracy), else until |g_pq| <= 1e-17 ||G||_F.
+void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2* G, const int64_t* uoff,
+                   double2* U, const int64_t* loff, double* lam, int rel, double2* scratch,
+                   const int64_t* soff, hipStream_t st);
+
+// ---- factorization ----
+void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
+void launch_gram_fill(const LevelView& v, const ColourTasks& c, hipStream_t st);
+void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st);
+void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
+void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, hipStream_t st);
+void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
+void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st);
+void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st);
+
+// Level end: parent blocks from children (copy of kept k~ x k~ parts, padded
+// couplings plus fills, carried fills).
+struct MergeTask {
+  int64_t dst;         // element offset of the destination sub-block origin
+  int64_t ldd;
+  int32_t kind;        // 0 near slot, 1 admissible (coupling + optional fill), 2 fill slot
+  int32_t slot;        // source slot (kinds 0, 2) or fill slot / -1 (kind 1)
+  int32_t ca, cb;      // child clusters
+  int64_t soff;        // coupling offset (kind 1)
+  int32_t ska, skb;    // coupling dims (construction ranks)
+};
+void launch_zero(double2* p, int64_t n, hipStream_t st);
+void launch_merge(const LevelView& v, const MergeTask* t, int nt, const double2* S, double2* dst,
+                  hipStream_t st);
+void launch_parent_basis(int np, const int32_t* pn, const int32_t* pk, const int32_t* k1,
+                         const int32_t* k2, const int32_t* off1, const int64_t* toff, const double2* T,
+                         const int64_t* boff, double2* B, hipStream_t st);
+
+// Dense LU with partial pivoting of one panel (rows j0.., 64 columns) of an
+// n x n column-major matrix: factorizes in place, records pivots, swaps rows
+// across the whole matrix, writes the explicit inverse of the unit-lower
+// diagonal block (64 x 64, ld 64) to linv.
+void launch_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv, double2* linv, int32_t* flag,
+                        hipStream_t st);
+void launch_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv, hipStream_t st);
+void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream_t st);
+
+// ---- sweeps (nrhs columns; per-level vectors with leading dimension ldv) ----
+void launch_fwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
+                      int64_t ldv, int nrhs, int adj, hipStream_t st);
+void launch_fwd_gather(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
+                       int64_t ldv, int nrhs, int adj, hipStream_t st);
+void launch_bwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
+                      int64_t ldv, int nrhs, int adj, hipStream_t st);
+void launch_vmerge(int np, const int32_t* kt, const int64_t* cvoff, const int64_t* pvoff, int64_t ldc,
+                   int64_t ldp, int nrhs, double2* cvec, double2* pvec, int up, const int32_t* nonempty,
+                   hipStream_t st);
+void launch_permute_in(const double2* x, int64_t ldx, const int64_t* perm, const double* scale,
+                       int conj_in, int64_t N, int nrhs, double2* out, int64_t ldo, hipStream_t st);
+void launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, const double* scale,
+                        int conj_out, int64_t N, int nrhs, double2* y, int64_t ldy, int accumulate,
+                        hipStream_t st);
+void launch_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
+                       int conj_trans, hipStream_t st);
+
+// ---- H^2 matrix-vector product ----
+void launch_near_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* boff,
+                    const double2* blocks, const int64_t* cstart, const int32_t* csize, const double2* x,
+                    double2* y, int64_t ld, int nrhs, hipStream_t st);
+void launch_basis_mv(int nc, const int32_t* rows, const int32_t* cols, const int64_t* moff,
+                     const double2* M, const int64_t* xoff, const double2* x, const int64_t* yoff,
+                     double2* y, int64_t ldx, int64_t ldy, int nrhs, int trans, int accumulate,
+                     hipStream_t st);
+void launch_coupling_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* soff,
+                        const int32_t* kr, const int32_t* kc, const double2* S, const int64_t* xoff,
+                        const double2* x, const int64_t* yoff, double2* y, int64_t ld, int nrhs,
+                        hipStream_t st);
+
+// ---- refinement helpers ----
+void launch_residual(const double2* b, int64_t ldb, const double2* ax, int64_t lda, double2* r, int64_t ldr,
+                     int64_t N, int nrhs, hipStream_t st);
+void launch_axpy_cols(const double2* d, int64_t ldd, double2* x, int64_t ldx, int64_t N, int nrhs,
+                      hipStream_t st);
+void launch_col_norms(const double2* x, int64_t ld, int64_t N, int nrhs, double* out, hipStream_t st);
+
+}  // namespace h2

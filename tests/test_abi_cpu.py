@@ -1,0 +1,88 @@
+"""C-ABI checks that need no GPU: exports, argument validation, host structure vs the oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1703_06155_amd as h2
+from oracle import h2_oracle as O
+from paper_1703_06155_amd import inputs as I
+
+
+def test_library_exports_every_declared_function():
+    names = h2.declared_functions()
+    assert {"h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec"} <= set(names)
+    L = h2.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("grid,leaf,eta", [((16, 16, 16), 32, 1.0), ((13, 27, 19), 48, 1.0), ((10, 7, 9), 12, 1.0),
+                                           ((9, 5, 3), 7, 0.7), ((8, 8, 8), 16, 0.0), ((6, 6, 6), 8, 1.0)])
+def test_host_structure_matches_oracle(grid, leaf, eta):
+    """The library's tree, partition and colouring are bit-identical to the oracle's."""
+    pts = I.cube_grid(*grid)
+    got = h2.structure(pts, I.CELL, leaf, eta)
+    S = O.build_structure(pts, I.CELL, leaf, eta)
+    L = S.L
+    assert got["L"] == L
+    assert got["l0"] == (S.l0 if S.l0 is not None else -1)
+    assert got["leaves"] == len(S.clusters[L])
+    assert got["adm_leaf"] == len(S.adm[L]) and got["near_leaf"] == len(S.near[L])
+    assert np.array_equal(got["perm"], S.perm)
+    assert np.array_equal(got["colours"], S.colour[L].astype(np.int32))
+
+
+def _build_status(**over):
+    pr = I.make_problem("t", (4, 4, 4), 8, 1e-4)
+    args = dict(points=np.ascontiguousarray(pr.points), n=pr.n, k=pr.k, h=pr.h, chi=np.ascontiguousarray(pr.chi),
+                leaf=8, eta=1.0, eps=1e-4)
+    args.update(over)
+    out = ctypes.c_void_p()
+    L = h2.lib()
+    pts, chi = args["points"], args["chi"]
+    st = L.h2_build(pts.ctypes.data_as(h2._DP) if pts is not None else None, args["n"], args["k"], args["h"],
+                    chi.ctypes.data_as(h2._DP) if chi is not None else None, args["leaf"], args["eta"], args["eps"],
+                    None, None, ctypes.byref(out))
+    return st, L.h2_last_error().decode()
+
+
+@pytest.mark.parametrize("over", [dict(n=0), dict(k=0.0), dict(k=float("nan")), dict(h=-1.0), dict(leaf=0),
+                                  dict(eta=-0.5), dict(eps=0.0), dict(eps=1.0), dict(points=None), dict(chi=None)])
+def test_build_rejects_bad_arguments_before_touching_a_device(over):
+    st, msg = _build_status(**over)
+    assert st == h2.H2_ERR_ARG and msg
+
+
+def test_build_rejects_nonpositive_or_nonfinite_contrast():
+    pr = I.make_problem("t", (4, 4, 4), 8, 1e-4)
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        chi = pr.chi.copy()
+        chi[5] = bad
+        st, _ = _build_status(chi=np.ascontiguousarray(chi))
+        assert st == h2.H2_ERR_ARG
+
+
+def test_duplicate_points_are_rejected():
+    pts = np.zeros((40, 3))
+    st, msg = _build_status(points=pts, n=40, chi=np.ones(40))
+    assert st == h2.H2_ERR_ARG and "duplicate" in msg
+
+
+def test_calls_on_null_handle_fail_cleanly():
+    L = h2.lib()
+    x = ctypes.c_void_p(1)
+    assert L.h2_factor(None, None) == h2.H2_ERR_ARG
+    assert L.h2_solve(None, x, x, 1, 1, 0.0, 0, None, None) == h2.H2_ERR_ARG
+    assert L.h2_solve_adjoint(None, x, x, 1, 1, None) == h2.H2_ERR_ARG
+    assert L.h2_matvec(None, x, x, 1, 1, 0, None) == h2.H2_ERR_ARG
+    L.h2_destroy(None)
+
+
+def test_valid_build_without_a_gpu_reports_device_error():
+    """With valid arguments the next failure point is the device check (no CPU fallback)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, msg = _build_status()
+    assert st == h2.H2_ERR_DEVICE, msg

@@ -116,11 +116,96 @@ struct TileAcc {
   }
 };
 
-// Load a 64 x TK tile of op(A) (rows [0, m), k in [k0, k0 + TK) of K) into LDS.
-// A points at element (0, 0) of op(A)'s row/col origin in storage.
+// Per-thread staging of one TK slab: 4 elements of op(A) and 4 of op(B).
+template <typename CT>
+struct SlabRegs {
+  CT a[4], b[4];
+};
+
+// Global -> registers for the slab starting at k0 (zero outside [0,m) x [0,K) / [0,K) x [0,n)).
+template <typename CT>
+__device__ __forceinline__ void slab_fetch(SlabRegs<CT>& r, const CT* __restrict__ A, int64_t lda, int opA,
+                                           const CT* __restrict__ B, int64_t ldb, int opB, int m, int n, int K,
+                                           int k0) {
+  const int t = threadIdx.x;
+  if (opA == OP_N || opA == OP_R) {
+    const int i = t & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + (t >> 6) + 4 * e;
+      r.a[e] = (i < m && k < K) ? A[i + (int64_t)k * lda] : CT{0, 0};
+    }
+  } else {
+    const int k = k0 + (t & 15);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = (t >> 4) + 16 * e;
+      r.a[e] = (i < m && k < K) ? A[k + (int64_t)i * lda] : CT{0, 0};
+    }
+  }
+  if (opB == OP_N || opB == OP_R) {
+    const int k = k0 + (t & 15);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = (t >> 4) + 16 * e;
+      r.b[e] = (j < n && k < K) ? B[k + (int64_t)j * ldb] : CT{0, 0};
+    }
+  } else {
+    const int j = t & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + (t >> 6) + 4 * e;
+      r.b[e] = (j < n && k < K) ? B[j + (int64_t)k * ldb] : CT{0, 0};
+    }
+  }
+}
+
+// Registers -> LDS in the layout mma_slab reads (conjugation applied here).
 template <typename R, typename CT>
-__device__ __forceinline__ void load_a(TileSmem<R>& s, const CT* __restrict__ A, int64_t lda, int op,
-                                       int m, int K, int k0) {
+__device__ __forceinline__ void slab_store(TileSmem<R>& s, const SlabRegs<CT>& r, int opA, int opB) {
+  const int t = threadIdx.x;
+  const bool ca = (opA == OP_C || opA == OP_R), cb = (opB == OP_C || opB == OP_R);
+  if (opA == OP_N || opA == OP_R) {
+    const int i = t & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = (t >> 6) + 4 * e;
+      s.are[kk][i] = r.a[e].x;
+      s.aim[kk][i] = ca ? -r.a[e].y : r.a[e].y;
+    }
+  } else {
+    const int kk = t & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = (t >> 4) + 16 * e;
+      s.are[kk][i] = r.a[e].x;
+      s.aim[kk][i] = ca ? -r.a[e].y : r.a[e].y;
+    }
+  }
+  if (opB == OP_N || opB == OP_R) {
+    const int kk = t & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = (t >> 4) + 16 * e;
+      s.bre[kk][j] = r.b[e].x;
+      s.bim[kk][j] = cb ? -r.b[e].y : r.b[e].y;
+    }
+  } else {
+    const int j = t & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int kk = (t >> 6) + 4 * e;
+      s.bre[kk][j] = r.b[e].x;
+      s.bim[kk][j] = cb ? -r.b[e].y : r.b[e].y;
+    }
+  }
+}
+
+// Load a 64 x TK tile of op(A) and a TK x 64 tile of op(B) straight into LDS
+// (generated-entry kernels write LDS themselves and use mma_slab directly).
+template <typename R, typename CT>
+__device__ __forceinline__ void load_a(TileSmem<R>& s, const CT* __restrict__ A, int64_t lda, int op, int m, int K,
+                                       int k0) {
   const int t = threadIdx.x;
   if (op == OP_N || op == OP_R) {
     const int i = t & 63;
@@ -143,36 +228,6 @@ __device__ __forceinline__ void load_a(TileSmem<R>& s, const CT* __restrict__ A,
       if (i < m && k < K) v = A[k + (int64_t)i * lda];
       s.are[kk][i] = v.x;
       s.aim[kk][i] = (op == OP_C) ? -v.y : v.y;
-    }
-  }
-}
-
-// Load a TK x 64 tile of op(B) (k in [k0, k0 + TK), cols [0, n)) into LDS.
-template <typename R, typename CT>
-__device__ __forceinline__ void load_b(TileSmem<R>& s, const CT* __restrict__ B, int64_t ldb, int op,
-                                       int n, int K, int k0) {
-  const int t = threadIdx.x;
-  if (op == OP_N || op == OP_R) {
-    const int kk = t & 15;
-    const int k = k0 + kk;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = (t >> 4) + 16 * e;
-      CT v{0, 0};
-      if (j < n && k < K) v = B[k + (int64_t)j * ldb];
-      s.bre[kk][j] = v.x;
-      s.bim[kk][j] = (op == OP_R) ? -v.y : v.y;
-    }
-  } else {
-    const int j = t & 63;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int kk = (t >> 6) + 4 * e;
-      const int k = k0 + kk;
-      CT v{0, 0};
-      if (j < n && k < K) v = B[j + (int64_t)k * ldb];
-      s.bre[kk][j] = v.x;
-      s.bim[kk][j] = (op == OP_C) ? -v.y : v.y;
     }
   }
 }
@@ -211,20 +266,65 @@ __device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc) 
   }
 }
 
-// acc += op(A)[0:m, 0:K] * op(B)[0:K, 0:n] (m, n <= 64).
+// acc += op(A)[0:m, 0:K] * op(B)[0:K, 0:n] (m, n <= 64), with the next slab's
+// global loads in flight while the current slab is multiplied.
 template <typename R, typename CT>
-__device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const CT* A, int64_t lda,
-                                          int opA, const CT* B, int64_t ldb, int opB, int m, int n,
-                                          int K) {
+__device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const CT* A, int64_t lda, int opA,
+                                          const CT* B, int64_t ldb, int opB, int m, int n, int K) {
+  if (K <= 0) return;
+  SlabRegs<CT> r;
+  slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, 0);
   for (int k0 = 0; k0 < K; k0 += TK) {
     __syncthreads();
-    load_a<R, CT>(s, A, lda, opA, m, K, k0);
-    load_b<R, CT>(s, B, ldb, opB, n, K, k0);
+    slab_store<R, CT>(s, r, opA, opB);
     __syncthreads();
+    if (k0 + TK < K) slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, k0 + TK);
     mma_slab<R>(s, acc);
   }
 }
 
+// Per-thread prefetch of the 16 elements of C that this thread's accumulators cover.
+template <typename R, typename CT>
+struct TilePre {
+  CT c[2][2][4];
+};
+
+template <typename R, typename CT>
+__device__ __forceinline__ void prefetch_tile(TilePre<R, CT>& p, const CT* C, int64_t ldc, int m, int n) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + t * 16 + (lane & 15);
+        const int j = wc * 32 + u * 16 + acc_col<R>(lane, v);
+        p.c[t][u][v] = (i < m && j < n) ? C[i + (int64_t)j * ldc] : CT{0, 0};
+      }
+}
+
+// C = pre - acc for a tile prefetched with prefetch_tile.
+template <typename R, typename CT>
+__device__ __forceinline__ void store_tile_sub_pre(const TileAcc<R>& acc, const TilePre<R, CT>& p, CT* C, int64_t ldc,
+                                                   int m, int n) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr * 32 + t * 16 + (lane & 15);
+        const int j = wc * 32 + u * 16 + acc_col<R>(lane, v);
+        if (i < m && j < n) {
+          const CT o = p.c[t][u][v];
+          C[i + (int64_t)j * ldc] = CT{o.x - acc.re[t][u][v], o.y - acc.im[t][u][v]};
+        }
+      }
+}
 
 // C[0:m, 0:n] (op)= acc, C column-major with leading dimension ldc.
 template <typename R, typename CT>

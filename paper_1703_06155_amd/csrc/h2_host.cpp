@@ -203,7 +203,7 @@ struct h2_ctx {
   std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
   // sweep workspace
   std::vector<h2::DArr<double2>> vbuf;
-  h2::DArr<double2> vtmp, vtmp2, vtmp3;
+  h2::DArr<double2> vtmp, vtmp2, vtmp3, sw_scratch, sw_part;
   int vbuf_nrhs = 0;
   h2::DArr<double> d_norms;
   std::vector<std::vector<int64_t>> stats_rows;
@@ -957,13 +957,15 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     F.LU.alloc(lu_off[nc]);
     F.CP.alloc(cp_off[nc]);
     F.RP.alloc(cp_off[nc]);
-    DArr<double2> Bp, W, temp, lu_scr, eig_scr;
+    DArr<double2> Bp, W, temp, lu_scr, eig_scr, gram_part;
     Bp.alloc(bp_off[nc]);
     W.alloc(w_off[nc]);
     temp.alloc(temp_max);
     int maxcl = 1;
     for (ColourPlan& C : P.cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
     lu_scr.alloc((size_t)maxcl * 256 * 256 * (nmax > 64 ? 1 : 0) + 1);
+    const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
+    gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 2 * 130 * 130 * (nmax > 64 ? 1 : 0) + 1);
     // blocks of this level
     if (l == L) {
@@ -1012,6 +1014,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     v.slot_a = P.d_slot_a.p;
     v.slot_b = P.d_slot_b.p;
     v.slots = slots.p;
+    v.nnear = P.nnear;
     v.diag_slot = P.d_diag_slot.p;
     v.np_ptr = P.d_np_ptr.p;
     v.np_cl = P.d_np_cl.p;
@@ -1066,7 +1069,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.colour = c;
       ct.tiles = F.tiles;
       hipEvent_t e0 = ev.next(st);
-      launch_gram_fill(v, ct, st);
+      launch_gram_fill(v, ct, gram_part.p, gram_pstride, st);
       check_launch("gram_fill");
       launch_xform(v, ct, 0, st);
       launch_xform(v, ct, 1, st);
@@ -1074,8 +1077,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       launch_step0_eig(v, ct, eig_scr.p, st);
       check_launch("step0_eig");
       launch_xform(v, ct, 2, st);
-      launch_proj(v, ct, temp.p, 0, st);
-      launch_proj(v, ct, temp.p, 1, st);
+      if (F.tiles == 1) {
+        launch_proj_fused(v, ct, st);
+      } else {
+        launch_proj(v, ct, temp.p, 0, st);
+        launch_proj(v, ct, temp.p, 1, st);
+      }
       check_launch("projection");
       hipEvent_t e1 = ev.next(st);
       launch_lu(v, ct, lu_scr.p, st);
@@ -1314,6 +1321,17 @@ static void ensure_vbuf(h2_ctx* H, int nrhs) {
   H->vtmp.alloc(std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs);
   H->vtmp2.alloc(std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs);
   H->vtmp3.alloc(std::max<int64_t>(1, H->N) * nrhs);
+  // sweep scratch: per colour cluster and block of 64 right-hand sides, one (64 tiles) x 64 panel
+  int64_t blk = 1;
+  for (size_t j = 0; j < H->flev.size(); ++j) {
+    int maxcl = 1;
+    for (const ColourPlan& C : H->plans[j].cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
+    const int64_t ldp = (int64_t)H->flev[j].tiles * 64;
+    blk = std::max<int64_t>(blk, (int64_t)maxcl * ldp * 64);
+  }
+  const int64_t zb = (nrhs + 63) / 64;
+  H->sw_scratch.alloc(blk * zb);
+  H->sw_part.alloc(blk * zb * BWD_SPLIT);
   H->vbuf_nrhs = nrhs;
 }
 
@@ -1337,7 +1355,7 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
   const int64_t N = H->N;
   ensure_vbuf(H, nrhs);
   if (H->flev.empty()) {
-    launch_dense_gemv(H->Zinv.p, N, in, H->vtmp2.p, N, nrhs, adj, st);
+    launch_dense_apply(H->Zinv.p, N, in, H->vtmp2.p, N, nrhs, adj, st);
     HIPCHK(hipMemcpyAsync(out, H->vtmp2.p, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
     check_launch("host.cpp:1314");
     return;
@@ -1350,8 +1368,7 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
     LevelPlan& P = H->plans[j];
     for (int c = 0; c < P.ncol; ++c) {
       ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
-      launch_fwd_local(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, st);
-      launch_fwd_gather(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, st);
+      launch_sweep_fwd(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, H->sw_scratch.p, st);
     }
     const int npar = S.nclusters(P.l - 1);
     if (j + 1 < nlev) {
@@ -1364,7 +1381,7 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
       d_po.upload(po, st);
       launch_vmerge(npar, F.d_kt.p, F.d_voff.p, d_po.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp.p, 1,
                     P.d_nonempty.p, st);
-      launch_dense_gemv(H->Zinv.p, H->nf, H->vtmp.p, H->vtmp2.p, H->nf, nrhs, adj, st);
+      launch_dense_apply(H->Zinv.p, H->nf, H->vtmp.p, H->vtmp2.p, H->nf, nrhs, adj, st);
       launch_vmerge(npar, F.d_kt.p, F.d_voff.p, d_po.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp2.p, 0,
                     P.d_nonempty.p, st);
       check_launch("host.cpp:1342");
@@ -1382,7 +1399,8 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
     }
     for (int c = P.ncol - 1; c >= 0; --c) {
       ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
-      launch_bwd_local(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, st);
+      launch_sweep_bwd(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, H->sw_part.p, BWD_SPLIT,
+                       H->sw_scratch.p, st);
     }
     check_launch("host.cpp:1359");
   }

@@ -331,7 +331,9 @@ __device__ __forceinline__ void rr_pair(int k, int round, int m, int& p, int& q)
 __device__ void jacobi_core(double2* A, double2* U, int m, int rel, Rot* rot, int* flag, double fro) {
   const int tid = threadIdx.x;
   const int h = m / 2;
-  const double tol_abs = 2e-17 * fro;
+  // stopping rules reachable in double precision: |g_pq| <= 1e-15 ||G||_F (absolute)
+  // or |g_pq| <= 4e-16 sqrt(|g_pp g_qq|) (relative accuracy for the small eigenvalues)
+  const double tol_abs = 1e-15 * fro;
   for (int sweep = 0; sweep < 24; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
@@ -342,7 +344,7 @@ __device__ void jacobi_core(double2* A, double2* U, int m, int rel, Rot* rot, in
         const double a = A[p + p * m].x, d = A[q + q * m].x;
         const double2 b = A[p + q * m];
         const double bb = sqrt(cabs2(b));
-        bool go = rel ? (bb > 2.2e-16 * sqrt(fabs(a * d)) && bb > 1e-300) : (bb > tol_abs);
+        bool go = rel ? (bb > 4e-16 * sqrt(fabs(a * d)) && bb > 1e-300) : (bb > tol_abs);
         Rot R;
         if (go) {
           const double th = (d - a) / (2.0 * bb);
@@ -585,28 +587,50 @@ void launch_householder_perp(const LevelView& v, int nc, hipStream_t st) {
   hipLaunchKernelGGL(k_householder_perp, dim3(nc), dim3(256), 0, st, v);
 }
 
-// Step 0 Gram of the fill-ins in block row i: H_i = sum_b F_ib F_ib^H.
-__global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c) {
+// Step 0 Gram of the fill-ins in block row i: H_i = sum_b F_ib F_ib^H, split over
+// GRAM_SPLIT partial sums (partner j goes to part j % GRAM_SPLIT) that
+// k_gram_fill_reduce adds in a fixed order.  Partial j of colour cluster x sits at
+// part + j * pstride + x * (64 tiles)^2.  grid: (cluster, tiles^2, part)
+
+__global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, double2* part, int64_t pstride) {
   __shared__ TileSmem<double> s;
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i];
   const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const int sp = blockIdx.z;
   if (tr * 64 >= n || tc * 64 >= n) return;
   const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
   TileAcc<double> acc;
   acc.zero();
-  for (int j = v.fp_ptr[i]; j < v.fp_ptr[i + 1]; ++j) {
+  for (int j = v.fp_ptr[i] + sp; j < v.fp_ptr[i + 1]; j += GRAM_SPLIT) {
     const int b = v.fp_cl[j];
     const double2* F = v.slots + v.slot_off[v.fp_srow[j]];
     const int mb = dim_before(v, b, c.colour);
     gemm_tile<double, double2>(s, acc, F + tr * 64, n, OP_N, F + tc * 64, n, OP_C, m, nn, mb);
   }
-  store_tile<double, double2>(acc, v.W + v.w_off[i] + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
+  const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
+  double2* P = part + (int64_t)sp * pstride + (int64_t)blockIdx.x * cstride;
+  store_tile<double, double2>(acc, P + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
 }
 
-void launch_gram_fill(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+// H_i = sum of the partial Grams in a fixed order (deterministic)
+__global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* part, int64_t pstride) {
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i];
+  double2* H = v.W + v.w_off[i];
+  const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
+  const double2* P0 = part + (int64_t)blockIdx.x * cstride;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    double2 a = P0[e];
+    for (int sp = 1; sp < GRAM_SPLIT; ++sp) a = cadd(a, P0[(int64_t)sp * pstride + e]);
+    H[e] = a;
+  }
+}
+
+void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st) {
   if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_gram_fill, dim3(c.ncl, c.tiles * c.tiles), dim3(256), 0, st, v, c);
+  hipLaunchKernelGGL(k_gram_fill, dim3(c.ncl, c.tiles * c.tiles, GRAM_SPLIT), dim3(256), 0, st, v, c, part, pstride);
+  hipLaunchKernelGGL(k_gram_fill_reduce, dim3(c.ncl), dim3(256), 0, st, v, c, part, pstride);
 }
 
 // phase 0: X = H B_perp ; phase 1: G' = B_perp^H X ; phase 2: Q~[:, k:n] = B_perp U'
@@ -668,21 +692,68 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
     double2* W = v.W + v.w_off[i];
     double2* Gp = W + (int64_t)n * n + (int64_t)n * d;
     double2* Up = Gp + (int64_t)d * d;
-    double2 *A = sA, *Uw = sU;
-    if (d > JLDS) {
-      A = scratch + (int64_t)blockIdx.x * 2 * 130 * 130;
-      Uw = A + 130 * 130;
+    // p = 0 exactly when every eigenvalue of G' is below tau0^2 = (eps_fill nu)^2 (then
+    // sigma_1(W) < eps_fill nu < nu and the threshold tau = eps_fill max(nu, sigma_1) = tau0):
+    // tested by a Cholesky factorization of tau0^2 I - G', which succeeds iff it is
+    // positive definite.  Any orthonormal complement then serves as B~perp: U' = I.
+    const double tau0 = v.eps_fill * v.nu[i];
+    const bool forced = v.forced && v.forced[i] >= 0;
+    bool skip;
+    if (forced) {
+      skip = v.forced[i] - k <= 0;
+    } else {
+      double2* M = (d <= JLDS) ? sA : scratch + (int64_t)blockIdx.x * 2 * 130 * 130;
+      for (int e = tid; e < d * d; e += blockDim.x) {
+        const int r = e % d, q = e / d;
+        const double2 gv = Gp[e];
+        M[e] = (r == q) ? make_double2(tau0 * tau0 - gv.x, 0.0) : make_double2(-gv.x, -gv.y);
+      }
+      __syncthreads();
+      skip = tau0 > 0.0;
+      for (int j = 0; j < d && skip; ++j) {
+        const double piv = M[j + j * d].x;
+        if (!(piv > 0.0)) {
+          skip = false;
+          break;
+        }
+        const double ljj = sqrt(piv);
+        for (int r = j + 1 + tid; r < d; r += blockDim.x) {
+          M[r + j * d].x /= ljj;
+          M[r + j * d].y /= ljj;
+        }
+        __syncthreads();
+        const int rem = d - j - 1;
+        for (int e = tid; e < rem * rem; e += blockDim.x) {
+          const int r = j + 1 + e % rem, q = j + 1 + e / rem;
+          if (q <= r) M[r + q * d] = csub(M[r + q * d], cmul(M[r + j * d], cconj(M[q + j * d])));
+        }
+        __syncthreads();
+      }
+      __syncthreads();
     }
-    jacobi_solve(Gp, d, d, A, Uw, lam, Up, d, 0, rot, &flag, red);
-    const double s1 = sqrt(fmax(lam[0], 0.0));
-    const double tau = v.eps_fill * fmax(v.nu[i], s1);
-    if (tau > 0.0) {
-      for (int j = 0; j < d; ++j)
-        if (sqrt(fmax(lam[j], 0.0)) > tau) p = j + 1;
-    }
-    if (tid == 0 && v.margins) {
-      v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(lam[p - 1], 0.0)) / tau : 1e300;
-      v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(lam[p], 0.0)) / tau : 0.0;
+    if (skip) {
+      for (int e = tid; e < d * d; e += blockDim.x) Up[e] = make_double2((e % d) == (e / d) ? 1.0 : 0.0, 0.0);
+      if (tid == 0 && v.margins) {
+        v.margins[2 * i] = 1e300;
+        v.margins[2 * i + 1] = -1.0;  // sigma_1 / tau < 1, not evaluated
+      }
+    } else {
+      double2 *A = sA, *Uw = sU;
+      if (d > JLDS) {
+        A = scratch + (int64_t)blockIdx.x * 2 * 130 * 130;
+        Uw = A + 130 * 130;
+      }
+      jacobi_solve(Gp, d, d, A, Uw, lam, Up, d, 0, rot, &flag, red);
+      const double s1 = sqrt(fmax(lam[0], 0.0));
+      const double tau = v.eps_fill * fmax(v.nu[i], s1);
+      if (tau > 0.0) {
+        for (int j = 0; j < d; ++j)
+          if (sqrt(fmax(lam[j], 0.0)) > tau) p = j + 1;
+      }
+      if (tid == 0 && v.margins) {
+        v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(lam[p - 1], 0.0)) / tau : 1e300;
+        v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(lam[p], 0.0)) / tau : 0.0;
+      }
     }
   }
   if (v.forced && v.forced[i] >= 0) p = min(max(v.forced[i] - k, 0), d);
@@ -742,6 +813,39 @@ __global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double
     gemm_tile<double, double2>(s, acc, T + tr * 64, nx, OP_N, Q + (int64_t)tc * 64 * ny, ny, OP_R, m, nn, ny);
     store_tile<double, double2>(acc, Z + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
   }
+}
+
+// Fused Step 2 for levels whose blocks fit one 64x64 tile: the workgroup owns the
+// whole block, so Z <- Q~_x^H Z and Z <- Z conj(Q~_y) are applied in place.  Fill
+// blocks keep only the k~_x kept rows of a row cluster eliminated now.
+__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c) {
+  __shared__ TileSmem<double> s;
+  const int sl = c.pj_slot[blockIdx.x];
+  const int x = v.slot_a[sl], y = v.slot_b[sl];
+  const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
+  const int nx = v.n[x], ny = v.n[y];
+  const bool fill = sl >= v.nnear;
+  const int rows = cx ? (fill ? v.kt[x] : nx) : dim_before(v, x, c.colour);
+  const int cols_in = cy ? ny : dim_before(v, y, c.colour);
+  double2* Z = v.slots + v.slot_off[sl];
+  if (cx && rows > 0 && cols_in > 0) {
+    TileAcc<double> acc;
+    acc.zero();
+    gemm_tile<double, double2>(s, acc, v.Q + v.q_off[x], nx, OP_C, Z, nx, OP_N, rows, cols_in, nx);
+    store_tile<double, double2>(acc, Z, nx, rows, cols_in, ST_SET);
+    __syncthreads();
+  }
+  if (cy && rows > 0 && ny > 0) {
+    TileAcc<double> acc;
+    acc.zero();
+    gemm_tile<double, double2>(s, acc, Z, nx, OP_N, v.Q + v.q_off[y], ny, OP_R, rows, ny, ny);
+    store_tile<double, double2>(acc, Z, nx, rows, ny, ST_SET);
+  }
+}
+
+void launch_proj_fused(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+  if (c.npj <= 0) return;
+  hipLaunchKernelGGL(k_proj_fused, dim3(c.npj), dim3(256), 0, st, v, c);
 }
 
 void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, hipStream_t st) {
@@ -908,6 +1012,10 @@ __global__ void __launch_bounds__(256) k_schur(LevelView v, ColourTasks c) {
   const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
   if (tr * 64 >= ma || tc * 64 >= mb) return;
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
+  const int na = v.n[a];
+  double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
+  TilePre<double, double2> pre;
+  prefetch_tile<double, double2>(pre, Z, na, m, nn);  // target loads overlap the contraction
   TileAcc<double> acc;
   acc.zero();
   for (int e = c.sc_cptr[task]; e < c.sc_cptr[task + 1]; ++e) {
@@ -919,9 +1027,7 @@ __global__ void __launch_bounds__(256) k_schur(LevelView v, ColourTasks c) {
     const double2* R = v.RP + v.rp_off[i] + (int64_t)(v.np_off[c.sc_jb[e]] + tc * 64) * rmax;
     gemm_tile<double, double2>(s, acc, C, pr, OP_N, R, rmax, OP_N, m, nn, r);
   }
-  const int na = v.n[a];
-  double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
-  store_tile<double, double2>(acc, Z, na, m, nn, ST_SUB);
+  store_tile_sub_pre<double, double2>(acc, pre, Z, na, m, nn);
 }
 
 void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st) {
@@ -1125,151 +1231,383 @@ void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream
 }
 
 // ===========================================================================
-// Substitution sweeps (nrhs columns)
+// Substitution sweeps (nrhs columns, right-hand sides are the N dimension of
+// the MFMA tiles; blockIdx.z selects a block of 64 right-hand sides)
 // ===========================================================================
-// Forward (adj = 0): b_i <- Q~^H b_i ; b_i' <- (L^-1 P) b_i'.
-// Adjoint phase A (adj = 1): g_i <- Q~^T g_i ; g_i' <- U^-H g_i'.
-__global__ void __launch_bounds__(256) k_fwd_local(LevelView v, ColourTasks c, double2* vec,
-                                                   const int64_t* voff, int64_t ldv, int nrhs, int adj) {
-  __shared__ double2 xs[512];
-  __shared__ double2 ys[512];
+// C (m x n) (op)= op(A) op(B) over every 64x64 tile, by one workgroup.
+__device__ void wg_gemm(TileSmem<double>& s, const double2* A, int64_t lda, int opA, const double2* B, int64_t ldb,
+                        int opB, double2* C, int64_t ldc, int m, int n, int K, int mode) {
+  for (int tr = 0; tr * 64 < m; ++tr)
+    for (int tc = 0; tc * 64 < n; ++tc) {
+      const int mm = min(64, m - tr * 64), nn = min(64, n - tc * 64);
+      const double2* At = (opA == OP_N || opA == OP_R) ? A + tr * 64 : A + (int64_t)tr * 64 * lda;
+      const double2* Bt = (opB == OP_N || opB == OP_R) ? B + (int64_t)tc * 64 * ldb : B + tc * 64;
+      TileAcc<double> acc;
+      acc.zero();
+      gemm_tile<double, double2>(s, acc, At, lda, opA, Bt, ldb, opB, mm, nn, K);
+      store_tile<double, double2>(acc, C + tr * 64 + (int64_t)tc * 64 * ldc, ldc, mm, nn, mode);
+    }
+}
+
+// Forward (adj 0): b_i <- Q~^H b_i, b_i' <- (L^-1 P) b_i'.
+// Adjoint phase A (adj 1): g_i <- Q~^T g_i, g_i' <- U^-H g_i'.
+// scratch: (ncl * gridDim.z) blocks of (64 tiles) x 64.
+__global__ void __launch_bounds__(256) k_sw_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, double2* scratch) {
+  __shared__ TileSmem<double> s;
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  if (n == 0) return;
+  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int ldy = c.tiles * 64;
+  double2* Y = scratch + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * ldy * 64;
+  double2* b = vec + voff[i] + (int64_t)c0 * ldv;
   const double2* Q = v.Q + v.q_off[i];
-  const double2* Li = v.LU + v.lu_off[i];
-  const double2* Ui = Li + (int64_t)rmax * rmax;
-  for (int col = 0; col < nrhs; ++col) {
-    double2* b = vec + voff[i] + col * ldv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < n; e += blockDim.x) xs[e] = b[e];
-    __syncthreads();
-    for (int row = threadIdx.x; row < n; row += blockDim.x) {
-      double2 acc = make_double2(0, 0);
-      const double2* qc = Q + (int64_t)row * n;  // column `row` of Q~
-      if (!adj)
-        for (int e = 0; e < n; ++e) acc = cadd(acc, cmulc(qc[e], xs[e]));
-      else
-        for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(qc[e], xs[e]));
-      ys[row] = acc;
-    }
-    __syncthreads();
-    for (int row = threadIdx.x; row < n; row += blockDim.x) {
-      if (row < kt) {
-        b[row] = ys[row];
-      } else {
-        const int q = row - kt;
-        double2 acc = make_double2(0, 0);
-        if (!adj)
-          for (int e = 0; e < r; ++e) acc = cadd(acc, cmul(Li[q + (int64_t)e * rmax], ys[kt + e]));
-        else
-          for (int e = 0; e < r; ++e) acc = cadd(acc, cmulc(Ui[e + (int64_t)q * rmax], ys[kt + e]));
-        b[row] = acc;
-      }
-    }
+  wg_gemm(s, Q, n, adj ? OP_T : OP_C, b, ldv, OP_N, Y, ldy, n, nr, n, ST_SET);
+  __syncthreads();
+  for (int e = threadIdx.x; e < kt * nr; e += blockDim.x) {
+    const int row = e % kt, col = e / kt;
+    b[row + (int64_t)col * ldv] = Y[row + (int64_t)col * ldy];
+  }
+  if (r > 0) {
+    const double2* Li = v.LU + v.lu_off[i];
+    const double2* Ui = Li + (int64_t)rmax * rmax;
+    if (!adj)
+      wg_gemm(s, Li, rmax, OP_N, Y + kt, ldy, OP_N, b + kt, ldv, r, nr, r, ST_SET);
+    else
+      wg_gemm(s, Ui, rmax, OP_C, Y + kt, ldy, OP_N, b + kt, ldv, r, nr, r, ST_SET);
   }
 }
 
-void launch_fwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
-                      int nrhs, int adj, hipStream_t st) {
-  if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_fwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
-}
-
-// b_a[0:m_a] -= sum_i C_i[a] b_i'   (adj: g_a -= R_i[:, a]^H g_i')
-__global__ void __launch_bounds__(256) k_fwd_gather(LevelView v, ColourTasks c, double2* vec,
-                                                    const int64_t* voff, int64_t ldv, int nrhs, int adj) {
+// b_a[0:m_a] -= sum_i C_i[a] b_i'  (adj: g_a -= R_i[:, a]^H g_i').  grid: (target, row tiles, rhs blocks)
+__global__ void __launch_bounds__(256) k_sw_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                       int64_t ldv, int nrhs, int adj) {
+  __shared__ TileSmem<double> s;
   const int task = blockIdx.x;
   const int a = c.sv_cl[task];
   const int ma = dim_after(v, a, c.colour);
-  for (int col = 0; col < nrhs; ++col) {
-    for (int row = threadIdx.x; row < ma; row += blockDim.x) {
-      double2 acc = make_double2(0, 0);
-      for (int e = c.sv_cptr[task]; e < c.sv_cptr[task + 1]; ++e) {
-        const int i = c.sv_i[e];
-        const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
-        const double2* bi = vec + voff[i] + col * ldv + kt;
-        const int off = v.np_off[c.sv_ja[e]];
-        if (!adj) {
-          const int pr = v.prow[i];
-          const double2* C = v.CP + v.cp_off[i] + off + row;
-          for (int q = 0; q < r; ++q) acc = cadd(acc, cmul(C[(int64_t)q * pr], bi[q]));
-        } else {
-          const double2* R = v.RP + v.rp_off[i] + (int64_t)(off + row) * rmax;
-          for (int q = 0; q < r; ++q) acc = cadd(acc, cmulc(R[q], bi[q]));
-        }
-      }
-      double2* ba = vec + voff[a] + col * ldv;
-      ba[row] = csub(ba[row], acc);
+  const int tr = blockIdx.y;
+  if (tr * 64 >= ma) return;
+  const int m = min(64, ma - tr * 64);
+  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  TileAcc<double> acc;
+  acc.zero();
+  for (int e = c.sv_cptr[task]; e < c.sv_cptr[task + 1]; ++e) {
+    const int i = c.sv_i[e];
+    const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+    if (r <= 0) continue;
+    const int off = v.np_off[c.sv_ja[e]];
+    const double2* bi = vec + voff[i] + kt + (int64_t)c0 * ldv;
+    if (!adj) {
+      const int pr = v.prow[i];
+      gemm_tile<double, double2>(s, acc, v.CP + v.cp_off[i] + off + tr * 64, pr, OP_N, bi, ldv, OP_N, m, nr, r);
+    } else {
+      gemm_tile<double, double2>(s, acc, v.RP + v.rp_off[i] + (int64_t)(off + tr * 64) * rmax, rmax, OP_C, bi, ldv,
+                                 OP_N, m, nr, r);
     }
+  }
+  store_tile<double, double2>(acc, vec + voff[a] + tr * 64 + (int64_t)c0 * ldv, ldv, m, nr, ST_SUB);
+}
+
+// Partial sums of the backward gather: part_j = sum over partners of chunk j of
+// R_i[:, a] y_a (adj: C_i[a, :]^H g_a).  grid: (cluster, chunk, rhs blocks)
+__global__ void __launch_bounds__(256) k_sw_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+                                                        const int64_t* voff, int64_t ldv, int nrhs, int adj,
+                                                        double2* part, int nsplit) {
+  __shared__ TileSmem<double> s;
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  const int chunk = blockIdx.y;
+  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int ldp = c.tiles * 64;
+  double2* P = part + (((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * nsplit + chunk) * ldp * 64;
+  if (r <= 0) return;
+  const int pr = v.prow[i];
+  for (int tr = 0; tr * 64 < r; ++tr) {
+    const int m = min(64, r - tr * 64);
+    TileAcc<double> acc;
+    acc.zero();
+    for (int j = v.np_ptr[i] + chunk; j < v.np_ptr[i + 1]; j += nsplit) {
+      const int a = v.np_cl[j];
+      const int ma = (a == i) ? kt : dim_before(v, a, c.colour);
+      const double2* ya = vec + voff[a] + (int64_t)c0 * ldv;
+      const int off = v.np_off[j];
+      if (!adj)
+        gemm_tile<double, double2>(s, acc, v.RP + v.rp_off[i] + tr * 64 + (int64_t)off * rmax, rmax, OP_N, ya, ldv,
+                                   OP_N, m, nr, ma);
+      else
+        gemm_tile<double, double2>(s, acc, v.CP + v.cp_off[i] + off + (int64_t)tr * 64 * pr, pr, OP_C, ya, ldv, OP_N,
+                                   m, nr, ma);
+    }
+    store_tile<double, double2>(acc, P + tr * 64, ldp, m, nr, ST_SET);
   }
 }
 
-void launch_fwd_gather(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
-                       int nrhs, int adj, hipStream_t st) {
-  if (c.nsv <= 0) return;
-  hipLaunchKernelGGL(k_fwd_gather, dim3(c.nsv), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+// Backward (adj 0): y_i' <- U^-1 (y_i' - sum parts), y_i <- conj(Q~) y_i.
+// Adjoint phase B (adj 1): g_i' <- (L^-1 P)^H (g_i' - sum parts), g_i <- Q~ g_i.
+__global__ void __launch_bounds__(256) k_sw_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, const double2* part, int nsplit,
+                                                      double2* scratch) {
+  __shared__ TileSmem<double> s;
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  if (n == 0) return;
+  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int ldp = c.tiles * 64;
+  double2* Y = scratch + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * ldp * 64;
+  double2* y = vec + voff[i] + (int64_t)c0 * ldv;
+  const double2* P = part + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * nsplit * ldp * 64;
+  // Y = [y[0:kt]; acc] with acc = y' - sum of the partial sums
+  for (int e = threadIdx.x; e < n * nr; e += blockDim.x) {
+    const int row = e % n, col = e / n;
+    double2 val = y[row + (int64_t)col * ldv];
+    if (row >= kt)
+      for (int j = 0; j < nsplit; ++j) val = csub(val, P[(int64_t)j * ldp * 64 + (row - kt) + (int64_t)col * ldp]);
+    Y[row + (int64_t)col * ldp] = val;
+  }
+  __syncthreads();
+  if (r > 0) {
+    const double2* Li = v.LU + v.lu_off[i];
+    const double2* Ui = Li + (int64_t)rmax * rmax;
+    // y' into the vector, then copied back into Y for the basis change
+    if (!adj)
+      wg_gemm(s, Ui, rmax, OP_N, Y + kt, ldp, OP_N, y + kt, ldv, r, nr, r, ST_SET);
+    else
+      wg_gemm(s, Li, rmax, OP_C, Y + kt, ldp, OP_N, y + kt, ldv, r, nr, r, ST_SET);
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * nr; e += blockDim.x) {
+      const int row = e % r, col = e / r;
+      Y[kt + row + (int64_t)col * ldp] = y[kt + row + (int64_t)col * ldv];
+    }
+    __syncthreads();
+  }
+  const double2* Q = v.Q + v.q_off[i];
+  wg_gemm(s, Q, n, adj ? OP_N : OP_R, Y, ldp, OP_N, y, ldv, n, nr, n, ST_SET);
 }
 
-// Backward (adj = 0): y_i' <- U^-1 (y_i' - sum_a R_i[a] y_a) ; y_i <- conj(Q~) y_i.
-// Adjoint phase B (adj = 1): g_i' <- (L^-1 P)^H (g_i' - sum_a C_i[a]^H g_a) ; g_i <- Q~ g_i.
-__global__ void __launch_bounds__(256) k_bwd_local(LevelView v, ColourTasks c, double2* vec,
-                                                   const int64_t* voff, int64_t ldv, int nrhs, int adj) {
-  __shared__ double2 xs[512];
-  __shared__ double2 ys[512];
+// ---------------------------------------------------------------------------
+// Small right-hand-side counts (nrhs <= SMALL_RHS): matrix-vector products,
+// coalesced along the column-major storage.
+// ---------------------------------------------------------------------------
+// y[0:m] = op(M) x for column-major M (m x n, ld); op N or conj (R).  All threads.
+__device__ __forceinline__ void bv_gemv_n(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y,
+                                          bool conj) {
+  for (int row = threadIdx.x; row < m; row += blockDim.x) {
+    double2 acc = make_double2(0, 0);
+    const double2* Mr = M + row;
+    if (!conj)
+      for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(Mr[(int64_t)e * ld], x[e]));
+    else
+      for (int e = 0; e < n; ++e) acc = cadd(acc, cmulc(Mr[(int64_t)e * ld], x[e]));
+    y[row] = acc;
+  }
+}
+
+// y[0:n] = M^T x (conj: M^H x) for column-major M (m x n): one wavefront per output.
+__device__ __forceinline__ void bv_gemv_t(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y,
+                                          bool conj) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = w; j < n; j += nw) {
+    double2 acc = make_double2(0, 0);
+    const double2* Mc = M + (int64_t)j * ld;
+    if (!conj)
+      for (int r = lane; r < m; r += 64) acc = cadd(acc, cmul(Mc[r], x[r]));
+    else
+      for (int r = lane; r < m; r += 64) acc = cadd(acc, cmulc(Mc[r], x[r]));
+    acc.x = wave_sum(acc.x);
+    acc.y = wave_sum(acc.y);
+    if (lane == 0) y[j] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sv_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj) {
+  __shared__ double2 xs[512], ys[512];
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   const double2* Q = v.Q + v.q_off[i];
   const double2* Li = v.LU + v.lu_off[i];
   const double2* Ui = Li + (int64_t)rmax * rmax;
-  const int pr = v.prow[i];
   for (int col = 0; col < nrhs; ++col) {
-    double2* y = vec + voff[i] + col * ldv;
+    double2* b = vec + voff[i] + (int64_t)col * ldv;
     __syncthreads();
-    for (int e = threadIdx.x; e < n; e += blockDim.x) xs[e] = y[e];
+    for (int e = threadIdx.x; e < n; e += blockDim.x) xs[e] = b[e];
     __syncthreads();
-    // acc_q = y'_q - sum over partners
-    for (int q = threadIdx.x; q < r; q += blockDim.x) {
-      double2 acc = xs[kt + q];
-      for (int j = v.np_ptr[i]; j < v.np_ptr[i + 1]; ++j) {
-        const int a = v.np_cl[j];
-        const int ma = (a == i) ? kt : dim_before(v, a, c.colour);
-        const double2* ya = (a == i) ? nullptr : vec + voff[a] + col * ldv;
-        const int off = v.np_off[j];
-        if (!adj) {
-          const double2* R = v.RP + v.rp_off[i] + q + (int64_t)off * rmax;
-          for (int e = 0; e < ma; ++e) acc = csub(acc, cmul(R[(int64_t)e * rmax], (a == i) ? xs[e] : ya[e]));
-        } else {
-          const double2* C = v.CP + v.cp_off[i] + off + (int64_t)q * pr;
-          for (int e = 0; e < ma; ++e) acc = csub(acc, cmulc(C[e], (a == i) ? xs[e] : ya[e]));
-        }
-      }
-      ys[q] = acc;
-    }
+    bv_gemv_t(Q, n, n, n, xs, ys, !adj);  // Q~^H b  (adj: Q~^T g)
     __syncthreads();
-    for (int q = threadIdx.x; q < r; q += blockDim.x) {
-      double2 acc = make_double2(0, 0);
+    for (int e = threadIdx.x; e < kt; e += blockDim.x) b[e] = ys[e];
+    if (r > 0) {
       if (!adj)
-        for (int e = q; e < r; ++e) acc = cadd(acc, cmul(Ui[q + (int64_t)e * rmax], ys[e]));
+        bv_gemv_n(Li, rmax, r, r, ys + kt, b + kt, false);
       else
-        for (int e = 0; e < r; ++e) acc = cadd(acc, cmulc(Li[e + (int64_t)q * rmax], ys[e]));
-      xs[kt + q] = acc;
-    }
-    __syncthreads();
-    for (int row = threadIdx.x; row < n; row += blockDim.x) {
-      double2 acc = make_double2(0, 0);
-      if (!adj)
-        for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(cconj(Q[row + (int64_t)e * n]), xs[e]));
-      else
-        for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(Q[row + (int64_t)e * n], xs[e]));
-      y[row] = acc;
+        bv_gemv_t(Ui, rmax, r, r, ys + kt, b + kt, true);
     }
   }
 }
 
-void launch_bwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
-                      int nrhs, int adj, hipStream_t st) {
+__global__ void __launch_bounds__(256) k_sv_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                       int64_t ldv, int nrhs, int adj) {
+  __shared__ double2 red[4][128];
+  const int task = blockIdx.x;
+  const int a = c.sv_cl[task];
+  const int ma = dim_after(v, a, c.colour);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int col = 0; col < nrhs; ++col) {
+    for (int rb = 0; rb < ma; rb += 128) {
+      double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+      for (int e = c.sv_cptr[task]; e < c.sv_cptr[task + 1]; ++e) {
+        const int i = c.sv_i[e];
+        const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+        const double2* bi = vec + voff[i] + kt + (int64_t)col * ldv;
+        const int off = v.np_off[c.sv_ja[e]];
+        if (!adj) {
+          // rows on lanes, the r columns of C split over the four wavefronts
+          const int pr = v.prow[i];
+          for (int h = 0; h < 2; ++h) {
+            const int row = rb + h * 64 + lane;
+            if (row >= ma) continue;
+            const double2* C = v.CP + v.cp_off[i] + off + row;
+            for (int q = w; q < r; q += 4) acc[h] = cadd(acc[h], cmul(C[(int64_t)q * pr], bi[q]));
+          }
+        } else {
+          // row dot products: rows split over lanes of the wavefronts, r terms each
+          const double2* R = v.RP + v.rp_off[i];
+          for (int h = 0; h < 2; ++h) {
+            const int row = rb + h * 64 + lane;
+            if (row >= ma || w != 0) continue;
+            const double2* Rc = R + (int64_t)(off + row) * rmax;
+            for (int q = 0; q < r; ++q) acc[h] = cadd(acc[h], cmulc(Rc[q], bi[q]));
+          }
+        }
+      }
+      red[w][lane] = acc[0];
+      red[w][64 + lane] = acc[1];
+      __syncthreads();
+      if (threadIdx.x < 128) {
+        const int row = rb + threadIdx.x;
+        if (row < ma) {
+          double2 t = cadd(cadd(red[0][threadIdx.x], red[1][threadIdx.x]), cadd(red[2][threadIdx.x], red[3][threadIdx.x]));
+          double2* ba = vec + voff[a] + row + (int64_t)col * ldv;
+          *ba = csub(*ba, t);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sv_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+                                                        const int64_t* voff, int64_t ldv, int nrhs, int adj,
+                                                        double2* part, int nsplit) {
+  __shared__ double2 red[4][128];
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  const int chunk = blockIdx.y;
+  const int ldp = c.tiles * 64;
+  double2* P = part + ((int64_t)blockIdx.x * nsplit + chunk) * ldp * 64;
+  if (r <= 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int pr = v.prow[i];
+  for (int col = 0; col < nrhs; ++col) {
+    for (int qb = 0; qb < r; qb += 128) {
+      double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+      for (int j = v.np_ptr[i] + chunk; j < v.np_ptr[i + 1]; j += nsplit) {
+        const int a = v.np_cl[j];
+        const int ma = (a == i) ? kt : dim_before(v, a, c.colour);
+        const double2* ya = vec + voff[a] + (int64_t)col * ldv;
+        const int off = v.np_off[j];
+        if (!adj) {
+          const double2* R = v.RP + v.rp_off[i] + (int64_t)off * rmax;
+          for (int h = 0; h < 2; ++h) {
+            const int q = qb + h * 64 + lane;
+            if (q >= r) continue;
+            for (int e = w; e < ma; e += 4) acc[h] = cadd(acc[h], cmul(R[q + (int64_t)e * rmax], ya[e]));
+          }
+        } else {
+          const double2* C = v.CP + v.cp_off[i] + off;
+          for (int h = 0; h < 2; ++h) {
+            const int q = qb + h * 64 + lane;
+            if (q >= r) continue;
+            for (int e = w; e < ma; e += 4) acc[h] = cadd(acc[h], cmulc(C[e + (int64_t)q * pr], ya[e]));
+          }
+        }
+      }
+      red[w][lane] = acc[0];
+      red[w][64 + lane] = acc[1];
+      __syncthreads();
+      if (threadIdx.x < 128) {
+        const int q = qb + threadIdx.x;
+        if (q < r)
+          P[q + (int64_t)col * ldp] =
+              cadd(cadd(red[0][threadIdx.x], red[1][threadIdx.x]), cadd(red[2][threadIdx.x], red[3][threadIdx.x]));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sv_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, const double2* part,
+                                                      int nsplit) {
+  __shared__ double2 xs[512], ys[512];
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  const int ldp = c.tiles * 64;
+  const double2* Q = v.Q + v.q_off[i];
+  const double2* Li = v.LU + v.lu_off[i];
+  const double2* Ui = Li + (int64_t)rmax * rmax;
+  const double2* P = part + (int64_t)blockIdx.x * nsplit * ldp * 64;
+  for (int col = 0; col < nrhs; ++col) {
+    double2* y = vec + voff[i] + (int64_t)col * ldv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      double2 val = y[e];
+      if (e >= kt)
+        for (int j = 0; j < nsplit; ++j) val = csub(val, P[(int64_t)j * ldp * 64 + (e - kt) + (int64_t)col * ldp]);
+      xs[e] = val;
+    }
+    __syncthreads();
+    if (r > 0) {
+      if (!adj)
+        bv_gemv_n(Ui, rmax, r, r, xs + kt, ys, false);
+      else
+        bv_gemv_t(Li, rmax, r, r, xs + kt, ys, true);
+      __syncthreads();
+      for (int e = threadIdx.x; e < r; e += blockDim.x) xs[kt + e] = ys[e];
+      __syncthreads();
+    }
+    bv_gemv_n(Q, n, n, n, xs, y, !adj);  // conj(Q~) y  (adj: Q~ g)
+  }
+}
+
+void launch_sweep_fwd(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                      int nrhs, int adj, double2* scratch, hipStream_t st) {
   if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_bwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+  if (nrhs <= SMALL_RHS) {
+    hipLaunchKernelGGL(k_sv_fwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+    if (c.nsv > 0) hipLaunchKernelGGL(k_sv_fwd_gather, dim3(c.nsv), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+    return;
+  }
+  const int zb = (nrhs + 63) / 64;
+  hipLaunchKernelGGL(k_sw_fwd_local, dim3(c.ncl, 1, zb), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, scratch);
+  if (c.nsv > 0)
+    hipLaunchKernelGGL(k_sw_fwd_gather, dim3(c.nsv, c.tiles, zb), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+}
+
+void launch_sweep_bwd(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                      int nrhs, int adj, double2* part, int nsplit, double2* scratch, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  if (nrhs <= SMALL_RHS) {
+    hipLaunchKernelGGL(k_sv_bwd_partial, dim3(c.ncl, nsplit), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part,
+                       nsplit);
+    hipLaunchKernelGGL(k_sv_bwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, nsplit);
+    return;
+  }
+  const int zb = (nrhs + 63) / 64;
+  hipLaunchKernelGGL(k_sw_bwd_partial, dim3(c.ncl, nsplit, zb), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part,
+                     nsplit);
+  hipLaunchKernelGGL(k_sw_bwd_local, dim3(c.ncl, 1, zb), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, nsplit,
+                     scratch);
 }
 
 // up = 1: parent vector = [kept(c1); kept(c2)] ; up = 0: children's kept parts from the parent
@@ -1348,7 +1686,27 @@ void launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, con
                      ldy, accumulate);
 }
 
-// y = M x (conj_trans = 0) or M^H x (1) for an n x n dense M; x and y distinct, ld for both
+// y = M x (conj_trans = 0) or M^H x (1) for an n x n dense M; x and y distinct, ld for both.
+// One workgroup per (64-row tile, 64-rhs block).
+__global__ void __launch_bounds__(256) k_dense_apply(const double2* M, int64_t n, const double2* x, double2* y,
+                                                     int64_t ld, int nrhs, int conj_trans) {
+  __shared__ TileSmem<double> s;
+  const int tr = blockIdx.x, c0 = blockIdx.y * 64;
+  const int m = (int)imin64(64, n - (int64_t)tr * 64), nr = min(64, nrhs - c0);
+  TileAcc<double> acc;
+  acc.zero();
+  const double2* A = conj_trans ? M + (int64_t)tr * 64 * n : M + tr * 64;
+  gemm_tile<double, double2>(s, acc, A, n, conj_trans ? OP_C : OP_N, x + (int64_t)c0 * ld, ld, OP_N, m, nr, (int)n);
+  store_tile<double, double2>(acc, y + tr * 64 + (int64_t)c0 * ld, ld, m, nr, ST_SET);
+}
+
+void launch_dense_apply(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
+                        int conj_trans, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_dense_apply, dim3((unsigned)((n + 63) / 64), (nrhs + 63) / 64), dim3(256), 0, st, M, n, x, y, ld,
+                     nrhs, conj_trans);
+}
+
 __global__ void k_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
                              int conj_trans) {
   const int col = blockIdx.y;

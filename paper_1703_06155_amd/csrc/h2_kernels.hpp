@@ -41,6 +41,7 @@ struct LevelView {
   const int32_t* slot_a;
   const int32_t* slot_b;
   double2* slots;
+  int nnear;               // slots [0, nnear) are inadmissible blocks, the rest fill-receiving blocks
   const int32_t* diag_slot;
   // inadmissible partners N+(i) (incl. i), CSR
   const int32_t* np_ptr;
@@ -112,18 +113,20 @@ void launch_transpose_copy(const GemmTask* tasks, int ntasks, hipStream_t st);
 
 // Batched Hermitian eigensolver (cyclic Jacobi): G (d x d, ld d) per problem at
 // goff; writes eigenvalues descending (lam at loff) and eigenvectors (U at uoff,
-// ld d).  rel != 0: rotate until |g_pq| <= 1e-17 sqrt(|g_pp g_qq|) (relative
-// accuracy), else until |g_pq| <= 1e-17 ||G||_F.
+// ld d).  rel != 0: rotate until |g_pq| <= 4e-16 sqrt(|g_pp g_qq|) (relative
+// accuracy), else until |g_pq| <= 1e-15 ||G||_F.
 void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2* G, const int64_t* uoff,
                    double2* U, const int64_t* loff, double* lam, int rel, double2* scratch,
                    const int64_t* soff, hipStream_t st);
 
 // ---- factorization ----
+constexpr int GRAM_SPLIT = 16;  // partial sums of the Step 0 Gram
 void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
-void launch_gram_fill(const LevelView& v, const ColourTasks& c, hipStream_t st);
+void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);
 void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st);
 void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
 void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, hipStream_t st);
+void launch_proj_fused(const LevelView& v, const ColourTasks& c, hipStream_t st);
 void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
 void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st);
 void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st);
@@ -156,12 +159,14 @@ void launch_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv, hip
 void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream_t st);
 
 // ---- sweeps (nrhs columns; per-level vectors with leading dimension ldv) ----
-void launch_fwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
-                      int64_t ldv, int nrhs, int adj, hipStream_t st);
-void launch_fwd_gather(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
-                       int64_t ldv, int nrhs, int adj, hipStream_t st);
-void launch_bwd_local(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
-                      int64_t ldv, int nrhs, int adj, hipStream_t st);
+constexpr int BWD_SPLIT = 8;   // partial sums of the backward gather
+constexpr int SMALL_RHS = 4;   // up to this many right-hand sides the sweeps use matrix-vector kernels
+void launch_sweep_fwd(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                      int nrhs, int adj, double2* scratch, hipStream_t st);
+void launch_sweep_bwd(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
+                      int nrhs, int adj, double2* part, int nsplit, double2* scratch, hipStream_t st);
+void launch_dense_apply(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
+                        int conj_trans, hipStream_t st);
 void launch_vmerge(int np, const int32_t* kt, const int64_t* cvoff, const int64_t* pvoff, int64_t ldc,
                    int64_t ldp, int nrhs, double2* cvec, double2* pvec, int up, const int32_t* nonempty,
                    hipStream_t st);

@@ -145,3 +145,17 @@ def test_free_ranks_match_oracle_outside_band(grid, leaf, eps):
             if got[(l, t)][1] != fk[(l, t)] and not in_band_f:
                 bad.append(("kt", l, t, got[(l, t)][1], fk[(l, t)], mf))
     assert not bad, bad[:5]
+
+
+def test_adjoint_multi_rhs_equals_columns():
+    """The tile (many right-hand sides) and vector (few) sweep kernels agree."""
+    torch = _torch()
+    pr, H, Fz = _oracle(*CASES[1])
+    G = _gpu(pr, H, Fz).factor()
+    rng = np.random.default_rng(5)
+    Gm = rng.standard_normal((pr.n, 6)) + 1j * rng.standard_normal((pr.n, 6))
+    L = G.solve_adjoint(torch.from_numpy(Gm)).cpu().numpy()
+    for j in (0, 3, 5):
+        lj = G.solve_adjoint(torch.from_numpy(Gm[:, j].copy())).cpu().numpy()
+        assert _rel(L[:, j], lj) < 1e-13
+    assert _rel(L, O.solve_adjoint(Fz, Gm)) < 1e-10

@@ -966,7 +966,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     lu_scr.alloc((size_t)maxcl * 256 * 256 * (nmax > 64 ? 1 : 0) + 1);
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
-    eig_scr.alloc((size_t)maxcl * 2 * 130 * 130 * (nmax > 64 ? 1 : 0) + 1);
+    eig_scr.alloc((size_t)maxcl * STEP0_SCRATCH);
     // blocks of this level
     if (l == L) {
       slots.alloc(slot_off[P.nslot]);

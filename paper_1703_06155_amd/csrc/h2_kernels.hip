@@ -673,13 +673,206 @@ void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream
   hipLaunchKernelGGL(k_xform, dim3(c.ncl, c.tiles * c.tiles), dim3(256), 0, st, v, c, phase);
 }
 
+// ---------------------------------------------------------------------------
+// Step 0 eigen-solver for clusters that gain basis vectors (p > 0):
+// Householder reduction of G' to a real symmetric tridiagonal T, all
+// eigenvalues by bisection on Sturm counts, the p dominant eigenvectors by
+// inverse iteration on T mapped back through the reflectors and
+// re-orthonormalised, and an orthonormal complement by Householder QR.
+// O(d) dependent steps instead of the O(d * sweeps) rounds of cyclic Jacobi.
+// ---------------------------------------------------------------------------
+constexpr int TRI_MAX = 128;                                // largest d handled
+constexpr int64_t EIG_STRIDE = STEP0_SCRATCH;  // complex scratch per cluster
+static_assert(STEP0_SCRATCH >= 130 * 130 + 3 * TRI_MAX * TRI_MAX, "step 0 scratch");
+
+// Lower Householder tridiagonalization of the Hermitian d x d matrix A (ld d, both
+// triangles kept current): A = Q T Q^H, Q = H_0 ... H_{d-2}, H_j = I - tau_j v_j v_j^H,
+// v_j = [1; A[j+2:, j]] on rows j+1.., off-diagonal beta_j real.
+__device__ void hetrd_lower(double2* A, int d, double2* tau, double* dg, double* off, double2* w, double* red) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j + 1 < d; ++j) {
+    double part = 0.0;
+    for (int r = j + 2 + tid; r < d; r += blockDim.x) part += cabs2(A[r + j * d]);
+    const double xn2 = block_sum256(part, red);
+    const double2 alpha = A[j + 1 + j * d];
+    double2 t = make_double2(0, 0);
+    double beta = alpha.x;
+    if (xn2 > 0.0 || alpha.y != 0.0) {
+      beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
+      t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      const double2 den = make_double2(alpha.x - beta, alpha.y);
+      const double dd = cabs2(den);
+      const double2 sc = make_double2(den.x / dd, -den.y / dd);
+      for (int r = j + 2 + tid; r < d; r += blockDim.x) A[r + j * d] = cmul(A[r + j * d], sc);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      A[j + 1 + j * d] = make_double2(beta, 0.0);
+      tau[j] = t;
+      off[j] = beta;
+    }
+    __syncthreads();
+    if (t.x != 0.0 || t.y != 0.0) {
+      // p = tau A22 v over rows j+1..d-1
+      for (int r = j + 1 + tid; r < d; r += blockDim.x) {
+        double2 acc = A[r + (j + 1) * d];  // v[j+1] = 1
+        for (int c = j + 2; c < d; ++c) acc = cadd(acc, cmul(A[r + c * d], A[c + j * d]));
+        w[r] = cmul(t, acc);
+      }
+      __syncthreads();
+      // c = |tau|^2 v^H A22 v = conj(tau) (v^H p), real
+      double pr = 0.0;
+      for (int r = j + 1 + tid; r < d; r += blockDim.x) {
+        const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+        pr += cmulc(vr, w[r]).x * t.x + cmulc(vr, w[r]).y * t.y;  // Re(conj(tau) v^H p) term
+      }
+      const double cc = block_sum256(pr, red);
+      for (int r = j + 1 + tid; r < d; r += blockDim.x) {
+        const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+        w[r] = csub(w[r], make_double2(0.5 * cc * vr.x, 0.5 * cc * vr.y));
+      }
+      __syncthreads();
+      const int m = d - j - 1;
+      for (int e = tid; e < m * m; e += blockDim.x) {
+        const int r = j + 1 + e % m, c = j + 1 + e / m;
+        const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+        const double2 vc = (c == j + 1) ? make_double2(1, 0) : A[c + j * d];
+        // A22 -= w v^H + v w^H
+        A[r + c * d] = csub(A[r + c * d], cadd(cmul(w[r], cconj(vc)), cmul(vr, cconj(w[c]))));
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = tid; j < d; j += blockDim.x) dg[j] = A[j + j * d].x;
+  __syncthreads();
+}
+
+// number of eigenvalues of T below sigma (Sturm count of the LDL^T pivots)
+__device__ int sturm_count(const double* dg, const double* off, int d, double sigma, double pivmin) {
+  int cnt = 0;
+  double q = dg[0] - sigma;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < d; ++i) {
+    q = (dg[i] - sigma) - off[i - 1] * off[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// one solve of (T - lam I) y = b in place (tridiagonal LU with partial pivoting);
+// D, DU, DL are work arrays of length d; tiny pivots are replaced by +-pivmin.
+__device__ void tri_solve(const double* dg, const double* off, int d, double lam, double* b, double* D, double* DU,
+                          double* DL, double pivmin) {
+  for (int i = 0; i < d; ++i) {
+    D[i] = dg[i] - lam;
+    DU[i] = (i + 1 < d) ? off[i] : 0.0;
+    DL[i] = (i + 1 < d) ? off[i] : 0.0;
+  }
+  double* DU2 = DL;  // sub-diagonal storage is reused for the second super-diagonal after a swap
+  for (int i = 0; i + 1 < d; ++i) {
+    const double sub = DL[i];
+    if (fabs(D[i]) >= fabs(sub)) {
+      if (fabs(D[i]) < pivmin) D[i] = D[i] >= 0 ? pivmin : -pivmin;
+      const double f = sub / D[i];
+      D[i + 1] -= f * DU[i];
+      b[i + 1] -= f * b[i];
+      DU2[i] = 0.0;
+    } else {
+      const double f = D[i] / sub;
+      D[i] = sub;
+      const double tmp = D[i + 1];
+      D[i + 1] = DU[i] - f * tmp;
+      if (i + 2 < d) {
+        DU2[i] = DU[i + 1];
+        DU[i + 1] = -f * DU[i + 1];
+      } else {
+        DU2[i] = 0.0;
+      }
+      DU[i] = tmp;
+      const double tb = b[i];
+      b[i] = b[i + 1];
+      b[i + 1] = tb - f * b[i + 1];
+    }
+  }
+  if (fabs(D[d - 1]) < pivmin) D[d - 1] = D[d - 1] >= 0 ? pivmin : -pivmin;
+  b[d - 1] /= D[d - 1];
+  if (d > 1) b[d - 2] = (b[d - 2] - DU[d - 2] * b[d - 1]) / D[d - 2];
+  for (int i = d - 3; i >= 0; --i) b[i] = (b[i] - DU[i] * b[i + 1] - DU2[i] * b[i + 2]) / D[i];
+}
+
+// Orthonormal complement of the p orthonormal columns of X (d x p, ld d, overwritten)
+// written to E (d x (d - p), ld d).
+__device__ void householder_complement(double2* X, int d, int p, double2* E, double2* tau, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < d * (d - p); e += blockDim.x) {
+    const int r = e % d, c = e / d;
+    E[e] = make_double2(r == p + c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    double part = 0.0;
+    for (int r = j + 1 + tid; r < d; r += blockDim.x) part += cabs2(X[r + j * d]);
+    const double sigma = block_sum256(part, red);
+    const double2 alpha = X[j + j * d];
+    double2 t = make_double2(0, 0);
+    if (sigma > 0.0 || alpha.y != 0.0) {
+      const double beta = -copysign(sqrt(cabs2(alpha) + sigma), alpha.x);
+      t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      const double2 den = make_double2(alpha.x - beta, alpha.y);
+      const double dd = cabs2(den);
+      const double2 sc = make_double2(den.x / dd, -den.y / dd);
+      __syncthreads();
+      for (int r = j + 1 + tid; r < d; r += blockDim.x) X[r + j * d] = cmul(X[r + j * d], sc);
+      if (tid == 0) X[j + j * d] = make_double2(beta, 0.0);
+    }
+    if (tid == 0) tau[j] = t;
+    __syncthreads();
+    if (t.x != 0.0 || t.y != 0.0) {
+      for (int c = j + 1 + wv; c < p; c += 4) {
+        double2 w = make_double2(0, 0);
+        for (int r = j + lane; r < d; r += 64) {
+          const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
+          w = cadd(w, cmulc(vr, X[r + c * d]));
+        }
+        w.x = wave_sum(w.x);
+        w.y = wave_sum(w.y);
+        const double2 f = cmul(cconj(t), w);
+        for (int r = j + lane; r < d; r += 64) {
+          const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
+          X[r + c * d] = csub(X[r + c * d], cmul(vr, f));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = p - 1; j >= 0; --j) {
+    const double2 t = tau[j];
+    if (t.x == 0.0 && t.y == 0.0) continue;
+    for (int c = wv; c < d - p; c += 4) {
+      double2 w = make_double2(0, 0);
+      for (int r = j + lane; r < d; r += 64) {
+        const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
+        w = cadd(w, cmulc(vr, E[r + c * d]));
+      }
+      w.x = wave_sum(w.x);
+      w.y = wave_sum(w.y);
+      const double2 f = cmul(t, w);
+      for (int r = j + lane; r < d; r += 64) {
+        const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
+        E[r + c * d] = csub(E[r + c * d], cmul(vr, f));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Step 0 eigen-decomposition of G' = B_perp^H H B_perp, rank decision, Q~[:, 0:k] = B.
 __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, double2* scratch) {
   __shared__ double2 sA[JLDS * JLDS];
   __shared__ double2 sU[JLDS * JLDS];
-  __shared__ Rot rot[128];
   __shared__ double lam[256];
-  __shared__ int flag;
   __shared__ double red[4];
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], k = v.k[i], d = n - k;
@@ -702,7 +895,7 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
     if (forced) {
       skip = v.forced[i] - k <= 0;
     } else {
-      double2* M = (d <= JLDS) ? sA : scratch + (int64_t)blockIdx.x * 2 * 130 * 130;
+      double2* M = (d <= JLDS) ? sA : scratch + (int64_t)blockIdx.x * EIG_STRIDE;
       for (int e = tid; e < d * d; e += blockDim.x) {
         const int r = e % d, q = e / d;
         const double2 gv = Gp[e];
@@ -738,22 +931,129 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
         v.margins[2 * i + 1] = -1.0;  // sigma_1 / tau < 1, not evaluated
       }
     } else {
-      double2 *A = sA, *Uw = sU;
-      if (d > JLDS) {
-        A = scratch + (int64_t)blockIdx.x * 2 * 130 * 130;
-        Uw = A + 130 * 130;
+      // working copy of G' (LDS up to 64, else the cluster's scratch)
+      double2* scr = scratch + (int64_t)blockIdx.x * EIG_STRIDE;
+      double2* A = (d <= JLDS) ? sA : scr;
+      double2* X = scr + 130 * 130;                        // d x d: eigenvector block, then complement input
+      double* work = (double*)(scr + 130 * 130 + TRI_MAX * TRI_MAX);  // per-vector tridiagonal work (4 d doubles)
+      double2* wv = sU;                                    // d-vector scratch
+      double2* tauv = sU + TRI_MAX;
+      double* dg = lam;                                    // reuse: diag, then eigenvalues
+      __shared__ double off[TRI_MAX], eig[TRI_MAX];
+      __shared__ double bounds[2];
+      for (int e = tid; e < d * d; e += blockDim.x) A[e] = Gp[e];
+      __syncthreads();
+      hetrd_lower(A, d, tauv, dg, off, wv, red);
+      // Gershgorin interval and pivot floor
+      if (tid == 0) {
+        double lo = 1e300, hi = -1e300, emax = 0.0;
+        for (int r = 0; r < d; ++r) {
+          const double rad = (r > 0 ? fabs(off[r - 1]) : 0.0) + (r + 1 < d ? fabs(off[r]) : 0.0);
+          lo = fmin(lo, dg[r] - rad);
+          hi = fmax(hi, dg[r] + rad);
+          if (r + 1 < d) emax = fmax(emax, off[r] * off[r]);
+        }
+        bounds[0] = lo;
+        bounds[1] = hi;
+        red[3] = fmax(emax, 1.0) * 2.2250738585072014e-308 / 2.2e-16;  // pivmin
       }
-      jacobi_solve(Gp, d, d, A, Uw, lam, Up, d, 0, rot, &flag, red);
-      const double s1 = sqrt(fmax(lam[0], 0.0));
+      __syncthreads();
+      const double pivmin = red[3];
+      const double glo = bounds[0], ghi = bounds[1];
+      // every eigenvalue by bisection (thread j: the j-th largest)
+      for (int j = tid; j < d; j += blockDim.x) {
+        const int a = d - 1 - j;  // ascending index
+        double lo = glo - 2.2e-16 * fabs(glo) - pivmin, hi = ghi + 2.2e-16 * fabs(ghi) + pivmin;
+        for (int it = 0; it < 200; ++it) {
+          const double mid = 0.5 * (lo + hi);
+          if (mid == lo || mid == hi) break;
+          if (sturm_count(dg, off, d, mid, pivmin) >= a + 1)
+            hi = mid;
+          else
+            lo = mid;
+          if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        }
+        eig[j] = 0.5 * (lo + hi);
+      }
+      __syncthreads();
+      const double s1 = sqrt(fmax(eig[0], 0.0));
       const double tau = v.eps_fill * fmax(v.nu[i], s1);
-      if (tau > 0.0) {
+      if (tau > 0.0)
         for (int j = 0; j < d; ++j)
-          if (sqrt(fmax(lam[j], 0.0)) > tau) p = j + 1;
-      }
+          if (sqrt(fmax(eig[j], 0.0)) > tau) p = j + 1;
+      if (forced) p = min(max(v.forced[i] - k, 0), d);
       if (tid == 0 && v.margins) {
-        v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(lam[p - 1], 0.0)) / tau : 1e300;
-        v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(lam[p], 0.0)) / tau : 0.0;
+        v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(eig[p - 1], 0.0)) / tau : 1e300;
+        v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(eig[p], 0.0)) / tau : 0.0;
       }
+      // inverse iteration for the p dominant eigenvectors of T (one thread per vector)
+      const double tnorm = fmax(fabs(glo), fabs(ghi));
+      for (int j = tid; j < p; j += blockDim.x) {
+        double* b = work + (int64_t)j * 4 * TRI_MAX;
+        double *D = b + TRI_MAX, *DU = D + TRI_MAX, *DL = DU + TRI_MAX;
+        for (int r = 0; r < d; ++r) b[r] = 1.0 + 0.37 * (double)((r * (j + 3) + 7 * j) % 11) / 11.0;
+        const double lamj = eig[j] + 4.4e-16 * tnorm * (1 + j % 3);
+        for (int it = 0; it < 3; ++it) {
+          tri_solve(dg, off, d, lamj, b, D, DU, DL, fmax(pivmin, 2.2e-16 * tnorm));
+          double nrm = 0.0;
+          for (int r = 0; r < d; ++r) nrm += b[r] * b[r];
+          nrm = 1.0 / sqrt(nrm);
+          for (int r = 0; r < d; ++r) b[r] *= nrm;
+        }
+        for (int r = 0; r < d; ++r) X[r + (int64_t)j * d] = make_double2(b[r], 0.0);
+      }
+      __syncthreads();
+      // x = H_0 ... H_{d-2} y for the p vectors (wavefront per vector)
+      {
+        const int lane = tid & 63, wf = tid >> 6;
+        for (int j = d - 2; j >= 0; --j) {
+          const double2 t = tauv[j];
+          if (t.x == 0.0 && t.y == 0.0) continue;
+          for (int cidx = wf; cidx < p; cidx += 4) {
+            double2* x = X + (int64_t)cidx * d;
+            double2 sacc = make_double2(0, 0);
+            for (int r = j + 1 + lane; r < d; r += 64) {
+              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+              sacc = cadd(sacc, cmulc(vr, x[r]));
+            }
+            sacc.x = wave_sum(sacc.x);
+            sacc.y = wave_sum(sacc.y);
+            const double2 f = cmul(t, sacc);
+            for (int r = j + 1 + lane; r < d; r += 64) {
+              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+              x[r] = csub(x[r], cmul(vr, f));
+            }
+          }
+          __syncthreads();
+        }
+      }
+      // re-orthonormalise the p vectors (classical Gram-Schmidt, twice)
+      for (int cidx = 0; cidx < p; ++cidx) {
+        double2* x = X + (int64_t)cidx * d;
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = 0; q < cidx; ++q) {
+            const double2* y = X + (int64_t)q * d;
+            double pre = 0.0, pim = 0.0;
+            for (int r = tid; r < d; r += blockDim.x) {
+              const double2 z = cmulc(y[r], x[r]);
+              pre += z.x;
+              pim += z.y;
+            }
+            const double2 dot = make_double2(block_sum256(pre, red), block_sum256(pim, red));
+            for (int r = tid; r < d; r += blockDim.x) x[r] = csub(x[r], cmul(y[r], dot));
+            __syncthreads();
+          }
+        }
+        double pn = 0.0;
+        for (int r = tid; r < d; r += blockDim.x) pn += cabs2(x[r]);
+        const double nrm = 1.0 / sqrt(block_sum256(pn, red));
+        for (int r = tid; r < d; r += blockDim.x) x[r] = make_double2(x[r].x * nrm, x[r].y * nrm);
+        __syncthreads();
+      }
+      // U' = [X  complement(X)]
+      for (int e = tid; e < d * p; e += blockDim.x) Up[e] = X[e];
+      __syncthreads();
+      householder_complement(X, d, p, Up + (int64_t)p * d, tauv, red);
     }
   }
   if (v.forced && v.forced[i] >= 0) p = min(max(v.forced[i] - k, 0), d);

@@ -121,6 +121,7 @@ void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2*
 
 // ---- factorization ----
 constexpr int GRAM_SPLIT = 16;  // partial sums of the Step 0 Gram
+constexpr int64_t STEP0_SCRATCH = 130 * 130 + 3 * 128 * 128;  // complex elements per cluster of a colour
 void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);
 void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st);

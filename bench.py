@@ -46,6 +46,21 @@ def cpu_baseline(budget_s: float = 30.0) -> dict:
                       f"factor + 1 RHS refined to {hist[-1]:.1e} in {dt:.1f} s; construction excluded"}
 
 
+COPY_BYTES = 1 << 30      # one direction of the calibration copy
+
+
+def copy_calibration(torch):
+    """A plain 1 GiB device-to-device copy, 5 times: FETCH_SIZE / WRITE_SIZE of
+    its kernel divided by 1 GiB is the factor that turns the counters of any
+    other kernel into bytes."""
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,11 +68,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     import paper_1703_06155_amd as h2
     from paper_1703_06155_amd import inputs as I

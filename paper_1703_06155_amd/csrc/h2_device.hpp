@@ -232,26 +232,59 @@ __device__ __forceinline__ void load_a(TileSmem<R>& s, const CT* __restrict__ A,
   }
 }
 
-// acc += op(A_tile) * op(B_tile) for one TK slab resident in LDS.
+// How the four wavefronts share a tile of m x n outputs (uniform over the
+// block).  SPLIT_4: each wave owns one 32x32 quadrant.  SPLIT_ROWS (n <= 32)
+// and SPLIT_COLS (m <= 32): two quadrants, two waves per quadrant taking
+// alternate 4-wide k-steps.  SPLIT_1 (m, n <= 32): one quadrant, each wave one
+// k-step of four.  Waves whose own quadrant lies outside the tile are helpers;
+// tile_reduce adds their partial sums into the quadrant owners.
+enum TileSplit { SPLIT_4 = 0, SPLIT_ROWS = 1, SPLIT_COLS = 2, SPLIT_1 = 3 };
+
+__device__ __forceinline__ int tile_split(int m, int n) {
+  if (m > 32 && n > 32) return SPLIT_4;
+  if (m > 32) return SPLIT_ROWS;
+  if (n > 32) return SPLIT_COLS;
+  return SPLIT_1;
+}
+
+// acc += op(A_tile) * op(B_tile) for the first nk (<= TK, uniform over the
+// block) k-columns of one slab resident in LDS; the slab is zero beyond its
+// K range, so only whole 4-wide MFMA steps past nk are skipped.
 template <typename R>
-__device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc) {
+__device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc, int nk = TK, int split = SPLIT_4) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int li = lane & 15, lk = lane >> 4;
+  int qr = wr, qc = wc, kfirst = 0, kstep = 1;
+  if (split == SPLIT_ROWS) {
+    qc = 0;
+    kfirst = wc;
+    kstep = 2;
+  } else if (split == SPLIT_COLS) {
+    qr = 0;
+    kfirst = wr;
+    kstep = 2;
+  } else if (split == SPLIT_1) {
+    qr = qc = 0;
+    kfirst = w;
+    kstep = 4;
+  }
 #pragma unroll
-  for (int kq = 0; kq < TK / 4; ++kq) {
+  for (int q = 0; q < TK / 4; ++q) {
+    const int kq = kfirst + q * kstep;
+    if (kq >= TK / 4 || kq * 4 >= nk) break;
     const int kk = kq * 4 + lk;
     R ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      ar[t] = s.are[kk][wr * 32 + t * 16 + li];
-      ai[t] = s.aim[kk][wr * 32 + t * 16 + li];
+      ar[t] = s.are[kk][qr * 32 + t * 16 + li];
+      ai[t] = s.aim[kk][qr * 32 + t * 16 + li];
       nai[t] = -ai[t];
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      br[u] = s.bre[kk][wc * 32 + u * 16 + li];
-      bi[u] = s.bim[kk][wc * 32 + u * 16 + li];
+      br[u] = s.bre[kk][qc * 32 + u * 16 + li];
+      bi[u] = s.bim[kk][qc * 32 + u * 16 + li];
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -266,12 +299,69 @@ __device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc) 
   }
 }
 
+// Partial sums of helper waves -> quadrant owners, through the slab LDS (all
+// threads call it; the slab contents are dead afterwards).  Helpers end with
+// zero accumulators, so a later contraction into the same tile stays correct.
+template <typename R>
+__device__ __forceinline__ void tile_reduce(TileSmem<R>& s, TileAcc<R>& acc, int split) {
+  if (split == SPLIT_4) return;
+  static_assert(sizeof(TileSmem<R>) >= 2 * 32 * 64 * sizeof(R), "slab LDS too small for the reduction");
+  R* buf = reinterpret_cast<R*>(&s);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = ((t * 2 + u) * 4 + v) * 2;
+          buf[((slot * 32) + q) * 64 + lane] = acc.re[t][u][v];
+          buf[((slot * 32) + q + 1) * 64 + lane] = acc.im[t][u][v];
+        }
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = ((t * 2 + u) * 4 + v) * 2;
+          acc.re[t][u][v] += buf[((slot * 32) + q) * 64 + lane];
+          acc.im[t][u][v] += buf[((slot * 32) + q + 1) * 64 + lane];
+        }
+  };
+  __syncthreads();
+  bool owner;
+  if (split == SPLIT_ROWS) {  // helpers 1 -> 0, 3 -> 2
+    owner = !(w & 1);
+    if (!owner) put(w >> 1);
+    __syncthreads();
+    if (owner) add(w >> 1);
+  } else {  // SPLIT_COLS: helpers 2 -> 0, 3 -> 1; SPLIT_1: then 1 -> 0
+    owner = (split == SPLIT_COLS) ? (w < 2) : (w == 0);
+    if (w >= 2) put(w - 2);
+    __syncthreads();
+    if (w < 2) add(w);
+    if (split == SPLIT_1) {
+      __syncthreads();
+      if (w == 1) put(0);
+      __syncthreads();
+      if (w == 0) add(0);
+    }
+  }
+  if (!owner) acc.zero();
+  __syncthreads();
+}
+
 // acc += op(A)[0:m, 0:K] * op(B)[0:K, 0:n] (m, n <= 64), with the next slab's
 // global loads in flight while the current slab is multiplied.
 template <typename R, typename CT>
 __device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const CT* A, int64_t lda, int opA,
                                           const CT* B, int64_t ldb, int opB, int m, int n, int K) {
   if (K <= 0) return;
+  const int split = tile_split(m, n);
   SlabRegs<CT> r;
   slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, 0);
   for (int k0 = 0; k0 < K; k0 += TK) {
@@ -279,8 +369,9 @@ __device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const
     slab_store<R, CT>(s, r, opA, opB);
     __syncthreads();
     if (k0 + TK < K) slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, k0 + TK);
-    mma_slab<R>(s, acc);
+    mma_slab<R>(s, acc, min(TK, K - k0), split);
   }
+  tile_reduce<R>(s, acc, split);
 }
 
 // Per-thread prefetch of the 16 elements of C that this thread's accumulators cover.

@@ -124,6 +124,7 @@ struct LevelPlan {
   std::vector<int32_t> np_ptr, np_cl, np_srow, np_scol;
   std::vector<int32_t> fp_ptr, fp_cl, fp_srow;
   std::vector<ColourPlan> cols;
+  ColourPlan fin;                 // Schur updates still pending when the level ends
   std::vector<MergeSrc> merge;  // into level l-1 (slots) or the final dense block
   // device copies of the static lists
   DArr<int32_t> d_colour, d_nonempty, d_slot_a, d_slot_b, d_diag_slot, d_np_ptr, d_np_cl, d_np_srow, d_np_scol,
@@ -159,7 +160,7 @@ struct BuildLevel {
 
 // factor data of one level (kept for the sweeps)
 struct FactorLevel {
-  std::vector<int32_t> n, kt;
+  std::vector<int32_t> n, kt, k;  // sizes, factor ranks k~, construction ranks
   int64_t ntot = 0;
   DArr<int32_t> d_n, d_k, d_kt, d_forced, d_np_off, d_prow, d_flags;
   DArr<int64_t> d_slot_off, d_q_off, d_b_off, d_bp_off, d_lu_off, d_cp_off, d_rp_off, d_w_off, d_voff;
@@ -201,6 +202,7 @@ struct h2_ctx {
   h2::DArr<double2> Zf, Zinv;
   std::vector<double> timing;
   std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
+  bool ledger_valid = false;
   // sweep workspace
   std::vector<h2::DArr<double2>> vbuf;
   h2::DArr<double2> vtmp, vtmp2, vtmp3, sw_scratch, sw_part;
@@ -307,29 +309,49 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     P.cols[cx].pj_slot.push_back(s);
     if (cy != cx) P.cols[cy].pj_slot.push_back(s);
   }
+  // Schur updates are deferred: the contribution of an eliminated cluster i to
+  // a block (a, b) stays pending until a or b is processed (its rows/columns
+  // are then needed and change coordinates) or the level ends.  Every block is
+  // therefore written at most three times per level, with all contributions of
+  // an interval summed in one pass.
+  std::vector<std::vector<std::array<int32_t, 3>>> pending(P.nslot);
+  auto flush_into = [&](ColourPlan& C, const std::vector<int32_t>& slots) {
+    C.sc_slot.clear();
+    C.sc_cptr.assign(1, 0);
+    C.sc_i.clear();
+    C.sc_ja.clear();
+    C.sc_jb.clear();
+    for (int s : slots) {
+      auto& pl = pending[s];
+      if (pl.empty()) continue;
+      C.sc_slot.push_back(s);
+      for (const auto& t : pl) {
+        C.sc_i.push_back(t[0]);
+        C.sc_ja.push_back(t[1]);
+        C.sc_jb.push_back(t[2]);
+      }
+      C.sc_cptr.push_back((int32_t)C.sc_i.size());
+      pl.clear();
+      pl.shrink_to_fit();
+    }
+  };
   for (int c = 0; c < P.ncol; ++c) {
     ColourPlan& C = P.cols[c];
-    // Schur targets grouped by slot
-    std::vector<std::array<int32_t, 4>> con;
+    std::vector<int32_t> touched(C.pj_slot.begin(), C.pj_slot.end());
+    std::sort(touched.begin(), touched.end());
+    flush_into(C, touched);
     for (int i : C.cl)
       for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
-        for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y) {
-          const int s = P.slot_of(P.np_cl[x], P.np_cl[y]);
-          con.push_back({s, i, x, y});
-        }
-    std::sort(con.begin(), con.end());
-    C.sc_cptr.push_back(0);
-    for (size_t e = 0; e < con.size(); ++e) {
-      if (e == 0 || con[e][0] != con[e - 1][0]) {
-        if (e) C.sc_cptr.push_back((int32_t)e);
-        C.sc_slot.push_back(con[e][0]);
-      }
-      C.sc_i.push_back(con[e][1]);
-      C.sc_ja.push_back(con[e][2]);
-      C.sc_jb.push_back(con[e][3]);
-    }
-    C.sc_cptr.push_back((int32_t)con.size());
-    if (C.sc_slot.empty()) C.sc_cptr.assign(1, 0);
+        for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
+          pending[P.slot_of(P.np_cl[x], P.np_cl[y])].push_back({i, x, y});
+  }
+  {
+    std::vector<int32_t> all(P.nslot);
+    for (int s2 = 0; s2 < P.nslot; ++s2) all[s2] = s2;
+    flush_into(P.fin, all);
+  }
+  for (int c = 0; c < P.ncol; ++c) {
+    ColourPlan& C = P.cols[c];
     // panels and solve gathers
     std::vector<std::array<int32_t, 3>> sv;
     for (int i : C.cl)
@@ -417,6 +439,11 @@ static void upload_plan(LevelPlan& P, hipStream_t st) {
     C.d_sv_i.upload(C.sv_i, st);
     C.d_sv_ja.upload(C.sv_ja, st);
   }
+  P.fin.d_sc_slot.upload(P.fin.sc_slot, st);
+  P.fin.d_sc_cptr.upload(P.fin.sc_cptr, st);
+  P.fin.d_sc_i.upload(P.fin.sc_i, st);
+  P.fin.d_sc_ja.upload(P.fin.sc_ja, st);
+  P.fin.d_sc_jb.upload(P.fin.sc_jb, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -838,7 +865,6 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->factored = false;
   H->flev.clear();
   H->timing.assign(6, 0.0);
-  H->ledger.assign(10, 0.0);
   H->stats_rows.clear();
   EventPool ev;
   std::vector<std::array<hipEvent_t, 4>> phase_ev;
@@ -1066,8 +1092,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.sv_i = C.d_sv_i.p;
       ct.sv_ja = C.d_sv_ja.p;
       ct.nsv = (int)C.sv_cl.size();
-      ct.colour = c;
+      ct.colour = c - 1;  // the flush sees the blocks as they are before colour c
       ct.tiles = F.tiles;
+      hipEvent_t es = ev.next(st);
+      launch_schur(v, ct, st);
+      check_launch("schur");
+      ct.colour = c;
       hipEvent_t e0 = ev.next(st);
       launch_gram_fill(v, ct, gram_part.p, gram_pstride, st);
       check_launch("gram_fill");
@@ -1090,10 +1120,24 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       launch_panels(v, ct, st);
       check_launch("panels");
       hipEvent_t e2 = ev.next(st);
+      phase_ev.push_back({es, e0, e1, e2});
+    }
+    {
+      // updates still pending at the end of the level
+      ColourTasks ct{};
+      ct.sc_slot = P.fin.d_sc_slot.p;
+      ct.sc_cptr = P.fin.d_sc_cptr.p;
+      ct.sc_i = P.fin.d_sc_i.p;
+      ct.sc_ja = P.fin.d_sc_ja.p;
+      ct.sc_jb = P.fin.d_sc_jb.p;
+      ct.nsc = (int)P.fin.sc_slot.size();
+      ct.colour = P.ncol - 1;
+      ct.tiles = F.tiles;
+      hipEvent_t es = ev.next(st);
       launch_schur(v, ct, st);
-      hipEvent_t e3 = ev.next(st);
       check_launch("schur");
-      phase_ev.push_back({e0, e1, e2, e3});
+      hipEvent_t ee = ev.next(st);
+      phase_ev.push_back({es, ee, ee, ee});
     }
     // one synchronisation per level: ranks k~ and pivot status
     F.kt.assign(nc, 0);
@@ -1104,30 +1148,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     if (flags[0]) fail(H2_ERR_SINGULAR, "zero pivot in the partial LU of a cluster at level " + std::to_string(l));
     for (int i = 0; i < nc; ++i)
       if (!P.nonempty[i]) F.kt[i] = 0;
-    // flop / byte ledger of this level from the actual ranks
-    for (int c = 0; c < P.ncol; ++c) {
-      H->ledger[7] += 1.0;  // one Schur launch per colour
-      for (int i : P.cols[c].cl) {
-        const double n = F.n[i], kt = F.kt[i], r = n - kt, k = kk[i], d = n - k;
-        double M = 0.0, fillcols = 0.0;
-        for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
-          const int a = P.np_cl[x];
-          M += (a == i) ? kt : (P.colour[a] < c ? F.kt[a] : F.n[a]);
-        }
-        for (int x = P.fp_ptr[i]; x < P.fp_ptr[i + 1]; ++x) {
-          const int b = P.fp_cl[x];
-          fillcols += (P.colour[b] < c ? F.kt[b] : F.n[b]);
-        }
-        const double schur = 8.0 * M * M * r;
-        H->ledger[6] += schur;
-        H->ledger[9] += 16.0 * (2.0 * M * M + 2.0 * M * r);  // targets read+written, panels read
-        // Gram, B_perp transforms, projections (rows and columns of every touched block), LU, panels
-        const double gram = 8.0 * n * n * fillcols + 8.0 * (n * n * d + n * d * d + n * d * d);
-        const double proj = 8.0 * n * n * (M - kt + n + fillcols) * 2.0;
-        const double lu = 8.0 / 3.0 * r * r * r + 8.0 * r * r * (M + M);
-        H->ledger[8] += schur + gram + proj + lu;
-      }
-    }
+    F.k = kk;
     // merge into the parent level (or the final dense block)
     hipEvent_t e_m0 = ev.next(st);
     const int npar = S.nclusters(l - 1);
@@ -1229,12 +1250,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->stats_rows.push_back({l0 - 1, (int64_t)S.nclusters(l0 - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
   H->timing[5] = elapsed(e_f0, t_end);
   for (auto& pe : phase_ev) {
-    H->timing[1] += elapsed(pe[0], pe[1]);
-    H->timing[2] += elapsed(pe[1], pe[2]);
-    H->timing[3] += elapsed(pe[2], pe[3]);
+    H->timing[3] += elapsed(pe[0], pe[1]);
+    H->timing[1] += elapsed(pe[1], pe[2]);
+    H->timing[2] += elapsed(pe[2], pe[3]);
   }
   H->timing[0] = elapsed(t_begin, t_end);
-  H->ledger[8] += 8.0 / 3.0 * (double)H->nf * H->nf * H->nf + 8.0 * (double)H->nf * H->nf * H->nf;
+  H->ledger_valid = false;
   H->factored = true;
 }
 
@@ -1815,11 +1836,61 @@ extern "C" h2_status h2_forced_ranks_layout(h2_handle H, int32_t* out, int64_t c
   });
 }
 
+// Algorithmic flop / byte ledger of the last factorization, from its actual
+// ranks (complex multiply-add = 8 flops).  Schur: every eliminated cluster i
+// adds 8 (sum_a m_a)^2 r_i flops over its partners' current row counts m_a;
+// bytes count every flushed block read and written once per flush and every
+// panel slice read once per term.
+static void compute_ledger(h2_ctx* H) {
+  const Structure& S = H->S;
+  const int L = S.L;
+  H->ledger.assign(10, 0.0);
+  for (size_t j = 0; j < H->flev.size(); ++j) {
+    const LevelPlan& P = H->plans[j];
+    const FactorLevel& F = H->flev[j];
+    auto dim_after = [&](int a, int c) -> double { return P.colour[a] <= c ? F.kt[a] : F.n[a]; };
+    auto flush_bytes = [&](const ColourPlan& C, int c) {
+      if (!C.sc_slot.empty()) H->ledger[7] += 1.0;
+      for (int s : C.sc_slot) H->ledger[9] += 32.0 * dim_after(P.slot_a[s], c) * dim_after(P.slot_b[s], c);
+    };
+    for (int c = 0; c < P.ncol; ++c) {
+      flush_bytes(P.cols[c], c - 1);
+      for (int i : P.cols[c].cl) {
+        const double n = F.n[i], kt = F.kt[i], r = n - kt, k = F.k[i], d = n - k;
+        double M = 0.0, fillcols = 0.0, np = 0.0;
+        for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
+          const int a = P.np_cl[x];
+          M += (a == i) ? kt : (P.colour[a] < c ? F.kt[a] : F.n[a]);
+          np += 1.0;
+        }
+        for (int x = P.fp_ptr[i]; x < P.fp_ptr[i + 1]; ++x) {
+          const int b = P.fp_cl[x];
+          fillcols += (P.colour[b] < c ? F.kt[b] : F.n[b]);
+        }
+        const double schur = 8.0 * M * M * r;
+        H->ledger[6] += schur;
+        H->ledger[9] += 16.0 * 2.0 * np * M * r;  // C rows and R columns of every term
+        // Gram, B_perp transforms, projections (rows and columns of every touched block), LU, panels
+        const double gram = 8.0 * n * n * fillcols + 8.0 * (n * n * d + n * d * d + n * d * d);
+        const double proj = 8.0 * n * n * (M - kt + n + fillcols) * 2.0;
+        const double lu = 8.0 / 3.0 * r * r * r + 8.0 * r * r * (M + M);
+        H->ledger[8] += schur + gram + proj + lu;
+      }
+    }
+    flush_bytes(P.fin, P.ncol - 1);
+  }
+  (void)L;
+  const double nf = (double)H->nf;
+  H->ledger[8] += 8.0 / 3.0 * nf * nf * nf + 8.0 * nf * nf * nf;
+  H->ledger_valid = true;
+}
+
 extern "C" h2_status h2_factor_timing(h2_handle H, double* out, int32_t n_out) {
   return guarded([&] {
     if (!H || !out || n_out < 6) fail(H2_ERR_ARG, "invalid argument");
     if (!H->factored) fail(H2_ERR_STATE, "h2_factor_timing before h2_factor");
     for (int i = 0; i < 6; ++i) out[i] = H->timing[i];
+    if (n_out > 6 && !H->ledger_valid) compute_ledger(H);
     for (int i = 6; i < std::min<int32_t>(n_out, 10); ++i) out[i] = H->ledger.size() > (size_t)i ? H->ledger[i] : 0.0;
   });
 }

@@ -1303,7 +1303,36 @@ void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st) {
 }
 
 // Step 3b: Z_ab[0:m_a, 0:m_b] -= sum_i C_i[a] R_i[b] (gather over the colour's clusters)
-__global__ void __launch_bounds__(256) k_schur(LevelView v, ColourTasks c) {
+// One deferred Schur contribution of cluster i to a target block: the rows of
+// its C panel that belong to partner ja and the columns of its R panel that
+// belong to partner jb (eq. 12 with the panels of eqs. 10-11).
+struct SchurTerm {
+  const double2* C;
+  const double2* R;
+  int ldc, ldr, r;
+};
+
+__device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks& c, int e, int tr, int tc,
+                                           SchurTerm& t) {
+  const int i = c.sc_i[e];
+  const int n = v.n[i], kt = v.kt[i];
+  t.r = n - kt;
+  if (t.r <= 0) return false;
+  const int rmax = n - v.k[i];
+  t.ldc = v.prow[i];
+  t.ldr = rmax;
+  t.C = v.CP + v.cp_off[i] + v.np_off[c.sc_ja[e]] + tr * 64;
+  t.R = v.RP + v.rp_off[i] + (int64_t)(v.np_off[c.sc_jb[e]] + tc * 64) * rmax;
+  return true;
+}
+
+// Flush of the Schur updates (eq. 12) pending on a target block: every
+// cluster eliminated since the block was last brought up to date adds
+// -C_a R_b.  The contraction runs over the concatenated ranks of all pending
+// terms as one stream of K slabs, with the next slab (possibly of the next
+// term) in flight while the current one is multiplied.  Block dimensions are
+// those after colour c.colour (kept rows for processed clusters).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur(LevelView v, ColourTasks c) {
   __shared__ TileSmem<double> s;
   const int task = blockIdx.x;
   const int sl = c.sc_slot[task];
@@ -1312,22 +1341,41 @@ __global__ void __launch_bounds__(256) k_schur(LevelView v, ColourTasks c) {
   const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
   if (tr * 64 >= ma || tc * 64 >= mb) return;
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
+  const int e_end = c.sc_cptr[task + 1];
+  int e = c.sc_cptr[task];
+  SchurTerm cur;
+  while (e < e_end && !schur_term(v, c, e, tr, tc, cur)) ++e;
+  if (e >= e_end) return;  // nothing eliminated against this block
   const int na = v.n[a];
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
-  TilePre<double, double2> pre;
-  prefetch_tile<double, double2>(pre, Z, na, m, nn);  // target loads overlap the contraction
   TileAcc<double> acc;
   acc.zero();
-  for (int e = c.sc_cptr[task]; e < c.sc_cptr[task + 1]; ++e) {
-    const int i = c.sc_i[e];
-    const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
-    if (r <= 0) continue;
-    const int pr = v.prow[i];
-    const double2* C = v.CP + v.cp_off[i] + v.np_off[c.sc_ja[e]] + tr * 64;
-    const double2* R = v.RP + v.rp_off[i] + (int64_t)(v.np_off[c.sc_jb[e]] + tc * 64) * rmax;
-    gemm_tile<double, double2>(s, acc, C, pr, OP_N, R, rmax, OP_N, m, nn, r);
+  SlabRegs<double2> regs;
+  int k0 = 0;
+  const int split = tile_split(m, nn);
+  slab_fetch<double2>(regs, cur.C, cur.ldc, OP_N, cur.R, cur.ldr, OP_N, m, nn, cur.r, 0);
+  while (true) {
+    const int nk = min(TK, cur.r - k0);
+    __syncthreads();
+    slab_store<double, double2>(s, regs, OP_N, OP_N);
+    __syncthreads();
+    SchurTerm nxt = cur;
+    int nk0 = k0 + TK;
+    bool more = true;
+    if (nk0 >= cur.r) {
+      nk0 = 0;
+      ++e;
+      while (e < e_end && !schur_term(v, c, e, tr, tc, nxt)) ++e;
+      more = e < e_end;
+    }
+    if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
+    mma_slab<double>(s, acc, nk, split);
+    if (!more) break;
+    cur = nxt;
+    k0 = nk0;
   }
-  store_tile_sub_pre<double, double2>(acc, pre, Z, na, m, nn);
+  tile_reduce<double>(s, acc, split);
+  store_tile<double, double2>(acc, Z, na, m, nn, ST_SUB);
 }
 
 void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st) {

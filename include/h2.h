@@ -94,6 +94,13 @@ h2_status h2_build(const double* points, int64_t n, double k, double h, const do
                    int32_t leaf, double eta, double eps, const h2_options* opt,
                    void* hip_stream, h2_handle* out);
 
+/* Replace the per-cell contrast (host array of n values, each finite and
+ * > 0, caller order).  Only the diagonal of Z = A D^-1 depends on the
+ * contrast, so the nested bases and couplings are kept and the inadmissible
+ * leaf blocks are recomputed; the result equals a fresh h2_build with the new
+ * contrast.  The handle becomes unfactored.  Synchronises the stream. */
+h2_status h2_set_contrast(h2_handle H, const double* contrast, void* hip_stream);
+
 /* Factor Z = L U in the product form of eq. 34 (Alg. 1 with Steps 0-3 per
  * cluster, Algs. 2-4; coupling/transfer updates eqs. 20-23 / 33; final LU of
  * the level-(l0-1) block).  Synchronises once per level to size the next
@@ -112,9 +119,23 @@ h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld
 
 /* lam = M^-H g: the conjugate transposes of the sweeps of eq. 35 applied in
  * reverse order over the same factors (the exact adjoint of the computed
- * solve).  g and lam may alias.  Asynchronous. */
-h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld,
-                           void* hip_stream);
+ * solve).  With tol > 0 the result is refined against A_H2^H = D conj(Z_H2)
+ * exactly as h2_solve refines against A_H2.  g and lam may alias.  Without
+ * refinement the call is asynchronous; info may be NULL. */
+h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld, double tol,
+                           int32_t max_iter, void* hip_stream, h2_solve_info* info);
+
+/* Gradient of a real loss with respect to the per-cell contrast through
+ * x = A^-1 b, given x (nrhs columns), g = dL/d conj(x) in PyTorch's convention
+ * and lam = A^-H g from h2_solve_adjoint: column j of A equals
+ * chi_j (k^2 h^3 G e_j + c e_j) + e_j (c the self term of the diagonal), so
+ * grad_chi[j] = sum over columns of Re(conj(lam_j - g_j) x_j) / chi_j.
+ * x, g, lam: device, column-major with leading dimension ld; grad_chi: device,
+ * n doubles, overwritten, in the caller's point order.  Exact for the exact
+ * inverse; with the factorization's lam the error is of the order of the
+ * solve's residual.  Asynchronous. */
+h2_status h2_contrast_gradient(h2_handle H, const void* x, const void* g, const void* lam, int32_t nrhs,
+                               int64_t ld, double* grad_chi, void* hip_stream);
 
 /* y = A_H2 x (conj_transpose = 0) or y = A_H2^H x (conj_transpose = 1), with
  * the inadmissible leaf blocks and V_t S_ts V_s^T (eq. 2) applied through the

@@ -61,7 +61,10 @@ def lib():
         L.h2_factor.argtypes = [_P, _P]
         L.h2_solve.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P,
                                ctypes.POINTER(SolveInfo)]
-        L.h2_solve_adjoint.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, _P]
+        L.h2_solve_adjoint.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P,
+                                       ctypes.POINTER(SolveInfo)]
+        L.h2_contrast_gradient.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P]
+        L.h2_set_contrast.argtypes = [_P, _DP, _P]
         L.h2_matvec.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P]
         L.h2_destroy.argtypes = [_P]
         L.h2_destroy.restype = None
@@ -73,7 +76,8 @@ def lib():
         L.h2_forced_ranks_layout.argtypes = [_P, _I32P, ctypes.c_int64, _I64P]
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
-                     "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing"):
+                     "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
+                     "h2_set_contrast"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -201,12 +205,41 @@ class H2:
                        "rel_residual_first": si.rel_residual_first}
         return x
 
-    def solve_adjoint(self, g, stream=None):
+    def solve_adjoint(self, g, tol=0.0, max_iter=20, stream=None, info=False):
         buf, nrhs, vec = _as_cols(g, self.n)
         out = _torch().empty_like(buf)
+        si = SolveInfo()
         _check(lib().h2_solve_adjoint(self._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                      nrhs, self.n, _stream_ptr(stream)), "h2_solve_adjoint")
-        return _from_cols(out, vec)
+                                      nrhs, self.n, float(tol), int(max_iter), _stream_ptr(stream), ctypes.byref(si)),
+               "h2_solve_adjoint")
+        lam = _from_cols(out, vec)
+        if info:
+            return lam, {"iterations": si.iterations, "rel_residual": si.rel_residual,
+                         "rel_residual_first": si.rel_residual_first}
+        return lam
+
+    def contrast_gradient(self, x, g, lam, stream=None):
+        """dL/dchi (float64 device tensor, caller order) from x, g = dL/d conj(x) and lam = A^-H g."""
+        xb, nrhs, _ = _as_cols(x, self.n)
+        gb, nrhs_g, _ = _as_cols(g, self.n)
+        lb, nrhs_l, _ = _as_cols(lam, self.n)
+        if not (nrhs == nrhs_g == nrhs_l):
+            raise ValueError("x, g and lam need the same number of columns")
+        out = _torch().empty(self.n, dtype=_torch().float64, device="cuda")
+        _check(lib().h2_contrast_gradient(self._h, ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(gb.data_ptr()),
+                                          ctypes.c_void_p(lb.data_ptr()), nrhs, self.n,
+                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+               "h2_contrast_gradient")
+        return out
+
+    def set_contrast(self, chi, stream=None):
+        """New per-cell contrast (host values); the handle must be factored again."""
+        chi = np.ascontiguousarray(chi, dtype=np.float64).reshape(-1)
+        if chi.size != self.n:
+            raise ValueError(f"expected {self.n} contrast values, got {chi.size}")
+        _check(lib().h2_set_contrast(self._h, _dptr(chi), _stream_ptr(stream)), "h2_set_contrast")
+        self.chi = chi.copy()
+        return self
 
     def matvec(self, x, adjoint=False, stream=None):
         buf, nrhs, vec = _as_cols(x, self.n)

@@ -88,9 +88,10 @@ struct DArr {
     HIPCHK(hipMalloc((void**)&p, cnt * sizeof(T)));
     n = cnt;
   }
-  // blocking: the host vector may be a temporary
+  // blocking: the host vector may be a temporary.  An allocation of the same
+  // size is reused, so device pointers taken from it stay valid.
   void upload(const std::vector<T>& v, hipStream_t st) {
-    alloc(v.size());
+    if (!p || n != std::max<size_t>(v.size(), 1)) alloc(v.size());
     if (!v.empty()) {
       HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -183,7 +184,7 @@ struct h2_ctx {
   std::vector<int64_t> lvl_base;
   bool has_forced = false;
   // device geometry
-  h2::DArr<double> d_pts, d_chi, d_scale_solve, d_scale_mat;
+  h2::DArr<double> d_pts, d_chi, d_scale_solve, d_scale_mat, d_chi_user;
   h2::DArr<int32_t> d_leafid;
   h2::DArr<int64_t> d_perm;
   h2::GeomView geom{};
@@ -193,7 +194,7 @@ struct h2_ctx {
   h2::DArr<double2> near_orig;             // inadmissible leaf blocks (S.near[L] order)
   std::vector<int64_t> near_off;
   h2::DArr<int64_t> d_near_off, d_leaf_start;
-  h2::DArr<int32_t> d_near_ptr, d_near_col, d_leaf_size;
+  h2::DArr<int32_t> d_near_ptr, d_near_col, d_leaf_size, d_near_pr, d_near_pc;
   // factorization
   bool factored = false;
   std::vector<h2::FactorLevel> flev;       // index L - l
@@ -812,13 +813,12 @@ static void construct(h2_ctx* H, hipStream_t st) {
     }
     for (int t = 0; t < S.nclusters(L); ++t) sz[t] = (int32_t)S.size[L][t];
     std::vector<int64_t> cs(S.start[L].begin(), S.start[L].end());
-    DArr<int32_t> d_pr, d_pc;
-    d_pr.upload(pr, st);
-    d_pc.upload(pc, st);
+    H->d_near_pr.upload(pr, st);
+    H->d_near_pc.upload(pc, st);
     H->d_leaf_size.upload(sz, st);
     H->d_leaf_start.upload(cs, st);
     H->d_near_off.upload(H->near_off, st);
-    launch_near_blocks(g, d_pr.p, d_pc.p, H->d_near_off.p, H->d_leaf_start.p, H->d_leaf_size.p,
+    launch_near_blocks(g, H->d_near_pr.p, H->d_near_pc.p, H->d_near_off.p, H->d_leaf_start.p, H->d_leaf_size.p,
                        H->d_leaf_start.p, H->d_leaf_size.p, (int)nl.size(), H->near_orig.p, st);
     check_launch("host.cpp:795");
     std::vector<int32_t> nptr(S.nclusters(L) + 1, 0);
@@ -1549,6 +1549,31 @@ extern "C" h2_status h2_structure(const double* points, int64_t n, double h, int
   });
 }
 
+// Contrast-dependent device arrays: chi in tree and caller order and the
+// scalings D = diag(k^2 h^3 chi) (matvec) and D^-1 (solve).
+static void upload_contrast(h2_ctx* H, const double* contrast, hipStream_t st) {
+  const int64_t n = H->N;
+  const double k2h3 = H->k * H->k * std::pow(H->h, 3.0);
+  std::vector<double> chi(n), ssolve(n), smat(n);
+  for (int64_t t = 0; t < n; ++t) {
+    const int64_t i = H->S.perm[t];
+    chi[t] = contrast[i];
+    smat[t] = k2h3 * contrast[i];
+    ssolve[t] = 1.0 / smat[t];
+  }
+  H->chi_tree = chi;
+  H->d_chi.upload(chi, st);
+  H->d_chi_user.upload(std::vector<double>(contrast, contrast + n), st);
+  H->d_scale_solve.upload(ssolve, st);
+  H->d_scale_mat.upload(smat, st);
+}
+
+static void validate_contrast(const double* contrast, int64_t n) {
+  if (!contrast) fail(H2_ERR_ARG, "contrast is NULL");
+  for (int64_t i = 0; i < n; ++i)
+    if (!(contrast[i] > 0.0) || !std::isfinite(contrast[i])) fail(H2_ERR_ARG, "contrast must be finite and > 0");
+}
+
 extern "C" h2_status h2_build(const double* points, int64_t n, double k, double h, const double* contrast, int32_t leaf,
                               double eta, double eps, const h2_options* opt, void* hip_stream, h2_handle* out) {
   return guarded([&] {
@@ -1584,26 +1609,20 @@ extern "C" h2_status h2_build(const double* points, int64_t n, double k, double 
       }
     }
     // geometry in tree order
-    std::vector<double> pts(3 * n), chi(n), ssolve(n), smat(n);
+    std::vector<double> pts(3 * n);
     const double h3 = std::pow(h, 3.0);
     const double k2h3 = k * k * h3;
     for (int64_t t = 0; t < n; ++t) {
       const int64_t i = S.perm[t];
       for (int d = 0; d < 3; ++d) pts[3 * t + d] = points[3 * i + d];
-      chi[t] = contrast[i];
-      smat[t] = k2h3 * contrast[i];
-      ssolve[t] = 1.0 / smat[t];
     }
-    H->chi_tree = chi;
     std::vector<int32_t> leafid(n);
     for (int t = 0; t < S.nclusters(L); ++t)
       for (int64_t e = 0; e < S.size[L][t]; ++e) leafid[S.start[L][t] + e] = t;
     H->d_pts.upload(pts, st);
-    H->d_chi.upload(chi, st);
+    upload_contrast(H.get(), contrast, st);
     H->d_leafid.upload(leafid, st);
     H->d_perm.upload(S.perm, st);
-    H->d_scale_solve.upload(ssolve, st);
-    H->d_scale_mat.upload(smat, st);
     const double a = std::cbrt(3.0 / (4.0 * M_PI)) * h;
     // c = (1 + jka) e^{-jka} - 1
     const double ka = k * a;
@@ -1646,13 +1665,12 @@ extern "C" h2_status h2_build(const double* points, int64_t n, double k, double 
       }
       for (int t = 0; t < S.nclusters(L); ++t) sz[t] = (int32_t)S.size[L][t];
       std::vector<int64_t> cs(S.start[L].begin(), S.start[L].end());
-      DArr<int32_t> d_pr, d_pc;
-      d_pr.upload(pr, st);
-      d_pc.upload(pc, st);
+      H->d_near_pr.upload(pr, st);
+      H->d_near_pc.upload(pc, st);
       H->d_leaf_size.upload(sz, st);
       H->d_leaf_start.upload(cs, st);
       H->d_near_off.upload(H->near_off, st);
-      launch_near_blocks(g, d_pr.p, d_pc.p, H->d_near_off.p, H->d_leaf_start.p, H->d_leaf_size.p, H->d_leaf_start.p,
+      launch_near_blocks(g, H->d_near_pr.p, H->d_near_pc.p, H->d_near_off.p, H->d_leaf_start.p, H->d_leaf_size.p, H->d_leaf_start.p,
                          H->d_leaf_size.p, (int)nl.size(), H->near_orig.p, st);
       check_launch("host.cpp:1590");
       std::vector<int32_t> nptr(S.nclusters(L) + 1, 0);
@@ -1664,6 +1682,24 @@ extern "C" h2_status h2_build(const double* points, int64_t n, double k, double 
     H->d_norms.alloc(4096);
     HIPCHK(hipStreamSynchronize(st));
     *out = H.release();
+  });
+}
+
+extern "C" h2_status h2_set_contrast(h2_handle H, const double* contrast, void* hip_stream) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    validate_contrast(contrast, H->N);
+    hipStream_t st = (hipStream_t)hip_stream;
+    H->factored = false;
+    upload_contrast(H, contrast, st);
+    H->geom.chi = H->d_chi.p;
+    // only the diagonal of Z depends on chi: recompute the inadmissible leaf blocks
+    const Structure& S = H->S;
+    launch_near_blocks(H->geom, H->d_near_pr.p, H->d_near_pc.p, H->d_near_off.p, H->d_leaf_start.p,
+                       H->d_leaf_size.p, H->d_leaf_start.p, H->d_leaf_size.p, (int)S.near[S.L].size(),
+                       H->near_orig.p, st);
+    check_launch("set_contrast");
+    HIPCHK(hipStreamSynchronize(st));
   });
 }
 
@@ -1686,85 +1722,106 @@ static void validate_vec(h2_handle H, const void* a, const void* b, int32_t nrhs
   if (ld < H->N) fail(H2_ERR_ARG, "ld < n");
 }
 
-extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
-                              int32_t max_iter, void* hip_stream, h2_solve_info* info) {
-  return guarded([&] {
-    validate_vec(H, b, x, nrhs, ld);
-    if (!(tol >= 0) || !std::isfinite(tol)) fail(H2_ERR_ARG, "tol must be finite and >= 0");
-    if (tol > 0 && max_iter < 1) fail(H2_ERR_ARG, "max_iter < 1 with tol > 0");
-    if (!H->factored) fail(H2_ERR_STATE, "h2_solve before a successful h2_factor");
-    hipStream_t st = (hipStream_t)hip_stream;
-    const int64_t N = H->N;
-    ensure_vbuf(H, nrhs);
-    const double2* bb = (const double2*)b;
-    double2* xx = (double2*)x;
-    // copy of b (b and x may alias)
-    DArr<double2> b0;
-    b0.alloc(N * nrhs);
-    HIPCHK(hipMemcpy2DAsync(b0.p, N * sizeof(double2), bb, ld * sizeof(double2), N * sizeof(double2), nrhs,
-                            hipMemcpyDeviceToDevice, st));
-    auto solve_once = [&](const double2* rhs, int64_t ldr, double2* outx, int64_t ldo, int accumulate) {
+// x = M^-1 b (adj = 0) or x = M^-H b (adj = 1), M = L U D, optionally refined
+// against A_H2 (adj = 0) or A_H2^H (adj = 1) until the column-max relative
+// residual is <= tol.  b and x may alias.
+static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
+                          int32_t max_iter, hipStream_t st, h2_solve_info* info) {
+  validate_vec(H, b, x, nrhs, ld);
+  if (!(tol >= 0) || !std::isfinite(tol)) fail(H2_ERR_ARG, "tol must be finite and >= 0");
+  if (tol > 0 && max_iter < 1) fail(H2_ERR_ARG, "max_iter < 1 with tol > 0");
+  if (!H->factored) fail(H2_ERR_STATE, "solve before a successful h2_factor");
+  const int64_t N = H->N;
+  ensure_vbuf(H, nrhs);
+  const double2* bb = (const double2*)b;
+  double2* xx = (double2*)x;
+  // copy of b (b and x may alias)
+  DArr<double2> b0;
+  b0.alloc(N * nrhs);
+  HIPCHK(hipMemcpy2DAsync(b0.p, N * sizeof(double2), bb, ld * sizeof(double2), N * sizeof(double2), nrhs,
+                          hipMemcpyDeviceToDevice, st));
+  auto solve_once = [&](const double2* rhs, int64_t ldr, double2* outx, int64_t ldo, int accumulate) {
+    if (!adj) {
+      // M^-1 = D^-1 Z^-1
       launch_permute_in(rhs, ldr, H->d_perm.p, nullptr, 0, N, nrhs, H->vtmp3.p, N, st);
       sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 0, st);
       launch_permute_out(H->vtmp3.p, N, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, outx, ldo, accumulate, st);
-      check_launch("host.cpp:1643");
-    };
-    solve_once(b0.p, N, xx, ld, 0);
-    if (info) {
-      info->iterations = 0;
-      info->rel_residual = -1.0;
-      info->rel_residual_first = -1.0;
+    } else {
+      // M^-H = Z^-H D^-1
+      launch_permute_in(rhs, ldr, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, H->vtmp3.p, N, st);
+      sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 1, st);
+      launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, outx, ldo, accumulate, st);
     }
-    if (tol <= 0) return;
-    // iterative refinement against A_H2 = Z_H2 D
-    DArr<double2> r, ax, vt;
-    r.alloc(N * nrhs);
-    ax.alloc(N * nrhs);
-    vt.alloc(N * nrhs);
-    std::vector<double> nb(nrhs), nr(nrhs);
-    DArr<double> d_nb;
-    d_nb.alloc(nrhs);
-    launch_col_norms(b0.p, N, N, nrhs, d_nb.p, st);
-    HIPCHK(hipMemcpyAsync(nb.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-    int it = 0;
-    double rel = 0, first = -1;
-    for (;;) {
+    check_launch("solve");
+  };
+  solve_once(b0.p, N, xx, ld, 0);
+  if (info) {
+    info->iterations = 0;
+    info->rel_residual = -1.0;
+    info->rel_residual_first = -1.0;
+  }
+  if (tol <= 0) return;
+  // iterative refinement against A_H2 = Z_H2 D (or its conjugate transpose D conj(Z_H2))
+  DArr<double2> r, ax, vt;
+  r.alloc(N * nrhs);
+  ax.alloc(N * nrhs);
+  vt.alloc(N * nrhs);
+  std::vector<double> nb(nrhs), nr(nrhs);
+  DArr<double> d_nb;
+  d_nb.alloc(nrhs);
+  launch_col_norms(b0.p, N, N, nrhs, d_nb.p, st);
+  HIPCHK(hipMemcpyAsync(nb.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  int it = 0;
+  double rel = 0, first = -1;
+  for (;;) {
+    if (!adj) {
       launch_permute_in(xx, ld, H->d_perm.p, H->d_scale_mat.p, 0, N, nrhs, vt.p, N, st);
       matvec_tree(H, vt.p, H->vtmp3.p, nrhs, st);
       launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, ax.p, N, 0, st);
-      launch_residual(b0.p, N, ax.p, N, r.p, N, N, nrhs, st);
-      launch_col_norms(r.p, N, N, nrhs, d_nb.p, st);
-      check_launch("host.cpp:1670");
-      HIPCHK(hipMemcpyAsync(nr.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      rel = 0;
-      for (int c = 0; c < nrhs; ++c) rel = std::max(rel, nb[c] > 0 ? nr[c] / nb[c] : nr[c]);
-      if (first < 0) first = rel;
-      if (rel <= tol || it >= max_iter) break;
-      solve_once(r.p, N, xx, ld, 1);
-      ++it;
+    } else {
+      launch_permute_in(xx, ld, H->d_perm.p, nullptr, 1, N, nrhs, vt.p, N, st);
+      matvec_tree(H, vt.p, H->vtmp3.p, nrhs, st);
+      launch_permute_out(H->vtmp3.p, N, H->d_perm.p, H->d_scale_mat.p, 1, N, nrhs, ax.p, N, 0, st);
     }
-    if (info) {
-      info->iterations = it;
-      info->rel_residual = rel;
-      info->rel_residual_first = first;
-    }
-    if (rel > tol) fail(H2_ERR_NOCONV, "refinement did not reach tol within max_iter");
-  });
+    launch_residual(b0.p, N, ax.p, N, r.p, N, N, nrhs, st);
+    launch_col_norms(r.p, N, N, nrhs, d_nb.p, st);
+    check_launch("refinement residual");
+    HIPCHK(hipMemcpyAsync(nr.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    rel = 0;
+    for (int c = 0; c < nrhs; ++c) rel = std::max(rel, nb[c] > 0 ? nr[c] / nb[c] : nr[c]);
+    if (first < 0) first = rel;
+    if (rel <= tol || it >= max_iter) break;
+    solve_once(r.p, N, xx, ld, 1);
+    ++it;
+  }
+  if (info) {
+    info->iterations = it;
+    info->rel_residual = rel;
+    info->rel_residual_first = first;
+  }
+  if (rel > tol) fail(H2_ERR_NOCONV, "refinement did not reach tol within max_iter");
 }
 
-extern "C" h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld,
-                                      void* hip_stream) {
+extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
+                              int32_t max_iter, void* hip_stream, h2_solve_info* info) {
+  return guarded([&] { solve_refined(H, 0, b, x, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info); });
+}
+
+extern "C" h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld, double tol,
+                                      int32_t max_iter, void* hip_stream, h2_solve_info* info) {
+  return guarded([&] { solve_refined(H, 1, g, lam, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info); });
+}
+
+extern "C" h2_status h2_contrast_gradient(h2_handle H, const void* x, const void* g, const void* lam, int32_t nrhs,
+                                          int64_t ld, double* grad_chi, void* hip_stream) {
   return guarded([&] {
-    validate_vec(H, g, lam, nrhs, ld);
-    if (!H->factored) fail(H2_ERR_STATE, "h2_solve_adjoint before a successful h2_factor");
+    validate_vec(H, x, g, nrhs, ld);
+    if (!lam || !grad_chi) fail(H2_ERR_ARG, "null pointer");
     hipStream_t st = (hipStream_t)hip_stream;
-    const int64_t N = H->N;
-    ensure_vbuf(H, nrhs);
-    launch_permute_in((const double2*)g, ld, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, H->vtmp3.p, N, st);
-    sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 1, st);
-    launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, (double2*)lam, ld, 0, st);
-    check_launch("host.cpp:1700");
+    launch_contrast_grad((const double2*)x, (const double2*)g, (const double2*)lam, ld, nrhs, H->d_chi_user.p,
+                         H->N, grad_chi, st);
+    check_launch("contrast gradient");
   });
 }
 

@@ -2218,4 +2218,27 @@ void launch_col_norms(const double2* x, int64_t ld, int64_t N, int nrhs, double*
   hipLaunchKernelGGL(k_col_norms, dim3(nrhs), dim3(256), 0, st, x, ld, N, out);
 }
 
+// dL/dchi_j = sum over columns of Re(conj(lam_j - g_j) x_j) / chi_j: column j
+// of A is chi_j (K e_j + c e_j) + e_j, so dA/dchi_j = (A e_j - e_j) / chi_j,
+// and lam^H A = g^H for lam = A^-H g.
+__global__ void k_contrast_grad(const double2* x, const double2* g, const double2* lam, int64_t ld, int nrhs,
+                                const double* chi, int64_t N, double* grad) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N; j += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+      const int64_t e = j + (int64_t)c * ld;
+      const double2 d = csub(lam[e], g[e]);
+      acc += d.x * x[e].x + d.y * x[e].y;
+    }
+    grad[j] = acc / chi[j];
+  }
+}
+
+void launch_contrast_grad(const double2* x, const double2* g, const double2* lam, int64_t ld, int nrhs,
+                          const double* chi, int64_t N, double* grad, hipStream_t st) {
+  if (N <= 0) return;
+  const int blocks = (int)imin64(4096, (N + 255) / 256);
+  hipLaunchKernelGGL(k_contrast_grad, dim3(blocks), dim3(256), 0, st, x, g, lam, ld, nrhs, chi, N, grad);
+}
+
 }  // namespace h2

@@ -198,5 +198,7 @@ void launch_residual(const double2* b, int64_t ldb, const double2* ax, int64_t l
 void launch_axpy_cols(const double2* d, int64_t ldd, double2* x, int64_t ldx, int64_t N, int nrhs,
                       hipStream_t st);
 void launch_col_norms(const double2* x, int64_t ld, int64_t N, int nrhs, double* out, hipStream_t st);
+void launch_contrast_grad(const double2* x, const double2* g, const double2* lam, int64_t ld, int nrhs,
+                          const double* chi, int64_t N, double* grad, hipStream_t st);
 
 }  // namespace h2

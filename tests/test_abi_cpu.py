@@ -74,8 +74,11 @@ def test_calls_on_null_handle_fail_cleanly():
     x = ctypes.c_void_p(1)
     assert L.h2_factor(None, None) == h2.H2_ERR_ARG
     assert L.h2_solve(None, x, x, 1, 1, 0.0, 0, None, None) == h2.H2_ERR_ARG
-    assert L.h2_solve_adjoint(None, x, x, 1, 1, None) == h2.H2_ERR_ARG
+    assert L.h2_solve_adjoint(None, x, x, 1, 1, 0.0, 0, None, None) == h2.H2_ERR_ARG
     assert L.h2_matvec(None, x, x, 1, 1, 0, None) == h2.H2_ERR_ARG
+    assert L.h2_contrast_gradient(None, x, x, x, 1, 1, x, None) == h2.H2_ERR_ARG
+    chi = (ctypes.c_double * 1)(1.0)
+    assert L.h2_set_contrast(None, chi, None) == h2.H2_ERR_ARG
     L.h2_destroy(None)
 
 

@@ -1,0 +1,160 @@
+"""Differentiation through the H^2 solve on the GPU: the autograd wrapper, the
+refined adjoint solve, the contrast gradient and h2_set_contrast.
+
+References: the oracle (same approximate factorization), a dense FP64 adjoint
+computed with NumPy, and central finite differences of the refined solve.
+"""
+import numpy as np
+import pytest
+
+import paper_1703_06155_amd as h2
+from oracle import h2_oracle as O
+from paper_1703_06155_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _obs_kernel(points, k, h, nobs, seed=5):
+    """Free-space kernel from the cells to observation points on a sphere of
+    radius twice the box edge around the box centre."""
+    lo, hi = points.min(0) - h / 2, points.max(0) + h / 2
+    centre = (lo + hi) / 2
+    obs = I.fibonacci_sphere(nobs, centre, 2.0 * float(np.max(hi - lo)))
+    r = np.linalg.norm(obs[:, None, :] - points[None, :, :], axis=2)
+    return np.exp(-1j * k * r) / (4 * np.pi * r)
+
+
+def _scatter_loss_setup(pr, nobs=32):
+    rng = np.random.default_rng(11)
+    Gobs = _obs_kernel(pr.points, pr.k, pr.h, nobs)
+    Et = rng.standard_normal(nobs) + 1j * rng.standard_normal(nobs)
+    return Gobs, Et
+
+
+def _dense_reference(pr, b, Gobs, Et):
+    """Loss, dL/db and dL/dchi of L = sum |Gobs (k^2 h^3 chi x) - Et|^2, x = A^-1 b, dense FP64."""
+    A = O.dense_A(pr.points, pr.k, pr.h, pr.chi)
+    x = np.linalg.solve(A, b)
+    k2h3 = pr.k ** 2 * pr.h ** 3
+    res = Gobs @ (k2h3 * pr.chi * x) - Et
+    L = float(np.sum(np.abs(res) ** 2))
+    w = 2.0 * k2h3 * (Gobs.conj().T @ res)       # dL/d conj(s) with s = k^2 h^3 chi x (times 2)
+    gx = pr.chi * w                              # gradient reaching x
+    lam = np.linalg.solve(A.conj().T, gx)
+    gchi = np.real(np.conj(lam - gx) * x) / pr.chi + np.real(np.conj(w) * x)
+    return L, lam, gchi
+
+
+def _loss_torch(torch, x, chi_t, pr, Gobs_t, Et_t):
+    k2h3 = pr.k ** 2 * pr.h ** 3
+    return (Gobs_t @ (k2h3 * chi_t.to(torch.complex128) * x) - Et_t).abs().pow(2).sum()
+
+
+def test_refined_adjoint_solves_the_conjugate_transpose():
+    torch = _torch()
+    pr = I.make_problem("t", (8, 8, 8), 16, 1e-5)
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps).factor()
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((pr.n, 2)) + 1j * rng.standard_normal((pr.n, 2))
+    lam, info = G.solve_adjoint(torch.from_numpy(g), tol=1e-12, info=True)
+    assert info["rel_residual"] <= 1e-12
+    r = G.matvec(lam, adjoint=True).cpu().numpy() - g
+    assert np.linalg.norm(r, axis=0).max() / np.linalg.norm(g, axis=0).min() < 1e-11
+
+
+def test_contrast_gradient_matches_oracle():
+    """Same approximate factorization (ranks pinned), no refinement: the GPU's
+    x, lam and gradient equal the oracle's."""
+    torch = _torch()
+    pr = I.make_problem("t", (10, 7, 9), 12, 1e-5)
+    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    Fz = O.factor(H)
+    fr = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(Fz))
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr).factor()
+    rng = np.random.default_rng(4)
+    b = pr.rhs[:, 0]
+    gx = rng.standard_normal(pr.n) + 1j * rng.standard_normal(pr.n)
+    x = G.solve(torch.from_numpy(b))
+    lam = G.solve_adjoint(torch.from_numpy(gx))
+    gchi = G.contrast_gradient(x, torch.from_numpy(gx), lam).cpu().numpy()
+    xo = O.solve(Fz, b)
+    lam_o, gchi_o = O.contrast_gradient(Fz, xo, gx)
+    assert _rel(lam.cpu().numpy(), lam_o) < 1e-10
+    assert _rel(gchi, gchi_o) < 1e-10
+
+
+def test_set_contrast_equals_fresh_build():
+    torch = _torch()
+    pr = I.make_problem("t", (8, 8, 8), 16, 1e-4)
+    chi2 = I.contrast(pr.n, seed=99)
+    b = torch.from_numpy(pr.rhs[:, 0].copy())
+    G1 = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps).factor()
+    G1.set_contrast(chi2).factor()
+    G2 = h2.H2(pr.points, pr.k, pr.h, chi2, pr.leaf, pr.eta, pr.eps).factor()
+    x1 = G1.solve(b).cpu().numpy()
+    x2 = G2.solve(b).cpu().numpy()
+    assert _rel(x1, x2) < 1e-14
+    with pytest.raises(h2.H2Error):
+        G1.set_contrast(chi2)
+        G1.solve(b)  # unfactored after set_contrast
+
+
+def test_autograd_matches_dense_fp64_adjoint():
+    """torch.autograd through H2Solve (both solves refined) against the dense
+    FP64 adjoint gradient; the two differ by the H^2 approximation (eps 1e-6)."""
+    torch = _torch()
+    from paper_1703_06155_amd.autograd import h2_solve
+    pr = I.make_problem("t", (8, 8, 8), 16, 1e-6)
+    Gobs, Et = _scatter_loss_setup(pr)
+    b = pr.rhs[:, 0]
+    L_ref, gb_ref, gchi_ref = _dense_reference(pr, b, Gobs, Et)
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps).factor()
+    b_t = torch.from_numpy(b.copy()).cuda().requires_grad_(True)
+    chi_t = torch.from_numpy(pr.chi.copy()).cuda().requires_grad_(True)
+    x = h2_solve(b_t, chi_t, G, 1e-12, 20)
+    L = _loss_torch(torch, x, chi_t, pr, torch.from_numpy(Gobs).cuda(), torch.from_numpy(Et).cuda())
+    L.backward()
+    assert abs(L.item() - L_ref) / L_ref < 1e-5
+    assert _rel(b_t.grad.cpu().numpy(), gb_ref) < 1e-4
+    assert _rel(chi_t.grad.cpu().numpy(), gchi_ref) < 1e-4
+
+
+def test_autograd_matches_central_differences():
+    """Central differences (relative step 1e-6) of the refined H^2 solve, with
+    the contrast changed through h2_set_contrast, on sampled cells."""
+    torch = _torch()
+    from paper_1703_06155_amd.autograd import h2_solve
+    pr = I.make_problem("t", (8, 8, 8), 16, 1e-5)
+    Gobs, Et = _scatter_loss_setup(pr)
+    Gobs_t, Et_t = torch.from_numpy(Gobs).cuda(), torch.from_numpy(Et).cuda()
+    b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps).factor()
+    chi_t = torch.from_numpy(pr.chi.copy()).cuda().requires_grad_(True)
+    x = h2_solve(b, chi_t, G, 1e-13, 30)
+    _loss_torch(torch, x, chi_t, pr, Gobs_t, Et_t).backward()
+    grad = chi_t.grad.cpu().numpy()
+    cells = np.random.default_rng(21).choice(pr.n, 6, replace=False)
+
+    def loss_at(chi):
+        G.set_contrast(chi).factor()
+        xx = G.solve(b, tol=1e-13, max_iter=30)
+        return _loss_torch(torch, xx, torch.from_numpy(chi).cuda(), pr, Gobs_t, Et_t).item()
+
+    scale = np.abs(grad).max()
+    for j in cells:
+        d = 1e-6 * pr.chi[j]
+        cp, cm = pr.chi.copy(), pr.chi.copy()
+        cp[j] += d
+        cm[j] -= d
+        fd = (loss_at(cp) - loss_at(cm)) / (2 * d)
+        assert abs(fd - grad[j]) <= 1e-5 * scale, (j, fd, grad[j])

@@ -101,6 +101,13 @@ h2_status h2_build(const double* points, int64_t n, double k, double h, const do
  * contrast.  The handle becomes unfactored.  Synchronises the stream. */
 h2_status h2_set_contrast(h2_handle H, const double* contrast, void* hip_stream);
 
+/* Select the arithmetic of the next h2_factor: H2_FP64, or H2_MIXED where the
+ * Schur updates (eq. 12) and the zero-introducing projections (eqs. 5/30) run
+ * on complex FP32 matrix cores with FP32 accumulation while Step 0, the
+ * partial LU and the refinement residual stay FP64.  A change of precision
+ * leaves the handle unfactored. */
+h2_status h2_set_precision(h2_handle H, int32_t precision);
+
 /* Factor Z = L U in the product form of eq. 34 (Alg. 1 with Steps 0-3 per
  * cluster, Algs. 2-4; coupling/transfer updates eqs. 20-23 / 33; final LU of
  * the level-(l0-1) block).  Synchronises once per level to size the next

@@ -868,6 +868,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->stats_rows.clear();
   EventPool ev;
   std::vector<std::array<hipEvent_t, 4>> phase_ev;
+  const bool mixed = H->precision == H2_MIXED;
   hipEvent_t t_begin = ev.next(st);
   if (l0 < 0) {
     // no admissible block anywhere: LU of the whole matrix
@@ -1095,7 +1096,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.colour = c - 1;  // the flush sees the blocks as they are before colour c
       ct.tiles = F.tiles;
       hipEvent_t es = ev.next(st);
-      launch_schur(v, ct, st);
+      launch_schur(v, ct, mixed, st);
       check_launch("schur");
       ct.colour = c;
       hipEvent_t e0 = ev.next(st);
@@ -1108,10 +1109,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       check_launch("step0_eig");
       launch_xform(v, ct, 2, st);
       if (F.tiles == 1) {
-        launch_proj_fused(v, ct, st);
+        launch_proj_fused(v, ct, mixed, st);
       } else {
-        launch_proj(v, ct, temp.p, 0, st);
-        launch_proj(v, ct, temp.p, 1, st);
+        launch_proj(v, ct, temp.p, 0, mixed, st);
+        launch_proj(v, ct, temp.p, 1, mixed, st);
       }
       check_launch("projection");
       hipEvent_t e1 = ev.next(st);
@@ -1134,7 +1135,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.colour = P.ncol - 1;
       ct.tiles = F.tiles;
       hipEvent_t es = ev.next(st);
-      launch_schur(v, ct, st);
+      launch_schur(v, ct, mixed, st);
       check_launch("schur");
       hipEvent_t ee = ev.next(st);
       phase_ev.push_back({es, ee, ee, ee});
@@ -1700,6 +1701,15 @@ extern "C" h2_status h2_set_contrast(h2_handle H, const double* contrast, void* 
                        H->near_orig.p, st);
     check_launch("set_contrast");
     HIPCHK(hipStreamSynchronize(st));
+  });
+}
+
+extern "C" h2_status h2_set_precision(h2_handle H, int32_t precision) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    if (precision != H2_FP64 && precision != H2_MIXED) fail(H2_ERR_ARG, "unknown precision");
+    if (precision != H->precision) H->factored = false;
+    H->precision = precision;
   });
 }
 

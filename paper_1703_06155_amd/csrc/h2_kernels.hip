@@ -1066,11 +1066,13 @@ void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch
 }
 
 // Step 2 projections.  side 0: T = (x in colour ? Q~_x^H : I) Z ; side 1: Z = T (y in colour ? conj(Q~_y) : I)
-__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side) {
-  __shared__ TileSmem<double> s;
+template <typename R>
+__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side, int which) {
+  __shared__ TileSmem<R> s;
   const int task = blockIdx.x;
   const int sl = c.pj_slot[task];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
+  if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
   const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
   const int nx = v.n[x], ny = v.n[y];
   // rows of the output: for blocks whose row cluster is eliminated now and that
@@ -1090,12 +1092,12 @@ __global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double
       }
       return;
     }
-    TileAcc<double> acc;
+    TileAcc<R> acc;
     acc.zero();
     const double2* Q = v.Q + v.q_off[x];
-    gemm_tile<double, double2>(s, acc, Q + (int64_t)tr * 64 * nx, nx, OP_C, Z + (int64_t)tc * 64 * nx, nx, OP_N, m,
+    gemm_tile<R, double2>(s, acc, Q + (int64_t)tr * 64 * nx, nx, OP_C, Z + (int64_t)tc * 64 * nx, nx, OP_N, m,
                                nn, nx);
-    store_tile<double, double2>(acc, T + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
+    store_tile<R, double2>(acc, T + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
   } else {
     const int rows = rows_in;
     if (tr * 64 >= rows || tc * 64 >= cols_in) return;
@@ -1107,21 +1109,23 @@ __global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double
       }
       return;
     }
-    TileAcc<double> acc;
+    TileAcc<R> acc;
     acc.zero();
     const double2* Q = v.Q + v.q_off[y];
-    gemm_tile<double, double2>(s, acc, T + tr * 64, nx, OP_N, Q + (int64_t)tc * 64 * ny, ny, OP_R, m, nn, ny);
-    store_tile<double, double2>(acc, Z + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
+    gemm_tile<R, double2>(s, acc, T + tr * 64, nx, OP_N, Q + (int64_t)tc * 64 * ny, ny, OP_R, m, nn, ny);
+    store_tile<R, double2>(acc, Z + tr * 64 + (int64_t)tc * 64 * nx, nx, m, nn, ST_SET);
   }
 }
 
 // Fused Step 2 for levels whose blocks fit one 64x64 tile: the workgroup owns the
 // whole block, so Z <- Q~_x^H Z and Z <- Z conj(Q~_y) are applied in place.  Fill
 // blocks keep only the k~_x kept rows of a row cluster eliminated now.
-__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c) {
-  __shared__ TileSmem<double> s;
+template <typename R>
+__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, int which) {
+  __shared__ TileSmem<R> s;
   const int sl = c.pj_slot[blockIdx.x];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
+  if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
   const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
   const int nx = v.n[x], ny = v.n[y];
   const bool fill = sl >= v.nnear;
@@ -1129,28 +1133,41 @@ __global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c) 
   const int cols_in = cy ? ny : dim_before(v, y, c.colour);
   double2* Z = v.slots + v.slot_off[sl];
   if (cx && rows > 0 && cols_in > 0) {
-    TileAcc<double> acc;
+    TileAcc<R> acc;
     acc.zero();
-    gemm_tile<double, double2>(s, acc, v.Q + v.q_off[x], nx, OP_C, Z, nx, OP_N, rows, cols_in, nx);
-    store_tile<double, double2>(acc, Z, nx, rows, cols_in, ST_SET);
+    gemm_tile<R, double2>(s, acc, v.Q + v.q_off[x], nx, OP_C, Z, nx, OP_N, rows, cols_in, nx);
+    store_tile<R, double2>(acc, Z, nx, rows, cols_in, ST_SET);
     __syncthreads();
   }
   if (cy && rows > 0 && ny > 0) {
-    TileAcc<double> acc;
+    TileAcc<R> acc;
     acc.zero();
-    gemm_tile<double, double2>(s, acc, Z, nx, OP_N, v.Q + v.q_off[y], ny, OP_R, rows, ny, ny);
-    store_tile<double, double2>(acc, Z, nx, rows, ny, ST_SET);
+    gemm_tile<R, double2>(s, acc, Z, nx, OP_N, v.Q + v.q_off[y], ny, OP_R, rows, ny, ny);
+    store_tile<R, double2>(acc, Z, nx, rows, ny, ST_SET);
   }
 }
 
-void launch_proj_fused(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+// The mixed form projects the off-diagonal blocks in complex FP32 and keeps the
+// diagonal blocks (which hold the large self terms of Z) in FP64.
+void launch_proj_fused(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.npj <= 0) return;
-  hipLaunchKernelGGL(k_proj_fused, dim3(c.npj), dim3(256), 0, st, v, c);
+  if (mixed) {
+    hipLaunchKernelGGL(k_proj_fused<float>, dim3(c.npj), dim3(256), 0, st, v, c, (int)PJ_OFFDIAG);
+    hipLaunchKernelGGL(k_proj_fused<double>, dim3(c.npj), dim3(256), 0, st, v, c, (int)PJ_DIAG);
+  } else {
+    hipLaunchKernelGGL(k_proj_fused<double>, dim3(c.npj), dim3(256), 0, st, v, c, (int)PJ_ALL);
+  }
 }
 
-void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, hipStream_t st) {
+void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, bool mixed, hipStream_t st) {
   if (c.npj <= 0) return;
-  hipLaunchKernelGGL(k_proj, dim3(c.npj, c.tiles * c.tiles), dim3(256), 0, st, v, c, temp, side);
+  const dim3 grid(c.npj, c.tiles * c.tiles);
+  if (mixed) {
+    hipLaunchKernelGGL(k_proj<float>, grid, dim3(256), 0, st, v, c, temp, side, (int)PJ_OFFDIAG);
+    hipLaunchKernelGGL(k_proj<double>, grid, dim3(256), 0, st, v, c, temp, side, (int)PJ_DIAG);
+  } else {
+    hipLaunchKernelGGL(k_proj<double>, grid, dim3(256), 0, st, v, c, temp, side, (int)PJ_ALL);
+  }
 }
 
 // Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n]; explicit
@@ -1332,8 +1349,9 @@ __device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks
 // terms as one stream of K slabs, with the next slab (possibly of the next
 // term) in flight while the current one is multiplied.  Block dimensions are
 // those after colour c.colour (kept rows for processed clusters).
+template <typename R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur(LevelView v, ColourTasks c) {
-  __shared__ TileSmem<double> s;
+  __shared__ TileSmem<R> s;
   const int task = blockIdx.x;
   const int sl = c.sc_slot[task];
   const int a = v.slot_a[sl], b = v.slot_b[sl];
@@ -1348,7 +1366,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   if (e >= e_end) return;  // nothing eliminated against this block
   const int na = v.n[a];
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
-  TileAcc<double> acc;
+  TileAcc<R> acc;
   acc.zero();
   SlabRegs<double2> regs;
   int k0 = 0;
@@ -1357,7 +1375,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   while (true) {
     const int nk = min(TK, cur.r - k0);
     __syncthreads();
-    slab_store<double, double2>(s, regs, OP_N, OP_N);
+    slab_store<R, double2>(s, regs, OP_N, OP_N);
     __syncthreads();
     SchurTerm nxt = cur;
     int nk0 = k0 + TK;
@@ -1369,18 +1387,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       more = e < e_end;
     }
     if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
-    mma_slab<double>(s, acc, nk, split);
+    mma_slab<R>(s, acc, nk, split);
     if (!more) break;
     cur = nxt;
     k0 = nk0;
   }
-  tile_reduce<double>(s, acc, split);
-  store_tile<double, double2>(acc, Z, na, m, nn, ST_SUB);
+  tile_reduce<R>(s, acc, split);
+  store_tile<R, double2>(acc, Z, na, m, nn, ST_SUB);
 }
 
-void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st) {
+void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.nsc <= 0) return;
-  hipLaunchKernelGGL(k_schur, dim3(c.nsc, c.tiles * c.tiles), dim3(256), 0, st, v, c);
+  if (mixed)
+    hipLaunchKernelGGL(k_schur<float>, dim3(c.nsc, c.tiles * c.tiles), dim3(256), 0, st, v, c);
+  else
+    hipLaunchKernelGGL(k_schur<double>, dim3(c.nsc, c.tiles * c.tiles), dim3(256), 0, st, v, c);
 }
 
 // ===========================================================================

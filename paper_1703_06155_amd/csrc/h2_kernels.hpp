@@ -10,6 +10,7 @@ namespace h2 {
 // Operand access modes: element (i, k) of op(A) / (k, j) of op(B).
 enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2, OP_R = 3 };  // R = conjugate, not transposed
 // Epilogue of a tile: C = acc, C += acc, C -= acc.
+enum ProjSel { PJ_ALL = 0, PJ_OFFDIAG = 1, PJ_DIAG = 2 };  // which blocks a projection launch handles
 enum StoreMode : int { ST_SET = 0, ST_ADD = 1, ST_SUB = 2 };
 
 // Geometry and kernel constants of the VIE matrix Z = A D^-1 (tree order).
@@ -126,11 +127,11 @@ void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);
 void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st);
 void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
-void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, hipStream_t st);
-void launch_proj_fused(const LevelView& v, const ColourTasks& c, hipStream_t st);
+void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, bool mixed, hipStream_t st);
+void launch_proj_fused(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st);
 void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
 void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st);
-void launch_schur(const LevelView& v, const ColourTasks& c, hipStream_t st);
+void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st);
 
 // Level end: parent blocks from children (copy of kept k~ x k~ parts, padded
 // couplings plus fills, carried fills).

@@ -183,8 +183,8 @@ h2_status h2_forced_ranks_layout(h2_handle H, int32_t* out, int64_t cap, int64_t
  * projection (Steps 0-2), out[2] partial LU and panels, out[3] Schur
  * updates (eq. 12), out[4] level merges, out[5] final LU; n_out >= 6.
  * With n_out >= 10 the algorithmic ledger follows, computed from the actual
- * ranks: out[6] Schur flops (8 (sum m_a)^2 r per eliminated cluster,
- * complex), out[7] number of Schur launches (updates are deferred and flushed
+ * ranks: out[6] Schur flops (4 r ((sum m_a)^2 + sum m_a^2) per eliminated
+ * cluster: the blocks (a, b) with a <= b of its partners, complex), out[7] number of Schur launches (updates are deferred and flushed
  * into a block just before its row or column cluster is processed, and at the
  * end of the level), out[8] flops of the whole factorization, out[9] Schur
  * bytes (each flushed block read and written once per flush, each panel slice

@@ -58,21 +58,23 @@ struct Fail {
 template <typename T>
 struct DArr {
   T* p = nullptr;
-  size_t n = 0;
+  size_t n = 0;    // elements in use
+  size_t cap = 0;  // elements allocated
   DArr() = default;
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
-  DArr(DArr&& o) noexcept : p(o.p), n(o.n) {
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
     o.p = nullptr;
-    o.n = 0;
+    o.n = o.cap = 0;
   }
   DArr& operator=(DArr&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
+      cap = o.cap;
       o.p = nullptr;
-      o.n = 0;
+      o.n = o.cap = 0;
     }
     return *this;
   }
@@ -80,18 +82,34 @@ struct DArr {
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
+  // Keeps the existing allocation when it is large enough: buffers that live
+  // in the handle are reused by the next factorization instead of being
+  // mapped again (mapping tens of GB costs seconds).  Contents are undefined.
   void alloc(size_t cnt) {
-    release();
     if (cnt == 0) cnt = 1;
-    HIPCHK(hipMalloc((void**)&p, cnt * sizeof(T)));
-    n = cnt;
+    if (p && cap >= cnt) {
+      n = cnt;
+      return;
+    }
+    release();
+    const hipError_t e = hipMalloc((void**)&p, cnt * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      size_t fr = 0, tot = 0;
+      (void)hipGetLastError();
+      (void)hipMemGetInfo(&fr, &tot);
+      fail(e == hipErrorOutOfMemory ? H2_ERR_OOM : H2_ERR_DEVICE,
+           "device allocation of " + std::to_string(cnt * sizeof(T) >> 20) + " MiB failed (" +
+               std::to_string(fr >> 20) + " of " + std::to_string(tot >> 20) + " MiB free)");
+    }
+    n = cap = cnt;
   }
-  // blocking: the host vector may be a temporary.  An allocation of the same
-  // size is reused, so device pointers taken from it stay valid.
+  // blocking: the host vector may be a temporary.  An allocation that is large
+  // enough is reused, so device pointers taken from it stay valid.
   void upload(const std::vector<T>& v, hipStream_t st) {
-    if (!p || n != std::max<size_t>(v.size(), 1)) alloc(v.size());
+    alloc(v.size());
     if (!v.empty()) {
       HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -117,6 +135,7 @@ struct MergeSrc {  // rank-independent part of a merge task
   int32_t ci, dj;  // which child of the parent row / column cluster
   int32_t kind, slot, adm;  // kind 0 near / 1 admissible (adm = pair index) / 2 fill
   int32_t ca, cb;
+  int32_t tr;      // the source slot stores (cb, ca): read it transposed
 };
 
 struct LevelPlan {
@@ -124,6 +143,7 @@ struct LevelPlan {
   std::vector<int32_t> colour, nonempty, slot_a, slot_b, diag_slot;
   std::vector<int32_t> np_ptr, np_cl, np_srow, np_scol;
   std::vector<int32_t> fp_ptr, fp_cl, fp_srow;
+  std::vector<int32_t> near_src;  // near slot -> index in S.near[l]
   std::vector<ColourPlan> cols;
   ColourPlan fin;                 // Schur updates still pending when the level ends
   std::vector<MergeSrc> merge;  // into level l-1 (slots) or the final dense block
@@ -132,6 +152,14 @@ struct LevelPlan {
       d_fp_ptr, d_fp_cl, d_fp_srow;
   // row-wise slot lookup: for cluster a, (b, slot) sorted by b
   std::vector<int32_t> rl_ptr, rl_b, rl_slot;
+  // Code of block (a, b): the slot index when stored as (a, b) (a <= b), or
+  // ~slot when it is the transpose of the stored block (b, a).
+  // INT32_MIN when the pair has no slot.
+  int slot_code(int a, int b) const {
+    const int s = (a <= b) ? slot_of(a, b) : slot_of(b, a);
+    if (s < 0) return INT32_MIN;
+    return (a <= b) ? s : ~s;
+  }
   int slot_of(int a, int b) const {
     auto beg = rl_b.begin() + rl_ptr[a], end = rl_b.begin() + rl_ptr[a + 1];
     auto it = std::lower_bound(beg, end, b);
@@ -198,6 +226,9 @@ struct h2_ctx {
   // factorization
   bool factored = false;
   std::vector<h2::FactorLevel> flev;       // index L - l
+  h2::DArr<double2> slot_buf[2];           // block arenas of even / odd levels (index L - l)
+  h2::DArr<double2> ws_bp, ws_w, ws_temp, ws_lu, ws_eig, ws_gram;  // per-level work space
+  h2::DArr<h2::MergeTask> ws_merge;
   int64_t nf = 0;
   std::vector<int32_t> final_off;          // per cluster of level l0-1
   h2::DArr<double2> Zf, Zinv;
@@ -232,29 +263,41 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     std::vector<int32_t> fillp(P.np_ptr.begin(), P.np_ptr.end() - 1);
     for (const Pair& p : S.near[l]) P.np_cl[fillp[p.first]++] = p.second;
   }
-  // near slots, in S.near order
-  P.nnear = (int)S.near[l].size();
+  // Blocks are stored once per unordered pair {a, b} (a <= b): every state of
+  // the factorization is complex symmetric (Z is, the projections act as a
+  // congruence with Q~^H, and Schur complements of symmetric matrices stay
+  // symmetric), so block (b, a) is the transpose of block (a, b).
+  // Near slots: the pairs of S.near with a <= b, in S.near order.
+  P.near_src.clear();
+  std::vector<int64_t> nearkeys;
+  for (size_t e = 0; e < S.near[l].size(); ++e) {
+    const Pair& p = S.near[l][e];
+    if (p.first > p.second) continue;
+    P.near_src.push_back((int32_t)e);
+    nearkeys.push_back((int64_t)p.first * nc + p.second);
+  }
+  P.nnear = (int)P.near_src.size();
   std::vector<int64_t> keys;
   keys.reserve(S.near[l].size() * 4);
   for (int i = 0; i < nc; ++i) {
     for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
-      for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y) keys.push_back((int64_t)P.np_cl[x] * nc + P.np_cl[y]);
+      for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
+        if (P.np_cl[x] <= P.np_cl[y]) keys.push_back((int64_t)P.np_cl[x] * nc + P.np_cl[y]);
   }
   std::sort(keys.begin(), keys.end());
   keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
   // remove near pairs from keys -> fill pairs
-  std::vector<int64_t> nearkeys(S.near[l].size());
-  for (size_t e = 0; e < S.near[l].size(); ++e)
-    nearkeys[e] = (int64_t)S.near[l][e].first * nc + S.near[l][e].second;
+  std::vector<int64_t> nearsorted(nearkeys);
+  std::sort(nearsorted.begin(), nearsorted.end());
   std::vector<int64_t> fillkeys;
-  std::set_difference(keys.begin(), keys.end(), nearkeys.begin(), nearkeys.end(), std::back_inserter(fillkeys));
-  // also every parent of a fill slot of the level below is a fill slot here (kept for safety)
+  std::set_difference(keys.begin(), keys.end(), nearsorted.begin(), nearsorted.end(),
+                      std::back_inserter(fillkeys));
   P.nslot = P.nnear + (int)fillkeys.size();
   P.slot_a.resize(P.nslot);
   P.slot_b.resize(P.nslot);
   for (int e = 0; e < P.nnear; ++e) {
-    P.slot_a[e] = S.near[l][e].first;
-    P.slot_b[e] = S.near[l][e].second;
+    P.slot_a[e] = (int32_t)(nearkeys[e] / nc);
+    P.slot_b[e] = (int32_t)(nearkeys[e] % nc);
   }
   for (size_t e = 0; e < fillkeys.size(); ++e) {
     P.slot_a[P.nnear + e] = (int32_t)(fillkeys[e] / nc);
@@ -282,22 +325,29 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
   for (int i = 0; i < nc; ++i)
     for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
       const int a = P.np_cl[x];
-      P.np_srow[x] = P.slot_of(i, a);
-      P.np_scol[x] = P.slot_of(a, i);
+      P.np_srow[x] = P.slot_code(i, a);
+      P.np_scol[x] = P.slot_code(a, i);
       if (a == i) P.diag_slot[i] = P.np_srow[x];
     }
-  // fill partner lists (row i, non-near b)
+  // fill partner lists: row i, non-near b, in either stored orientation
   P.fp_ptr.assign(nc + 1, 0);
-  for (int s = P.nnear; s < P.nslot; ++s) P.fp_ptr[P.slot_a[s] + 1]++;
+  for (int s = P.nnear; s < P.nslot; ++s) {
+    P.fp_ptr[P.slot_a[s] + 1]++;
+    P.fp_ptr[P.slot_b[s] + 1]++;
+  }
   for (int t = 0; t < nc; ++t) P.fp_ptr[t + 1] += P.fp_ptr[t];
-  P.fp_cl.resize(P.nslot - P.nnear);
-  P.fp_srow.resize(P.nslot - P.nnear);
+  P.fp_cl.resize(P.fp_ptr[nc]);
+  P.fp_srow.resize(P.fp_ptr[nc]);
   {
     std::vector<int32_t> fillp(P.fp_ptr.begin(), P.fp_ptr.end() - 1);
     for (int s = P.nnear; s < P.nslot; ++s) {
-      const int e = fillp[P.slot_a[s]]++;
-      P.fp_cl[e] = P.slot_b[s];
-      P.fp_srow[e] = s;
+      const int a = P.slot_a[s], b = P.slot_b[s];
+      int e = fillp[a]++;
+      P.fp_cl[e] = b;
+      P.fp_srow[e] = s;  // block (a, b) as stored
+      e = fillp[b]++;
+      P.fp_cl[e] = a;
+      P.fp_srow[e] = ~s;  // block (b, a): the stored block transposed
     }
   }
   // colours
@@ -344,7 +394,7 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     for (int i : C.cl)
       for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
         for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
-          pending[P.slot_of(P.np_cl[x], P.np_cl[y])].push_back({i, x, y});
+          if (P.np_cl[x] <= P.np_cl[y]) pending[P.slot_of(P.np_cl[x], P.np_cl[y])].push_back({i, x, y});
   }
   {
     std::vector<int32_t> all(P.nslot);
@@ -376,38 +426,45 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
   }
 }
 
-// merge plan from level l (plan P) into level l-1 (plan Pp, or the final block when l == l0)
+// merge plan from level l (plan P) into level l-1 (plan Pp, or the final block when l == l0).
+// Ordered child pairs (a, b) are placed at (a & 1, b & 1) of the parent block
+// (a / 2, b / 2).  Parent levels store pairs with a / 2 <= b / 2 (full blocks on
+// the diagonal), so ordered pairs below the parent diagonal are skipped; the
+// final dense block takes every ordered pair.
 static void build_merge(h2_ctx* H, LevelPlan& P, const LevelPlan* Pp) {
   const Structure& S = H->S;
   const int l = P.l;
   const int npar = S.nclusters(l - 1);
   P.merge.clear();
   auto parent_pos = [&](int a, int b) -> int {
-    if (Pp) return Pp->slot_of(a / 2, b / 2);
+    if (Pp) return (a / 2 <= b / 2) ? Pp->slot_of(a / 2, b / 2) : -2;  // -2: below the parent diagonal
     return (a / 2) * npar + (b / 2);  // final dense block: pair index
   };
   std::vector<char> is_adm_fill(P.nslot, 0);
   for (size_t e = 0; e < S.adm[l].size(); ++e) {
     const Pair& p = S.adm[l][e];
-    const int fs = P.slot_of(p.first, p.second);
+    const int code = P.slot_code(p.first, p.second);
+    const int fs = code == INT32_MIN ? -1 : (code < 0 ? ~code : code);
     if (fs >= 0) is_adm_fill[fs] = 1;
     const int pp = parent_pos(p.first, p.second);
+    if (pp == -2) continue;
     if (pp < 0) fail(H2_ERR_INTERNAL, "admissible pair without an inadmissible parent");
-    P.merge.push_back({pp, p.first & 1, p.second & 1, 1, fs, (int32_t)e, p.first, p.second});
+    P.merge.push_back({pp, p.first & 1, p.second & 1, 1, fs, (int32_t)e, p.first, p.second, code < 0 ? 1 : 0});
   }
   for (int s = 0; s < P.nslot; ++s) {
-    const int a = P.slot_a[s], b = P.slot_b[s];
-    if (s < P.nnear) {
+    if (s >= P.nnear && is_adm_fill[s]) continue;
+    const int kind = s < P.nnear ? 0 : 2;
+    for (int o = 0; o < 2; ++o) {
+      const int a = o ? P.slot_b[s] : P.slot_a[s], b = o ? P.slot_a[s] : P.slot_b[s];
+      if (o && a == b) continue;
       const int pp = parent_pos(a, b);
-      if (pp < 0) fail(H2_ERR_INTERNAL, "inadmissible pair without an inadmissible parent");
-      P.merge.push_back({pp, a & 1, b & 1, 0, s, -1, a, b});
-    } else if (!is_adm_fill[s]) {
-      const int pp = parent_pos(a, b);
+      if (pp == -2) continue;
       if (pp < 0) {
+        if (kind == 0) fail(H2_ERR_INTERNAL, "inadmissible pair without an inadmissible parent");
         if (!Pp) fail(H2_ERR_INTERNAL, "fill-in outside the final block");
         fail(H2_ERR_INTERNAL, "carried fill-in without a parent slot");
       }
-      P.merge.push_back({pp, a & 1, b & 1, 2, s, -1, a, b});
+      P.merge.push_back({pp, a & 1, b & 1, kind, s, -1, a, b, o});
     }
   }
 }
@@ -859,11 +916,36 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
 
 static void dense_lu_inverse(h2_ctx* H, hipStream_t st);
 
+static void release_factor_buffers(h2_ctx* H) {
+  H->flev.clear();
+  H->slot_buf[0].release();
+  H->slot_buf[1].release();
+  H->ws_bp.release();
+  H->ws_w.release();
+  H->ws_temp.release();
+  H->ws_lu.release();
+  H->ws_eig.release();
+  H->ws_gram.release();
+  H->ws_merge.release();
+  H->Zf.release();
+  H->Zinv.release();
+  H->vbuf.clear();
+  H->vbuf_nrhs = 0;
+}
+
 static void factor_impl(h2_ctx* H, hipStream_t st) {
   const Structure& S = H->S;
   const int L = S.L, l0 = S.l0;
   H->factored = false;
-  H->flev.clear();
+  // buffers of the previous factorization are reused; nothing of it may still run
+  HIPCHK(hipStreamSynchronize(st));
+  {
+    // when device memory is short, start from nothing rather than from the
+    // previous factorization's buffers (its factors would sit beside the new arenas)
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot) release_factor_buffers(H);
+  }
+  H->vbuf_nrhs = 0;  // level sizes may change with the ranks: resize the sweep buffers
   H->timing.assign(6, 0.0);
   H->stats_rows.clear();
   EventPool ev;
@@ -893,8 +975,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   }
   const int nlev = L - l0 + 1;
   H->flev.resize(nlev);
-  DArr<double2> slots;  // current level's block arena
-  DArr<double2> parent_slots;
+  // block arenas of consecutive levels alternate between two handle-owned buffers
   std::vector<int32_t> n_cur(S.nclusters(L));
   for (int t = 0; t < S.nclusters(L); ++t) n_cur[t] = (int32_t)S.size[L][t];
   for (int l = L; l >= l0; --l) {
@@ -907,12 +988,15 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     std::vector<int32_t> kk(Bd.k.begin(), Bd.k.end());
     for (int t = 0; t < nc; ++t)
       if (!P.nonempty[t]) kk[t] = 0;
-    int nmax = 0;
+    int nmax = 0, dmax = 1;
     for (int t = 0; t < nc; ++t) {
       nmax = std::max(nmax, F.n[t]);
       if (F.n[t] < kk[t]) fail(H2_ERR_INTERNAL, "basis wider than its cluster");
-      if (F.n[t] - kk[t] > 128) fail(H2_ERR_INTERNAL, "cluster complement dimension above 128 (kernel limit)");
-      if (kk[t] > 128) fail(H2_ERR_INTERNAL, "cluster basis wider than 128 (kernel limit)");
+      if (F.n[t] - kk[t] > STEP0_DMAX || kk[t] > STEP0_DMAX)
+        fail(H2_ERR_INTERNAL, "level " + std::to_string(l) + " cluster " + std::to_string(t) + ": n = " +
+                                  std::to_string(F.n[t]) + ", k = " + std::to_string(kk[t]) +
+                                  " beyond the kernel limit of 512");
+      dmax = std::max(dmax, F.n[t] - kk[t]);
     }
     if (nmax > 512) fail(H2_ERR_INTERNAL, "cluster dimension above 512 (kernel limit)");
     F.tiles = std::max(1, (nmax + 63) / 64);
@@ -984,28 +1068,47 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     F.LU.alloc(lu_off[nc]);
     F.CP.alloc(cp_off[nc]);
     F.RP.alloc(cp_off[nc]);
-    DArr<double2> Bp, W, temp, lu_scr, eig_scr, gram_part;
+    DArr<double2>& slots = H->slot_buf[j & 1];
+    DArr<double2>& parent_slots = H->slot_buf[(j + 1) & 1];
+    DArr<double2>& Bp = H->ws_bp;
+    DArr<double2>& W = H->ws_w;
+    DArr<double2>& temp = H->ws_temp;
+    DArr<double2>& lu_scr = H->ws_lu;
+    DArr<double2>& eig_scr = H->ws_eig;
+    DArr<double2>& gram_part = H->ws_gram;
     Bp.alloc(bp_off[nc]);
     W.alloc(w_off[nc]);
-    temp.alloc(temp_max);
+    if (F.tiles > 1) temp.alloc(temp_max);  // the one-tile levels project in place
     int maxcl = 1;
     for (ColourPlan& C : P.cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
-    lu_scr.alloc((size_t)maxcl * 256 * 256 * (nmax > 64 ? 1 : 0) + 1);
+    lu_scr.alloc((size_t)maxcl * dmax * dmax * (dmax > 64 ? 1 : 0) + 1);
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
-    eig_scr.alloc((size_t)maxcl * STEP0_SCRATCH);
+    eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);
     // blocks of this level
     if (l == L) {
       slots.alloc(slot_off[P.nslot]);
-      launch_zero(slots.p, slot_off[P.nslot], st);
-      // inadmissible leaf blocks first (same order as S.near[L] and same sizes)
-      HIPCHK(hipMemcpyAsync(slots.p, H->near_orig.p, H->near_off.back() * sizeof(double2), hipMemcpyDeviceToDevice,
-                            st));
+      launch_zero(slots.p + slot_off[P.nnear], slot_off[P.nslot] - slot_off[P.nnear], st);  // fill blocks
+      // inadmissible leaf blocks (a <= b) from the construction's near blocks
+      {
+        std::vector<int64_t> so(P.nnear), dofs(P.nnear), len(P.nnear);
+        for (int e = 0; e < P.nnear; ++e) {
+          so[e] = H->near_off[P.near_src[e]];
+          dofs[e] = slot_off[e];
+          len[e] = slot_off[e + 1] - slot_off[e];
+        }
+        DArr<int64_t> d_so, d_do, d_len;
+        d_so.upload(so, st);
+        d_do.upload(dofs, st);
+        d_len.upload(len, st);
+        launch_copy_blocks(H->near_orig.p, d_so.p, slots.p, d_do.p, d_len.p, P.nnear, st);
+        check_launch("near block copy");
+        HIPCHK(hipStreamSynchronize(st));
+      }
       F.B.alloc(b_off[nc]);
       if (b_off[nc] > 0)
         HIPCHK(hipMemcpyAsync(F.B.p, Bd.basis.p, b_off[nc] * sizeof(double2), hipMemcpyDeviceToDevice, st));
     } else {
-      slots = std::move(parent_slots);
       // parent bases: transfer matrices padded with zero rows (eq. 23)
       const FactorLevel& Fc = H->flev[j - 1];
       const BuildLevel& Bc = H->build[j - 1];
@@ -1105,7 +1208,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       launch_xform(v, ct, 0, st);
       launch_xform(v, ct, 1, st);
       check_launch("xform");
-      launch_step0_eig(v, ct, eig_scr.p, st);
+      launch_step0_eig(v, ct, eig_scr.p, dmax, st);
       check_launch("step0_eig");
       launch_xform(v, ct, 2, st);
       if (F.tiles == 1) {
@@ -1116,7 +1219,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       }
       check_launch("projection");
       hipEvent_t e1 = ev.next(st);
-      launch_lu(v, ct, lu_scr.p, st);
+      launch_lu(v, ct, lu_scr.p, dmax, st);
       check_launch("lu");
       launch_panels(v, ct, st);
       check_launch("panels");
@@ -1182,6 +1285,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         t.soff = m.adm >= 0 ? Bd.soff[m.adm] : 0;
         t.ska = m.adm >= 0 ? Bd.k[m.ca] : 0;
         t.skb = m.adm >= 0 ? Bd.k[m.cb] : 0;
+        t.tr = m.tr;
       }
     } else {
       H->final_off.assign(npar + 1, 0);
@@ -1203,9 +1307,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         t.soff = m.adm >= 0 ? Bd.soff[m.adm] : 0;
         t.ska = m.adm >= 0 ? Bd.k[m.ca] : 0;
         t.skb = m.adm >= 0 ? Bd.k[m.cb] : 0;
+        t.tr = m.tr;
       }
     }
-    DArr<MergeTask> d_mt;
+    DArr<MergeTask>& d_mt = H->ws_merge;
     d_mt.alloc(mt.size());
     if (!mt.empty())
       HIPCHK(hipMemcpyAsync(d_mt.p, mt.data(), mt.size() * sizeof(MergeTask), hipMemcpyHostToDevice, st));
@@ -1242,7 +1347,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       H->stats_rows.push_back({l, ncl, sn, mn, sk, mk, skt, mkt, ncl ? nkt : 0, el});
     }
     n_cur = n_par;
-    slots.release();
+    // keep this level's block arena for the next factorization unless memory is
+    // short (the level two steps up reuses it; keeping it costs its full size)
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot) slots.release();
+    }
   }
   hipEvent_t e_f0 = ev.next(st);
   dense_lu_inverse(H, st);
@@ -1924,22 +2034,25 @@ static void compute_ledger(h2_ctx* H) {
       flush_bytes(P.cols[c], c - 1);
       for (int i : P.cols[c].cl) {
         const double n = F.n[i], kt = F.kt[i], r = n - kt, k = F.k[i], d = n - k;
-        double M = 0.0, fillcols = 0.0, np = 0.0;
+        double M = 0.0, M2 = 0.0, fillcols = 0.0, np = 0.0;
         for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x) {
           const int a = P.np_cl[x];
-          M += (a == i) ? kt : (P.colour[a] < c ? F.kt[a] : F.n[a]);
+          const double ma = (a == i) ? kt : (P.colour[a] < c ? F.kt[a] : F.n[a]);
+          M += ma;
+          M2 += ma * ma;
           np += 1.0;
         }
         for (int x = P.fp_ptr[i]; x < P.fp_ptr[i + 1]; ++x) {
           const int b = P.fp_cl[x];
           fillcols += (P.colour[b] < c ? F.kt[b] : F.n[b]);
         }
-        const double schur = 8.0 * M * M * r;
+        // targets (a, b) with a <= b only: the other half is their transpose
+        const double schur = 8.0 * r * 0.5 * (M * M + M2);
         H->ledger[6] += schur;
-        H->ledger[9] += 16.0 * 2.0 * np * M * r;  // C rows and R columns of every term
-        // Gram, B_perp transforms, projections (rows and columns of every touched block), LU, panels
+        H->ledger[9] += 16.0 * (np + 1.0) * M * r;  // C rows and R columns of every term
+        // Gram, B_perp transforms, projections (one side of every stored block of row i), LU, panels
         const double gram = 8.0 * n * n * fillcols + 8.0 * (n * n * d + n * d * d + n * d * d);
-        const double proj = 8.0 * n * n * (M - kt + n + fillcols) * 2.0;
+        const double proj = 8.0 * n * n * (M - kt + n + fillcols);
         const double lu = 8.0 / 3.0 * r * r * r + 8.0 * r * r * (M + M);
         H->ledger[8] += schur + gram + proj + lu;
       }

@@ -507,7 +507,7 @@ __device__ __forceinline__ int dim_after(const LevelView& v, int a, int c) {
 // B_perp: orthonormal complement of the basis B (n x k) through Householder QR.
 __global__ void __launch_bounds__(256) k_householder_perp(LevelView v) {
   __shared__ double2 sA[64 * 64];
-  __shared__ double2 tau[128];
+  __shared__ double2 tau[STEP0_DMAX];
   __shared__ double red[4];
   const int i = blockIdx.x;
   const int n = v.n[i], k = v.k[i], d = n - k;
@@ -604,9 +604,17 @@ __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, d
   acc.zero();
   for (int j = v.fp_ptr[i] + sp; j < v.fp_ptr[i + 1]; j += GRAM_SPLIT) {
     const int b = v.fp_cl[j];
-    const double2* F = v.slots + v.slot_off[v.fp_srow[j]];
+    const int code = v.fp_srow[j];
     const int mb = dim_before(v, b, c.colour);
-    gemm_tile<double, double2>(s, acc, F + tr * 64, n, OP_N, F + tc * 64, n, OP_C, m, nn, mb);
+    if (code >= 0) {  // F_ib stored as (i, b): n x m_b, ld n
+      const double2* F = v.slots + v.slot_off[code];
+      gemm_tile<double, double2>(s, acc, F + tr * 64, n, OP_N, F + tc * 64, n, OP_C, m, nn, mb);
+    } else {  // stored as (b, i): F_ib = S^T with S m_b x n, ld n_b
+      const double2* Sb = v.slots + v.slot_off[~code];
+      const int nb = v.n[b];
+      gemm_tile<double, double2>(s, acc, Sb + (int64_t)tr * 64 * nb, nb, OP_T, Sb + (int64_t)tc * 64 * nb, nb, OP_R,
+                                 m, nn, mb);
+    }
   }
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
   double2* P = part + (int64_t)sp * pstride + (int64_t)blockIdx.x * cstride;
@@ -681,9 +689,9 @@ void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream
 // re-orthonormalised, and an orthonormal complement by Householder QR.
 // O(d) dependent steps instead of the O(d * sweeps) rounds of cyclic Jacobi.
 // ---------------------------------------------------------------------------
-constexpr int TRI_MAX = 128;                                // largest d handled
-constexpr int64_t EIG_STRIDE = STEP0_SCRATCH;  // complex scratch per cluster
-static_assert(STEP0_SCRATCH >= 130 * 130 + 3 * TRI_MAX * TRI_MAX, "step 0 scratch");
+// Scratch per cluster (dm = the level's largest d): G' copy (dm x dm), eigenvector
+// block (dm x dm), tridiagonal work (4 dm doubles per vector): 4 dm^2 complex.
+static_assert(STEP0_DMAX + STEP0_DMAX <= JLDS * JLDS, "d-vectors and reflector scalars share the LDS block");
 
 // Lower Householder tridiagonalization of the Hermitian d x d matrix A (ld d, both
 // triangles kept current): A = Q T Q^H, Q = H_0 ... H_{d-2}, H_j = I - tau_j v_j v_j^H,
@@ -869,10 +877,11 @@ __device__ void householder_complement(double2* X, int d, int p, double2* E, dou
 }
 
 // Step 0 eigen-decomposition of G' = B_perp^H H B_perp, rank decision, Q~[:, 0:k] = B.
-__global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, double2* scratch) {
+__global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, double2* scratch, int dm) {
   __shared__ double2 sA[JLDS * JLDS];
   __shared__ double2 sU[JLDS * JLDS];
-  __shared__ double lam[256];
+  __shared__ double lam[STEP0_DMAX];
+  const int64_t stride = 4 * (int64_t)dm * dm;
   __shared__ double red[4];
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], k = v.k[i], d = n - k;
@@ -895,7 +904,7 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
     if (forced) {
       skip = v.forced[i] - k <= 0;
     } else {
-      double2* M = (d <= JLDS) ? sA : scratch + (int64_t)blockIdx.x * EIG_STRIDE;
+      double2* M = (d <= JLDS) ? sA : scratch + (int64_t)blockIdx.x * stride;
       for (int e = tid; e < d * d; e += blockDim.x) {
         const int r = e % d, q = e / d;
         const double2 gv = Gp[e];
@@ -932,14 +941,14 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
       }
     } else {
       // working copy of G' (LDS up to 64, else the cluster's scratch)
-      double2* scr = scratch + (int64_t)blockIdx.x * EIG_STRIDE;
+      double2* scr = scratch + (int64_t)blockIdx.x * stride;
       double2* A = (d <= JLDS) ? sA : scr;
-      double2* X = scr + 130 * 130;                        // d x d: eigenvector block, then complement input
-      double* work = (double*)(scr + 130 * 130 + TRI_MAX * TRI_MAX);  // per-vector tridiagonal work (4 d doubles)
+      double2* X = scr + (int64_t)dm * dm;                 // d x d: eigenvector block, then complement input
+      double* work = (double*)(scr + 2 * (int64_t)dm * dm);  // per-vector tridiagonal work (4 dm doubles)
       double2* wv = sU;                                    // d-vector scratch
-      double2* tauv = sU + TRI_MAX;
+      double2* tauv = sU + STEP0_DMAX;
       double* dg = lam;                                    // reuse: diag, then eigenvalues
-      __shared__ double off[TRI_MAX], eig[TRI_MAX];
+      __shared__ double off[STEP0_DMAX], eig[STEP0_DMAX];
       __shared__ double bounds[2];
       for (int e = tid; e < d * d; e += blockDim.x) A[e] = Gp[e];
       __syncthreads();
@@ -989,8 +998,8 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
       // inverse iteration for the p dominant eigenvectors of T (one thread per vector)
       const double tnorm = fmax(fabs(glo), fabs(ghi));
       for (int j = tid; j < p; j += blockDim.x) {
-        double* b = work + (int64_t)j * 4 * TRI_MAX;
-        double *D = b + TRI_MAX, *DU = D + TRI_MAX, *DL = DU + TRI_MAX;
+        double* b = work + (int64_t)j * 4 * dm;
+        double *D = b + dm, *DU = D + dm, *DL = DU + dm;
         for (int r = 0; r < d; ++r) b[r] = 1.0 + 0.37 * (double)((r * (j + 3) + 7 * j) % 11) / 11.0;
         const double lamj = eig[j] + 4.4e-16 * tnorm * (1 + j % 3);
         for (int it = 0; it < 3; ++it) {
@@ -1060,9 +1069,9 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
   if (tid == 0) v.kt[i] = k + p;
 }
 
-void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st) {
+void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, int dm, hipStream_t st) {
   if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_step0_eig, dim3(c.ncl), dim3(256), 0, st, v, c, scratch);
+  hipLaunchKernelGGL(k_step0_eig, dim3(c.ncl), dim3(256), 0, st, v, c, scratch, dm);
 }
 
 // Step 2 projections.  side 0: T = (x in colour ? Q~_x^H : I) Z ; side 1: Z = T (y in colour ? conj(Q~_y) : I)
@@ -1172,9 +1181,9 @@ void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int si
 
 // Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n]; explicit
 // L^-1 P and U^-1 (ld rmax = n - k).
-__global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2* scratch) {
+__global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2* scratch, int rm) {
   __shared__ double2 sF[64 * 64];
-  __shared__ int perm[256];
+  __shared__ int perm[STEP0_DMAX];
   __shared__ double rv[256];
   __shared__ int ri[256];
   const int i = c.cl[blockIdx.x];
@@ -1182,7 +1191,7 @@ __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2*
   if (r <= 0) return;
   const int tid = threadIdx.x;
   const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
-  double2* F = (r <= 64) ? sF : scratch + (int64_t)blockIdx.x * 256 * 256;
+  double2* F = (r <= 64) ? sF : scratch + (int64_t)blockIdx.x * rm * rm;
   for (int e = tid; e < r * r; e += blockDim.x) {
     const int a = e % r, b = e / r;
     F[e] = Z[kt + a + (int64_t)(kt + b) * n];
@@ -1271,9 +1280,9 @@ __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2*
   }
 }
 
-void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st) {
+void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int rm, hipStream_t st) {
   if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_lu, dim3(c.ncl), dim3(256), 0, st, v, c, scratch);
+  hipLaunchKernelGGL(k_lu, dim3(c.ncl), dim3(256), 0, st, v, c, scratch, rm);
 }
 
 // Step 3a panels: R_i[:, a] = (L^-1 P) Z_ia[k~:n, 0:m_a]; C_i[a, :] = Z_ai[0:m_a, k~:n] U^-1.
@@ -1297,17 +1306,30 @@ __global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
     // R: r x ma
     if (tr * 64 >= r || tc * 64 >= ma) return;
     const int m = min(64, r - tr * 64), nn = min(64, ma - tc * 64);
-    const double2* Zia = v.slots + v.slot_off[v.np_srow[ja]] + kt;  // rows k~.. of slot (i, a), ld n
-    gemm_tile<double, double2>(s, acc, Li + tr * 64, rmax, OP_N, Zia + (int64_t)tc * 64 * n, n, OP_N, m, nn, r);
+    const int code = v.np_srow[ja];
+    if (code >= 0) {  // rows k~.. of block (i, a), ld n
+      const double2* Zia = v.slots + v.slot_off[code] + kt;
+      gemm_tile<double, double2>(s, acc, Li + tr * 64, rmax, OP_N, Zia + (int64_t)tc * 64 * n, n, OP_N, m, nn, r);
+    } else {  // block (i, a) = S^T, S = stored (a, i) with ld n_a: columns k~.. of S
+      const double2* Sai = v.slots + v.slot_off[~code] + (int64_t)kt * na;
+      gemm_tile<double, double2>(s, acc, Li + tr * 64, rmax, OP_N, Sai + tc * 64, na, OP_T, m, nn, r);
+    }
     double2* R = v.RP + v.rp_off[i] + (int64_t)off * rmax;
     store_tile<double, double2>(acc, R + tr * 64 + (int64_t)tc * 64 * rmax, rmax, m, nn, ST_SET);
   } else {
     // C: ma x r
     if (tr * 64 >= ma || tc * 64 >= r) return;
     const int m = min(64, ma - tr * 64), nn = min(64, r - tc * 64);
-    const double2* Zai = v.slots + v.slot_off[v.np_scol[ja]] + (int64_t)kt * na;  // cols k~.. of slot (a, i)
-    gemm_tile<double, double2>(s, acc, Zai + tr * 64, na, OP_N, Ui + (int64_t)tc * 64 * rmax, rmax, OP_N, m, nn,
-                               r);
+    const int code = v.np_scol[ja];
+    if (code >= 0) {  // columns k~.. of block (a, i), ld n_a
+      const double2* Zai = v.slots + v.slot_off[code] + (int64_t)kt * na;
+      gemm_tile<double, double2>(s, acc, Zai + tr * 64, na, OP_N, Ui + (int64_t)tc * 64 * rmax, rmax, OP_N, m, nn,
+                                 r);
+    } else {  // block (a, i) = S^T, S = stored (i, a) with ld n: rows k~.. of S
+      const double2* Sia = v.slots + v.slot_off[~code] + kt;
+      gemm_tile<double, double2>(s, acc, Sia + (int64_t)tr * 64 * n, n, OP_T, Ui + (int64_t)tc * 64 * rmax, rmax,
+                                 OP_N, m, nn, r);
+    }
     const int pr = v.prow[i];
     double2* C = v.CP + v.cp_off[i] + off;
     store_tile<double, double2>(acc, C + tr * 64 + (int64_t)tc * 64 * pr, pr, m, nn, ST_SET);
@@ -1412,6 +1434,21 @@ __global__ void k_zero(double2* p, int64_t n) {
     p[e] = make_double2(0, 0);
 }
 
+// dst + dst_off[b] <- src + src_off[b], len[b] elements, one workgroup per block
+__global__ void k_copy_blocks(const double2* src, const int64_t* src_off, double2* dst, const int64_t* dst_off,
+                              const int64_t* len) {
+  const int b = blockIdx.x;
+  const double2* a = src + src_off[b];
+  double2* d = dst + dst_off[b];
+  for (int64_t e = threadIdx.x; e < len[b]; e += blockDim.x) d[e] = a[e];
+}
+
+void launch_copy_blocks(const double2* src, const int64_t* src_off, double2* dst, const int64_t* dst_off,
+                        const int64_t* len, int nb, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_copy_blocks, dim3(nb), dim3(256), 0, st, src, src_off, dst, dst_off, len);
+}
+
 void launch_zero(double2* p, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   int blocks = (int)imin64(8192, (n + 255) / 256);
@@ -1422,21 +1459,22 @@ __global__ void k_merge(LevelView v, const MergeTask* tasks, const double2* S, d
   const MergeTask t = tasks[blockIdx.x];
   const int ka = v.kt[t.ca], kb = v.kt[t.cb];
   double2* D = dst + t.dst;
+  // source element (i, j) of the ordered pair (ca, cb); a transposed source
+  // stores (cb, ca) with leading dimension n_cb
+  const int64_t si = t.tr ? (int64_t)v.n[t.cb] : 1, sj = t.tr ? 1 : (int64_t)v.n[t.ca];
   if (t.kind == 0 || t.kind == 2) {
     const double2* Z = v.slots + v.slot_off[t.slot];
-    const int ld = v.n[t.ca];
     for (int e = threadIdx.x; e < ka * kb; e += blockDim.x) {
       const int i = e % ka, j = e / ka;
-      D[i + j * t.ldd] = Z[i + (int64_t)j * ld];
+      D[i + j * t.ldd] = Z[i * si + j * sj];
     }
   } else {
     const double2* F = t.slot >= 0 ? v.slots + v.slot_off[t.slot] : nullptr;
-    const int ld = v.n[t.ca];
     for (int e = threadIdx.x; e < ka * kb; e += blockDim.x) {
       const int i = e % ka, j = e / ka;
       double2 val = make_double2(0, 0);
       if (i < t.ska && j < t.skb) val = S[t.soff + i + (int64_t)j * t.ska];
-      if (F) val = cadd(val, F[i + (int64_t)j * ld]);
+      if (F) val = cadd(val, F[i * si + j * sj]);
       D[i + j * t.ldd] = val;
     }
   }

@@ -42,18 +42,19 @@ struct LevelView {
   const int32_t* slot_a;
   const int32_t* slot_b;
   double2* slots;
-  int nnear;               // slots [0, nnear) are inadmissible blocks, the rest fill-receiving blocks
+  int nnear;               // slots [0, nnear) are inadmissible blocks, the rest fill-receiving blocks;
+                           // one slot per unordered pair (slot_a <= slot_b), block (b, a) = its transpose
   const int32_t* diag_slot;
   // inadmissible partners N+(i) (incl. i), CSR
   const int32_t* np_ptr;
   const int32_t* np_cl;
-  const int32_t* np_srow;  // slot (i, a)
-  const int32_t* np_scol;  // slot (a, i)
+  const int32_t* np_srow;  // code of block (i, a): slot, or ~slot when stored as (a, i)
+  const int32_t* np_scol;  // code of block (a, i)
   const int32_t* np_off;   // offset of a inside the panels (sum of n over earlier partners)
   // fill partners (admissible / ancestor-admissible pairs reached by fill-ins), CSR
   const int32_t* fp_ptr;
   const int32_t* fp_cl;
-  const int32_t* fp_srow;
+  const int32_t* fp_srow;  // code of block (i, b)
   // per-cluster storage
   const int64_t* q_off;  double2* Q;     // Q~ (n x n), kept-first: [B B_add B~perp]
   const int64_t* b_off;  double2* B;     // B (n x k)
@@ -122,14 +123,14 @@ void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2*
 
 // ---- factorization ----
 constexpr int GRAM_SPLIT = 16;  // partial sums of the Step 0 Gram
-constexpr int64_t STEP0_SCRATCH = 130 * 130 + 3 * 128 * 128;  // complex elements per cluster of a colour
+constexpr int STEP0_DMAX = 512;  // largest cluster complement n - k (Step 0, Step 1, partial LU)
 void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);
 void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st);
-void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
+void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, int dm, hipStream_t st);
 void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int side, bool mixed, hipStream_t st);
 void launch_proj_fused(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st);
-void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, hipStream_t st);
+void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int rm, hipStream_t st);
 void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st);
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st);
 
@@ -143,8 +144,11 @@ struct MergeTask {
   int32_t ca, cb;      // child clusters
   int64_t soff;        // coupling offset (kind 1)
   int32_t ska, skb;    // coupling dims (construction ranks)
+  int32_t tr;          // source slot holds (cb, ca): read transposed
 };
 void launch_zero(double2* p, int64_t n, hipStream_t st);
+void launch_copy_blocks(const double2* src, const int64_t* src_off, double2* dst, const int64_t* dst_off,
+                        const int64_t* len, int nb, hipStream_t st);
 void launch_merge(const LevelView& v, const MergeTask* t, int nt, const double2* S, double2* dst,
                   hipStream_t st);
 void launch_parent_basis(int np, const int32_t* pn, const int32_t* pk, const int32_t* k1,

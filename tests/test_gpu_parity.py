@@ -10,8 +10,8 @@ pytestmark = pytest.mark.gpu
 
 # small problems the oracle finishes in seconds; several tiles, ragged leaves, multiple levels
 CASES = [((8, 8, 8), 16, 1e-4), ((10, 7, 9), 12, 1e-5), ((6, 6, 6), 8, 1e-6), ((9, 5, 3), 7, 1e-3),
-         ((12, 12, 12), 27, 1e-4)]
-IDS = ["8^3_leaf16", "10x7x9_leaf12", "6^3_leaf8", "9x5x3_leaf7", "12^3_leaf27"]
+         ((12, 12, 12), 27, 1e-4), ((12, 12, 24), 27, 1e-4)]
+IDS = ["8^3_leaf16", "10x7x9_leaf12", "6^3_leaf8", "9x5x3_leaf7", "12^3_leaf27", "12x12x24_leaf27"]
 
 
 def _torch():

@@ -194,6 +194,8 @@ struct FactorLevel {
   DArr<int32_t> d_n, d_k, d_kt, d_forced, d_np_off, d_prow, d_flags;
   DArr<int64_t> d_slot_off, d_q_off, d_b_off, d_bp_off, d_lu_off, d_cp_off, d_rp_off, d_w_off, d_voff;
   DArr<double> d_margins;
+  DArr<double2> d_pmax;   // 4 unsigned 64-bit maxima per cluster (mixed form)
+  DArr<int32_t> d_f32_ok;
   DArr<double2> Q, LU, CP, RP, B;
   std::vector<int64_t> voff;
   LevelView view{};
@@ -1064,6 +1066,11 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     F.d_w_off.upload(w_off, st);
     F.d_voff.upload(F.voff, st);
     F.d_margins.alloc(2 * nc);
+    if (mixed) {
+      F.d_pmax.alloc(2 * nc);
+      launch_zero(F.d_pmax.p, 2 * nc, st);
+      F.d_f32_ok.alloc(nc);
+    }
     F.Q.alloc(q_off[nc]);
     F.LU.alloc(lu_off[nc]);
     F.CP.alloc(cp_off[nc]);
@@ -1171,6 +1178,8 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     v.W = W.p;
     v.flags = F.d_flags.p;
     v.margins = F.d_margins.p;
+    v.pmax = mixed ? reinterpret_cast<unsigned long long*>(F.d_pmax.p) : nullptr;
+    v.f32_ok = mixed ? F.d_f32_ok.p : nullptr;
     launch_householder_perp(v, nc, st);
     check_launch("host.cpp:1040");
     hipEvent_t e_lev0 = ev.next(st);
@@ -1222,6 +1231,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       launch_lu(v, ct, lu_scr.p, dmax, st);
       check_launch("lu");
       launch_panels(v, ct, st);
+      if (mixed) launch_f32_ok(v, ct, F32_KAPPA, st);
       check_launch("panels");
       hipEvent_t e2 = ev.next(st);
       phase_ev.push_back({es, e0, e1, e2});

@@ -1285,6 +1285,33 @@ void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int r
   hipLaunchKernelGGL(k_lu, dim3(c.ncl), dim3(256), 0, st, v, c, scratch, rm);
 }
 
+// Largest |re| + |im| over the workgroup, folded into *dst with an atomic max on
+// the bit pattern (monotone for non-negative doubles).
+__device__ void block_max_to(double mx, unsigned long long* dst) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__device__ void panel_max(const TileAcc<double>& acc, unsigned long long* dst) {
+  double mx = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mx = fmax(mx, fabs(acc.re[t][u][q]) + fabs(acc.im[t][u][q]));
+  block_max_to(mx, dst);
+}
+
 // Step 3a panels: R_i[:, a] = (L^-1 P) Z_ia[k~:n, 0:m_a]; C_i[a, :] = Z_ai[0:m_a, k~:n] U^-1.
 // grid: (panel task, 2x2 tiles, which)
 __global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
@@ -1316,6 +1343,19 @@ __global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
     }
     double2* R = v.RP + v.rp_off[i] + (int64_t)off * rmax;
     store_tile<double, double2>(acc, R + tr * 64 + (int64_t)tc * 64 * rmax, rmax, m, nn, ST_SET);
+    if (v.pmax) {
+      panel_max(acc, &v.pmax[4 * i + 1]);
+      if (tr == 0 && tc == 0) {  // largest entry of the input block Z_ia[k~:n, 0:m_a]
+        double mx = 0.0;
+        for (int e = threadIdx.x; e < r * ma; e += blockDim.x) {
+          const int q = e % r, j = e / r;
+          const double2 z = code >= 0 ? v.slots[v.slot_off[code] + kt + q + (int64_t)j * n]
+                                      : v.slots[v.slot_off[~code] + j + (int64_t)(kt + q) * na];
+          mx = fmax(mx, fabs(z.x) + fabs(z.y));
+        }
+        block_max_to(mx, &v.pmax[4 * i + 2]);
+      }
+    }
   } else {
     // C: ma x r
     if (tr * 64 >= ma || tc * 64 >= r) return;
@@ -1333,6 +1373,7 @@ __global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
     const int pr = v.prow[i];
     double2* C = v.CP + v.cp_off[i] + off;
     store_tile<double, double2>(acc, C + tr * 64 + (int64_t)tc * 64 * pr, pr, m, nn, ST_SET);
+    if (v.pmax) panel_max(acc, &v.pmax[4 * i]);
   }
 }
 
@@ -1354,6 +1395,7 @@ struct SchurTerm {
 __device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks& c, int e, int tr, int tc,
                                            SchurTerm& t) {
   const int i = c.sc_i[e];
+  if (c.term_sel >= 0 && (v.f32_ok[i] != 0) != (c.term_sel != 0)) return false;
   const int n = v.n[i], kt = v.kt[i];
   t.r = n - kt;
   if (t.r <= 0) return false;
@@ -1418,12 +1460,42 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   store_tile<R, double2>(acc, Z, na, m, nn, ST_SUB);
 }
 
+// The mixed form splits every flush: terms of clusters whose panels show no
+// growth run on FP32 matrix cores, the others (where the Schur update nearly
+// cancels the block and FP32 rounding would dominate) in FP64.
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.nsc <= 0) return;
-  if (mixed)
-    hipLaunchKernelGGL(k_schur<float>, dim3(c.nsc, c.tiles * c.tiles), dim3(256), 0, st, v, c);
-  else
-    hipLaunchKernelGGL(k_schur<double>, dim3(c.nsc, c.tiles * c.tiles), dim3(256), 0, st, v, c);
+  const dim3 grid(c.nsc, c.tiles * c.tiles);
+  if (mixed) {
+    ColourTasks c1 = c, c0 = c;
+    c1.term_sel = 1;
+    c0.term_sel = 0;
+    hipLaunchKernelGGL(k_schur<float>, grid, dim3(256), 0, st, v, c1);
+    hipLaunchKernelGGL(k_schur<double>, grid, dim3(256), 0, st, v, c0);
+  } else {
+    ColourTasks ca = c;
+    ca.term_sel = -1;
+    hipLaunchKernelGGL(k_schur<double>, grid, dim3(256), 0, st, v, ca);
+  }
+}
+
+// f32_ok[i]: the FP32 rounding of cluster i's Schur terms, about
+// u32 sqrt(r) max|C| max|R|, stays within kappa u32 of the largest entry of the
+// blocks its panels were formed from.
+__global__ void k_f32_ok(LevelView v, ColourTasks c, double kappa) {
+  for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < c.ncl; e += blockDim.x * gridDim.x) {
+    const int i = c.cl[e];
+    const int r = v.n[i] - v.kt[i];
+    const double gc = __longlong_as_double((long long)v.pmax[4 * i]);
+    const double gr = __longlong_as_double((long long)v.pmax[4 * i + 1]);
+    const double z = __longlong_as_double((long long)v.pmax[4 * i + 2]);
+    v.f32_ok[i] = (r <= 0) || (gc * gr * sqrt((double)r) <= kappa * z);
+  }
+}
+
+void launch_f32_ok(const LevelView& v, const ColourTasks& c, double kappa, hipStream_t st) {
+  if (c.ncl <= 0) return;
+  hipLaunchKernelGGL(k_f32_ok, dim3((c.ncl + 255) / 256), dim3(256), 0, st, v, c, kappa);
 }
 
 // ===========================================================================

@@ -66,6 +66,8 @@ struct LevelView {
   const int64_t* w_off;  double2* W;     // workspace: H (n x n), X (n x d), G' (d x d), U' (d x d)
   int32_t* flags;                        // [0]: 1 + cluster of a zero pivot
   double* margins;                       // per cluster (sigma_p / tau, sigma_{p+1} / tau)
+  unsigned long long* pmax;              // 4 per cluster: max |C|, max |R|, max |input block| (double bits), unused
+  int32_t* f32_ok;                       // per cluster: its Schur terms may run in FP32 (mixed form)
 };
 
 // Per-colour task lists (device arrays).
@@ -79,6 +81,7 @@ struct ColourTasks {
   int nsv;                                // solve gather targets and contributions
   int colour;
   int tiles;                              // 64-wide tiles per block side (ceil(max n / 64))
+  int term_sel;                           // Schur flush: -1 every term, 1 FP32-safe terms only, 0 the others
 };
 
 // Generic host-resolved batched GEMM task: C (op)= op(A) op(B).
@@ -123,6 +126,9 @@ void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2*
 
 // ---- factorization ----
 constexpr int GRAM_SPLIT = 16;  // partial sums of the Step 0 Gram
+// Mixed form: a cluster's Schur terms run in FP32 when sqrt(r) max|C| max|R| is
+// at most this multiple of the largest entry of the blocks they were formed from.
+constexpr double F32_KAPPA = 8.0;
 constexpr int STEP0_DMAX = 512;  // largest cluster complement n - k (Step 0, Step 1, partial LU)
 void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);
@@ -133,6 +139,7 @@ void launch_proj_fused(const LevelView& v, const ColourTasks& c, bool mixed, hip
 void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int rm, hipStream_t st);
 void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st);
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st);
+void launch_f32_ok(const LevelView& v, const ColourTasks& c, double kappa, hipStream_t st);
 
 // Level end: parent blocks from children (copy of kept k~ x k~ parts, padded
 // couplings plus fills, carried fills).

@@ -46,6 +46,51 @@ def cpu_baseline(budget_s: float = 30.0) -> dict:
                       f"factor + 1 RHS refined to {hist[-1]:.1e} in {dt:.1f} s; construction excluded"}
 
 
+# HBM bytes per launch of the FP64 Schur flush kernel on the default workload,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a 1 GiB copy
+# (profiles/k_schur_cube32_fp64.md); valid only for the kernel sources hashed here.
+SCHUR_TRAFFIC = {"sources_sha256": "48e7076e4a1f2bdc547cf10c020d4045a408fee7539bcaa43dce55a4a30bac05",
+                 "bytes_per_launch": 821654940}
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of the Schur flush kernel's source: the tile engine header, the
+    kernel interface header and the kernel's own section of the kernel file."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1703_06155_amd", "csrc")
+    for f in ("h2_device.hpp", "h2_kernels.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(csrc, "h2_kernels.hip"), "rb") as fh:
+        src = fh.read()
+    a, b = src.index(b"struct SchurTerm"), src.index(b"void launch_schur(")
+    h.update(src[a:b])
+    return h.hexdigest()
+
+
+def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dict:
+    """Roofline of the Schur flush kernel from the algorithmic ledger and the
+    launch durations the library measured with HIP events on its stream."""
+    per_launch_s = ms * 1e-3 / max(launches, 1)
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)  # flop / byte
+    intensity = flops / nbytes if nbytes > 0 else float("inf")
+    traffic = None
+    if SCHUR_TRAFFIC["sources_sha256"] and SCHUR_TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+        traffic = SCHUR_TRAFFIC["bytes_per_launch"]
+    if intensity >= ridge:
+        achieved = flops / max(launches, 1) / per_launch_s / 1e12 if ms > 0 else 0.0
+        out = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        achieved = nbytes / max(launches, 1) / per_launch_s / 1e9 if ms > 0 else 0.0
+        out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": "k_schur<double>",
+                "launches": launches, "flops_per_launch": flops / max(launches, 1),
+                "bytes_per_launch_algorithmic": nbytes / max(launches, 1), "intensity_flop_per_byte": intensity,
+                "avg_launch_ms": ms / max(launches, 1)})
+    return out
+
+
 COPY_BYTES = 1 << 30      # one direction of the calibration copy
 
 
@@ -108,11 +153,12 @@ def main():
     for k in range(args.steps):
         x, info = step()
         infos.append(info)
-        tm = G.timing()
+        tm = G.timing(ledger=False)
         timings.append(tm)
         fac_ms.append(tm[0])
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    ledger = G.timing()[6:]  # algorithmic ledger of the last factorization (same ranks every step)
     ms_per_step = 1000.0 * total / args.steps
     # solve-only timings (factor resident)
     torch.cuda.synchronize()
@@ -137,14 +183,14 @@ def main():
     mixed_fac = []
     for k in range(args.steps):
         xm, info_m = step()
-        mixed_fac.append(G.timing()[:6])
+        mixed_fac.append(G.timing(ledger=False))
     torch.cuda.synchronize()
     mixed_total = time.perf_counter() - t1
     tm_mixed = np.mean(np.array(mixed_fac), axis=0)
     tm = np.mean(np.array(timings), axis=0)
-    schur_flops, schur_launches, factor_flops, schur_bytes = tm[6], tm[7], tm[8], tm[9]
+    schur_flops, schur_launches, factor_flops, schur_bytes = ledger
     schur_ms = tm[3]
-    achieved = schur_flops / (schur_ms * 1e-3) / 1e12 if schur_ms > 0 else 0.0
+    roof = schur_roofline(schur_flops, schur_bytes, schur_ms, int(schur_launches))
     out = {
         "metric": "H² factor unknowns/s + solve ms at rel. residual 1e-8, mixed/batched vs FP64",
         "value": pr.n * args.steps / total,
@@ -178,11 +224,7 @@ def main():
                             "final_lu": tm[5]},
         "factor_tflops": factor_flops / (tm[0] * 1e-3) / 1e12,
         "levels": stats.tolist(),
-        "roofline": {"kernel": "k_schur", "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "launches": int(schur_launches), "flops_per_launch": schur_flops / max(schur_launches, 1),
-                     "avg_launch_ms": schur_ms / max(schur_launches, 1),
-                     "hbm_gbs_algorithmic": schur_bytes / (schur_ms * 1e-3) / 1e9 if schur_ms > 0 else 0.0},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

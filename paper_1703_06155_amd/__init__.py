@@ -270,11 +270,12 @@ class H2:
                "h2_forced_ranks_layout")
         return out.reshape(-1, 4)
 
-    def timing(self) -> np.ndarray:
-        """[total, steps 0-2, LU + panels, Schur, merges, final LU] ms, then the ledger:
-        Schur flops, Schur launches, factor flops, Schur bytes."""
-        out = np.zeros(10)
-        _check(lib().h2_factor_timing(self._h, _dptr(out), 10), "h2_factor_timing")
+    def timing(self, ledger: bool = True) -> np.ndarray:
+        """[total, steps 0-2, LU + panels, Schur, merges, final LU] ms of the last
+        factorization, then (ledger=True) its algorithmic ledger: Schur flops,
+        Schur launches, factor flops, Schur bytes (computed on the host on first request)."""
+        out = np.zeros(10 if ledger else 6)
+        _check(lib().h2_factor_timing(self._h, _dptr(out), out.size), "h2_factor_timing")
         return out
 
 

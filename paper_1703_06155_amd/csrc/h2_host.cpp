@@ -1473,7 +1473,7 @@ static void ensure_vbuf(h2_ctx* H, int nrhs) {
   }
   const int64_t zb = (nrhs + 63) / 64;
   H->sw_scratch.alloc(blk * zb);
-  H->sw_part.alloc(blk * zb * BWD_SPLIT);
+  H->sw_part.alloc(blk * std::max<int64_t>(zb * BWD_SPLIT, SV_SPLIT));
   H->vbuf_nrhs = nrhs;
 }
 

@@ -1869,33 +1869,60 @@ __global__ void __launch_bounds__(256) k_sw_bwd_local(LevelView v, ColourTasks c
 // coalesced along the column-major storage.
 // ---------------------------------------------------------------------------
 // y[0:m] = op(M) x for column-major M (m x n, ld); op N or conj (R).  All threads.
-__device__ __forceinline__ void bv_gemv_n(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y,
-                                          bool conj) {
-  for (int row = threadIdx.x; row < m; row += blockDim.x) {
-    double2 acc = make_double2(0, 0);
-    const double2* Mr = M + row;
-    if (!conj)
-      for (int e = 0; e < n; ++e) acc = cadd(acc, cmul(Mr[(int64_t)e * ld], x[e]));
-    else
-      for (int e = 0; e < n; ++e) acc = cadd(acc, cmulc(Mr[(int64_t)e * ld], x[e]));
-    y[row] = acc;
-  }
+__device__ __forceinline__ double2 cfma(double2 acc, double2 a, double2 x, bool conj) {
+  return cadd(acc, conj ? cmulc(a, x) : cmul(a, x));
 }
 
-// y[0:n] = M^T x (conj: M^H x) for column-major M (m x n): one wavefront per output.
-__device__ __forceinline__ void bv_gemv_t(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y,
-                                          bool conj) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = w; j < n; j += nw) {
+// y[0:m] = M x (conj: conj(M) x) for column-major M (m x n, m <= 512), x in LDS.
+// Lanes own rows, the four wavefronts take interleaved columns with eight
+// independent loads in flight per step; partial sums meet in LDS.
+__device__ void bv_gemv_n(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y, bool conj) {
+  __shared__ double2 red[4][512];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    const int r = r0 + lane;
+    if (r >= m) continue;
+    const double2* Mr = M + r;
     double2 acc = make_double2(0, 0);
-    const double2* Mc = M + (int64_t)j * ld;
-    if (!conj)
-      for (int r = lane; r < m; r += 64) acc = cadd(acc, cmul(Mc[r], x[r]));
-    else
-      for (int r = lane; r < m; r += 64) acc = cadd(acc, cmulc(Mc[r], x[r]));
-    acc.x = wave_sum(acc.x);
-    acc.y = wave_sum(acc.y);
-    if (lane == 0) y[j] = acc;
+    int j = w;
+    for (; j + 28 < n; j += 32) {
+      double2 a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = Mr[(int64_t)(j + 4 * u) * ld];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cfma(acc, a[u], x[j + 4 * u], conj);
+    }
+    for (; j < n; j += 4) acc = cfma(acc, Mr[(int64_t)j * ld], x[j], conj);
+    red[w][r] = acc;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < m; r += blockDim.x) y[r] = cadd(cadd(red[0][r], red[1][r]), cadd(red[2][r], red[3][r]));
+  __syncthreads();
+}
+
+// y[0:n] = M^T x (conj: M^H x) for column-major M (m x n), x in LDS: each
+// wavefront reduces eight columns at a time (loads of all eight in flight).
+__device__ void bv_gemv_t(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y, bool conj) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int j0 = w * 8; j0 < n; j0 += 32) {
+    double2 acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = make_double2(0, 0);
+    for (int r = lane; r < m; r += 64) {
+      const double2 xv = x[r];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < n) acc[u] = cfma(acc[u], M[r + (int64_t)(j0 + u) * ld], xv, conj);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc[u].x = wave_sum(acc[u].x);
+      acc[u].y = wave_sum(acc[u].y);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < n) y[j0 + u] = acc[u];
   }
 }
 
@@ -1946,7 +1973,18 @@ __global__ void __launch_bounds__(256) k_sv_fwd_gather(LevelView v, ColourTasks 
             const int row = rb + h * 64 + lane;
             if (row >= ma) continue;
             const double2* C = v.CP + v.cp_off[i] + off + row;
-            for (int q = w; q < r; q += 4) acc[h] = cadd(acc[h], cmul(C[(int64_t)q * pr], bi[q]));
+            int q = w;
+            for (; q + 12 < r; q += 16) {
+              double2 cv[4], bv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                cv[u] = C[(int64_t)(q + 4 * u) * pr];
+                bv[u] = bi[q + 4 * u];
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc[h] = cadd(acc[h], cmul(cv[u], bv[u]));
+            }
+            for (; q < r; q += 4) acc[h] = cadd(acc[h], cmul(C[(int64_t)q * pr], bi[q]));
           }
         } else {
           // row dot products: rows split over lanes of the wavefronts, r terms each
@@ -2000,7 +2038,18 @@ __global__ void __launch_bounds__(256) k_sv_bwd_partial(LevelView v, ColourTasks
           for (int h = 0; h < 2; ++h) {
             const int q = qb + h * 64 + lane;
             if (q >= r) continue;
-            for (int e = w; e < ma; e += 4) acc[h] = cadd(acc[h], cmul(R[q + (int64_t)e * rmax], ya[e]));
+            int e = w;
+            for (; e + 12 < ma; e += 16) {
+              double2 rv[4], yv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                rv[u] = R[q + (int64_t)(e + 4 * u) * rmax];
+                yv[u] = ya[e + 4 * u];
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc[h] = cadd(acc[h], cmul(rv[u], yv[u]));
+            }
+            for (; e < ma; e += 4) acc[h] = cadd(acc[h], cmul(R[q + (int64_t)e * rmax], ya[e]));
           }
         } else {
           const double2* C = v.CP + v.cp_off[i] + off;
@@ -2077,9 +2126,9 @@ void launch_sweep_bwd(const LevelView& v, const ColourTasks& c, double2* vec, co
                       int nrhs, int adj, double2* part, int nsplit, double2* scratch, hipStream_t st) {
   if (c.ncl <= 0) return;
   if (nrhs <= SMALL_RHS) {
-    hipLaunchKernelGGL(k_sv_bwd_partial, dim3(c.ncl, nsplit), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part,
-                       nsplit);
-    hipLaunchKernelGGL(k_sv_bwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, nsplit);
+    hipLaunchKernelGGL(k_sv_bwd_partial, dim3(c.ncl, SV_SPLIT), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj,
+                       part, SV_SPLIT);
+    hipLaunchKernelGGL(k_sv_bwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, SV_SPLIT);
     return;
   }
   const int zb = (nrhs + 63) / 64;

@@ -172,7 +172,8 @@ void launch_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv, hip
 void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream_t st);
 
 // ---- sweeps (nrhs columns; per-level vectors with leading dimension ldv) ----
-constexpr int BWD_SPLIT = 8;   // partial sums of the backward gather
+constexpr int BWD_SPLIT = 8;   // partial sums of the backward gather (many right-hand sides)
+constexpr int SV_SPLIT = 32;   // partial sums of the backward gather (matrix-vector sweeps)
 constexpr int SMALL_RHS = 4;   // up to this many right-hand sides the sweeps use matrix-vector kernels
 void launch_sweep_fwd(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
                       int nrhs, int adj, double2* scratch, hipStream_t st);

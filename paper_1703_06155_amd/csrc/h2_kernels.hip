@@ -1179,19 +1179,23 @@ void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int si
   }
 }
 
-// Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n]; explicit
-// L^-1 P and U^-1 (ld rmax = n - k).
+// Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n] (eqs. 9-11),
+// then explicit L^-1 P and U^-1 (ld rmax = n - k) by in-place triangular
+// inversion.  F lives in LDS up to LU_LDS_MAX, else in the cluster's scratch.
+constexpr int LU_LDS_MAX = 96;
+
 __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2* scratch, int rm) {
-  __shared__ double2 sF[64 * 64];
+  __shared__ double2 sF[LU_LDS_MAX * LU_LDS_MAX];
   __shared__ int perm[STEP0_DMAX];
-  __shared__ double rv[256];
-  __shared__ int ri[256];
+  __shared__ double2 tmp[STEP0_DMAX];
+  __shared__ int s_piv;
+  __shared__ double s_pv;
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (r <= 0) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
-  double2* F = (r <= 64) ? sF : scratch + (int64_t)blockIdx.x * rm * rm;
+  double2* F = (r <= LU_LDS_MAX) ? sF : scratch + (int64_t)blockIdx.x * rm * rm;
   for (int e = tid; e < r * r; e += blockDim.x) {
     const int a = e % r, b = e / r;
     F[e] = Z[kt + a + (int64_t)(kt + b) * n];
@@ -1199,34 +1203,34 @@ __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2*
   for (int a = tid; a < r; a += blockDim.x) perm[a] = a;
   __syncthreads();
   for (int j = 0; j < r; ++j) {
-    // pivot search: max |re| + |im| in column j, rows j..r-1, first index on ties
-    double best = -1.0;
-    int bi = r;
-    for (int a = j + tid; a < r; a += blockDim.x) {
-      const double val = fabs(F[a + j * r].x) + fabs(F[a + j * r].y);
-      if (val > best) {
-        best = val;
-        bi = a;
-      }
-    }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) {
-        const double v2 = rv[tid + o];
-        const int i2 = ri[tid + o];
-        if (v2 > rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) {
-          rv[tid] = v2;
-          ri[tid] = i2;
+    // pivot search by the first wavefront: max |re| + |im| in column j, first index on ties
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = r;
+      for (int a = j + lane; a < r; a += 64) {
+        const double val = fabs(F[a + j * r].x) + fabs(F[a + j * r].y);
+        if (val > best) {
+          best = val;
+          bi = a;
         }
       }
-      __syncthreads();
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_piv = bi;
+        s_pv = best;
+      }
     }
-    const int pj = ri[0];
-    const double pv = rv[0];
     __syncthreads();
-    if (!(pv > 0.0)) {
+    const int pj = s_piv;
+    if (!(s_pv > 0.0)) {
       if (tid == 0) atomicMax(v.flags, i + 1);
       return;
     }
@@ -1241,42 +1245,61 @@ __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2*
         perm[j] = perm[pj];
         perm[pj] = t;
       }
+      __syncthreads();
     }
-    __syncthreads();
     const double2 piv = F[j + j * r];
     const double pd = cabs2(piv);
     const double2 pinv = make_double2(piv.x / pd, -piv.y / pd);
-    for (int a = j + 1 + tid; a < r; a += blockDim.x) F[a + j * r] = cmul(F[a + j * r], pinv);
-    __syncthreads();
     const int rem = r - j - 1;
+    // multipliers go to tmp first so that the trailing update reads unscaled values only once
+    for (int a = tid; a < rem; a += blockDim.x) tmp[a] = cmul(F[j + 1 + a + j * r], pinv);
+    __syncthreads();
+    for (int a = tid; a < rem; a += blockDim.x) F[j + 1 + a + j * r] = tmp[a];
     for (int e = tid; e < rem * rem; e += blockDim.x) {
-      const int a = j + 1 + e % rem, b = j + 1 + e / rem;
-      F[a + b * r] = csub(F[a + b * r], cmul(F[a + j * r], F[j + b * r]));
+      const int a = e % rem, b = j + 1 + e / rem;
+      F[j + 1 + a + b * r] = csub(F[j + 1 + a + b * r], cmul(tmp[a], F[j + b * r]));
     }
     __syncthreads();
   }
+  // U^-1 in place (upper triangle): column j from the inverted leading block,
+  // U^-1[0:j, j] = -U^-1[0:j, 0:j] U[0:j, j] / U[j, j]
+  for (int j = 0; j < r; ++j) {
+    const double2 u = F[j + j * r];
+    const double ud = cabs2(u);
+    const double2 uinv = make_double2(u.x / ud, -u.y / ud);
+    for (int a = tid; a < j; a += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      for (int mm = a; mm < j; ++mm) acc = cadd(acc, cmul(F[a + mm * r], F[mm + j * r]));
+      tmp[a] = acc;
+    }
+    __syncthreads();
+    for (int a = tid; a < j; a += blockDim.x) {
+      const double2 t = cmul(tmp[a], uinv);
+      F[a + j * r] = make_double2(-t.x, -t.y);
+    }
+    if (tid == 0) F[j + j * r] = uinv;
+    __syncthreads();
+  }
+  // L^-1 in place (strict lower triangle, unit diagonal), columns right to left:
+  // L^-1[j+1:, j] = -L^-1[j+1:, j+1:] L[j+1:, j]
+  for (int j = r - 2; j >= 0; --j) {
+    for (int a = j + 1 + tid; a < r; a += blockDim.x) {
+      double2 acc = F[a + j * r];  // the unit diagonal of L^-1 times L[a, j]
+      for (int mm = j + 1; mm < a; ++mm) acc = cadd(acc, cmul(F[a + mm * r], F[mm + j * r]));
+      tmp[a] = acc;
+    }
+    __syncthreads();
+    for (int a = j + 1 + tid; a < r; a += blockDim.x) F[a + j * r] = make_double2(-tmp[a].x, -tmp[a].y);
+    __syncthreads();
+  }
+  // write out: U^-1 (upper) and L^-1 P (column j of L^-1 at column perm[j])
   double2* Li = v.LU + v.lu_off[i];
   double2* Ui = Li + (int64_t)rmax * rmax;
-  // column-wise triangular inverses
-  for (int col = tid; col < r; col += blockDim.x) {
-    // U^-1 column col
-    for (int a = col; a >= 0; --a) {
-      double2 acc = make_double2(a == col ? 1.0 : 0.0, 0.0);
-      for (int mm = a + 1; mm <= col; ++mm) acc = csub(acc, cmul(F[a + mm * r], Ui[mm + (int64_t)col * rmax]));
-      const double2 u = F[a + a * r];
-      const double ud = cabs2(u);
-      Ui[a + (int64_t)col * rmax] = cmul(acc, make_double2(u.x / ud, -u.y / ud));
-    }
-    for (int a = col + 1; a < r; ++a) Ui[a + (int64_t)col * rmax] = make_double2(0, 0);
-    // (L^-1)[:, col] placed at column perm[col] of L^-1 P
-    double2* Lc = Li + (int64_t)perm[col] * rmax;
-    for (int a = 0; a < col; ++a) Lc[a] = make_double2(0, 0);
-    Lc[col] = make_double2(1, 0);
-    for (int a = col + 1; a < r; ++a) {
-      double2 acc = make_double2(0, 0);
-      for (int mm = col; mm < a; ++mm) acc = cadd(acc, cmul(F[a + mm * r], Lc[mm]));
-      Lc[a] = make_double2(-acc.x, -acc.y);
-    }
+  for (int e = tid; e < r * r; e += blockDim.x) {
+    const int a = e % r, b = e / r;
+    const double2 f = F[a + b * r];
+    Ui[a + (int64_t)b * rmax] = (a <= b) ? f : make_double2(0, 0);
+    Li[a + (int64_t)perm[b] * rmax] = (a > b) ? f : make_double2(a == b ? 1.0 : 0.0, 0.0);
   }
 }
 

@@ -810,13 +810,14 @@ __device__ void tri_solve(const double* dg, const double* off, int d, double lam
   for (int i = d - 3; i >= 0; --i) b[i] = (b[i] - DU[i] * b[i + 1] - DU2[i] * b[i + 2]) / D[i];
 }
 
-// Orthonormal complement of the p orthonormal columns of X (d x p, ld d, overwritten)
-// written to E (d x (d - p), ld d).
-__device__ void householder_complement(double2* X, int d, int p, double2* E, double2* tau, double* red) {
+// Householder QR of the p columns of X (d x p, ld d, overwritten by the
+// reflectors): E (d x d, ld d) = H_0 ... H_{p-1}, whose first p columns are an
+// orthonormal basis of span(X) and the rest its orthonormal complement.
+__device__ void householder_basis(double2* X, int d, int p, double2* E, double2* tau, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int e = tid; e < d * (d - p); e += blockDim.x) {
+  for (int e = tid; e < d * d; e += blockDim.x) {
     const int r = e % d, c = e / d;
-    E[e] = make_double2(r == p + c ? 1.0 : 0.0, 0.0);
+    E[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   for (int j = 0; j < p; ++j) {
@@ -858,7 +859,7 @@ __device__ void householder_complement(double2* X, int d, int p, double2* E, dou
   for (int j = p - 1; j >= 0; --j) {
     const double2 t = tau[j];
     if (t.x == 0.0 && t.y == 0.0) continue;
-    for (int c = wv; c < d - p; c += 4) {
+    for (int c = wv; c < d; c += 4) {
       double2 w = make_double2(0, 0);
       for (int r = j + lane; r < d; r += 64) {
         const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
@@ -873,6 +874,48 @@ __device__ void householder_complement(double2* X, int d, int p, double2* E, dou
       }
     }
     __syncthreads();
+  }
+}
+
+// Eigenvalues of the symmetric tridiagonal T (diagonal dg, off-diagonal off) with
+// ascending indices ks[0..cnt), out[t] for target t.  Multisection: groups of G
+// lanes of one wavefront (G a power of two) bracket one eigenvalue, each lane
+// placing one Sturm-count probe per round, so a round narrows the bracket G + 1
+// fold; every thread of the block calls this.
+__device__ void tri_eig_targets(const double* dg, const double* off, int d, double glo, double ghi, double pivmin,
+                                const int* ks, int cnt, double* out) {
+  int G = 64;
+  while (G > 1 && (int)(blockDim.x / G) < cnt) G >>= 1;
+  const int ngroups = blockDim.x / G;
+  const int lane = threadIdx.x & 63, gid = threadIdx.x / G, m = threadIdx.x % G;
+  const int gbase = (lane / G) * G;
+  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  for (int t0 = 0; t0 < cnt; t0 += ngroups) {
+    const int t = t0 + gid;
+    const int k = t < cnt ? ks[t] : 0;
+    double lo = glo - 2.2e-16 * fabs(glo) - pivmin, hi = ghi + 2.2e-16 * fabs(ghi) + pivmin;
+    bool done = t >= cnt;
+    while (__ballot(!done) != 0ull) {
+      const double x = lo + (hi - lo) * (double)(m + 1) / (double)(G + 1);
+      const bool ge = !done && sturm_count(dg, off, d, x, pivmin) >= k + 1;
+      const unsigned long long mask = (__ballot(ge) >> gbase) & gmask;
+      if (!done) {
+        double nlo, nhi;
+        if (mask) {
+          const int f = __ffsll((long long)mask) - 1;
+          nhi = lo + (hi - lo) * (double)(f + 1) / (double)(G + 1);
+          nlo = f > 0 ? lo + (hi - lo) * (double)f / (double)(G + 1) : lo;
+        } else {
+          nlo = lo + (hi - lo) * (double)G / (double)(G + 1);
+          nhi = hi;
+        }
+        if ((nlo == lo && nhi == hi) || !(nhi > nlo)) done = true;
+        lo = nlo;
+        hi = nhi;
+        if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) done = true;
+      }
+    }
+    if (t < cnt && m == 0) out[t] = 0.5 * (lo + hi);
   }
 }
 
@@ -969,28 +1012,28 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
       __syncthreads();
       const double pivmin = red[3];
       const double glo = bounds[0], ghi = bounds[1];
-      // every eigenvalue by bisection (thread j: the j-th largest)
-      for (int j = tid; j < d; j += blockDim.x) {
-        const int a = d - 1 - j;  // ascending index
-        double lo = glo - 2.2e-16 * fabs(glo) - pivmin, hi = ghi + 2.2e-16 * fabs(ghi) + pivmin;
-        for (int it = 0; it < 200; ++it) {
-          const double mid = 0.5 * (lo + hi);
-          if (mid == lo || mid == hi) break;
-          if (sturm_count(dg, off, d, mid, pivmin) >= a + 1)
-            hi = mid;
-          else
-            lo = mid;
-          if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-        }
-        eig[j] = 0.5 * (lo + hi);
-      }
+      __shared__ int ks[STEP0_DMAX];
+      __shared__ int s_p;
+      // largest eigenvalue, then the rank decision against tau^2 by one Sturm count
+      if (tid == 0) ks[0] = d - 1;
+      __syncthreads();
+      tri_eig_targets(dg, off, d, glo, ghi, pivmin, ks, 1, eig);
       __syncthreads();
       const double s1 = sqrt(fmax(eig[0], 0.0));
       const double tau = v.eps_fill * fmax(v.nu[i], s1);
-      if (tau > 0.0)
-        for (int j = 0; j < d; ++j)
-          if (sqrt(fmax(eig[j], 0.0)) > tau) p = j + 1;
-      if (forced) p = min(max(v.forced[i] - k, 0), d);
+      if (tid == 0) {
+        int pp = (tau > 0.0) ? d - sturm_count(dg, off, d, tau * tau, pivmin) : 0;
+        if (forced) pp = min(max(v.forced[i] - k, 0), d);
+        s_p = pp;
+      }
+      __syncthreads();
+      p = s_p;
+      // the p largest eigenvalues (and the next one, for the margin), descending
+      const int ne = min(p + 1, d);
+      for (int j = tid; j < ne; j += blockDim.x) ks[j] = d - 1 - j;
+      __syncthreads();
+      tri_eig_targets(dg, off, d, glo, ghi, pivmin, ks, ne, eig);
+      __syncthreads();
       if (tid == 0 && v.margins) {
         v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(eig[p - 1], 0.0)) / tau : 1e300;
         v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(eig[p], 0.0)) / tau : 0.0;
@@ -1036,33 +1079,8 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
           __syncthreads();
         }
       }
-      // re-orthonormalise the p vectors (classical Gram-Schmidt, twice)
-      for (int cidx = 0; cidx < p; ++cidx) {
-        double2* x = X + (int64_t)cidx * d;
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int q = 0; q < cidx; ++q) {
-            const double2* y = X + (int64_t)q * d;
-            double pre = 0.0, pim = 0.0;
-            for (int r = tid; r < d; r += blockDim.x) {
-              const double2 z = cmulc(y[r], x[r]);
-              pre += z.x;
-              pim += z.y;
-            }
-            const double2 dot = make_double2(block_sum256(pre, red), block_sum256(pim, red));
-            for (int r = tid; r < d; r += blockDim.x) x[r] = csub(x[r], cmul(y[r], dot));
-            __syncthreads();
-          }
-        }
-        double pn = 0.0;
-        for (int r = tid; r < d; r += blockDim.x) pn += cabs2(x[r]);
-        const double nrm = 1.0 / sqrt(block_sum256(pn, red));
-        for (int r = tid; r < d; r += blockDim.x) x[r] = make_double2(x[r].x * nrm, x[r].y * nrm);
-        __syncthreads();
-      }
-      // U' = [X  complement(X)]
-      for (int e = tid; e < d * p; e += blockDim.x) Up[e] = X[e];
-      __syncthreads();
-      householder_complement(X, d, p, Up + (int64_t)p * d, tauv, red);
+      // U' = [orthonormal basis of span(X), its complement] from one Householder QR of X
+      householder_basis(X, d, p, Up, tauv, red);
     }
   }
   if (v.forced && v.forced[i] >= 0) p = min(max(v.forced[i] - k, 0), d);

@@ -108,6 +108,13 @@ h2_status h2_set_contrast(h2_handle H, const double* contrast, void* hip_stream)
  * leaves the handle unfactored. */
 h2_status h2_set_precision(h2_handle H, int32_t precision);
 
+/* Replay the forward/backward sweeps of h2_solve and h2_solve_adjoint from HIP
+ * graphs (enable != 0): the first solve with a given right-hand-side count and
+ * direction after each factorization captures the sweep's launches on a
+ * private stream; later solves launch the graph on the caller's stream.
+ * Results are identical to the direct launches.  Default: off. */
+h2_status h2_set_sweep_graph(h2_handle H, int32_t enable);
+
 /* Factor Z = L U in the product form of eq. 34 (Alg. 1 with Steps 0-3 per
  * cluster, Algs. 2-4; coupling/transfer updates eqs. 20-23 / 33; final LU of
  * the level-(l0-1) block).  Synchronises once per level to size the next

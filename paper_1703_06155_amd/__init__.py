@@ -66,6 +66,7 @@ def lib():
         L.h2_contrast_gradient.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P]
         L.h2_set_contrast.argtypes = [_P, _DP, _P]
         L.h2_set_precision.argtypes = [_P, ctypes.c_int32]
+        L.h2_set_sweep_graph.argtypes = [_P, ctypes.c_int32]
         L.h2_matvec.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P]
         L.h2_destroy.argtypes = [_P]
         L.h2_destroy.restype = None
@@ -78,7 +79,7 @@ def lib():
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
-                     "h2_set_contrast", "h2_set_precision"):
+                     "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -195,6 +196,11 @@ class H2:
         if precision not in ("fp64", "mixed"):
             raise ValueError(precision)
         _check(lib().h2_set_precision(self._h, H2_MIXED if precision == "mixed" else H2_FP64), "h2_set_precision")
+        return self
+
+    def set_sweep_graph(self, enable: bool = True):
+        """Replay the solve sweeps from captured HIP graphs."""
+        _check(lib().h2_set_sweep_graph(self._h, 1 if enable else 0), "h2_set_sweep_graph")
         return self
 
     def factor(self, stream=None):

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <array>
 #include <climits>
 #include <iterator>
@@ -184,6 +185,7 @@ struct BuildLevel {
   DArr<int32_t> d_cptr, d_ccol; // admissible CSR by row cluster (into S.adm order)
   DArr<int64_t> d_cstart, d_xoff;  // cluster starts (tree order), xhat offsets
   DArr<double> d_nu;
+  DArr<double2> mv_x, mv_y;     // matvec work: x_hat, y_hat (ktot x nrhs)
   int64_t ktot = 0;             // sum of k
 };
 
@@ -233,6 +235,19 @@ struct h2_ctx {
   h2::DArr<h2::MergeTask> ws_merge;
   int64_t nf = 0;
   std::vector<int32_t> final_off;          // per cluster of level l0-1
+  h2::DArr<int64_t> d_final_off;           // the same (without the total), on the device
+  // the sweeps as captured graphs, keyed by (nrhs, adjoint); they run on vtmp3 in place
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::pair<int, int>, hipGraphExec_t> sweep_graphs;
+  void drop_graphs() {
+    for (auto& g : sweep_graphs) (void)hipGraphExecDestroy(g.second);
+    sweep_graphs.clear();
+  }
+  ~h2_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
   h2::DArr<double2> Zf, Zinv;
   std::vector<double> timing;
   std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
@@ -948,6 +963,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot) release_factor_buffers(H);
   }
   H->vbuf_nrhs = 0;  // level sizes may change with the ranks: resize the sweep buffers
+  H->drop_graphs();
   H->timing.assign(6, 0.0);
   H->stats_rows.clear();
   EventPool ev;
@@ -1301,6 +1317,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       H->final_off.assign(npar + 1, 0);
       for (int p = 0; p < npar; ++p) H->final_off[p + 1] = H->final_off[p] + n_par[p];
       H->nf = H->final_off[npar];
+      H->d_final_off.upload(std::vector<int64_t>(H->final_off.begin(), H->final_off.end() - 1), st);
       dst_total = H->nf * H->nf;
       for (size_t e = 0; e < P.merge.size(); ++e) {
         const MergeSrc& m = P.merge[e];
@@ -1457,6 +1474,7 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
 // ---------------------------------------------------------------------------
 static void ensure_vbuf(h2_ctx* H, int nrhs) {
   if (H->vbuf_nrhs >= nrhs && !H->vbuf.empty()) return;
+  H->drop_graphs();  // captured sweeps point at the old buffers
   H->vbuf.clear();
   H->vbuf.resize(H->flev.size());
   for (size_t j = 0; j < H->flev.size(); ++j) H->vbuf[j].alloc(std::max<int64_t>(1, H->flev[j].ntot) * nrhs);
@@ -1518,16 +1536,12 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
       launch_vmerge(npar, F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, H->vbuf[j].p, H->vbuf[j + 1].p, 1,
                     P.d_nonempty.p, st);
     } else {
-      std::vector<int64_t> po(H->final_off.begin(), H->final_off.end() - 1);
-      DArr<int64_t> d_po;
-      d_po.upload(po, st);
-      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, d_po.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp.p, 1,
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp.p, 1,
                     P.d_nonempty.p, st);
       launch_dense_apply(H->Zinv.p, H->nf, H->vtmp.p, H->vtmp2.p, H->nf, nrhs, adj, st);
-      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, d_po.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp2.p, 0,
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp2.p, 0,
                     P.d_nonempty.p, st);
-      check_launch("host.cpp:1342");
-      HIPCHK(hipStreamSynchronize(st));
+      check_launch("final block");
     }
     check_launch("host.cpp:1345");
   }
@@ -1549,6 +1563,43 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
   HIPCHK(hipMemcpyAsync(out, H->vbuf[0].p, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
 }
 
+// The sweep on H->vtmp3 in place, replayed from a captured graph when enabled.
+static void sweep_vtmp3(h2_ctx* H, int nrhs, int adj, hipStream_t st) {
+  if (!H->use_graph || H->flev.empty()) {
+    sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, adj, st);
+    return;
+  }
+  ensure_vbuf(H, nrhs);
+  const auto key = std::make_pair(nrhs, adj);
+  auto it = H->sweep_graphs.find(key);
+  if (it == H->sweep_graphs.end()) {
+    if (!H->cap_stream) HIPCHK(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+    // the capture stream starts after everything queued on st so far
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev, st));
+    HIPCHK(hipStreamWaitEvent(H->cap_stream, ev, 0));
+    HIPCHK(hipStreamSynchronize(H->cap_stream));
+    (void)hipEventDestroy(ev);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, adj, H->cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(H->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(H->cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    it = H->sweep_graphs.emplace(key, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, st));
+}
+
 // y (tree order) = Z_H2 v (tree order)
 static void matvec_tree(h2_ctx* H, const double2* v, double2* y, int nrhs, hipStream_t st) {
   const Structure& S = H->S;
@@ -1562,7 +1613,8 @@ static void matvec_tree(h2_ctx* H, const double2* v, double2* y, int nrhs, hipSt
     BuildLevel& B = H->build[L - l];
     const int nc = S.nclusters(l);
     if (B.ktot == 0) continue;
-    DArr<double2> xh, yh;
+    DArr<double2>& xh = B.mv_x;
+    DArr<double2>& yh = B.mv_y;
     xh.alloc(B.ktot * nrhs);
     yh.alloc(B.ktot * nrhs);
     launch_basis_mv(nc, B.d_rows.p, B.d_k.p, B.d_voff.p, B.V.p, B.d_cstart.p, v, B.d_xoff.p, xh.p, N, B.ktot, nrhs, 1,
@@ -1571,8 +1623,7 @@ static void matvec_tree(h2_ctx* H, const double2* v, double2* y, int nrhs, hipSt
                        yh.p, B.ktot, nrhs, st);
     launch_basis_mv(nc, B.d_rows.p, B.d_k.p, B.d_voff.p, B.V.p, B.d_xoff.p, yh.p, B.d_cstart.p, y, B.ktot, N, nrhs, 0,
                     1, st);
-    check_launch("host.cpp:1386");
-    HIPCHK(hipStreamSynchronize(st));
+    check_launch("matvec level");
   }
 }
 
@@ -1824,6 +1875,14 @@ extern "C" h2_status h2_set_contrast(h2_handle H, const double* contrast, void* 
   });
 }
 
+extern "C" h2_status h2_set_sweep_graph(h2_handle H, int32_t enable) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    H->use_graph = enable != 0;
+    if (!H->use_graph) H->drop_graphs();
+  });
+}
+
 extern "C" h2_status h2_set_precision(h2_handle H, int32_t precision) {
   return guarded([&] {
     if (!H) fail(H2_ERR_ARG, "handle is NULL");
@@ -1874,12 +1933,12 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
     if (!adj) {
       // M^-1 = D^-1 Z^-1
       launch_permute_in(rhs, ldr, H->d_perm.p, nullptr, 0, N, nrhs, H->vtmp3.p, N, st);
-      sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 0, st);
+      sweep_vtmp3(H, nrhs, 0, st);
       launch_permute_out(H->vtmp3.p, N, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, outx, ldo, accumulate, st);
     } else {
       // M^-H = Z^-H D^-1
       launch_permute_in(rhs, ldr, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, H->vtmp3.p, N, st);
-      sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, 1, st);
+      sweep_vtmp3(H, nrhs, 1, st);
       launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, outx, ldo, accumulate, st);
     }
     check_launch("solve");

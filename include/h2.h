@@ -157,6 +157,22 @@ h2_status h2_contrast_gradient(h2_handle H, const void* x, const void* g, const 
 h2_status h2_matvec(h2_handle H, const void* x, void* y, int32_t nrhs, int64_t ld,
                     int32_t conj_transpose, void* hip_stream);
 
+/* Factor `count` independent handles together.  Each handle works on a stream
+ * of its own (default priority, created on first use) and up to eight host
+ * threads drive them, so that the small launches of many problems fill the
+ * device side by side; all of them start after the work already queued on
+ * hip_stream, and hip_stream waits for all of them.  Handles must be distinct.
+ * Returns the first failure ("batch item k: ..."); the other items are still
+ * factored. */
+h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream);
+
+/* x[k] = M_k^-1 b[k] for every handle k as h2_solve does (nrhs columns,
+ * leading dimension ld[k], refinement to tol when tol > 0, infos[k] when infos
+ * is not NULL), concurrently in the manner of h2_factor_batch.  b[k], x[k] are
+ * device pointers; b[k] and x[k] may alias. */
+h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
+                         const int64_t* ld, double tol, int32_t max_iter, void* hip_stream, h2_solve_info* infos);
+
 /* Release every resource of H (NULL is ignored). */
 void h2_destroy(h2_handle H);
 

@@ -67,6 +67,10 @@ def lib():
         L.h2_set_contrast.argtypes = [_P, _DP, _P]
         L.h2_set_precision.argtypes = [_P, ctypes.c_int32]
         L.h2_set_sweep_graph.argtypes = [_P, ctypes.c_int32]
+        L.h2_factor_batch.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, _P]
+        L.h2_solve_batch.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                     ctypes.c_int32, _I64P, ctypes.c_double, ctypes.c_int32, _P,
+                                     ctypes.POINTER(SolveInfo)]
         L.h2_matvec.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P]
         L.h2_destroy.argtypes = [_P]
         L.h2_destroy.restype = None
@@ -79,7 +83,8 @@ def lib():
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
-                     "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph"):
+                     "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
+                     "h2_solve_batch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -291,3 +296,37 @@ def forced_ranks_from_oracle(construct_ranks: dict, factor_ranks: dict) -> np.nd
     keys = sorted(construct_ranks, key=lambda lt: (-lt[0], lt[1]))
     rows = [(l, t, construct_ranks[(l, t)], factor_ranks.get((l, t), -1)) for (l, t) in keys]
     return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
+
+
+def factor_batch(solvers, stream=None):
+    """Factor several independent :class:`H2` handles together (h2_factor_batch)."""
+    arr = (_P * len(solvers))(*[sv._h.value for sv in solvers])
+    _check(lib().h2_factor_batch(arr, len(solvers), _stream_ptr(stream)), "h2_factor_batch")
+    return solvers
+
+
+def solve_batch(solvers, rhs, tol=0.0, max_iter=20, stream=None, info=False):
+    """x_k = M_k^-1 b_k for every handle (h2_solve_batch); every b_k has the same number of columns."""
+    torch = _torch()
+    bufs, outs, nrhs = [], [], None
+    for sv, b in zip(solvers, rhs):
+        buf, nr, vec = _as_cols(b, sv.n)
+        if nrhs is None:
+            nrhs = nr
+        elif nr != nrhs:
+            raise ValueError("every right-hand side needs the same number of columns")
+        bufs.append((buf, vec))
+        outs.append(torch.empty_like(buf))
+    cnt = len(solvers)
+    hs = (_P * cnt)(*[sv._h.value for sv in solvers])
+    bp = (_P * cnt)(*[b.data_ptr() for b, _ in bufs])
+    xp = (_P * cnt)(*[o.data_ptr() for o in outs])
+    ld = np.ascontiguousarray([sv.n for sv in solvers], dtype=np.int64)
+    infos = (SolveInfo * cnt)()
+    _check(lib().h2_solve_batch(hs, cnt, bp, xp, nrhs, ld.ctypes.data_as(_I64P), float(tol), int(max_iter),
+                                _stream_ptr(stream), infos), "h2_solve_batch")
+    xs = [_from_cols(o, vec) for o, (_, vec) in zip(outs, bufs)]
+    if info:
+        return xs, [{"iterations": i.iterations, "rel_residual": i.rel_residual,
+                     "rel_residual_first": i.rel_residual_first} for i in infos]
+    return xs

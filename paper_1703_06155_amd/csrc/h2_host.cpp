@@ -20,7 +20,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -239,6 +242,7 @@ struct h2_ctx {
   // the sweeps as captured graphs, keyed by (nrhs, adjoint); they run on vtmp3 in place
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
+  hipStream_t own_stream = nullptr;        // the handle's stream inside batched calls
   std::map<std::pair<int, int>, hipGraphExec_t> sweep_graphs;
   void drop_graphs() {
     for (auto& g : sweep_graphs) (void)hipGraphExecDestroy(g.second);
@@ -247,6 +251,7 @@ struct h2_ctx {
   ~h2_ctx() {
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
   }
   h2::DArr<double2> Zf, Zinv;
   std::vector<double> timing;
@@ -1992,6 +1997,59 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
   if (rel > tol) fail(H2_ERR_NOCONV, "refinement did not reach tol within max_iter");
 }
 
+// Run fn(k, stream_k) for every handle k concurrently: handle k works on its own
+// stream from its own host thread (at most `workers` threads pull handles from a
+// shared counter), after everything queued on the caller's stream, which in turn
+// waits for all of them.  The first failure is reported.
+template <typename Fn>
+static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
+  if (!hs || count < 1) fail(H2_ERR_ARG, "empty batch");
+  for (int32_t k = 0; k < count; ++k) {
+    if (!hs[k]) fail(H2_ERR_ARG, "handle is NULL");
+    for (int32_t q = 0; q < k; ++q)
+      if (hs[q] == hs[k]) fail(H2_ERR_ARG, "a handle appears twice in the batch");
+  }
+  hipEvent_t start;
+  HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(start, st));
+  for (int32_t k = 0; k < count; ++k) {
+    if (!hs[k]->own_stream) HIPCHK(hipStreamCreateWithFlags(&hs[k]->own_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamWaitEvent(hs[k]->own_stream, start, 0));
+  }
+  std::atomic<int32_t> next{0};
+  std::mutex mu;
+  h2_status first = H2_OK;
+  std::string first_msg;
+  const int workers = std::max(1, std::min<int>(count, 8));
+  auto work = [&]() {
+    for (;;) {
+      const int32_t k = next.fetch_add(1);
+      if (k >= count) return;
+      const h2_status stt = guarded([&] { fn(k, hs[k]->own_stream); });
+      if (stt != H2_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (first == H2_OK) {
+          first = stt;
+          first_msg = "batch item " + std::to_string(k) + ": " + g_err;
+        }
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < workers; ++w) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  for (int32_t k = 0; k < count; ++k) {
+    hipEvent_t done;
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(done, hs[k]->own_stream));
+    HIPCHK(hipStreamWaitEvent(st, done, 0));
+    (void)hipEventDestroy(done);
+  }
+  (void)hipEventDestroy(start);
+  if (first != H2_OK) fail(first, first_msg);
+}
+
 extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
                               int32_t max_iter, void* hip_stream, h2_solve_info* info) {
   return guarded([&] { solve_refined(H, 0, b, x, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info); });
@@ -2000,6 +2058,31 @@ extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs,
 extern "C" h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld, double tol,
                                       int32_t max_iter, void* hip_stream, h2_solve_info* info) {
   return guarded([&] { solve_refined(H, 1, g, lam, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info); });
+}
+
+extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream) {
+  return guarded([&] {
+    run_batch(hs, count, (hipStream_t)hip_stream, [&](int32_t k, hipStream_t s) {
+      try {
+        factor_impl(hs[k], s);
+      } catch (...) {
+        hs[k]->factored = false;
+        throw;
+      }
+    });
+  });
+}
+
+extern "C" h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
+                                    const int64_t* ld, double tol, int32_t max_iter, void* hip_stream,
+                                    h2_solve_info* infos) {
+  return guarded([&] {
+    if (!b || !x || !ld) fail(H2_ERR_ARG, "null pointer");
+    run_batch(hs, count, (hipStream_t)hip_stream, [&](int32_t k, hipStream_t s) {
+      solve_refined(hs[k], 0, b[k], x[k], nrhs, ld[k], tol, max_iter, s, infos ? &infos[k] : nullptr);
+      if (tol <= 0) HIPCHK(hipStreamSynchronize(s));
+    });
+  });
 }
 
 extern "C" h2_status h2_contrast_gradient(h2_handle H, const void* x, const void* g, const void* lam, int32_t nrhs,

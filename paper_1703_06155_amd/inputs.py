@@ -99,18 +99,18 @@ def config(idx: int, nrhs: int = 1) -> Problem:
     raise ValueError("config 3 is a batch: use batch_problems()")
 
 
-def batch_problems(count: int = 64, nrhs: int = 16) -> list:
-    """Independent box problems with sides U{12..32}, problem p seeded 1000+p."""
+def batch_problems(count: int = 64, nrhs: int = 16, sides=(12, 32), leaf: int = 48) -> list:
+    """Independent box problems with sides U{sides[0]..sides[1]}, problem p seeded 1000+p."""
     out = []
     for p in range(count):
         rng = np.random.default_rng(1000 + p)
-        grid = tuple(int(v) for v in rng.integers(12, 33, size=3))
+        grid = tuple(int(v) for v in rng.integers(sides[0], sides[1] + 1, size=3))
         pts = cube_grid(*grid)
         chi = rng.uniform(0.5, 1.5, pts.shape[0])
         dirs = rng.standard_normal((nrhs, 3))
         dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
         out.append(Problem(f"box{p}_{grid[0]}x{grid[1]}x{grid[2]}", grid, pts, chi,
-                           WAVENUMBER, CELL, 48, 1.0, 1e-4, plane_waves(pts, dirs)))
+                           WAVENUMBER, CELL, leaf, 1.0, 1e-4, plane_waves(pts, dirs)))
     return out
 
 

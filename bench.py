@@ -106,6 +106,45 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
 
 
+def batch_leg(torch, h2, I, chunk: int) -> dict:
+    """Independent box problems (sides U{12..32} cells, leaf 48, eps 1e-4, 16 plane-wave
+    right-hand sides each): factor + 16-RHS solve refined to 1e-8, one problem at a time
+    versus batched (h2_factor_batch / h2_solve_batch, graph-replayed sweeps), in chunks
+    of `chunk` problems whose handles are released after their solve."""
+    probs = I.batch_problems(count=64, nrhs=16)
+    n_total = sum(pr.n for pr in probs)
+
+    def run(batched: bool) -> float:
+        elapsed = 0.0
+        for c0 in range(0, len(probs), chunk):
+            part = probs[c0:c0 + chunk]
+            hs = [h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps) for pr in part]
+            rhs = [torch.from_numpy(pr.rhs.copy()).cuda() for pr in part]
+            for G in hs:
+                G.set_sweep_graph(batched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if batched:
+                h2.factor_batch(hs)
+                h2.solve_batch(hs, rhs, tol=1e-8, max_iter=20)
+            else:
+                for G, b in zip(hs, rhs):
+                    G.factor()
+                    G.solve(b, tol=1e-8, max_iter=20)
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            for G in hs:
+                G.close()
+        return elapsed
+
+    t_seq = run(False)
+    t_bat = run(True)
+    return {"workload": "64 box problems, sides U{12..32}, leaf 48, eps 1e-4, 16 RHS each, refined to 1e-8",
+            "unknowns": n_total, "chunk": chunk, "sequential_s": t_seq, "batched_s": t_bat,
+            "sequential_unknowns_per_s": n_total / t_seq, "batched_unknowns_per_s": n_total / t_bat,
+            "speedup": t_seq / t_bat}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", action="store_true", help="also time the 64-problem batching workload")
+    ap.add_argument("--batch-chunk", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
     args = ap.parse_args()
@@ -226,6 +267,9 @@ def main():
         "levels": stats.tolist(),
         "roofline": roof,
     }
+    if args.batch:
+        G.close()
+        out["batch"] = batch_leg(torch, h2, I, args.batch_chunk)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

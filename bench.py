@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", action="store_true", help="also time the 64-problem batching workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batching leg")
     ap.add_argument("--batch-chunk", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
@@ -267,7 +267,7 @@ def main():
         "levels": stats.tolist(),
         "roofline": roof,
     }
-    if args.batch:
+    if not args.no_batch:
         G.close()
         out["batch"] = batch_leg(torch, h2, I, args.batch_chunk)
     if not args.no_cpu_baseline:

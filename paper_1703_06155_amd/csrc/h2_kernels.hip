@@ -1200,20 +1200,23 @@ void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int si
 // Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n] (eqs. 9-11),
 // then explicit L^-1 P and U^-1 (ld rmax = n - k) by in-place triangular
 // inversion.  F lives in LDS up to LU_LDS_MAX, else in the cluster's scratch.
-constexpr int LU_LDS_MAX = 96;
+constexpr int LU_LDS_MAX = 100;
 
 __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2* scratch, int rm) {
   __shared__ double2 sF[LU_LDS_MAX * LU_LDS_MAX];
-  __shared__ int perm[STEP0_DMAX];
-  __shared__ double2 tmp[STEP0_DMAX];
+  __shared__ double2 sT[LU_LDS_MAX];
+  __shared__ int16_t perm[STEP0_DMAX];
   __shared__ int s_piv;
   __shared__ double s_pv;
+  static_assert(STEP0_DMAX <= 32767, "pivot indices are 16-bit");
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (r <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
-  double2* F = (r <= LU_LDS_MAX) ? sF : scratch + (int64_t)blockIdx.x * rm * rm;
+  const bool in_lds = r <= LU_LDS_MAX;
+  double2* F = in_lds ? sF : scratch + (int64_t)blockIdx.x * ((int64_t)rm * rm + rm);
+  double2* tmp = in_lds ? sT : F + (int64_t)rm * rm;
   for (int e = tid; e < r * r; e += blockDim.x) {
     const int a = e % r, b = e / r;
     F[e] = Z[kt + a + (int64_t)(kt + b) * n];
@@ -1259,7 +1262,7 @@ __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2*
         F[pj + b * r] = t;
       }
       if (tid == 0) {
-        const int t = perm[j];
+        const int16_t t = perm[j];
         perm[j] = perm[pj];
         perm[pj] = t;
       }
@@ -2300,6 +2303,41 @@ void launch_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y
 // ===========================================================================
 // H^2 matrix-vector product pieces
 // ===========================================================================
+// Block-row GEMV y[0:m] = sum over e of M_e x_e (M_e column-major m x n_e with
+// leading dimension m): lanes own rows, the four wavefronts take interleaved
+// blocks, eight loads in flight per lane; partial sums meet in LDS.
+template <typename BlockOf>
+__device__ __forceinline__ void blockrow_gemv(int m, int e0, int e1, BlockOf blk, double2* y) {
+  __shared__ double2 red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r0 = 0; r0 < m; r0 += 64) {
+    const int row = r0 + lane;
+    double2 acc = make_double2(0, 0);
+    if (row < m) {
+      for (int e = e0 + w; e < e1; e += 4) {
+        const double2* M;
+        const double2* xs;
+        int ns;
+        blk(e, M, xs, ns);
+        M += row;
+        int q = 0;
+        for (; q + 7 < ns; q += 8) {
+          double2 a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u] = M[(int64_t)(q + u) * m];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = cadd(acc, cmul(a[u], xs[q + u]));
+        }
+        for (; q < ns; ++q) acc = cadd(acc, cmul(M[(int64_t)q * m], xs[q]));
+      }
+    }
+    red[w][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64 && row < m) y[row] = cadd(cadd(red[0][lane], red[1][lane]), cadd(red[2][lane], red[3][lane]));
+    __syncthreads();
+  }
+}
+
 // y_t = sum_{s in near(t)} Z_ts x_s for leaf clusters (row-cluster CSR)
 __global__ void __launch_bounds__(256) k_near_mv(const int32_t* rptr, const int32_t* rcol, const int64_t* boff,
                                                  const double2* blocks, const int64_t* cstart,
@@ -2307,26 +2345,22 @@ __global__ void __launch_bounds__(256) k_near_mv(const int32_t* rptr, const int3
                                                  int nrhs) {
   const int t = blockIdx.x;
   const int m = csize[t];
-  for (int col = 0; col < nrhs; ++col) {
-    for (int row = threadIdx.x; row < m; row += blockDim.x) {
-      double2 acc = make_double2(0, 0);
-      for (int e = rptr[t]; e < rptr[t + 1]; ++e) {
-        const int s = rcol[e];
-        const int ns = csize[s];
-        const double2* Bk = blocks + boff[e] + row;
-        const double2* xs = x + cstart[s] + col * ld;
-        for (int q = 0; q < ns; ++q) acc = cadd(acc, cmul(Bk[(int64_t)q * m], xs[q]));
-      }
-      y[cstart[t] + row + col * ld] = acc;
-    }
-  }
+  for (int col = 0; col < nrhs; ++col)
+    blockrow_gemv(m, rptr[t], rptr[t + 1],
+                  [&](int e, const double2*& M, const double2*& xs, int& ns) {
+                    const int s = rcol[e];
+                    ns = csize[s];
+                    M = blocks + boff[e];
+                    xs = x + cstart[s] + col * ld;
+                  },
+                  y + cstart[t] + col * ld);
 }
 
 void launch_near_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* boff, const double2* blocks,
                     const int64_t* cstart, const int32_t* csize, const double2* x, double2* y, int64_t ld, int nrhs,
                     hipStream_t st) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_near_mv, dim3(nc), dim3(128), 0, st, rptr, rcol, boff, blocks, cstart, csize, x, y, ld,
+  hipLaunchKernelGGL(k_near_mv, dim3(nc), dim3(256), 0, st, rptr, rcol, boff, blocks, cstart, csize, x, y, ld,
                      nrhs);
 }
 
@@ -2365,31 +2399,28 @@ void launch_basis_mv(int nc, const int32_t* rows, const int32_t* cols, const int
 }
 
 // yhat_t = sum_{s in adm(t)} S_ts xhat_s
-__global__ void k_coupling_mv(const int32_t* rptr, const int32_t* rcol, const int64_t* soff, const int32_t* kr,
-                              const int32_t* kc, const double2* S, const int64_t* xoff, const double2* x,
-                              const int64_t* yoff, double2* y, int64_t ld, int nrhs) {
+__global__ void __launch_bounds__(256) k_coupling_mv(const int32_t* rptr, const int32_t* rcol, const int64_t* soff,
+                                                     const int32_t* kr, const int32_t* kc, const double2* S,
+                                                     const int64_t* xoff, const double2* x, const int64_t* yoff,
+                                                     double2* y, int64_t ld, int nrhs) {
   const int t = blockIdx.x;
   const int m = kr[t];
-  for (int col = 0; col < nrhs; ++col) {
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      double2 acc = make_double2(0, 0);
-      for (int e = rptr[t]; e < rptr[t + 1]; ++e) {
-        const int s = rcol[e];
-        const int n = kc[s];
-        const double2* St = S + soff[e] + i;
-        const double2* xs = x + xoff[s] + col * ld;
-        for (int j = 0; j < n; ++j) acc = cadd(acc, cmul(St[(int64_t)j * m], xs[j]));
-      }
-      y[yoff[t] + i + col * ld] = acc;
-    }
-  }
+  for (int col = 0; col < nrhs; ++col)
+    blockrow_gemv(m, rptr[t], rptr[t + 1],
+                  [&](int e, const double2*& M, const double2*& xs, int& ns) {
+                    const int s = rcol[e];
+                    ns = kc[s];
+                    M = S + soff[e];
+                    xs = x + xoff[s] + col * ld;
+                  },
+                  y + yoff[t] + col * ld);
 }
 
 void launch_coupling_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* soff, const int32_t* kr,
                         const int32_t* kc, const double2* S, const int64_t* xoff, const double2* x,
                         const int64_t* yoff, double2* y, int64_t ld, int nrhs, hipStream_t st) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_coupling_mv, dim3(nc), dim3(128), 0, st, rptr, rcol, soff, kr, kc, S, xoff, x, yoff, y, ld,
+  hipLaunchKernelGGL(k_coupling_mv, dim3(nc), dim3(256), 0, st, rptr, rcol, soff, kr, kc, S, xoff, x, yoff, y, ld,
                      nrhs);
 }
 

@@ -691,18 +691,28 @@ void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream
 // ---------------------------------------------------------------------------
 // Scratch per cluster (dm = the level's largest d): G' copy (dm x dm), eigenvector
 // block (dm x dm), tridiagonal work (4 dm doubles per vector): 4 dm^2 complex.
-static_assert(STEP0_DMAX + STEP0_DMAX <= JLDS * JLDS, "d-vectors and reflector scalars share the LDS block");
 
-// Lower Householder tridiagonalization of the Hermitian d x d matrix A (ld d, both
-// triangles kept current): A = Q T Q^H, Q = H_0 ... H_{d-2}, H_j = I - tau_j v_j v_j^H,
-// v_j = [1; A[j+2:, j]] on rows j+1.., off-diagonal beta_j real.
-__device__ void hetrd_lower(double2* A, int d, double2* tau, double* dg, double* off, double2* w, double* red) {
-  const int tid = threadIdx.x;
+
+// Packed lower storage of a Hermitian d x d matrix: element (r, c), r >= c, of
+// column c sits at c d - c (c - 1) / 2 + (r - c).
+__device__ __forceinline__ int pidx(int r, int c, int d) { return c * d - (c * (c - 1)) / 2 + (r - c); }
+__device__ __forceinline__ double2 pget(const double2* P, int r, int c, int d) {
+  return r >= c ? P[pidx(r, c, d)] : cconj(P[pidx(c, r, d)]);
+}
+
+// Lower Householder tridiagonalization of the Hermitian matrix in packed lower
+// storage P: A = Q T Q^H, Q = H_0 ... H_{d-2}, H_j = I - tau_j v_j v_j^H with
+// v_j = [1; P(j+2:, j)] on rows j+1.., off-diagonal beta_j real.  The
+// product A22 v runs on all four wavefronts (interleaved columns, lanes on
+// rows); red2 holds 4 x 64 partial sums.
+__device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double* off, double2* w, double* red,
+                             double2 (*red2)[64]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = 0; j + 1 < d; ++j) {
     double part = 0.0;
-    for (int r = j + 2 + tid; r < d; r += blockDim.x) part += cabs2(A[r + j * d]);
+    for (int r = j + 2 + tid; r < d; r += blockDim.x) part += cabs2(P[pidx(r, j, d)]);
     const double xn2 = block_sum256(part, red);
-    const double2 alpha = A[j + 1 + j * d];
+    const double2 alpha = P[pidx(j + 1, j, d)];
     double2 t = make_double2(0, 0);
     double beta = alpha.x;
     if (xn2 > 0.0 || alpha.y != 0.0) {
@@ -711,47 +721,56 @@ __device__ void hetrd_lower(double2* A, int d, double2* tau, double* dg, double*
       const double2 den = make_double2(alpha.x - beta, alpha.y);
       const double dd = cabs2(den);
       const double2 sc = make_double2(den.x / dd, -den.y / dd);
-      for (int r = j + 2 + tid; r < d; r += blockDim.x) A[r + j * d] = cmul(A[r + j * d], sc);
+      for (int r = j + 2 + tid; r < d; r += blockDim.x) P[pidx(r, j, d)] = cmul(P[pidx(r, j, d)], sc);
     }
     __syncthreads();
     if (tid == 0) {
-      A[j + 1 + j * d] = make_double2(beta, 0.0);
+      P[pidx(j + 1, j, d)] = make_double2(beta, 0.0);
       tau[j] = t;
       off[j] = beta;
     }
     __syncthreads();
-    if (t.x != 0.0 || t.y != 0.0) {
-      // p = tau A22 v over rows j+1..d-1
-      for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-        double2 acc = A[r + (j + 1) * d];  // v[j+1] = 1
-        for (int c = j + 2; c < d; ++c) acc = cadd(acc, cmul(A[r + c * d], A[c + j * d]));
-        w[r] = cmul(t, acc);
-      }
+    if (t.x == 0.0 && t.y == 0.0) continue;
+    // p = tau A22 v over rows j+1..d-1
+    for (int r0 = j + 1; r0 < d; r0 += 64) {
+      const int r = r0 + lane;
+      double2 acc = make_double2(0, 0);
+      if (r < d)
+        for (int c = j + 1 + wv; c < d; c += 4) {
+          const double2 vc = (c == j + 1) ? make_double2(1, 0) : P[pidx(c, j, d)];
+          acc = cadd(acc, cmul(pget(P, r, c, d), vc));
+        }
+      red2[wv][lane] = acc;
       __syncthreads();
-      // c = |tau|^2 v^H A22 v = conj(tau) (v^H p), real
-      double pr = 0.0;
-      for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-        const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
-        pr += cmulc(vr, w[r]).x * t.x + cmulc(vr, w[r]).y * t.y;  // Re(conj(tau) v^H p) term
-      }
-      const double cc = block_sum256(pr, red);
-      for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-        const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
-        w[r] = csub(w[r], make_double2(0.5 * cc * vr.x, 0.5 * cc * vr.y));
-      }
-      __syncthreads();
-      const int m = d - j - 1;
-      for (int e = tid; e < m * m; e += blockDim.x) {
-        const int r = j + 1 + e % m, c = j + 1 + e / m;
-        const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
-        const double2 vc = (c == j + 1) ? make_double2(1, 0) : A[c + j * d];
-        // A22 -= w v^H + v w^H
-        A[r + c * d] = csub(A[r + c * d], cadd(cmul(w[r], cconj(vc)), cmul(vr, cconj(w[c]))));
-      }
+      if (tid < 64 && r < d) w[r] = cmul(t, cadd(cadd(red2[0][lane], red2[1][lane]), cadd(red2[2][lane], red2[3][lane])));
       __syncthreads();
     }
+    // c = Re(conj(tau) v^H p)
+    double pr = 0.0;
+    for (int r = j + 1 + tid; r < d; r += blockDim.x) {
+      const double2 vr = (r == j + 1) ? make_double2(1, 0) : P[pidx(r, j, d)];
+      const double2 z = cmulc(vr, w[r]);
+      pr += z.x * t.x + z.y * t.y;
+    }
+    const double cc = block_sum256(pr, red);
+    for (int r = j + 1 + tid; r < d; r += blockDim.x) {
+      const double2 vr = (r == j + 1) ? make_double2(1, 0) : P[pidx(r, j, d)];
+      w[r] = csub(w[r], make_double2(0.5 * cc * vr.x, 0.5 * cc * vr.y));
+    }
+    __syncthreads();
+    // A22 -= w v^H + v w^H on the lower triangle (waves on columns, lanes on rows)
+    for (int c = j + 1 + wv; c < d; c += 4) {
+      const double2 vc = (c == j + 1) ? make_double2(1, 0) : P[pidx(c, j, d)];
+      const double2 wc = w[c];
+      const int base = pidx(c, c, d) - c;
+      for (int r = c + lane; r < d; r += 64) {
+        const double2 vr = (r == j + 1) ? make_double2(1, 0) : P[pidx(r, j, d)];
+        P[base + r] = csub(P[base + r], cadd(cmul(w[r], cconj(vc)), cmul(vr, cconj(wc))));
+      }
+    }
+    __syncthreads();
   }
-  for (int j = tid; j < d; j += blockDim.x) dg[j] = A[j + j * d].x;
+  for (int j = tid; j < d; j += blockDim.x) dg[j] = P[pidx(j, j, d)].x;
   __syncthreads();
 }
 
@@ -920,9 +939,12 @@ __device__ void tri_eig_targets(const double* dg, const double* off, int d, doub
 }
 
 // Step 0 eigen-decomposition of G' = B_perp^H H B_perp, rank decision, Q~[:, 0:k] = B.
+constexpr int STEP0_PACK_LDS = 120;  // packed Hermitian matrices up to this order live in LDS
+
 __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, double2* scratch, int dm) {
-  __shared__ double2 sA[JLDS * JLDS];
-  __shared__ double2 sU[JLDS * JLDS];
+  __shared__ double2 sP[STEP0_PACK_LDS * (STEP0_PACK_LDS + 1) / 2];
+  __shared__ double2 sU[2 * STEP0_DMAX];
+  __shared__ double2 red2[4][64];
   __shared__ double lam[STEP0_DMAX];
   const int64_t stride = 4 * (int64_t)dm * dm;
   __shared__ double red[4];
@@ -947,30 +969,32 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
     if (forced) {
       skip = v.forced[i] - k <= 0;
     } else {
-      double2* M = (d <= JLDS) ? sA : scratch + (int64_t)blockIdx.x * stride;
+      double2* M = (d <= STEP0_PACK_LDS) ? sP : scratch + (int64_t)blockIdx.x * stride;  // packed lower
       for (int e = tid; e < d * d; e += blockDim.x) {
         const int r = e % d, q = e / d;
+        if (r < q) continue;
         const double2 gv = Gp[e];
-        M[e] = (r == q) ? make_double2(tau0 * tau0 - gv.x, 0.0) : make_double2(-gv.x, -gv.y);
+        M[pidx(r, q, d)] = (r == q) ? make_double2(tau0 * tau0 - gv.x, 0.0) : make_double2(-gv.x, -gv.y);
       }
       __syncthreads();
       skip = tau0 > 0.0;
       for (int j = 0; j < d && skip; ++j) {
-        const double piv = M[j + j * d].x;
+        const double piv = M[pidx(j, j, d)].x;
         if (!(piv > 0.0)) {
           skip = false;
           break;
         }
         const double ljj = sqrt(piv);
         for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-          M[r + j * d].x /= ljj;
-          M[r + j * d].y /= ljj;
+          const int q = pidx(r, j, d);
+          M[q].x /= ljj;
+          M[q].y /= ljj;
         }
         __syncthreads();
-        const int rem = d - j - 1;
-        for (int e = tid; e < rem * rem; e += blockDim.x) {
-          const int r = j + 1 + e % rem, q = j + 1 + e / rem;
-          if (q <= r) M[r + q * d] = csub(M[r + q * d], cmul(M[r + j * d], cconj(M[q + j * d])));
+        for (int q = j + 1 + (tid >> 6); q < d; q += 4) {
+          const double2 lq = cconj(M[pidx(q, j, d)]);
+          const int base = pidx(q, q, d) - q;
+          for (int r = q + (tid & 63); r < d; r += 64) M[base + r] = csub(M[base + r], cmul(M[pidx(r, j, d)], lq));
         }
         __syncthreads();
       }
@@ -983,9 +1007,9 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
         v.margins[2 * i + 1] = -1.0;  // sigma_1 / tau < 1, not evaluated
       }
     } else {
-      // working copy of G' (LDS up to 64, else the cluster's scratch)
+      // working copy of G' in packed lower storage (LDS up to STEP0_PACK_LDS, else the cluster's scratch)
       double2* scr = scratch + (int64_t)blockIdx.x * stride;
-      double2* A = (d <= JLDS) ? sA : scr;
+      double2* A = (d <= STEP0_PACK_LDS) ? sP : scr;
       double2* X = scr + (int64_t)dm * dm;                 // d x d: eigenvector block, then complement input
       double* work = (double*)(scr + 2 * (int64_t)dm * dm);  // per-vector tridiagonal work (4 dm doubles)
       double2* wv = sU;                                    // d-vector scratch
@@ -993,9 +1017,12 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
       double* dg = lam;                                    // reuse: diag, then eigenvalues
       __shared__ double off[STEP0_DMAX], eig[STEP0_DMAX];
       __shared__ double bounds[2];
-      for (int e = tid; e < d * d; e += blockDim.x) A[e] = Gp[e];
+      for (int e = tid; e < d * d; e += blockDim.x) {
+        const int r = e % d, q = e / d;
+        if (r >= q) A[pidx(r, q, d)] = Gp[e];
+      }
       __syncthreads();
-      hetrd_lower(A, d, tauv, dg, off, wv, red);
+      hetrd_packed(A, d, tauv, dg, off, wv, red, red2);
       // Gershgorin interval and pivot floor
       if (tid == 0) {
         double lo = 1e300, hi = -1e300, emax = 0.0;
@@ -1065,14 +1092,14 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
             double2* x = X + (int64_t)cidx * d;
             double2 sacc = make_double2(0, 0);
             for (int r = j + 1 + lane; r < d; r += 64) {
-              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[pidx(r, j, d)];
               sacc = cadd(sacc, cmulc(vr, x[r]));
             }
             sacc.x = wave_sum(sacc.x);
             sacc.y = wave_sum(sacc.y);
             const double2 f = cmul(t, sacc);
             for (int r = j + 1 + lane; r < d; r += 64) {
-              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[r + j * d];
+              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[pidx(r, j, d)];
               x[r] = csub(x[r], cmul(vr, f));
             }
           }

@@ -693,26 +693,70 @@ void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream
 // block (dm x dm), tridiagonal work (4 dm doubles per vector): 4 dm^2 complex.
 
 
-// Packed lower storage of a Hermitian d x d matrix: element (r, c), r >= c, of
-// column c sits at c d - c (c - 1) / 2 + (r - c).
+// ---------------------------------------------------------------------------
+// Step 0 (Section 3.2, the basis extension by the fill-ins).  One workgroup of
+// S0_NT threads per cluster; G' (d x d Hermitian) is held in packed lower
+// storage, in LDS up to order STEP0_PACK_LDS, else in the cluster's scratch.
+// ---------------------------------------------------------------------------
+constexpr int S0_NT = 1024, S0_NW = S0_NT / 64;
+constexpr int STEP0_PACK_LDS = 120;
+constexpr int S0_PACK = STEP0_PACK_LDS * (STEP0_PACK_LDS + 1) / 2;  // double2 slots of the LDS matrix region
+static_assert(STEP0_DMAX % 64 == 0 && STEP0_DMAX <= 512, "d-vectors are spread over at most eight elements per lane");
+
+// Packed lower storage: element (r, c), r >= c, at c d - c (c - 1) / 2 + (r - c).
 __device__ __forceinline__ int pidx(int r, int c, int d) { return c * d - (c * (c - 1)) / 2 + (r - c); }
-__device__ __forceinline__ double2 pget(const double2* P, int r, int c, int d) {
-  return r >= c ? P[pidx(r, c, d)] : cconj(P[pidx(c, r, d)]);
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// Sum / maximum over the workgroup's wavefronts in a fixed order (the same value in every thread).
+__device__ __forceinline__ double s0_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < S0_NW; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ double s0_max(double v, double* red) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int w = 1; w < S0_NW; ++w) s = fmax(s, red[w]);
+  __syncthreads();
+  return s;
 }
 
-// Lower Householder tridiagonalization of the Hermitian matrix in packed lower
-// storage P: A = Q T Q^H, Q = H_0 ... H_{d-2}, H_j = I - tau_j v_j v_j^H with
-// v_j = [1; P(j+2:, j)] on rows j+1.., off-diagonal beta_j real.  The
-// product A22 v runs on all four wavefronts (interleaved columns, lanes on
-// rows); red2 holds 4 x 64 partial sums.
-__device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double* off, double2* w, double* red,
-                             double2 (*red2)[64]) {
+// Lower Householder tridiagonalization A = Q T Q^H of the Hermitian matrix in
+// packed lower storage P: Q = H_0 ... H_{d-2}, H_j = I - tau_j v_j v_j^H,
+// v_j = [1; P(j+2:d, j)] on rows j+1..d-1, real off-diagonal beta_j.  Every
+// wavefront forms v_j in registers (element r = lane + 64 q) from the same data
+// in the same order, so the scalars agree bit for bit without a barrier; the
+// product tau A22 v runs a row per wavefront (lanes on columns), the rank-2
+// update a column per wavefront (lanes on rows).  ws and vs are d-vectors.
+template <int NQ>
+__device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double* off, double2* ws, double2* vs) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int j = 0; j + 1 < d; ++j) {
-    double part = 0.0;
-    for (int r = j + 2 + tid; r < d; r += blockDim.x) part += cabs2(P[pidx(r, j, d)]);
-    const double xn2 = block_sum256(part, red);
-    const double2 alpha = P[pidx(j + 1, j, d)];
+    const int cj = pidx(j, j, d) - j;  // P[cj + r] = A(r, j) for r >= j
+    double2 v[NQ];
+    double xn2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = lane + 64 * q;
+      v[q] = (r > j + 1 && r < d) ? P[cj + r] : make_double2(0, 0);
+      xn2 += cabs2(v[q]);
+    }
+    xn2 = wave_sum(xn2);
+    const double2 alpha = P[cj + j + 1];
     double2 t = make_double2(0, 0);
     double beta = alpha.x;
     if (xn2 > 0.0 || alpha.y != 0.0) {
@@ -721,51 +765,79 @@ __device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double
       const double2 den = make_double2(alpha.x - beta, alpha.y);
       const double dd = cabs2(den);
       const double2 sc = make_double2(den.x / dd, -den.y / dd);
-      for (int r = j + 2 + tid; r < d; r += blockDim.x) P[pidx(r, j, d)] = cmul(P[pidx(r, j, d)], sc);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[q] = cmul(v[q], sc);
     }
-    __syncthreads();
     if (tid == 0) {
-      P[pidx(j + 1, j, d)] = make_double2(beta, 0.0);
       tau[j] = t;
       off[j] = beta;
     }
-    __syncthreads();
-    if (t.x == 0.0 && t.y == 0.0) continue;
-    // p = tau A22 v over rows j+1..d-1
-    for (int r0 = j + 1; r0 < d; r0 += 64) {
-      const int r = r0 + lane;
-      double2 acc = make_double2(0, 0);
-      if (r < d)
-        for (int c = j + 1 + wv; c < d; c += 4) {
-          const double2 vc = (c == j + 1) ? make_double2(1, 0) : P[pidx(c, j, d)];
-          acc = cadd(acc, cmul(pget(P, r, c, d), vc));
+    if (t.x == 0.0 && t.y == 0.0) continue;  // column j is already [beta; 0]: nothing written, no barrier needed
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (lane + 64 * q == j + 1) v[q] = make_double2(1, 0);
+    if (wv == 0)
+      for (int q = 0; q < NQ; ++q) {
+        const int r = lane + 64 * q;
+        if (r > j && r < d) vs[r] = v[q];
+      }
+    // ws = tau A22 v, two rows per wavefront step
+    for (int r = j + 1 + wv; r < d; r += 2 * S0_NW) {
+      const int r2 = r + S0_NW;
+      const int cr = pidx(r, r, d) - r, cr2 = pidx(r2 < d ? r2 : r, r2 < d ? r2 : r, d) - (r2 < d ? r2 : r);
+      double2 a1 = make_double2(0, 0), a2 = make_double2(0, 0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c = lane + 64 * q;
+        if (c > j && c < d) {
+          const double2 e1 = c <= r ? P[pidx(r, c, d)] : cconj(P[cr + c]);
+          a1 = cadd(a1, cmul(e1, v[q]));
+          if (r2 < d) {
+            const double2 e2 = c <= r2 ? P[pidx(r2, c, d)] : cconj(P[cr2 + c]);
+            a2 = cadd(a2, cmul(e2, v[q]));
+          }
         }
-      red2[wv][lane] = acc;
-      __syncthreads();
-      if (tid < 64 && r < d) w[r] = cmul(t, cadd(cadd(red2[0][lane], red2[1][lane]), cadd(red2[2][lane], red2[3][lane])));
-      __syncthreads();
+      }
+      a1.x = wave_sum(a1.x);
+      a1.y = wave_sum(a1.y);
+      a2.x = wave_sum(a2.x);
+      a2.y = wave_sum(a2.y);
+      if (lane == 0) {
+        ws[r] = cmul(t, a1);
+        if (r2 < d) ws[r2] = cmul(t, a2);
+      }
     }
-    // c = Re(conj(tau) v^H p)
+    __syncthreads();
+    // w = ws - (Re(conj(tau) v^H ws) / 2) v, each wavefront for its own lanes
+    double2 w[NQ];
     double pr = 0.0;
-    for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-      const double2 vr = (r == j + 1) ? make_double2(1, 0) : P[pidx(r, j, d)];
-      const double2 z = cmulc(vr, w[r]);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = lane + 64 * q;
+      w[q] = (r > j && r < d) ? ws[r] : make_double2(0, 0);
+      const double2 z = cmulc(v[q], w[q]);
       pr += z.x * t.x + z.y * t.y;
     }
-    const double cc = block_sum256(pr, red);
-    for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-      const double2 vr = (r == j + 1) ? make_double2(1, 0) : P[pidx(r, j, d)];
-      w[r] = csub(w[r], make_double2(0.5 * cc * vr.x, 0.5 * cc * vr.y));
+    const double hc = 0.5 * wave_sum(pr);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) w[q] = csub(w[q], make_double2(hc * v[q].x, hc * v[q].y));
+    if (wv == 0) {
+      for (int q = 0; q < NQ; ++q) {
+        const int r = lane + 64 * q;
+        if (r > j + 1 && r < d) P[cj + r] = v[q];
+      }
+      if (lane == 0) P[cj + j + 1] = make_double2(beta, 0.0);
     }
-    __syncthreads();
-    // A22 -= w v^H + v w^H on the lower triangle (waves on columns, lanes on rows)
-    for (int c = j + 1 + wv; c < d; c += 4) {
-      const double2 vc = (c == j + 1) ? make_double2(1, 0) : P[pidx(c, j, d)];
-      const double2 wc = w[c];
-      const int base = pidx(c, c, d) - c;
-      for (int r = c + lane; r < d; r += 64) {
-        const double2 vr = (r == j + 1) ? make_double2(1, 0) : P[pidx(r, j, d)];
-        P[base + r] = csub(P[base + r], cadd(cmul(w[r], cconj(vc)), cmul(vr, cconj(wc))));
+    // A22 -= w v^H + v w^H on the lower triangle, a column per wavefront
+    for (int c = j + 1 + wv; c < d; c += S0_NW) {
+      const double2 vc = vs[c], wsc = ws[c];
+      const double2 wc = csub(wsc, make_double2(hc * vc.x, hc * vc.y));
+      const int cc = pidx(c, c, d) - c;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int r = lane + 64 * q;
+        if (r >= c && r < d)
+          P[cc + r] = csub(P[cc + r], cadd(cmul(w[q], cconj(vc)), cmul(v[q], cconj(wc))));
       }
     }
     __syncthreads();
@@ -788,121 +860,44 @@ __device__ int sturm_count(const double* dg, const double* off, int d, double si
   return cnt;
 }
 
-// one solve of (T - lam I) y = b in place (tridiagonal LU with partial pivoting);
-// D, DU, DL are work arrays of length d; tiny pivots are replaced by +-pivmin.
-__device__ void tri_solve(const double* dg, const double* off, int d, double lam, double* b, double* D, double* DU,
-                          double* DL, double pivmin) {
-  for (int i = 0; i < d; ++i) {
-    D[i] = dg[i] - lam;
-    DU[i] = (i + 1 < d) ? off[i] : 0.0;
-    DL[i] = (i + 1 < d) ? off[i] : 0.0;
-  }
-  double* DU2 = DL;  // sub-diagonal storage is reused for the second super-diagonal after a swap
-  for (int i = 0; i + 1 < d; ++i) {
-    const double sub = DL[i];
-    if (fabs(D[i]) >= fabs(sub)) {
-      if (fabs(D[i]) < pivmin) D[i] = D[i] >= 0 ? pivmin : -pivmin;
-      const double f = sub / D[i];
-      D[i + 1] -= f * DU[i];
-      b[i + 1] -= f * b[i];
-      DU2[i] = 0.0;
-    } else {
-      const double f = D[i] / sub;
-      D[i] = sub;
-      const double tmp = D[i + 1];
-      D[i + 1] = DU[i] - f * tmp;
-      if (i + 2 < d) {
-        DU2[i] = DU[i + 1];
-        DU[i + 1] = -f * DU[i + 1];
-      } else {
-        DU2[i] = 0.0;
+// The same count without divisions, for a T scaled to norm <= 1 (diagonal dn,
+// squared off-diagonal e2): sign changes of the leading principal minors
+// p_i = (dn_i - x) p_{i-1} - e2_{i-1} p_{i-2}, kept in range by exact
+// power-of-two rescaling; a zero minor takes the sign opposite to its
+// predecessor (the limit of a negative pivot).
+__device__ int sturm_count_minors(const double* dn, const double* e2, int d, double x) {
+  double p0 = 1.0, p1 = dn[0] - x;
+  bool n1 = !(p1 > 0.0);
+  int cnt = n1;
+  for (int i = 1; i < d; ++i) {
+    const double p2 = (dn[i] - x) * p1 - e2[i - 1] * p0;
+    const bool n2 = (p2 == 0.0) ? !n1 : (p2 < 0.0);
+    cnt += (n2 != n1);
+    p0 = p1;
+    p1 = p2;
+    n1 = n2;
+    if ((i & 3) == 0) {
+      const double m = fmax(fabs(p0), fabs(p1));
+      if (m > 0x1p256) {
+        p0 *= 0x1p-512;
+        p1 *= 0x1p-512;
+      } else if (m < 0x1p-256) {
+        p0 *= 0x1p512;
+        p1 *= 0x1p512;
       }
-      DU[i] = tmp;
-      const double tb = b[i];
-      b[i] = b[i + 1];
-      b[i + 1] = tb - f * b[i + 1];
     }
   }
-  if (fabs(D[d - 1]) < pivmin) D[d - 1] = D[d - 1] >= 0 ? pivmin : -pivmin;
-  b[d - 1] /= D[d - 1];
-  if (d > 1) b[d - 2] = (b[d - 2] - DU[d - 2] * b[d - 1]) / D[d - 2];
-  for (int i = d - 3; i >= 0; --i) b[i] = (b[i] - DU[i] * b[i + 1] - DU2[i] * b[i + 2]) / D[i];
+  return cnt;
 }
 
-// Householder QR of the p columns of X (d x p, ld d, overwritten by the
-// reflectors): E (d x d, ld d) = H_0 ... H_{p-1}, whose first p columns are an
-// orthonormal basis of span(X) and the rest its orthonormal complement.
-__device__ void householder_basis(double2* X, int d, int p, double2* E, double2* tau, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int e = tid; e < d * d; e += blockDim.x) {
-    const int r = e % d, c = e / d;
-    E[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < p; ++j) {
-    double part = 0.0;
-    for (int r = j + 1 + tid; r < d; r += blockDim.x) part += cabs2(X[r + j * d]);
-    const double sigma = block_sum256(part, red);
-    const double2 alpha = X[j + j * d];
-    double2 t = make_double2(0, 0);
-    if (sigma > 0.0 || alpha.y != 0.0) {
-      const double beta = -copysign(sqrt(cabs2(alpha) + sigma), alpha.x);
-      t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-      const double2 den = make_double2(alpha.x - beta, alpha.y);
-      const double dd = cabs2(den);
-      const double2 sc = make_double2(den.x / dd, -den.y / dd);
-      __syncthreads();
-      for (int r = j + 1 + tid; r < d; r += blockDim.x) X[r + j * d] = cmul(X[r + j * d], sc);
-      if (tid == 0) X[j + j * d] = make_double2(beta, 0.0);
-    }
-    if (tid == 0) tau[j] = t;
-    __syncthreads();
-    if (t.x != 0.0 || t.y != 0.0) {
-      for (int c = j + 1 + wv; c < p; c += 4) {
-        double2 w = make_double2(0, 0);
-        for (int r = j + lane; r < d; r += 64) {
-          const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
-          w = cadd(w, cmulc(vr, X[r + c * d]));
-        }
-        w.x = wave_sum(w.x);
-        w.y = wave_sum(w.y);
-        const double2 f = cmul(cconj(t), w);
-        for (int r = j + lane; r < d; r += 64) {
-          const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
-          X[r + c * d] = csub(X[r + c * d], cmul(vr, f));
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int j = p - 1; j >= 0; --j) {
-    const double2 t = tau[j];
-    if (t.x == 0.0 && t.y == 0.0) continue;
-    for (int c = wv; c < d; c += 4) {
-      double2 w = make_double2(0, 0);
-      for (int r = j + lane; r < d; r += 64) {
-        const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
-        w = cadd(w, cmulc(vr, E[r + c * d]));
-      }
-      w.x = wave_sum(w.x);
-      w.y = wave_sum(w.y);
-      const double2 f = cmul(t, w);
-      for (int r = j + lane; r < d; r += 64) {
-        const double2 vr = (r == j) ? make_double2(1, 0) : X[r + j * d];
-        E[r + c * d] = csub(E[r + c * d], cmul(vr, f));
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Eigenvalues of the symmetric tridiagonal T (diagonal dg, off-diagonal off) with
-// ascending indices ks[0..cnt), out[t] for target t.  Multisection: groups of G
-// lanes of one wavefront (G a power of two) bracket one eigenvalue, each lane
-// placing one Sturm-count probe per round, so a round narrows the bracket G + 1
-// fold; every thread of the block calls this.
-__device__ void tri_eig_targets(const double* dg, const double* off, int d, double glo, double ghi, double pivmin,
-                                const int* ks, int cnt, double* out) {
+// Eigenvalues of the scaled tridiagonal (dn, e2, spectrum inside [glo, ghi])
+// with ascending indices ks[0..cnt), out[t] for target t.  Multisection: groups
+// of G lanes of one wavefront (G a power of two) bracket one eigenvalue, each
+// lane placing one Sturm-count probe per round, so a round narrows the bracket
+// G + 1 fold; stops at a bracket of a few units in the last place of the
+// eigenvalue or of the norm.  Every thread of the workgroup calls this.
+__device__ void tri_eig_targets(const double* dn, const double* e2, int d, double glo, double ghi, const int* ks,
+                                int cnt, double* out) {
   int G = 64;
   while (G > 1 && (int)(blockDim.x / G) < cnt) G >>= 1;
   const int ngroups = blockDim.x / G;
@@ -912,11 +907,11 @@ __device__ void tri_eig_targets(const double* dg, const double* off, int d, doub
   for (int t0 = 0; t0 < cnt; t0 += ngroups) {
     const int t = t0 + gid;
     const int k = t < cnt ? ks[t] : 0;
-    double lo = glo - 2.2e-16 * fabs(glo) - pivmin, hi = ghi + 2.2e-16 * fabs(ghi) + pivmin;
+    double lo = glo - 2.2e-16 * fabs(glo) - 0x1p-60, hi = ghi + 2.2e-16 * fabs(ghi) + 0x1p-60;
     bool done = t >= cnt;
     while (__ballot(!done) != 0ull) {
       const double x = lo + (hi - lo) * (double)(m + 1) / (double)(G + 1);
-      const bool ge = !done && sturm_count(dg, off, d, x, pivmin) >= k + 1;
+      const bool ge = !done && sturm_count_minors(dn, e2, d, x) >= k + 1;
       const unsigned long long mask = (__ballot(ge) >> gbase) & gmask;
       if (!done) {
         double nlo, nhi;
@@ -931,26 +926,106 @@ __device__ void tri_eig_targets(const double* dg, const double* off, int d, doub
         if ((nlo == lo && nhi == hi) || !(nhi > nlo)) done = true;
         lo = nlo;
         hi = nhi;
-        if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) done = true;
+        if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 0x1p-52) done = true;
       }
     }
     if (t < cnt && m == 0) out[t] = 0.5 * (lo + hi);
   }
 }
 
-// Step 0 eigen-decomposition of G' = B_perp^H H B_perp, rank decision, Q~[:, 0:k] = B.
-constexpr int STEP0_PACK_LDS = 120;  // packed Hermitian matrices up to this order live in LDS
+// Inverse iteration for one eigenvector of T (dg, off) with shift lam: T - lam I
+// = P L U with partial pivoting once, then three solves from a fixed start
+// vector (each normalised; the scale is folded into the next forward pass), the
+// result written to y (length d).  The factors live in six interleaved arrays of
+// the caller's work area, element i of array a at W[(a d + i) nb], so that
+// neighbouring threads (vectors) touch neighbouring words; the recurrences run in
+// registers with the next operands loaded a step ahead.
+__device__ void tri_inverse_iteration(const double* dg, const double* off, int d, double lam, double pivmin,
+                                      int seed, double* W, int nb, double2* y) {
+  double* rD = W;
+  double* DU = W + (size_t)d * nb;
+  double* DU2 = DU + (size_t)d * nb;
+  double* F = DU2 + (size_t)d * nb;
+  double* S = F + (size_t)d * nb;
+  double* b = S + (size_t)d * nb;
+  // factorization
+  double cd = dg[0] - lam, cdu = d > 1 ? off[0] : 0.0;
+  for (int i = 0; i + 1 < d; ++i) {
+    const double sub = off[i], nd = dg[i + 1] - lam, ndu = (i + 2 < d) ? off[i + 1] : 0.0;
+    const size_t o = (size_t)i * nb;
+    if (fabs(cd) >= fabs(sub)) {
+      if (fabs(cd) < pivmin) cd = cd >= 0 ? pivmin : -pivmin;
+      const double f = sub / cd;
+      rD[o] = 1.0 / cd;
+      DU[o] = cdu;
+      DU2[o] = 0.0;
+      F[o] = f;
+      S[o] = 0.0;
+      cd = nd - f * cdu;
+      cdu = ndu;
+    } else {
+      const double f = cd / sub;
+      rD[o] = 1.0 / sub;
+      DU[o] = nd;
+      DU2[o] = ndu;
+      F[o] = f;
+      S[o] = 1.0;
+      cd = cdu - f * nd;
+      cdu = -f * ndu;
+    }
+  }
+  if (fabs(cd) < pivmin) cd = cd >= 0 ? pivmin : -pivmin;
+  rD[(size_t)(d - 1) * nb] = 1.0 / cd;
+  double scale = 1.0;
+  for (int it = 0; it < 3; ++it) {
+    // forward: b <- L^-1 P^T (scale b)
+    auto start = [&](int r) { return 1.0 + 0.37 * (double)((r * (seed + 3) + 7 * seed) % 11) / 11.0; };
+    double cur = it == 0 ? start(0) : b[0] * scale;
+    double nxt = d > 1 ? (it == 0 ? start(1) : b[nb] * scale) : 0.0;
+    for (int i = 0; i + 1 < d; ++i) {
+      const size_t o = (size_t)i * nb;
+      const double f = F[o];
+      const bool sw = S[o] != 0.0;
+      const double after = (i + 2 < d) ? (it == 0 ? start(i + 2) : b[o + 2 * (size_t)nb] * scale) : 0.0;
+      if (!sw) {
+        b[o] = cur;
+        cur = nxt - f * cur;
+      } else {
+        b[o] = nxt;
+        cur = cur - f * nxt;
+      }
+      nxt = after;
+    }
+    // backward: U x = b
+    double x1 = cur * rD[(size_t)(d - 1) * nb], x2 = 0.0;
+    b[(size_t)(d - 1) * nb] = x1;
+    double nrm = x1 * x1;
+    for (int i = d - 2; i >= 0; --i) {
+      const size_t o = (size_t)i * nb;
+      const double xi = (b[o] - DU[o] * x1 - DU2[o] * x2) * rD[o];
+      b[o] = xi;
+      nrm += xi * xi;
+      x2 = x1;
+      x1 = xi;
+    }
+    scale = 1.0 / sqrt(nrm);
+  }
+  for (int i = 0; i < d; ++i) y[i] = make_double2(b[(size_t)i * nb] * scale, 0.0);
+}
 
-__global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, double2* scratch, int dm) {
-  __shared__ double2 sP[STEP0_PACK_LDS * (STEP0_PACK_LDS + 1) / 2];
-  __shared__ double2 sU[2 * STEP0_DMAX];
-  __shared__ double2 red2[4][64];
-  __shared__ double lam[STEP0_DMAX];
+template <int NQ>
+__global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c, double2* scratch, int dm) {
+  __shared__ double2 sP[S0_PACK];
+  __shared__ double2 ws[STEP0_DMAX], vs[STEP0_DMAX], tauv[STEP0_DMAX];
+  __shared__ double dg[STEP0_DMAX], off[STEP0_DMAX], eig[STEP0_DMAX];
+  __shared__ int ks[STEP0_DMAX];
+  __shared__ double red[S0_NW];
+  __shared__ double bounds[4];
+  __shared__ int s_p;
   const int64_t stride = 4 * (int64_t)dm * dm;
-  __shared__ double red[4];
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], k = v.k[i], d = n - k;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double2* Q = v.Q + v.q_off[i];
   const double2* B = v.B + v.b_off[i];
   for (int e = tid; e < n * k; e += blockDim.x) Q[e] = B[e];
@@ -959,44 +1034,58 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
     double2* W = v.W + v.w_off[i];
     double2* Gp = W + (int64_t)n * n + (int64_t)n * d;
     double2* Up = Gp + (int64_t)d * d;
+    double2* scr = scratch + (int64_t)blockIdx.x * stride;
+    double2* A = (d <= STEP0_PACK_LDS) ? sP : scr;  // packed lower working matrix
     // p = 0 exactly when every eigenvalue of G' is below tau0^2 = (eps_fill nu)^2 (then
-    // sigma_1(W) < eps_fill nu < nu and the threshold tau = eps_fill max(nu, sigma_1) = tau0):
-    // tested by a Cholesky factorization of tau0^2 I - G', which succeeds iff it is
-    // positive definite.  Any orthonormal complement then serves as B~perp: U' = I.
+    // sigma_1(W) < eps_fill nu < nu and the threshold tau = eps_fill max(nu, sigma_1) = tau0).
+    // G' is positive semidefinite, so a diagonal entry >= tau0^2 rules this out and
+    // ||G'||_F < tau0^2 proves it; otherwise an LDL^H factorization of tau0^2 I - G'
+    // decides (positive pivots iff positive definite).  Any orthonormal complement then
+    // serves as B~perp: U' = I.
     const double tau0 = v.eps_fill * v.nu[i];
+    const double t02 = tau0 * tau0;
     const bool forced = v.forced && v.forced[i] >= 0;
     bool skip;
     if (forced) {
       skip = v.forced[i] - k <= 0;
     } else {
-      double2* M = (d <= STEP0_PACK_LDS) ? sP : scratch + (int64_t)blockIdx.x * stride;  // packed lower
+      double fro = 0.0, gmax = 0.0;
       for (int e = tid; e < d * d; e += blockDim.x) {
-        const int r = e % d, q = e / d;
-        if (r < q) continue;
         const double2 gv = Gp[e];
-        M[pidx(r, q, d)] = (r == q) ? make_double2(tau0 * tau0 - gv.x, 0.0) : make_double2(-gv.x, -gv.y);
+        fro += cabs2(gv);
+        if (e % d == e / d) gmax = fmax(gmax, gv.x);
       }
-      __syncthreads();
-      skip = tau0 > 0.0;
-      for (int j = 0; j < d && skip; ++j) {
-        const double piv = M[pidx(j, j, d)].x;
-        if (!(piv > 0.0)) {
-          skip = false;
-          break;
-        }
-        const double ljj = sqrt(piv);
-        for (int r = j + 1 + tid; r < d; r += blockDim.x) {
-          const int q = pidx(r, j, d);
-          M[q].x /= ljj;
-          M[q].y /= ljj;
-        }
-        __syncthreads();
-        for (int q = j + 1 + (tid >> 6); q < d; q += 4) {
-          const double2 lq = cconj(M[pidx(q, j, d)]);
-          const int base = pidx(q, q, d) - q;
-          for (int r = q + (tid & 63); r < d; r += 64) M[base + r] = csub(M[base + r], cmul(M[pidx(r, j, d)], lq));
+      fro = s0_sum(fro, red);
+      gmax = s0_max(gmax, red);
+      if (!(tau0 > 0.0) || gmax >= t02) {
+        skip = false;
+      } else if (fro < t02 * t02) {
+        skip = true;
+      } else {
+        for (int e = tid; e < d * d; e += blockDim.x) {
+          const int r = e % d, q = e / d;
+          if (r < q) continue;
+          const double2 gv = Gp[e];
+          A[pidx(r, q, d)] = (r == q) ? make_double2(t02 - gv.x, 0.0) : make_double2(-gv.x, -gv.y);
         }
         __syncthreads();
+        skip = true;
+        for (int j = 0; j < d; ++j) {
+          const double piv = A[pidx(j, j, d)].x;
+          if (!(piv > 0.0)) {
+            skip = false;
+            break;
+          }
+          const double rp = 1.0 / piv;
+          const int cj = pidx(j, j, d) - j;
+          for (int q = j + 1 + wv; q < d; q += S0_NW) {
+            const double2 lq = cconj(A[cj + q]);
+            const double2 mq = make_double2(lq.x * rp, lq.y * rp);
+            const int cq = pidx(q, q, d) - q;
+            for (int r = q + lane; r < d; r += 64) A[cq + r] = csub(A[cq + r], cmul(A[cj + r], mq));
+          }
+          __syncthreads();
+        }
       }
       __syncthreads();
     }
@@ -1007,23 +1096,13 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
         v.margins[2 * i + 1] = -1.0;  // sigma_1 / tau < 1, not evaluated
       }
     } else {
-      // working copy of G' in packed lower storage (LDS up to STEP0_PACK_LDS, else the cluster's scratch)
-      double2* scr = scratch + (int64_t)blockIdx.x * stride;
-      double2* A = (d <= STEP0_PACK_LDS) ? sP : scr;
-      double2* X = scr + (int64_t)dm * dm;                 // d x d: eigenvector block, then complement input
-      double* work = (double*)(scr + 2 * (int64_t)dm * dm);  // per-vector tridiagonal work (4 dm doubles)
-      double2* wv = sU;                                    // d-vector scratch
-      double2* tauv = sU + STEP0_DMAX;
-      double* dg = lam;                                    // reuse: diag, then eigenvalues
-      __shared__ double off[STEP0_DMAX], eig[STEP0_DMAX];
-      __shared__ double bounds[2];
       for (int e = tid; e < d * d; e += blockDim.x) {
         const int r = e % d, q = e / d;
         if (r >= q) A[pidx(r, q, d)] = Gp[e];
       }
       __syncthreads();
-      hetrd_packed(A, d, tauv, dg, off, wv, red, red2);
-      // Gershgorin interval and pivot floor
+      hetrd_packed<NQ>(A, d, tauv, dg, off, ws, vs);
+      // Gershgorin interval, pivot floor and the power-of-two scale of T
       if (tid == 0) {
         double lo = 1e300, hi = -1e300, emax = 0.0;
         for (int r = 0; r < d; ++r) {
@@ -1034,19 +1113,26 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
         }
         bounds[0] = lo;
         bounds[1] = hi;
-        red[3] = fmax(emax, 1.0) * 2.2250738585072014e-308 / 2.2e-16;  // pivmin
+        bounds[2] = fmax(emax, 1.0) * 2.2250738585072014e-308 / 2.2e-16;  // pivmin
+        int ex;
+        frexp(fmax(fmax(fabs(lo), fabs(hi)), 1e-300), &ex);
+        bounds[3] = ldexp(1.0, -ex);  // 1 / 2^ex with 2^ex >= max(|lo|, |hi|)
       }
       __syncthreads();
-      const double pivmin = red[3];
-      const double glo = bounds[0], ghi = bounds[1];
-      __shared__ int ks[STEP0_DMAX];
-      __shared__ int s_p;
-      // largest eigenvalue, then the rank decision against tau^2 by one Sturm count
+      const double glo = bounds[0], ghi = bounds[1], pivmin = bounds[2], sinv = bounds[3];
+      double* dn = (double*)ws;  // scaled diagonal and squared off-diagonal
+      double* e2 = dn + STEP0_DMAX;
+      for (int r = tid; r < d; r += blockDim.x) {
+        dn[r] = dg[r] * sinv;
+        const double o = (r + 1 < d) ? off[r] * sinv : 0.0;
+        e2[r] = o * o;
+      }
       if (tid == 0) ks[0] = d - 1;
       __syncthreads();
-      tri_eig_targets(dg, off, d, glo, ghi, pivmin, ks, 1, eig);
+      // largest eigenvalue, then the rank decision against tau^2 by one Sturm count
+      tri_eig_targets(dn, e2, d, glo * sinv, ghi * sinv, ks, 1, eig);
       __syncthreads();
-      const double s1 = sqrt(fmax(eig[0], 0.0));
+      const double s1 = sqrt(fmax(eig[0] / sinv, 0.0));
       const double tau = v.eps_fill * fmax(v.nu[i], s1);
       if (tid == 0) {
         int pp = (tau > 0.0) ? d - sturm_count(dg, off, d, tau * tau, pivmin) : 0;
@@ -1059,55 +1145,165 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
       const int ne = min(p + 1, d);
       for (int j = tid; j < ne; j += blockDim.x) ks[j] = d - 1 - j;
       __syncthreads();
-      tri_eig_targets(dg, off, d, glo, ghi, pivmin, ks, ne, eig);
+      tri_eig_targets(dn, e2, d, glo * sinv, ghi * sinv, ks, ne, eig);
+      __syncthreads();
+      for (int j = tid; j < ne; j += blockDim.x) eig[j] /= sinv;
       __syncthreads();
       if (tid == 0 && v.margins) {
         v.margins[2 * i] = (tau > 0 && p > 0) ? sqrt(fmax(eig[p - 1], 0.0)) / tau : 1e300;
         v.margins[2 * i + 1] = (tau > 0 && p < d) ? sqrt(fmax(eig[p], 0.0)) / tau : 0.0;
       }
+      // eigenvector block X (d x p, ld d) and the inverse-iteration work area: in LDS
+      // behind the packed matrix when they fit, else in the cluster's scratch
+      const int used = (d <= STEP0_PACK_LDS) ? d * (d + 1) / 2 : 0;
+      const int tail = S0_PACK - used;
+      double2* X;
+      double* work;
+      int nb;
+      if (d * p + 3 * d * min(p, 4) <= tail) {
+        X = sP + used;
+        work = (double*)(X + d * p);
+        nb = min(p, (tail - d * p) / (3 * d));
+      } else {
+        X = scr + (int64_t)dm * dm;
+        work = (double*)(scr + 2 * (int64_t)dm * dm);
+        nb = min(p, (int)((4 * (int64_t)dm * dm) / (6 * (int64_t)d)));
+      }
+      nb = max(1, min(nb, (int)blockDim.x));
       // inverse iteration for the p dominant eigenvectors of T (one thread per vector)
       const double tnorm = fmax(fabs(glo), fabs(ghi));
-      for (int j = tid; j < p; j += blockDim.x) {
-        double* b = work + (int64_t)j * 4 * dm;
-        double *D = b + dm, *DU = D + dm, *DL = DU + dm;
-        for (int r = 0; r < d; ++r) b[r] = 1.0 + 0.37 * (double)((r * (j + 3) + 7 * j) % 11) / 11.0;
-        const double lamj = eig[j] + 4.4e-16 * tnorm * (1 + j % 3);
-        for (int it = 0; it < 3; ++it) {
-          tri_solve(dg, off, d, lamj, b, D, DU, DL, fmax(pivmin, 2.2e-16 * tnorm));
-          double nrm = 0.0;
-          for (int r = 0; r < d; ++r) nrm += b[r] * b[r];
-          nrm = 1.0 / sqrt(nrm);
-          for (int r = 0; r < d; ++r) b[r] *= nrm;
-        }
-        for (int r = 0; r < d; ++r) X[r + (int64_t)j * d] = make_double2(b[r], 0.0);
+      for (int j0 = 0; j0 < p; j0 += nb) {
+        const int j = j0 + tid;
+        if (tid < nb && j < p)
+          tri_inverse_iteration(dg, off, d, eig[j] + 4.4e-16 * tnorm * (1 + j % 3), fmax(pivmin, 2.2e-16 * tnorm), j,
+                                work + tid, nb, X + (int64_t)j * d);
+        __syncthreads();
       }
-      __syncthreads();
-      // x = H_0 ... H_{d-2} y for the p vectors (wavefront per vector)
-      {
-        const int lane = tid & 63, wf = tid >> 6;
+      // x = H_0 ... H_{d-2} y, one vector per wavefront, held in registers
+      for (int cidx = wv; cidx < p; cidx += S0_NW) {
+        double2* x = X + (int64_t)cidx * d;
+        double2 xr[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int r = lane + 64 * q;
+          xr[q] = (r < d) ? x[r] : make_double2(0, 0);
+        }
         for (int j = d - 2; j >= 0; --j) {
           const double2 t = tauv[j];
           if (t.x == 0.0 && t.y == 0.0) continue;
-          for (int cidx = wf; cidx < p; cidx += 4) {
-            double2* x = X + (int64_t)cidx * d;
-            double2 sacc = make_double2(0, 0);
-            for (int r = j + 1 + lane; r < d; r += 64) {
-              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[pidx(r, j, d)];
-              sacc = cadd(sacc, cmulc(vr, x[r]));
-            }
-            sacc.x = wave_sum(sacc.x);
-            sacc.y = wave_sum(sacc.y);
-            const double2 f = cmul(t, sacc);
-            for (int r = j + 1 + lane; r < d; r += 64) {
-              const double2 vr = (r == j + 1) ? make_double2(1, 0) : A[pidx(r, j, d)];
-              x[r] = csub(x[r], cmul(vr, f));
-            }
+          const int cj = pidx(j, j, d) - j;
+          double2 vr[NQ];
+          double2 s = make_double2(0, 0);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int r = lane + 64 * q;
+            vr[q] = (r > j && r < d) ? (r == j + 1 ? make_double2(1, 0) : A[cj + r]) : make_double2(0, 0);
+            s = cadd(s, cmulc(vr[q], xr[q]));
           }
-          __syncthreads();
+          s.x = wave_sum(s.x);
+          s.y = wave_sum(s.y);
+          const double2 f = cmul(t, s);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) xr[q] = csub(xr[q], cmul(vr[q], f));
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int r = lane + 64 * q;
+          if (r < d) x[r] = xr[q];
         }
       }
-      // U' = [orthonormal basis of span(X), its complement] from one Householder QR of X
-      householder_basis(X, d, p, Up, tauv, red);
+      __syncthreads();
+      // U' = [orthonormal basis of span(X), its complement] = H'_0 ... H'_{p-1} from a
+      // Householder QR of X.  QR: every wavefront forms the reflector in registers,
+      // the owners update the later columns, one barrier per column.
+      for (int j = 0; j < p; ++j) {
+        double2* xj = X + (int64_t)j * d;
+        double2 vr[NQ];
+        double sg = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int r = lane + 64 * q;
+          vr[q] = (r > j && r < d) ? xj[r] : make_double2(0, 0);
+          sg += cabs2(vr[q]);
+        }
+        sg = wave_sum(sg);
+        const double2 alpha = xj[j];
+        double2 t = make_double2(0, 0);
+        double beta = alpha.x;
+        if (sg > 0.0 || alpha.y != 0.0) {
+          beta = -copysign(sqrt(cabs2(alpha) + sg), alpha.x);
+          t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+          const double2 den = make_double2(alpha.x - beta, alpha.y);
+          const double dd = cabs2(den);
+          const double2 sc = make_double2(den.x / dd, -den.y / dd);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) vr[q] = cmul(vr[q], sc);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (lane + 64 * q == j) vr[q] = make_double2(1, 0);
+        if (t.x != 0.0 || t.y != 0.0) {
+          for (int cc = j + 1 + wv; cc < p; cc += S0_NW) {
+            double2* xc = X + (int64_t)cc * d;
+            double2 s = make_double2(0, 0);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const int r = lane + 64 * q;
+              if (r >= j && r < d) s = cadd(s, cmulc(vr[q], xc[r]));
+            }
+            s.x = wave_sum(s.x);
+            s.y = wave_sum(s.y);
+            const double2 f = cmul(cconj(t), s);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const int r = lane + 64 * q;
+              if (r >= j && r < d) xc[r] = csub(xc[r], cmul(vr[q], f));
+            }
+          }
+        }
+        __syncthreads();
+        if (wv == 0) {
+          for (int q = 0; q < NQ; ++q) {
+            const int r = lane + 64 * q;
+            if (r > j && r < d) xj[r] = vr[q];
+          }
+          if (lane == 0) {
+            xj[j] = make_double2(beta, 0.0);
+            tauv[j] = t;
+          }
+        }
+      }
+      __syncthreads();
+      // columns of E = H'_0 ... H'_{p-1}, one per wavefront in registers
+      for (int cc = wv; cc < d; cc += S0_NW) {
+        double2 er[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) er[q] = make_double2(lane + 64 * q == cc ? 1.0 : 0.0, 0.0);
+        for (int j = min(cc, p - 1); j >= 0; --j) {
+          const double2 t = tauv[j];
+          if (t.x == 0.0 && t.y == 0.0) continue;
+          const double2* xj = X + (int64_t)j * d;
+          double2 vr[NQ];
+          double2 s = make_double2(0, 0);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int r = lane + 64 * q;
+            vr[q] = (r >= j && r < d) ? (r == j ? make_double2(1, 0) : xj[r]) : make_double2(0, 0);
+            s = cadd(s, cmulc(vr[q], er[q]));
+          }
+          s.x = wave_sum(s.x);
+          s.y = wave_sum(s.y);
+          const double2 f = cmul(t, s);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) er[q] = csub(er[q], cmul(vr[q], f));
+        }
+        double2* uc = Up + (int64_t)cc * d;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int r = lane + 64 * q;
+          if (r < d) uc[r] = er[q];
+        }
+      }
     }
   }
   if (v.forced && v.forced[i] >= 0) p = min(max(v.forced[i] - k, 0), d);
@@ -1116,7 +1312,15 @@ __global__ void __launch_bounds__(256) k_step0_eig(LevelView v, ColourTasks c, d
 
 void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, int dm, hipStream_t st) {
   if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_step0_eig, dim3(c.ncl), dim3(256), 0, st, v, c, scratch, dm);
+  // lanes hold d-vectors in NQ registers each: the smallest of 1, 2, 4, 8 with 64 NQ >= dm
+  if (dm <= 64)
+    hipLaunchKernelGGL(k_step0_eig<1>, dim3(c.ncl), dim3(S0_NT), 0, st, v, c, scratch, dm);
+  else if (dm <= 128)
+    hipLaunchKernelGGL(k_step0_eig<2>, dim3(c.ncl), dim3(S0_NT), 0, st, v, c, scratch, dm);
+  else if (dm <= 256)
+    hipLaunchKernelGGL(k_step0_eig<4>, dim3(c.ncl), dim3(S0_NT), 0, st, v, c, scratch, dm);
+  else
+    hipLaunchKernelGGL(k_step0_eig<8>, dim3(c.ncl), dim3(S0_NT), 0, st, v, c, scratch, dm);
 }
 
 // Step 2 projections.  side 0: T = (x in colour ? Q~_x^H : I) Z ; side 1: Z = T (y in colour ? conj(Q~_y) : I)

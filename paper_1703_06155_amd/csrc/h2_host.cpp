@@ -1109,7 +1109,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     if (F.tiles > 1) temp.alloc(temp_max);  // the one-tile levels project in place
     int maxcl = 1;
     for (ColourPlan& C : P.cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
-    lu_scr.alloc((size_t)maxcl * ((size_t)dmax * dmax + dmax) * (dmax > 100 ? 1 : 0) + 1);  // k_lu beyond its LDS size
+    lu_scr.alloc((size_t)maxcl * ((size_t)dmax * dmax + dmax) * (dmax > LU_LDS_MAX ? 1 : 0) + 1);  // k_lu beyond its LDS size
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);

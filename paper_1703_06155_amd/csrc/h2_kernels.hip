@@ -1429,11 +1429,200 @@ void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int si
 }
 
 // Step 3a: partial LU with partial pivoting of F = Z_ii[k~:n, k~:n] (eqs. 9-11),
-// then explicit L^-1 P and U^-1 (ld rmax = n - k) by in-place triangular
-// inversion.  F lives in LDS up to LU_LDS_MAX, else in the cluster's scratch.
-constexpr int LU_LDS_MAX = 100;
+// then explicit L^-1 P and U^-1 (ld rmax = n - k).
+//
+// Up to LU_REG_MAX rows the elimination runs in registers: wavefront w owns the
+// columns c = w + 16 s, lane l rows l and l + 64.  Pivoting is implicit (rows
+// stay where they are; each row carries its position in the row-swapped order,
+// and ties in max |re| + |im| go to the lowest position, as with explicit
+// swaps), so a step costs one barrier: the owner of column j picks the pivot
+// and posts the multipliers, every wavefront then updates its later columns.
+// The factors are then written in the swapped order to F (LDS up to
+// LU_LDS_MAX rows, else the cluster's scratch), and every column of U^-1 and of
+// L^-1 is formed by one wavefront by substitution in registers and stored
+// straight to the outputs.
+constexpr int LU_NT = 1024, LU_NW = LU_NT / 64, LU_REG_MAX = 128, LU_CPW = LU_REG_MAX / LU_NW;
 
-__global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2* scratch, int rm) {
+// value of lane l (wavefront-uniform) of a complex register
+__device__ __forceinline__ double rl(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 lane_read(double2 v, int l) { return make_double2(rl(v.x, l), rl(v.y, l)); }
+__device__ __forceinline__ double2 pick2(const double2 (&x)[2], int q) { return q == 0 ? x[0] : x[1]; }
+
+__global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, double2* scratch, int rm) {
+  __shared__ double2 sF[LU_LDS_MAX * LU_LDS_MAX];
+  __shared__ double2 lbuf[2][LU_REG_MAX];
+  __shared__ double2 dinv[LU_REG_MAX];
+  __shared__ int pivrow[LU_REG_MAX], pjpos[LU_REG_MAX];
+  __shared__ int s_fail;
+  const int i = c.cl[blockIdx.x];
+  const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
+  if (r <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
+  double2* F = (r <= LU_LDS_MAX) ? sF : scratch + (int64_t)blockIdx.x * ((int64_t)rm * rm + rm);
+  double2 col[LU_CPW][2];
+  int pos[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) pos[q] = lane + 64 * q;
+#pragma unroll
+  for (int s = 0; s < LU_CPW; ++s) {
+    const int cc = wv + LU_NW * s;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int a = lane + 64 * q;
+      col[s][q] = (cc < r && a < r) ? Z[kt + a + (int64_t)(kt + cc) * n] : make_double2(0, 0);
+    }
+  }
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    const int so = j / LU_NW;
+    if (wv == j % LU_NW) {
+      double2 x[2];
+#pragma unroll
+      for (int s = 0; s < LU_CPW; ++s)
+        if (s == so) {
+          x[0] = col[s][0];
+          x[1] = col[s][1];
+        }
+      // pivot: largest |re| + |im| among the rows not yet eliminated, lowest position on ties
+      double best = -1.0;
+      int bpos = 1 << 30, brow = 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int a = lane + 64 * q;
+        if (a < r && pos[q] >= j) {
+          const double val = fabs(x[q].x) + fabs(x[q].y);
+          if (val > best || (val == best && pos[q] < bpos)) {
+            best = val;
+            bpos = pos[q];
+            brow = a;
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int op = __shfl_xor(bpos, o, 64), orow = __shfl_xor(brow, o, 64);
+        if (ov > best || (ov == best && op < bpos)) {
+          best = ov;
+          bpos = op;
+          brow = orow;
+        }
+      }
+      const int pr = __builtin_amdgcn_readfirstlane(brow);
+      const double2 piv = lane_read(pick2(x, pr >> 6), pr & 63);
+      const double pd = cabs2(piv);
+      const double2 pinv = make_double2(piv.x / pd, -piv.y / pd);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int a = lane + 64 * q;
+        const bool below = a < r && pos[q] >= j && a != pr;
+        const double2 l = below ? cmul(x[q], pinv) : make_double2(0, 0);
+        if (below) x[q] = l;
+        if (a < LU_REG_MAX) lbuf[j & 1][a] = l;
+      }
+#pragma unroll
+      for (int s = 0; s < LU_CPW; ++s)
+        if (s == so) {
+          col[s][0] = x[0];
+          col[s][1] = x[1];
+        }
+      if (lane == 0) {
+        if (!(best > 0.0)) s_fail = 1;
+        pivrow[j] = pr;
+        pjpos[j] = __builtin_amdgcn_readfirstlane(bpos);
+        dinv[j] = pinv;
+      }
+    }
+    __syncthreads();
+    if (s_fail) {
+      if (tid == 0) atomicMax(v.flags, i + 1);
+      return;
+    }
+    const int pr = pivrow[j], pp = pjpos[j];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int a = lane + 64 * q;
+      pos[q] = (a == pr) ? j : (pos[q] == j ? pp : pos[q]);
+    }
+    double2 l[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) l[q] = lbuf[j & 1][lane + 64 * q];
+#pragma unroll
+    for (int s = 0; s < LU_CPW; ++s) {
+      if (wv + LU_NW * s > j && wv + LU_NW * s < r) {
+        const double2 xp = lane_read(pick2(col[s], pr >> 6), pr & 63);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) col[s][q] = csub(col[s][q], cmul(l[q], xp));
+      }
+    }
+  }
+  // the factors in the swapped row order
+#pragma unroll
+  for (int s = 0; s < LU_CPW; ++s) {
+    const int cc = wv + LU_NW * s;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int a = lane + 64 * q;
+      if (cc < r && a < r) F[pos[q] + (int64_t)cc * r] = col[s][q];
+    }
+  }
+  __syncthreads();
+  double2* Li = v.LU + v.lu_off[i];
+  double2* Ui = Li + (int64_t)rmax * rmax;
+  // column j of U^-1: back substitution U x = e_j
+  for (int j = wv; j < r; j += LU_NW) {
+    double2 x[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) x[q] = make_double2(lane + 64 * q == j ? 1.0 : 0.0, 0.0);
+    for (int mm = j; mm >= 0; --mm) {
+      const double2 xm = cmul(lane_read(pick2(x, mm >> 6), mm & 63), dinv[mm]);
+      const double2* fc = F + (int64_t)mm * r;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int a = lane + 64 * q;
+        if (a < mm) x[q] = csub(x[q], cmul(fc[a], xm));
+        if (a == mm) x[q] = xm;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int a = lane + 64 * q;
+      if (a < r) Ui[a + (int64_t)j * rmax] = a <= j ? x[q] : make_double2(0, 0);
+    }
+  }
+  // column j of L^-1 (unit lower): forward substitution L y = e_j, stored at column pivrow[j]
+  for (int j = wv; j < r; j += LU_NW) {
+    double2 y[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) y[q] = make_double2(lane + 64 * q == j ? 1.0 : 0.0, 0.0);
+    for (int mm = j; mm + 1 < r; ++mm) {
+      const double2 ym = lane_read(pick2(y, mm >> 6), mm & 63);
+      const double2* fc = F + (int64_t)mm * r;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int a = lane + 64 * q;
+        if (a > mm && a < r) y[q] = csub(y[q], cmul(fc[a], ym));
+      }
+    }
+    double2* lc = Li + (int64_t)pivrow[j] * rmax;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int a = lane + 64 * q;
+      if (a < r) lc[a] = a >= j ? y[q] : make_double2(0, 0);
+    }
+  }
+}
+
+// Beyond LU_REG_MAX rows: the same factorization with explicit row swaps on F
+// (LDS up to LU_LDS_MAX, else scratch) by a 256-thread workgroup.
+__global__ void __launch_bounds__(256) k_lu_big(LevelView v, ColourTasks c, double2* scratch, int rm) {
   __shared__ double2 sF[LU_LDS_MAX * LU_LDS_MAX];
   __shared__ double2 sT[LU_LDS_MAX];
   __shared__ int16_t perm[STEP0_DMAX];
@@ -1557,7 +1746,10 @@ __global__ void __launch_bounds__(256) k_lu(LevelView v, ColourTasks c, double2*
 
 void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int rm, hipStream_t st) {
   if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_lu, dim3(c.ncl), dim3(256), 0, st, v, c, scratch, rm);
+  if (rm <= LU_REG_MAX)
+    hipLaunchKernelGGL(k_lu_reg, dim3(c.ncl), dim3(LU_NT), 0, st, v, c, scratch, rm);
+  else
+    hipLaunchKernelGGL(k_lu_big, dim3(c.ncl), dim3(256), 0, st, v, c, scratch, rm);
 }
 
 // Largest |re| + |im| over the workgroup, folded into *dst with an atomic max on

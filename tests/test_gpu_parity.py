@@ -8,10 +8,12 @@ from paper_1703_06155_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-# small problems the oracle finishes in seconds; several tiles, ragged leaves, multiple levels
+# small problems the oracle finishes in seconds; several tiles, ragged leaves, multiple levels; the last
+# two have clusters of about 108 and 144 unknowns (the wide-cluster paths of Step 0 and of the partial LU)
 CASES = [((8, 8, 8), 16, 1e-4), ((10, 7, 9), 12, 1e-5), ((6, 6, 6), 8, 1e-6), ((9, 5, 3), 7, 1e-3),
-         ((12, 12, 12), 27, 1e-4), ((12, 12, 24), 27, 1e-4)]
-IDS = ["8^3_leaf16", "10x7x9_leaf12", "6^3_leaf8", "9x5x3_leaf7", "12^3_leaf27", "12x12x24_leaf27"]
+         ((12, 12, 12), 27, 1e-4), ((12, 12, 24), 27, 1e-4), ((12, 12, 12), 110, 1e-4), ((16, 12, 12), 150, 1e-4)]
+IDS = ["8^3_leaf16", "10x7x9_leaf12", "6^3_leaf8", "9x5x3_leaf7", "12^3_leaf27", "12x12x24_leaf27", "12^3_leaf110",
+       "16x12x12_leaf150"]
 
 
 def _torch():

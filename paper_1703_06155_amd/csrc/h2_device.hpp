@@ -35,10 +35,50 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
+// Wavefront reductions on the DPP network (no LDS round trips): quad
+// permutations and row rotations combine the 16 lanes of a row, row_bcast:15 and
+// row_bcast:31 carry the row results up to lane 63, whose value every lane then
+// reads.  All 64 lanes must be active.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane63_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xb1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4e>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124>(v);       // row_ror:4
+  v += dpp_f64<0x128>(v);       // row_ror:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return lane63_f64(v);
+}
+__device__ __forceinline__ int wave_min_int(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0xb1, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x4e, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x124, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x128, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x142, 0xa, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+// maximum of non-negative values (lanes outside a DPP source read 0)
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_f64<0xb1>(v));
+  v = fmax(v, dpp_f64<0x4e>(v));
+  v = fmax(v, dpp_f64<0x124>(v));
+  v = fmax(v, dpp_f64<0x128>(v));
+  v = fmax(v, dpp_f64<0x142, 0xa>(v));
+  v = fmax(v, dpp_f64<0x143, 0xc>(v));
+  return lane63_f64(v);
 }
 
 // Workgroup-wide sum for 256 threads; `red` holds >= 4 doubles of LDS.

@@ -706,11 +706,6 @@ static_assert(STEP0_DMAX % 64 == 0 && STEP0_DMAX <= 512, "d-vectors are spread o
 // Packed lower storage: element (r, c), r >= c, at c d - c (c - 1) / 2 + (r - c).
 __device__ __forceinline__ int pidx(int r, int c, int d) { return c * d - (c * (c - 1)) / 2 + (r - c); }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
 // Sum / maximum over the workgroup's wavefronts in a fixed order (the same value in every thread).
 __device__ __forceinline__ double s0_sum(double v, double* red) {
   v = wave_sum(v);
@@ -723,8 +718,8 @@ __device__ __forceinline__ double s0_sum(double v, double* red) {
   __syncthreads();
   return s;
 }
-__device__ __forceinline__ double s0_max(double v, double* red) {
-  v = wave_max(v);
+__device__ __forceinline__ double s0_max(double v, double* red) {  // v >= 0
+  v = wave_max_nonneg(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -744,7 +739,10 @@ __device__ __forceinline__ double s0_max(double v, double* red) {
 // update a column per wavefront (lanes on rows).  ws and vs are d-vectors.
 template <int NQ>
 __device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double* off, double2* ws, double2* vs) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int cb[NQ];  // P[cb[q] + r] = A(r, c) for the lane's columns c = lane + 64 q and r >= c
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) cb[q] = pidx(lane + 64 * q, lane + 64 * q, d) - (lane + 64 * q);
   for (int j = 0; j + 1 < d; ++j) {
     const int cj = pidx(j, j, d) - j;  // P[cj + r] = A(r, j) for r >= j
     double2 v[NQ];
@@ -761,10 +759,11 @@ __device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double
     double beta = alpha.x;
     if (xn2 > 0.0 || alpha.y != 0.0) {
       beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
-      t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+      const double rb = 1.0 / beta;
+      t = make_double2((beta - alpha.x) * rb, -alpha.y * rb);
       const double2 den = make_double2(alpha.x - beta, alpha.y);
-      const double dd = cabs2(den);
-      const double2 sc = make_double2(den.x / dd, -den.y / dd);
+      const double rdd = 1.0 / cabs2(den);
+      const double2 sc = make_double2(den.x * rdd, -den.y * rdd);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) v[q] = cmul(v[q], sc);
     }
@@ -790,10 +789,10 @@ __device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double
       for (int q = 0; q < NQ; ++q) {
         const int c = lane + 64 * q;
         if (c > j && c < d) {
-          const double2 e1 = c <= r ? P[pidx(r, c, d)] : cconj(P[cr + c]);
+          const double2 e1 = c <= r ? P[cb[q] + r] : cconj(P[cr + c]);
           a1 = cadd(a1, cmul(e1, v[q]));
           if (r2 < d) {
-            const double2 e2 = c <= r2 ? P[pidx(r2, c, d)] : cconj(P[cr2 + c]);
+            const double2 e2 = c <= r2 ? P[cb[q] + r2] : cconj(P[cr2 + c]);
             a2 = cadd(a2, cmul(e2, v[q]));
           }
         }
@@ -847,11 +846,13 @@ __device__ void hetrd_packed(double2* P, int d, double2* tau, double* dg, double
 }
 
 // number of eigenvalues of T below sigma (Sturm count of the LDL^T pivots)
-__device__ int sturm_count(const double* dg, const double* off, int d, double sigma, double pivmin) {
+__device__ int sturm_count(const double* __restrict__ dg, const double* __restrict__ off, int d, double sigma,
+                           double pivmin) {
   int cnt = 0;
   double q = dg[0] - sigma;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0) ++cnt;
+#pragma unroll 4
   for (int i = 1; i < d; ++i) {
     q = (dg[i] - sigma) - off[i - 1] * off[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
@@ -863,51 +864,95 @@ __device__ int sturm_count(const double* dg, const double* off, int d, double si
 // The same count without divisions, for a T scaled to norm <= 1 (diagonal dn,
 // squared off-diagonal e2): sign changes of the leading principal minors
 // p_i = (dn_i - x) p_{i-1} - e2_{i-1} p_{i-2}, kept in range by exact
-// power-of-two rescaling; a zero minor takes the sign opposite to its
-// predecessor (the limit of a negative pivot).
-__device__ int sturm_count_minors(const double* dn, const double* e2, int d, double x) {
+// power-of-two rescaling.  A zero minor is replaced by -2^-200 times its
+// predecessor (a tiny negative pivot, the limit the LDL^T count takes), so every
+// minor is nonzero and a sign change is the xor of the two sign bits.  Branch-free.
+__device__ int sturm_count_minors(const double* __restrict__ dn, const double* __restrict__ e2, int d, double x) {
   double p0 = 1.0, p1 = dn[0] - x;
-  bool n1 = !(p1 > 0.0);
-  int cnt = n1;
-  for (int i = 1; i < d; ++i) {
-    const double p2 = (dn[i] - x) * p1 - e2[i - 1] * p0;
-    const bool n2 = (p2 == 0.0) ? !n1 : (p2 < 0.0);
-    cnt += (n2 != n1);
+  p1 = (p1 == 0.0) ? -0x1p-200 : p1;
+  unsigned cnt = (unsigned)__double2hiint(p1) >> 31;
+  auto step = [&](double dd, double ee) {
+    double p2 = (dd - x) * p1 - ee * p0;
+    p2 = (p2 == 0.0) ? -0x1p-200 * p1 : p2;
+    cnt += (unsigned)(__double2hiint(p2) ^ __double2hiint(p1)) >> 31;
     p0 = p1;
     p1 = p2;
-    n1 = n2;
-    if ((i & 3) == 0) {
-      const double m = fmax(fabs(p0), fabs(p1));
-      if (m > 0x1p256) {
-        p0 *= 0x1p-512;
-        p1 *= 0x1p-512;
-      } else if (m < 0x1p-256) {
-        p0 *= 0x1p512;
-        p1 *= 0x1p512;
-      }
-    }
+  };
+  int i = 1;
+  // four steps per round with their operands loaded up front; |p| grows at most
+  // four-fold per step (|dn - x| <= 2, e2 <= 1), so one range check per round suffices
+  for (; i + 3 < d; i += 4) {
+    const double d0 = dn[i], d1 = dn[i + 1], d2 = dn[i + 2], d3 = dn[i + 3];
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+    step(d0, f0);
+    step(d1, f1);
+    step(d2, f2);
+    step(d3, f3);
+    const double m = fmax(fabs(p0), fabs(p1));
+    const double sc = m > 0x1p256 ? 0x1p-512 : (m < 0x1p-256 ? 0x1p512 : 1.0);
+    p0 *= sc;
+    p1 *= sc;
   }
-  return cnt;
+  for (; i < d; ++i) step(dn[i], e2[i - 1]);
+  return (int)cnt;
 }
 
 // Eigenvalues of the scaled tridiagonal (dn, e2, spectrum inside [glo, ghi])
-// with ascending indices ks[0..cnt), out[t] for target t.  Multisection: groups
-// of G lanes of one wavefront (G a power of two) bracket one eigenvalue, each
-// lane placing one Sturm-count probe per round, so a round narrows the bracket
-// G + 1 fold; stops at a bracket of a few units in the last place of the
-// eigenvalue or of the norm.  Every thread of the workgroup calls this.
+// with ascending indices ks[0..cnt), out[t] for target t.  Multisection: a group
+// of G probes brackets one eigenvalue, each probe one Sturm count per round, so a
+// round narrows the bracket G + 1 fold; stops at a bracket of a few units in the
+// last place of the eigenvalue or of the norm.  Up to S0_NW targets, a group is
+// W whole wavefronts (W the largest power of two with W cnt <= S0_NW), combined
+// through firstge[2 S0_NW] in LDS; beyond that, groups of G lanes of one wavefront.
+// Every thread of the workgroup calls this.
 __device__ void tri_eig_targets(const double* dn, const double* e2, int d, double glo, double ghi, const int* ks,
-                                int cnt, double* out) {
+                                int cnt, double* out, int* firstge) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double lo0 = glo - 2.2e-16 * fabs(glo) - 0x1p-60, hi0 = ghi + 2.2e-16 * fabs(ghi) + 0x1p-60;
+  if (cnt <= S0_NW) {
+    int W = S0_NW;
+    while (W * cnt > S0_NW) W >>= 1;
+    const int G = 64 * W, t = wv / W, m = (wv % W) * 64 + lane;
+    const int k = t < cnt ? ks[t] : 0;
+    const double rg = 1.0 / (double)(G + 1), fm = (double)(m + 1) * rg;
+    double lo = lo0, hi = hi0;
+    bool done = t >= cnt;
+    for (;;) {
+      const bool ge = !done && sturm_count_minors(dn, e2, d, lo + (hi - lo) * fm) >= k + 1;
+      const unsigned long long mask = __ballot(ge);
+      if (lane == 0) firstge[wv] = mask ? (wv % W) * 64 + __ffsll((long long)mask) - 1 : G;
+      __syncthreads();
+      if (!done) {
+        int f = G;
+        for (int u = 0; u < W; ++u) f = min(f, firstge[t * W + u]);
+        const double w = hi - lo;
+        const double nlo = f > 0 ? lo + w * ((double)f * rg) : lo;   // probe f - 1, or lo
+        const double nhi = f < G ? lo + w * ((double)(f + 1) * rg) : hi;
+        if ((nlo == lo && nhi == hi) || !(nhi > nlo)) done = true;
+        lo = nlo;
+        hi = nhi;
+        if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 0x1p-52) done = true;
+      }
+      if (lane == 0) firstge[S0_NW + wv] = done;
+      __syncthreads();
+      bool all = true;
+      for (int u = 0; u < S0_NW; ++u) all = all && firstge[S0_NW + u];
+      if (all) break;
+    }
+    if (t < cnt && m == 0) out[t] = 0.5 * (lo + hi);
+    __syncthreads();
+    return;
+  }
   int G = 64;
   while (G > 1 && (int)(blockDim.x / G) < cnt) G >>= 1;
   const int ngroups = blockDim.x / G;
-  const int lane = threadIdx.x & 63, gid = threadIdx.x / G, m = threadIdx.x % G;
+  const int gid = threadIdx.x / G, m = threadIdx.x % G;
   const int gbase = (lane / G) * G;
   const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
   for (int t0 = 0; t0 < cnt; t0 += ngroups) {
     const int t = t0 + gid;
     const int k = t < cnt ? ks[t] : 0;
-    double lo = glo - 2.2e-16 * fabs(glo) - 0x1p-60, hi = ghi + 2.2e-16 * fabs(ghi) + 0x1p-60;
+    double lo = lo0, hi = hi0;
     bool done = t >= cnt;
     while (__ballot(!done) != 0ull) {
       const double x = lo + (hi - lo) * (double)(m + 1) / (double)(G + 1);
@@ -931,6 +976,7 @@ __device__ void tri_eig_targets(const double* dn, const double* e2, int d, doubl
     }
     if (t < cnt && m == 0) out[t] = 0.5 * (lo + hi);
   }
+  __syncthreads();
 }
 
 // Inverse iteration for one eigenvector of T (dg, off) with shift lam: T - lam I
@@ -940,8 +986,9 @@ __device__ void tri_eig_targets(const double* dn, const double* e2, int d, doubl
 // the caller's work area, element i of array a at W[(a d + i) nb], so that
 // neighbouring threads (vectors) touch neighbouring words; the recurrences run in
 // registers with the next operands loaded a step ahead.
-__device__ void tri_inverse_iteration(const double* dg, const double* off, int d, double lam, double pivmin,
-                                      int seed, double* W, int nb, double2* y) {
+__device__ void tri_inverse_iteration(const double* __restrict__ dg, const double* __restrict__ off, int d,
+                                      double lam, double pivmin, int seed, double* __restrict__ W, int nb,
+                                      double2* __restrict__ y) {
   double* rD = W;
   double* DU = W + (size_t)d * nb;
   double* DU2 = DU + (size_t)d * nb;
@@ -950,6 +997,7 @@ __device__ void tri_inverse_iteration(const double* dg, const double* off, int d
   double* b = S + (size_t)d * nb;
   // factorization
   double cd = dg[0] - lam, cdu = d > 1 ? off[0] : 0.0;
+#pragma unroll 4
   for (int i = 0; i + 1 < d; ++i) {
     const double sub = off[i], nd = dg[i + 1] - lam, ndu = (i + 2 < d) ? off[i + 1] : 0.0;
     const size_t o = (size_t)i * nb;
@@ -982,6 +1030,7 @@ __device__ void tri_inverse_iteration(const double* dg, const double* off, int d
     auto start = [&](int r) { return 1.0 + 0.37 * (double)((r * (seed + 3) + 7 * seed) % 11) / 11.0; };
     double cur = it == 0 ? start(0) : b[0] * scale;
     double nxt = d > 1 ? (it == 0 ? start(1) : b[nb] * scale) : 0.0;
+#pragma unroll 4
     for (int i = 0; i + 1 < d; ++i) {
       const size_t o = (size_t)i * nb;
       const double f = F[o];
@@ -1000,6 +1049,7 @@ __device__ void tri_inverse_iteration(const double* dg, const double* off, int d
     double x1 = cur * rD[(size_t)(d - 1) * nb], x2 = 0.0;
     b[(size_t)(d - 1) * nb] = x1;
     double nrm = x1 * x1;
+#pragma unroll 4
     for (int i = d - 2; i >= 0; --i) {
       const size_t o = (size_t)i * nb;
       const double xi = (b[o] - DU[o] * x1 - DU2[o] * x2) * rD[o];
@@ -1019,13 +1069,14 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
   __shared__ double2 ws[STEP0_DMAX], vs[STEP0_DMAX], tauv[STEP0_DMAX];
   __shared__ double dg[STEP0_DMAX], off[STEP0_DMAX], eig[STEP0_DMAX];
   __shared__ int ks[STEP0_DMAX];
+  __shared__ int firstge[2 * S0_NW];
   __shared__ double red[S0_NW];
   __shared__ double bounds[4];
   __shared__ int s_p;
   const int64_t stride = 4 * (int64_t)dm * dm;
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], k = v.k[i], d = n - k;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   double2* Q = v.Q + v.q_off[i];
   const double2* B = v.B + v.b_off[i];
   for (int e = tid; e < n * k; e += blockDim.x) Q[e] = B[e];
@@ -1129,10 +1180,16 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
       }
       if (tid == 0) ks[0] = d - 1;
       __syncthreads();
-      // largest eigenvalue, then the rank decision against tau^2 by one Sturm count
-      tri_eig_targets(dn, e2, d, glo * sinv, ghi * sinv, ks, 1, eig);
-      __syncthreads();
-      const double s1 = sqrt(fmax(eig[0] / sinv, 0.0));
+      // the largest eigenvalue matters only above nu^2 (tau = eps_fill max(nu, sigma_1)):
+      // one Sturm count at nu^2 (or the Gershgorin bound) settles that first; then the
+      // rank decision against tau^2 by one Sturm count
+      const double nu2s = v.nu[i] * v.nu[i] * sinv;
+      const bool below_nu = nu2s > ghi * sinv || sturm_count_minors(dn, e2, d, nu2s) == d;
+      double s1 = 0.0;
+      if (!below_nu) {
+        tri_eig_targets(dn, e2, d, glo * sinv, ghi * sinv, ks, 1, eig, firstge);
+        s1 = sqrt(fmax(eig[0] / sinv, 0.0));
+      }
       const double tau = v.eps_fill * fmax(v.nu[i], s1);
       if (tid == 0) {
         int pp = (tau > 0.0) ? d - sturm_count(dg, off, d, tau * tau, pivmin) : 0;
@@ -1145,8 +1202,7 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
       const int ne = min(p + 1, d);
       for (int j = tid; j < ne; j += blockDim.x) ks[j] = d - 1 - j;
       __syncthreads();
-      tri_eig_targets(dn, e2, d, glo * sinv, ghi * sinv, ks, ne, eig);
-      __syncthreads();
+      tri_eig_targets(dn, e2, d, glo * sinv, ghi * sinv, ks, ne, eig, firstge);
       for (int j = tid; j < ne; j += blockDim.x) eig[j] /= sinv;
       __syncthreads();
       if (tid == 0 && v.margins) {
@@ -1462,7 +1518,7 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (r <= 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
   double2* F = (r <= LU_LDS_MAX) ? sF : scratch + (int64_t)blockIdx.x * ((int64_t)rm * rm + rm);
   double2 col[LU_CPW][2];
@@ -1492,7 +1548,7 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
         }
       // pivot: largest |re| + |im| among the rows not yet eliminated, lowest position on ties
       double best = -1.0;
-      int bpos = 1 << 30, brow = 0;
+      int bpos = 0x7fffffff, brow = 0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int a = lane + 64 * q;
@@ -1505,17 +1561,13 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
           }
         }
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, 64);
-        const int op = __shfl_xor(bpos, o, 64), orow = __shfl_xor(brow, o, 64);
-        if (ov > best || (ov == best && op < bpos)) {
-          best = ov;
-          bpos = op;
-          brow = orow;
-        }
-      }
-      const int pr = __builtin_amdgcn_readfirstlane(brow);
+      const double lbest = best;
+      best = wave_max_nonneg(fmax(best, 0.0));  // 0: no nonzero candidate, the block is singular
+      const int ppos = wave_min_int(lbest == best ? bpos : 0x7fffffff);
+      const unsigned long long hit = __ballot(lbest == best && bpos == ppos);
+      const int src = hit ? __ffsll((long long)hit) - 1 : 0;
+      const int pr = min(max(__builtin_amdgcn_readlane(brow, src), 0), r - 1);
+      bpos = ppos;
       const double2 piv = lane_read(pick2(x, pr >> 6), pr & 63);
       const double pd = cabs2(piv);
       const double2 pinv = make_double2(piv.x / pd, -piv.y / pd);
@@ -1534,9 +1586,9 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
           col[s][1] = x[1];
         }
       if (lane == 0) {
-        if (!(best > 0.0)) s_fail = 1;
+        if (!(best > 0.0) || !hit) s_fail = 1;
         pivrow[j] = pr;
-        pjpos[j] = __builtin_amdgcn_readfirstlane(bpos);
+        pjpos[j] = bpos;
         dinv[j] = pinv;
       }
     }
@@ -1581,6 +1633,7 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
     double2 x[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) x[q] = make_double2(lane + 64 * q == j ? 1.0 : 0.0, 0.0);
+#pragma unroll 2
     for (int mm = j; mm >= 0; --mm) {
       const double2 xm = cmul(lane_read(pick2(x, mm >> 6), mm & 63), dinv[mm]);
       const double2* fc = F + (int64_t)mm * r;
@@ -1602,6 +1655,7 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
     double2 y[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) y[q] = make_double2(lane + 64 * q == j ? 1.0 : 0.0, 0.0);
+#pragma unroll 2
     for (int mm = j; mm + 1 < r; ++mm) {
       const double2 ym = lane_read(pick2(y, mm >> 6), mm & 63);
       const double2* fc = F + (int64_t)mm * r;
@@ -1756,8 +1810,7 @@ void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int r
 // the bit pattern (monotone for non-negative doubles).
 __device__ void block_max_to(double mx, unsigned long long* dst) {
   __shared__ double red[4];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  mx = wave_max_nonneg(mx);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[w] = mx;

@@ -289,9 +289,11 @@ __device__ __forceinline__ int tile_split(int m, int n) {
 
 // acc += op(A_tile) * op(B_tile) for the first nk (<= TK, uniform over the
 // block) k-columns of one slab resident in LDS; the slab is zero beyond its
-// K range, so only whole 4-wide MFMA steps past nk are skipped.
+// K range, so only whole 4-wide MFMA steps past nk are skipped, and so are the
+// 16 x 16 output blocks outside the m x n tile.
 template <typename R>
-__device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc, int nk = TK, int split = SPLIT_4) {
+__device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc, int nk = TK, int split = SPLIT_4,
+                                         int m = TM, int n = TN) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int li = lane & 15, lk = lane >> 4;
@@ -330,12 +332,66 @@ __device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc, 
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
+        if (qr * 32 + t * 16 >= m || qc * 32 + u * 16 >= n) continue;
         // C^T = op(B)^T op(A)^T : pass the B fragment as the MFMA's first operand
         acc.re[t][u] = mfma16(br[u], ar[t], acc.re[t][u]);
         acc.re[t][u] = mfma16(bi[u], nai[t], acc.re[t][u]);
         acc.im[t][u] = mfma16(br[u], ai[t], acc.im[t][u]);
         acc.im[t][u] = mfma16(bi[u], ar[t], acc.im[t][u]);
       }
+  }
+}
+
+// Balanced variant: the tile's mt x nt active 16 x 16 output blocks (block k at
+// row block k % mt, column block k / mt) are dealt to the four wavefronts in
+// contiguous runs of ceil(mt nt / 4), so no wavefront carries more than that;
+// wavefront w keeps its j-th block in accumulator slot j (re[j >> 1][j & 1]).
+template <typename R>
+__device__ __forceinline__ void mma_slab_bal(const TileSmem<R>& s, TileAcc<R>& acc, int nk, int mt, int nt) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int cnt = mt * nt, per = (cnt + 3) >> 2, k0 = w * per;
+#pragma unroll
+  for (int q = 0; q < TK / 4; ++q) {
+    if (q * 4 >= nk) break;
+    const int kk = q * 4 + lk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kb = k0 + j;
+      if (j >= per || kb >= cnt) continue;
+      const int rb = kb % mt, cb = kb / mt;
+      const R ar = s.are[kk][rb * 16 + li], ai = s.aim[kk][rb * 16 + li];
+      const R br = s.bre[kk][cb * 16 + li], bi = s.bim[kk][cb * 16 + li];
+      auto& re = acc.re[j >> 1][j & 1];
+      auto& im = acc.im[j >> 1][j & 1];
+      re = mfma16(br, ar, re);
+      re = mfma16(bi, -ai, re);
+      im = mfma16(br, ai, im);
+      im = mfma16(bi, ar, im);
+    }
+  }
+}
+
+// C[0:m, 0:n] -= acc for the blocks mma_slab_bal assigned to this wavefront.
+template <typename R, typename CT>
+__device__ __forceinline__ void store_tile_bal_sub(const TileAcc<R>& acc, CT* C, int64_t ldc, int m, int n, int mt,
+                                                   int nt) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cnt = mt * nt, per = (cnt + 3) >> 2, k0 = w * per;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int kb = k0 + j;
+    if (j >= per || kb >= cnt) continue;
+    const int rb = kb % mt, cb = kb / mt;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb * 16 + (lane & 15), jj = cb * 16 + acc_col<R>(lane, v);
+      if (i < m && jj < n) {
+        CT* p = C + i + (int64_t)jj * ldc;
+        const CT o = *p;
+        *p = CT{o.x - acc.re[j >> 1][j & 1][v], o.y - acc.im[j >> 1][j & 1][v]};
+      }
+    }
   }
 }
 
@@ -409,7 +465,7 @@ __device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const
     slab_store<R, CT>(s, r, opA, opB);
     __syncthreads();
     if (k0 + TK < K) slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, k0 + TK);
-    mma_slab<R>(s, acc, min(TK, K - k0), split);
+    mma_slab<R>(s, acc, min(TK, K - k0), split, m, n);
   }
   tile_reduce<R>(s, acc, split);
 }

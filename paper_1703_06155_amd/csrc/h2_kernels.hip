@@ -1954,7 +1954,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   acc.zero();
   SlabRegs<double2> regs;
   int k0 = 0;
-  const int split = tile_split(m, nn);
+  const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
   slab_fetch<double2>(regs, cur.C, cur.ldc, OP_N, cur.R, cur.ldr, OP_N, m, nn, cur.r, 0);
   while (true) {
     const int nk = min(TK, cur.r - k0);
@@ -1971,13 +1971,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       more = e < e_end;
     }
     if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
-    mma_slab<R>(s, acc, nk, split);
+    mma_slab_bal<R>(s, acc, nk, mt, nt);
     if (!more) break;
     cur = nxt;
     k0 = nk0;
   }
-  tile_reduce<R>(s, acc, split);
-  store_tile<R, double2>(acc, Z, na, m, nn, ST_SUB);
+  store_tile_bal_sub<R, double2>(acc, Z, na, m, nn, mt, nt);
 }
 
 // The mixed form splits every flush: terms of clusters whose panels show no

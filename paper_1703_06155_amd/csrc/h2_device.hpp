@@ -395,6 +395,26 @@ __device__ __forceinline__ void store_tile_bal_sub(const TileAcc<R>& acc, CT* C,
   }
 }
 
+// C[0:m, 0:n] = acc for the blocks mma_slab_bal assigned to this wavefront
+// (together the four wavefronts cover every 16 x 16 block of the m x n tile).
+template <typename R, typename CT>
+__device__ __forceinline__ void store_tile_bal_set(const TileAcc<R>& acc, CT* C, int64_t ldc, int m, int n, int mt,
+                                                   int nt) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cnt = mt * nt, per = (cnt + 3) >> 2, k0 = w * per;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int kb = k0 + j;
+    if (j >= per || kb >= cnt) continue;
+    const int rb = kb % mt, cb = kb / mt;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb * 16 + (lane & 15), jj = cb * 16 + acc_col<R>(lane, v);
+      if (i < m && jj < n) C[i + (int64_t)jj * ldc] = CT{acc.re[j >> 1][j & 1][v], acc.im[j >> 1][j & 1][v]};
+    }
+  }
+}
+
 // Partial sums of helper waves -> quadrant owners, through the slab LDS (all
 // threads call it; the slab contents are dead afterwards).  Helpers end with
 // zero accumulators, so a later contraction into the same tile stays correct.

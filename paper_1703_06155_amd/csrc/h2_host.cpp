@@ -127,8 +127,13 @@ struct DArr {
 struct ColourPlan {
   std::vector<int32_t> cl, pj_slot, sc_slot, sc_cptr, sc_i, sc_ja, sc_jb, pn_i, pn_ja, sv_cl, sv_cptr, sv_i,
       sv_ja;
+  // Schur tasks with many terms are split along the contraction into chunks of at
+  // most SCHUR_CHUNK_TERMS terms: per task {chunk, chunks, first partial slot, group}
+  // ({-1, 1, 0, 0} when whole); nps partial slots and ngrp groups in all
+  std::vector<int32_t> sc_sp, sc_gtask;
+  int nps = 0, ngrp = 0;
   DArr<int32_t> d_cl, d_pj_slot, d_sc_slot, d_sc_cptr, d_sc_i, d_sc_ja, d_sc_jb, d_pn_i, d_pn_ja, d_sv_cl,
-      d_sv_cptr, d_sv_i, d_sv_ja;
+      d_sv_cptr, d_sv_i, d_sv_ja, d_sc_sp, d_sc_gtask;
   DArr<int64_t> d_pj_toff;
   std::vector<int64_t> pj_toff;
   int64_t temp_elems = 0;
@@ -235,6 +240,7 @@ struct h2_ctx {
   std::vector<h2::FactorLevel> flev;       // index L - l
   h2::DArr<double2> slot_buf[2];           // block arenas of even / odd levels (index L - l)
   h2::DArr<double2> ws_bp, ws_w, ws_temp, ws_lu, ws_eig, ws_gram;  // per-level work space
+  h2::DArr<double2> ws_scp;                                          // partial tiles of split Schur tasks
   h2::DArr<h2::MergeTask> ws_merge;
   int64_t nf = 0;
   std::vector<int32_t> final_off;          // per cluster of level l0-1
@@ -394,16 +400,34 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     C.sc_i.clear();
     C.sc_ja.clear();
     C.sc_jb.clear();
+    C.sc_sp.clear();
+    C.sc_gtask.clear();
+    C.nps = C.ngrp = 0;
     for (int s : slots) {
       auto& pl = pending[s];
       if (pl.empty()) continue;
-      C.sc_slot.push_back(s);
-      for (const auto& t : pl) {
-        C.sc_i.push_back(t[0]);
-        C.sc_ja.push_back(t[1]);
-        C.sc_jb.push_back(t[2]);
+      const int T = (int)pl.size();
+      const int np = (T + SCHUR_CHUNK_TERMS - 1) / SCHUR_CHUNK_TERMS;
+      for (int ch = 0; ch < np; ++ch) {
+        const int t0 = (int)((int64_t)T * ch / np), t1 = (int)((int64_t)T * (ch + 1) / np);
+        C.sc_slot.push_back(s);
+        for (int x = t0; x < t1; ++x) {
+          C.sc_i.push_back(pl[x][0]);
+          C.sc_ja.push_back(pl[x][1]);
+          C.sc_jb.push_back(pl[x][2]);
+        }
+        C.sc_cptr.push_back((int32_t)C.sc_i.size());
+        if (np == 1) {
+          C.sc_sp.insert(C.sc_sp.end(), {-1, 1, 0, 0});
+        } else {
+          C.sc_sp.insert(C.sc_sp.end(), {ch, np, C.nps, C.ngrp});
+        }
       }
-      C.sc_cptr.push_back((int32_t)C.sc_i.size());
+      if (np > 1) {
+        C.sc_gtask.push_back((int32_t)C.sc_slot.size() - np);
+        C.nps += np;
+        C.ngrp += 1;
+      }
       pl.clear();
       pl.shrink_to_fit();
     }
@@ -512,6 +536,8 @@ static void upload_plan(LevelPlan& P, hipStream_t st) {
     C.d_sc_i.upload(C.sc_i, st);
     C.d_sc_ja.upload(C.sc_ja, st);
     C.d_sc_jb.upload(C.sc_jb, st);
+    C.d_sc_sp.upload(C.sc_sp, st);
+    C.d_sc_gtask.upload(C.sc_gtask, st);
     C.d_pn_i.upload(C.pn_i, st);
     C.d_pn_ja.upload(C.pn_ja, st);
     C.d_sv_cl.upload(C.sv_cl, st);
@@ -524,6 +550,8 @@ static void upload_plan(LevelPlan& P, hipStream_t st) {
   P.fin.d_sc_i.upload(P.fin.sc_i, st);
   P.fin.d_sc_ja.upload(P.fin.sc_ja, st);
   P.fin.d_sc_jb.upload(P.fin.sc_jb, st);
+  P.fin.d_sc_sp.upload(P.fin.sc_sp, st);
+  P.fin.d_sc_gtask.upload(P.fin.sc_gtask, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,6 +976,7 @@ static void release_factor_buffers(h2_ctx* H) {
   H->ws_lu.release();
   H->ws_eig.release();
   H->ws_gram.release();
+  H->ws_scp.release();
   H->ws_merge.release();
   H->Zf.release();
   H->Zinv.release();
@@ -1113,6 +1142,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);
+    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile)
+    int max_nps = P.fin.nps;
+    for (const ColourPlan& C : P.cols) max_nps = std::max(max_nps, C.nps);
+    H->ws_scp.alloc((size_t)std::max<int64_t>(1, (int64_t)max_nps * F.tiles * F.tiles * 4096));
     // blocks of this level
     if (l == L) {
       slots.alloc(slot_off[P.nslot]);
@@ -1218,6 +1251,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.sc_ja = C.d_sc_ja.p;
       ct.sc_jb = C.d_sc_jb.p;
       ct.nsc = (int)C.sc_slot.size();
+      ct.sc_sp = C.d_sc_sp.p;
+      ct.sc_gtask = C.d_sc_gtask.p;
+      ct.ngrp = C.ngrp;
+      ct.sc_part = H->ws_scp.p;
       ct.pn_i = C.d_pn_i.p;
       ct.pn_ja = C.d_pn_ja.p;
       ct.npn = (int)C.pn_i.size();
@@ -1266,6 +1303,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.sc_ja = P.fin.d_sc_ja.p;
       ct.sc_jb = P.fin.d_sc_jb.p;
       ct.nsc = (int)P.fin.sc_slot.size();
+      ct.sc_sp = P.fin.d_sc_sp.p;
+      ct.sc_gtask = P.fin.d_sc_gtask.p;
+      ct.ngrp = P.fin.ngrp;
+      ct.sc_part = H->ws_scp.p;
       ct.colour = P.ncol - 1;
       ct.tiles = F.tiles;
       hipEvent_t es = ev.next(st);
@@ -2180,7 +2221,11 @@ static void compute_ledger(h2_ctx* H) {
     auto dim_after = [&](int a, int c) -> double { return P.colour[a] <= c ? F.kt[a] : F.n[a]; };
     auto flush_bytes = [&](const ColourPlan& C, int c) {
       if (!C.sc_slot.empty()) H->ledger[7] += 1.0;
-      for (int s : C.sc_slot) H->ledger[9] += 32.0 * dim_after(P.slot_a[s], c) * dim_after(P.slot_b[s], c);
+      for (size_t x = 0; x < C.sc_slot.size(); ++x) {
+        if (C.sc_sp[4 * x] > 0) continue;  // a later chunk of a split task: same block
+        const int s = C.sc_slot[x];
+        H->ledger[9] += 32.0 * dim_after(P.slot_a[s], c) * dim_after(P.slot_b[s], c);
+      }
     };
     for (int c = 0; c < P.ncol; ++c) {
       flush_bytes(P.cols[c], c - 1);

@@ -1943,40 +1943,79 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
   if (tr * 64 >= ma || tc * 64 >= mb) return;
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
+  const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
+  const int part = c.sc_sp[4 * task], nparts = c.sc_sp[4 * task + 1];
   const int e_end = c.sc_cptr[task + 1];
   int e = c.sc_cptr[task];
   SchurTerm cur;
   while (e < e_end && !schur_term(v, c, e, tr, tc, cur)) ++e;
-  if (e >= e_end) return;  // nothing eliminated against this block
+  if (e >= e_end && nparts == 1) return;  // nothing eliminated against this block
   const int na = v.n[a];
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
   TileAcc<R> acc;
   acc.zero();
-  SlabRegs<double2> regs;
-  int k0 = 0;
-  const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
-  slab_fetch<double2>(regs, cur.C, cur.ldc, OP_N, cur.R, cur.ldr, OP_N, m, nn, cur.r, 0);
-  while (true) {
-    const int nk = min(TK, cur.r - k0);
-    __syncthreads();
-    slab_store<R, double2>(s, regs, OP_N, OP_N);
-    __syncthreads();
-    SchurTerm nxt = cur;
-    int nk0 = k0 + TK;
-    bool more = true;
-    if (nk0 >= cur.r) {
-      nk0 = 0;
-      ++e;
-      while (e < e_end && !schur_term(v, c, e, tr, tc, nxt)) ++e;
-      more = e < e_end;
+  if (e < e_end) {
+    SlabRegs<double2> regs;
+    int k0 = 0;
+    slab_fetch<double2>(regs, cur.C, cur.ldc, OP_N, cur.R, cur.ldr, OP_N, m, nn, cur.r, 0);
+    while (true) {
+      const int nk = min(TK, cur.r - k0);
+      __syncthreads();
+      slab_store<R, double2>(s, regs, OP_N, OP_N);
+      __syncthreads();
+      SchurTerm nxt = cur;
+      int nk0 = k0 + TK;
+      bool more = true;
+      if (nk0 >= cur.r) {
+        nk0 = 0;
+        ++e;
+        while (e < e_end && !schur_term(v, c, e, tr, tc, nxt)) ++e;
+        more = e < e_end;
+      }
+      if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
+      mma_slab_bal<R>(s, acc, nk, mt, nt);
+      if (!more) break;
+      cur = nxt;
+      k0 = nk0;
     }
-    if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
-    mma_slab_bal<R>(s, acc, nk, mt, nt);
-    if (!more) break;
-    cur = nxt;
-    k0 = nk0;
   }
-  store_tile_bal_sub<R, double2>(acc, Z, na, m, nn, mt, nt);
+  if (nparts == 1) {
+    store_tile_bal_sub<R, double2>(acc, Z, na, m, nn, mt, nt);
+    return;
+  }
+  // a chunk of a split task: its partial tile goes to scratch (k_schur_reduce adds the chunks)
+  const int64_t tt = (int64_t)c.tiles * c.tiles;
+  double2* Pc = c.sc_part + (((int64_t)c.sc_sp[4 * task + 2] + part) * tt + blockIdx.y) * 4096;
+  store_tile_bal_set<R, double2>(acc, Pc, 64, m, nn, mt, nt);
+}
+
+// Split tasks: Z -= the sum of the chunks' partial tiles, added in chunk order
+// (one workgroup per group and tile).
+__global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c) {
+  const int task = c.sc_gtask[blockIdx.x];
+  const int sl = c.sc_slot[task];
+  const int a = v.slot_a[sl], b = v.slot_b[sl];
+  const int ma = dim_after(v, a, c.colour), mb = dim_after(v, b, c.colour);
+  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  if (tr * 64 >= ma || tc * 64 >= mb) return;
+  const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
+  const int nparts = c.sc_sp[4 * task + 1];
+  const int64_t tt = (int64_t)c.tiles * c.tiles;
+  const double2* P0 = c.sc_part + ((int64_t)c.sc_sp[4 * task + 2] * tt + blockIdx.y) * 4096;
+  const int na = v.n[a];
+  double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
+  for (int q = threadIdx.x; q < m * nn; q += blockDim.x) {
+    const int i = q % m, j = q / m;
+    double2 sum = make_double2(0, 0);
+    for (int ch = 0; ch < nparts; ++ch) {
+      const double2 pv = P0[(int64_t)ch * tt * 4096 + i + 64 * j];
+      sum.x += pv.x;
+      sum.y += pv.y;
+    }
+    double2* z = Z + i + (int64_t)j * na;
+    const double2 o = *z;
+    *z = make_double2(o.x - sum.x, o.y - sum.y);
+  }
 }
 
 // The mixed form splits every flush: terms of clusters whose panels show no
@@ -1985,16 +2024,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.nsc <= 0) return;
   const dim3 grid(c.nsc, c.tiles * c.tiles);
+  const dim3 rgrid(c.ngrp > 0 ? c.ngrp : 1, c.tiles * c.tiles);
   if (mixed) {
     ColourTasks c1 = c, c0 = c;
     c1.term_sel = 1;
     c0.term_sel = 0;
     hipLaunchKernelGGL(k_schur<float>, grid, dim3(256), 0, st, v, c1);
+    if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c1);
     hipLaunchKernelGGL(k_schur<double>, grid, dim3(256), 0, st, v, c0);
+    if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c0);
   } else {
     ColourTasks ca = c;
     ca.term_sel = -1;
     hipLaunchKernelGGL(k_schur<double>, grid, dim3(256), 0, st, v, ca);
+    if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, ca);
   }
 }
 

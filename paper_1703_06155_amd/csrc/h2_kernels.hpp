@@ -76,6 +76,9 @@ struct ColourTasks {
   const int32_t* pj_slot; const int64_t* pj_toff; int npj;   // projection slots, temp offsets
   const int32_t* sc_slot; const int32_t* sc_cptr; const int32_t* sc_i; const int32_t* sc_ja;
   const int32_t* sc_jb; int nsc;          // Schur targets and their contributions
+  const int32_t* sc_sp;                   // per task {chunk, chunks, first partial slot, group}
+  const int32_t* sc_gtask; int ngrp;      // split groups: first task of each
+  double2* sc_part;                       // partial tiles of split tasks
   const int32_t* pn_i; const int32_t* pn_ja; int npn;          // panel tasks (i, partner pos)
   const int32_t* sv_cl; const int32_t* sv_cptr; const int32_t* sv_i; const int32_t* sv_ja;
   int nsv;                                // solve gather targets and contributions
@@ -130,6 +133,7 @@ constexpr int GRAM_SPLIT = 16;  // partial sums of the Step 0 Gram
 // at most this multiple of the largest entry of the blocks they were formed from.
 constexpr double F32_KAPPA = 8.0;
 constexpr int STEP0_DMAX = 512;  // largest cluster complement n - k (Step 0, Step 1, partial LU)
+constexpr int SCHUR_CHUNK_TERMS = 6;  // Schur tasks with more terms are split along the contraction
 constexpr int LU_LDS_MAX = 96;  // Step 3a keeps F in LDS up to this many rows, else in scratch
 void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);

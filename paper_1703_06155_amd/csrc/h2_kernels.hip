@@ -1912,10 +1912,11 @@ struct SchurTerm {
   int ldc, ldr, r;
 };
 
-__device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks& c, int e, int tr, int tc,
+// sel: -1 every term, 1 only terms of clusters whose FP32 Schur terms are safe, 0 the others
+__device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks& c, int e, int tr, int tc, int sel,
                                            SchurTerm& t) {
   const int i = c.sc_i[e];
-  if (c.term_sel >= 0 && (v.f32_ok[i] != 0) != (c.term_sel != 0)) return false;
+  if (sel >= 0 && (v.f32_ok[i] != 0) != (sel != 0)) return false;
   const int n = v.n[i], kt = v.kt[i];
   t.r = n - kt;
   if (t.r <= 0) return false;
@@ -1932,10 +1933,53 @@ __device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks
 // -C_a R_b.  The contraction runs over the concatenated ranks of all pending
 // terms as one stream of K slabs, with the next slab (possibly of the next
 // term) in flight while the current one is multiplied.  Block dimensions are
-// those after colour c.colour (kept rows for processed clusters).
+// those after colour c.colour (kept rows for processed clusters).  The mixed
+// form (MIX) multiplies the slabs of terms whose clusters' panels show no
+// growth on FP32 matrix cores into a second set of accumulators, folded into
+// the FP64 ones at the end; the other terms (where the update nearly cancels
+// the block and FP32 rounding would dominate) stay in FP64.
+union SchurSmem {
+  TileSmem<double> d;
+  TileSmem<float> f;
+};
+static_assert(sizeof(SchurSmem) >= 2 * 64 * 64 * sizeof(float), "slab LDS holds one 64 x 64 complex FP32 tile");
+
+// acc += sum over the task's terms selected by sel of C_a R_b (one K stream)
 template <typename R>
+__device__ __forceinline__ void schur_stream(const LevelView& v, const ColourTasks& c, int e, int e_end, int tr,
+                                             int tc, int m, int nn, int mt, int nt, int sel, TileSmem<R>& s,
+                                             TileAcc<R>& acc) {
+  SchurTerm cur;
+  while (e < e_end && !schur_term(v, c, e, tr, tc, sel, cur)) ++e;
+  if (e >= e_end) return;
+  SlabRegs<double2> regs;
+  int k0 = 0;
+  slab_fetch<double2>(regs, cur.C, cur.ldc, OP_N, cur.R, cur.ldr, OP_N, m, nn, cur.r, 0);
+  while (true) {
+    const int nk = min(TK, cur.r - k0);
+    __syncthreads();
+    slab_store<R, double2>(s, regs, OP_N, OP_N);
+    __syncthreads();
+    SchurTerm nxt = cur;
+    int nk0 = k0 + TK;
+    bool more = true;
+    if (nk0 >= cur.r) {
+      nk0 = 0;
+      ++e;
+      while (e < e_end && !schur_term(v, c, e, tr, tc, sel, nxt)) ++e;
+      more = e < e_end;
+    }
+    if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
+    mma_slab_bal<R>(s, acc, nk, mt, nt);
+    if (!more) break;
+    cur = nxt;
+    k0 = nk0;
+  }
+}
+
+template <bool MIX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur(LevelView v, ColourTasks c) {
-  __shared__ TileSmem<R> s;
+  __shared__ SchurSmem s;
   const int task = blockIdx.x;
   const int sl = c.sc_slot[task];
   const int a = v.slot_a[sl], b = v.slot_b[sl];
@@ -1945,48 +1989,66 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
   const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
   const int part = c.sc_sp[4 * task], nparts = c.sc_sp[4 * task + 1];
-  const int e_end = c.sc_cptr[task + 1];
-  int e = c.sc_cptr[task];
-  SchurTerm cur;
-  while (e < e_end && !schur_term(v, c, e, tr, tc, cur)) ++e;
-  if (e >= e_end && nparts == 1) return;  // nothing eliminated against this block
+  const int e0 = c.sc_cptr[task], e_end = c.sc_cptr[task + 1];
+  {
+    int e = e0;
+    SchurTerm t;
+    while (e < e_end && !schur_term(v, c, e, tr, tc, -1, t)) ++e;
+    if (e >= e_end && nparts == 1) return;  // nothing eliminated against this block
+  }
   const int na = v.n[a];
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
-  TileAcc<R> acc;
+  TileAcc<double> acc;
   acc.zero();
-  if (e < e_end) {
-    SlabRegs<double2> regs;
-    int k0 = 0;
-    slab_fetch<double2>(regs, cur.C, cur.ldc, OP_N, cur.R, cur.ldr, OP_N, m, nn, cur.r, 0);
-    while (true) {
-      const int nk = min(TK, cur.r - k0);
-      __syncthreads();
-      slab_store<R, double2>(s, regs, OP_N, OP_N);
-      __syncthreads();
-      SchurTerm nxt = cur;
-      int nk0 = k0 + TK;
-      bool more = true;
-      if (nk0 >= cur.r) {
-        nk0 = 0;
-        ++e;
-        while (e < e_end && !schur_term(v, c, e, tr, tc, nxt)) ++e;
-        more = e < e_end;
+  if (MIX) {
+    // FP32 terms first; their sums then seed the FP64 accumulators (through LDS:
+    // the two MFMA shapes place a block's elements on different lanes), so the
+    // two accumulator sets are never live together
+    TileAcc<float> accf;
+    accf.zero();
+    schur_stream<float>(v, c, e0, e_end, tr, tc, m, nn, mt, nt, 1, s.f, accf);
+    float* fre = reinterpret_cast<float*>(&s);
+    float* fim = fre + 64 * 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int cnt = mt * nt, per = (cnt + 3) >> 2;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kb = w * per + j;
+      if (j >= per || kb >= cnt) continue;
+      const int rb = kb % mt, cb = kb / mt;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = rb * 16 + (lane & 15) + 64 * (cb * 16 + acc_col<float>(lane, q));
+        fre[o] = accf.re[j >> 1][j & 1][q];
+        fim[o] = accf.im[j >> 1][j & 1][q];
       }
-      if (more) slab_fetch<double2>(regs, nxt.C, nxt.ldc, OP_N, nxt.R, nxt.ldr, OP_N, m, nn, nxt.r, nk0);
-      mma_slab_bal<R>(s, acc, nk, mt, nt);
-      if (!more) break;
-      cur = nxt;
-      k0 = nk0;
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kb = w * per + j;
+      if (j >= per || kb >= cnt) continue;
+      const int rb = kb % mt, cb = kb / mt;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = rb * 16 + (lane & 15) + 64 * (cb * 16 + acc_col<double>(lane, q));
+        acc.re[j >> 1][j & 1][q] = (double)fre[o];
+        acc.im[j >> 1][j & 1][q] = (double)fim[o];
+      }
+    }
+    schur_stream<double>(v, c, e0, e_end, tr, tc, m, nn, mt, nt, 0, s.d, acc);
+  } else {
+    schur_stream<double>(v, c, e0, e_end, tr, tc, m, nn, mt, nt, -1, s.d, acc);
   }
   if (nparts == 1) {
-    store_tile_bal_sub<R, double2>(acc, Z, na, m, nn, mt, nt);
+    store_tile_bal_sub<double, double2>(acc, Z, na, m, nn, mt, nt);
     return;
   }
   // a chunk of a split task: its partial tile goes to scratch (k_schur_reduce adds the chunks)
   const int64_t tt = (int64_t)c.tiles * c.tiles;
   double2* Pc = c.sc_part + (((int64_t)c.sc_sp[4 * task + 2] + part) * tt + blockIdx.y) * 4096;
-  store_tile_bal_set<R, double2>(acc, Pc, 64, m, nn, mt, nt);
+  store_tile_bal_set<double, double2>(acc, Pc, 64, m, nn, mt, nt);
 }
 
 // Split tasks: Z -= the sum of the chunks' partial tiles, added in chunk order
@@ -2018,27 +2080,14 @@ __global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c
   }
 }
 
-// The mixed form splits every flush: terms of clusters whose panels show no
-// growth run on FP32 matrix cores, the others (where the Schur update nearly
-// cancels the block and FP32 rounding would dominate) in FP64.
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.nsc <= 0) return;
-  const dim3 grid(c.nsc, c.tiles * c.tiles);
-  const dim3 rgrid(c.ngrp > 0 ? c.ngrp : 1, c.tiles * c.tiles);
-  if (mixed) {
-    ColourTasks c1 = c, c0 = c;
-    c1.term_sel = 1;
-    c0.term_sel = 0;
-    hipLaunchKernelGGL(k_schur<float>, grid, dim3(256), 0, st, v, c1);
-    if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c1);
-    hipLaunchKernelGGL(k_schur<double>, grid, dim3(256), 0, st, v, c0);
-    if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c0);
-  } else {
-    ColourTasks ca = c;
-    ca.term_sel = -1;
-    hipLaunchKernelGGL(k_schur<double>, grid, dim3(256), 0, st, v, ca);
-    if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, ca);
-  }
+  const dim3 grid(c.nsc, c.tiles * c.tiles), rgrid(c.ngrp > 0 ? c.ngrp : 1, c.tiles * c.tiles);
+  if (mixed)
+    hipLaunchKernelGGL(k_schur<true>, grid, dim3(256), 0, st, v, c);
+  else
+    hipLaunchKernelGGL(k_schur<false>, grid, dim3(256), 0, st, v, c);
+  if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c);
 }
 
 // f32_ok[i]: the FP32 rounding of cluster i's Schur terms, about

@@ -84,7 +84,6 @@ struct ColourTasks {
   int nsv;                                // solve gather targets and contributions
   int colour;
   int tiles;                              // 64-wide tiles per block side (ceil(max n / 64))
-  int term_sel;                           // Schur flush: -1 every term, 1 FP32-safe terms only, 0 the others
 };
 
 // Generic host-resolved batched GEMM task: C (op)= op(A) op(B).

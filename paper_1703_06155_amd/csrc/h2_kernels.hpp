@@ -132,7 +132,7 @@ constexpr int GRAM_SPLIT = 16;  // partial sums of the Step 0 Gram
 // at most this multiple of the largest entry of the blocks they were formed from.
 constexpr double F32_KAPPA = 8.0;
 constexpr int STEP0_DMAX = 512;  // largest cluster complement n - k (Step 0, Step 1, partial LU)
-constexpr int SCHUR_CHUNK_TERMS = 6;  // Schur tasks with more terms are split along the contraction
+constexpr int SCHUR_CHUNK_TERMS = 10;  // Schur tasks with more terms are split along the contraction
 constexpr int LU_LDS_MAX = 96;  // Step 3a keeps F in LDS up to this many rows, else in scratch
 void launch_householder_perp(const LevelView& v, int nc, hipStream_t st);
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st);

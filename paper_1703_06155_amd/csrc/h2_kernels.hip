@@ -590,7 +590,41 @@ void launch_householder_perp(const LevelView& v, int nc, hipStream_t st) {
 // Step 0 Gram of the fill-ins in block row i: H_i = sum_b F_ib F_ib^H, split over
 // GRAM_SPLIT partial sums (partner j goes to part j % GRAM_SPLIT) that
 // k_gram_fill_reduce adds in a fixed order.  Partial j of colour cluster x sits at
-// part + j * pstride + x * (64 tiles)^2.  grid: (cluster, tiles^2, part)
+// part + j * pstride + x * (64 tiles)^2.  grid: (cluster, tiles^2, part).  The
+// partners of a part form one K stream with the next slab always in flight, and
+// the tile's 16 x 16 output blocks are dealt evenly to the four wavefronts.
+struct GramTerm {
+  const double2* A;
+  const double2* B;
+  int64_t lda, ldb;
+  int opA, opB, K;
+};
+
+__device__ __forceinline__ bool gram_term(const LevelView& v, const ColourTasks& c, int i, int j, int tr, int tc,
+                                          GramTerm& t) {
+  const int b = v.fp_cl[j];
+  const int code = v.fp_srow[j];
+  t.K = dim_before(v, b, c.colour);
+  if (t.K <= 0) return false;
+  if (code >= 0) {  // F_ib stored as (i, b): n x m_b, ld n
+    const int n = v.n[i];
+    const double2* F = v.slots + v.slot_off[code];
+    t.A = F + tr * 64;
+    t.B = F + tc * 64;
+    t.lda = t.ldb = n;
+    t.opA = OP_N;
+    t.opB = OP_C;
+  } else {  // stored as (b, i): F_ib = S^T with S m_b x n, ld n_b
+    const int nb = v.n[b];
+    const double2* Sb = v.slots + v.slot_off[~code];
+    t.A = Sb + (int64_t)tr * 64 * nb;
+    t.B = Sb + (int64_t)tc * 64 * nb;
+    t.lda = t.ldb = nb;
+    t.opA = OP_T;
+    t.opB = OP_R;
+  }
+  return true;
+}
 
 __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, double2* part, int64_t pstride) {
   __shared__ TileSmem<double> s;
@@ -600,25 +634,41 @@ __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, d
   const int sp = blockIdx.z;
   if (tr * 64 >= n || tc * 64 >= n) return;
   const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
+  const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
   TileAcc<double> acc;
   acc.zero();
-  for (int j = v.fp_ptr[i] + sp; j < v.fp_ptr[i + 1]; j += GRAM_SPLIT) {
-    const int b = v.fp_cl[j];
-    const int code = v.fp_srow[j];
-    const int mb = dim_before(v, b, c.colour);
-    if (code >= 0) {  // F_ib stored as (i, b): n x m_b, ld n
-      const double2* F = v.slots + v.slot_off[code];
-      gemm_tile<double, double2>(s, acc, F + tr * 64, n, OP_N, F + tc * 64, n, OP_C, m, nn, mb);
-    } else {  // stored as (b, i): F_ib = S^T with S m_b x n, ld n_b
-      const double2* Sb = v.slots + v.slot_off[~code];
-      const int nb = v.n[b];
-      gemm_tile<double, double2>(s, acc, Sb + (int64_t)tr * 64 * nb, nb, OP_T, Sb + (int64_t)tc * 64 * nb, nb, OP_R,
-                                 m, nn, mb);
+  const int j_end = v.fp_ptr[i + 1];
+  int j = v.fp_ptr[i] + sp;
+  GramTerm cur;
+  while (j < j_end && !gram_term(v, c, i, j, tr, tc, cur)) j += GRAM_SPLIT;
+  if (j < j_end) {
+    SlabRegs<double2> regs;
+    int k0 = 0;
+    slab_fetch<double2>(regs, cur.A, cur.lda, cur.opA, cur.B, cur.ldb, cur.opB, m, nn, cur.K, 0);
+    while (true) {
+      const int nk = min(TK, cur.K - k0);
+      __syncthreads();
+      slab_store<double, double2>(s, regs, cur.opA, cur.opB);
+      __syncthreads();
+      GramTerm nxt = cur;
+      int nk0 = k0 + TK;
+      bool more = true;
+      if (nk0 >= cur.K) {
+        nk0 = 0;
+        j += GRAM_SPLIT;
+        while (j < j_end && !gram_term(v, c, i, j, tr, tc, nxt)) j += GRAM_SPLIT;
+        more = j < j_end;
+      }
+      if (more) slab_fetch<double2>(regs, nxt.A, nxt.lda, nxt.opA, nxt.B, nxt.ldb, nxt.opB, m, nn, nxt.K, nk0);
+      mma_slab_bal<double>(s, acc, nk, mt, nt);
+      if (!more) break;
+      cur = nxt;
+      k0 = nk0;
     }
   }
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
   double2* P = part + (int64_t)sp * pstride + (int64_t)blockIdx.x * cstride;
-  store_tile<double, double2>(acc, P + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
+  store_tile_bal_set<double, double2>(acc, P + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, mt, nt);
 }
 
 // H_i = sum of the partial Grams in a fixed order (deterministic)
@@ -2051,8 +2101,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   store_tile_bal_set<double, double2>(acc, Pc, 64, m, nn, mt, nt);
 }
 
-// Split tasks: Z -= the sum of the chunks' partial tiles, added in chunk order
-// (one workgroup per group and tile).
+// Split tasks: Z -= the sum of the chunks' partial tiles, added in chunk order.
+// grid: (group, tiles^2, 4); each workgroup takes a quarter of the tile's
+// elements, four per thread, with the block values and all four elements'
+// partials of a chunk in flight together.
 __global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c) {
   const int task = c.sc_gtask[blockIdx.x];
   const int sl = c.sc_slot[task];
@@ -2066,23 +2118,38 @@ __global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c
   const double2* P0 = c.sc_part + ((int64_t)c.sc_sp[4 * task + 2] * tt + blockIdx.y) * 4096;
   const int na = v.n[a];
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
-  for (int q = threadIdx.x; q < m * nn; q += blockDim.x) {
-    const int i = q % m, j = q / m;
-    double2 sum = make_double2(0, 0);
-    for (int ch = 0; ch < nparts; ++ch) {
-      const double2 pv = P0[(int64_t)ch * tt * 4096 + i + 64 * j];
-      sum.x += pv.x;
-      sum.y += pv.y;
-    }
-    double2* z = Z + i + (int64_t)j * na;
-    const double2 o = *z;
-    *z = make_double2(o.x - sum.x, o.y - sum.y);
+  int off[4];
+  bool ok[4];
+  double2 zv[4], sum[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = blockIdx.z * 1024 + u * 256 + threadIdx.x;  // element (q % 64, q / 64) of the tile
+    const int i = q & 63, j = q >> 6;
+    ok[u] = i < m && j < nn;
+    off[u] = i + 64 * j;
+    zv[u] = ok[u] ? Z[i + (int64_t)j * na] : make_double2(0, 0);
+    sum[u] = make_double2(0, 0);
   }
+#pragma unroll 2
+  for (int ch = 0; ch < nparts; ++ch) {
+    const double2* Pc = P0 + (int64_t)ch * tt * 4096;
+    double2 pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pv[u] = ok[u] ? Pc[off[u]] : make_double2(0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sum[u].x += pv[u].x;
+      sum[u].y += pv[u].y;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (ok[u]) Z[(off[u] & 63) + (int64_t)(off[u] >> 6) * na] = make_double2(zv[u].x - sum[u].x, zv[u].y - sum[u].y);
 }
 
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.nsc <= 0) return;
-  const dim3 grid(c.nsc, c.tiles * c.tiles), rgrid(c.ngrp > 0 ? c.ngrp : 1, c.tiles * c.tiles);
+  const dim3 grid(c.nsc, c.tiles * c.tiles), rgrid(c.ngrp > 0 ? c.ngrp : 1, c.tiles * c.tiles, 4);
   if (mixed)
     hipLaunchKernelGGL(k_schur<true>, grid, dim3(256), 0, st, v, c);
   else

@@ -272,80 +272,13 @@ __device__ __forceinline__ void load_a(TileSmem<R>& s, const CT* __restrict__ A,
   }
 }
 
-// How the four wavefronts share a tile of m x n outputs (uniform over the
-// block).  SPLIT_4: each wave owns one 32x32 quadrant.  SPLIT_ROWS (n <= 32)
-// and SPLIT_COLS (m <= 32): two quadrants, two waves per quadrant taking
-// alternate 4-wide k-steps.  SPLIT_1 (m, n <= 32): one quadrant, each wave one
-// k-step of four.  Waves whose own quadrant lies outside the tile are helpers;
-// tile_reduce adds their partial sums into the quadrant owners.
-enum TileSplit { SPLIT_4 = 0, SPLIT_ROWS = 1, SPLIT_COLS = 2, SPLIT_1 = 3 };
-
-__device__ __forceinline__ int tile_split(int m, int n) {
-  if (m > 32 && n > 32) return SPLIT_4;
-  if (m > 32) return SPLIT_ROWS;
-  if (n > 32) return SPLIT_COLS;
-  return SPLIT_1;
-}
-
 // acc += op(A_tile) * op(B_tile) for the first nk (<= TK, uniform over the
-// block) k-columns of one slab resident in LDS; the slab is zero beyond its
-// K range, so only whole 4-wide MFMA steps past nk are skipped, and so are the
-// 16 x 16 output blocks outside the m x n tile.
-template <typename R>
-__device__ __forceinline__ void mma_slab(const TileSmem<R>& s, TileAcc<R>& acc, int nk = TK, int split = SPLIT_4,
-                                         int m = TM, int n = TN) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int li = lane & 15, lk = lane >> 4;
-  int qr = wr, qc = wc, kfirst = 0, kstep = 1;
-  if (split == SPLIT_ROWS) {
-    qc = 0;
-    kfirst = wc;
-    kstep = 2;
-  } else if (split == SPLIT_COLS) {
-    qr = 0;
-    kfirst = wr;
-    kstep = 2;
-  } else if (split == SPLIT_1) {
-    qr = qc = 0;
-    kfirst = w;
-    kstep = 4;
-  }
-#pragma unroll
-  for (int q = 0; q < TK / 4; ++q) {
-    const int kq = kfirst + q * kstep;
-    if (kq >= TK / 4 || kq * 4 >= nk) break;
-    const int kk = kq * 4 + lk;
-    R ar[2], ai[2], nai[2], br[2], bi[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      ar[t] = s.are[kk][qr * 32 + t * 16 + li];
-      ai[t] = s.aim[kk][qr * 32 + t * 16 + li];
-      nai[t] = -ai[t];
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      br[u] = s.bre[kk][qc * 32 + u * 16 + li];
-      bi[u] = s.bim[kk][qc * 32 + u * 16 + li];
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        if (qr * 32 + t * 16 >= m || qc * 32 + u * 16 >= n) continue;
-        // C^T = op(B)^T op(A)^T : pass the B fragment as the MFMA's first operand
-        acc.re[t][u] = mfma16(br[u], ar[t], acc.re[t][u]);
-        acc.re[t][u] = mfma16(bi[u], nai[t], acc.re[t][u]);
-        acc.im[t][u] = mfma16(br[u], ai[t], acc.im[t][u]);
-        acc.im[t][u] = mfma16(bi[u], ar[t], acc.im[t][u]);
-      }
-  }
-}
-
-// Balanced variant: the tile's mt x nt active 16 x 16 output blocks (block k at
-// row block k % mt, column block k / mt) are dealt to the four wavefronts in
-// contiguous runs of ceil(mt nt / 4), so no wavefront carries more than that;
-// wavefront w keeps its j-th block in accumulator slot j (re[j >> 1][j & 1]).
+// block) k-columns of one slab resident in LDS (zero beyond its K range, so only
+// whole 4-wide MFMA steps past nk are skipped).  The tile's mt x nt active 16 x 16
+// output blocks (block k at row block k % mt, column block k / mt) are dealt to
+// the four wavefronts in contiguous runs of ceil(mt nt / 4), so no wavefront
+// carries more than that; wavefront w keeps its j-th block in accumulator slot j
+// (re[j >> 1][j & 1]).
 template <typename R>
 __device__ __forceinline__ void mma_slab_bal(const TileSmem<R>& s, TileAcc<R>& acc, int nk, int mt, int nt) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -415,69 +348,13 @@ __device__ __forceinline__ void store_tile_bal_set(const TileAcc<R>& acc, CT* C,
   }
 }
 
-// Partial sums of helper waves -> quadrant owners, through the slab LDS (all
-// threads call it; the slab contents are dead afterwards).  Helpers end with
-// zero accumulators, so a later contraction into the same tile stays correct.
-template <typename R>
-__device__ __forceinline__ void tile_reduce(TileSmem<R>& s, TileAcc<R>& acc, int split) {
-  if (split == SPLIT_4) return;
-  static_assert(sizeof(TileSmem<R>) >= 2 * 32 * 64 * sizeof(R), "slab LDS too small for the reduction");
-  R* buf = reinterpret_cast<R*>(&s);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  auto put = [&](int slot) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int q = ((t * 2 + u) * 4 + v) * 2;
-          buf[((slot * 32) + q) * 64 + lane] = acc.re[t][u][v];
-          buf[((slot * 32) + q + 1) * 64 + lane] = acc.im[t][u][v];
-        }
-  };
-  auto add = [&](int slot) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int q = ((t * 2 + u) * 4 + v) * 2;
-          acc.re[t][u][v] += buf[((slot * 32) + q) * 64 + lane];
-          acc.im[t][u][v] += buf[((slot * 32) + q + 1) * 64 + lane];
-        }
-  };
-  __syncthreads();
-  bool owner;
-  if (split == SPLIT_ROWS) {  // helpers 1 -> 0, 3 -> 2
-    owner = !(w & 1);
-    if (!owner) put(w >> 1);
-    __syncthreads();
-    if (owner) add(w >> 1);
-  } else {  // SPLIT_COLS: helpers 2 -> 0, 3 -> 1; SPLIT_1: then 1 -> 0
-    owner = (split == SPLIT_COLS) ? (w < 2) : (w == 0);
-    if (w >= 2) put(w - 2);
-    __syncthreads();
-    if (w < 2) add(w);
-    if (split == SPLIT_1) {
-      __syncthreads();
-      if (w == 1) put(0);
-      __syncthreads();
-      if (w == 0) add(0);
-    }
-  }
-  if (!owner) acc.zero();
-  __syncthreads();
-}
-
 // acc += op(A)[0:m, 0:K] * op(B)[0:K, 0:n] (m, n <= 64), with the next slab's
 // global loads in flight while the current slab is multiplied.
 template <typename R, typename CT>
 __device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const CT* A, int64_t lda, int opA,
                                           const CT* B, int64_t ldb, int opB, int m, int n, int K) {
   if (K <= 0) return;
-  const int split = tile_split(m, n);
+  const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
   SlabRegs<CT> r;
   slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, 0);
   for (int k0 = 0; k0 < K; k0 += TK) {
@@ -485,82 +362,41 @@ __device__ __forceinline__ void gemm_tile(TileSmem<R>& s, TileAcc<R>& acc, const
     slab_store<R, CT>(s, r, opA, opB);
     __syncthreads();
     if (k0 + TK < K) slab_fetch<CT>(r, A, lda, opA, B, ldb, opB, m, n, K, k0 + TK);
-    mma_slab<R>(s, acc, min(TK, K - k0), split, m, n);
+    mma_slab_bal<R>(s, acc, min(TK, K - k0), mt, nt);
   }
-  tile_reduce<R>(s, acc, split);
 }
 
-// Per-thread prefetch of the 16 elements of C that this thread's accumulators cover.
-template <typename R, typename CT>
-struct TilePre {
-  CT c[2][2][4];
-};
-
-template <typename R, typename CT>
-__device__ __forceinline__ void prefetch_tile(TilePre<R, CT>& p, const CT* C, int64_t ldc, int m, int n) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + t * 16 + (lane & 15);
-        const int j = wc * 32 + u * 16 + acc_col<R>(lane, v);
-        p.c[t][u][v] = (i < m && j < n) ? C[i + (int64_t)j * ldc] : CT{0, 0};
-      }
-}
-
-// C = pre - acc for a tile prefetched with prefetch_tile.
-template <typename R, typename CT>
-__device__ __forceinline__ void store_tile_sub_pre(const TileAcc<R>& acc, const TilePre<R, CT>& p, CT* C, int64_t ldc,
-                                                   int m, int n) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + t * 16 + (lane & 15);
-        const int j = wc * 32 + u * 16 + acc_col<R>(lane, v);
-        if (i < m && j < n) {
-          const CT o = p.c[t][u][v];
-          C[i + (int64_t)j * ldc] = CT{o.x - acc.re[t][u][v], o.y - acc.im[t][u][v]};
-        }
-      }
-}
-
-// C[0:m, 0:n] (op)= acc, C column-major with leading dimension ldc.
+// C[0:m, 0:n] (op)= acc, C column-major with leading dimension ldc, for the
+// 16 x 16 blocks mma_slab_bal dealt to this wavefront (the same m, n).
 template <typename R, typename CT>
 __device__ __forceinline__ void store_tile(const TileAcc<R>& acc, CT* C, int64_t ldc, int m, int n,
                                            int mode) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
+  const int mt = (m + 15) >> 4, nt = (n + 15) >> 4;
+  const int cnt = mt * nt, per = (cnt + 3) >> 2, k0 = w * per;
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int j = 0; j < 4; ++j) {
+    const int kb = k0 + j;
+    if (j >= per || kb >= cnt) continue;
+    const int rb = kb % mt, cb = kb / mt;
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = wr * 32 + t * 16 + (lane & 15);
-        const int j = wc * 32 + u * 16 + acc_col<R>(lane, v);
-        if (i < m && j < n) {
-          CT* p = C + i + (int64_t)j * ldc;
-          R xr = acc.re[t][u][v], xi = acc.im[t][u][v];
-          if (mode == ST_SET) {
-            *p = CT{xr, xi};
-          } else {
-            CT o = *p;
-            if (mode == ST_ADD)
-              *p = CT{o.x + xr, o.y + xi};
-            else
-              *p = CT{o.x - xr, o.y - xi};
-          }
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb * 16 + (lane & 15), jj = cb * 16 + acc_col<R>(lane, v);
+      if (i < m && jj < n) {
+        CT* p = C + i + (int64_t)jj * ldc;
+        const R xr = acc.re[j >> 1][j & 1][v], xi = acc.im[j >> 1][j & 1][v];
+        if (mode == ST_SET) {
+          *p = CT{xr, xi};
+        } else {
+          const CT o = *p;
+          if (mode == ST_ADD)
+            *p = CT{o.x + xr, o.y + xi};
+          else
+            *p = CT{o.x - xr, o.y - xi};
         }
       }
+    }
+  }
 }
 
 }  // namespace h2

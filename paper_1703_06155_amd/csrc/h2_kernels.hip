@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) k_leaf_gram(GeomView g, const uint32_t* m
       }
     }
     __syncthreads();
-    mma_slab<double>(s, acc);
+    mma_slab_bal<double>(s, acc, TK, (m + 15) >> 4, (nn + 15) >> 4);
   }
   double2* G = part + (int64_t)ch * stride + goff[t] + tr * 64 + (int64_t)tc * 64 * n;
   store_tile<double, double2>(acc, G, n, m, nn, ST_SET);
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) k_proj_rows(GeomView g, const uint32_t* m
       }
     }
     __syncthreads();
-    mma_slab<double>(s, acc);
+    mma_slab_bal<double>(s, acc, TK, (m + 15) >> 4, (nn + 15) >> 4);
   }
   double2* out = Y + yoff[c] + tr * 64 + (int64_t)tc * 64 * yld[c];
   store_tile<double, double2>(acc, out, yld[c], m, nn, ST_SET);
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(256) k_coupling_x(GeomView g, const int32_t* p
       }
     }
     __syncthreads();
-    mma_slab<double>(s, acc);
+    mma_slab_bal<double>(s, acc, TK, (m + 15) >> 4, (nn + 15) >> 4);
   }
   store_tile<double, double2>(acc, X + xoff[p] + tr * 64 + (int64_t)tc * 64 * kt, kt, m, nn, ST_SET);
 }

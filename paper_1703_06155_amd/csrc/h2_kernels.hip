@@ -593,6 +593,8 @@ void launch_householder_perp(const LevelView& v, int nc, hipStream_t st) {
 // part + j * pstride + x * (64 tiles)^2.  grid: (cluster, tiles^2, part).  The
 // partners of a part form one K stream with the next slab always in flight, and
 // the tile's 16 x 16 output blocks are dealt evenly to the four wavefronts.
+constexpr int GRAM_RED_BLOCKS = 8;
+
 struct GramTerm {
   const double2* A;
   const double2* B;
@@ -671,14 +673,15 @@ __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, d
   store_tile_bal_set<double, double2>(acc, P + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, mt, nt);
 }
 
-// H_i = sum of the partial Grams in a fixed order (deterministic)
+// H_i = sum of the partial Grams in a fixed order (deterministic); grid (cluster,
+// GRAM_RED_BLOCKS) with the entries interleaved over the workgroups
 __global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* part, int64_t pstride) {
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i];
   double2* H = v.W + v.w_off[i];
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
   const double2* P0 = part + (int64_t)blockIdx.x * cstride;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < n * n; e += gridDim.y * blockDim.x) {
     double2 a = P0[e];
     for (int sp = 1; sp < GRAM_SPLIT; ++sp) a = cadd(a, P0[(int64_t)sp * pstride + e]);
     H[e] = a;
@@ -688,7 +691,7 @@ __global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* pa
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st) {
   if (c.ncl <= 0) return;
   hipLaunchKernelGGL(k_gram_fill, dim3(c.ncl, c.tiles * c.tiles, GRAM_SPLIT), dim3(256), 0, st, v, c, part, pstride);
-  hipLaunchKernelGGL(k_gram_fill_reduce, dim3(c.ncl), dim3(256), 0, st, v, c, part, pstride);
+  hipLaunchKernelGGL(k_gram_fill_reduce, dim3(c.ncl, GRAM_RED_BLOCKS), dim3(256), 0, st, v, c, part, pstride);
 }
 
 // phase 0: X = H B_perp ; phase 1: G' = B_perp^H X ; phase 2: Q~[:, k:n] = B_perp U'

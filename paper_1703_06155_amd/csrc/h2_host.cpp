@@ -132,8 +132,10 @@ struct ColourPlan {
   // ({-1, 1, 0, 0} when whole); nps partial slots and ngrp groups in all
   std::vector<int32_t> sc_sp, sc_gtask;
   int nps = 0, ngrp = 0;
+  // the same flush unsplit (one task per block), used when the partial tiles do not fit
+  std::vector<int32_t> sc_slot_u, sc_cptr_u, sc_sp_u;
   DArr<int32_t> d_cl, d_pj_slot, d_sc_slot, d_sc_cptr, d_sc_i, d_sc_ja, d_sc_jb, d_pn_i, d_pn_ja, d_sv_cl,
-      d_sv_cptr, d_sv_i, d_sv_ja, d_sc_sp, d_sc_gtask;
+      d_sv_cptr, d_sv_i, d_sv_ja, d_sc_sp, d_sc_gtask, d_sc_slot_u, d_sc_cptr_u, d_sc_sp_u;
   DArr<int64_t> d_pj_toff;
   std::vector<int64_t> pj_toff;
   int64_t temp_elems = 0;
@@ -403,6 +405,9 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     C.sc_sp.clear();
     C.sc_gtask.clear();
     C.nps = C.ngrp = 0;
+    C.sc_slot_u.clear();
+    C.sc_cptr_u.assign(1, 0);
+    C.sc_sp_u.clear();
     for (int s : slots) {
       auto& pl = pending[s];
       if (pl.empty()) continue;
@@ -428,6 +433,9 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
         C.nps += np;
         C.ngrp += 1;
       }
+      C.sc_slot_u.push_back(s);
+      C.sc_cptr_u.push_back((int32_t)C.sc_i.size());
+      C.sc_sp_u.insert(C.sc_sp_u.end(), {-1, 1, 0, 0});
       pl.clear();
       pl.shrink_to_fit();
     }
@@ -538,6 +546,9 @@ static void upload_plan(LevelPlan& P, hipStream_t st) {
     C.d_sc_jb.upload(C.sc_jb, st);
     C.d_sc_sp.upload(C.sc_sp, st);
     C.d_sc_gtask.upload(C.sc_gtask, st);
+    C.d_sc_slot_u.upload(C.sc_slot_u, st);
+    C.d_sc_cptr_u.upload(C.sc_cptr_u, st);
+    C.d_sc_sp_u.upload(C.sc_sp_u, st);
     C.d_pn_i.upload(C.pn_i, st);
     C.d_pn_ja.upload(C.pn_ja, st);
     C.d_sv_cl.upload(C.sv_cl, st);
@@ -552,6 +563,9 @@ static void upload_plan(LevelPlan& P, hipStream_t st) {
   P.fin.d_sc_jb.upload(P.fin.sc_jb, st);
   P.fin.d_sc_sp.upload(P.fin.sc_sp, st);
   P.fin.d_sc_gtask.upload(P.fin.sc_gtask, st);
+  P.fin.d_sc_slot_u.upload(P.fin.sc_slot_u, st);
+  P.fin.d_sc_cptr_u.upload(P.fin.sc_cptr_u, st);
+  P.fin.d_sc_sp_u.upload(P.fin.sc_sp_u, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1142,10 +1156,39 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);
-    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile)
+    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile), when that fits in a
+    // quarter of the free device memory; otherwise this level flushes every block whole
     int max_nps = P.fin.nps;
     for (const ColourPlan& C : P.cols) max_nps = std::max(max_nps, C.nps);
-    H->ws_scp.alloc((size_t)std::max<int64_t>(1, (int64_t)max_nps * F.tiles * F.tiles * 4096));
+    const size_t scp_elems = (size_t)std::max<int64_t>(1, (int64_t)max_nps * F.tiles * F.tiles * 4096);
+    bool split_ok = true;
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        const size_t have = H->ws_scp.cap * sizeof(double2);
+        split_ok = scp_elems * sizeof(double2) <= (have + fr) / 4;
+      }
+    }
+    if (split_ok) H->ws_scp.alloc(scp_elems);
+    auto schur_lists = [&](const ColourPlan& C, ColourTasks& ct) {
+      if (split_ok) {
+        ct.sc_slot = C.d_sc_slot.p;
+        ct.sc_cptr = C.d_sc_cptr.p;
+        ct.sc_sp = C.d_sc_sp.p;
+        ct.nsc = (int)C.sc_slot.size();
+        ct.sc_gtask = C.d_sc_gtask.p;
+        ct.ngrp = C.ngrp;
+        ct.sc_part = H->ws_scp.p;
+      } else {
+        ct.sc_slot = C.d_sc_slot_u.p;
+        ct.sc_cptr = C.d_sc_cptr_u.p;
+        ct.sc_sp = C.d_sc_sp_u.p;
+        ct.nsc = (int)C.sc_slot_u.size();
+        ct.sc_gtask = nullptr;
+        ct.ngrp = 0;
+        ct.sc_part = nullptr;
+      }
+    };
     // blocks of this level
     if (l == L) {
       slots.alloc(slot_off[P.nslot]);
@@ -1245,16 +1288,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       ct.pj_slot = C.d_pj_slot.p;
       ct.pj_toff = C.d_pj_toff.p;
       ct.npj = (int)C.pj_slot.size();
-      ct.sc_slot = C.d_sc_slot.p;
-      ct.sc_cptr = C.d_sc_cptr.p;
       ct.sc_i = C.d_sc_i.p;
       ct.sc_ja = C.d_sc_ja.p;
       ct.sc_jb = C.d_sc_jb.p;
-      ct.nsc = (int)C.sc_slot.size();
-      ct.sc_sp = C.d_sc_sp.p;
-      ct.sc_gtask = C.d_sc_gtask.p;
-      ct.ngrp = C.ngrp;
-      ct.sc_part = H->ws_scp.p;
+      schur_lists(C, ct);
       ct.pn_i = C.d_pn_i.p;
       ct.pn_ja = C.d_pn_ja.p;
       ct.npn = (int)C.pn_i.size();
@@ -1297,16 +1334,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     {
       // updates still pending at the end of the level
       ColourTasks ct{};
-      ct.sc_slot = P.fin.d_sc_slot.p;
-      ct.sc_cptr = P.fin.d_sc_cptr.p;
       ct.sc_i = P.fin.d_sc_i.p;
       ct.sc_ja = P.fin.d_sc_ja.p;
       ct.sc_jb = P.fin.d_sc_jb.p;
-      ct.nsc = (int)P.fin.sc_slot.size();
-      ct.sc_sp = P.fin.d_sc_sp.p;
-      ct.sc_gtask = P.fin.d_sc_gtask.p;
-      ct.ngrp = P.fin.ngrp;
-      ct.sc_part = H->ws_scp.p;
+      schur_lists(P.fin, ct);
       ct.colour = P.ncol - 1;
       ct.tiles = F.tiles;
       hipEvent_t es = ev.next(st);

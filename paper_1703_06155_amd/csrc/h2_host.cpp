@@ -128,14 +128,15 @@ struct ColourPlan {
   std::vector<int32_t> cl, pj_slot, sc_slot, sc_cptr, sc_i, sc_ja, sc_jb, pn_i, pn_ja, sv_cl, sv_cptr, sv_i,
       sv_ja;
   // Schur tasks with many terms are split along the contraction into chunks of at
-  // most SCHUR_CHUNK_TERMS terms: per task {chunk, chunks, first partial slot, group}
-  // ({-1, 1, 0, 0} when whole); nps partial slots and ngrp groups in all
+  // most SCHUR_CHUNK_TERMS terms: per task {chunk, chunks, chunks of earlier groups,
+  // group} ({-1, 1, 0, 0} when whole); nps chunks and ngrp groups in all
   std::vector<int32_t> sc_sp, sc_gtask;
+  std::vector<int32_t> sc_gbase;  // per group, set per factorization: first 64 x 64 partial tile
   int nps = 0, ngrp = 0;
   // the same flush unsplit (one task per block), used when the partial tiles do not fit
   std::vector<int32_t> sc_slot_u, sc_cptr_u, sc_sp_u;
   DArr<int32_t> d_cl, d_pj_slot, d_sc_slot, d_sc_cptr, d_sc_i, d_sc_ja, d_sc_jb, d_pn_i, d_pn_ja, d_sv_cl,
-      d_sv_cptr, d_sv_i, d_sv_ja, d_sc_sp, d_sc_gtask, d_sc_slot_u, d_sc_cptr_u, d_sc_sp_u;
+      d_sv_cptr, d_sv_i, d_sv_ja, d_sc_sp, d_sc_gtask, d_sc_slot_u, d_sc_cptr_u, d_sc_sp_u, d_sc_gbase;
   DArr<int64_t> d_pj_toff;
   std::vector<int64_t> pj_toff;
   int64_t temp_elems = 0;
@@ -980,6 +981,8 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
 
 static void dense_lu_inverse(h2_ctx* H, hipStream_t st);
 
+constexpr size_t SCHUR_PART_MAX_BYTES = size_t(8) << 30;
+
 static void release_factor_buffers(h2_ctx* H) {
   H->flev.clear();
   H->slot_buf[0].release();
@@ -1156,20 +1159,38 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);
-    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile), when that fits in a
-    // quarter of the free device memory; otherwise this level flushes every block whole
-    int max_nps = P.fin.nps;
-    for (const ColourPlan& C : P.cols) max_nps = std::max(max_nps, C.nps);
-    const size_t scp_elems = (size_t)std::max<int64_t>(1, (int64_t)max_nps * F.tiles * F.tiles * 4096);
+    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile), when that fits in
+    // SCHUR_PART_MAX_BYTES and an eighth of the free device memory (the buffer is kept
+    // for later factorizations; large allocations cost about 28 ms per GB); otherwise
+    // this level flushes every block whole
+    // A chunk of a split flush of block (a, b) keeps ceil(n_a / 64) ceil(n_b / 64) tiles.
+    auto group_bases = [&](ColourPlan& C) -> int64_t {
+      C.sc_gbase.resize(C.ngrp);
+      int64_t run = 0;
+      for (int g = 0; g < C.ngrp; ++g) {
+        const int task = C.sc_gtask[g], sl = C.sc_slot[task];
+        const int64_t ta = (F.n[P.slot_a[sl]] + 63) / 64, tb = (F.n[P.slot_b[sl]] + 63) / 64;
+        C.sc_gbase[g] = (int32_t)run;
+        run += (int64_t)C.sc_sp[4 * task + 1] * ta * tb;
+      }
+      return run;
+    };
+    int64_t max_tiles = group_bases(P.fin);
+    for (ColourPlan& C : P.cols) max_tiles = std::max(max_tiles, group_bases(C));
+    const size_t scp_elems = (size_t)std::max<int64_t>(1, max_tiles * 4096);
     bool split_ok = true;
     {
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
         const size_t have = H->ws_scp.cap * sizeof(double2);
-        split_ok = scp_elems * sizeof(double2) <= (have + fr) / 4;
+        split_ok = scp_elems * sizeof(double2) <= std::min(SCHUR_PART_MAX_BYTES, (have + fr) / 8);
       }
     }
-    if (split_ok) H->ws_scp.alloc(scp_elems);
+    if (split_ok) {
+      H->ws_scp.alloc(scp_elems);
+      P.fin.d_sc_gbase.upload(P.fin.sc_gbase, st);
+      for (ColourPlan& C : P.cols) C.d_sc_gbase.upload(C.sc_gbase, st);
+    }
     auto schur_lists = [&](const ColourPlan& C, ColourTasks& ct) {
       if (split_ok) {
         ct.sc_slot = C.d_sc_slot.p;
@@ -1177,6 +1198,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         ct.sc_sp = C.d_sc_sp.p;
         ct.nsc = (int)C.sc_slot.size();
         ct.sc_gtask = C.d_sc_gtask.p;
+        ct.sc_gbase = C.d_sc_gbase.p;
         ct.ngrp = C.ngrp;
         ct.sc_part = H->ws_scp.p;
       } else {
@@ -1185,6 +1207,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         ct.sc_sp = C.d_sc_sp_u.p;
         ct.nsc = (int)C.sc_slot_u.size();
         ct.sc_gtask = nullptr;
+        ct.sc_gbase = nullptr;
         ct.ngrp = 0;
         ct.sc_part = nullptr;
       }

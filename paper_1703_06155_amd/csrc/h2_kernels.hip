@@ -2098,9 +2098,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     store_tile_bal_sub<double, double2>(acc, Z, na, m, nn, mt, nt);
     return;
   }
-  // a chunk of a split task: its partial tile goes to scratch (k_schur_reduce adds the chunks)
-  const int64_t tt = (int64_t)c.tiles * c.tiles;
-  double2* Pc = c.sc_part + (((int64_t)c.sc_sp[4 * task + 2] + part) * tt + blockIdx.y) * 4096;
+  // a chunk of a split task: its partial tile goes to scratch (k_schur_reduce adds the
+  // chunks); the group keeps ta tb tiles per chunk, ta = ceil(n_a / 64), tb = ceil(n_b / 64)
+  const int ta = (na + 63) >> 6, tb = (v.n[b] + 63) >> 6;
+  double2* Pc = c.sc_part + ((int64_t)c.sc_gbase[c.sc_sp[4 * task + 3]] + (int64_t)part * ta * tb + tr + ta * tc) * 4096;
   store_tile_bal_set<double, double2>(acc, Pc, 64, m, nn, mt, nt);
 }
 
@@ -2117,9 +2118,10 @@ __global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c
   if (tr * 64 >= ma || tc * 64 >= mb) return;
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
   const int nparts = c.sc_sp[4 * task + 1];
-  const int64_t tt = (int64_t)c.tiles * c.tiles;
-  const double2* P0 = c.sc_part + ((int64_t)c.sc_sp[4 * task + 2] * tt + blockIdx.y) * 4096;
   const int na = v.n[a];
+  const int ta = (na + 63) >> 6, tb = (v.n[b] + 63) >> 6;
+  const int64_t tt = (int64_t)ta * tb;
+  const double2* P0 = c.sc_part + ((int64_t)c.sc_gbase[blockIdx.x] + tr + ta * tc) * 4096;
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
   int off[4];
   bool ok[4];

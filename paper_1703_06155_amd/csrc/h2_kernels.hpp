@@ -76,8 +76,9 @@ struct ColourTasks {
   const int32_t* pj_slot; const int64_t* pj_toff; int npj;   // projection slots, temp offsets
   const int32_t* sc_slot; const int32_t* sc_cptr; const int32_t* sc_i; const int32_t* sc_ja;
   const int32_t* sc_jb; int nsc;          // Schur targets and their contributions
-  const int32_t* sc_sp;                   // per task {chunk, chunks, first partial slot, group}
+  const int32_t* sc_sp;                   // per task {chunk, chunks, chunks of earlier groups, group}
   const int32_t* sc_gtask; int ngrp;      // split groups: first task of each
+  const int32_t* sc_gbase;                // split groups: first 64 x 64 partial tile of each
   double2* sc_part;                       // partial tiles of split tasks
   const int32_t* pn_i; const int32_t* pn_ja; int npn;          // panel tasks (i, partner pos)
   const int32_t* sv_cl; const int32_t* sv_cptr; const int32_t* sv_i; const int32_t* sv_ja;

@@ -46,11 +46,12 @@ def cpu_baseline(budget_s: float = 30.0) -> dict:
                       f"factor + 1 RHS refined to {hist[-1]:.1e} in {dt:.1f} s; construction excluded"}
 
 
-# HBM bytes per launch of the FP64 Schur flush kernel on the default workload,
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a 1 GiB copy
-# (profiles/k_schur_cube32_fp64.md); valid only for the kernel sources hashed here.
-SCHUR_TRAFFIC = {"sources_sha256": "48e7076e4a1f2bdc547cf10c020d4045a408fee7539bcaa43dce55a4a30bac05",
-                 "bytes_per_launch": 821654940}
+# HBM bytes per FP64 Schur flush (flush kernel + partial-tile reduction) on the
+# default workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
+# 1 GiB copy (profiles/k_schur_cube32_fp64.md); valid only for the kernel sources
+# hashed here.
+SCHUR_TRAFFIC = {"sources_sha256": "0721612d522a3b8a74987a9ad8d035ab6611e6201d99e5c7ba724cc45427018f",
+                 "bytes_per_launch": 910002275}
 
 
 def kernel_sources_sha256() -> str:
@@ -70,8 +71,10 @@ def kernel_sources_sha256() -> str:
 
 
 def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dict:
-    """Roofline of the Schur flush kernel from the algorithmic ledger and the
-    launch durations the library measured with HIP events on its stream."""
+    """Roofline of the Schur flush (the FP64 flush kernel plus the kernel that adds
+    the partial tiles of split target blocks) from the algorithmic ledger and the
+    flush durations the library measured with HIP events on its stream; one
+    "launch" is one flush of a colour's pending updates."""
     per_launch_s = ms * 1e-3 / max(launches, 1)
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)  # flop / byte
     intensity = flops / nbytes if nbytes > 0 else float("inf")
@@ -84,7 +87,7 @@ def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dic
     else:
         achieved = nbytes / max(launches, 1) / per_launch_s / 1e9 if ms > 0 else 0.0
         out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": "k_schur<double>",
+    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": "k_schur<false> + k_schur_reduce",
                 "launches": launches, "flops_per_launch": flops / max(launches, 1),
                 "bytes_per_launch_algorithmic": nbytes / max(launches, 1), "intensity_flop_per_byte": intensity,
                 "avg_launch_ms": ms / max(launches, 1)})

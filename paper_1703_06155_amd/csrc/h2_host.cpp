@@ -263,6 +263,8 @@ struct h2_ctx {
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
   h2::DArr<double2> Zf, Zinv;
+  h2::DArr<double2> dl_linv, dl_uinv, dl_tmp;  // final dense LU work space (kept between factorizations)
+  h2::DArr<int32_t> dl_piv, dl_flag;
   std::vector<double> timing;
   std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
   bool ledger_valid = false;
@@ -997,6 +999,11 @@ static void release_factor_buffers(h2_ctx* H) {
   H->ws_merge.release();
   H->Zf.release();
   H->Zinv.release();
+  H->dl_linv.release();
+  H->dl_uinv.release();
+  H->dl_tmp.release();
+  H->dl_piv.release();
+  H->dl_flag.release();
   H->vbuf.clear();
   H->vbuf_nrhs = 0;
 }
@@ -1503,11 +1510,14 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
   H->Zinv.alloc(std::max<int64_t>(1, n * n));
   if (n == 0) return;
   double2* A = H->Zf.p;
-  DArr<int32_t> piv, flag;
+  DArr<int32_t>& piv = H->dl_piv;
+  DArr<int32_t>& flag = H->dl_flag;
   piv.alloc(n);
-  flag.upload(std::vector<int32_t>(1, 0), st);
+  flag.alloc(1);
+  HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int32_t), st));
   const int64_t nb = (n + 63) / 64;
-  DArr<double2> linv, uinv;
+  DArr<double2>& linv = H->dl_linv;
+  DArr<double2>& uinv = H->dl_uinv;
   linv.alloc(nb * 64 * 64);
   uinv.alloc(nb * 64 * 64);
   for (int64_t b = 0; b < nb; ++b) {
@@ -1539,7 +1549,7 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
   launch_zero(X, n * n, st);
   launch_apply_perm_cols(X, n, piv.p, st);
   check_launch("host.cpp:1248");
-  DArr<double2> tmp;
+  DArr<double2>& tmp = H->dl_tmp;
   tmp.alloc(64 * n);
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0);

@@ -1434,12 +1434,11 @@ void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch
 
 // Step 2 projections.  side 0: T = (x in colour ? Q~_x^H : I) Z ; side 1: Z = T (y in colour ? conj(Q~_y) : I)
 template <typename R>
-__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side, int which) {
-  __shared__ TileSmem<R> s;
+__device__ __forceinline__ void proj_body(const LevelView& v, const ColourTasks& c, double2* temp, int side,
+                                          TileSmem<R>& s) {
   const int task = blockIdx.x;
   const int sl = c.pj_slot[task];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
-  if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
   const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
   const int nx = v.n[x], ny = v.n[y];
   // rows of the output: for blocks whose row cluster is eliminated now and that
@@ -1484,15 +1483,38 @@ __global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double
   }
 }
 
-// Fused Step 2 for levels whose blocks fit one 64x64 tile: the workgroup owns the
-// whole block, so Z <- Q~_x^H Z and Z <- Z conj(Q~_y) are applied in place.  Fill
-// blocks keep only the k~_x kept rows of a row cluster eliminated now.
 template <typename R>
-__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, int which) {
+__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side, int which) {
   __shared__ TileSmem<R> s;
   const int sl = c.pj_slot[blockIdx.x];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
   if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
+  proj_body<R>(v, c, temp, side, s);
+}
+
+union ProjSmem {
+  TileSmem<double> d;
+  TileSmem<float> f;
+};
+
+// Mixed form in one launch: diagonal blocks (the large self terms of Z) in FP64,
+// the others on FP32 matrix cores.
+__global__ void __launch_bounds__(256) k_proj_mixed(LevelView v, ColourTasks c, double2* temp, int side) {
+  __shared__ ProjSmem s;
+  const int sl = c.pj_slot[blockIdx.x];
+  if (v.slot_a[sl] == v.slot_b[sl])
+    proj_body<double>(v, c, temp, side, s.d);
+  else
+    proj_body<float>(v, c, temp, side, s.f);
+}
+
+// Fused Step 2 for levels whose blocks fit one 64x64 tile: the workgroup owns the
+// whole block, so Z <- Q~_x^H Z and Z <- Z conj(Q~_y) are applied in place.  Fill
+// blocks keep only the k~_x kept rows of a row cluster eliminated now.
+template <typename R>
+__device__ __forceinline__ void proj_fused_body(const LevelView& v, const ColourTasks& c, TileSmem<R>& s) {
+  const int sl = c.pj_slot[blockIdx.x];
+  const int x = v.slot_a[sl], y = v.slot_b[sl];
   const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
   const int nx = v.n[x], ny = v.n[y];
   const bool fill = sl >= v.nnear;
@@ -1514,13 +1536,30 @@ __global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, 
   }
 }
 
+template <typename R>
+__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, int which) {
+  __shared__ TileSmem<R> s;
+  const int sl = c.pj_slot[blockIdx.x];
+  const int x = v.slot_a[sl], y = v.slot_b[sl];
+  if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
+  proj_fused_body<R>(v, c, s);
+}
+
+__global__ void __launch_bounds__(256) k_proj_fused_mixed(LevelView v, ColourTasks c) {
+  __shared__ ProjSmem s;
+  const int sl = c.pj_slot[blockIdx.x];
+  if (v.slot_a[sl] == v.slot_b[sl])
+    proj_fused_body<double>(v, c, s.d);
+  else
+    proj_fused_body<float>(v, c, s.f);
+}
+
 // The mixed form projects the off-diagonal blocks in complex FP32 and keeps the
 // diagonal blocks (which hold the large self terms of Z) in FP64.
 void launch_proj_fused(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
   if (c.npj <= 0) return;
   if (mixed) {
-    hipLaunchKernelGGL(k_proj_fused<float>, dim3(c.npj), dim3(256), 0, st, v, c, (int)PJ_OFFDIAG);
-    hipLaunchKernelGGL(k_proj_fused<double>, dim3(c.npj), dim3(256), 0, st, v, c, (int)PJ_DIAG);
+    hipLaunchKernelGGL(k_proj_fused_mixed, dim3(c.npj), dim3(256), 0, st, v, c);
   } else {
     hipLaunchKernelGGL(k_proj_fused<double>, dim3(c.npj), dim3(256), 0, st, v, c, (int)PJ_ALL);
   }
@@ -1530,8 +1569,7 @@ void launch_proj(const LevelView& v, const ColourTasks& c, double2* temp, int si
   if (c.npj <= 0) return;
   const dim3 grid(c.npj, c.tiles * c.tiles);
   if (mixed) {
-    hipLaunchKernelGGL(k_proj<float>, grid, dim3(256), 0, st, v, c, temp, side, (int)PJ_OFFDIAG);
-    hipLaunchKernelGGL(k_proj<double>, grid, dim3(256), 0, st, v, c, temp, side, (int)PJ_DIAG);
+    hipLaunchKernelGGL(k_proj_mixed, grid, dim3(256), 0, st, v, c, temp, side);
   } else {
     hipLaunchKernelGGL(k_proj<double>, grid, dim3(256), 0, st, v, c, temp, side, (int)PJ_ALL);
   }

@@ -208,7 +208,6 @@ struct FactorLevel {
   DArr<int64_t> d_slot_off, d_q_off, d_b_off, d_bp_off, d_lu_off, d_cp_off, d_rp_off, d_w_off, d_voff;
   DArr<double> d_margins;
   DArr<double2> d_pmax;   // 4 unsigned 64-bit maxima per cluster (mixed form)
-  DArr<int32_t> d_f32_ok;
   DArr<double2> Q, LU, CP, RP, B;
   std::vector<int64_t> voff;
   LevelView view{};
@@ -1143,7 +1142,6 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     if (mixed) {
       F.d_pmax.alloc(2 * nc);
       launch_zero(F.d_pmax.p, 2 * nc, st);
-      F.d_f32_ok.alloc(nc);
     }
     F.Q.alloc(q_off[nc]);
     F.LU.alloc(lu_off[nc]);
@@ -1306,7 +1304,6 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     v.flags = F.d_flags.p;
     v.margins = F.d_margins.p;
     v.pmax = mixed ? reinterpret_cast<unsigned long long*>(F.d_pmax.p) : nullptr;
-    v.f32_ok = mixed ? F.d_f32_ok.p : nullptr;
     launch_householder_perp(v, nc, st);
     check_launch("host.cpp:1040");
     hipEvent_t e_lev0 = ev.next(st);
@@ -1356,7 +1353,6 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       launch_lu(v, ct, lu_scr.p, dmax, st);
       check_launch("lu");
       launch_panels(v, ct, st);
-      if (mixed) launch_f32_ok(v, ct, F32_KAPPA, st);
       check_launch("panels");
       hipEvent_t e2 = ev.next(st);
       phase_ev.push_back({es, e0, e1, e2});

@@ -2003,14 +2003,24 @@ struct SchurTerm {
   int ldc, ldr, r;
 };
 
+// Cluster i's Schur terms may run in FP32 when their FP32 rounding, about
+// u32 sqrt(r) max|C| max|R|, stays within F32_KAPPA u32 of the largest entry of the
+// blocks its panels were formed from (maxima recorded by the panel kernel).
+__device__ __forceinline__ bool f32_safe(const LevelView& v, int i, int r) {
+  const double gc = __longlong_as_double((long long)v.pmax[4 * i]);
+  const double gr = __longlong_as_double((long long)v.pmax[4 * i + 1]);
+  const double z = __longlong_as_double((long long)v.pmax[4 * i + 2]);
+  return gc * gr * sqrt((double)r) <= F32_KAPPA * z;
+}
+
 // sel: -1 every term, 1 only terms of clusters whose FP32 Schur terms are safe, 0 the others
 __device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks& c, int e, int tr, int tc, int sel,
                                            SchurTerm& t) {
   const int i = c.sc_i[e];
-  if (sel >= 0 && (v.f32_ok[i] != 0) != (sel != 0)) return false;
   const int n = v.n[i], kt = v.kt[i];
   t.r = n - kt;
   if (t.r <= 0) return false;
+  if (sel >= 0 && f32_safe(v, i, t.r) != (sel != 0)) return false;
   const int rmax = n - v.k[i];
   t.ldc = v.prow[i];
   t.ldr = rmax;
@@ -2198,25 +2208,6 @@ void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStrea
   else
     hipLaunchKernelGGL(k_schur<false>, grid, dim3(256), 0, st, v, c);
   if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c);
-}
-
-// f32_ok[i]: the FP32 rounding of cluster i's Schur terms, about
-// u32 sqrt(r) max|C| max|R|, stays within kappa u32 of the largest entry of the
-// blocks its panels were formed from.
-__global__ void k_f32_ok(LevelView v, ColourTasks c, double kappa) {
-  for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < c.ncl; e += blockDim.x * gridDim.x) {
-    const int i = c.cl[e];
-    const int r = v.n[i] - v.kt[i];
-    const double gc = __longlong_as_double((long long)v.pmax[4 * i]);
-    const double gr = __longlong_as_double((long long)v.pmax[4 * i + 1]);
-    const double z = __longlong_as_double((long long)v.pmax[4 * i + 2]);
-    v.f32_ok[i] = (r <= 0) || (gc * gr * sqrt((double)r) <= kappa * z);
-  }
-}
-
-void launch_f32_ok(const LevelView& v, const ColourTasks& c, double kappa, hipStream_t st) {
-  if (c.ncl <= 0) return;
-  hipLaunchKernelGGL(k_f32_ok, dim3((c.ncl + 255) / 256), dim3(256), 0, st, v, c, kappa);
 }
 
 // ===========================================================================

@@ -67,7 +67,6 @@ struct LevelView {
   int32_t* flags;                        // [0]: 1 + cluster of a zero pivot
   double* margins;                       // per cluster (sigma_p / tau, sigma_{p+1} / tau)
   unsigned long long* pmax;              // 4 per cluster: max |C|, max |R|, max |input block| (double bits), unused
-  int32_t* f32_ok;                       // per cluster: its Schur terms may run in FP32 (mixed form)
 };
 
 // Per-colour task lists (device arrays).
@@ -144,7 +143,6 @@ void launch_proj_fused(const LevelView& v, const ColourTasks& c, bool mixed, hip
 void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int rm, hipStream_t st);
 void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st);
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st);
-void launch_f32_ok(const LevelView& v, const ColourTasks& c, double kappa, hipStream_t st);
 
 // Level end: parent blocks from children (copy of kept k~ x k~ parts, padded
 // couplings plus fills, carried fills).

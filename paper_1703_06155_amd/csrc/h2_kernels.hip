@@ -2302,42 +2302,44 @@ void launch_parent_basis(int np, const int32_t* pn, const int32_t* pk, const int
 // ===========================================================================
 __global__ void __launch_bounds__(1024) k_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv,
                                                       double2* linv, int32_t* flag) {
-  __shared__ double rv[1024];
-  __shared__ int64_t ri[1024];
-  const int tid = threadIdx.x;
+  __shared__ double rv[16];
+  __shared__ int ri[16];
+  __shared__ double2 sD[64 * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int w = (int)imin64(64, n - j0);
   for (int jj = 0; jj < w; ++jj) {
     const int64_t j = j0 + jj;
+    // pivot: largest |re| + |im| in column j from row j on, lowest row on ties
     double best = -1.0;
-    int64_t bi = n;
+    int bi = 0x7fffffff;
     for (int64_t a = j + tid; a < n; a += blockDim.x) {
       const double2 x = A[a + j * n];
       const double val = fabs(x.x) + fabs(x.y);
       if (val > best) {
         best = val;
-        bi = a;
+        bi = (int)a;
       }
     }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-      if (tid < o) {
-        if (rv[tid + o] > rv[tid] || (rv[tid + o] == rv[tid] && ri[tid + o] < ri[tid])) {
-          rv[tid] = rv[tid + o];
-          ri[tid] = ri[tid + o];
-        }
-      }
-      __syncthreads();
+    const double wm = wave_max_nonneg(fmax(best, 0.0));
+    const int wi = wave_min_int(best == wm ? bi : 0x7fffffff);
+    if (lane == 0) {
+      rv[wv] = wm;
+      ri[wv] = wi;
     }
-    const int64_t pj = ri[0];
-    const double pv = rv[0];
     __syncthreads();
-    if (!(pv > 0.0)) {
+    double pv = rv[0];
+    int pj = ri[0];
+    for (int u = 1; u < 16; ++u)
+      if (rv[u] > pv || (rv[u] == pv && ri[u] < pj)) {
+        pv = rv[u];
+        pj = ri[u];
+      }
+    __syncthreads();
+    if (!(pv > 0.0) || pj >= n) {
       if (tid == 0) *flag = 1;
       return;
     }
-    if (tid == 0) piv[j] = (int32_t)pj;
+    if (tid == 0) piv[j] = pj;
     if (pj != j)
       for (int64_t b = tid; b < n; b += blockDim.x) {
         const double2 t = A[j + b * n];
@@ -2350,31 +2352,26 @@ __global__ void __launch_bounds__(1024) k_dense_panel(double2* A, int64_t n, int
     const double2 pinv = make_double2(p.x / pd, -p.y / pd);
     for (int64_t a = j + 1 + tid; a < n; a += blockDim.x) A[a + j * n] = cmul(A[a + j * n], pinv);
     __syncthreads();
-    // update the remaining columns of the panel only
-    const int64_t rows = n - j - 1;
-    const int cols = w - jj - 1;
-    for (int64_t e = tid; e < rows * cols; e += blockDim.x) {
-      const int64_t a = j + 1 + e % rows, b = j + 1 + e / rows;
-      A[a + b * n] = csub(A[a + b * n], cmul(A[a + j * n], A[j + b * n]));
+    // update the remaining columns of the panel: a column per wavefront, rows on lanes
+    for (int b = jj + 1 + wv; b < w; b += 16) {
+      const int64_t cb = (j0 + b) * n;
+      const double2 ub = A[j + cb];
+      for (int64_t a = j + 1 + lane; a < n; a += 64) A[a + cb] = csub(A[a + cb], cmul(A[a + j * n], ub));
     }
     __syncthreads();
   }
-  // explicit inverse of the unit-lower diagonal block
-  for (int col = tid; col < w; col += blockDim.x) {
-    for (int a = 0; a < w; ++a) {
-      double2 val;
-      if (a < col)
-        val = make_double2(0, 0);
-      else if (a == col)
-        val = make_double2(1, 0);
-      else {
-        double2 acc = make_double2(0, 0);
-        for (int mm = col; mm < a; ++mm)
-          acc = cadd(acc, cmul(A[j0 + a + (j0 + mm) * n], linv[mm + col * 64]));
-        val = make_double2(-acc.x, -acc.y);
+  // explicit inverse of the unit-lower diagonal block: a column per wavefront by
+  // forward substitution, rows on lanes, the block in LDS
+  for (int e = tid; e < w * w; e += blockDim.x) sD[(e % w) + 64 * (e / w)] = A[j0 + (e % w) + (j0 + e / w) * n];
+  __syncthreads();
+  for (int col = wv; col < 64; col += 16) {
+    double2 y = make_double2(lane == col ? 1.0 : 0.0, 0.0);
+    if (col < w)
+      for (int mm = col; mm + 1 < w; ++mm) {
+        const double2 ym = lane_read(y, mm);
+        if (lane > mm && lane < w) y = csub(y, cmul(sD[lane + 64 * mm], ym));
       }
-      linv[a + col * 64] = val;
-    }
+    linv[lane + col * 64] = (col < w && lane >= col && lane < w) ? y : make_double2(0, 0);
   }
 }
 
@@ -2383,22 +2380,34 @@ void launch_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv, double2
   hipLaunchKernelGGL(k_dense_panel, dim3(1), dim3(1024), 0, st, A, n, j0, piv, linv, flag);
 }
 
-// inverse of the upper-triangular 64 x 64 (or smaller) diagonal block at A (ld n) -> Uinv (ld 64)
-__global__ void k_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv) {
-  const int col = threadIdx.x;
-  if (col >= w) return;
-  for (int a = col; a >= 0; --a) {
-    double2 acc = make_double2(a == col ? 1.0 : 0.0, 0.0);
-    for (int mm = a + 1; mm <= col; ++mm) acc = csub(acc, cmul(A[a + mm * n], Uinv[mm + col * 64]));
-    const double2 u = A[a + a * n];
+// inverse of the upper-triangular 64 x 64 (or smaller) diagonal block at A (ld n) -> Uinv
+// (ld 64): a column per wavefront by back substitution, rows on lanes, the block in LDS
+__global__ void __launch_bounds__(1024) k_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv) {
+  __shared__ double2 sU[64 * 64];
+  __shared__ double2 dinv[64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < w * w; e += blockDim.x) sU[(e % w) + 64 * (e / w)] = A[(e % w) + (int64_t)(e / w) * n];
+  __syncthreads();
+  if (tid < w) {
+    const double2 u = sU[tid + 64 * tid];
     const double ud = cabs2(u);
-    Uinv[a + col * 64] = cmul(acc, make_double2(u.x / ud, -u.y / ud));
+    dinv[tid] = make_double2(u.x / ud, -u.y / ud);
   }
-  for (int a = col + 1; a < 64; ++a) Uinv[a + col * 64] = make_double2(0, 0);
+  __syncthreads();
+  for (int col = wv; col < 64; col += 16) {
+    double2 x = make_double2(lane == col ? 1.0 : 0.0, 0.0);
+    if (col < w)
+      for (int mm = col; mm >= 0; --mm) {
+        const double2 xm = cmul(lane_read(x, mm), dinv[mm]);
+        if (lane == mm) x = xm;
+        if (lane < mm) x = csub(x, cmul(sU[lane + 64 * mm], xm));
+      }
+    Uinv[lane + col * 64] = (col < w && lane <= col) ? x : make_double2(0, 0);
+  }
 }
 
 void launch_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv, hipStream_t st) {
-  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(64), 0, st, A, n, w, Uinv);
+  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(1024), 0, st, A, n, w, Uinv);
 }
 
 // X (n x n) = P: the permutation produced by the recorded row interchanges

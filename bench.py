@@ -87,7 +87,7 @@ def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dic
     else:
         achieved = nbytes / max(launches, 1) / per_launch_s / 1e9 if ms > 0 else 0.0
         out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": "k_schur<false> + k_schur_reduce",
+    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": "k_schur_fp64 + k_schur_reduce",
                 "launches": launches, "flops_per_launch": flops / max(launches, 1),
                 "bytes_per_launch_algorithmic": nbytes / max(launches, 1), "intensity_flop_per_byte": intensity,
                 "avg_launch_ms": ms / max(launches, 1)})

@@ -2039,6 +2039,8 @@ __device__ __forceinline__ bool schur_term(const LevelView& v, const ColourTasks
 // growth on FP32 matrix cores into a second set of accumulators, folded into
 // the FP64 ones at the end; the other terms (where the update nearly cancels
 // the block and FP32 rounding would dominate) stay in FP64.
+constexpr int MIX_MIN_K = 64;
+
 union SchurSmem {
   TileSmem<double> d;
   TileSmem<float> f;
@@ -2079,8 +2081,7 @@ __device__ __forceinline__ void schur_stream(const LevelView& v, const ColourTas
 }
 
 template <bool MIX>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur(LevelView v, ColourTasks c) {
-  __shared__ SchurSmem s;
+__device__ __forceinline__ void schur_flush(const LevelView& v, const ColourTasks& c, SchurSmem& s) {
   const int task = blockIdx.x;
   const int sl = c.sc_slot[task];
   const int a = v.slot_a[sl], b = v.slot_b[sl];
@@ -2101,7 +2102,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
   TileAcc<double> acc;
   acc.zero();
+  // mixed form: the FP32 pass pays only when the FP32-safe terms carry enough of
+  // the contraction (MIX_MIN_K columns); otherwise every term runs in FP64
+  bool split_prec = false;
   if (MIX) {
+    int kf = 0;
+    SchurTerm t;
+    for (int e = e0; e < e_end && kf < MIX_MIN_K; ++e)
+      if (schur_term(v, c, e, tr, tc, 1, t)) kf += t.r;
+    split_prec = kf >= MIX_MIN_K;
+  }
+  if (split_prec) {
     // FP32 terms first; their sums then seed the FP64 accumulators (through LDS:
     // the two MFMA shapes place a block's elements on different lanes), so the
     // two accumulator sets are never live together
@@ -2151,6 +2162,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const int ta = (na + 63) >> 6, tb = (v.n[b] + 63) >> 6;
   double2* Pc = c.sc_part + ((int64_t)c.sc_gbase[c.sc_sp[4 * task + 3]] + (int64_t)part * ta * tb + tr + ta * tc) * 4096;
   store_tile_bal_set<double, double2>(acc, Pc, 64, m, nn, mt, nt);
+}
+
+// FP64 form at four waves per SIMD (128 registers); the mixed form needs both
+// accumulator shapes and runs at three.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_schur_fp64(LevelView v,
+                                                                                        ColourTasks c) {
+  __shared__ SchurSmem s;
+  schur_flush<false>(v, c, s);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur_mixed(LevelView v,
+                                                                                         ColourTasks c) {
+  __shared__ SchurSmem s;
+  schur_flush<true>(v, c, s);
 }
 
 // Split tasks: Z -= the sum of the chunks' partial tiles, added in chunk order.
@@ -2204,9 +2229,9 @@ void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStrea
   if (c.nsc <= 0) return;
   const dim3 grid(c.nsc, c.tiles * c.tiles), rgrid(c.ngrp > 0 ? c.ngrp : 1, c.tiles * c.tiles, 4);
   if (mixed)
-    hipLaunchKernelGGL(k_schur<true>, grid, dim3(256), 0, st, v, c);
+    hipLaunchKernelGGL(k_schur_mixed, grid, dim3(256), 0, st, v, c);
   else
-    hipLaunchKernelGGL(k_schur<false>, grid, dim3(256), 0, st, v, c);
+    hipLaunchKernelGGL(k_schur_fp64, grid, dim3(256), 0, st, v, c);
   if (c.ngrp > 0) hipLaunchKernelGGL(k_schur_reduce, rgrid, dim3(256), 0, st, v, c);
 }
 

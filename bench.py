@@ -70,6 +70,36 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
+KERNEL_FAMILIES = ("gram_fill", "step0_basis", "projection", "partial_lu", "panels", "schur", "merge", "final_lu")
+LATENCY_BOUND = ("step0_basis", "partial_lu")
+
+
+def kernel_rooflines(led: dict, solve1_ms: float, matvec_ms: float) -> dict:
+    """Roofline position of every kernel family of one FP64 factorization (HIP-event
+    intervals of a factorization run with kernel timing on, algorithmic flops and bytes
+    of the library's ledger), of the 1-RHS forward + backward sweeps (bytes of the
+    factors they read) and of one H^2 matvec.  Both fractions are given; `bound` names
+    the roof the kernel's intensity points to, or "latency" for the per-cluster
+    eigen-solver and LU kernels, which are bound by dependent steps."""
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    out = {}
+    for fam in KERNEL_FAMILIES:
+        ms, flops, nbytes = led[fam]
+        if ms <= 0:
+            continue
+        tf = flops / (ms * 1e-3) / 1e12
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        inten = flops / nbytes if nbytes > 0 else float("inf")
+        bound = "latency" if fam in LATENCY_BOUND else ("mfma" if inten >= ridge else "hbm")
+        out[fam] = {"ms": float(ms), "gflop": flops / 1e9, "gbytes": nbytes / 1e9, "bound": bound,
+                    "tflops": tf, "mfma_frac": tf / PEAK_FP64_TFLOPS, "gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+    for fam, ms, nbytes in (("sweeps_1rhs", solve1_ms, led["sweep_bytes_per_rhs"]),
+                            ("matvec_1rhs", matvec_ms, led["matvec_bytes"])):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[fam] = {"ms": ms, "gbytes": nbytes / 1e9, "bound": "hbm", "gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+    return out
+
+
 def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dict:
     """Roofline of the Schur flush (the FP64 flush kernel plus the kernel that adds
     the partial tiles of split target blocks) from the algorithmic ledger and the
@@ -112,16 +142,18 @@ def copy_calibration(torch):
 def batch_leg(torch, h2, I, chunk: int) -> dict:
     """Independent box problems (sides U{12..32} cells, leaf 48, eps 1e-4, 16 plane-wave
     right-hand sides each): factor + 16-RHS solve refined to 1e-8, one problem at a time
-    versus batched (h2_factor_batch / h2_solve_batch, graph-replayed sweeps), in chunks
-    of `chunk` problems whose handles are released after their solve."""
+    in FP64 versus batched (h2_factor_batch / h2_solve_batch, graph-replayed sweeps) in
+    FP64 and in the mixed form, in chunks of `chunk` problems whose handles are released
+    after their solve.  Every run reports the largest final residual over the problems."""
     probs = I.batch_problems(count=64, nrhs=16)
     n_total = sum(pr.n for pr in probs)
 
-    def run(batched: bool) -> float:
-        elapsed = 0.0
+    def run(batched: bool, precision: str) -> tuple:
+        elapsed, worst, iters = 0.0, 0.0, 0
         for c0 in range(0, len(probs), chunk):
             part = probs[c0:c0 + chunk]
-            hs = [h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps) for pr in part]
+            hs = [h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, precision=precision)
+                  for pr in part]
             rhs = [torch.from_numpy(pr.rhs.copy()).cuda() for pr in part]
             for G in hs:
                 G.set_sweep_graph(batched)
@@ -129,23 +161,31 @@ def batch_leg(torch, h2, I, chunk: int) -> dict:
             t0 = time.perf_counter()
             if batched:
                 h2.factor_batch(hs)
-                h2.solve_batch(hs, rhs, tol=1e-8, max_iter=20)
+                _, infos = h2.solve_batch(hs, rhs, tol=1e-8, max_iter=20, info=True)
             else:
+                infos = []
                 for G, b in zip(hs, rhs):
                     G.factor()
-                    G.solve(b, tol=1e-8, max_iter=20)
+                    infos.append(G.solve(b, tol=1e-8, max_iter=20, info=True)[1])
             torch.cuda.synchronize()
             elapsed += time.perf_counter() - t0
+            worst = max([worst] + [i["rel_residual"] for i in infos])
+            iters = max([iters] + [i["iterations"] for i in infos])
             for G in hs:
                 G.close()
-        return elapsed
+        return elapsed, worst, iters
 
-    t_seq = run(False)
-    t_bat = run(True)
+    t_seq, r_seq, it_seq = run(False, "fp64")
+    t_bat, r_bat, it_bat = run(True, "fp64")
+    t_mix, r_mix, it_mix = run(True, "mixed")
     return {"workload": "64 box problems, sides U{12..32}, leaf 48, eps 1e-4, 16 RHS each, refined to 1e-8",
             "unknowns": n_total, "chunk": chunk, "sequential_s": t_seq, "batched_s": t_bat,
             "sequential_unknowns_per_s": n_total / t_seq, "batched_unknowns_per_s": n_total / t_bat,
-            "speedup": t_seq / t_bat}
+            "speedup": t_seq / t_bat,
+            "batched_mixed_s": t_mix, "batched_mixed_unknowns_per_s": n_total / t_mix,
+            "mixed_batched_vs_fp64_sequential": t_seq / t_mix, "mixed_batched_vs_fp64_batched": t_bat / t_mix,
+            "max_rel_residual": {"fp64_sequential": r_seq, "fp64_batched": r_bat, "mixed_batched": r_mix},
+            "max_refine_iterations": {"fp64_sequential": it_seq, "fp64_batched": it_bat, "mixed_batched": it_mix}}
 
 
 def main():
@@ -219,6 +259,18 @@ def main():
     torch.cuda.synchronize()
     solve64_ms = 1000.0 * (time.perf_counter() - t1)
     stats = G.stats()
+    # per-kernel roofline: one more FP64 factorization (untimed) with events around every kernel family
+    for _ in range(2):
+        G.matvec(b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    G.matvec(b)
+    torch.cuda.synchronize()
+    matvec_ms = 1000.0 * (time.perf_counter() - t1)
+    G.set_kernel_timing(True)
+    G.factor()
+    kern = kernel_rooflines(G.kernel_ledger(), solve1_ms, matvec_ms)
+    G.set_kernel_timing(False)
     # mixed form: complex FP32 Schur updates and projections, FP64 refinement to the same residual
     G.set_precision("mixed")
     step()
@@ -269,6 +321,7 @@ def main():
         "factor_tflops": factor_flops / (tm[0] * 1e-3) / 1e12,
         "levels": stats.tolist(),
         "roofline": roof,
+        "kernel_roofline": kern,
     }
     if not args.no_batch:
         G.close()

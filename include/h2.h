@@ -215,6 +215,28 @@ h2_status h2_forced_ranks_layout(h2_handle H, int32_t* out, int64_t cap, int64_t
  * a factorization. */
 h2_status h2_factor_timing(h2_handle H, double* out, int32_t n_out);
 
+/* Per-kernel timing of later factorizations (enable != 0): the factorization
+ * records HIP events around each kernel family of every colour on its stream
+ * (a few hundred extra events per factorization, so leave it off where the
+ * factorization itself is timed).  Default: off.  Diagnostics only. */
+h2_status h2_set_kernel_timing(h2_handle H, int32_t enable);
+
+/* Roofline ledger per kernel family of the last h2_factor, from its actual
+ * ranks (complex multiply-add = 8 flops; bytes count what the operation must
+ * move through HBM, each operand read and each result written once).
+ * Families f = 0..7: Step 0 Gram of the fill-ins (eq. 16), Step 0 complement,
+ * eigenvectors and Q~ (eqs. 17-19; latency-bound), Step 2 projections
+ * (eqs. 5-8), partial LU with the triangular inverses (eqs. 9-11), the C and R
+ * panels (eqs. 12-13), Schur updates (eq. 12), level merges (eqs. 20-23),
+ * final dense LU.  out[3f] = milliseconds (summed HIP event intervals; -1 when
+ * the factorization ran without h2_set_kernel_timing; the Schur, merge and
+ * final LU intervals are always measured), out[3f+1] = flops,
+ * out[3f+2] = bytes.  out[24] = bytes one right-hand side's forward and
+ * backward sweeps must read (Q~ twice, L^-1 P, U^-1, the C and R panels, the
+ * final inverse); out[25] = bytes one H^2 matvec must read (near blocks,
+ * expanded bases, couplings).  n_out >= 26; H2_ERR_STATE before h2_factor. */
+h2_status h2_kernel_ledger(h2_handle H, double* out, int32_t n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,10 +81,12 @@ def lib():
         L.h2_stats.argtypes = [_P, _I64P, ctypes.c_int32, _I32P]
         L.h2_forced_ranks_layout.argtypes = [_P, _I32P, ctypes.c_int64, _I64P]
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
+        L.h2_set_kernel_timing.argtypes = [_P, ctypes.c_int32]
+        L.h2_kernel_ledger.argtypes = [_P, _DP, ctypes.c_int32]
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
-                     "h2_solve_batch"):
+                     "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -288,6 +290,25 @@ class H2:
         out = np.zeros(10 if ledger else 6)
         _check(lib().h2_factor_timing(self._h, _dptr(out), out.size), "h2_factor_timing")
         return out
+
+    def set_kernel_timing(self, enable: bool = True):
+        """Time every kernel family of later factorizations with HIP events (diagnostics)."""
+        _check(lib().h2_set_kernel_timing(self._h, 1 if enable else 0), "h2_set_kernel_timing")
+        return self
+
+    def kernel_ledger(self) -> dict:
+        """{family: (ms, flops, bytes)} of the last factorization (h2_kernel_ledger; ms is -1
+        when kernel timing was off), plus the bytes one right-hand side's sweeps and one
+        matvec must read."""
+        out = np.zeros(26)
+        _check(lib().h2_kernel_ledger(self._h, _dptr(out), out.size), "h2_kernel_ledger")
+        d = {f: (out[3 * i], out[3 * i + 1], out[3 * i + 2]) for i, f in enumerate(KERNEL_FAMILIES)}
+        d["sweep_bytes_per_rhs"] = out[24]
+        d["matvec_bytes"] = out[25]
+        return d
+
+
+KERNEL_FAMILIES = ("gram_fill", "step0_basis", "projection", "partial_lu", "panels", "schur", "merge", "final_lu")
 
 
 def forced_ranks_from_oracle(construct_ranks: dict, factor_ranks: dict) -> np.ndarray:

@@ -15,6 +15,7 @@
 #include <array>
 #include <climits>
 #include <iterator>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -267,6 +268,11 @@ struct h2_ctx {
   std::vector<double> timing;
   std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
   bool ledger_valid = false;
+  // per kernel family of the last factorization: ms (HIP events), flops, bytes
+  bool kernel_timing = false;
+  std::vector<double> kernel_ms;           // 8 families (see h2_kernel_ledger); -1 = not measured
+  std::vector<double> kernel_led;          // 3 per family + sweep bytes + matvec bytes
+  double merge_elems = 0;                  // elements of the parent blocks the merges wrote
   // sweep workspace
   std::vector<h2::DArr<double2>> vbuf;
   h2::DArr<double2> vtmp, vtmp2, vtmp3, sw_scratch, sw_part;
@@ -1023,8 +1029,13 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->drop_graphs();
   H->timing.assign(6, 0.0);
   H->stats_rows.clear();
+  H->merge_elems = 0;
+  H->kernel_ms.assign(8, -1.0);
   EventPool ev;
   std::vector<std::array<hipEvent_t, 4>> phase_ev;
+  // per-kernel intervals when kernel timing is on: {begin, end, family}
+  std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> kern_ev;
+  const bool ktime = H->kernel_timing;
   const bool mixed = H->precision == H2_MIXED;
   hipEvent_t t_begin = ev.next(st);
   if (l0 < 0) {
@@ -1045,6 +1056,9 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     H->timing[0] = elapsed(t_begin, t_end);
     H->timing[5] = elapsed(t_m, t_end);
+    for (int f = 0; f < 7; ++f) H->kernel_ms[f] = 0.0;
+    H->kernel_ms[7] = H->timing[5];
+    H->ledger_valid = false;
     H->factored = true;
     return;
   }
@@ -1304,8 +1318,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     v.flags = F.d_flags.p;
     v.margins = F.d_margins.p;
     v.pmax = mixed ? reinterpret_cast<unsigned long long*>(F.d_pmax.p) : nullptr;
+    hipEvent_t e_hp = ktime ? ev.next(st) : nullptr;
     launch_householder_perp(v, nc, st);
     check_launch("host.cpp:1040");
+    if (ktime) kern_ev.emplace_back(e_hp, ev.next(st), 1);
     hipEvent_t e_lev0 = ev.next(st);
     for (int c = 0; c < P.ncol; ++c) {
       ColourPlan& C = P.cols[c];
@@ -1336,12 +1352,16 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       hipEvent_t e0 = ev.next(st);
       launch_gram_fill(v, ct, gram_part.p, gram_pstride, st);
       check_launch("gram_fill");
+      hipEvent_t eg = ktime ? ev.next(st) : nullptr;
+      if (ktime) kern_ev.emplace_back(e0, eg, 0);
       launch_xform(v, ct, 0, st);
       launch_xform(v, ct, 1, st);
       check_launch("xform");
       launch_step0_eig(v, ct, eig_scr.p, dmax, st);
       check_launch("step0_eig");
       launch_xform(v, ct, 2, st);
+      hipEvent_t ex = ktime ? ev.next(st) : nullptr;
+      if (ktime) kern_ev.emplace_back(eg, ex, 1);
       if (F.tiles == 1) {
         launch_proj_fused(v, ct, mixed, st);
       } else {
@@ -1350,11 +1370,17 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       }
       check_launch("projection");
       hipEvent_t e1 = ev.next(st);
+      if (ktime) kern_ev.emplace_back(ex, e1, 2);
       launch_lu(v, ct, lu_scr.p, dmax, st);
       check_launch("lu");
+      hipEvent_t el = ktime ? ev.next(st) : nullptr;
       launch_panels(v, ct, st);
       check_launch("panels");
       hipEvent_t e2 = ev.next(st);
+      if (ktime) {
+        kern_ev.emplace_back(e1, el, 3);
+        kern_ev.emplace_back(el, e2, 4);
+      }
       phase_ev.push_back({es, e0, e1, e2});
     }
     {
@@ -1452,6 +1478,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       H->Zf.alloc(dst_total);
       dst = H->Zf.p;
     }
+    H->merge_elems += (double)dst_total;
     launch_zero(dst, dst_total, st);
     launch_merge(v, d_mt.p, (int)mt.size(), Bd.S.p, dst, st);
     check_launch("host.cpp:1167");
@@ -1496,6 +1523,13 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     H->timing[2] += elapsed(pe[2], pe[3]);
   }
   H->timing[0] = elapsed(t_begin, t_end);
+  if (ktime) {
+    for (int f = 0; f < 5; ++f) H->kernel_ms[f] = 0.0;
+    for (auto& ke : kern_ev) H->kernel_ms[std::get<2>(ke)] += elapsed(std::get<0>(ke), std::get<1>(ke));
+  }
+  H->kernel_ms[5] = H->timing[3];
+  H->kernel_ms[6] = H->timing[4];
+  H->kernel_ms[7] = H->timing[5];
   H->ledger_valid = false;
   H->factored = true;
 }
@@ -2273,8 +2307,14 @@ extern "C" h2_status h2_forced_ranks_layout(h2_handle H, int32_t* out, int64_t c
 // panel slice read once per term.
 static void compute_ledger(h2_ctx* H) {
   const Structure& S = H->S;
-  const int L = S.L;
   H->ledger.assign(10, 0.0);
+  // per family: [3f + 1] flops, [3f + 2] bytes ([3f] holds the time, filled on request)
+  std::vector<double>& K = H->kernel_led;
+  K.assign(26, 0.0);
+  auto add = [&](int f, double flops, double bytes) {
+    K[3 * f + 1] += flops;
+    K[3 * f + 2] += bytes;
+  };
   for (size_t j = 0; j < H->flev.size(); ++j) {
     const LevelPlan& P = H->plans[j];
     const FactorLevel& F = H->flev[j];
@@ -2289,6 +2329,16 @@ static void compute_ledger(h2_ctx* H) {
     };
     for (int c = 0; c < P.ncol; ++c) {
       flush_bytes(P.cols[c], c - 1);
+      // Step 2: every stored block with an end in this colour, read and written once;
+      // Q~^H from the left when its row cluster is in the colour, conj(Q~) from the right
+      // when its column cluster is
+      for (int sl : P.cols[c].pj_slot) {
+        const int x = P.slot_a[sl], y = P.slot_b[sl];
+        const bool cx = P.colour[x] == c, cy = P.colour[y] == c;
+        const double rows = cx ? F.n[x] : dim_after(x, c - 1), cols = cy ? F.n[y] : dim_after(y, c - 1);
+        add(2, (cx ? 8.0 * F.n[x] * F.n[x] * cols : 0.0) + (cy ? 8.0 * rows * F.n[y] * F.n[y] : 0.0),
+            32.0 * rows * cols);
+      }
       for (int i : P.cols[c].cl) {
         const double n = F.n[i], kt = F.kt[i], r = n - kt, k = F.k[i], d = n - k;
         double M = 0.0, M2 = 0.0, fillcols = 0.0, np = 0.0;
@@ -2312,13 +2362,34 @@ static void compute_ledger(h2_ctx* H) {
         const double proj = 8.0 * n * n * (M - kt + n + fillcols);
         const double lu = 8.0 / 3.0 * r * r * r + 8.0 * r * r * (M + M);
         H->ledger[8] += schur + gram + proj + lu;
+        // Gram G = W W^H of the n x fillcols fill-ins: W read, G written
+        add(0, 8.0 * n * n * fillcols, 16.0 * n * fillcols + 16.0 * n * n);
+        // G' = Bp^H G Bp (n^2 d + n d^2) and Q~ = [B, Bp U'] (n d^2): G, Bp read, Q~ written
+        add(1, 8.0 * (n * n * d + 2.0 * n * d * d), 16.0 * (2.0 * n * n + n * d));
+        // Q~ of the cluster read once by the projections
+        add(2, 0.0, 16.0 * n * n);
+        // LU of the r x r block and both triangular inverses: block read, L^-1 P and U^-1 written
+        add(3, 16.0 / 3.0 * r * r * r, 48.0 * r * r);
+        // C = Z_ai' U^-1 and R = L^-1 P Z_i'a over the M partner rows: inputs read for each panel,
+        // panels written, L^-1 P and U^-1 read
+        add(4, 16.0 * r * r * M, 64.0 * r * M + 32.0 * r * r);
+        // one right-hand side: Q~ (forward and backward), L^-1 P, U^-1, C and R panels
+        K[24] += 16.0 * (2.0 * n * n + 2.0 * r * r + 2.0 * r * M);
       }
     }
     flush_bytes(P.fin, P.ncol - 1);
   }
-  (void)L;
   const double nf = (double)H->nf;
   H->ledger[8] += 8.0 / 3.0 * nf * nf * nf + 8.0 * nf * nf * nf;
+  add(5, H->ledger[6], H->ledger[9]);
+  add(6, 0.0, 32.0 * H->merge_elems);  // every parent element written once, its source read once
+  add(7, 8.0 / 3.0 * nf * nf * nf + 8.0 * nf * nf * nf, 32.0 * nf * nf);
+  K[24] += 16.0 * nf * nf;  // the final inverse
+  // matvec: near blocks, the expanded bases of every level and the couplings, once each
+  double mv = (double)H->near_orig.n;
+  for (const BuildLevel& B : H->build) mv += (double)B.V.n + (double)B.S.n;
+  K[25] = 16.0 * mv;
+  (void)S;
   H->ledger_valid = true;
 }
 
@@ -2329,5 +2400,22 @@ extern "C" h2_status h2_factor_timing(h2_handle H, double* out, int32_t n_out) {
     for (int i = 0; i < 6; ++i) out[i] = H->timing[i];
     if (n_out > 6 && !H->ledger_valid) compute_ledger(H);
     for (int i = 6; i < std::min<int32_t>(n_out, 10); ++i) out[i] = H->ledger.size() > (size_t)i ? H->ledger[i] : 0.0;
+  });
+}
+
+extern "C" h2_status h2_set_kernel_timing(h2_handle H, int32_t enable) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    H->kernel_timing = enable != 0;
+  });
+}
+
+extern "C" h2_status h2_kernel_ledger(h2_handle H, double* out, int32_t n_out) {
+  return guarded([&] {
+    if (!H || !out || n_out < 26) fail(H2_ERR_ARG, "invalid argument");
+    if (!H->factored) fail(H2_ERR_STATE, "h2_kernel_ledger before h2_factor");
+    if (!H->ledger_valid) compute_ledger(H);
+    for (int i = 0; i < 26; ++i) out[i] = H->kernel_led[i];
+    for (int f = 0; f < 8; ++f) out[3 * f] = H->kernel_ms[f];
   });
 }

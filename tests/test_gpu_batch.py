@@ -47,3 +47,26 @@ def test_batch_rejects_duplicates_and_empty():
         h2.factor_batch([G, G])
     with pytest.raises(h2.H2Error):
         h2.factor_batch([])
+
+
+def test_batch_mixed_equals_one_by_one_and_refines():
+    """The mixed form (complex FP32 Schur terms and projections) batched: bit-identical
+    to one handle at a time, refined to the FP64 form's residual of 1e-8."""
+    torch = _torch()
+    probs = I.batch_problems(count=4, nrhs=4, sides=(8, 16), leaf=16)
+    solo, batch = [], []
+    for pr in probs:
+        solo.append(h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, precision="mixed").factor())
+        batch.append(h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, precision="mixed"))
+    h2.factor_batch(batch)
+    rhs = [torch.from_numpy(pr.rhs.copy()) for pr in probs]
+    xs, infos = h2.solve_batch(batch, rhs, tol=1e-8, info=True)
+    for k, pr in enumerate(probs):
+        x1, i1 = solo[k].solve(rhs[k], tol=1e-8, info=True)
+        assert np.array_equal(xs[k].cpu().numpy(), x1.cpu().numpy()), k
+        assert infos[k]["rel_residual"] <= 1e-8, infos[k]
+        ref = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps).factor()
+        xr = ref.solve(rhs[k], tol=1e-8).cpu().numpy()
+        rel = np.linalg.norm(xs[k].cpu().numpy() - xr) / np.linalg.norm(xr)
+        print(f"problem {k}: N={pr.n} mixed iterations {infos[k]['iterations']}, vs refined FP64 {rel:.1e}")
+        assert rel <= 1e-6

@@ -2619,38 +2619,52 @@ __device__ __forceinline__ double2 cfma(double2 acc, double2 a, double2 x, bool 
   return cadd(acc, conj ? cmulc(a, x) : cmul(a, x));
 }
 
+// The per-cluster kernels of the 1-RHS sweeps run one 512-thread workgroup per
+// cluster: at the upper levels a colour holds one to six clusters whose Q~ (up
+// to n = 512) one workgroup streams alone, so the loads in flight per workgroup
+// set the time.
+constexpr int SV_NT = 512;
+constexpr int SV_NW = SV_NT / 64;
+
 // y[0:m] = M x (conj: conj(M) x) for column-major M (m x n, m <= 512), x in LDS.
-// Lanes own rows, the four wavefronts take interleaved columns with eight
-// independent loads in flight per step; partial sums meet in LDS.
+// Lanes own rows, the SV_NW wavefronts take interleaved columns with eight
+// independent loads in flight per step; partial sums meet in LDS, 64 rows at a
+// time.  Every thread of the workgroup must call it (it holds barriers).
 __device__ void bv_gemv_n(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y, bool conj) {
-  __shared__ double2 red[4][512];
+  __shared__ double2 red[SV_NW][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int r0 = 0; r0 < m; r0 += 64) {
     const int r = r0 + lane;
-    if (r >= m) continue;
-    const double2* Mr = M + r;
     double2 acc = make_double2(0, 0);
-    int j = w;
-    for (; j + 28 < n; j += 32) {
-      double2 a[8];
+    if (r < m) {
+      const double2* Mr = M + r;
+      int j = w;
+      for (; j + 7 * SV_NW < n; j += 8 * SV_NW) {
+        double2 a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = Mr[(int64_t)(j + 4 * u) * ld];
+        for (int u = 0; u < 8; ++u) a[u] = Mr[(int64_t)(j + SV_NW * u) * ld];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc = cfma(acc, a[u], x[j + 4 * u], conj);
+        for (int u = 0; u < 8; ++u) acc = cfma(acc, a[u], x[j + SV_NW * u], conj);
+      }
+      for (; j < n; j += SV_NW) acc = cfma(acc, Mr[(int64_t)j * ld], x[j], conj);
     }
-    for (; j < n; j += 4) acc = cfma(acc, Mr[(int64_t)j * ld], x[j], conj);
-    red[w][r] = acc;
+    red[w][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64 && r0 + (int)threadIdx.x < m) {
+      double2 t = red[0][threadIdx.x];
+#pragma unroll
+      for (int q = 1; q < SV_NW; ++q) t = cadd(t, red[q][threadIdx.x]);
+      y[r0 + threadIdx.x] = t;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int r = threadIdx.x; r < m; r += blockDim.x) y[r] = cadd(cadd(red[0][r], red[1][r]), cadd(red[2][r], red[3][r]));
-  __syncthreads();
 }
 
 // y[0:n] = M^T x (conj: M^H x) for column-major M (m x n), x in LDS: each
 // wavefront reduces eight columns at a time (loads of all eight in flight).
 __device__ void bv_gemv_t(const double2* M, int64_t ld, int m, int n, const double2* x, double2* y, bool conj) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int j0 = w * 8; j0 < n; j0 += 32) {
+  for (int j0 = w * 8; j0 < n; j0 += 8 * SV_NW) {
     double2 acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = make_double2(0, 0);
@@ -2672,7 +2686,7 @@ __device__ void bv_gemv_t(const double2* M, int64_t ld, int m, int n, const doub
   }
 }
 
-__global__ void __launch_bounds__(256) k_sv_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+__global__ void __launch_bounds__(SV_NT) k_sv_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
                                                       int64_t ldv, int nrhs, int adj) {
   __shared__ double2 xs[512], ys[512];
   const int i = c.cl[blockIdx.x];
@@ -2820,7 +2834,7 @@ __global__ void __launch_bounds__(256) k_sv_bwd_partial(LevelView v, ColourTasks
   }
 }
 
-__global__ void __launch_bounds__(256) k_sv_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+__global__ void __launch_bounds__(SV_NT) k_sv_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
                                                       int64_t ldv, int nrhs, int adj, const double2* part,
                                                       int nsplit) {
   __shared__ double2 xs[512], ys[512];
@@ -2858,7 +2872,7 @@ void launch_sweep_fwd(const LevelView& v, const ColourTasks& c, double2* vec, co
                       int nrhs, int adj, double2* scratch, hipStream_t st) {
   if (c.ncl <= 0) return;
   if (nrhs <= SMALL_RHS) {
-    hipLaunchKernelGGL(k_sv_fwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+    hipLaunchKernelGGL(k_sv_fwd_local, dim3(c.ncl), dim3(SV_NT), 0, st, v, c, vec, voff, ldv, nrhs, adj);
     if (c.nsv > 0) hipLaunchKernelGGL(k_sv_fwd_gather, dim3(c.nsv), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
     return;
   }
@@ -2874,7 +2888,7 @@ void launch_sweep_bwd(const LevelView& v, const ColourTasks& c, double2* vec, co
   if (nrhs <= SMALL_RHS) {
     hipLaunchKernelGGL(k_sv_bwd_partial, dim3(c.ncl, SV_SPLIT), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj,
                        part, SV_SPLIT);
-    hipLaunchKernelGGL(k_sv_bwd_local, dim3(c.ncl), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, SV_SPLIT);
+    hipLaunchKernelGGL(k_sv_bwd_local, dim3(c.ncl), dim3(SV_NT), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, SV_SPLIT);
     return;
   }
   const int zb = (nrhs + 63) / 64;

@@ -2711,9 +2711,17 @@ __global__ void __launch_bounds__(SV_NT) k_sv_fwd_local(LevelView v, ColourTasks
   }
 }
 
-__global__ void __launch_bounds__(256) k_sv_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+// Sum over the wavefronts' partial results of the 1-RHS gather kernels.
+__device__ __forceinline__ double2 red_sum(const double2 (*red)[128], int t) {
+  double2 s = red[0][t];
+#pragma unroll
+  for (int q = 1; q < SV_NW; ++q) s = cadd(s, red[q][t]);
+  return s;
+}
+
+__global__ void __launch_bounds__(SV_NT) k_sv_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
                                                        int64_t ldv, int nrhs, int adj) {
-  __shared__ double2 red[4][128];
+  __shared__ double2 red[SV_NW][128];
   const int task = blockIdx.x;
   const int a = c.sv_cl[task];
   const int ma = dim_after(v, a, c.colour);
@@ -2727,24 +2735,24 @@ __global__ void __launch_bounds__(256) k_sv_fwd_gather(LevelView v, ColourTasks 
         const double2* bi = vec + voff[i] + kt + (int64_t)col * ldv;
         const int off = v.np_off[c.sv_ja[e]];
         if (!adj) {
-          // rows on lanes, the r columns of C split over the four wavefronts
+          // rows on lanes, the r columns of C split over the wavefronts
           const int pr = v.prow[i];
           for (int h = 0; h < 2; ++h) {
             const int row = rb + h * 64 + lane;
             if (row >= ma) continue;
             const double2* C = v.CP + v.cp_off[i] + off + row;
             int q = w;
-            for (; q + 12 < r; q += 16) {
+            for (; q + 3 * SV_NW < r; q += 4 * SV_NW) {
               double2 cv[4], bv[4];
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
-                cv[u] = C[(int64_t)(q + 4 * u) * pr];
-                bv[u] = bi[q + 4 * u];
+                cv[u] = C[(int64_t)(q + SV_NW * u) * pr];
+                bv[u] = bi[q + SV_NW * u];
               }
 #pragma unroll
               for (int u = 0; u < 4; ++u) acc[h] = cadd(acc[h], cmul(cv[u], bv[u]));
             }
-            for (; q < r; q += 4) acc[h] = cadd(acc[h], cmul(C[(int64_t)q * pr], bi[q]));
+            for (; q < r; q += SV_NW) acc[h] = cadd(acc[h], cmul(C[(int64_t)q * pr], bi[q]));
           }
         } else {
           // row dot products: rows split over lanes of the wavefronts, r terms each
@@ -2763,7 +2771,7 @@ __global__ void __launch_bounds__(256) k_sv_fwd_gather(LevelView v, ColourTasks 
       if (threadIdx.x < 128) {
         const int row = rb + threadIdx.x;
         if (row < ma) {
-          double2 t = cadd(cadd(red[0][threadIdx.x], red[1][threadIdx.x]), cadd(red[2][threadIdx.x], red[3][threadIdx.x]));
+          double2 t = red_sum(red, threadIdx.x);
           double2* ba = vec + voff[a] + row + (int64_t)col * ldv;
           *ba = csub(*ba, t);
         }
@@ -2773,10 +2781,10 @@ __global__ void __launch_bounds__(256) k_sv_fwd_gather(LevelView v, ColourTasks 
   }
 }
 
-__global__ void __launch_bounds__(256) k_sv_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+__global__ void __launch_bounds__(SV_NT) k_sv_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
                                                         const int64_t* voff, int64_t ldv, int nrhs, int adj,
                                                         double2* part, int nsplit) {
-  __shared__ double2 red[4][128];
+  __shared__ double2 red[SV_NW][128];
   const int i = c.cl[blockIdx.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   const int chunk = blockIdx.y;
@@ -2799,24 +2807,24 @@ __global__ void __launch_bounds__(256) k_sv_bwd_partial(LevelView v, ColourTasks
             const int q = qb + h * 64 + lane;
             if (q >= r) continue;
             int e = w;
-            for (; e + 12 < ma; e += 16) {
+            for (; e + 3 * SV_NW < ma; e += 4 * SV_NW) {
               double2 rv[4], yv[4];
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
-                rv[u] = R[q + (int64_t)(e + 4 * u) * rmax];
-                yv[u] = ya[e + 4 * u];
+                rv[u] = R[q + (int64_t)(e + SV_NW * u) * rmax];
+                yv[u] = ya[e + SV_NW * u];
               }
 #pragma unroll
               for (int u = 0; u < 4; ++u) acc[h] = cadd(acc[h], cmul(rv[u], yv[u]));
             }
-            for (; e < ma; e += 4) acc[h] = cadd(acc[h], cmul(R[q + (int64_t)e * rmax], ya[e]));
+            for (; e < ma; e += SV_NW) acc[h] = cadd(acc[h], cmul(R[q + (int64_t)e * rmax], ya[e]));
           }
         } else {
           const double2* C = v.CP + v.cp_off[i] + off;
           for (int h = 0; h < 2; ++h) {
             const int q = qb + h * 64 + lane;
             if (q >= r) continue;
-            for (int e = w; e < ma; e += 4) acc[h] = cadd(acc[h], cmulc(C[e + (int64_t)q * pr], ya[e]));
+            for (int e = w; e < ma; e += SV_NW) acc[h] = cadd(acc[h], cmulc(C[e + (int64_t)q * pr], ya[e]));
           }
         }
       }
@@ -2827,7 +2835,7 @@ __global__ void __launch_bounds__(256) k_sv_bwd_partial(LevelView v, ColourTasks
         const int q = qb + threadIdx.x;
         if (q < r)
           P[q + (int64_t)col * ldp] =
-              cadd(cadd(red[0][threadIdx.x], red[1][threadIdx.x]), cadd(red[2][threadIdx.x], red[3][threadIdx.x]));
+              red_sum(red, threadIdx.x);
       }
       __syncthreads();
     }
@@ -2873,7 +2881,7 @@ void launch_sweep_fwd(const LevelView& v, const ColourTasks& c, double2* vec, co
   if (c.ncl <= 0) return;
   if (nrhs <= SMALL_RHS) {
     hipLaunchKernelGGL(k_sv_fwd_local, dim3(c.ncl), dim3(SV_NT), 0, st, v, c, vec, voff, ldv, nrhs, adj);
-    if (c.nsv > 0) hipLaunchKernelGGL(k_sv_fwd_gather, dim3(c.nsv), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj);
+    if (c.nsv > 0) hipLaunchKernelGGL(k_sv_fwd_gather, dim3(c.nsv), dim3(SV_NT), 0, st, v, c, vec, voff, ldv, nrhs, adj);
     return;
   }
   const int zb = (nrhs + 63) / 64;
@@ -2886,7 +2894,7 @@ void launch_sweep_bwd(const LevelView& v, const ColourTasks& c, double2* vec, co
                       int nrhs, int adj, double2* part, int nsplit, double2* scratch, hipStream_t st) {
   if (c.ncl <= 0) return;
   if (nrhs <= SMALL_RHS) {
-    hipLaunchKernelGGL(k_sv_bwd_partial, dim3(c.ncl, SV_SPLIT), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj,
+    hipLaunchKernelGGL(k_sv_bwd_partial, dim3(c.ncl, SV_SPLIT), dim3(SV_NT), 0, st, v, c, vec, voff, ldv, nrhs, adj,
                        part, SV_SPLIT);
     hipLaunchKernelGGL(k_sv_bwd_local, dim3(c.ncl), dim3(SV_NT), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, SV_SPLIT);
     return;

@@ -127,7 +127,7 @@ void launch_jacobi(int nprob, const int32_t* dims, const int64_t* goff, double2*
                    const int64_t* soff, hipStream_t st);
 
 // ---- factorization ----
-constexpr int GRAM_SPLIT = 32;  // partial sums of the Step 0 Gram (two workgroups per CU at ~13 clusters a colour)
+constexpr int GRAM_SPLIT = 64;  // partial sums of the Step 0 Gram (several workgroups per CU at ~13 clusters a colour)
 // Mixed form: a cluster's Schur terms run in FP32 when sqrt(r) max|C| max|R| is
 // at most this multiple of the largest entry of the blocks they were formed from.
 constexpr double F32_KAPPA = 8.0;

@@ -593,7 +593,7 @@ void launch_householder_perp(const LevelView& v, int nc, hipStream_t st) {
 // part + j * pstride + x * (64 tiles)^2.  grid: (cluster, tiles^2, part).  The
 // partners of a part form one K stream with the next slab always in flight, and
 // the tile's 16 x 16 output blocks are dealt evenly to the four wavefronts.
-constexpr int GRAM_RED_BLOCKS = 8;
+constexpr int GRAM_RED_BLOCKS = 32;
 
 struct GramTerm {
   const double2* A;

@@ -50,8 +50,8 @@ def cpu_baseline(budget_s: float = 30.0) -> dict:
 # default workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
 # 1 GiB copy (profiles/k_schur_cube32_fp64.md); valid only for the kernel sources
 # hashed here.
-SCHUR_TRAFFIC = {"sources_sha256": "086cf91c723900f240bd48e44db567d6fb6b24202c4574bdc8b514ddd075c5a0",
-                 "bytes_per_launch": 952669225}
+SCHUR_TRAFFIC = {"sources_sha256": "8d0ef45760b189416cd8b410a670676237a85e2c082123f289136bebc7a94a34",
+                 "bytes_per_launch": 952878868}
 
 
 def kernel_sources_sha256() -> str:

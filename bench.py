@@ -48,10 +48,10 @@ def cpu_baseline(budget_s: float = 30.0) -> dict:
 
 # HBM bytes per FP64 Schur flush (flush kernel + partial-tile reduction) on the
 # default workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
-# 1 GiB copy (profiles/k_schur_cube32_fp64.md); valid only for the kernel sources
-# hashed here.
+# 1 GiB copy (profiles/k_schur_cube32_fp64.md); valid only for that 32^3 workload
+# and the kernel sources hashed here.
 SCHUR_TRAFFIC = {"sources_sha256": "8d0ef45760b189416cd8b410a670676237a85e2c082123f289136bebc7a94a34",
-                 "bytes_per_launch": 952878868}
+                 "bytes_per_launch": 952878868, "grid": 32}
 
 
 def kernel_sources_sha256() -> str:
@@ -100,7 +100,7 @@ def kernel_rooflines(led: dict, solve1_ms: float, matvec_ms: float) -> dict:
     return out
 
 
-def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dict:
+def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: int) -> dict:
     """Roofline of the Schur flush (the FP64 flush kernel plus the kernel that adds
     the partial tiles of split target blocks) from the algorithmic ledger and the
     flush durations the library measured with HIP events on its stream; one
@@ -109,7 +109,8 @@ def schur_roofline(flops: float, nbytes: float, ms: float, launches: int) -> dic
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)  # flop / byte
     intensity = flops / nbytes if nbytes > 0 else float("inf")
     traffic = None
-    if SCHUR_TRAFFIC["sources_sha256"] and SCHUR_TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+    if (grid == SCHUR_TRAFFIC["grid"] and SCHUR_TRAFFIC["sources_sha256"]
+            and SCHUR_TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
         traffic = SCHUR_TRAFFIC["bytes_per_launch"]
     if intensity >= ridge:
         achieved = flops / max(launches, 1) / per_launch_s / 1e12 if ms > 0 else 0.0
@@ -286,7 +287,7 @@ def main():
     tm = np.mean(np.array(timings), axis=0)
     schur_flops, schur_launches, factor_flops, schur_bytes = ledger
     schur_ms = tm[3]
-    roof = schur_roofline(schur_flops, schur_bytes, schur_ms, int(schur_launches))
+    roof = schur_roofline(schur_flops, schur_bytes, schur_ms, int(schur_launches), g)
     out = {
         "metric": "H² factor unknowns/s + solve ms at rel. residual 1e-8, mixed/batched vs FP64",
         "value": pr.n * args.steps / total,

@@ -54,7 +54,7 @@ typedef enum {
   H2_ERR_SINGULAR = 3,  /* zero pivot in a partial or final LU */
   H2_ERR_STATE = 4,     /* call out of order (e.g. solve before factor) */
   H2_ERR_DEVICE = 5,    /* no usable gfx950 device, or a HIP runtime error */
-  H2_ERR_NOCONV = 6,    /* refinement did not reach tol within max_iter */
+  H2_ERR_NOCONV = 6,    /* refinement did not reach tol within max_iter, or its residual is not finite */
   H2_ERR_INTERNAL = 7   /* size beyond a kernel limit, or an internal invariant broke */
 } h2_status;
 

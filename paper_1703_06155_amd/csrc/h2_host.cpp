@@ -15,6 +15,7 @@
 #include <array>
 #include <climits>
 #include <iterator>
+#include <limits>
 #include <tuple>
 #include <chrono>
 #include <cmath>
@@ -2118,8 +2119,22 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
     HIPCHK(hipMemcpyAsync(nr.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     rel = 0;
-    for (int c = 0; c < nrhs; ++c) rel = std::max(rel, nb[c] > 0 ? nr[c] / nb[c] : nr[c]);
+    bool finite = true;
+    for (int c = 0; c < nrhs; ++c) {
+      const double rc = nb[c] > 0 ? nr[c] / nb[c] : nr[c];
+      if (!std::isfinite(rc)) finite = false;
+      rel = std::max(rel, rc);
+    }
+    if (!finite) rel = std::numeric_limits<double>::infinity();
     if (first < 0) first = rel;
+    if (!finite) {
+      if (info) {
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->rel_residual_first = first;
+      }
+      fail(H2_ERR_NOCONV, "refinement residual is not finite after " + std::to_string(it) + " iterations");
+    }
     if (rel <= tol || it >= max_iter) break;
     solve_once(r.p, N, xx, ld, 1);
     ++it;
@@ -2129,7 +2144,11 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
     info->rel_residual = rel;
     info->rel_residual_first = first;
   }
-  if (rel > tol) fail(H2_ERR_NOCONV, "refinement did not reach tol within max_iter");
+  if (rel > tol) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "refinement did not reach tol within max_iter (relative residual %.3e after %d iterations, %.3e before)", rel, it, first);
+    fail(H2_ERR_NOCONV, msg);
+  }
 }
 
 // Run fn(k, stream_k) for every handle k concurrently: handle k works on its own

@@ -70,7 +70,6 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-KERNEL_FAMILIES = ("gram_fill", "step0_basis", "projection", "partial_lu", "panels", "schur", "merge", "final_lu")
 LATENCY_BOUND = ("step0_basis", "partial_lu")
 
 
@@ -83,6 +82,7 @@ def kernel_rooflines(led: dict, solve1_ms: float, matvec_ms: float) -> dict:
     eigen-solver and LU kernels, which are bound by dependent steps."""
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
     out = {}
+    from paper_1703_06155_amd import KERNEL_FAMILIES
     for fam in KERNEL_FAMILIES:
         ms, flops, nbytes = led[fam]
         if ms <= 0:

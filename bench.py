@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -73,7 +74,7 @@ def kernel_sources_sha256() -> str:
 LATENCY_BOUND = ("step0_basis", "partial_lu")
 
 
-def kernel_rooflines(led: dict, solve1_ms: float, matvec_ms: float) -> dict:
+def kernel_rooflines(led: dict, solve1_ms: float = None, matvec_ms: float = None, mixed: bool = False) -> dict:
     """Roofline position of every kernel family of one FP64 factorization (HIP-event
     intervals of a factorization run with kernel timing on, algorithmic flops and bytes
     of the library's ledger), of the 1-RHS forward + backward sweeps (bytes of the
@@ -93,6 +94,12 @@ def kernel_rooflines(led: dict, solve1_ms: float, matvec_ms: float) -> dict:
         bound = "latency" if fam in LATENCY_BOUND else ("mfma" if inten >= ridge else "hbm")
         out[fam] = {"ms": float(ms), "gflop": flops / 1e9, "gbytes": nbytes / 1e9, "bound": bound,
                     "tflops": tf, "mfma_frac": tf / PEAK_FP64_TFLOPS, "gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS}
+        if mixed:
+            # complex FP32 terms where the routing allows, FP64 elsewhere: both peaks bound the rate
+            # (the ledger's bytes are those of the FP64 form)
+            out[fam]["mfma_frac_fp32_peak"] = tf / PEAK_FP32_TFLOPS
+    if solve1_ms is None:
+        return out
     for fam, ms, nbytes in (("sweeps_1rhs", solve1_ms, led["sweep_bytes_per_rhs"]),
                             ("matvec_1rhs", matvec_ms, led["matvec_bytes"])):
         gbs = nbytes / (ms * 1e-3) / 1e9
@@ -284,6 +291,10 @@ def main():
     torch.cuda.synchronize()
     mixed_total = time.perf_counter() - t1
     tm_mixed = np.mean(np.array(mixed_fac), axis=0)
+    G.set_kernel_timing(True)
+    G.factor()
+    kern_mixed = kernel_rooflines(G.kernel_ledger(), mixed=True)
+    G.set_kernel_timing(False)
     tm = np.mean(np.array(timings), axis=0)
     schur_flops, schur_launches, factor_flops, schur_bytes = ledger
     schur_ms = tm[3]
@@ -314,7 +325,8 @@ def main():
                   "factor_ms": float(tm_mixed[0]), "refine_iterations": info_m["iterations"],
                   "rel_residual": info_m["rel_residual"], "rel_residual_first": info_m["rel_residual_first"],
                   "factor_phase_ms": {"steps0_2": tm_mixed[1], "lu_panels": tm_mixed[2], "schur": tm_mixed[3],
-                                      "merge": tm_mixed[4], "final_lu": tm_mixed[5]}},
+                                      "merge": tm_mixed[4], "final_lu": tm_mixed[5]},
+                  "kernel_roofline": kern_mixed},
         "solve_ms_1rhs": solve1_ms,
         "solve_ms_64rhs": solve64_ms,
         "factor_phase_ms": {"steps0_2": tm[1], "lu_panels": tm[2], "schur": tm[3], "merge": tm[4],

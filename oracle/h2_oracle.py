@@ -36,7 +36,9 @@ in the design notes):
   R8  the eliminated coordinates come first in Q = [V_perp  V] (eq. 4).
 
 Parity pins (tests/test_oracle_*.py): tree and partition invariants and
-counts, nested-basis identities, zero introduction (eqs. 7-8), the
+counts, kernel entries against closed forms, nested-basis identities, the
+Step 0 rank rule on fill-ins of designed spectrum and the eq. 17 bound on
+the dropped fill-ins, zero introduction (eqs. 7-8), the
 no-truncation limit against a dense solve of the represented matrix, the
 eta = 0 limit against dense LU, the adjoint dot-product identity, accuracy
 versus eps, linear storage on rods, and the gradient against finite
@@ -444,12 +446,42 @@ class Factorization:
     stats: list = field(default_factory=list)
 
 
-def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None):
+def fill_spectrum(Bi, W, nu_i, efill, cap):
+    """Step 0 of one cluster (eqs. 16-17 / 25-26): the directions of the fill-ins
+    W outside the current basis Bi, and how many of them to add.
+
+    G = P W W^H P^H with P = I - Bi Bi^H (eq. 16); its eigenvectors U and the
+    square roots sig of its eigenvalues, largest first, are the left singular
+    vectors and singular values of P W.  The threshold is
+    tau = efill * max(nu_i, sig_1) (R5: relative to the larger of the cluster's
+    construction sigma_1 and the fill-ins' own); p = #{sig_j > tau}, at most
+    cap.  Returns (U, sig, tau, p, margin), margin = (sig_p / tau,
+    sig_{p+1} / tau) for the rank-parity band.
+    """
+    n_i = Bi.shape[0]
+    P = np.eye(n_i) - Bi @ Bi.conj().T
+    G = P @ (W @ W.conj().T) @ P.conj().T
+    G = 0.5 * (G + G.conj().T)
+    lam, U = np.linalg.eigh(G)
+    lam, U = lam[::-1], U[:, ::-1]
+    sig = np.sqrt(np.maximum(lam, 0.0))
+    tau = efill * max(nu_i, sig[0])
+    p = _truncate(sig, tau, cap) if tau > 0 else 0
+    margin = (np.inf, 0.0)
+    if tau > 0:
+        margin = (sig[p - 1] / tau if p > 0 else np.inf,
+                  sig[p] / tau if p < sig.size else 0.0)
+    return U, sig, tau, p, margin
+
+
+def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_trace=None):
     """Level-by-level factorization Z_H2 = L U in product form (eq. 34).
 
     order="colour": clusters of one colour take each step together (R2);
     order="sequential": one cluster at a time in the same colour-major order.
     forced_kt maps (level, cluster) -> k~ to pin the Step 0 rank decisions.
+    trace / step0_trace (lists, test use) receive the state at the start of
+    every level / the fill-ins W and threshold of every Step 0.
     """
     S = H.S
     L = S.L
@@ -506,18 +538,10 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None):
                 margin = (np.inf, 0.0)
                 if cols and n_i > 0:
                     W = np.hstack(cols)
-                    P = np.eye(n_i) - Bi @ Bi.conj().T
-                    G = P @ (W @ W.conj().T) @ P.conj().T
-                    G = 0.5 * (G + G.conj().T)
-                    lam, U = np.linalg.eigh(G)
-                    lam, U = lam[::-1], U[:, ::-1]
-                    sig = np.sqrt(np.maximum(lam, 0.0))
-                    tau = efill * max(nu[i], sig[0])
-                    p = _truncate(sig, tau, n_i - k_i) if tau > 0 else 0
-                    if tau > 0:
-                        margin = (sig[p - 1] / tau if p > 0 else np.inf,
-                                  sig[p] / tau if p < sig.size else 0.0)
+                    U, sig, tau, p, margin = fill_spectrum(Bi, W, nu[i], efill, n_i - k_i)
                     ledger["gemm"] += 8.0 * n_i * n_i * W.shape[1]
+                    if step0_trace is not None:
+                        step0_trace.append(dict(level=l, cluster=i, W=W, tau=tau, p=p))
                 else:
                     U = np.zeros((n_i, 0), complex)
                     p = 0

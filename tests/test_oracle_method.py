@@ -4,6 +4,9 @@ Each test checks the oracle against something it does not compute itself: a
 dense LAPACK solve, an exact algebraic identity of the paper, a closed form,
 or a finite difference.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -123,19 +126,99 @@ def test_zero_introduction_and_factor_identities():
                 assert np.isfinite(Lm).all() and np.isfinite(Um).all()
 
 
-def test_eliminated_rows_of_far_blocks_are_below_threshold():
-    """After Step 2 the eliminated rows of every admissible/fill block are small (eq. 17 truncation)."""
+def test_projection_annihilates_construction_basis_on_far_blocks():
+    """Eqs. 7-8 on the represented matrix: the eliminated part Q~[:, :r] is orthogonal to the
+    cluster's construction basis, so it annihilates every admissible leaf block V_t S V_s^T."""
     pr, H = _prob((8, 8, 8), 16, 1e-4)
-    tr = []
-    Fz = O.factor(H, trace=tr)
+    Fz = O.factor(H)
     lev = Fz.levels[0]
-    st = tr[0]
     S = H.S
     Zh = O.h2_dense(H)
     for (t, s) in S.adm[S.L]:
         f = lev["facs"][t]
         blk = Zh[np.ix_(S.clusters[S.L][t], S.clusters[S.L][s])]
         assert np.linalg.norm(f.Q[:, :f.r].conj().T @ blk) < 1e-12 * np.linalg.norm(blk) + 1e-15
+
+
+def test_step0_dropped_fill_is_below_threshold():
+    """Eq. 17 truncation on real fill-ins: after Step 0 the part of the fill-ins W_i that the
+    eliminated directions Q~[:, :r] still see has 2-norm <= tau_i (the dropped singular values)."""
+    pr, H = _prob((10, 7, 9), 12, 1e-5)
+    rec = []
+    Fz = O.factor(H, step0_trace=rec)
+    assert len(rec) > 20
+    by_level = {lev["level"]: lev for lev in Fz.levels}
+    for e in rec:
+        f = by_level[e["level"]]["facs"][e["cluster"]]
+        dropped = np.linalg.norm(f.Q[:, :f.r].conj().T @ e["W"], 2) if f.r else 0.0
+        assert dropped <= e["tau"] * (1 + 1e-9) + 1e-15
+
+
+def _designed_fills(n, k, sig, seed=5):
+    """Fill-ins with a prescribed spectrum outside a k-column basis: W = Qc diag(sig) Y^H + Bi X,
+    Qc orthonormal and orthogonal to Bi (so (I - Bi Bi^H) W has singular values sig exactly)."""
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Q, _ = np.linalg.qr(M)
+    Bi, Qc = Q[:, :k], Q[:, k:k + len(sig)]
+    w = 3 * len(sig) + 2
+    Y, _ = np.linalg.qr(rng.standard_normal((w, len(sig))) + 1j * rng.standard_normal((w, len(sig))))
+    X = rng.standard_normal((k, w)) + 1j * rng.standard_normal((k, w))
+    return Bi, Qc, Qc @ np.diag(sig) @ Y.conj().T + Bi @ X
+
+
+@pytest.mark.parametrize("nu,sig,efill,cap,p_exp", [
+    # the fill-ins dominate (sigma_1(W) = 50 > nu = 1): tau = 1e-2 * 50 = 0.5
+    (1.0, [50.0, 3.0, 0.6, 0.4, 1e-3], 1e-2, 6, 3),
+    # the construction dominates (nu = 1000 > 50): tau = 10
+    (1000.0, [50.0, 3.0, 0.6, 0.4, 1e-3], 1e-2, 6, 1),
+    # tau = 0.5 again, but only two directions fit beside the basis
+    (1.0, [50.0, 3.0, 0.6, 0.4, 1e-3], 1e-2, 2, 2),
+    # every direction below tau = 1e-3 * 2 = 2e-3 except the first two
+    (2.0, [1.5, 0.01, 1e-3, 1e-4], 1e-3, 6, 2),
+])
+def test_step0_threshold_on_designed_spectrum(nu, sig, efill, cap, p_exp):
+    """Step 0 rank rule (eqs. 16-17 with the R5 threshold tau = eps_fill max(nu_i, sigma_1(W)))
+    on fill-ins whose singular values outside the basis are known by construction: the kept
+    count p_exp is read off the designed spectrum; the added directions span the designed
+    leading singular vectors; what is dropped has norm sig[p_exp] <= tau."""
+    n, k = 9, 2
+    Bi, Qc, W = _designed_fills(n, k, np.array(sig))
+    U, s, tau, p, _ = O.fill_spectrum(Bi, W, nu, efill, cap)
+    assert p == p_exp
+    # G = W W^H squares the spectrum: compare sig^2 to the accuracy of the Gram's eigenvalues
+    assert np.allclose(s[:len(sig)] ** 2, np.square(sig), rtol=1e-9, atol=1e-13 * max(sig) ** 2)
+    Ua = U[:, :p]
+    # same span as the designed leading directions
+    assert np.linalg.norm(Ua @ Ua.conj().T - Qc[:, :p] @ Qc[:, :p].conj().T, 2) < 1e-8
+    Bt = np.hstack([Bi, Ua])
+    rest = np.linalg.norm(W - Bt @ (Bt.conj().T @ W), 2)
+    expect_rest = sig[p] if p < len(sig) else 0.0
+    assert abs(rest - expect_rest) <= 1e-9 * max(sig)
+    if p < cap:
+        assert rest <= tau
+
+
+def test_green_function_closed_forms():
+    """Kernel entries e^{-jkr}/(4 pi r) at r = m h on one axis against values evaluated from the
+    square-root closed forms of cos/sin at multiples of 36 degrees (tests/golden/green_entries.json);
+    A_ij = k^2 chi_j h^3 Z_ij for the same pairs."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "green_entries.json")) as f:
+        gold = json.load(f)
+    k, h = gold["k"], gold["h"]
+    assert k == I.WAVENUMBER and h == I.CELL
+    pts = I.cube_grid(11, 1, 1)
+    chi = I.contrast(pts.shape[0], 0)
+    Z = O.dense_Z(pts, k, h, chi)
+    A = O.dense_A(pts, k, h, chi)
+    zb = O.z_block(pts, [0], np.arange(11), k, h, chi)[0]
+    for e in gold["entries"]:
+        m = e["m"]
+        want = complex(e["re"], e["im"])
+        assert abs(Z[0, m] - want) <= 1e-14, (m, Z[0, m], want)
+        assert abs(zb[m] - want) <= 1e-14
+        assert abs(Z[m, 0] - want) <= 1e-14
+        assert abs(A[0, m] - (2 * np.pi) ** 2 * h ** 3 * chi[m] * want) <= 1e-15
 
 
 @pytest.mark.parametrize("grid,leaf,eps", [((8, 8, 8), 16, 1e-4), ((10, 7, 9), 12, 1e-5)])

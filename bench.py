@@ -1,15 +1,20 @@
 """Benchmark: H^2 factorization + refined solve on one MI355X.
 
 A step is one pass of the hot path over the resident H^2 matrix of the
-headline workload (32^3 cube grid, N = 32768, leaf 64, eta = 1, eps = 1e-4):
+headline workload (64^3 cube grid, N = 262144, leaf 64, eta = 1, eps = 1e-4):
 the level-by-level factorization followed by one right-hand side solved and
 iteratively refined to a relative residual of 1e-8 against the H^2 matrix.
 Construction of the H^2 representation is setup (untimed), as in the paper.
+Both arithmetic forms run on the same matrix: FP64, and the mixed form
+(complex FP32 Schur updates and projections, FP64 elsewhere), each refined to
+the same residual.
 
-Prints one JSON line.  `value` = unknowns per second of whole steps
-(N * steps / timed seconds); the factorization rate alone, the solve times
-(1 RHS refined, 1 RHS plain, 64 RHS plain), the Schur kernel's roofline and
-the CPU oracle's rate on a bounded sample are reported beside it.
+Prints one JSON line.  `value` = unknowns per second of whole steps of the
+faster form (N * steps / timed seconds); both forms' rates, factor times per
+level, warm solve medians (1 RHS refined, 1 RHS plain, 64 RHS plain), the
+Schur flush roofline, every kernel family's roofline, a 32^3 leg, the
+64-problem batching leg and the CPU oracle's rate on the small workload are
+reported beside it.
 """
 from __future__ import annotations
 
@@ -29,30 +34,50 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 (matrix)
 PEAK_HBM_GBS = 8000.0
 
 
-def cpu_baseline(budget_s: float = 30.0) -> dict:
-    """The oracle on a 16^3 sub-cube of the same generator (leaf 64, eps 1e-4)."""
-    from threadpoolctl import threadpool_info
+def cpu_baseline() -> dict:
+    """The oracle on the small cube workload itself (16^3, N = 4096, leaf 32, eta 1,
+    eps 1e-6): factor + 1 RHS refined to 1e-8, construction excluded (timed apart), once
+    with every host thread the BLAS may use and once limited to one thread (the paper's
+    timings are single-core)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import h2_oracle as O
     from paper_1703_06155_amd import inputs as I
 
-    pr = I.make_problem("cpu_sample", (16, 16, 16), 64, 1e-4)
-    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    pr = I.config(0)
     t0 = time.perf_counter()
-    Fz = O.factor(H)
-    x, hist = O.refine(Fz, pr.rhs[:, 0], tol=1e-8, max_iter=10)
-    dt = time.perf_counter() - t0
+    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    construct_s = time.perf_counter() - t0
+
+    def run():
+        t0 = time.perf_counter()
+        Fz = O.factor(H)
+        t1 = time.perf_counter()
+        _, hist = O.refine(Fz, pr.rhs[:, 0], tol=1e-8, max_iter=10)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, hist
+
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": pr.n / dt, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"16^3 sub-cube of the same generator (N={pr.n}, leaf 64, eta 1, eps 1e-4): "
-                      f"factor + 1 RHS refined to {hist[-1]:.1e} in {dt:.1f} s; construction excluded"}
+    f_all, s_all, hist = run()
+    with threadpool_limits(limits=1):
+        f_one, s_one, _ = run()
+    sample = (f"the oracle on the 16^3 cube workload (N={pr.n}, leaf 32, eta 1, eps 1e-6): factor + 1 RHS "
+              f"refined to {hist[-1]:.1e}; construction ({construct_s:.1f} s) excluded; os.cpu_count() = "
+              f"{os.cpu_count()}, BLAS threads = {threads}")
+    print(f"# cpu baseline done ({f_all + s_all:.1f} s all threads, {f_one + s_one:.1f} s one thread)",
+          file=sys.stderr, flush=True)
+    return {"value": pr.n / (f_all + s_all), "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
+            "sample": sample, "factor_s": f_all, "solve_refined_s": s_all, "construct_s": construct_s,
+            "os_cpu_count": os.cpu_count(),
+            "single_thread": {"value": pr.n / (f_one + s_one), "unit": "unknowns/s", "cores": 1,
+                              "factor_s": f_one, "solve_refined_s": s_one}}
 
 
-# HBM bytes per FP64 Schur flush (flush kernel + partial-tile reduction) on the
-# default workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
-# 1 GiB copy (profiles/k_schur_cube32_fp64.md); valid only for that 32^3 workload
-# and the kernel sources hashed here.
-SCHUR_TRAFFIC = {"sources_sha256": "8d0ef45760b189416cd8b410a670676237a85e2c082123f289136bebc7a94a34",
-                 "bytes_per_launch": 952878868, "grid": 32}
+# HBM bytes per Schur flush (flush kernel + partial-tile reduction), keyed by
+# (cube side, form), from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
+# 1 GiB copy (the summaries under profiles/); valid only for that workload and the
+# kernel sources hashed here.
+SCHUR_TRAFFIC = {(32, "fp64"): {"sources_sha256": "8d0ef45760b189416cd8b410a670676237a85e2c082123f289136bebc7a94a34",
+                                "bytes_per_launch": 952878868}}
 
 
 def kernel_sources_sha256() -> str:
@@ -107,7 +132,7 @@ def kernel_rooflines(led: dict, solve1_ms: float = None, matvec_ms: float = None
     return out
 
 
-def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: int) -> dict:
+def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: int, form: str = "fp64") -> dict:
     """Roofline of the Schur flush (the FP64 flush kernel plus the kernel that adds
     the partial tiles of split target blocks) from the algorithmic ledger and the
     flush durations the library measured with HIP events on its stream; one
@@ -116,16 +141,17 @@ def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: 
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)  # flop / byte
     intensity = flops / nbytes if nbytes > 0 else float("inf")
     traffic = None
-    if (grid == SCHUR_TRAFFIC["grid"] and SCHUR_TRAFFIC["sources_sha256"]
-            and SCHUR_TRAFFIC["sources_sha256"] == kernel_sources_sha256()):
-        traffic = SCHUR_TRAFFIC["bytes_per_launch"]
+    rec = SCHUR_TRAFFIC.get((grid, form))
+    if rec and rec["sources_sha256"] == kernel_sources_sha256():
+        traffic = rec["bytes_per_launch"]
     if intensity >= ridge:
         achieved = flops / max(launches, 1) / per_launch_s / 1e12 if ms > 0 else 0.0
         out = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
     else:
         achieved = nbytes / max(launches, 1) / per_launch_s / 1e9 if ms > 0 else 0.0
         out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": "k_schur_fp64 + k_schur_reduce",
+    kernel = "k_schur_fp64 + k_schur_reduce" if form == "fp64" else "k_schur_mixed + k_schur_reduce"
+    out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": kernel,
                 "launches": launches, "flops_per_launch": flops / max(launches, 1),
                 "bytes_per_launch_algorithmic": nbytes / max(launches, 1), "intensity_flop_per_byte": intensity,
                 "avg_launch_ms": ms / max(launches, 1)})
@@ -196,14 +222,84 @@ def batch_leg(torch, h2, I, chunk: int) -> dict:
             "max_refine_iterations": {"fp64_sequential": it_seq, "fp64_batched": it_bat, "mixed_batched": it_mix}}
 
 
+def median_ms(torch, fn, reps: int = 5) -> float:
+    """Median wall time (ms) of `reps` warm calls, each bracketed by device synchronisation."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(1000.0 * (time.perf_counter() - t0))
+    return float(np.median(ts))
+
+
+def form_leg(torch, G, pr, precision: str, steps: int, warmup: int, b, B64, tag: str) -> dict:
+    """One arithmetic form on the resident H^2 matrix: `warmup` untimed and `steps` timed
+    steps (factor + 1 RHS refined to 1e-8), then warm solve and matvec medians and one
+    more factorization with every kernel family timed (untimed, for the roofline)."""
+    G.set_precision(precision)
+
+    def step():
+        G.factor()
+        return G.solve(b, tol=1e-8, max_iter=20, info=True)
+
+    for w in range(warmup):
+        step()
+        print(f"# {tag} {precision} warmup {w} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timings, levels, infos = [], [], []
+    for k in range(steps):
+        _, info = step()
+        infos.append(info)
+        timings.append(G.timing(ledger=False))
+        levels.append(G.level_timing())
+        print(f"# {tag} {precision} step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ledger = G.timing()[6:]
+    info = infos[-1]
+    solve_ref_ms = median_ms(torch, lambda: G.solve(b, tol=1e-8, max_iter=20))
+    solve1_ms = median_ms(torch, lambda: G.solve(b))
+    solve64_ms = median_ms(torch, lambda: G.solve(B64))
+    matvec_ms = median_ms(torch, lambda: G.matvec(b))
+    stats = G.stats()
+    G.set_kernel_timing(True)
+    G.factor()
+    kern = kernel_rooflines(G.kernel_ledger(), solve1_ms, matvec_ms, mixed=(precision == "mixed"))
+    G.set_kernel_timing(False)
+    print(f"# {tag} {precision} solves and kernel timing done", file=sys.stderr, flush=True)
+    tm = np.median(np.array(timings), axis=0)
+    lv = np.median(np.array(levels), axis=0)
+    out = {"precision": precision, "steps": steps, "warmup": warmup, "total_s": total,
+           "unknowns_per_s": pr.n * steps / total, "ms_per_step": 1000.0 * total / steps,
+           "factor_ms": float(tm[0]), "factor_unknowns_per_s": pr.n / (tm[0] * 1e-3),
+           "factor_phase_ms": {"steps0_2": tm[1], "lu_panels": tm[2], "schur": tm[3], "merge": tm[4],
+                               "final_lu": tm[5]},
+           "factor_tflops": ledger[2] / (tm[0] * 1e-3) / 1e12,
+           "level_ms": [{"level": int(r[0]), "clusters": int(r[1]), "sum_n": int(r[2]), "max_n": int(r[3]),
+                         "sum_kt": int(r[6]), "eliminated": int(r[9]), "ms": float(ms)}
+                        for r, ms in zip(stats, lv)],
+           "refine_iterations": info["iterations"], "rel_residual": info["rel_residual"],
+           "rel_residual_first": info["rel_residual_first"],
+           "solve_ms_refined_1e-8": solve_ref_ms, "solve_ms_1rhs": solve1_ms, "solve_ms_64rhs": solve64_ms,
+           "matvec_ms_1rhs": matvec_ms, "kernel_roofline": kern,
+           "_ledger": ledger, "_schur_ms": float(tm[3])}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=32)
+    ap.add_argument("--grid", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batching leg")
+    ap.add_argument("--no-cube32", action="store_true", help="skip the 32^3 leg")
+    ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--batch-chunk", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
@@ -226,119 +322,69 @@ def main():
     G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    print(f"# build {build_s:.2f} s (setup, untimed)", file=sys.stderr, flush=True)
+    print(f"# build {g}^3 {build_s:.2f} s (setup, untimed)", file=sys.stderr, flush=True)
     b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
     B64 = torch.from_numpy(I.plane_waves(pr.points, I.directions(64, 3))).cuda()
-
-    def step():
-        G.factor()
-        return G.solve(b, tol=1e-8, max_iter=20, info=True)
-
-    for w in range(args.warmup):
-        step()
-        print(f"# warmup {w} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    fac_ms = []
-    timings = []
-    for k in range(args.steps):
-        x, info = step()
-        infos.append(info)
-        tm = G.timing(ledger=False)
-        timings.append(tm)
-        fac_ms.append(tm[0])
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    ledger = G.timing()[6:]  # algorithmic ledger of the last factorization (same ranks every step)
-    ms_per_step = 1000.0 * total / args.steps
-    # solve-only timings (factor resident)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    x, info = G.solve(b, tol=1e-8, max_iter=20, info=True)
-    torch.cuda.synchronize()
-    solve_ref_ms = 1000.0 * (time.perf_counter() - t1)
-    t1 = time.perf_counter()
-    G.solve(b)
-    torch.cuda.synchronize()
-    solve1_ms = 1000.0 * (time.perf_counter() - t1)
-    t1 = time.perf_counter()
-    G.solve(B64)
-    torch.cuda.synchronize()
-    solve64_ms = 1000.0 * (time.perf_counter() - t1)
-    stats = G.stats()
-    # per-kernel roofline: one more FP64 factorization (untimed) with events around every kernel family
-    for _ in range(2):
-        G.matvec(b)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    G.matvec(b)
-    torch.cuda.synchronize()
-    matvec_ms = 1000.0 * (time.perf_counter() - t1)
-    G.set_kernel_timing(True)
-    G.factor()
-    kern = kernel_rooflines(G.kernel_ledger(), solve1_ms, matvec_ms)
-    G.set_kernel_timing(False)
-    # mixed form: complex FP32 Schur updates and projections, FP64 refinement to the same residual
-    G.set_precision("mixed")
-    step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    mixed_fac = []
-    for k in range(args.steps):
-        xm, info_m = step()
-        mixed_fac.append(G.timing(ledger=False))
-    torch.cuda.synchronize()
-    mixed_total = time.perf_counter() - t1
-    tm_mixed = np.mean(np.array(mixed_fac), axis=0)
-    G.set_kernel_timing(True)
-    G.factor()
-    kern_mixed = kernel_rooflines(G.kernel_ledger(), mixed=True)
-    G.set_kernel_timing(False)
-    tm = np.mean(np.array(timings), axis=0)
-    schur_flops, schur_launches, factor_flops, schur_bytes = ledger
-    schur_ms = tm[3]
-    roof = schur_roofline(schur_flops, schur_bytes, schur_ms, int(schur_launches), g)
+    forms = [f for f in args.forms.split(",") if f]
+    legs = {f: form_leg(torch, G, pr, f, args.steps, args.warmup, b, B64, f"{g}^3") for f in forms}
+    head = max(legs.values(), key=lambda d: d["unknowns_per_s"])
+    hf = head["precision"]
+    schur_flops, schur_launches, factor_flops, schur_bytes = head["_ledger"]
+    roof = schur_roofline(schur_flops, schur_bytes, head["_schur_ms"], int(schur_launches), g, hf)
+    for d in legs.values():
+        d.pop("_ledger")
+        d.pop("_schur_ms")
+    G.close()
+    del G
+    torch.cuda.empty_cache()
     out = {
         "metric": "H² factor unknowns/s + solve ms at rel. residual 1e-8, mixed/batched vs FP64",
-        "value": pr.n * args.steps / total,
+        "value": head["unknowns_per_s"],
         "unit": "unknowns/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c128" if hf == "fp64" else "c128+c64",
         "data": "synthetic",
-        "config": {"workload": f"VIE cube grid {g}^3 (N={pr.n}), leaf 64, eta 1, eps 1e-4, FP64 form, "
-                               f"factor + 1 RHS refined to 1e-8", "N": pr.n, "leaf": 64, "eta": 1.0,
-                   "eps": 1e-4, "precision": "fp64"},
-        "factor_ms": float(np.mean(fac_ms)),
-        "factor_unknowns_per_s": pr.n / (np.mean(fac_ms) * 1e-3),
-        "solve_ms_refined_1e-8": solve_ref_ms,
-        "refine_iterations": info["iterations"],
-        "rel_residual": info["rel_residual"],
-        "rel_residual_first": info["rel_residual_first"],
-        "mixed": {"unknowns_per_s": pr.n * args.steps / mixed_total, "ms_per_step": 1000.0 * mixed_total / args.steps,
-                  "factor_ms": float(tm_mixed[0]), "refine_iterations": info_m["iterations"],
-                  "rel_residual": info_m["rel_residual"], "rel_residual_first": info_m["rel_residual_first"],
-                  "factor_phase_ms": {"steps0_2": tm_mixed[1], "lu_panels": tm_mixed[2], "schur": tm_mixed[3],
-                                      "merge": tm_mixed[4], "final_lu": tm_mixed[5]},
-                  "kernel_roofline": kern_mixed},
-        "solve_ms_1rhs": solve1_ms,
-        "solve_ms_64rhs": solve64_ms,
-        "factor_phase_ms": {"steps0_2": tm[1], "lu_panels": tm[2], "schur": tm[3], "merge": tm[4],
-                            "final_lu": tm[5]},
-        "factor_tflops": factor_flops / (tm[0] * 1e-3) / 1e12,
-        "levels": stats.tolist(),
+        "config": {"workload": f"VIE cube grid {g}^3 (N={pr.n}), leaf 64, eta 1, eps 1e-4, "
+                               f"factor + 1 RHS refined to 1e-8; value = the faster form ({hf})",
+                   "N": pr.n, "leaf": 64, "eta": 1.0, "eps": 1e-4, "precision": hf, "build_s": build_s},
+        "factor_ms": head["factor_ms"],
+        "factor_unknowns_per_s": head["factor_unknowns_per_s"],
+        "solve_ms_refined_1e-8": head["solve_ms_refined_1e-8"],
+        "solve_ms_1rhs": head["solve_ms_1rhs"],
+        "solve_ms_64rhs": head["solve_ms_64rhs"],
+        "refine_iterations": head["refine_iterations"],
+        "rel_residual": head["rel_residual"],
+        "forms": legs,
         "roofline": roof,
-        "kernel_roofline": kern,
     }
+    if "fp64" in legs and "mixed" in legs:
+        out["mixed_vs_fp64"] = {"step": legs["mixed"]["unknowns_per_s"] / legs["fp64"]["unknowns_per_s"],
+                                "factor": legs["fp64"]["factor_ms"] / legs["mixed"]["factor_ms"],
+                                "solve_refined": legs["fp64"]["solve_ms_refined_1e-8"]
+                                / legs["mixed"]["solve_ms_refined_1e-8"]}
+    if not args.no_cube32 and g != 32:
+        p32 = I.make_problem("cube32", (32, 32, 32), 64, 1e-4)
+        G32 = h2.H2(p32.points, p32.k, p32.h, p32.chi, p32.leaf, p32.eta, p32.eps)
+        b32 = torch.from_numpy(p32.rhs[:, 0].copy()).cuda()
+        B32 = torch.from_numpy(I.plane_waves(p32.points, I.directions(64, 3))).cuda()
+        leg32 = form_leg(torch, G32, p32, "fp64", max(args.steps, 3), 1, b32, B32, "32^3")
+        leg32.pop("_ledger")
+        leg32.pop("_schur_ms")
+        leg32.pop("kernel_roofline")
+        leg32["workload"] = "VIE cube grid 32^3 (N=32768), leaf 64, eta 1, eps 1e-4, FP64, factor + 1 RHS refined"
+        out["cube32"] = leg32
+        G32.close()
+        del G32
+        torch.cuda.empty_cache()
     if not args.no_batch:
-        G.close()
         out["batch"] = batch_leg(torch, h2, I, args.batch_chunk)
+        print("# batch leg done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

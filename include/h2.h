@@ -194,6 +194,13 @@ h2_status h2_structure(const double* points, int64_t n, double h, int32_t leaf, 
  * The final dense block is reported as one more row with level = l0 - 1. */
 h2_status h2_stats(h2_handle H, int64_t* out, int32_t rows_cap, int32_t* rows);
 
+/* Milliseconds of each factored level of the last h2_factor (its Steps 0-3 for
+ * every colour, the flush of its pending Schur updates and its merge into the
+ * parent level, eqs. 20-23), one value per row of h2_stats in the same order,
+ * the final dense LU last; HIP events on the factorization's stream.  cap is
+ * the number of doubles ms can hold (ms may be NULL to query *count). */
+h2_status h2_level_timing(h2_handle H, double* ms, int32_t cap, int32_t* count);
+
 /* Rank decisions of the last build/factor as (level, cluster, k, k~) int32
  * quadruples for every nonempty cluster of every factored level, finest level
  * first; this array (length 4 * *count) is also the forced_ranks format:

@@ -83,10 +83,11 @@ def lib():
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
         L.h2_set_kernel_timing.argtypes = [_P, ctypes.c_int32]
         L.h2_kernel_ledger.argtypes = [_P, _DP, ctypes.c_int32]
+        L.h2_level_timing.argtypes = [_P, _DP, ctypes.c_int32, _I32P]
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
-                     "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger"):
+                     "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -290,6 +291,15 @@ class H2:
         out = np.zeros(10 if ledger else 6)
         _check(lib().h2_factor_timing(self._h, _dptr(out), out.size), "h2_factor_timing")
         return out
+
+    def level_timing(self) -> np.ndarray:
+        """Milliseconds of each factored level of the last factorization (rows of
+        :meth:`stats`, the final dense LU last)."""
+        cnt = ctypes.c_int32()
+        _check(lib().h2_level_timing(self._h, None, 0, ctypes.byref(cnt)), "h2_level_timing")
+        out = np.zeros(max(cnt.value, 1))
+        _check(lib().h2_level_timing(self._h, _dptr(out), out.size, ctypes.byref(cnt)), "h2_level_timing")
+        return out[:cnt.value]
 
     def set_kernel_timing(self, enable: bool = True):
         """Time every kernel family of later factorizations with HIP events (diagnostics)."""

@@ -280,6 +280,7 @@ struct h2_ctx {
   int vbuf_nrhs = 0;
   h2::DArr<double> d_norms;
   std::vector<std::vector<int64_t>> stats_rows;
+  std::vector<double> level_ms;            // per stats row: ms of that level (Steps 0-3 and its merge) / final LU
 };
 
 namespace h2 {
@@ -1030,6 +1031,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->drop_graphs();
   H->timing.assign(6, 0.0);
   H->stats_rows.clear();
+  H->level_ms.clear();
   H->merge_elems = 0;
   H->kernel_ms.assign(8, -1.0);
   EventPool ev;
@@ -1074,6 +1076,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     BuildLevel& Bd = H->build[j];
     FactorLevel& F = H->flev[j];
     const int nc = P.nc;
+    hipEvent_t e_level = ev.next(st);
     F.n = n_cur;
     std::vector<int32_t> kk(Bd.k.begin(), Bd.k.end());
     for (int t = 0; t < nc; ++t)
@@ -1486,6 +1489,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     hipEvent_t e_m1 = ev.next(st);
     HIPCHK(hipStreamSynchronize(st));
     H->timing[4] += elapsed(e_m0, e_m1);
+    H->level_ms.push_back(elapsed(e_level, e_m1));
     (void)e_lev0;
     // stats row
     {
@@ -1518,6 +1522,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
   H->stats_rows.push_back({l0 - 1, (int64_t)S.nclusters(l0 - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
   H->timing[5] = elapsed(e_f0, t_end);
+  H->level_ms.push_back(H->timing[5]);
   for (auto& pe : phase_ev) {
     H->timing[3] += elapsed(pe[0], pe[1]);
     H->timing[1] += elapsed(pe[1], pe[2]);
@@ -2292,6 +2297,17 @@ extern "C" h2_status h2_stats(h2_handle H, int64_t* out, int32_t rows_cap, int32
     *rows = nr;
     for (int r = 0; r < std::min(nr, (int)rows_cap); ++r)
       for (int c = 0; c < 10; ++c) out[10 * r + c] = H->stats_rows[r][c];
+  });
+}
+
+extern "C" h2_status h2_level_timing(h2_handle H, double* ms, int32_t cap, int32_t* count) {
+  return guarded([&] {
+    if (!H || !count) fail(H2_ERR_ARG, "NULL argument");
+    if (!H->factored) fail(H2_ERR_STATE, "h2_level_timing before h2_factor");
+    const int nr = (int)H->level_ms.size();
+    *count = nr;
+    if (ms)
+      for (int r = 0; r < std::min(nr, (int)cap); ++r) ms[r] = H->level_ms[r];
   });
 }
 

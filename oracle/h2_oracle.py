@@ -474,7 +474,7 @@ def fill_spectrum(Bi, W, nu_i, efill, cap):
     return U, sig, tau, p, margin
 
 
-def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_trace=None):
+def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_trace=None, stop_level=None):
     """Level-by-level factorization Z_H2 = L U in product form (eq. 34).
 
     order="colour": clusters of one colour take each step together (R2);
@@ -482,6 +482,9 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
     forced_kt maps (level, cluster) -> k~ to pin the Step 0 rank decisions.
     trace / step0_trace (lists, test use) receive the state at the start of
     every level / the fill-ins W and threshold of every Step 0.
+    stop_level (default l0): the last level factored; the matrix merged to the
+    level above it is then factored densely (Sec. III-C: when a level brings
+    few zeros, the rest is better done by a dense LU).
     """
     S = H.S
     L = S.L
@@ -495,6 +498,9 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
             Zt[a0:a0 + B.shape[0], b0:b0 + B.shape[1]] = B
         return Factorization(H, [], _lu(Zt), Zt.shape[0], order, ledger)
 
+    ls = S.l0 if stop_level is None else int(stop_level)
+    if not S.l0 <= ls <= L:
+        raise ValueError(f"stop_level must lie in [l0, L] = [{S.l0}, {L}]")
     # level-L state
     nsz = np.array([c.size for c in S.clusters[L]], dtype=np.int64)
     B = [H.basis[L][t] for t in range(len(nsz))]
@@ -504,7 +510,7 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
     fills = {}
     levels = []
     stats = []
-    for l in range(L, S.l0 - 1, -1):
+    for l in range(L, ls - 1, -1):
         if trace is not None:
             trace.append(dict(level=l, n=nsz.copy(), B=list(B), Z={a: v.copy() for a, v in Z.items()},
                               fills={a: v.copy() for a, v in fills.items()}))
@@ -655,7 +661,7 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
             cb = 0 if b % 2 == 0 else off1[b // 2]
             dst[ra:ra + M.shape[0], cb:cb + M.shape[1]] += M
 
-        if pl >= S.l0:
+        if pl >= ls:
             parent_pairs = S.near[pl]
         else:
             nz = [p for p in range(npar) if S.clusters[pl][p].size]
@@ -672,6 +678,10 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
             if (a, b) in admset:
                 continue
             key = (a // 2, b // 2)
+            if pl < ls:
+                # the dense final block holds every pair: the carried fill lands there
+                place(Znew[key], a, b, M)
+                continue
             if key in Znew:
                 raise AssertionError("ancestor-admissible fill under an inadmissible parent")
             if key not in fnew:
@@ -679,8 +689,10 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
             place(fnew[key], a, b, M)
         levels.append(dict(level=l, facs=facs, kt=kt.copy(), n=nsz.copy(), off1=off1,
                            n_par=n_par, groups=[g for g in groups]))
+        if pl < ls and pl >= S.l0:
+            _add_far_blocks(H, pl, l, n_par, off1, Znew)
         # parent bases: transfer matrices padded with zero rows (eq. 23)
-        if pl >= S.l0:
+        if pl >= ls:
             Bn = []
             for p in range(npar):
                 if S.clusters[pl][p].size == 0:
@@ -700,8 +712,8 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
         nsz = n_par
         Z = Znew
         fills = fnew
-    # final dense block at level l0 - 1 (Alg. 1, line 14)
-    pl = S.l0 - 1
+    # final dense block at level ls - 1 (Alg. 1, line 14)
+    pl = ls - 1
     nz = [p for p in range(len(S.clusters[pl])) if S.clusters[pl][p].size]
     offs = {}
     o = 0
@@ -715,6 +727,50 @@ def factor(H, eps_fill=None, order="colour", forced_kt=None, trace=None, step0_t
         raise AssertionError("fill-ins left outside the final block")
     ledger["lu"] += 8.0 / 3.0 * o ** 3
     return Factorization(H, levels, _lu(Zf), o, order, ledger, stats)
+
+
+def _add_far_blocks(H, pl, l, n_par, off1, Znew):
+    """Early stop: the blocks of level-pl pairs that are admissible at pl or at an
+    ancestor level l' (eqs. 2-3) in the merged coordinates of level pl:
+    B_p E_p S_{p'q'} E_q^T B_q^T, with B_p the padded transfer matrix (eq. 23) and
+    E_p the product of the transfer-matrix rows along the path from p up to p'."""
+    S = H.S
+    near = set(S.near[pl])
+    adm = [set(S.adm[m]) for m in range(S.L + 1)]
+    nz = [p for p in range(len(S.clusters[pl])) if S.clusters[pl][p].size]
+    Bp = {}
+    for p in nz:
+        T = H.basis[pl][p]
+        k1 = H.rank[l][2 * p] if S.clusters[l][2 * p].size else 0
+        k2 = H.rank[l][2 * p + 1] if S.clusters[l][2 * p + 1].size else 0
+        M = np.zeros((n_par[p], T.shape[1]), complex)
+        M[:k1] = T[:k1]
+        M[off1[p]:off1[p] + k2] = T[k1:k1 + k2]
+        Bp[p] = M
+
+    def expanded(p, lev):
+        """B_p E_p: the columns of the level-lev ancestor's basis, restricted to p."""
+        X = Bp[p]
+        c = p
+        for m in range(pl, lev, -1):
+            par = c // 2
+            k_first = H.rank[m][2 * par] if S.clusters[m][2 * par].size else 0
+            rows = slice(0, H.rank[m][c]) if c % 2 == 0 else slice(k_first, k_first + H.rank[m][c])
+            X = X @ H.basis[m - 1][par][rows]
+            c = par
+        return X
+
+    for p in nz:
+        for q in nz:
+            if (p, q) in near:
+                continue
+            for lev in range(pl, S.l0 - 1, -1):
+                pa, qa = p >> (pl - lev), q >> (pl - lev)
+                if (pa, qa) in adm[lev]:
+                    Znew[(p, q)] += expanded(p, lev) @ H.coupling[lev][(pa, qa)] @ expanded(q, lev).T
+                    break
+            else:
+                raise AssertionError("pair covered by no admissible block")
 
 
 # --------------------------------------------------------------------------

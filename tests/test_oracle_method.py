@@ -91,6 +91,27 @@ def test_no_truncation_limit_equals_dense_solve(grid, leaf, eps):
     assert _dense_inverse_check(Fs, H, 1e-11) < 1e-11
 
 
+@pytest.mark.parametrize("grid,leaf,eps", [((10, 7, 9), 12, 1e-5), ((8, 8, 8), 4, 1e-4), ((9, 5, 3), 7, 1e-3)])
+def test_early_stop_no_truncation_equals_dense_solve(grid, leaf, eps):
+    """Early stop (Sec. III-C): factoring levels L..ls and finishing with a dense LU of the
+    matrix merged to level ls - 1, whose far blocks come from the nested bases and
+    couplings of every coarser admissible level, still solves Z_H2 exactly when nothing is
+    truncated, for every stop level from l0 to L."""
+    pr, H = _prob(grid, leaf, eps)
+    S = H.S
+    assert S.L - S.l0 >= 2
+    sizes = []
+    for ls in range(S.l0, S.L + 1):
+        Fz = O.factor(H, eps_fill=1e-14, stop_level=ls)
+        assert len(Fz.levels) == S.L - ls + 1
+        assert _dense_inverse_check(Fz, H, 1e-11) < 1e-11
+        sizes.append(Fz.final_n)
+    # fewer factored levels leave a larger dense block
+    assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+    with pytest.raises(ValueError):
+        O.factor(H, stop_level=S.l0 - 1)
+
+
 def test_eta_zero_is_dense_lu():
     """eta = 0: no block is admissible, the method reduces to LU of the whole matrix."""
     pr, H = _prob((8, 8, 8), 16, 1e-4, eta=0.0)

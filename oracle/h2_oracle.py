@@ -11,6 +11,7 @@ It restates, in slow and readable NumPy/SciPy (complex128), what Ma & Jiao,
 * nested cluster bases and coupling matrices             (Sec. II, eqs. 2-3)
 * level-by-level factorization, Steps 0-3                (Sec. III-A/B, eqs. 4-33, Algs. 1-4)
 * product-form factors and their inverse                 (Sec. III-C, eqs. 34-35)
+* early stop: a dense LU once a level brings few zeros    (Sec. III-C, closing remark)
 * forward / backward substitution                        (Sec. IV, eqs. 36-42, Algs. 5-6)
 * the relative residual used as the accuracy measure      (Sec. VI-B)
 
@@ -40,9 +41,11 @@ counts, kernel entries against closed forms, nested-basis identities, the
 Step 0 rank rule on fill-ins of designed spectrum and the eq. 17 bound on
 the dropped fill-ins, zero introduction (eqs. 7-8), the
 no-truncation limit against a dense solve of the represented matrix, the
-eta = 0 limit against dense LU, the adjoint dot-product identity, accuracy
-versus eps, linear storage on rods, and the gradient against finite
-differences of a dense solve.  No function here is "parity unpinned".
+eta = 0 limit against dense LU, the early stop at every level from l0 to L
+against a dense solve of the represented matrix (no truncation), the adjoint
+dot-product identity, accuracy versus eps, linear storage on rods, and the
+gradient against finite differences of a dense solve.  No function here is
+"parity unpinned".
 """
 from __future__ import annotations
 

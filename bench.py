@@ -268,7 +268,8 @@ def form_leg(torch, G, pr, precision: str, steps: int, warmup: int, b, B64, tag:
     stats = G.stats()
     G.set_kernel_timing(True)
     G.factor()
-    kern = kernel_rooflines(G.kernel_ledger(), solve1_ms, matvec_ms, mixed=(precision == "mixed"))
+    kled = G.kernel_ledger()
+    kern = kernel_rooflines(kled, solve1_ms, matvec_ms, mixed=(precision == "mixed"))
     G.set_kernel_timing(False)
     print(f"# {tag} {precision} solves and kernel timing done", file=sys.stderr, flush=True)
     tm = np.median(np.array(timings), axis=0)
@@ -286,6 +287,7 @@ def form_leg(torch, G, pr, precision: str, steps: int, warmup: int, b, B64, tag:
            "rel_residual_first": info["rel_residual_first"],
            "solve_ms_refined_1e-8": solve_ref_ms, "solve_ms_1rhs": solve1_ms, "solve_ms_64rhs": solve64_ms,
            "matvec_ms_1rhs": matvec_ms, "kernel_roofline": kern,
+           "schur_fp32_flop_frac": kled["schur_fp32_flop_frac"],
            "_ledger": ledger, "_schur_ms": float(tm[3])}
     return out
 

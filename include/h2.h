@@ -71,6 +71,24 @@ typedef struct {
   const int32_t* forced_ranks; /* optional host array pinning rank decisions, layout in
                                   h2_forced_ranks_layout(); NULL: decide from eps */
   int64_t forced_ranks_len;    /* number of int32 entries behind forced_ranks */
+  /* Optional device allocator (both or neither; Python passes PyTorch's caching
+   * allocator).  Every device buffer the handle owns then comes from alloc(bytes,
+   * stream, alloc_ctx), where stream is the hipStream_t of the call that needs it,
+   * and goes back through free(p, stream, alloc_ctx) after the library has waited
+   * for all of its device work.  alloc returning NULL makes the call fail with
+   * H2_ERR_OOM; the handle stays usable (a failed h2_factor leaves it unfactored).
+   * Buffers grow on demand and are kept by the handle until h2_destroy, so calls
+   * after the first factorization and solve of a given size allocate nothing.
+   * The functions may be called from the library's batch threads.  NULL: the
+   * library uses hipMalloc / hipFree. */
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* p, void* stream, void* ctx);
+  void* alloc_ctx;
+  int32_t stop_level;          /* last level factored (Sec. III-C, closing remark): levels
+                                  L..stop_level take Steps 0-3, and the matrix merged to
+                                  level stop_level - 1 is factored by a dense LU; 0: the
+                                  coarsest admissible level l0 (Alg. 1); otherwise it must
+                                  lie in [l0, L] (H2_ERR_ARG) */
 } h2_options;
 
 typedef struct {
@@ -115,9 +133,28 @@ h2_status h2_set_precision(h2_handle H, int32_t precision);
  * Results are identical to the direct launches.  Default: off. */
 h2_status h2_set_sweep_graph(h2_handle H, int32_t enable);
 
+/* Change the stop level of later factorizations (the meaning of
+ * h2_options.stop_level; 0 = l0).  The handle becomes unfactored. */
+h2_status h2_set_stop_level(h2_handle H, int32_t level);
+
+/* The stop level in force (*level = 0 when no block is admissible). */
+h2_status h2_stop_level(h2_handle H, int32_t* level);
+
+/* Choose the stop level by measurement: factor with the stop at l0, l0 + 1, ...
+ * (HIP-event time of each whole factorization, ms[e] for the stop l0 + e when
+ * ms is not NULL, n_ms entries, -1 where not tried) and keep the fastest.  A
+ * run stopped at l knows the kept unknowns of level l + 1, i.e. the dense block
+ * a stop at l + 1 would leave; the search ends before that block would exceed
+ * max_final unknowns.  The handle is left factored with the chosen level
+ * (*chosen).  Synchronises the stream. */
+h2_status h2_tune_stop_level(h2_handle H, int64_t max_final, void* hip_stream, int32_t* chosen, double* ms,
+                             int32_t n_ms);
+
 /* Factor Z = L U in the product form of eq. 34 (Alg. 1 with Steps 0-3 per
  * cluster, Algs. 2-4; coupling/transfer updates eqs. 20-23 / 33; final LU of
- * the level-(l0-1) block).  Synchronises once per level to size the next
+ * the block merged to the level above the stop level, l0 - 1 by default; an
+ * early stop adds to it the blocks of coarser admissible pairs expanded
+ * through the transfer matrices, eqs. 2-3).  Synchronises once per level to size the next
  * level's storage.  H2_ERR_SINGULAR leaves the handle unfactored. */
 h2_status h2_factor(h2_handle H, void* hip_stream);
 
@@ -241,7 +278,11 @@ h2_status h2_set_kernel_timing(h2_handle H, int32_t enable);
  * out[3f+2] = bytes.  out[24] = bytes one right-hand side's forward and
  * backward sweeps must read (Q~ twice, L^-1 P, U^-1, the C and R panels, the
  * final inverse); out[25] = bytes one H^2 matvec must read (near blocks,
- * expanded bases, couplings).  n_out >= 26; H2_ERR_STATE before h2_factor. */
+ * expanded bases, couplings).  out[26] (when n_out >= 27) = the fraction of
+ * the Schur flops whose cluster passed the mixed form's FP32 test (0 for
+ * FP64; a flush still runs a block's FP32-safe terms in FP64 when they carry
+ * fewer than 64 contraction columns).  n_out >= 26; H2_ERR_STATE before
+ * h2_factor. */
 h2_status h2_kernel_ledger(h2_handle H, double* out, int32_t n_out);
 
 #ifdef __cplusplus

@@ -31,10 +31,35 @@ class H2Error(RuntimeError):
         super().__init__(f"{call}: {name}: {message}")
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t), ("precision", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("eps_fill", ctypes.c_double), ("forced_ranks", ctypes.POINTER(ctypes.c_int32)),
-                ("forced_ranks_len", ctypes.c_int64)]
+                ("forced_ranks_len", ctypes.c_int64), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p), ("stop_level", ctypes.c_int32)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    """h2_options.alloc backed by PyTorch's caching allocator (NULL on failure)."""
+    torch = _torch()
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # out of memory, or no device: the library reports H2_ERR_OOM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        _torch().cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# the C function pointers must outlive every handle that uses them
+TORCH_ALLOCATOR = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
 
 
 class SolveInfo(ctypes.Structure):
@@ -84,10 +109,14 @@ def lib():
         L.h2_set_kernel_timing.argtypes = [_P, ctypes.c_int32]
         L.h2_kernel_ledger.argtypes = [_P, _DP, ctypes.c_int32]
         L.h2_level_timing.argtypes = [_P, _DP, ctypes.c_int32, _I32P]
+        L.h2_set_stop_level.argtypes = [_P, ctypes.c_int32]
+        L.h2_stop_level.argtypes = [_P, _I32P]
+        L.h2_tune_stop_level.argtypes = [_P, ctypes.c_int64, _P, _I32P, _DP, ctypes.c_int32]
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
-                     "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing"):
+                     "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing",
+                     "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,9 +196,10 @@ class H2:
     """
 
     def __init__(self, points, k, h, chi, leaf, eta, eps, eps_fill=None, precision="fp64", forced_ranks=None,
-                 stream=None):
+                 stream=None, allocator="torch", stop_level=0):
         pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
         chi = np.ascontiguousarray(chi, dtype=np.float64).reshape(-1)
+        self._points = pts
         self.n = pts.shape[0]
         self.k, self.h, self.leaf, self.eta, self.eps = float(k), float(h), int(leaf), float(eta), float(eps)
         self.chi = chi.copy()
@@ -179,10 +209,18 @@ class H2:
         opt.precision = H2_MIXED if precision == "mixed" else H2_FP64
         opt.order = 0
         opt.eps_fill = float(eps_fill) if eps_fill else 0.0
+        opt.stop_level = int(stop_level or 0)
         if forced_ranks is not None:
             self._forced = np.ascontiguousarray(forced_ranks, dtype=np.int32).reshape(-1)
             opt.forced_ranks = self._forced.ctypes.data_as(_I32P)
             opt.forced_ranks_len = self._forced.size
+        # device memory: PyTorch's caching allocator ("torch"), the library's own hipMalloc
+        # (None), or a pair of ctypes callbacks (ALLOC_FN, FREE_FN)
+        if allocator == "torch":
+            allocator = TORCH_ALLOCATOR
+        self._allocator = allocator
+        if allocator is not None:
+            opt.alloc, opt.free = allocator
         self._h = ctypes.c_void_p()
         st = _stream_ptr(stream)
         _check(lib().h2_build(_dptr(pts), self.n, self.k, self.h, _dptr(chi), self.leaf, self.eta, self.eps,
@@ -205,6 +243,31 @@ class H2:
             raise ValueError(precision)
         _check(lib().h2_set_precision(self._h, H2_MIXED if precision == "mixed" else H2_FP64), "h2_set_precision")
         return self
+
+    def set_stop_level(self, level: int = 0):
+        """Last factored level of later factorizations (0: l0); the handle becomes unfactored."""
+        _check(lib().h2_set_stop_level(self._h, int(level)), "h2_set_stop_level")
+        return self
+
+    def stop_level(self) -> int:
+        out = ctypes.c_int32()
+        _check(lib().h2_stop_level(self._h, ctypes.byref(out)), "h2_stop_level")
+        return out.value
+
+    def tune_stop_level(self, max_final: int = 12288, stream=None):
+        """Pick the fastest stop level by factoring with each candidate (h2_tune_stop_level);
+        returns (chosen level, {level: factor ms}) and leaves the handle factored."""
+        ms = np.full(64, -1.0)
+        chosen = ctypes.c_int32()
+        _check(lib().h2_tune_stop_level(self._h, int(max_final), _stream_ptr(stream), ctypes.byref(chosen),
+                                        _dptr(ms), ms.size), "h2_tune_stop_level")
+        base = self.stop_level_range()[0]
+        return chosen.value, {base + e: float(t) for e, t in enumerate(ms) if t >= 0}
+
+    def stop_level_range(self):
+        """(l0, L) of the handle's block tree."""
+        st = structure(self._points, self.h, self.leaf, self.eta)
+        return st["l0"], st["L"]
 
     def set_sweep_graph(self, enable: bool = True):
         """Replay the solve sweeps from captured HIP graphs."""
@@ -310,11 +373,12 @@ class H2:
         """{family: (ms, flops, bytes)} of the last factorization (h2_kernel_ledger; ms is -1
         when kernel timing was off), plus the bytes one right-hand side's sweeps and one
         matvec must read."""
-        out = np.zeros(26)
+        out = np.zeros(27)
         _check(lib().h2_kernel_ledger(self._h, _dptr(out), out.size), "h2_kernel_ledger")
         d = {f: (out[3 * i], out[3 * i + 1], out[3 * i + 2]) for i, f in enumerate(KERNEL_FAMILIES)}
         d["sweep_bytes_per_rhs"] = out[24]
         d["matvec_bytes"] = out[25]
+        d["schur_fp32_flop_frac"] = out[26]
         return d
 
 

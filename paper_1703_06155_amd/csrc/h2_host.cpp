@@ -61,17 +61,46 @@ struct Fail {
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
+// Where device memory comes from: the caller's allocator when h2_build was given
+// one (h2_options.alloc / free / alloc_ctx), else hipMalloc / hipFree.  Every call
+// on a handle runs with that handle's allocator and stream installed for the
+// calling thread (AllocScope), so buffers allocated anywhere inside the call take
+// it; each buffer remembers the allocator it came from.
+struct DevAllocator {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx) = nullptr;
+  void (*free)(void* p, void* stream, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+static thread_local const DevAllocator* t_alloc = nullptr;
+static thread_local hipStream_t t_stream = nullptr;
+static thread_local bool t_device_idle = false;  // set while h2_destroy frees after one device-wide wait
+
+struct AllocScope {
+  const DevAllocator* prev_a;
+  hipStream_t prev_s;
+  AllocScope(const DevAllocator* a, hipStream_t s) : prev_a(t_alloc), prev_s(t_stream) {
+    t_alloc = (a && a->alloc && a->free) ? a : nullptr;
+    t_stream = s;
+  }
+  ~AllocScope() {
+    t_alloc = prev_a;
+    t_stream = prev_s;
+  }
+};
+
 template <typename T>
 struct DArr {
   T* p = nullptr;
   size_t n = 0;    // elements in use
   size_t cap = 0;  // elements allocated
+  const DevAllocator* from = nullptr;  // caller's allocator that provided p (NULL: hipMalloc)
   DArr() = default;
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
-  DArr(DArr&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n), cap(o.cap), from(o.from) {
     o.p = nullptr;
     o.n = o.cap = 0;
+    o.from = nullptr;
   }
   DArr& operator=(DArr&& o) noexcept {
     if (this != &o) {
@@ -79,15 +108,27 @@ struct DArr {
       p = o.p;
       n = o.n;
       cap = o.cap;
+      from = o.from;
       o.p = nullptr;
       o.n = o.cap = 0;
+      o.from = nullptr;
     }
     return *this;
   }
   ~DArr() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (from) {
+        // the caller's allocator may hand the memory out again at once: nothing
+        // queued by this library may still use it
+        if (!t_device_idle) (void)hipDeviceSynchronize();
+        from->free(p, t_stream, from->ctx);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
+    from = nullptr;
     n = cap = 0;
   }
   // Keeps the existing allocation when it is large enough: buffers that live
@@ -100,6 +141,13 @@ struct DArr {
       return;
     }
     release();
+    if (t_alloc) {
+      p = static_cast<T*>(t_alloc->alloc(cnt * sizeof(T), t_stream, t_alloc->ctx));
+      if (!p) fail(H2_ERR_OOM, "the caller's allocator returned NULL for " + std::to_string(cnt * sizeof(T)) + " bytes");
+      from = t_alloc;
+      n = cap = cnt;
+      return;
+    }
     const hipError_t e = hipMalloc((void**)&p, cnt * sizeof(T));
     if (e != hipSuccess) {
       p = nullptr;
@@ -219,6 +267,7 @@ struct FactorLevel {
 }  // namespace h2
 
 struct h2_ctx {
+  h2::DevAllocator allocator;              // first member: outlives every buffer it provided
   h2::Structure S;
   int64_t N = 0;
   double k = 0, h = 0, eta = 0, eps = 0, eps_fill = 0;
@@ -279,6 +328,17 @@ struct h2_ctx {
   h2::DArr<double2> vtmp, vtmp2, vtmp3, sw_scratch, sw_part;
   int vbuf_nrhs = 0;
   h2::DArr<double> d_norms;
+  h2::DArr<double2> mv_in, mv_out;         // h2_matvec work vectors
+  h2::DArr<double2> rf_b0, rf_r, rf_ax, rf_vt;  // refinement work vectors
+  h2::DArr<double> rf_nb;
+  h2::DArr<h2::GemmTask> gm_tasks;         // task lists of run_gemms (final dense LU)
+  h2::DArr<int32_t> gm_tt, gm_rc;
+  h2::DArr<int32_t> lv_k1, lv_k2, lv_off1; // per-level uploads of factor_impl
+  h2::DArr<int64_t> lv_toff, lv_so, lv_do, lv_len;
+  int stop = -1;                           // last factored level (l0 unless stopped early, Sec. III-C)
+  h2::DArr<double2> fb_X, fb_Y;            // early stop: expanded bases and their products with couplings
+  h2::DArr<int32_t> fb_n, fb_k, fb_k1, fb_k2, fb_off1;
+  h2::DArr<int64_t> fb_toff, fb_xoff;
   std::vector<std::vector<int64_t>> stats_rows;
   std::vector<double> level_ms;            // per stats row: ms of that level (Steps 0-3 and its merge) / final LU
 };
@@ -581,7 +641,9 @@ static void upload_plan(LevelPlan& P, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // batched GEMM helper (host-resolved tasks)
 // ---------------------------------------------------------------------------
-static void run_gemms(const std::vector<GemmTask>& tasks, hipStream_t st) {
+// Task lists live in handle-owned grow-only buffers; the call waits for its
+// launch before the lists are reused.
+static void run_gemms(h2_ctx* H, const std::vector<GemmTask>& tasks, hipStream_t st) {
   if (tasks.empty()) return;
   std::vector<int32_t> tt, rc;
   for (size_t i = 0; i < tasks.size(); ++i) {
@@ -592,8 +654,9 @@ static void run_gemms(const std::vector<GemmTask>& tasks, hipStream_t st) {
         rc.push_back(a | (b << 16));
       }
   }
-  DArr<GemmTask> dt;
-  DArr<int32_t> dtt, drc;
+  DArr<GemmTask>& dt = H->gm_tasks;
+  DArr<int32_t>& dtt = H->gm_tt;
+  DArr<int32_t>& drc = H->gm_rc;
   dt.alloc(tasks.size());
   HIPCHK(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(GemmTask), hipMemcpyHostToDevice, st));
   dtt.upload(tt, st);
@@ -820,7 +883,7 @@ static void construct(h2_ctx* H, hipStream_t st) {
       }
       // rows of a child with k = 0 must read as zero
       launch_zero(B.V.p, B.voff[nc], st);
-      run_gemms(tasks, st);
+      run_gemms(H, tasks, st);
     }
     B.ktot = 0;
     for (int t = 0; t < nc; ++t) B.ktot += B.k[t];
@@ -881,7 +944,7 @@ static void construct(h2_ctx* H, hipStream_t st) {
         trans.push_back({B.S.p + B.soff[e], nullptr, B.S.p + B.soff[et], (int64_t)std::max(1, B.k[t]), 0,
                          (int64_t)std::max(1, B.k[s]), B.k[t], B.k[s], 0, 0, 0, 0});
       }
-      run_gemms(tasks, st);
+      run_gemms(H, tasks, st);
       DArr<GemmTask> dtr;
       dtr.alloc(trans.size());
       HIPCHK(hipMemcpyAsync(dtr.p, trans.data(), trans.size() * sizeof(GemmTask), hipMemcpyHostToDevice, st));
@@ -1015,6 +1078,158 @@ static void release_factor_buffers(h2_ctx* H) {
   H->vbuf_nrhs = 0;
 }
 
+// Early stop (Sec. III-C): the final dense block is the matrix merged to level
+// pl = ls - 1.  Its pairs that are inadmissible at pl come from the merge; every
+// other pair (p, q) lies in an admissible block (p', q') of some level lev <= pl
+// (eq. 2), whose entries in the merged coordinates of level pl are
+// X_p S_p'q' X_q^T with X_p = B_p E_p: B_p the transfer matrix of p padded with
+// zero rows for its children's added columns (eq. 23) and E_p the product of
+// the transfer-matrix rows along the path from p up to p' (eq. 3).  The carried
+// fill-ins of those pairs were placed by the merge; these products are added.
+static void add_far_blocks(h2_ctx* H, int ls, const std::vector<int32_t>& n_par, const std::vector<int32_t>& off1,
+                           hipStream_t st) {
+  const Structure& S = H->S;
+  const int L = S.L, l0 = S.l0, pl = ls - 1;
+  const int npar = S.nclusters(pl);
+  const int nlv = pl - l0 + 1;  // levels pl, pl - 1, ..., l0
+  auto kc = [&](int lev, int t) -> int64_t { return S.size[lev][t] ? H->build[L - lev].k[t] : 0; };
+  // X_p^(lev) for every nonempty p of level pl: n_par[p] x k(ancestor at lev), packed
+  std::vector<int64_t> xoff((size_t)nlv * npar + 1, 0);
+  for (int d = 0; d < nlv; ++d)
+    for (int p = 0; p < npar; ++p) {
+      const size_t e = (size_t)d * npar + p;
+      xoff[e + 1] = xoff[e] + (S.size[pl][p] ? (int64_t)n_par[p] * kc(pl - d, p >> d) : 0);
+    }
+  H->fb_X.alloc(xoff.back());
+  launch_zero(H->fb_X.p, (int64_t)H->fb_X.n, st);
+  {
+    // level pl: the padded transfer matrices
+    const BuildLevel& Bp = H->build[L - pl];
+    std::vector<int32_t> pn(npar), pk(npar), k1(npar), k2(npar);
+    for (int p = 0; p < npar; ++p) {
+      pn[p] = S.size[pl][p] ? n_par[p] : 0;
+      pk[p] = (int32_t)kc(pl, p);
+      k1[p] = (int32_t)kc(ls, 2 * p);
+      k2[p] = (int32_t)kc(ls, 2 * p + 1);
+    }
+    H->fb_n.upload(pn, st);
+    H->fb_k.upload(pk, st);
+    H->fb_k1.upload(k1, st);
+    H->fb_k2.upload(k2, st);
+    H->fb_off1.upload(off1, st);
+    H->fb_toff.upload(std::vector<int64_t>(Bp.boff.begin(), Bp.boff.end() - 1), st);
+    H->fb_xoff.upload(std::vector<int64_t>(xoff.begin(), xoff.begin() + npar), st);
+    launch_parent_basis(npar, H->fb_n.p, H->fb_k.p, H->fb_k1.p, H->fb_k2.p, H->fb_off1.p, H->fb_toff.p,
+                        Bp.basis.p, H->fb_xoff.p, H->fb_X.p, st);
+    check_launch("far blocks: padded transfer matrices");
+  }
+  // coarser levels: X_p^(lev) = X_p^(lev+1) T_par[rows of the child on the path]
+  for (int d = 1; d < nlv; ++d) {
+    const int lev = pl - d;
+    const BuildLevel& Bl = H->build[L - lev];
+    std::vector<GemmTask> tasks;
+    for (int p = 0; p < npar; ++p) {
+      if (!S.size[pl][p] || n_par[p] == 0) continue;
+      const int c = p >> (d - 1), par = c >> 1;
+      const int64_t kchild = kc(lev + 1, c), kpar = kc(lev, par);
+      if (kchild == 0 || kpar == 0) continue;
+      const int64_t ldt = kc(lev + 1, 2 * par) + kc(lev + 1, 2 * par + 1);
+      const int64_t row0 = (c & 1) ? kc(lev + 1, 2 * par) : 0;
+      GemmTask t{};
+      t.A = H->fb_X.p + xoff[(size_t)(d - 1) * npar + p];
+      t.lda = n_par[p];
+      t.B = Bl.basis.p + Bl.boff[par] + row0;
+      t.ldb = ldt;
+      t.C = H->fb_X.p + xoff[(size_t)d * npar + p];
+      t.ldc = n_par[p];
+      t.m = n_par[p];
+      t.n = (int32_t)kpar;
+      t.K = (int32_t)kchild;
+      t.opA = OP_N;
+      t.opB = OP_N;
+      t.mode = ST_SET;
+      tasks.push_back(t);
+    }
+    run_gemms(H, tasks, st);
+  }
+  // every pair not inadmissible at pl: Y = X_p S_p'q', then Z_f(p, q) += Y X_q^T
+  std::vector<std::unordered_map<int64_t, int32_t>> adm_index(nlv);
+  for (int d = 0; d < nlv; ++d) {
+    const int lev = pl - d;
+    const int64_t nc = S.nclusters(lev);
+    for (size_t e = 0; e < S.adm[lev].size(); ++e)
+      adm_index[d][(int64_t)S.adm[lev][e].first * nc + S.adm[lev][e].second] = (int32_t)e;
+  }
+  std::unordered_map<int64_t, char> near_pl;
+  for (const Pair& pr : S.near[pl]) near_pl[(int64_t)pr.first * npar + pr.second] = 1;
+  struct Far {
+    int p, q, d, e;
+  };
+  std::vector<Far> far;
+  int64_t ytot = 0;
+  std::vector<int64_t> yoff;
+  for (int p = 0; p < npar; ++p) {
+    if (!S.size[pl][p] || n_par[p] == 0) continue;
+    for (int q = 0; q < npar; ++q) {
+      if (!S.size[pl][q] || n_par[q] == 0) continue;
+      if (near_pl.count((int64_t)p * npar + q)) continue;
+      int found = -1, fe = -1;
+      for (int d = 0; d < nlv && found < 0; ++d) {
+        const int64_t nc = S.nclusters(pl - d);
+        auto it = adm_index[d].find((int64_t)(p >> d) * nc + (q >> d));
+        if (it != adm_index[d].end()) {
+          found = d;
+          fe = it->second;
+        }
+      }
+      if (found < 0) fail(H2_ERR_INTERNAL, "early stop: a pair covered by no admissible block");
+      if (kc(pl - found, p >> found) == 0 || kc(pl - found, q >> found) == 0) continue;
+      far.push_back({p, q, found, fe});
+      yoff.push_back(ytot);
+      ytot += (int64_t)n_par[p] * kc(pl - found, q >> found);
+    }
+  }
+  if (far.empty()) return;
+  H->fb_Y.alloc(ytot);
+  std::vector<GemmTask> t1, t2;
+  for (size_t f = 0; f < far.size(); ++f) {
+    const Far& F = far[f];
+    const int lev = pl - F.d;
+    const BuildLevel& Bl = H->build[L - lev];
+    const int64_t kp = kc(lev, F.p >> F.d), kq = kc(lev, F.q >> F.d);
+    GemmTask a{};
+    a.A = H->fb_X.p + xoff[(size_t)F.d * npar + F.p];
+    a.lda = n_par[F.p];
+    a.B = Bl.S.p + Bl.soff[F.e];
+    a.ldb = kp;
+    a.C = H->fb_Y.p + yoff[f];
+    a.ldc = n_par[F.p];
+    a.m = n_par[F.p];
+    a.n = (int32_t)kq;
+    a.K = (int32_t)kp;
+    a.opA = OP_N;
+    a.opB = OP_N;
+    a.mode = ST_SET;
+    t1.push_back(a);
+    GemmTask b{};
+    b.A = H->fb_Y.p + yoff[f];
+    b.lda = n_par[F.p];
+    b.B = H->fb_X.p + xoff[(size_t)F.d * npar + F.q];
+    b.ldb = n_par[F.q];
+    b.C = H->Zf.p + H->final_off[F.p] + (int64_t)H->final_off[F.q] * H->nf;
+    b.ldc = H->nf;
+    b.m = n_par[F.p];
+    b.n = n_par[F.q];
+    b.K = (int32_t)kq;
+    b.opA = OP_N;
+    b.opB = OP_T;
+    b.mode = ST_ADD;
+    t2.push_back(b);
+  }
+  run_gemms(H, t1, st);
+  run_gemms(H, t2, st);
+}
+
 static void factor_impl(h2_ctx* H, hipStream_t st) {
   const Structure& S = H->S;
   const int L = S.L, l0 = S.l0;
@@ -1065,12 +1280,13 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     H->factored = true;
     return;
   }
-  const int nlev = L - l0 + 1;
+  const int ls = H->stop;  // last factored level; the matrix merged to level ls - 1 is factored densely
+  const int nlev = L - ls + 1;
   H->flev.resize(nlev);
   // block arenas of consecutive levels alternate between two handle-owned buffers
   std::vector<int32_t> n_cur(S.nclusters(L));
   for (int t = 0; t < S.nclusters(L); ++t) n_cur[t] = (int32_t)S.size[L][t];
-  for (int l = L; l >= l0; --l) {
+  for (int l = L; l >= ls; --l) {
     const int j = L - l;
     LevelPlan& P = H->plans[j];
     BuildLevel& Bd = H->build[j];
@@ -1182,10 +1398,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);
-    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile), when that fits in
-    // SCHUR_PART_MAX_BYTES and an eighth of the free device memory (the buffer is kept
-    // for later factorizations; large allocations cost about 28 ms per GB); otherwise
-    // this level flushes every block whole
+    // split Schur tasks: one 64 x 64 partial tile per (chunk, tile) when the level's
+    // partial tiles fit in SCHUR_PART_MAX_BYTES, otherwise this level flushes every
+    // block whole.  The choice depends on the level's sizes only (never on free
+    // device memory), so a problem's arithmetic - the order in which a block's terms
+    // are summed and, in the mixed form, which of them run in FP32 - is the same in
+    // every run, batched or not; the buffer is kept for later factorizations.
     // A chunk of a split flush of block (a, b) keeps ceil(n_a / 64) ceil(n_b / 64) tiles.
     auto group_bases = [&](ColourPlan& C) -> int64_t {
       C.sc_gbase.resize(C.ngrp);
@@ -1201,14 +1419,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     int64_t max_tiles = group_bases(P.fin);
     for (ColourPlan& C : P.cols) max_tiles = std::max(max_tiles, group_bases(C));
     const size_t scp_elems = (size_t)std::max<int64_t>(1, max_tiles * 4096);
-    bool split_ok = true;
-    {
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-        const size_t have = H->ws_scp.cap * sizeof(double2);
-        split_ok = scp_elems * sizeof(double2) <= std::min(SCHUR_PART_MAX_BYTES, (have + fr) / 8);
-      }
-    }
+    const bool split_ok = scp_elems * sizeof(double2) <= SCHUR_PART_MAX_BYTES;
     if (split_ok) {
       H->ws_scp.alloc(scp_elems);
       P.fin.d_sc_gbase.upload(P.fin.sc_gbase, st);
@@ -1247,7 +1458,9 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
           dofs[e] = slot_off[e];
           len[e] = slot_off[e + 1] - slot_off[e];
         }
-        DArr<int64_t> d_so, d_do, d_len;
+        DArr<int64_t>& d_so = H->lv_so;
+        DArr<int64_t>& d_do = H->lv_do;
+        DArr<int64_t>& d_len = H->lv_len;
         d_so.upload(so, st);
         d_do.upload(dofs, st);
         d_len.upload(len, st);
@@ -1269,8 +1482,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         off1[p] = H->plans[j - 1].nonempty[2 * p] ? Fc.kt[2 * p] : 0;
       }
       std::vector<int64_t> toff(Bd.boff.begin(), Bd.boff.end() - 1);
-      DArr<int32_t> d_k1, d_k2, d_off1;
-      DArr<int64_t> d_toff;
+      DArr<int32_t>& d_k1 = H->lv_k1;
+      DArr<int32_t>& d_k2 = H->lv_k2;
+      DArr<int32_t>& d_off1 = H->lv_off1;
+      DArr<int64_t>& d_toff = H->lv_toff;
       d_k1.upload(k1, st);
       d_k2.upload(k2, st);
       d_off1.upload(off1, st);
@@ -1423,7 +1638,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     std::vector<MergeTask> mt(P.merge.size());
     int64_t dst_total = 0;
     std::vector<int64_t> pslot_off;
-    if (l > l0) {
+    if (l > ls) {
       const LevelPlan& Pp = H->plans[j + 1];
       pslot_off.assign(Pp.nslot + 1, 0);
       for (int s = 0; s < Pp.nslot; ++s)
@@ -1475,7 +1690,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     if (!mt.empty())
       HIPCHK(hipMemcpyAsync(d_mt.p, mt.data(), mt.size() * sizeof(MergeTask), hipMemcpyHostToDevice, st));
     double2* dst;
-    if (l > l0) {
+    if (l > ls) {
       parent_slots.alloc(dst_total);
       dst = parent_slots.p;
     } else {
@@ -1485,7 +1700,8 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     H->merge_elems += (double)dst_total;
     launch_zero(dst, dst_total, st);
     launch_merge(v, d_mt.p, (int)mt.size(), Bd.S.p, dst, st);
-    check_launch("host.cpp:1167");
+    check_launch("merge");
+    if (l == ls && ls > l0) add_far_blocks(H, ls, n_par, off1, st);
     hipEvent_t e_m1 = ev.next(st);
     HIPCHK(hipStreamSynchronize(st));
     H->timing[4] += elapsed(e_m0, e_m1);
@@ -1520,7 +1736,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   dense_lu_inverse(H, st);
   hipEvent_t t_end = ev.next(st);
   HIPCHK(hipStreamSynchronize(st));
-  H->stats_rows.push_back({l0 - 1, (int64_t)S.nclusters(l0 - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
+  H->stats_rows.push_back({ls - 1, (int64_t)S.nclusters(ls - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
   H->timing[5] = elapsed(e_f0, t_end);
   H->level_ms.push_back(H->timing[5]);
   for (auto& pe : phase_ev) {
@@ -1564,11 +1780,11 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
       // U12 = L11^-1 A12 (in place: one tile row owns all 64 rows of its columns)
       std::vector<GemmTask> t1{{linv.p + b * 4096, A + j0 + (j0 + w) * n, A + j0 + (j0 + w) * n, 64, n, n, (int32_t)w,
                                 (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SET}};
-      run_gemms(t1, st);
+      run_gemms(H, t1, st);
       // A22 -= L21 U12
       std::vector<GemmTask> t2{{A + (j0 + w) + j0 * n, A + j0 + (j0 + w) * n, A + (j0 + w) + (j0 + w) * n, n, n, n,
                                 (int32_t)rest, (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SUB}};
-      run_gemms(t2, st);
+      run_gemms(H, t2, st);
     }
   }
   int32_t hf = 0;
@@ -1592,10 +1808,10 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
     std::vector<GemmTask> t;
     if (j0 > 0)
       t.push_back({A + j0, X, X + j0, n, n, n, (int32_t)w, (int32_t)n, (int32_t)j0, OP_N, OP_N, ST_SUB});
-    run_gemms(t, st);
+    run_gemms(H, t, st);
     std::vector<GemmTask> t2{{linv.p + b * 4096, X + j0, tmp.p, 64, n, 64, (int32_t)w, (int32_t)n, (int32_t)w, OP_N,
                               OP_N, ST_SET}};
-    run_gemms(t2, st);
+    run_gemms(H, t2, st);
     HIPCHK(hipMemcpy2DAsync(X + j0, n * sizeof(double2), tmp.p, 64 * sizeof(double2), w * sizeof(double2), n,
                             hipMemcpyDeviceToDevice, st));
   }
@@ -1605,10 +1821,10 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
     if (rest > 0)
       t.push_back({A + j0 + (j0 + w) * n, X + j0 + w, X + j0, n, n, n, (int32_t)w, (int32_t)n, (int32_t)rest, OP_N,
                    OP_N, ST_SUB});
-    run_gemms(t, st);
+    run_gemms(H, t, st);
     std::vector<GemmTask> t2{{uinv.p + b * 4096, X + j0, tmp.p, 64, n, 64, (int32_t)w, (int32_t)n, (int32_t)w, OP_N,
                               OP_N, ST_SET}};
-    run_gemms(t2, st);
+    run_gemms(H, t2, st);
     HIPCHK(hipMemcpy2DAsync(X + j0, n * sizeof(double2), tmp.p, 64 * sizeof(double2), w * sizeof(double2), n,
                             hipMemcpyDeviceToDevice, st));
   }
@@ -1618,26 +1834,58 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // sweeps
 // ---------------------------------------------------------------------------
-static void ensure_vbuf(h2_ctx* H, int nrhs) {
-  if (H->vbuf_nrhs >= nrhs && !H->vbuf.empty()) return;
-  H->drop_graphs();  // captured sweeps point at the old buffers
-  H->vbuf.clear();
-  H->vbuf.resize(H->flev.size());
-  for (size_t j = 0; j < H->flev.size(); ++j) H->vbuf[j].alloc(std::max<int64_t>(1, H->flev[j].ntot) * nrhs);
-  H->vtmp.alloc(std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs);
-  H->vtmp2.alloc(std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs);
-  H->vtmp3.alloc(std::max<int64_t>(1, H->N) * nrhs);
-  // sweep scratch: per colour cluster and block of 64 right-hand sides, one (64 tiles) x 64 panel
-  int64_t blk = 1;
+// Element counts of the sweep work buffers for nrhs right-hand sides: one
+// vector per factored level, three N-vectors (final block in / out and the
+// solve's own copy), the many-RHS panel scratch and the backward gather's
+// partial sums.
+struct SweepLayout {
+  std::vector<int64_t> vbuf;
+  int64_t vtmp = 0, vtmp3 = 0, scratch = 0, part = 0;
+  int64_t total() const {
+    int64_t t = 2 * vtmp + vtmp3 + scratch + part;
+    for (int64_t v : vbuf) t += v;
+    return t;
+  }
+};
+
+static SweepLayout sweep_layout(const h2_ctx* H, int nrhs) {
+  SweepLayout L;
+  L.vbuf.resize(H->flev.size());
+  for (size_t j = 0; j < H->flev.size(); ++j) L.vbuf[j] = std::max<int64_t>(1, H->flev[j].ntot) * nrhs;
+  L.vtmp = std::max<int64_t>(1, std::max(H->nf, H->N)) * nrhs;
+  L.vtmp3 = std::max<int64_t>(1, H->N) * nrhs;
+  // per colour cluster: one (64 tiles) x 64 panel per block of 64 right-hand sides
+  // (many RHS), SV_SPLIT partial vectors of SMALL_RHS columns (few RHS)
+  int64_t blk = 1, blk_small = 1;
   for (size_t j = 0; j < H->flev.size(); ++j) {
     int maxcl = 1;
     for (const ColourPlan& C : H->plans[j].cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
     const int64_t ldp = (int64_t)H->flev[j].tiles * 64;
     blk = std::max<int64_t>(blk, (int64_t)maxcl * ldp * 64);
+    blk_small = std::max<int64_t>(blk_small, (int64_t)maxcl * ldp * SMALL_RHS * SV_SPLIT);
   }
-  const int64_t zb = (nrhs + 63) / 64;
-  H->sw_scratch.alloc(blk * zb);
-  H->sw_part.alloc(blk * std::max<int64_t>(zb * BWD_SPLIT, SV_SPLIT));
+  if (nrhs <= SMALL_RHS) {
+    L.scratch = 1;
+    L.part = blk_small;
+  } else {
+    const int64_t zb = (nrhs + 63) / 64;
+    L.scratch = blk * zb;
+    L.part = blk * zb * BWD_SPLIT;
+  }
+  return L;
+}
+
+static void ensure_vbuf(h2_ctx* H, int nrhs) {
+  if (H->vbuf_nrhs >= nrhs && !H->vbuf.empty()) return;
+  H->drop_graphs();  // captured sweeps point at the old buffers
+  const SweepLayout L = sweep_layout(H, nrhs);
+  H->vbuf.resize(H->flev.size());  // existing buffers are kept when large enough
+  for (size_t j = 0; j < H->flev.size(); ++j) H->vbuf[j].alloc(L.vbuf[j]);
+  H->vtmp.alloc(L.vtmp);
+  H->vtmp2.alloc(L.vtmp);
+  H->vtmp3.alloc(L.vtmp3);
+  H->sw_scratch.alloc(L.scratch);
+  H->sw_part.alloc(L.part);
   H->vbuf_nrhs = nrhs;
 }
 
@@ -1655,37 +1903,54 @@ static ColourTasks colour_tasks(const ColourPlan& C, int c, int tiles) {
   return ct;
 }
 
+// Device work buffers of one sweep (laid out by sweep_layout).
+struct SweepBufs {
+  std::vector<double2*> vbuf;
+  double2 *vtmp = nullptr, *vtmp2 = nullptr, *vtmp3 = nullptr, *scratch = nullptr, *part = nullptr;
+};
+
+static SweepBufs handle_bufs(h2_ctx* H, int nrhs) {
+  ensure_vbuf(H, nrhs);
+  SweepBufs B;
+  for (auto& v : H->vbuf) B.vbuf.push_back(v.p);
+  B.vtmp = H->vtmp.p;
+  B.vtmp2 = H->vtmp2.p;
+  B.vtmp3 = H->vtmp3.p;
+  B.scratch = H->sw_scratch.p;
+  B.part = H->sw_part.p;
+  return B;
+}
+
 // in (tree order, ld N) -> out (tree order, ld N): out = M^-1 in (adj = 0) or M^-H in (adj = 1), on Z
-static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj, hipStream_t st) {
+static void sweep(h2_ctx* H, const SweepBufs& W, const double2* in, double2* out, int nrhs, int adj, hipStream_t st) {
   const Structure& S = H->S;
   const int64_t N = H->N;
-  ensure_vbuf(H, nrhs);
   if (H->flev.empty()) {
-    launch_dense_apply(H->Zinv.p, N, in, H->vtmp2.p, N, nrhs, adj, st);
-    HIPCHK(hipMemcpyAsync(out, H->vtmp2.p, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    launch_dense_apply(H->Zinv.p, N, in, W.vtmp2, N, nrhs, adj, st);
+    HIPCHK(hipMemcpyAsync(out, W.vtmp2, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
     check_launch("host.cpp:1314");
     return;
   }
   const int nlev = (int)H->flev.size();
   // level L vector = input
-  HIPCHK(hipMemcpyAsync(H->vbuf[0].p, in, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(W.vbuf[0], in, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
   for (int j = 0; j < nlev; ++j) {
     FactorLevel& F = H->flev[j];
     LevelPlan& P = H->plans[j];
     for (int c = 0; c < P.ncol; ++c) {
       ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
-      launch_sweep_fwd(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, H->sw_scratch.p, st);
+      launch_sweep_fwd(F.view, ct, W.vbuf[j], F.d_voff.p, F.ntot, nrhs, adj, W.scratch, st);
     }
     const int npar = S.nclusters(P.l - 1);
     if (j + 1 < nlev) {
       FactorLevel& Fp = H->flev[j + 1];
-      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, H->vbuf[j].p, H->vbuf[j + 1].p, 1,
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, W.vbuf[j], W.vbuf[j + 1], 1,
                     P.d_nonempty.p, st);
     } else {
-      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp.p, 1,
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, W.vbuf[j], W.vtmp, 1,
                     P.d_nonempty.p, st);
-      launch_dense_apply(H->Zinv.p, H->nf, H->vtmp.p, H->vtmp2.p, H->nf, nrhs, adj, st);
-      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, H->vbuf[j].p, H->vtmp2.p, 0,
+      launch_dense_apply(H->Zinv.p, H->nf, W.vtmp, W.vtmp2, H->nf, nrhs, adj, st);
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, W.vbuf[j], W.vtmp2, 0,
                     P.d_nonempty.p, st);
       check_launch("final block");
     }
@@ -1696,26 +1961,26 @@ static void sweep(h2_ctx* H, const double2* in, double2* out, int nrhs, int adj,
     LevelPlan& P = H->plans[j];
     if (j + 1 < nlev) {
       FactorLevel& Fp = H->flev[j + 1];
-      launch_vmerge(S.nclusters(P.l - 1), F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, H->vbuf[j].p,
-                    H->vbuf[j + 1].p, 0, P.d_nonempty.p, st);
+      launch_vmerge(S.nclusters(P.l - 1), F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, W.vbuf[j],
+                    W.vbuf[j + 1], 0, P.d_nonempty.p, st);
     }
     for (int c = P.ncol - 1; c >= 0; --c) {
       ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
-      launch_sweep_bwd(F.view, ct, H->vbuf[j].p, F.d_voff.p, F.ntot, nrhs, adj, H->sw_part.p, BWD_SPLIT,
-                       H->sw_scratch.p, st);
+      launch_sweep_bwd(F.view, ct, W.vbuf[j], F.d_voff.p, F.ntot, nrhs, adj, W.part, BWD_SPLIT,
+                       W.scratch, st);
     }
     check_launch("host.cpp:1359");
   }
-  HIPCHK(hipMemcpyAsync(out, H->vbuf[0].p, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(out, W.vbuf[0], N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
 }
 
 // The sweep on H->vtmp3 in place, replayed from a captured graph when enabled.
 static void sweep_vtmp3(h2_ctx* H, int nrhs, int adj, hipStream_t st) {
+  const SweepBufs W = handle_bufs(H, nrhs);
   if (!H->use_graph || H->flev.empty()) {
-    sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, adj, st);
+    sweep(H, W, H->vtmp3.p, H->vtmp3.p, nrhs, adj, st);
     return;
   }
-  ensure_vbuf(H, nrhs);
   const auto key = std::make_pair(nrhs, adj);
   auto it = H->sweep_graphs.find(key);
   if (it == H->sweep_graphs.end()) {
@@ -1730,7 +1995,7 @@ static void sweep_vtmp3(h2_ctx* H, int nrhs, int adj, hipStream_t st) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
     try {
-      sweep(H, H->vtmp3.p, H->vtmp3.p, nrhs, adj, H->cap_stream);
+      sweep(H, W, H->vtmp3.p, H->vtmp3.p, nrhs, adj, H->cap_stream);
     } catch (...) {
       (void)hipStreamEndCapture(H->cap_stream, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -1898,6 +2163,12 @@ extern "C" h2_status h2_build(const double* points, int64_t n, double k, double 
     validate_build(points, n, k, h, contrast, leaf, eta, eps, opt, out);
     *out = nullptr;
     std::unique_ptr<h2_ctx> H(new h2_ctx());
+    if (opt && opt->struct_size >= offsetof(h2_options, alloc_ctx) + sizeof(void*)) {
+      H->allocator.alloc = opt->alloc;
+      H->allocator.free = opt->free;
+      H->allocator.ctx = opt->alloc_ctx;
+    }
+    AllocScope scope(&H->allocator, (hipStream_t)hip_stream);
     std::vector<char> msg;
     if (!build_structure(points, n, h, leaf, eta, H->S, msg)) fail(H2_ERR_ARG, msg.data());
     check_device();
@@ -1963,8 +2234,16 @@ extern "C" h2_status h2_build(const double* points, int64_t n, double k, double 
       H->plans.clear();
       H->plans.resize(L - S.l0 + 1);
       for (int l = L; l >= S.l0; --l) build_plan_level(H.get(), l, H->plans[L - l]);
+      int stop = S.l0;
+      if (opt && opt->struct_size >= offsetof(h2_options, stop_level) + sizeof(int32_t) && opt->stop_level != 0) {
+        if (opt->stop_level < S.l0 || opt->stop_level > L)
+          fail(H2_ERR_ARG, "stop_level " + std::to_string(opt->stop_level) + " outside [l0, L] = [" +
+                               std::to_string(S.l0) + ", " + std::to_string(L) + "]");
+        stop = opt->stop_level;
+      }
+      H->stop = stop;
       for (int l = L; l >= S.l0; --l)
-        build_merge(H.get(), H->plans[L - l], l > S.l0 ? &H->plans[L - l + 1] : nullptr);
+        build_merge(H.get(), H->plans[L - l], l > stop ? &H->plans[L - l + 1] : nullptr);
       for (auto& P : H->plans) upload_plan(P, st);
     }
     if (S.l0 >= 0) {
@@ -2008,6 +2287,7 @@ extern "C" h2_status h2_set_contrast(h2_handle H, const double* contrast, void* 
     if (!H) fail(H2_ERR_ARG, "handle is NULL");
     validate_contrast(contrast, H->N);
     hipStream_t st = (hipStream_t)hip_stream;
+    AllocScope scope(&H->allocator, st);
     H->factored = false;
     upload_contrast(H, contrast, st);
     H->geom.chi = H->d_chi.p;
@@ -2038,9 +2318,93 @@ extern "C" h2_status h2_set_precision(h2_handle H, int32_t precision) {
   });
 }
 
+static void set_stop(h2_ctx* H, int stop);
+
+extern "C" h2_status h2_set_stop_level(h2_handle H, int32_t level) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    const Structure& S = H->S;
+    if (S.l0 < 0) {
+      if (level != 0) fail(H2_ERR_ARG, "no admissible block: the whole matrix is factored densely");
+      return;
+    }
+    const int stop = level == 0 ? S.l0 : level;
+    if (stop < S.l0 || stop > S.L)
+      fail(H2_ERR_ARG, "stop level " + std::to_string(level) + " outside [l0, L] = [" + std::to_string(S.l0) +
+                           ", " + std::to_string(S.L) + "]");
+    set_stop(H, stop);
+  });
+}
+
+// Measured choice of the stop level: factor with the stop at l0, l0 + 1, ... and
+// keep the fastest.  A run that stops at ls knows the ranks of every level above
+// it, hence the dense block a stop at ls + 1 would leave (the kept unknowns of
+// level ls + 1); the search ends before that block would exceed max_final.
+static void set_stop(h2_ctx* H, int stop) {
+  const Structure& S = H->S;
+  if (stop == H->stop) return;
+  const int old = H->stop;
+  H->stop = stop;
+  H->factored = false;
+  for (int l : {old, stop}) build_merge(H, H->plans[S.L - l], l > stop ? &H->plans[S.L - l + 1] : nullptr);
+}
+
+extern "C" h2_status h2_tune_stop_level(h2_handle H, int64_t max_final, void* hip_stream, int32_t* chosen,
+                                        double* ms, int32_t n_ms) {
+  return guarded([&] {
+    if (!H || !chosen) fail(H2_ERR_ARG, "NULL argument");
+    if (max_final < 1) fail(H2_ERR_ARG, "max_final < 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    AllocScope scope(&H->allocator, st);
+    const Structure& S = H->S;
+    for (int32_t e = 0; ms && e < n_ms; ++e) ms[e] = -1.0;
+    if (S.l0 < 0) {
+      factor_impl(H, st);
+      *chosen = 0;
+      return;
+    }
+    int best = S.l0;
+    double best_ms = 0;
+    for (int ls = S.l0; ls <= S.L; ++ls) {
+      if (ls > S.l0) {
+        // the dense block a stop at ls leaves: the kept unknowns of level ls (known from the last run)
+        const FactorLevel& F = H->flev[S.L - ls];
+        int64_t nf = 0;
+        for (int t = 0; t < S.nclusters(ls); ++t)
+          if (S.size[ls][t]) nf += F.kt[t];
+        if (nf > max_final) break;
+      }
+      set_stop(H, ls);
+      try {
+        factor_impl(H, st);
+      } catch (...) {
+        H->factored = false;
+        throw;
+      }
+      const double t = H->timing[0];
+      if (ms && ls - S.l0 < n_ms) ms[ls - S.l0] = t;
+      if (ls == S.l0 || t < best_ms) {
+        best = ls;
+        best_ms = t;
+      }
+    }
+    set_stop(H, best);
+    if (!H->factored) factor_impl(H, st);
+    *chosen = best;
+  });
+}
+
+extern "C" h2_status h2_stop_level(h2_handle H, int32_t* level) {
+  return guarded([&] {
+    if (!H || !level) fail(H2_ERR_ARG, "NULL argument");
+    *level = H->S.l0 < 0 ? 0 : H->stop;
+  });
+}
+
 extern "C" h2_status h2_factor(h2_handle H, void* hip_stream) {
   return guarded([&] {
     if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    AllocScope scope(&H->allocator, (hipStream_t)hip_stream);
     try {
       factor_impl(H, (hipStream_t)hip_stream);
     } catch (...) {
@@ -2070,11 +2434,6 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
   ensure_vbuf(H, nrhs);
   const double2* bb = (const double2*)b;
   double2* xx = (double2*)x;
-  // copy of b (b and x may alias)
-  DArr<double2> b0;
-  b0.alloc(N * nrhs);
-  HIPCHK(hipMemcpy2DAsync(b0.p, N * sizeof(double2), bb, ld * sizeof(double2), N * sizeof(double2), nrhs,
-                          hipMemcpyDeviceToDevice, st));
   auto solve_once = [&](const double2* rhs, int64_t ldr, double2* outx, int64_t ldo, int accumulate) {
     if (!adj) {
       // M^-1 = D^-1 Z^-1
@@ -2089,20 +2448,32 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
     }
     check_launch("solve");
   };
-  solve_once(b0.p, N, xx, ld, 0);
   if (info) {
     info->iterations = 0;
     info->rel_residual = -1.0;
     info->rel_residual_first = -1.0;
   }
-  if (tol <= 0) return;
+  if (tol <= 0) {
+    // b is read into the sweep's own buffer before x is written, so they may alias;
+    // no host synchronisation and no allocation beyond first use
+    solve_once(bb, ld, xx, ld, 0);
+    return;
+  }
+  // copy of b (b and x may alias), kept for the residuals; work vectors live in the handle
+  DArr<double2>& b0 = H->rf_b0;
+  b0.alloc(N * nrhs);
+  HIPCHK(hipMemcpy2DAsync(b0.p, N * sizeof(double2), bb, ld * sizeof(double2), N * sizeof(double2), nrhs,
+                          hipMemcpyDeviceToDevice, st));
+  solve_once(b0.p, N, xx, ld, 0);
   // iterative refinement against A_H2 = Z_H2 D (or its conjugate transpose D conj(Z_H2))
-  DArr<double2> r, ax, vt;
+  DArr<double2>& r = H->rf_r;
+  DArr<double2>& ax = H->rf_ax;
+  DArr<double2>& vt = H->rf_vt;
   r.alloc(N * nrhs);
   ax.alloc(N * nrhs);
   vt.alloc(N * nrhs);
   std::vector<double> nb(nrhs), nr(nrhs);
-  DArr<double> d_nb;
+  DArr<double>& d_nb = H->rf_nb;
   d_nb.alloc(nrhs);
   launch_col_norms(b0.p, N, N, nrhs, d_nb.p, st);
   HIPCHK(hipMemcpyAsync(nb.data(), d_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2184,7 +2555,10 @@ static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
     for (;;) {
       const int32_t k = next.fetch_add(1);
       if (k >= count) return;
-      const h2_status stt = guarded([&] { fn(k, hs[k]->own_stream); });
+      const h2_status stt = guarded([&] {
+        AllocScope scope(&hs[k]->allocator, hs[k]->own_stream);
+        fn(k, hs[k]->own_stream);
+      });
       if (stt != H2_OK) {
         std::lock_guard<std::mutex> lk(mu);
         if (first == H2_OK) {
@@ -2211,12 +2585,18 @@ static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
 
 extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
                               int32_t max_iter, void* hip_stream, h2_solve_info* info) {
-  return guarded([&] { solve_refined(H, 0, b, x, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info); });
+  return guarded([&] {
+    AllocScope scope(H ? &H->allocator : nullptr, (hipStream_t)hip_stream);
+    solve_refined(H, 0, b, x, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info);
+  });
 }
 
 extern "C" h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int32_t nrhs, int64_t ld, double tol,
                                       int32_t max_iter, void* hip_stream, h2_solve_info* info) {
-  return guarded([&] { solve_refined(H, 1, g, lam, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info); });
+  return guarded([&] {
+    AllocScope scope(H ? &H->allocator : nullptr, (hipStream_t)hip_stream);
+    solve_refined(H, 1, g, lam, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, info);
+  });
 }
 
 extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream) {
@@ -2262,8 +2642,11 @@ extern "C" h2_status h2_matvec(h2_handle H, const void* x, void* y, int32_t nrhs
     validate_vec(H, x, y, nrhs, ld);
     if (x == y) fail(H2_ERR_ARG, "x and y must not alias");
     hipStream_t st = (hipStream_t)hip_stream;
+    AllocScope scope(&H->allocator, st);
     const int64_t N = H->N;
-    DArr<double2> v, w;
+    // handle-owned, grown on demand: the product stays asynchronous
+    DArr<double2>& v = H->mv_in;
+    DArr<double2>& w = H->mv_out;
     v.alloc(N * nrhs);
     w.alloc(N * nrhs);
     if (!conj_transpose) {
@@ -2275,16 +2658,20 @@ extern "C" h2_status h2_matvec(h2_handle H, const void* x, void* y, int32_t nrhs
       matvec_tree(H, v.p, w.p, nrhs, st);
       launch_permute_out(w.p, N, H->d_perm.p, H->d_scale_mat.p, 1, N, nrhs, (double2*)y, ld, 0, st);
     }
-    check_launch("host.cpp:1723");
-    HIPCHK(hipStreamSynchronize(st));
+    check_launch("matvec");
   });
 }
 
 extern "C" void h2_destroy(h2_handle H) {
+  if (!H) return;
   try {
+    // one wait for the device, then every buffer goes back without another
+    (void)hipDeviceSynchronize();
+    t_device_idle = true;
     delete H;
   } catch (...) {
   }
+  t_device_idle = false;
 }
 
 extern "C" const char* h2_last_error(void) { return g_err.c_str(); }
@@ -2345,7 +2732,8 @@ static void compute_ledger(h2_ctx* H) {
   H->ledger.assign(10, 0.0);
   // per family: [3f + 1] flops, [3f + 2] bytes ([3f] holds the time, filled on request)
   std::vector<double>& K = H->kernel_led;
-  K.assign(26, 0.0);
+  K.assign(27, 0.0);
+  double schur_fp32 = 0.0;  // mixed form: Schur flops of clusters whose terms may run in FP32
   auto add = [&](int f, double flops, double bytes) {
     K[3 * f + 1] += flops;
     K[3 * f + 2] += bytes;
@@ -2354,6 +2742,12 @@ static void compute_ledger(h2_ctx* H) {
     const LevelPlan& P = H->plans[j];
     const FactorLevel& F = H->flev[j];
     auto dim_after = [&](int a, int c) -> double { return P.colour[a] <= c ? F.kt[a] : F.n[a]; };
+    // the panel maxima the mixed flush routes by (max|C|, max|R|, max|input block| per cluster)
+    std::vector<unsigned long long> pmax;
+    if (H->precision == H2_MIXED && F.d_pmax.p) {
+      pmax.resize(4 * (size_t)P.nc);
+      HIPCHK(hipMemcpy(pmax.data(), F.d_pmax.p, pmax.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    }
     auto flush_bytes = [&](const ColourPlan& C, int c) {
       if (!C.sc_slot.empty()) H->ledger[7] += 1.0;
       for (size_t x = 0; x < C.sc_slot.size(); ++x) {
@@ -2391,6 +2785,13 @@ static void compute_ledger(h2_ctx* H) {
         // targets (a, b) with a <= b only: the other half is their transpose
         const double schur = 8.0 * r * 0.5 * (M * M + M2);
         H->ledger[6] += schur;
+        if (!pmax.empty() && r > 0) {
+          double gc, gr, z;
+          std::memcpy(&gc, &pmax[4 * i], 8);
+          std::memcpy(&gr, &pmax[4 * i + 1], 8);
+          std::memcpy(&z, &pmax[4 * i + 2], 8);
+          if (gc * gr * std::sqrt(r) <= F32_KAPPA * z) schur_fp32 += schur;
+        }
         H->ledger[9] += 16.0 * (np + 1.0) * M * r;  // C rows and R columns of every term
         // Gram, B_perp transforms, projections (one side of every stored block of row i), LU, panels
         const double gram = 8.0 * n * n * fillcols + 8.0 * (n * n * d + n * d * d + n * d * d);
@@ -2424,6 +2825,7 @@ static void compute_ledger(h2_ctx* H) {
   double mv = (double)H->near_orig.n;
   for (const BuildLevel& B : H->build) mv += (double)B.V.n + (double)B.S.n;
   K[25] = 16.0 * mv;
+  K[26] = H->ledger[6] > 0 ? schur_fp32 / H->ledger[6] : 0.0;
   (void)S;
   H->ledger_valid = true;
 }
@@ -2450,7 +2852,7 @@ extern "C" h2_status h2_kernel_ledger(h2_handle H, double* out, int32_t n_out) {
     if (!H || !out || n_out < 26) fail(H2_ERR_ARG, "invalid argument");
     if (!H->factored) fail(H2_ERR_STATE, "h2_kernel_ledger before h2_factor");
     if (!H->ledger_valid) compute_ledger(H);
-    for (int i = 0; i < 26; ++i) out[i] = H->kernel_led[i];
+    for (int i = 0; i < std::min<int32_t>(n_out, 27); ++i) out[i] = H->kernel_led[i];
     for (int f = 0; f < 8; ++f) out[3 * f] = H->kernel_ms[f];
   });
 }

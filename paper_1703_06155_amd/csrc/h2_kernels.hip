@@ -2789,7 +2789,7 @@ __global__ void __launch_bounds__(SV_NT) k_sv_bwd_partial(LevelView v, ColourTas
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   const int chunk = blockIdx.y;
   const int ldp = c.tiles * 64;
-  double2* P = part + ((int64_t)blockIdx.x * nsplit + chunk) * ldp * 64;
+  double2* P = part + ((int64_t)blockIdx.x * nsplit + chunk) * ldp * SMALL_RHS;  // ldp x nrhs partial per chunk
   if (r <= 0) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pr = v.prow[i];
@@ -2852,14 +2852,15 @@ __global__ void __launch_bounds__(SV_NT) k_sv_bwd_local(LevelView v, ColourTasks
   const double2* Q = v.Q + v.q_off[i];
   const double2* Li = v.LU + v.lu_off[i];
   const double2* Ui = Li + (int64_t)rmax * rmax;
-  const double2* P = part + (int64_t)blockIdx.x * nsplit * ldp * 64;
+  const double2* P = part + (int64_t)blockIdx.x * nsplit * ldp * SMALL_RHS;
   for (int col = 0; col < nrhs; ++col) {
     double2* y = vec + voff[i] + (int64_t)col * ldv;
     __syncthreads();
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
       double2 val = y[e];
       if (e >= kt)
-        for (int j = 0; j < nsplit; ++j) val = csub(val, P[(int64_t)j * ldp * 64 + (e - kt) + (int64_t)col * ldp]);
+        for (int j = 0; j < nsplit; ++j)
+          val = csub(val, P[(int64_t)j * ldp * SMALL_RHS + (e - kt) + (int64_t)col * ldp]);
       xs[e] = val;
     }
     __syncthreads();

@@ -195,6 +195,7 @@ void launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, con
 void launch_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
                        int conj_trans, hipStream_t st);
 
+
 // ---- H^2 matrix-vector product ----
 void launch_near_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* boff,
                     const double2* blocks, const int64_t* cstart, const int32_t* csize, const double2* x,

@@ -1,0 +1,82 @@
+"""Early stop (Sec. III-C, closing remark): levels L..ls take Steps 0-3 and the
+matrix merged to level ls - 1, far blocks expanded through the transfer
+matrices and couplings of every coarser admissible level, is factored densely.
+
+Checked against the oracle stopped at the same level (ranks pinned), for every
+stop level of three multi-level trees, and the measured choice of the stop
+level (h2_tune_stop_level) on the 32^3 workload."""
+import numpy as np
+import pytest
+
+import paper_1703_06155_amd as h2
+from oracle import h2_oracle as O
+from paper_1703_06155_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((10, 7, 9), 12, 1e-5), ((8, 8, 8), 4, 1e-4), ((9, 5, 3), 7, 1e-3)]
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _maxrel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("grid,leaf,eps", CASES, ids=["10x7x9", "8c_leaf4", "9x5x3"])
+def test_every_stop_level_matches_oracle(grid, leaf, eps):
+    torch = _torch()
+    pr = I.make_problem("es", grid, leaf, eps, nrhs=2, rhs_seed=4)
+    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    S = H.S
+    g = np.random.default_rng(6).standard_normal((pr.n, 2)) + 0.5j
+    for ls in range(S.l0, S.L + 1):
+        print(f"early stop: grid {grid}, leaf {leaf}, stop level {ls} of [{S.l0}, {S.L}]", flush=True)
+        Fz = O.factor(H, stop_level=ls)
+        fr = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(Fz))
+        G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr, stop_level=ls)
+        try:
+            assert G.stop_level() == ls
+            G.factor()
+            st = G.stats()
+            assert st[-1][0] == ls - 1 and st[-1][2] == Fz.final_n
+            x = G.solve(torch.from_numpy(pr.rhs.copy())).cpu().numpy()
+            assert _maxrel(x, O.solve(Fz, pr.rhs)) < 1e-10
+            lam = G.solve_adjoint(torch.from_numpy(g)).cpu().numpy()
+            assert _maxrel(lam, O.solve_adjoint(Fz, g)) < 1e-10
+        finally:
+            G.close()
+
+
+def test_stop_level_switch_and_tuner_on_cube32():
+    torch = _torch()
+    pr = I.config(1)
+    b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    try:
+        l0, L = G.stop_level_range()
+        assert G.stop_level() == l0
+        G.factor()
+        x0 = G.solve(b, tol=1e-10, max_iter=20)
+        G.set_stop_level(l0 + 1)
+        with pytest.raises(h2.H2Error):
+            G.solve(b)  # unfactored after a change of stop level
+        G.factor()
+        x1, info = G.solve(b, tol=1e-10, max_iter=20, info=True)
+        assert info["rel_residual"] <= 1e-10
+        assert _maxrel(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-8
+        with pytest.raises(h2.H2Error):
+            G.set_stop_level(L + 1)
+        chosen, ms = G.tune_stop_level(max_final=12288)
+        print(f"32^3 stop level tuning: {ms}, chosen {chosen}")
+        assert l0 <= chosen <= L and chosen in ms and len(ms) >= 2
+        assert ms[chosen] == min(ms.values())
+        x2, info = G.solve(b, tol=1e-10, max_iter=20, info=True)
+        assert info["rel_residual"] <= 1e-10
+        assert _maxrel(x2.cpu().numpy(), x0.cpu().numpy()) < 1e-8
+    finally:
+        G.close()

@@ -277,7 +277,7 @@ h2_status h2_set_kernel_timing(h2_handle H, int32_t enable);
  * final LU intervals are always measured), out[3f+1] = flops,
  * out[3f+2] = bytes.  out[24] = bytes one right-hand side's forward and
  * backward sweeps must read (Q~ twice, L^-1 P, U^-1, the C and R panels, the
- * final inverse); out[25] = bytes one H^2 matvec must read (near blocks,
+ * final block's L and U factors); out[25] = bytes one H^2 matvec must read (near blocks,
  * expanded bases, couplings).  out[26] (when n_out >= 27) = the fraction of
  * the Schur flops whose cluster passed the mixed form's FP32 test (0 for
  * FP64; a flush still runs a block's FP32-safe terms in FP64 when they carry

@@ -312,9 +312,9 @@ struct h2_ctx {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
-  h2::DArr<double2> Zf, Zinv;
-  h2::DArr<double2> dl_linv, dl_uinv, dl_tmp;  // final dense LU work space (kept between factorizations)
-  h2::DArr<int32_t> dl_piv, dl_flag;
+  h2::DArr<double2> Zf;                    // final dense block, overwritten by its LU factors
+  h2::DArr<double2> dl_linv, dl_uinv;       // inverses of the final LU's 64 x 64 diagonal blocks
+  h2::DArr<int32_t> dl_piv, dl_flag, dl_perm;
   std::vector<double> timing;
   std::vector<double> ledger;              // [6] Schur flops, [7] Schur launches, [8] factor flops, [9] Schur bytes
   bool ledger_valid = false;
@@ -702,6 +702,8 @@ static int forced_k_of(h2_ctx* H, int l, int t) {
   return H->forced_k[H->lvl_base[l] + t];
 }
 
+constexpr int CONSTRUCT_PASSES = 3;  // Gram passes of the construction eigen-decomposition
+
 static void construct(h2_ctx* H, hipStream_t st) {
   const Structure& S = H->S;
   const int L = S.L, l0 = S.l0;
@@ -827,7 +829,106 @@ static void construct(h2_ctx* H, hipStream_t st) {
     d_dim.upload(dim, st);
     if (dmax > 255) fail(H2_ERR_INTERNAL, "construction Gram larger than 255 (eigensolver limit)");
     launch_jacobi(nc, d_dim.p, d_goff.p, G.p, d_uoff.p, U.p, d_loff.p, lam.p, 1, scratch.p, d_soff.p, st);
-    check_launch("host.cpp:607");
+    check_launch("construction eigensolver");
+    // Refinement passes.  The Gram W W^H of a far-field row W carries rounding of order
+    // u sigma_1^2 in every entry, which moves the eigenvectors of singular values near
+    // the truncation threshold by ~u sigma_1^2 / (sigma_k^2 - sigma_{k+1}^2) (1e-7 at
+    // eps = 1e-4 with a 5 % gap).  Rotating the rows first, B = U0^H W, and taking the
+    // Gram of B again leaves errors of order u sigma_1 (sigma_i + sigma_j) in entry
+    // (i, j): its eigenvectors U1 make U = U0 U1 accurate to ~u sigma_1 / (sigma_k -
+    // sigma_{k+1}), the accuracy of an SVD of W, and its eigenvalues the sigma_j^2.
+    // A second refinement pass removes what the first left of U0's error.
+    for (int pass = 1; pass < CONSTRUCT_PASSES; ++pass) {
+      const bool leaf = (l == L);
+      std::vector<int64_t> cstart2, ybase2(nc + 1, 0);
+      std::vector<int32_t> csize2, ck2, yld2;
+      std::vector<int64_t> yoff2;
+      const int nch = leaf ? nc : S.nclusters(l + 1);
+      int kmax2 = 0;
+      if (leaf) {
+        cstart2.assign(S.start[l].begin(), S.start[l].end());
+        csize2.resize(nc);
+        for (int t = 0; t < nc; ++t) csize2[t] = (int32_t)S.size[l][t];
+        ck2 = dim;
+        yld2 = dim;
+        kmax2 = dmax;
+      } else {
+        const BuildLevel& C = H->build[L - l - 1];
+        cstart2.assign(S.start[l + 1].begin(), S.start[l + 1].end());
+        csize2.resize(nch);
+        ck2.resize(nch);
+        yld2.resize(nch);
+        for (int c = 0; c < nch; ++c) {
+          csize2[c] = (int32_t)S.size[l + 1][c];
+          ck2[c] = C.k[c];
+          yld2[c] = dim[c / 2];
+          kmax2 = std::max(kmax2, ck2[c]);
+        }
+      }
+      int64_t rowsum = 0;
+      for (int t = 0; t < nc; ++t) rowsum += dim[t];
+      int64_t chunk = 8192;
+      while (chunk > 256 && rowsum * chunk * 16 > ((int64_t)1 << 31)) chunk /= 2;
+      chunk = std::min<int64_t>(chunk, H->N);
+      for (int t = 0; t < nc; ++t) ybase2[t + 1] = ybase2[t] + (int64_t)dim[t] * chunk;
+      if (leaf) {
+        yoff2.assign(ybase2.begin(), ybase2.end() - 1);
+      } else {
+        const BuildLevel& C = H->build[L - l - 1];
+        yoff2.resize(nch);
+        for (int c = 0; c < nch; ++c) yoff2[c] = ybase2[c / 2] + ((c & 1) ? C.k[c - 1] : 0);
+      }
+      DArr<int64_t> d_cs2, d_yoff2, d_ybase2;
+      DArr<int32_t> d_sz2, d_ck2, d_yld2;
+      d_cs2.upload(cstart2, st);
+      d_sz2.upload(csize2, st);
+      d_ck2.upload(ck2, st);
+      d_yld2.upload(yld2, st);
+      d_yoff2.upload(yoff2, st);
+      d_ybase2.upload(std::vector<int64_t>(ybase2.begin(), ybase2.end() - 1), st);
+      DArr<double2> Y, Y2;
+      Y.alloc(std::max<int64_t>(1, ybase2[nc]));
+      if (!leaf) Y2.alloc(std::max<int64_t>(1, ybase2[nc]));
+      launch_zero(G.p, gtot, st);
+      const int ktr2 = std::max(1, (kmax2 + 63) / 64);
+      for (int64_t c0 = 0; c0 < H->N; c0 += chunk) {
+        const int ncols = (int)std::min<int64_t>(chunk, H->N - c0);
+        if (leaf) {
+          // B = U0^H Z[t, far columns] straight from the kernel entries
+          launch_proj_rows(g, d_mask.p, l, nc, d_cs2.p, d_sz2.p, d_ck2.p, d_uoff.p, U.p, d_yoff2.p, d_yld2.p, Y.p,
+                           c0, ncols, ktr2, st);
+          check_launch("construction second pass");
+          launch_gram_acc(nc, d_dim.p, d_ybase2.p, Y.p, ncols, d_goff.p, G.p, ntr, st);
+        } else {
+          const BuildLevel& C = H->build[L - l - 1];
+          launch_proj_rows(g, d_mask.p, l, nch, d_cs2.p, d_sz2.p, d_ck2.p, C.d_voff.p, C.V.p, d_yoff2.p, d_yld2.p,
+                           Y.p, c0, ncols, ktr2, st);
+          check_launch("construction second pass");
+          std::vector<GemmTask> rot;
+          for (int t = 0; t < nc; ++t) {
+            if (dim[t] == 0) continue;
+            rot.push_back({U.p + uoff[t], Y.p + ybase2[t], Y2.p + ybase2[t], dim[t], dim[t], dim[t], dim[t], ncols,
+                           dim[t], OP_C, OP_N, ST_SET});
+          }
+          run_gemms(H, rot, st);
+          launch_gram_acc(nc, d_dim.p, d_ybase2.p, Y2.p, ncols, d_goff.p, G.p, ntr, st);
+        }
+        check_launch("construction second pass");
+      }
+      DArr<double2> U1;
+      U1.alloc(gtot);
+      launch_jacobi(nc, d_dim.p, d_goff.p, G.p, d_uoff.p, U1.p, d_loff.p, lam.p, 1, scratch.p, d_soff.p, st);
+      check_launch("construction eigensolver, second pass");
+      // U = U0 U1 (written over the consumed Gram, then moved into U)
+      std::vector<GemmTask> prod;
+      for (int t = 0; t < nc; ++t) {
+        if (dim[t] == 0) continue;
+        prod.push_back({U.p + uoff[t], U1.p + uoff[t], G.p + uoff[t], dim[t], dim[t], dim[t], dim[t], dim[t], dim[t],
+                        OP_N, OP_N, ST_SET});
+      }
+      run_gemms(H, prod, st);
+      if (gtot > 0) HIPCHK(hipMemcpyAsync(U.p, G.p, gtot * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    }
     std::vector<double> hl(std::max<int64_t>(1, lt));
     HIPCHK(hipMemcpyAsync(hl.data(), lam.p, hl.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1051,7 +1152,7 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-static void dense_lu_inverse(h2_ctx* H, hipStream_t st);
+static void dense_lu_factor(h2_ctx* H, hipStream_t st);
 
 constexpr size_t SCHUR_PART_MAX_BYTES = size_t(8) << 30;
 
@@ -1068,10 +1169,8 @@ static void release_factor_buffers(h2_ctx* H) {
   H->ws_scp.release();
   H->ws_merge.release();
   H->Zf.release();
-  H->Zinv.release();
   H->dl_linv.release();
   H->dl_uinv.release();
-  H->dl_tmp.release();
   H->dl_piv.release();
   H->dl_flag.release();
   H->vbuf.clear();
@@ -1236,12 +1335,17 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->factored = false;
   // buffers of the previous factorization are reused; nothing of it may still run
   HIPCHK(hipStreamSynchronize(st));
-  {
-    // when device memory is short, start from nothing rather than from the
-    // previous factorization's buffers (its factors would sit beside the new arenas)
+  // With the library's own hipMalloc: when device memory is short, start from nothing
+  // rather than from the previous factorization's buffers (its factors would sit beside
+  // the new arenas).  A caller's allocator keeps what the library frees in its own cache
+  // (so the device's free memory says nothing about it) and frees that cache itself when
+  // an allocation fails: the handle keeps its buffers.
+  const bool own_memory = !(H->allocator.alloc && H->allocator.free);
+  auto memory_short = [&]() {
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot) release_factor_buffers(H);
-  }
+    return own_memory && hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot;
+  };
+  if (memory_short()) release_factor_buffers(H);
   H->vbuf_nrhs = 0;  // level sizes may change with the ranks: resize the sweep buffers
   H->drop_graphs();
   H->timing.assign(6, 0.0);
@@ -1269,7 +1373,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
                               S.size[L][a] * sizeof(double2), S.size[L][b], hipMemcpyDeviceToDevice, st));
     }
     hipEvent_t t_m = ev.next(st);
-    dense_lu_inverse(H, st);
+    dense_lu_factor(H, st);
     hipEvent_t t_end = ev.next(st);
     HIPCHK(hipStreamSynchronize(st));
     H->timing[0] = elapsed(t_begin, t_end);
@@ -1646,6 +1750,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       dst_total = pslot_off[Pp.nslot];
       for (size_t e = 0; e < P.merge.size(); ++e) {
         const MergeSrc& m = P.merge[e];
+        if (m.pslot < 0 || m.pslot >= Pp.nslot) fail(H2_ERR_INTERNAL, "merge plan does not match the stop level");
         const int pa = Pp.slot_a[m.pslot], pb = Pp.slot_b[m.pslot];
         const int64_t ld = n_par[pa];
         const int64_t ro = m.ci ? off1[pa] : 0, co = m.dj ? off1[pb] : 0;
@@ -1669,6 +1774,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       dst_total = H->nf * H->nf;
       for (size_t e = 0; e < P.merge.size(); ++e) {
         const MergeSrc& m = P.merge[e];
+        if (m.pslot < 0 || m.pslot >= npar * npar) fail(H2_ERR_INTERNAL, "merge plan does not match the stop level");
         const int pa = m.pslot / npar, pb = m.pslot % npar;
         const int64_t ro = H->final_off[pa] + (m.ci ? off1[pa] : 0);
         const int64_t co = H->final_off[pb] + (m.dj ? off1[pb] : 0);
@@ -1727,13 +1833,10 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     n_cur = n_par;
     // keep this level's block arena for the next factorization unless memory is
     // short (the level two steps up reuses it; keeping it costs its full size)
-    {
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot) slots.release();
-    }
+    if (memory_short()) slots.release();
   }
   hipEvent_t e_f0 = ev.next(st);
-  dense_lu_inverse(H, st);
+  dense_lu_factor(H, st);
   hipEvent_t t_end = ev.next(st);
   HIPCHK(hipStreamSynchronize(st));
   H->stats_rows.push_back({ls - 1, (int64_t)S.nclusters(ls - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
@@ -1756,10 +1859,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
   H->factored = true;
 }
 
-// Z_f^-1 by blocked LU with partial pivoting followed by blocked substitution on the identity.
-static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
+// P Z_f = L U by blocked LU with partial pivoting (64-column panels, GEMM
+// trailing updates), in place; the inverses of the 64 x 64 diagonal blocks of L
+// and U are kept for the blocked triangular solves of the sweeps, and the row
+// interchanges become one gather permutation.
+static void dense_lu_factor(h2_ctx* H, hipStream_t st) {
   const int64_t n = H->nf;
-  H->Zinv.alloc(std::max<int64_t>(1, n * n));
   if (n == 0) return;
   double2* A = H->Zf.p;
   DArr<int32_t>& piv = H->dl_piv;
@@ -1775,7 +1880,7 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0), rest = n - j0 - w;
     launch_dense_panel(A, n, j0, piv.p, linv.p + b * 4096, flag.p, st);
-    check_launch("host.cpp:1223");
+    check_launch("dense panel");
     if (rest > 0) {
       // U12 = L11^-1 A12 (in place: one tile row owns all 64 rows of its columns)
       std::vector<GemmTask> t1{{linv.p + b * 4096, A + j0 + (j0 + w) * n, A + j0 + (j0 + w) * n, 64, n, n, (int32_t)w,
@@ -1795,40 +1900,47 @@ static void dense_lu_inverse(h2_ctx* H, hipStream_t st) {
     const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0);
     launch_tri_inv_upper(A + j0 + j0 * n, n, (int)w, uinv.p + b * 4096, st);
   }
-  check_launch("host.cpp:1243");
-  // X = P, then X <- L^-1 X, X <- U^-1 X (block rows)
-  double2* X = H->Zinv.p;
-  launch_zero(X, n * n, st);
-  launch_apply_perm_cols(X, n, piv.p, st);
-  check_launch("host.cpp:1248");
-  DArr<double2>& tmp = H->dl_tmp;
-  tmp.alloc(64 * n);
-  for (int64_t b = 0; b < nb; ++b) {
-    const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0);
-    std::vector<GemmTask> t;
-    if (j0 > 0)
-      t.push_back({A + j0, X, X + j0, n, n, n, (int32_t)w, (int32_t)n, (int32_t)j0, OP_N, OP_N, ST_SUB});
-    run_gemms(H, t, st);
-    std::vector<GemmTask> t2{{linv.p + b * 4096, X + j0, tmp.p, 64, n, 64, (int32_t)w, (int32_t)n, (int32_t)w, OP_N,
-                              OP_N, ST_SET}};
-    run_gemms(H, t2, st);
-    HIPCHK(hipMemcpy2DAsync(X + j0, n * sizeof(double2), tmp.p, 64 * sizeof(double2), w * sizeof(double2), n,
-                            hipMemcpyDeviceToDevice, st));
-  }
-  for (int64_t b = nb - 1; b >= 0; --b) {
-    const int64_t j0 = b * 64, w = std::min<int64_t>(64, n - j0), rest = n - j0 - w;
-    std::vector<GemmTask> t;
-    if (rest > 0)
-      t.push_back({A + j0 + (j0 + w) * n, X + j0 + w, X + j0, n, n, n, (int32_t)w, (int32_t)n, (int32_t)rest, OP_N,
-                   OP_N, ST_SUB});
-    run_gemms(H, t, st);
-    std::vector<GemmTask> t2{{uinv.p + b * 4096, X + j0, tmp.p, 64, n, 64, (int32_t)w, (int32_t)n, (int32_t)w, OP_N,
-                              OP_N, ST_SET}};
-    run_gemms(H, t2, st);
-    HIPCHK(hipMemcpy2DAsync(X + j0, n * sizeof(double2), tmp.p, 64 * sizeof(double2), w * sizeof(double2), n,
-                            hipMemcpyDeviceToDevice, st));
-  }
+  check_launch("diagonal block inverses");
+  // the row interchanges applied in order, as one gather: (P v)[i] = v[perm[i]]
+  std::vector<int32_t> pv(n), perm(n);
+  HIPCHK(hipMemcpyAsync(pv.data(), piv.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+  for (int64_t j = 0; j < n; ++j) {
+    if (pv[j] < j || pv[j] >= n) fail(H2_ERR_INTERNAL, "final LU pivot out of range");
+    std::swap(perm[j], perm[pv[j]]);
+  }
+  H->dl_perm.upload(perm, st);
+}
+
+// y = Z_f^-1 x (adj = 0) or Z_f^-H x (adj = 1) with the final block's LU factors:
+// gather, L forward, U backward (or U^H forward, L^H backward, scatter).  x is
+// used as work space and overwritten; the result goes to y.  No host synchronisation.
+static void dense_lu_apply(h2_ctx* H, double2* x, double2* y, int nrhs, int adj, hipStream_t st) {
+  const int64_t n = H->nf;
+  if (n == 0) return;
+  const double2* A = H->Zf.p;
+  const int64_t nb = (n + 63) / 64;
+  const double2* linv = H->dl_linv.p;
+  const double2* uinv = H->dl_uinv.p;
+  if (!adj) {
+    launch_dense_perm(x, y, H->dl_perm.p, n, nrhs, n, 0, st);  // y = P x
+    for (int64_t b = 0; b < nb; ++b)                            // x = L^-1 y
+      launch_dense_trsv_step(A, n, b * 64, (int)std::min<int64_t>(64, n - b * 64), linv + b * 4096, y, x, n, nrhs,
+                             0, st);
+    for (int64_t b = nb - 1; b >= 0; --b)                       // y = U^-1 x
+      launch_dense_trsv_step(A, n, b * 64, (int)std::min<int64_t>(64, n - b * 64), uinv + b * 4096, x, y, n, nrhs,
+                             1, st);
+  } else {
+    for (int64_t b = 0; b < nb; ++b)                            // y = U^-H x
+      launch_dense_trsv_step(A, n, b * 64, (int)std::min<int64_t>(64, n - b * 64), uinv + b * 4096, x, y, n, nrhs,
+                             2, st);
+    for (int64_t b = nb - 1; b >= 0; --b)                       // x = L^-H y
+      launch_dense_trsv_step(A, n, b * 64, (int)std::min<int64_t>(64, n - b * 64), linv + b * 4096, y, x, n, nrhs,
+                             3, st);
+    launch_dense_perm(x, y, H->dl_perm.p, n, nrhs, n, 1, st);  // y = P^T x
+  }
+  check_launch("final block solve");
 }
 
 // ---------------------------------------------------------------------------
@@ -1926,7 +2038,8 @@ static void sweep(h2_ctx* H, const SweepBufs& W, const double2* in, double2* out
   const Structure& S = H->S;
   const int64_t N = H->N;
   if (H->flev.empty()) {
-    launch_dense_apply(H->Zinv.p, N, in, W.vtmp2, N, nrhs, adj, st);
+    HIPCHK(hipMemcpyAsync(W.vtmp, in, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    dense_lu_apply(H, W.vtmp, W.vtmp2, nrhs, adj, st);
     HIPCHK(hipMemcpyAsync(out, W.vtmp2, N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
     check_launch("host.cpp:1314");
     return;
@@ -1949,7 +2062,7 @@ static void sweep(h2_ctx* H, const SweepBufs& W, const double2* in, double2* out
     } else {
       launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, W.vbuf[j], W.vtmp, 1,
                     P.d_nonempty.p, st);
-      launch_dense_apply(H->Zinv.p, H->nf, W.vtmp, W.vtmp2, H->nf, nrhs, adj, st);
+      dense_lu_apply(H, W.vtmp, W.vtmp2, nrhs, adj, st);
       launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, W.vbuf[j], W.vtmp2, 0,
                     P.d_nonempty.p, st);
       check_launch("final block");
@@ -2343,10 +2456,12 @@ extern "C" h2_status h2_set_stop_level(h2_handle H, int32_t level) {
 static void set_stop(h2_ctx* H, int stop) {
   const Structure& S = H->S;
   if (stop == H->stop) return;
-  const int old = H->stop;
   H->stop = stop;
   H->factored = false;
-  for (int l : {old, stop}) build_merge(H, H->plans[S.L - l], l > stop ? &H->plans[S.L - l + 1] : nullptr);
+  // every level above the stop merges into its parent level's blocks, the stop level into
+  // the final dense block (levels below it are not factored)
+  for (int l = S.l0; l <= S.L; ++l)
+    build_merge(H, H->plans[S.L - l], l > stop ? &H->plans[S.L - l + 1] : nullptr);
 }
 
 extern "C" h2_status h2_tune_stop_level(h2_handle H, int64_t max_final, void* hip_stream, int32_t* chosen,
@@ -2816,11 +2931,11 @@ static void compute_ledger(h2_ctx* H) {
     flush_bytes(P.fin, P.ncol - 1);
   }
   const double nf = (double)H->nf;
-  H->ledger[8] += 8.0 / 3.0 * nf * nf * nf + 8.0 * nf * nf * nf;
+  H->ledger[8] += 8.0 / 3.0 * nf * nf * nf;
   add(5, H->ledger[6], H->ledger[9]);
   add(6, 0.0, 32.0 * H->merge_elems);  // every parent element written once, its source read once
-  add(7, 8.0 / 3.0 * nf * nf * nf + 8.0 * nf * nf * nf, 32.0 * nf * nf);
-  K[24] += 16.0 * nf * nf;  // the final inverse
+  add(7, 8.0 / 3.0 * nf * nf * nf, 32.0 * nf * nf);
+  K[24] += 16.0 * nf * nf;  // the final block's L and U factors
   // matvec: near blocks, the expanded bases of every level and the couplings, once each
   double mv = (double)H->near_orig.n;
   for (const BuildLevel& B : H->build) mv += (double)B.V.n + (double)B.S.n;

@@ -7,6 +7,9 @@
 // rows [0, k~) and the r = n - k~ eliminated ones rows [k~, n).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "h2_device.hpp"
 #include "h2_kernels.hpp"
 
@@ -2325,63 +2328,109 @@ void launch_parent_basis(int np, const int32_t* pn, const int32_t* pk, const int
 // ===========================================================================
 // Dense final LU (blocked right-looking, panel width 64)
 // ===========================================================================
+// Panel of the final dense LU: columns [j0, j0 + w) over rows [j0, n), partial
+// pivoting (largest |re| + |im|, lowest row on ties, as zgetrf).  Row interchanges
+// are applied to the panel's own columns only (k_dense_laswp applies them to the
+// others).  Columns are taken in groups of eight: within a group each column's
+// pivot search, scaling and rank-1 update touch only the group's columns; the
+// group then updates the rest of the panel by one rank-8 pass over the rows, so
+// the panel is streamed about w / 8 times instead of w times.
+constexpr int DP_GROUP = 8;
+
 __global__ void __launch_bounds__(1024) k_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv,
                                                       double2* linv, int32_t* flag) {
   __shared__ double rv[16];
   __shared__ int ri[16];
+  __shared__ double2 sU[DP_GROUP * 64];  // the group's rows of the later panel columns (U part)
   __shared__ double2 sD[64 * 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int w = (int)imin64(64, n - j0);
-  for (int jj = 0; jj < w; ++jj) {
-    const int64_t j = j0 + jj;
-    // pivot: largest |re| + |im| in column j from row j on, lowest row on ties
-    double best = -1.0;
-    int bi = 0x7fffffff;
-    for (int64_t a = j + tid; a < n; a += blockDim.x) {
-      const double2 x = A[a + j * n];
-      const double val = fabs(x.x) + fabs(x.y);
-      if (val > best) {
-        best = val;
-        bi = (int)a;
+  for (int g0 = 0; g0 < w; g0 += DP_GROUP) {
+    const int ge = min(w, g0 + DP_GROUP);
+    for (int jj = g0; jj < ge; ++jj) {
+      const int64_t j = j0 + jj;
+      // pivot: largest |re| + |im| in column j from row j on, lowest row on ties
+      double best = -1.0;
+      int bi = 0x7fffffff;
+      for (int64_t a = j + tid; a < n; a += blockDim.x) {
+        const double2 x = A[a + j * n];
+        const double val = fabs(x.x) + fabs(x.y);
+        if (val > best) {
+          best = val;
+          bi = (int)a;
+        }
+      }
+      const double wm = wave_max_nonneg(fmax(best, 0.0));
+      const int wi = wave_min_int(best == wm ? bi : 0x7fffffff);
+      if (lane == 0) {
+        rv[wv] = wm;
+        ri[wv] = wi;
+      }
+      __syncthreads();
+      double pv = rv[0];
+      int pj = ri[0];
+      for (int u = 1; u < 16; ++u)
+        if (rv[u] > pv || (rv[u] == pv && ri[u] < pj)) {
+          pv = rv[u];
+          pj = ri[u];
+        }
+      __syncthreads();
+      if (!(pv > 0.0) || pj >= n) {
+        if (tid == 0) *flag = 1;
+        return;
+      }
+      if (tid == 0) piv[j] = pj;
+      // interchange rows j and pj within the panel's columns
+      if (pj != j && tid < w) {
+        const int64_t cb = (j0 + tid) * n;
+        const double2 t = A[j + cb];
+        A[j + cb] = A[pj + cb];
+        A[pj + cb] = t;
+      }
+      __syncthreads();
+      const double2 p = A[j + j * n];
+      const double pd = cabs2(p);
+      const double2 pinv = make_double2(p.x / pd, -p.y / pd);
+      for (int64_t a = j + 1 + tid; a < n; a += blockDim.x) A[a + j * n] = cmul(A[a + j * n], pinv);
+      __syncthreads();
+      // rank-1 update of the group's later columns: a column per wavefront, rows on lanes
+      for (int b = jj + 1 + wv; b < ge; b += 16) {
+        const int64_t cb = (j0 + b) * n;
+        const double2 ub = A[j + cb];
+        for (int64_t a = j + 1 + lane; a < n; a += 64) A[a + cb] = csub(A[a + cb], cmul(A[a + j * n], ub));
+      }
+      __syncthreads();
+    }
+    if (ge >= w) break;
+    // U rows of the group for the later panel columns: U_g = L_gg^-1 A[group rows, later columns]
+    const int ng = ge - g0, nl = w - ge;
+    for (int b = tid; b < nl; b += blockDim.x) {
+      const int64_t cb = (j0 + ge + b) * n;
+      double2 u[DP_GROUP];
+#pragma unroll
+      for (int k = 0; k < DP_GROUP; ++k) {
+        if (k >= ng) break;
+        double2 v = A[j0 + g0 + k + cb];
+        for (int q = 0; q < k; ++q) v = csub(v, cmul(A[j0 + g0 + k + (j0 + g0 + q) * n], u[q]));
+        u[k] = v;
+        A[j0 + g0 + k + cb] = v;
+        sU[k + DP_GROUP * b] = v;
       }
     }
-    const double wm = wave_max_nonneg(fmax(best, 0.0));
-    const int wi = wave_min_int(best == wm ? bi : 0x7fffffff);
-    if (lane == 0) {
-      rv[wv] = wm;
-      ri[wv] = wi;
-    }
     __syncthreads();
-    double pv = rv[0];
-    int pj = ri[0];
-    for (int u = 1; u < 16; ++u)
-      if (rv[u] > pv || (rv[u] == pv && ri[u] < pj)) {
-        pv = rv[u];
-        pj = ri[u];
+    // rank-ng update of the later panel columns below the group: a row per thread
+    for (int64_t a = j0 + ge + tid; a < n; a += blockDim.x) {
+      double2 l[DP_GROUP];
+#pragma unroll
+      for (int k = 0; k < DP_GROUP; ++k) l[k] = k < ng ? A[a + (j0 + g0 + k) * n] : make_double2(0, 0);
+      for (int b = 0; b < nl; ++b) {
+        double2* p = A + a + (j0 + ge + b) * n;
+        double2 v = *p;
+#pragma unroll
+        for (int k = 0; k < DP_GROUP; ++k)
+          if (k < ng) v = csub(v, cmul(l[k], sU[k + DP_GROUP * b]));
+        *p = v;
       }
-    __syncthreads();
-    if (!(pv > 0.0) || pj >= n) {
-      if (tid == 0) *flag = 1;
-      return;
-    }
-    if (tid == 0) piv[j] = pj;
-    if (pj != j)
-      for (int64_t b = tid; b < n; b += blockDim.x) {
-        const double2 t = A[j + b * n];
-        A[j + b * n] = A[pj + b * n];
-        A[pj + b * n] = t;
-      }
-    __syncthreads();
-    const double2 p = A[j + j * n];
-    const double pd = cabs2(p);
-    const double2 pinv = make_double2(p.x / pd, -p.y / pd);
-    for (int64_t a = j + 1 + tid; a < n; a += blockDim.x) A[a + j * n] = cmul(A[a + j * n], pinv);
-    __syncthreads();
-    // update the remaining columns of the panel: a column per wavefront, rows on lanes
-    for (int b = jj + 1 + wv; b < w; b += 16) {
-      const int64_t cb = (j0 + b) * n;
-      const double2 ub = A[j + cb];
-      for (int64_t a = j + 1 + lane; a < n; a += 64) A[a + cb] = csub(A[a + cb], cmul(A[a + j * n], ub));
     }
     __syncthreads();
   }
@@ -2400,9 +2449,31 @@ __global__ void __launch_bounds__(1024) k_dense_panel(double2* A, int64_t n, int
   }
 }
 
+// The panel's row interchanges (rows j <-> piv[j], j = j0 .. j0 + w - 1, in order)
+// applied to every column outside the panel: a thread per column.
+__global__ void k_dense_laswp(double2* A, int64_t n, int64_t j0, int w, const int32_t* piv) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= n - w) return;
+  if (c >= j0) c += w;  // skip the panel's columns
+  double2* col = A + c * n;
+  for (int jj = 0; jj < w; ++jj) {
+    const int64_t j = j0 + jj, pj = piv[j];
+    // a panel that met a zero pivot stops early and leaves later entries unset
+    // (the factorization then fails): only in-range interchanges are applied
+    if (pj > j && pj < n) {
+      const double2 t = col[j];
+      col[j] = col[pj];
+      col[pj] = t;
+    }
+  }
+}
+
 void launch_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv, double2* linv, int32_t* flag,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_dense_panel, dim3(1), dim3(1024), 0, st, A, n, j0, piv, linv, flag);
+  const int w = (int)std::min<int64_t>(64, n - j0);
+  if (n - w > 0)
+    hipLaunchKernelGGL(k_dense_laswp, dim3((unsigned)((n - w + 255) / 256)), dim3(256), 0, st, A, n, j0, w, piv);
 }
 
 // inverse of the upper-triangular 64 x 64 (or smaller) diagonal block at A (ld n) -> Uinv
@@ -2453,6 +2524,119 @@ __global__ void k_perm_matrix(double2* X, int64_t n, const int32_t* piv) {
 void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream_t st) {
   int blocks = (int)imin64(1024, (n + 255) / 256);
   hipLaunchKernelGGL(k_perm_matrix, dim3(blocks), dim3(256), 0, st, X, n, piv);
+}
+
+// ---------------------------------------------------------------------------
+// Solves with the final block's LU factors (P Z_f = L U, L unit lower and U upper
+// stored in place, 64 x 64 inverses of their diagonal blocks kept).
+// ---------------------------------------------------------------------------
+// out[i] = in[perm[i]] (scatter = 0) or out[perm[i]] = in[i] (scatter = 1), nrhs columns
+__global__ void k_dense_perm(const double2* in, double2* out, const int32_t* perm, int64_t n, int nrhs, int64_t ld,
+                             int scatter) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t q = perm[i];
+  for (int c = 0; c < nrhs; ++c) {
+    if (scatter)
+      out[q + c * ld] = in[i + c * ld];
+    else
+      out[i + c * ld] = in[q + c * ld];
+  }
+}
+
+constexpr int TRSV_RHS = 16;  // right-hand sides per LDS pass
+
+// One block step of a right-looking triangular solve on the 64-row block at j0
+// (w rows).  Every workgroup forms t = D x_b for the block (D = its diagonal
+// block's inverse, or that inverse's conjugate transpose), workgroup 0 stores t
+// in y_b, and each workgroup subtracts the block's coupling times t from its
+// share of the rows still to be solved (in x, in place; x_b itself is only read):
+//   mode 0  L y = x, forward:  x[r] -= L[r, b] t for r >= j0 + w
+//   mode 1  U y = x, backward: x[r] -= U[r, b] t for r < j0
+//   mode 2  U^H y = x, forward:  x[r] -= U[b, r]^H t for r >= j0 + w
+//   mode 3  L^H y = x, backward: x[r] -= L[b, r]^H t for r < j0
+// Modes 0/1 read columns of the factor (a thread per row, coalesced); modes 2/3
+// read rows of it (a wavefront per row, 64 consecutive entries, DPP sums).
+__global__ void __launch_bounds__(256) k_dense_trsv_step(const double2* A, int64_t n, int64_t j0, int w,
+                                                         const double2* D, double2* x, double2* y, int64_t ld,
+                                                         int nrhs, int mode) {
+  __shared__ double2 t[64 * TRSV_RHS];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool fwd = (mode == 0 || mode == 2);
+  const int64_t r0 = fwd ? j0 + w : 0, r1 = fwd ? n : j0;
+  const bool rowwise = (mode >= 2);
+  const int64_t rows_per_wg = rowwise ? 16 : 256;
+  const int64_t rbeg = r0 + blockIdx.x * rows_per_wg;
+  for (int c0 = 0; c0 < nrhs; c0 += TRSV_RHS) {
+    const int nc = min(TRSV_RHS, nrhs - c0);
+    __syncthreads();
+    // t = D x_b (mode 0/1) or D^H x_b (mode 2/3) for nc columns: thread (row i, column group)
+    for (int e = tid; e < 64 * nc; e += blockDim.x) {
+      const int i = e & 63, c = e >> 6;
+      double2 acc = make_double2(0, 0);
+      if (i < w) {
+        const double2* xb = x + j0 + (c0 + c) * ld;
+        if (!rowwise)
+          for (int k = 0; k < w; ++k) acc = cadd(acc, cmul(D[i + 64 * k], xb[k]));
+        else
+          for (int k = 0; k < w; ++k) acc = cadd(acc, cmulc(D[k + 64 * i], xb[k]));
+      }
+      t[i + 64 * c] = acc;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+      for (int e = tid; e < 64 * nc; e += blockDim.x)
+        if ((e & 63) < w) y[j0 + (e & 63) + (c0 + (e >> 6)) * ld] = t[e];
+    if (!rowwise) {
+      const int64_t r = rbeg + tid;
+      if (r < r1 && r < rbeg + rows_per_wg) {
+        double2 acc[TRSV_RHS];
+#pragma unroll
+        for (int c = 0; c < TRSV_RHS; ++c) acc[c] = make_double2(0, 0);
+        for (int k = 0; k < w; ++k) {
+          const double2 a = A[r + (j0 + k) * n];
+#pragma unroll
+          for (int c = 0; c < TRSV_RHS; ++c)
+            if (c < nc) acc[c] = cadd(acc[c], cmul(a, t[k + 64 * c]));
+        }
+        for (int c = 0; c < nc; ++c) {
+          double2* p = x + r + (c0 + c) * ld;
+          *p = csub(*p, acc[c]);
+        }
+      }
+    } else {
+      // four wavefronts, four rows each; lane k holds conj(A[j0 + k, r])
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = rbeg + wv * 4 + q;
+        if (r >= r1) break;  // uniform per wavefront
+        const double2 a = lane < w ? cconj(A[j0 + lane + r * n]) : make_double2(0, 0);
+        for (int c = 0; c < nc; ++c) {
+          const double2 pr = cmul(a, t[lane + 64 * c]);
+          const double sr = wave_sum(pr.x), si = wave_sum(pr.y);
+          if (lane == 0) {
+            double2* p = x + r + (c0 + c) * ld;
+            *p = make_double2(p->x - sr, p->y - si);
+          }
+        }
+      }
+    }
+  }
+}
+
+void launch_dense_perm(const double2* in, double2* out, const int32_t* perm, int64_t n, int nrhs, int64_t ld,
+                       int scatter, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_dense_perm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, perm, n, nrhs, ld,
+                     scatter);
+}
+
+void launch_dense_trsv_step(const double2* A, int64_t n, int64_t j0, int w, const double2* D, double2* x,
+                            double2* y, int64_t ld, int nrhs, int mode, hipStream_t st) {
+  const bool fwd = (mode == 0 || mode == 2);
+  const int64_t rows = fwd ? n - j0 - w : j0;
+  const int64_t per = (mode >= 2) ? 16 : 256;
+  const int64_t nwg = std::max<int64_t>(1, (rows + per - 1) / per);
+  hipLaunchKernelGGL(k_dense_trsv_step, dim3((unsigned)nwg), dim3(256), 0, st, A, n, j0, w, D, x, y, ld, nrhs, mode);
 }
 
 // ===========================================================================

@@ -173,6 +173,15 @@ void launch_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv, double2
                         hipStream_t st);
 void launch_tri_inv_upper(const double2* A, int64_t n, int w, double2* Uinv, hipStream_t st);
 void launch_apply_perm_cols(double2* X, int64_t n, const int32_t* piv, hipStream_t st);
+// Solves with the final block's LU factors: row gather / scatter by a permutation
+// (nrhs columns, leading dimension ld) and one 64-row block step of a
+// right-looking triangular solve (mode 0: L forward, 1: U backward, 2: U^H
+// forward, 3: L^H backward; D = the inverse of the block's diagonal block; the
+// block's result goes to y, the other rows of x are updated in place).
+void launch_dense_perm(const double2* in, double2* out, const int32_t* perm, int64_t n, int nrhs, int64_t ld,
+                       int scatter, hipStream_t st);
+void launch_dense_trsv_step(const double2* A, int64_t n, int64_t j0, int w, const double2* D, double2* x,
+                            double2* y, int64_t ld, int nrhs, int mode, hipStream_t st);
 
 // ---- sweeps (nrhs columns; per-level vectors with leading dimension ldv) ----
 constexpr int BWD_SPLIT = 8;   // partial sums of the backward gather (many right-hand sides)

@@ -63,8 +63,9 @@ def test_cube32_pinned_ranks_elementwise_against_oracle():
         el = _maxrel(lam, d["lam"])
         xr = G.solve(b, tol=1e-12, max_iter=20).cpu().numpy()
         er = _maxrel(xr, d["x_refined"])
-        print(f"32^3 vs oracle, ranks pinned: x {ex:.2e}, lam {el:.2e}, refined x {er:.2e}")
-        assert ex < 1e-10 and el < 1e-10
+        nx = float(np.linalg.norm(x - d["x"]) / np.linalg.norm(d["x"]))
+        print(f"32^3 vs oracle, ranks pinned: x {ex:.2e} (norm-wise {nx:.2e}), lam {el:.2e}, refined x {er:.2e}")
+        assert ex < 1e-10 and el < 1e-10 and nx < 1e-10
         assert er < 1e-8
     finally:
         G.close()

@@ -168,6 +168,21 @@ h2_status h2_factor(h2_handle H, void* hip_stream);
 h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
                    int32_t max_iter, void* hip_stream, h2_solve_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): x = M^-1 b
+ * exactly as h2_solve with tol = 0 computes it (the same kernels, identical
+ * results), with every work buffer of the sweeps - the per-level vectors, the
+ * final-block vectors and the backward gather's partial sums - carved from a
+ * fixed 64 MiB device array that the library holds on each device it runs on
+ * until the process ends.  The call allocates nothing (no hipMalloc, no
+ * allocator callback); H must be factored.  Sizes whose work space exceeds
+ * 64 MiB (e.g. more than one right-hand side at N = 262144) are rejected with
+ * H2_ERR_ARG before any device work.  All calls on one device share that
+ * array and keep its last contents: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.  b and x
+ * are device pointers (ld >= n) and may alias.  Asynchronous. */
+h2_status h2_solve_noalloc(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, void* hip_stream);
+
 /* lam = M^-H g: the conjugate transposes of the sweeps of eq. 35 applied in
  * reverse order over the same factors (the exact adjoint of the computed
  * solve).  With tol > 0 the result is refined against A_H2^H = D conj(Z_H2)

@@ -86,6 +86,7 @@ def lib():
         L.h2_factor.argtypes = [_P, _P]
         L.h2_solve.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P,
                                ctypes.POINTER(SolveInfo)]
+        L.h2_solve_noalloc.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, _P]
         L.h2_solve_adjoint.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P,
                                        ctypes.POINTER(SolveInfo)]
         L.h2_contrast_gradient.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64, _P, _P]
@@ -116,7 +117,7 @@ def lib():
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
                      "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing",
-                     "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level"):
+                     "h2_solve_noalloc", "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -289,6 +290,15 @@ class H2:
             return x, {"iterations": si.iterations, "rel_residual": si.rel_residual,
                        "rel_residual_first": si.rel_residual_first}
         return x
+
+    def solve_noalloc(self, b, stream=None):
+        """x = M^-1 b through h2_solve_noalloc (the library allocates no device memory;
+        its work space is a fixed 64 MiB array per device)."""
+        buf, nrhs, vec = _as_cols(b, self.n)
+        out = _torch().empty_like(buf)
+        _check(lib().h2_solve_noalloc(self._h, ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      nrhs, self.n, _stream_ptr(stream)), "h2_solve_noalloc")
+        return _from_cols(out, vec)
 
     def solve_adjoint(self, g, tol=0.0, max_iter=20, stream=None, info=False):
         buf, nrhs, vec = _as_cols(g, self.n)

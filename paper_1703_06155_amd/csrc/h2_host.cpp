@@ -2715,6 +2715,46 @@ extern "C" h2_status h2_solve_adjoint(h2_handle H, const void* g, void* lam, int
   });
 }
 
+extern "C" h2_status h2_solve_noalloc(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld,
+                                     void* hip_stream) {
+  return guarded([&] {
+    validate_vec(H, b, x, nrhs, ld);
+    if (!H->factored) fail(H2_ERR_STATE, "solve before a successful h2_factor");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t N = H->N;
+    // the sweep's work buffers, each 256-byte aligned, carved from the fixed scratch
+    const SweepLayout L = sweep_layout(H, nrhs);
+    auto up = [](int64_t e) { return (e + 15) & ~int64_t(15); };
+    int64_t need = up(L.vtmp) * 2 + up(L.vtmp3) + up(L.scratch) + up(L.part);
+    for (int64_t v : L.vbuf) need += up(v);
+    if (need > NOALLOC_SCRATCH_ELEMS)
+      fail(H2_ERR_ARG, "h2_solve_noalloc: " + std::to_string(nrhs) + " right-hand sides of this problem need " +
+                           std::to_string((need * 16) >> 20) + " MiB of work space, beyond its fixed " +
+                           std::to_string((NOALLOC_SCRATCH_ELEMS * 16) >> 20) + " MiB");
+    hipError_t e = hipSuccess;
+    double2* base = noalloc_scratch(&e);
+    if (!base) fail(H2_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    SweepBufs W;
+    int64_t off = 0;
+    auto take = [&](int64_t elems) {
+      double2* p = base + off;
+      off += up(elems);
+      return p;
+    };
+    for (int64_t v : L.vbuf) W.vbuf.push_back(take(v));
+    W.vtmp = take(L.vtmp);
+    W.vtmp2 = take(L.vtmp);
+    W.vtmp3 = take(L.vtmp3);
+    W.scratch = take(L.scratch);
+    W.part = take(L.part);
+    // x = D^-1 Z^-1 b: b into tree order, the sweeps in place, scaled back to the caller's order
+    launch_permute_in((const double2*)b, ld, H->d_perm.p, nullptr, 0, N, nrhs, W.vtmp3, N, st);
+    sweep(H, W, W.vtmp3, W.vtmp3, nrhs, 0, st);
+    launch_permute_out(W.vtmp3, N, H->d_perm.p, H->d_scale_solve.p, 0, N, nrhs, (double2*)x, ld, 0, st);
+    check_launch("solve_noalloc");
+  });
+}
+
 extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream) {
   return guarded([&] {
     run_batch(hs, count, (hipStream_t)hip_stream, [&](int32_t k, hipStream_t s) {

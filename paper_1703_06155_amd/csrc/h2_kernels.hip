@@ -3402,4 +3402,35 @@ void launch_contrast_grad(const double2* x, const double2* g, const double2* lam
   hipLaunchKernelGGL(k_contrast_grad, dim3(blocks), dim3(256), 0, st, x, g, lam, ld, nrhs, chi, N, grad);
 }
 
+// ===========================================================================
+// Fixed scratch of the allocation-free solve (h2_solve_noalloc): the sweep's
+// per-level vectors, its final-block vectors and the backward gather's partial
+// sums.  Every call on a device shares that device's copy.
+// ===========================================================================
+static __device__ __align__(256) double2 scratch[NOALLOC_SCRATCH_ELEMS];
+
+double2* noalloc_scratch(hipError_t* err) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static double2* ptr[MAX_DEV] = {};
+  int dev = -1;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= MAX_DEV) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    // the array's name in host code is only a host-side stand-in: take the
+    // device address of this device's copy
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    ptr[dev] = static_cast<double2*>(p);
+  }
+  *err = hipSuccess;
+  return ptr[dev];
+}
+
 }  // namespace h2

@@ -204,6 +204,12 @@ void launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, con
 void launch_dense_gemv(const double2* M, int64_t n, const double2* x, double2* y, int64_t ld, int nrhs,
                        int conj_trans, hipStream_t st);
 
+// ---- fixed device scratch of the allocation-free solve ----
+// 64 MiB per device, held from the first use until the process ends.
+constexpr int64_t NOALLOC_SCRATCH_ELEMS = (int64_t(64) << 20) / 16;
+// Device address of the scratch array on the current device (looked up once per
+// device with hipGetSymbolAddress); NULL with *err set when the lookup fails.
+double2* noalloc_scratch(hipError_t* err);
 
 // ---- H^2 matrix-vector product ----
 void launch_near_mv(int nc, const int32_t* rptr, const int32_t* rcol, const int64_t* boff,

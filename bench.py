@@ -76,19 +76,18 @@ def cpu_baseline() -> dict:
 # (cube side, form), from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
 # 1 GiB copy (the summaries under profiles/); valid only for that workload and the
 # kernel sources hashed here.
-SCHUR_TRAFFIC = {(32, "fp64"): {"sources_sha256": "8d0ef45760b189416cd8b410a670676237a85e2c082123f289136bebc7a94a34",
-                                "bytes_per_launch": 952878868}}
+SCHUR_TRAFFIC = {(64, "mixed"): {"sources_sha256": "c580869f87fc761c8e286994701701d575e77d78a616cbea67be6d9c1a07590a",
+                                   "bytes_per_launch": 11585222194}}
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of the Schur flush kernel's source: the tile engine header, the
-    kernel interface header and the kernel's own section of the kernel file."""
+    """Hash of the Schur flush kernel's source: the tile engine header and the
+    kernel's own section of the kernel file."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1703_06155_amd", "csrc")
-    for f in ("h2_device.hpp", "h2_kernels.hpp"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "h2_device.hpp"), "rb") as fh:
+        h.update(fh.read())
     with open(os.path.join(csrc, "h2_kernels.hip"), "rb") as fh:
         src = fh.read()
     a, b = src.index(b"struct SchurTerm"), src.index(b"void launch_schur(")
@@ -207,6 +206,10 @@ def batch_leg(torch, h2, I, chunk: int) -> dict:
             iters = max([iters] + [i["iterations"] for i in infos])
             for G in hs:
                 G.close()
+            # the handles' memory went back to PyTorch's cache: hand it to the device before the
+            # next chunk allocates buffers of other sizes (untimed)
+            del hs, rhs
+            torch.cuda.empty_cache()
         return elapsed, worst, iters
 
     t_seq, r_seq, it_seq = run(False, "fp64")
@@ -302,6 +305,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batching leg")
     ap.add_argument("--no-cube32", action="store_true", help="skip the 32^3 leg")
     ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--stop-level", type=int, default=0,
+                    help="last factored level of the headline workload (0: chosen by measurement at setup)")
     ap.add_argument("--batch-chunk", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
@@ -331,6 +336,16 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     print(f"# build {g}^3 {build_s:.2f} s (setup, untimed)", file=sys.stderr, flush=True)
+    # setup, untimed: the stop level (Sec. III-C early stop) chosen by measurement
+    t0 = time.perf_counter()
+    if args.stop_level:
+        G.set_stop_level(args.stop_level)
+        stop, stop_ms = args.stop_level, {}
+    else:
+        stop, stop_ms = G.tune_stop_level(max_final=16384)
+    tune_s = time.perf_counter() - t0
+    print(f"# stop level {stop} ({ {k: round(v, 1) for k, v in stop_ms.items()} } ms), tuned in {tune_s:.1f} s",
+          file=sys.stderr, flush=True)
     b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
     B64 = torch.from_numpy(I.plane_waves(pr.points, I.directions(64, 3))).cuda()
     forms = [f for f in args.forms.split(",") if f]
@@ -360,7 +375,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"VIE cube grid {g}^3 (N={pr.n}), leaf 64, eta 1, eps 1e-4, "
                                f"factor + 1 RHS refined to 1e-8; value = the faster form ({hf})",
-                   "N": pr.n, "leaf": 64, "eta": 1.0, "eps": 1e-4, "precision": hf, "build_s": build_s},
+                   "N": pr.n, "leaf": 64, "eta": 1.0, "eps": 1e-4, "precision": hf, "build_s": build_s,
+                   "stop_level": stop, "stop_level_factor_ms": stop_ms, "stop_level_tuning_s": tune_s},
         "factor_ms": head["factor_ms"],
         "factor_unknowns_per_s": head["factor_unknowns_per_s"],
         "solve_ms_refined_1e-8": head["solve_ms_refined_1e-8"],
@@ -379,6 +395,7 @@ def main():
     if not args.no_cube32 and g != 32:
         p32 = I.make_problem("cube32", (32, 32, 32), 64, 1e-4)
         G32 = h2.H2(p32.points, p32.k, p32.h, p32.chi, p32.leaf, p32.eta, p32.eps)
+        stop32, stop32_ms = G32.tune_stop_level(max_final=16384)
         b32 = torch.from_numpy(p32.rhs[:, 0].copy()).cuda()
         B32 = torch.from_numpy(I.plane_waves(p32.points, I.directions(64, 3))).cuda()
         leg32 = form_leg(torch, G32, p32, "fp64", max(args.steps, 3), 1, b32, B32, "32^3")
@@ -386,6 +403,8 @@ def main():
         leg32.pop("_schur_ms")
         leg32.pop("kernel_roofline")
         leg32["workload"] = "VIE cube grid 32^3 (N=32768), leaf 64, eta 1, eps 1e-4, FP64, factor + 1 RHS refined"
+        leg32["stop_level"] = stop32
+        leg32["stop_level_factor_ms"] = stop32_ms
         out["cube32"] = leg32
         G32.close()
         del G32

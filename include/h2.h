@@ -33,7 +33,9 @@
  *     thread-local message readable with h2_last_error();
  *   - arguments are validated before any device work, so argument errors are
  *     reported without touching a GPU;
- *   - a handle is not thread-safe; distinct handles are independent.
+ *   - a handle is not thread-safe, and successive calls on one handle must be
+ *     ordered on the device (the same stream, or the caller synchronises
+ *     between streams); distinct handles are independent.
  */
 #ifndef H2MI_H
 #define H2MI_H

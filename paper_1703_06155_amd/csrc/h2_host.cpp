@@ -119,9 +119,11 @@ struct DArr {
   void release() {
     if (p) {
       if (from) {
-        // the caller's allocator may hand the memory out again at once: nothing
-        // queued by this library may still use it
-        if (!t_device_idle) (void)hipDeviceSynchronize();
+        // the caller's allocator may hand the memory out again at once: the handle's
+        // work on it must be done.  Calls on one handle are ordered on the device (the
+        // same stream, or the caller synchronises), so the current stream covers them;
+        // a device-wide wait here would also stall every other handle of a batch.
+        if (!t_device_idle) (void)hipStreamSynchronize(t_stream);
         from->free(p, t_stream, from->ctx);
       } else {
         (void)hipFree(p);
@@ -1884,13 +1886,14 @@ static void dense_lu_factor(h2_ctx* H, hipStream_t st) {
     check_launch("dense panel");
     if (rest > 0) {
       // U12 = L11^-1 A12 (in place: one tile row owns all 64 rows of its columns)
-      std::vector<GemmTask> t1{{linv.p + b * 4096, A + j0 + (j0 + w) * n, A + j0 + (j0 + w) * n, 64, n, n, (int32_t)w,
-                                (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SET}};
-      run_gemms(H, t1, st);
+      launch_gemm_one({linv.p + b * 4096, A + j0 + (j0 + w) * n, A + j0 + (j0 + w) * n, 64, n, n, (int32_t)w,
+                       (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SET},
+                      st);
       // A22 -= L21 U12
-      std::vector<GemmTask> t2{{A + (j0 + w) + j0 * n, A + j0 + (j0 + w) * n, A + (j0 + w) + (j0 + w) * n, n, n, n,
-                                (int32_t)rest, (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SUB}};
-      run_gemms(H, t2, st);
+      launch_gemm_one({A + (j0 + w) + j0 * n, A + j0 + (j0 + w) * n, A + (j0 + w) + (j0 + w) * n, n, n, n,
+                       (int32_t)rest, (int32_t)rest, (int32_t)w, OP_N, OP_N, ST_SUB},
+                      st);
+      check_launch("dense trailing update");
     }
   }
   int32_t hf = 0;

@@ -300,6 +300,25 @@ void launch_gemm_batched(const GemmTask* tasks, const int32_t* tile_task, const 
   hipLaunchKernelGGL(k_gemm_batched, dim3(ntiles), dim3(256), 0, st, tasks, tile_task, tile_rc);
 }
 
+// One GEMM passed by value (no task list in device memory): tile (blockIdx.x, blockIdx.y)
+__global__ void __launch_bounds__(256) k_gemm_one(GemmTask T) {
+  __shared__ TileSmem<double> s;
+  const int tr = blockIdx.x, tc = blockIdx.y;
+  const int m = min(64, T.m - tr * 64), n = min(64, T.n - tc * 64);
+  if (m <= 0 || n <= 0) return;
+  const double2* A = (T.opA == OP_N || T.opA == OP_R) ? T.A + tr * 64 : T.A + (int64_t)tr * 64 * T.lda;
+  const double2* B = (T.opB == OP_N || T.opB == OP_R) ? T.B + (int64_t)tc * 64 * T.ldb : T.B + tc * 64;
+  TileAcc<double> acc;
+  acc.zero();
+  gemm_tile<double, double2>(s, acc, A, T.lda, T.opA, B, T.ldb, T.opB, m, n, T.K);
+  store_tile<double, double2>(acc, T.C + tr * 64 + (int64_t)tc * 64 * T.ldc, T.ldc, m, n, T.mode);
+}
+
+void launch_gemm_one(const GemmTask& T, hipStream_t st) {
+  if (T.m <= 0 || T.n <= 0) return;
+  hipLaunchKernelGGL(k_gemm_one, dim3((T.m + 63) / 64, (T.n + 63) / 64), dim3(256), 0, st, T);
+}
+
 // C = A^T for each task (A m x n, ld lda -> C n x m, ld ldc)
 __global__ void k_transpose_copy(const GemmTask* tasks) {
   const GemmTask T = tasks[blockIdx.x];
@@ -2570,18 +2589,24 @@ __global__ void __launch_bounds__(256) k_dense_trsv_step(const double2* A, int64
   for (int c0 = 0; c0 < nrhs; c0 += TRSV_RHS) {
     const int nc = min(TRSV_RHS, nrhs - c0);
     __syncthreads();
-    // t = D x_b (mode 0/1) or D^H x_b (mode 2/3) for nc columns: thread (row i, column group)
+    // t = D x_b (mode 0/1) or D^H x_b (mode 2/3) for nc columns: thread (row i, column),
+    // sixteen loads in flight (D is zero outside the block's w x w corner)
     for (int e = tid; e < 64 * nc; e += blockDim.x) {
       const int i = e & 63, c = e >> 6;
       double2 acc = make_double2(0, 0);
-      if (i < w) {
-        const double2* xb = x + j0 + (c0 + c) * ld;
-        if (!rowwise)
-          for (int k = 0; k < w; ++k) acc = cadd(acc, cmul(D[i + 64 * k], xb[k]));
-        else
-          for (int k = 0; k < w; ++k) acc = cadd(acc, cmulc(D[k + 64 * i], xb[k]));
+      const double2* xb = x + j0 + (c0 + c) * ld;
+      for (int k0 = 0; k0 < w; k0 += 16) {
+        double2 dv[16], xv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int k = k0 + u;
+          dv[u] = k < w ? (rowwise ? D[k + 64 * i] : D[i + 64 * k]) : make_double2(0, 0);
+          xv[u] = k < w ? xb[k] : make_double2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = cadd(acc, rowwise ? cmulc(dv[u], xv[u]) : cmul(dv[u], xv[u]));
       }
-      t[i + 64 * c] = acc;
+      t[i + 64 * c] = i < w ? acc : make_double2(0, 0);
     }
     __syncthreads();
     if (blockIdx.x == 0)
@@ -2593,11 +2618,15 @@ __global__ void __launch_bounds__(256) k_dense_trsv_step(const double2* A, int64
         double2 acc[TRSV_RHS];
 #pragma unroll
         for (int c = 0; c < TRSV_RHS; ++c) acc[c] = make_double2(0, 0);
-        for (int k = 0; k < w; ++k) {
-          const double2 a = A[r + (j0 + k) * n];
+        for (int k0 = 0; k0 < w; k0 += 16) {
+          double2 av[16];
 #pragma unroll
-          for (int c = 0; c < TRSV_RHS; ++c)
-            if (c < nc) acc[c] = cadd(acc[c], cmul(a, t[k + 64 * c]));
+          for (int u = 0; u < 16; ++u) av[u] = (k0 + u < w) ? A[r + (j0 + k0 + u) * n] : make_double2(0, 0);
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int c = 0; c < TRSV_RHS; ++c)
+              if (c < nc) acc[c] = cadd(acc[c], cmul(av[u], t[k0 + u + 64 * c]));
         }
         for (int c = 0; c < nc; ++c) {
           double2* p = x + r + (c0 + c) * ld;

@@ -114,6 +114,8 @@ void launch_gram_acc(int ncl, const int32_t* dim, const int64_t* yoff, const dou
 void launch_coupling_x(const GeomView& g, int npairs, int ntr, int ntc, const int32_t* pt, const int32_t* ps,
                        const int64_t* tstart, const int32_t* tsz, const int32_t* tk, const int64_t* voff,
                        const double2* V, const int64_t* xoff, double2* X, hipStream_t st);
+// one GEMM task passed by value: a tile per workgroup, no host synchronisation
+void launch_gemm_one(const GemmTask& T, hipStream_t st);
 void launch_gemm_batched(const GemmTask* tasks, const int32_t* tile_task, const int32_t* tile_rc,
                          int ntiles, hipStream_t st);
 void launch_transpose_copy(const GemmTask* tasks, int ntasks, hipStream_t st);

@@ -1927,6 +1927,33 @@ static void dense_lu_apply(h2_ctx* H, double2* x, double2* y, int nrhs, int adj,
   const int64_t nb = (n + 63) / 64;
   const double2* linv = H->dl_linv.p;
   const double2* uinv = H->dl_uinv.p;
+  if (nrhs > SMALL_RHS) {
+    // many right-hand sides: each block step as two matrix-core GEMMs, y_b = D x_b
+    // (D or D^H) and the coupling update of the unsolved rows (ST_SUB)
+    double2* A0 = H->Zf.p;
+    auto step = [&](int64_t j0, int mode, const double2* D, double2* xin, double2* yout) {
+      const int w = (int)std::min<int64_t>(64, n - j0);
+      const bool fwd = (mode == 0 || mode == 2), herm = (mode >= 2);
+      launch_gemm_one({D, xin + j0, yout + j0, 64, n, n, w, nrhs, w, herm ? OP_C : OP_N, OP_N, ST_SET}, st);
+      const int64_t r0 = fwd ? j0 + w : 0, rows = fwd ? n - j0 - w : j0;
+      if (rows <= 0) return;
+      // coupling of the block's columns (L or U below / above it) or, for the adjoint, of its rows
+      const double2* Ac = herm ? A0 + j0 + r0 * n : A0 + r0 + j0 * n;
+      launch_gemm_one({Ac, yout + j0, xin + r0, n, n, n, (int32_t)rows, nrhs, w, herm ? OP_C : OP_N, OP_N, ST_SUB},
+                      st);
+    };
+    if (!adj) {
+      launch_dense_perm(x, y, H->dl_perm.p, n, nrhs, n, 0, st);  // y = P x
+      for (int64_t b = 0; b < nb; ++b) step(b * 64, 0, linv + b * 4096, y, x);        // x = L^-1 y
+      for (int64_t b = nb - 1; b >= 0; --b) step(b * 64, 1, uinv + b * 4096, x, y);   // y = U^-1 x
+    } else {
+      for (int64_t b = 0; b < nb; ++b) step(b * 64, 2, uinv + b * 4096, x, y);        // y = U^-H x
+      for (int64_t b = nb - 1; b >= 0; --b) step(b * 64, 3, linv + b * 4096, y, x);   // x = L^-H y
+      launch_dense_perm(x, y, H->dl_perm.p, n, nrhs, n, 1, st);  // y = P^T x
+    }
+    check_launch("final block solve");
+    return;
+  }
   if (!adj) {
     launch_dense_perm(x, y, H->dl_perm.p, n, nrhs, n, 0, st);  // y = P x
     for (int64_t b = 0; b < nb; ++b)                            // x = L^-1 y

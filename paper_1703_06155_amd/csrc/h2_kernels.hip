@@ -9,11 +9,45 @@
 
 #include <algorithm>
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "h2_device.hpp"
 #include "h2_kernels.hpp"
 
 namespace h2 {
+
+// The block index a kernel body works on: the hardware one for a problem's own
+// launch, or, inside a launch shared by several problems (BatchEntry), the
+// position within that problem's share.
+struct VBlock {
+  int x, y, z, gx, gy, gz;
+};
+__device__ __forceinline__ VBlock vblock() {
+  return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, (int)gridDim.z};
+}
+// entry of a shared launch that owns this workgroup (entries sorted by `first`)
+__device__ __forceinline__ const BatchEntry& locate(const BatchEntry* E, int ne, VBlock& VB) {
+  const int lin = blockIdx.x;
+  int lo = 0, hi = ne - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (E[mid].first <= lin)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const BatchEntry& e = E[lo];
+  int r = lin - e.first;
+  VB.gx = e.gx;
+  VB.gy = e.gy;
+  VB.gz = e.gz;
+  VB.x = r % e.gx;
+  r /= e.gx;
+  VB.y = r % e.gy;
+  VB.z = r / e.gy;
+  return e;
+}
 
 static inline __host__ __device__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
@@ -650,12 +684,13 @@ __device__ __forceinline__ bool gram_term(const LevelView& v, const ColourTasks&
   return true;
 }
 
-__global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, double2* part, int64_t pstride) {
+__device__ __forceinline__ void gram_fill_body(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride,
+                                               const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i];
-  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
-  const int sp = blockIdx.z;
+  const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
+  const int sp = VB.z;
   if (tr * 64 >= n || tc * 64 >= n) return;
   const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
   const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
@@ -691,23 +726,40 @@ __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, d
     }
   }
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
-  double2* P = part + (int64_t)sp * pstride + (int64_t)blockIdx.x * cstride;
+  double2* P = part + (int64_t)sp * pstride + (int64_t)VB.x * cstride;
   store_tile_bal_set<double, double2>(acc, P + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, mt, nt);
+}
+__global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, double2* part, int64_t pstride) {
+  gram_fill_body(v, c, part, pstride, vblock());
+}
+__global__ void __launch_bounds__(256) k_gram_fill_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  gram_fill_body(e.v, e.c, e.buf, e.aux, VB);
 }
 
 // H_i = sum of the partial Grams in a fixed order (deterministic); grid (cluster,
 // GRAM_RED_BLOCKS) with the entries interleaved over the workgroups
-__global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* part, int64_t pstride) {
-  const int i = c.cl[blockIdx.x];
+__device__ __forceinline__ void gram_fill_reduce_body(const LevelView& v, const ColourTasks& c, const double2* part,
+                                                      int64_t pstride, const VBlock& VB) {
+  const int i = c.cl[VB.x];
   const int n = v.n[i];
   double2* H = v.W + v.w_off[i];
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
-  const double2* P0 = part + (int64_t)blockIdx.x * cstride;
-  for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < n * n; e += gridDim.y * blockDim.x) {
+  const double2* P0 = part + (int64_t)VB.x * cstride;
+  for (int e = VB.y * blockDim.x + threadIdx.x; e < n * n; e += VB.gy * blockDim.x) {
     double2 a = P0[e];
     for (int sp = 1; sp < GRAM_SPLIT; ++sp) a = cadd(a, P0[(int64_t)sp * pstride + e]);
     H[e] = a;
   }
+}
+__global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* part, int64_t pstride) {
+  gram_fill_reduce_body(v, c, part, pstride, vblock());
+}
+__global__ void k_gram_fill_reduce_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  gram_fill_reduce_body(e.v, e.c, e.buf, e.aux, VB);
 }
 
 void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride, hipStream_t st) {
@@ -717,12 +769,12 @@ void launch_gram_fill(const LevelView& v, const ColourTasks& c, double2* part, i
 }
 
 // phase 0: X = H B_perp ; phase 1: G' = B_perp^H X ; phase 2: Q~[:, k:n] = B_perp U'
-__global__ void __launch_bounds__(256) k_xform(LevelView v, ColourTasks c, int phase) {
+__device__ __forceinline__ void xform_body(const LevelView& v, const ColourTasks& c, int phase, const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], k = v.k[i], d = n - k;
   if (d <= 0) return;
-  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
   double2* W = v.W + v.w_off[i];
   const double2* H = W;
   double2* X = W + (int64_t)n * n;
@@ -749,6 +801,12 @@ __global__ void __launch_bounds__(256) k_xform(LevelView v, ColourTasks c, int p
     double2* Qc = v.Q + v.q_off[i] + (int64_t)k * n;
     store_tile<double, double2>(acc, Qc + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, ST_SET);
   }
+}
+__global__ void __launch_bounds__(256) k_xform(LevelView v, ColourTasks c, int phase) { xform_body(v, c, phase, vblock()); }
+__global__ void __launch_bounds__(256) k_xform_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  xform_body(e.v, e.c, e.i0, VB);
 }
 
 void launch_xform(const LevelView& v, const ColourTasks& c, int phase, hipStream_t st) {
@@ -1139,7 +1197,8 @@ __device__ void tri_inverse_iteration(const double* __restrict__ dg, const doubl
 }
 
 template <int NQ>
-__global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c, double2* scratch, int dm) {
+__device__ __forceinline__ void step0_eig_body(const LevelView& v, const ColourTasks& c, double2* scratch, int dm,
+                                               const VBlock& VB) {
   __shared__ double2 sP[S0_PACK];
   __shared__ double2 ws[STEP0_DMAX], vs[STEP0_DMAX], tauv[STEP0_DMAX];
   __shared__ double dg[STEP0_DMAX], off[STEP0_DMAX], eig[STEP0_DMAX];
@@ -1149,7 +1208,7 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
   __shared__ double bounds[4];
   __shared__ int s_p;
   const int64_t stride = 4 * (int64_t)dm * dm;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], k = v.k[i], d = n - k;
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   double2* Q = v.Q + v.q_off[i];
@@ -1160,7 +1219,7 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
     double2* W = v.W + v.w_off[i];
     double2* Gp = W + (int64_t)n * n + (int64_t)n * d;
     double2* Up = Gp + (int64_t)d * d;
-    double2* scr = scratch + (int64_t)blockIdx.x * stride;
+    double2* scr = scratch + (int64_t)VB.x * stride;
     double2* A = (d <= STEP0_PACK_LDS) ? sP : scr;  // packed lower working matrix
     // p = 0 exactly when every eigenvalue of G' is below tau0^2 = (eps_fill nu)^2 (then
     // sigma_1(W) < eps_fill nu < nu and the threshold tau = eps_fill max(nu, sigma_1) = tau0).
@@ -1440,6 +1499,16 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
   if (v.forced && v.forced[i] >= 0) p = min(max(v.forced[i] - k, 0), d);
   if (tid == 0) v.kt[i] = k + p;
 }
+template <int NQ>
+__global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c, double2* scratch, int dm) {
+  step0_eig_body<NQ>(v, c, scratch, dm, vblock());
+}
+template <int NQ>
+__global__ void __launch_bounds__(S0_NT) k_step0_eig_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  step0_eig_body<NQ>(e.v, e.c, e.buf, e.i0, VB);
+}
 
 void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch, int dm, hipStream_t st) {
   if (c.ncl <= 0) return;
@@ -1457,8 +1526,8 @@ void launch_step0_eig(const LevelView& v, const ColourTasks& c, double2* scratch
 // Step 2 projections.  side 0: T = (x in colour ? Q~_x^H : I) Z ; side 1: Z = T (y in colour ? conj(Q~_y) : I)
 template <typename R>
 __device__ __forceinline__ void proj_body(const LevelView& v, const ColourTasks& c, double2* temp, int side,
-                                          TileSmem<R>& s) {
-  const int task = blockIdx.x;
+                                          TileSmem<R>& s, const VBlock& VB) {
+  const int task = VB.x;
   const int sl = c.pj_slot[task];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
   const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
@@ -1469,7 +1538,7 @@ __device__ __forceinline__ void proj_body(const LevelView& v, const ColourTasks&
   const int cols_in = cy ? ny : dim_before(v, y, c.colour);
   double2* Z = v.slots + v.slot_off[sl];
   double2* T = temp + c.pj_toff[task];
-  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
   if (side == 0) {
     if (tr * 64 >= rows_in || tc * 64 >= cols_in) return;
     const int m = min(64, rows_in - tr * 64), nn = min(64, cols_in - tc * 64);
@@ -1506,12 +1575,22 @@ __device__ __forceinline__ void proj_body(const LevelView& v, const ColourTasks&
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side, int which) {
+__device__ __forceinline__ void proj_kernel_body(const LevelView& v, const ColourTasks& c, double2* temp, int side,
+                                                 int which, const VBlock& VB) {
   __shared__ TileSmem<R> s;
-  const int sl = c.pj_slot[blockIdx.x];
+  const int sl = c.pj_slot[VB.x];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
   if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
-  proj_body<R>(v, c, temp, side, s);
+  proj_body<R>(v, c, temp, side, s, VB);
+}
+template <typename R>
+__global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double2* temp, int side, int which) {
+  proj_kernel_body<R>(v, c, temp, side, which, vblock());
+}
+__global__ void __launch_bounds__(256) k_proj_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  proj_kernel_body<double>(e.v, e.c, e.buf, e.i0, PJ_ALL, VB);
 }
 
 union ProjSmem {
@@ -1521,21 +1600,31 @@ union ProjSmem {
 
 // Mixed form in one launch: diagonal blocks (the large self terms of Z) in FP64,
 // the others on FP32 matrix cores.
-__global__ void __launch_bounds__(256) k_proj_mixed(LevelView v, ColourTasks c, double2* temp, int side) {
+__device__ __forceinline__ void proj_mixed_body(const LevelView& v, const ColourTasks& c, double2* temp, int side,
+                                                const VBlock& VB) {
   __shared__ ProjSmem s;
-  const int sl = c.pj_slot[blockIdx.x];
+  const int sl = c.pj_slot[VB.x];
   if (v.slot_a[sl] == v.slot_b[sl])
-    proj_body<double>(v, c, temp, side, s.d);
+    proj_body<double>(v, c, temp, side, s.d, VB);
   else
-    proj_body<float>(v, c, temp, side, s.f);
+    proj_body<float>(v, c, temp, side, s.f, VB);
+}
+__global__ void __launch_bounds__(256) k_proj_mixed(LevelView v, ColourTasks c, double2* temp, int side) {
+  proj_mixed_body(v, c, temp, side, vblock());
+}
+__global__ void __launch_bounds__(256) k_proj_mixed_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  proj_mixed_body(e.v, e.c, e.buf, e.i0, VB);
 }
 
 // Fused Step 2 for levels whose blocks fit one 64x64 tile: the workgroup owns the
 // whole block, so Z <- Q~_x^H Z and Z <- Z conj(Q~_y) are applied in place.  Fill
 // blocks keep only the k~_x kept rows of a row cluster eliminated now.
 template <typename R>
-__device__ __forceinline__ void proj_fused_body(const LevelView& v, const ColourTasks& c, TileSmem<R>& s) {
-  const int sl = c.pj_slot[blockIdx.x];
+__device__ __forceinline__ void proj_fused_body(const LevelView& v, const ColourTasks& c, TileSmem<R>& s,
+                                                const VBlock& VB) {
+  const int sl = c.pj_slot[VB.x];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
   const bool cx = v.colour[x] == c.colour, cy = v.colour[y] == c.colour;
   const int nx = v.n[x], ny = v.n[y];
@@ -1559,21 +1648,39 @@ __device__ __forceinline__ void proj_fused_body(const LevelView& v, const Colour
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, int which) {
+__device__ __forceinline__ void proj_fused_kernel_body(const LevelView& v, const ColourTasks& c, int which,
+                                                       const VBlock& VB) {
   __shared__ TileSmem<R> s;
-  const int sl = c.pj_slot[blockIdx.x];
+  const int sl = c.pj_slot[VB.x];
   const int x = v.slot_a[sl], y = v.slot_b[sl];
   if ((which == PJ_OFFDIAG && x == y) || (which == PJ_DIAG && x != y)) return;
-  proj_fused_body<R>(v, c, s);
+  proj_fused_body<R>(v, c, s, VB);
+}
+template <typename R>
+__global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, int which) {
+  proj_fused_kernel_body<R>(v, c, which, vblock());
+}
+__global__ void __launch_bounds__(256) k_proj_fused_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  proj_fused_kernel_body<double>(e.v, e.c, PJ_ALL, VB);
 }
 
-__global__ void __launch_bounds__(256) k_proj_fused_mixed(LevelView v, ColourTasks c) {
+__device__ __forceinline__ void proj_fused_mixed_body(const LevelView& v, const ColourTasks& c, const VBlock& VB) {
   __shared__ ProjSmem s;
-  const int sl = c.pj_slot[blockIdx.x];
+  const int sl = c.pj_slot[VB.x];
   if (v.slot_a[sl] == v.slot_b[sl])
-    proj_fused_body<double>(v, c, s.d);
+    proj_fused_body<double>(v, c, s.d, VB);
   else
-    proj_fused_body<float>(v, c, s.f);
+    proj_fused_body<float>(v, c, s.f, VB);
+}
+__global__ void __launch_bounds__(256) k_proj_fused_mixed(LevelView v, ColourTasks c) {
+  proj_fused_mixed_body(v, c, vblock());
+}
+__global__ void __launch_bounds__(256) k_proj_fused_mixed_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  proj_fused_mixed_body(e.v, e.c, VB);
 }
 
 // The mixed form projects the off-diagonal blocks in complex FP32 and keeps the
@@ -1622,18 +1729,19 @@ __device__ __forceinline__ double rl(double v, int l) {
 __device__ __forceinline__ double2 lane_read(double2 v, int l) { return make_double2(rl(v.x, l), rl(v.y, l)); }
 __device__ __forceinline__ double2 pick2(const double2 (&x)[2], int q) { return q == 0 ? x[0] : x[1]; }
 
-__global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, double2* scratch, int rm) {
+__device__ __forceinline__ void lu_reg_body(const LevelView& v, const ColourTasks& c, double2* scratch, int rm,
+                                            const VBlock& VB) {
   __shared__ double2 sF[LU_LDS_MAX * LU_LDS_MAX];
   __shared__ double2 lbuf[2][LU_REG_MAX];
   __shared__ double2 dinv[LU_REG_MAX];
   __shared__ int pivrow[LU_REG_MAX], pjpos[LU_REG_MAX];
   __shared__ int s_fail;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (r <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
-  double2* F = (r <= LU_LDS_MAX) ? sF : scratch + (int64_t)blockIdx.x * ((int64_t)rm * rm + rm);
+  double2* F = (r <= LU_LDS_MAX) ? sF : scratch + (int64_t)VB.x * ((int64_t)rm * rm + rm);
   double2 col[LU_CPW][2];
   int pos[2];
 #pragma unroll
@@ -1786,23 +1894,32 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
     }
   }
 }
+__global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, double2* scratch, int rm) {
+  lu_reg_body(v, c, scratch, rm, vblock());
+}
+__global__ void __launch_bounds__(LU_NT) k_lu_reg_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  lu_reg_body(e.v, e.c, e.buf, e.i0, VB);
+}
 
 // Beyond LU_REG_MAX rows: the same factorization with explicit row swaps on F
 // (LDS up to LU_LDS_MAX, else scratch) by a 256-thread workgroup.
-__global__ void __launch_bounds__(256) k_lu_big(LevelView v, ColourTasks c, double2* scratch, int rm) {
+__device__ __forceinline__ void lu_big_body(const LevelView& v, const ColourTasks& c, double2* scratch, int rm,
+                                            const VBlock& VB) {
   __shared__ double2 sF[LU_LDS_MAX * LU_LDS_MAX];
   __shared__ double2 sT[LU_LDS_MAX];
   __shared__ int16_t perm[STEP0_DMAX];
   __shared__ int s_piv;
   __shared__ double s_pv;
   static_assert(STEP0_DMAX <= 32767, "pivot indices are 16-bit");
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (r <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const double2* Z = v.slots + v.slot_off[v.diag_slot[i]];
   const bool in_lds = r <= LU_LDS_MAX;
-  double2* F = in_lds ? sF : scratch + (int64_t)blockIdx.x * ((int64_t)rm * rm + rm);
+  double2* F = in_lds ? sF : scratch + (int64_t)VB.x * ((int64_t)rm * rm + rm);
   double2* tmp = in_lds ? sT : F + (int64_t)rm * rm;
   for (int e = tid; e < r * r; e += blockDim.x) {
     const int a = e % r, b = e / r;
@@ -1910,6 +2027,14 @@ __global__ void __launch_bounds__(256) k_lu_big(LevelView v, ColourTasks c, doub
     Li[a + (int64_t)perm[b] * rmax] = (a > b) ? f : make_double2(a == b ? 1.0 : 0.0, 0.0);
   }
 }
+__global__ void __launch_bounds__(256) k_lu_big(LevelView v, ColourTasks c, double2* scratch, int rm) {
+  lu_big_body(v, c, scratch, rm, vblock());
+}
+__global__ void __launch_bounds__(256) k_lu_big_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  lu_big_body(e.v, e.c, e.buf, e.i0, VB);
+}
 
 void launch_lu(const LevelView& v, const ColourTasks& c, double2* scratch, int rm, hipStream_t st) {
   if (c.ncl <= 0) return;
@@ -1947,22 +2072,22 @@ __device__ void panel_max(const TileAcc<double>& acc, unsigned long long* dst) {
 
 // Step 3a panels: R_i[:, a] = (L^-1 P) Z_ia[k~:n, 0:m_a]; C_i[a, :] = Z_ai[0:m_a, k~:n] U^-1.
 // grid: (panel task, 2x2 tiles, which)
-__global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
+__device__ __forceinline__ void panels_body(const LevelView& v, const ColourTasks& c, const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int task = blockIdx.x;
+  const int task = VB.x;
   const int i = c.pn_i[task], ja = c.pn_ja[task];
   const int a = v.np_cl[ja];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (r <= 0) return;
   const int ma = (a == i) ? kt : dim_before(v, a, c.colour);
   const int na = v.n[a];
-  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
   const double2* Li = v.LU + v.lu_off[i];
   const double2* Ui = Li + (int64_t)rmax * rmax;
   const int off = v.np_off[ja];
   TileAcc<double> acc;
   acc.zero();
-  if (blockIdx.z == 0) {
+  if (VB.z == 0) {
     // R: r x ma
     if (tr * 64 >= r || tc * 64 >= ma) return;
     const int m = min(64, r - tr * 64), nn = min(64, ma - tc * 64);
@@ -2008,6 +2133,12 @@ __global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) {
     store_tile<double, double2>(acc, C + tr * 64 + (int64_t)tc * 64 * pr, pr, m, nn, ST_SET);
     if (v.pmax) panel_max(acc, &v.pmax[4 * i]);
   }
+}
+__global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) { panels_body(v, c, vblock()); }
+__global__ void __launch_bounds__(256) k_panels_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  panels_body(e.v, e.c, VB);
 }
 
 void launch_panels(const LevelView& v, const ColourTasks& c, hipStream_t st) {
@@ -2103,12 +2234,12 @@ __device__ __forceinline__ void schur_stream(const LevelView& v, const ColourTas
 }
 
 template <bool MIX>
-__device__ __forceinline__ void schur_flush(const LevelView& v, const ColourTasks& c, SchurSmem& s) {
-  const int task = blockIdx.x;
+__device__ __forceinline__ void schur_flush(const LevelView& v, const ColourTasks& c, SchurSmem& s, const VBlock& VB) {
+  const int task = VB.x;
   const int sl = c.sc_slot[task];
   const int a = v.slot_a[sl], b = v.slot_b[sl];
   const int ma = dim_after(v, a, c.colour), mb = dim_after(v, b, c.colour);
-  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
   if (tr * 64 >= ma || tc * 64 >= mb) return;
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
   const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
@@ -2191,39 +2322,53 @@ __device__ __forceinline__ void schur_flush(const LevelView& v, const ColourTask
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_schur_fp64(LevelView v,
                                                                                         ColourTasks c) {
   __shared__ SchurSmem s;
-  schur_flush<false>(v, c, s);
+  schur_flush<false>(v, c, s, vblock());
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_schur_fp64_b(const BatchEntry* E,
+                                                                                          int ne) {
+  __shared__ SchurSmem s;
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  schur_flush<false>(e.v, e.c, s, VB);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur_mixed(LevelView v,
                                                                                          ColourTasks c) {
   __shared__ SchurSmem s;
-  schur_flush<true>(v, c, s);
+  schur_flush<true>(v, c, s, vblock());
+}
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_schur_mixed_b(const BatchEntry* E,
+                                                                                           int ne) {
+  __shared__ SchurSmem s;
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  schur_flush<true>(e.v, e.c, s, VB);
 }
 
 // Split tasks: Z -= the sum of the chunks' partial tiles, added in chunk order.
 // grid: (group, tiles^2, 4); each workgroup takes a quarter of the tile's
 // elements, four per thread, with the block values and all four elements'
 // partials of a chunk in flight together.
-__global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c) {
-  const int task = c.sc_gtask[blockIdx.x];
+__device__ __forceinline__ void schur_reduce_body(const LevelView& v, const ColourTasks& c, const VBlock& VB) {
+  const int task = c.sc_gtask[VB.x];
   const int sl = c.sc_slot[task];
   const int a = v.slot_a[sl], b = v.slot_b[sl];
   const int ma = dim_after(v, a, c.colour), mb = dim_after(v, b, c.colour);
-  const int tr = blockIdx.y % c.tiles, tc = blockIdx.y / c.tiles;
+  const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
   if (tr * 64 >= ma || tc * 64 >= mb) return;
   const int m = min(64, ma - tr * 64), nn = min(64, mb - tc * 64);
   const int nparts = c.sc_sp[4 * task + 1];
   const int na = v.n[a];
   const int ta = (na + 63) >> 6, tb = (v.n[b] + 63) >> 6;
   const int64_t tt = (int64_t)ta * tb;
-  const double2* P0 = c.sc_part + ((int64_t)c.sc_gbase[blockIdx.x] + tr + ta * tc) * 4096;
+  const double2* P0 = c.sc_part + ((int64_t)c.sc_gbase[VB.x] + tr + ta * tc) * 4096;
   double2* Z = v.slots + v.slot_off[sl] + tr * 64 + (int64_t)tc * 64 * na;
   int off[4];
   bool ok[4];
   double2 zv[4], sum[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int q = blockIdx.z * 1024 + u * 256 + threadIdx.x;  // element (q % 64, q / 64) of the tile
+    const int q = VB.z * 1024 + u * 256 + threadIdx.x;  // element (q % 64, q / 64) of the tile
     const int i = q & 63, j = q >> 6;
     ok[u] = i < m && j < nn;
     off[u] = i + 64 * j;
@@ -2245,6 +2390,12 @@ __global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c
 #pragma unroll
   for (int u = 0; u < 4; ++u)
     if (ok[u]) Z[(off[u] & 63) + (int64_t)(off[u] >> 6) * na] = make_double2(zv[u].x - sum[u].x, zv[u].y - sum[u].y);
+}
+__global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c) { schur_reduce_body(v, c, vblock()); }
+__global__ void __launch_bounds__(256) k_schur_reduce_b(const BatchEntry* E, int ne) {
+  VBlock VB;
+  const BatchEntry& e = locate(E, ne, VB);
+  schur_reduce_body(e.v, e.c, VB);
 }
 
 void launch_schur(const LevelView& v, const ColourTasks& c, bool mixed, hipStream_t st) {
@@ -3429,6 +3580,98 @@ void launch_contrast_grad(const double2* x, const double2* g, const double2* lam
   if (N <= 0) return;
   const int blocks = (int)imin64(4096, (N + 255) / 256);
   hipLaunchKernelGGL(k_contrast_grad, dim3(blocks), dim3(256), 0, st, x, g, lam, ld, nrhs, chi, N, grad);
+}
+
+// ===========================================================================
+// Launches shared by several independent problems: the workgroups of one launch
+// are dealt to the problems' entries (BatchEntry, sorted by `first`); every kernel
+// body runs exactly as in the problem's own launch.
+// ===========================================================================
+// The entries one problem contributes to a stage of a colour, with the grids and
+// arguments its own launchers (launch_schur, launch_gram_fill, ...) would use.
+void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, double2* buf,
+                         int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out) {
+  auto add = [&](int kernel, int gx, int gy, int gz, double2* b, int64_t a, int i) {
+    if (gx <= 0 || gy <= 0 || gz <= 0) return;
+    BatchEntry e;
+    e.v = v;
+    e.c = c;
+    e.buf = b;
+    e.aux = a;
+    e.i0 = i;
+    e.gx = gx;
+    e.gy = gy;
+    e.gz = gz;
+    e.first = 0;
+    out.emplace_back(kernel, e);
+  };
+  const int t2 = c.tiles * c.tiles;
+  switch (stage) {
+    case BS_SCHUR:
+      if (c.nsc > 0) add(mixed ? BK_SCHUR_MIXED : BK_SCHUR_FP64, c.nsc, t2, 1, nullptr, 0, 0);
+      break;
+    case BS_SCHUR_REDUCE:
+      if (c.nsc > 0 && c.ngrp > 0) add(BK_SCHUR_REDUCE, c.ngrp, t2, 4, nullptr, 0, 0);
+      break;
+    case BS_GRAM:
+      add(BK_GRAM_FILL, c.ncl, t2, GRAM_SPLIT, buf, aux, 0);
+      break;
+    case BS_GRAM_REDUCE:
+      add(BK_GRAM_FILL_REDUCE, c.ncl, GRAM_RED_BLOCKS, 1, buf, aux, 0);
+      break;
+    case BS_XFORM0:
+    case BS_XFORM1:
+    case BS_XFORM2:
+      add(BK_XFORM, c.ncl, t2, 1, nullptr, 0, stage - BS_XFORM0);
+      break;
+    case BS_STEP0: {
+      const int k = i0 <= 64 ? BK_STEP0_1 : i0 <= 128 ? BK_STEP0_2 : i0 <= 256 ? BK_STEP0_4 : BK_STEP0_8;
+      add(k, c.ncl, 1, 1, buf, 0, i0);
+      break;
+    }
+    case BS_PROJ0:
+      if (c.tiles == 1)
+        add(mixed ? BK_PROJ_FUSED_MIXED : BK_PROJ_FUSED, c.npj, 1, 1, nullptr, 0, 0);
+      else
+        add(mixed ? BK_PROJ_MIXED : BK_PROJ, c.npj, t2, 1, buf, 0, 0);
+      break;
+    case BS_PROJ1:
+      if (c.tiles > 1) add(mixed ? BK_PROJ_MIXED : BK_PROJ, c.npj, t2, 1, buf, 0, 1);
+      break;
+    case BS_LU:
+      add(i0 <= LU_REG_MAX ? BK_LU_REG : BK_LU_BIG, c.ncl, 1, 1, buf, 0, i0);
+      break;
+    case BS_PANELS:
+      add(BK_PANELS, c.npn, t2, 2, nullptr, 0, 0);
+      break;
+    default:
+      break;
+  }
+}
+
+void launch_batched(int kernel, const BatchEntry* entries, int ne, int blocks, hipStream_t st) {
+  if (ne <= 0 || blocks <= 0) return;
+  const dim3 g(blocks), b256(256);
+  switch (kernel) {
+    case BK_SCHUR_FP64: hipLaunchKernelGGL(k_schur_fp64_b, g, b256, 0, st, entries, ne); break;
+    case BK_SCHUR_MIXED: hipLaunchKernelGGL(k_schur_mixed_b, g, b256, 0, st, entries, ne); break;
+    case BK_SCHUR_REDUCE: hipLaunchKernelGGL(k_schur_reduce_b, g, b256, 0, st, entries, ne); break;
+    case BK_GRAM_FILL: hipLaunchKernelGGL(k_gram_fill_b, g, b256, 0, st, entries, ne); break;
+    case BK_GRAM_FILL_REDUCE: hipLaunchKernelGGL(k_gram_fill_reduce_b, g, b256, 0, st, entries, ne); break;
+    case BK_XFORM: hipLaunchKernelGGL(k_xform_b, g, b256, 0, st, entries, ne); break;
+    case BK_STEP0_1: hipLaunchKernelGGL(k_step0_eig_b<1>, g, dim3(S0_NT), 0, st, entries, ne); break;
+    case BK_STEP0_2: hipLaunchKernelGGL(k_step0_eig_b<2>, g, dim3(S0_NT), 0, st, entries, ne); break;
+    case BK_STEP0_4: hipLaunchKernelGGL(k_step0_eig_b<4>, g, dim3(S0_NT), 0, st, entries, ne); break;
+    case BK_STEP0_8: hipLaunchKernelGGL(k_step0_eig_b<8>, g, dim3(S0_NT), 0, st, entries, ne); break;
+    case BK_PROJ: hipLaunchKernelGGL(k_proj_b, g, b256, 0, st, entries, ne); break;
+    case BK_PROJ_MIXED: hipLaunchKernelGGL(k_proj_mixed_b, g, b256, 0, st, entries, ne); break;
+    case BK_PROJ_FUSED: hipLaunchKernelGGL(k_proj_fused_b, g, b256, 0, st, entries, ne); break;
+    case BK_PROJ_FUSED_MIXED: hipLaunchKernelGGL(k_proj_fused_mixed_b, g, b256, 0, st, entries, ne); break;
+    case BK_LU_REG: hipLaunchKernelGGL(k_lu_reg_b, g, dim3(LU_NT), 0, st, entries, ne); break;
+    case BK_LU_BIG: hipLaunchKernelGGL(k_lu_big_b, g, b256, 0, st, entries, ne); break;
+    case BK_PANELS: hipLaunchKernelGGL(k_panels_b, g, b256, 0, st, entries, ne); break;
+    default: break;
+  }
 }
 
 // ===========================================================================

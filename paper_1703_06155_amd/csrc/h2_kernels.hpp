@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
+#include <vector>
 
 namespace h2 {
 
@@ -85,6 +87,43 @@ struct ColourTasks {
   int colour;
   int tiles;                              // 64-wide tiles per block side (ceil(max n / 64))
 };
+
+// One problem's share of a launch that serves several independent problems: the
+// launch's workgroups are dealt to the entries in order, entry e taking
+// gx * gy * gz workgroups from `first` on, laid out as the grid (gx, gy, gz) the
+// problem's own launch would use.  buf / aux / i0 carry the kernel's per-problem
+// arguments (work space pointer and stride, phase, side or size bound).
+struct BatchEntry {
+  LevelView v;
+  ColourTasks c;
+  double2* buf;
+  int64_t aux;
+  int32_t i0;
+  int32_t gx, gy, gz;
+  int32_t first;
+};
+
+// Kernels that run as one launch over several problems' entries (the same
+// bodies as the problems' own launches; the entries' grids and arguments follow
+// the matching single-problem launcher).
+enum BatchKernel : int {
+  BK_SCHUR_FP64, BK_SCHUR_MIXED, BK_SCHUR_REDUCE, BK_GRAM_FILL, BK_GRAM_FILL_REDUCE, BK_XFORM,
+  BK_STEP0_1, BK_STEP0_2, BK_STEP0_4, BK_STEP0_8, BK_PROJ, BK_PROJ_MIXED, BK_PROJ_FUSED, BK_PROJ_FUSED_MIXED,
+  BK_LU_REG, BK_LU_BIG, BK_PANELS
+};
+// entries: device array of ne entries sorted by `first`; blocks = total workgroups
+void launch_batched(int kernel, const BatchEntry* entries, int ne, int blocks, hipStream_t st);
+// The stages of one colour of a level, in launch order (each depends on the previous).
+enum BatchStage : int {
+  BS_SCHUR, BS_SCHUR_REDUCE, BS_GRAM, BS_GRAM_REDUCE, BS_XFORM0, BS_XFORM1, BS_STEP0, BS_XFORM2, BS_PROJ0,
+  BS_PROJ1, BS_LU, BS_PANELS, BS_COUNT
+};
+// Appends the (kernel, entry) pairs one problem contributes to a stage: buf / aux
+// are its work space and stride (Gram partials, eigen-solver, projection temp or
+// LU scratch), i0 its largest eliminated dimension (Step 0, LU); the grids follow
+// the single-problem launchers.
+void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, double2* buf,
+                         int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out);
 
 // Generic host-resolved batched GEMM task: C (op)= op(A) op(B).
 struct GemmTask {

@@ -102,3 +102,33 @@ def test_cube32_free_ranks_against_oracle():
                 bad.append(("kt", key, got[key][1], kt, flo, fhi))
     assert not bad, bad[:5]
     assert same_k >= len(rk) - 8
+
+
+def test_cube32_mixed_form_against_oracle():
+    """The mixed form on the 32^3 workload, ranks pinned to the oracle's: part of the
+    Schur flops go through the FP32 branch (the ledger's routed fraction is above 0),
+    the unrefined solve differs from the FP64 oracle's M^-1 b by that branch's
+    rounding only, and refinement against the FP64 H^2 matrix reaches the oracle's
+    refined solution."""
+    torch = _torch()
+    d, rk, rkt = _fixture()
+    pr = I.config(1)
+    keys = sorted(rk, key=lambda lt: (-lt[0], lt[1]))
+    forced = np.array([(l, t, rk[(l, t)][0], rkt[(l, t)][0] if (l, t) in rkt else -1) for l, t in keys],
+                      dtype=np.int32)
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=forced,
+              precision="mixed").factor()
+    try:
+        frac = G.kernel_ledger()["schur_fp32_flop_frac"]
+        b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
+        x = G.solve(b).cpu().numpy()
+        nx = float(np.linalg.norm(x - d["x"]) / np.linalg.norm(d["x"]))
+        xr, info = G.solve(b, tol=1e-12, max_iter=30, info=True)
+        er = _maxrel(xr.cpu().numpy(), d["x_refined"])
+        print(f"32^3 mixed vs oracle: FP32 fraction of Schur flops {frac:.3f}, unrefined x {nx:.2e} norm-wise, "
+              f"refined x {er:.2e} after {info['iterations']} iterations")
+        assert frac > 0.1
+        assert nx < 1e-4
+        assert info["rel_residual"] <= 1e-12 and er < 1e-8
+    finally:
+        G.close()

@@ -34,6 +34,7 @@ def test_every_stop_level_matches_oracle(grid, leaf, eps):
     H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
     S = H.S
     g = np.random.default_rng(6).standard_normal((pr.n, 2)) + 0.5j
+    g6 = np.random.default_rng(7).standard_normal((pr.n, 6)) + 1j * np.random.default_rng(8).standard_normal((pr.n, 6))
     for ls in range(S.l0, S.L + 1):
         print(f"early stop: grid {grid}, leaf {leaf}, stop level {ls} of [{S.l0}, {S.L}]", flush=True)
         Fz = O.factor(H, stop_level=ls)
@@ -48,6 +49,12 @@ def test_every_stop_level_matches_oracle(grid, leaf, eps):
             assert _maxrel(x, O.solve(Fz, pr.rhs)) < 1e-10
             lam = G.solve_adjoint(torch.from_numpy(g)).cpu().numpy()
             assert _maxrel(lam, O.solve_adjoint(Fz, g)) < 1e-10
+            # more right-hand sides than the matrix-vector sweeps take: the final
+            # block is solved by matrix-core GEMM steps
+            x6 = G.solve(torch.from_numpy(g6)).cpu().numpy()
+            assert _maxrel(x6, O.solve(Fz, g6)) < 1e-10
+            lam6 = G.solve_adjoint(torch.from_numpy(g6)).cpu().numpy()
+            assert _maxrel(lam6, O.solve_adjoint(Fz, g6)) < 1e-10
         finally:
             G.close()
 

@@ -175,13 +175,15 @@ def copy_calibration(torch):
 def batch_leg(torch, h2, I, chunk: int) -> dict:
     """Independent box problems (sides U{12..32} cells, leaf 48, eps 1e-4, 16 plane-wave
     right-hand sides each): factor + 16-RHS solve refined to 1e-8, one problem at a time
-    in FP64 versus batched (h2_factor_batch / h2_solve_batch, graph-replayed sweeps) in
-    FP64 and in the mixed form, in chunks of `chunk` problems whose handles are released
-    after their solve.  Every run reports the largest final residual over the problems."""
+    in FP64 versus batched (h2_factor_batch_mode / h2_solve_batch, graph-replayed sweeps):
+    fused launches across problems in FP64 and in the mixed form, and one stream per
+    problem in FP64, in chunks of `chunk` problems whose handles are released after their
+    solve.  Every run reports the largest final residual over the problems."""
     probs = I.batch_problems(count=64, nrhs=16)
     n_total = sum(pr.n for pr in probs)
 
-    def run(batched: bool, precision: str) -> tuple:
+    def run(mode, precision: str) -> tuple:
+        batched = mode is not None
         elapsed, worst, iters = 0.0, 0.0, 0
         for c0 in range(0, len(probs), chunk):
             part = probs[c0:c0 + chunk]
@@ -193,7 +195,7 @@ def batch_leg(torch, h2, I, chunk: int) -> dict:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if batched:
-                h2.factor_batch(hs)
+                h2.factor_batch(hs, mode=mode)
                 _, infos = h2.solve_batch(hs, rhs, tol=1e-8, max_iter=20, info=True)
             else:
                 infos = []
@@ -212,17 +214,21 @@ def batch_leg(torch, h2, I, chunk: int) -> dict:
             torch.cuda.empty_cache()
         return elapsed, worst, iters
 
-    t_seq, r_seq, it_seq = run(False, "fp64")
-    t_bat, r_bat, it_bat = run(True, "fp64")
-    t_mix, r_mix, it_mix = run(True, "mixed")
+    t_seq, r_seq, it_seq = run(None, "fp64")
+    t_bat, r_bat, it_bat = run("fused", "fp64")
+    t_str, r_str, it_str = run("streams", "fp64")
+    t_mix, r_mix, it_mix = run("fused", "mixed")
     return {"workload": "64 box problems, sides U{12..32}, leaf 48, eps 1e-4, 16 RHS each, refined to 1e-8",
             "unknowns": n_total, "chunk": chunk, "sequential_s": t_seq, "batched_s": t_bat,
             "sequential_unknowns_per_s": n_total / t_seq, "batched_unknowns_per_s": n_total / t_bat,
             "speedup": t_seq / t_bat,
+            "batched_streams_s": t_str, "batched_streams_unknowns_per_s": n_total / t_str,
             "batched_mixed_s": t_mix, "batched_mixed_unknowns_per_s": n_total / t_mix,
             "mixed_batched_vs_fp64_sequential": t_seq / t_mix, "mixed_batched_vs_fp64_batched": t_bat / t_mix,
-            "max_rel_residual": {"fp64_sequential": r_seq, "fp64_batched": r_bat, "mixed_batched": r_mix},
-            "max_refine_iterations": {"fp64_sequential": it_seq, "fp64_batched": it_bat, "mixed_batched": it_mix}}
+            "max_rel_residual": {"fp64_sequential": r_seq, "fp64_batched": r_bat, "fp64_streams": r_str,
+                                 "mixed_batched": r_mix},
+            "max_refine_iterations": {"fp64_sequential": it_seq, "fp64_batched": it_bat, "fp64_streams": it_str,
+                                      "mixed_batched": it_mix}}
 
 
 def median_ms(torch, fn, reps: int = 5) -> float:
@@ -336,16 +342,17 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     print(f"# build {g}^3 {build_s:.2f} s (setup, untimed)", file=sys.stderr, flush=True)
-    # setup, untimed: the stop level (Sec. III-C early stop) chosen by measurement
+    # setup, untimed: the stop level (Sec. III-C early stop) and the per-level Schur split
+    # thresholds chosen by measurement (h2_tune)
     t0 = time.perf_counter()
     if args.stop_level:
         G.set_stop_level(args.stop_level)
-        stop, stop_ms = args.stop_level, {}
+        tuning = {"stop_level": args.stop_level, "source": "--stop-level"}
     else:
-        stop, stop_ms = G.tune_stop_level(max_final=16384)
+        tuning = G.tune(max_final=16384)
+    stop = tuning["stop_level"]
     tune_s = time.perf_counter() - t0
-    print(f"# stop level {stop} ({ {k: round(v, 1) for k, v in stop_ms.items()} } ms), tuned in {tune_s:.1f} s",
-          file=sys.stderr, flush=True)
+    print(f"# tuning {tuning}, {tune_s:.1f} s", file=sys.stderr, flush=True)
     b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
     B64 = torch.from_numpy(I.plane_waves(pr.points, I.directions(64, 3))).cuda()
     forms = [f for f in args.forms.split(",") if f]
@@ -376,7 +383,7 @@ def main():
         "config": {"workload": f"VIE cube grid {g}^3 (N={pr.n}), leaf 64, eta 1, eps 1e-4, "
                                f"factor + 1 RHS refined to 1e-8; value = the faster form ({hf})",
                    "N": pr.n, "leaf": 64, "eta": 1.0, "eps": 1e-4, "precision": hf, "build_s": build_s,
-                   "stop_level": stop, "stop_level_factor_ms": stop_ms, "stop_level_tuning_s": tune_s},
+                   "stop_level": stop, "tuning": tuning, "tuning_s": tune_s},
         "factor_ms": head["factor_ms"],
         "factor_unknowns_per_s": head["factor_unknowns_per_s"],
         "solve_ms_refined_1e-8": head["solve_ms_refined_1e-8"],
@@ -395,7 +402,7 @@ def main():
     if not args.no_cube32 and g != 32:
         p32 = I.make_problem("cube32", (32, 32, 32), 64, 1e-4)
         G32 = h2.H2(p32.points, p32.k, p32.h, p32.chi, p32.leaf, p32.eta, p32.eps)
-        stop32, stop32_ms = G32.tune_stop_level(max_final=16384)
+        tune32 = G32.tune(max_final=16384)
         b32 = torch.from_numpy(p32.rhs[:, 0].copy()).cuda()
         B32 = torch.from_numpy(I.plane_waves(p32.points, I.directions(64, 3))).cuda()
         leg32 = form_leg(torch, G32, p32, "fp64", max(args.steps, 3), 1, b32, B32, "32^3")
@@ -403,8 +410,8 @@ def main():
         leg32.pop("_schur_ms")
         leg32.pop("kernel_roofline")
         leg32["workload"] = "VIE cube grid 32^3 (N=32768), leaf 64, eta 1, eps 1e-4, FP64, factor + 1 RHS refined"
-        leg32["stop_level"] = stop32
-        leg32["stop_level_factor_ms"] = stop32_ms
+        leg32["stop_level"] = tune32["stop_level"]
+        leg32["tuning"] = tune32
         out["cube32"] = leg32
         G32.close()
         del G32

@@ -139,6 +139,40 @@ h2_status h2_set_sweep_graph(h2_handle H, int32_t enable);
  * h2_options.stop_level; 0 = l0).  The handle becomes unfactored. */
 h2_status h2_set_stop_level(h2_handle H, int32_t level);
 
+/* Schur flush splitting at a level (level = -1: every level): a colour's flush
+ * whose tasks, kept whole, would make fewer than below_wgs 64 x 64 tile
+ * workgroups splits every task of more than 10 terms into chunks (partial
+ * tiles summed in a fixed order by a second kernel); a larger flush keeps
+ * every task whole.  below_wgs = -1 restores the default (8192), 0 never
+ * splits.  The choice depends on sizes only, so results stay deterministic for
+ * given settings; it changes the order in which a block's updates are summed,
+ * hence the rounding.  The handle becomes unfactored. */
+h2_status h2_set_schur_split(h2_handle H, int32_t level, int64_t below_wgs);
+
+#define H2_TUNING_MAX_LEVELS 64
+
+/* Measured settings of a handle (h2_tune). */
+typedef struct h2_tuning {
+  int32_t stop_level;        /* chosen stop level (0 when no block is admissible) */
+  int32_t from_cache;        /* 1: taken from the process-wide cache, only the final factorization ran */
+  int64_t split_below[H2_TUNING_MAX_LEVELS]; /* per level l: the Schur split threshold (-1: not factored) */
+  double factor_ms;          /* factorization time with the chosen settings */
+} h2_tuning;
+
+/* Autotuner: chooses the stop level (as h2_tune_stop_level, with the default
+ * split rule) and then, per factored level, the Schur split threshold among
+ * {0, 2048, 8192, 32768, unlimited} by one factorization per candidate (the
+ * candidate on every level at once; each level keeps the candidate under which
+ * its own time was lowest).  The result is stored in a process-wide cache
+ * keyed by the cluster tree (every cluster's size), eta, eps, the form, the
+ * forced ranks and max_final; a later call on any handle with the same key
+ * applies the cached settings and factors once.  The handle is left factored
+ * with the chosen settings.  Synchronises the stream.  Thread-safe. */
+h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h2_tuning* out);
+
+/* Empty the autotuner's cache. */
+h2_status h2_tune_cache_clear(void);
+
 /* The stop level in force (*level = 0 when no block is admissible). */
 h2_status h2_stop_level(h2_handle H, int32_t* level);
 
@@ -211,18 +245,38 @@ h2_status h2_contrast_gradient(h2_handle H, const void* x, const void* g, const 
 h2_status h2_matvec(h2_handle H, const void* x, void* y, int32_t nrhs, int64_t ld,
                     int32_t conj_transpose, void* hip_stream);
 
-/* Factor `count` independent handles together.  Each handle works on a stream
- * of its own (default priority, created on first use) and up to eight host
- * threads drive them, so that the small launches of many problems fill the
- * device side by side; all of them start after the work already queued on
- * hip_stream, and hip_stream waits for all of them.  Handles must be distinct.
- * Returns the first failure ("batch item k: ..."); the other items are still
- * factored. */
+/* Factor `count` independent handles together (h2_factor_batch_mode with
+ * H2_BATCH_FUSED). */
 h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream);
+
+/* Batch schedules of h2_factor_batch_mode. */
+#define H2_BATCH_FUSED 0   /* one launch per (level step, colour index, stage) for all problems */
+#define H2_BATCH_STREAMS 1 /* one stream per handle, driven by up to eight host threads */
+
+/* Factor `count` independent handles together; each handle's factors are
+ * bit-identical to those of h2_factor.  Handles must be distinct; each may use
+ * its own precision, stop level, forced ranks and allocator.
+ * H2_BATCH_FUSED: the problems advance in lockstep, level by level from each
+ *   one's finest level (Alg. 1), on hip_stream; every stage of colour index c
+ *   (Schur flush, Step 0 Gram and eigenvectors, projections, partial LU,
+ *   panels) is a single launch whose workgroups cover the work items of every
+ *   problem that has colour c (problems whose sizes select another kernel
+ *   variant go to a second launch of that variant).  Host synchronisation: once
+ *   per level step for all problems.  Timings of the handles (h2_timing,
+ *   h2_level_timing) then cover the whole batch up to that handle's end, and
+ *   per-kernel times are not measured.  The shared launches' work item table
+ *   lives in hs[0] (allocated through its allocator, kept for later batches).
+ * H2_BATCH_STREAMS: each handle works on a stream of its own (default
+ *   priority, created on first use) and up to eight host threads drive them;
+ *   all start after the work already queued on hip_stream, and hip_stream
+ *   waits for all of them.
+ * Returns the first failure ("batch item k: ..."); the other items are still
+ * factored.  H2_ERR_ARG for an unknown mode. */
+h2_status h2_factor_batch_mode(h2_handle* hs, int32_t count, void* hip_stream, int32_t mode);
 
 /* x[k] = M_k^-1 b[k] for every handle k as h2_solve does (nrhs columns,
  * leading dimension ld[k], refinement to tol when tol > 0, infos[k] when infos
- * is not NULL), concurrently in the manner of h2_factor_batch.  b[k], x[k] are
+ * is not NULL), concurrently in the manner of H2_BATCH_STREAMS.  b[k], x[k] are
  * device pointers; b[k] and x[k] may alias. */
 h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
                          const int64_t* ld, double tol, int32_t max_iter, void* hip_stream, h2_solve_info* infos);

@@ -22,6 +22,7 @@ H2_OK, H2_ERR_ARG, H2_ERR_OOM, H2_ERR_SINGULAR, H2_ERR_STATE, H2_ERR_DEVICE, H2_
 STATUS_NAMES = ["H2_OK", "H2_ERR_ARG", "H2_ERR_OOM", "H2_ERR_SINGULAR", "H2_ERR_STATE", "H2_ERR_DEVICE",
                 "H2_ERR_NOCONV", "H2_ERR_INTERNAL"]
 H2_FP64, H2_MIXED = 0, 1
+H2_BATCH_FUSED, H2_BATCH_STREAMS = 0, 1
 
 
 class H2Error(RuntimeError):
@@ -67,6 +68,14 @@ class SolveInfo(ctypes.Structure):
                 ("rel_residual_first", ctypes.c_double)]
 
 
+TUNING_MAX_LEVELS = 64
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("stop_level", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("split_below", ctypes.c_int64 * TUNING_MAX_LEVELS), ("factor_ms", ctypes.c_double)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -94,6 +103,7 @@ def lib():
         L.h2_set_precision.argtypes = [_P, ctypes.c_int32]
         L.h2_set_sweep_graph.argtypes = [_P, ctypes.c_int32]
         L.h2_factor_batch.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, _P]
+        L.h2_factor_batch_mode.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_int32]
         L.h2_solve_batch.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                      ctypes.c_int32, _I64P, ctypes.c_double, ctypes.c_int32, _P,
                                      ctypes.POINTER(SolveInfo)]
@@ -113,11 +123,16 @@ def lib():
         L.h2_set_stop_level.argtypes = [_P, ctypes.c_int32]
         L.h2_stop_level.argtypes = [_P, _I32P]
         L.h2_tune_stop_level.argtypes = [_P, ctypes.c_int64, _P, _I32P, _DP, ctypes.c_int32]
+        L.h2_set_schur_split.argtypes = [_P, ctypes.c_int32, ctypes.c_int64]
+        L.h2_tune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(Tuning)]
+        L.h2_tune_cache_clear.argtypes = []
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
+                     "h2_factor_batch_mode",
                      "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing",
-                     "h2_solve_noalloc", "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level"):
+                     "h2_solve_noalloc", "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level",
+                     "h2_set_schur_split", "h2_tune", "h2_tune_cache_clear"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -265,6 +280,21 @@ class H2:
         base = self.stop_level_range()[0]
         return chosen.value, {base + e: float(t) for e, t in enumerate(ms) if t >= 0}
 
+    def set_schur_split(self, below_wgs: int, level: int = -1):
+        """Schur flush split threshold in workgroups at `level` (-1: every level; below_wgs -1:
+        the default, 0: never split) (h2_set_schur_split)."""
+        _check(lib().h2_set_schur_split(self._h, int(level), int(below_wgs)), "h2_set_schur_split")
+        return self
+
+    def tune(self, max_final: int = 12288, stream=None) -> dict:
+        """Autotune the stop level and the per-level Schur split threshold (h2_tune, cached per
+        problem structure); leaves the handle factored with the chosen settings."""
+        t = Tuning()
+        _check(lib().h2_tune(self._h, int(max_final), _stream_ptr(stream), ctypes.byref(t)), "h2_tune")
+        split = {l: int(v) for l, v in enumerate(t.split_below) if v >= 0}
+        return {"stop_level": t.stop_level, "from_cache": bool(t.from_cache), "split_below": split,
+                "factor_ms": t.factor_ms}
+
     def stop_level_range(self):
         """(l0, L) of the handle's block tree."""
         st = structure(self._points, self.h, self.leaf, self.eta)
@@ -403,10 +433,20 @@ def forced_ranks_from_oracle(construct_ranks: dict, factor_ranks: dict) -> np.nd
     return np.asarray(rows, dtype=np.int32).reshape(-1, 4)
 
 
-def factor_batch(solvers, stream=None):
-    """Factor several independent :class:`H2` handles together (h2_factor_batch)."""
+def tune_cache_clear():
+    """Empty the autotuner's process-wide cache (h2_tune_cache_clear)."""
+    _check(lib().h2_tune_cache_clear(), "h2_tune_cache_clear")
+
+
+def factor_batch(solvers, stream=None, mode="fused"):
+    """Factor several independent :class:`H2` handles together (h2_factor_batch_mode):
+    mode "fused" launches each colour stage once for all problems, "streams" gives each
+    handle a stream of its own."""
+    modes = {"fused": H2_BATCH_FUSED, "streams": H2_BATCH_STREAMS}
+    if mode not in modes:
+        raise ValueError(f"mode must be one of {sorted(modes)}")
     arr = (_P * len(solvers))(*[sv._h.value for sv in solvers])
-    _check(lib().h2_factor_batch(arr, len(solvers), _stream_ptr(stream)), "h2_factor_batch")
+    _check(lib().h2_factor_batch_mode(arr, len(solvers), _stream_ptr(stream), modes[mode]), "h2_factor_batch_mode")
     return solvers
 
 

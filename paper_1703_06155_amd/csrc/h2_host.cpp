@@ -173,6 +173,71 @@ struct DArr {
   }
 };
 
+// Small host arrays of one factorization step (offsets, sizes, task lists) gathered
+// in one pinned buffer, copied to the device at once and spread to their arrays by
+// one kernel: no host wait per array.  Owned by a handle, grown on demand.  The
+// pinned buffer is rewritten only after the copy out of it has finished.
+struct Stager {
+  std::vector<char> buf;
+  std::vector<CopySeg> segs;
+  char* host = nullptr;
+  size_t host_cap = 0;
+  DArr<char> dev;
+  hipEvent_t copied = nullptr;
+  Stager() = default;
+  Stager(const Stager&) = delete;
+  Stager& operator=(const Stager&) = delete;
+  ~Stager() {
+    if (copied) {
+      (void)hipEventSynchronize(copied);
+      (void)hipEventDestroy(copied);
+    }
+    if (host) (void)hipHostFree(host);
+  }
+  static size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+  // d is sized for v now; its contents arrive with the next flush()
+  template <typename T>
+  void put(DArr<T>& d, const std::vector<T>& v) {
+    static_assert(sizeof(T) % 4 == 0, "staged elements are whole 4-byte words");
+    d.alloc(v.size());
+    if (v.empty()) return;
+    const size_t off = align16(buf.size()), bytes = v.size() * sizeof(T);
+    if (reinterpret_cast<uintptr_t>(d.p) % 16 != 0) fail(H2_ERR_INTERNAL, "staged device array not 16-byte aligned");
+    buf.resize(off + bytes);
+    std::memcpy(buf.data() + off, v.data(), bytes);
+    for (size_t o = 0; o < bytes; o += STAGE_PIECE)
+      segs.push_back({(int64_t)(off + o), (int64_t)std::min<size_t>(STAGE_PIECE, bytes - o),
+                      reinterpret_cast<char*>(d.p) + o});
+  }
+  void flush(hipStream_t st) {
+    if (segs.empty()) return;
+    const size_t toff = align16(buf.size()), total = toff + segs.size() * sizeof(CopySeg);
+    buf.resize(total);
+    std::memcpy(buf.data() + toff, segs.data(), segs.size() * sizeof(CopySeg));
+    if (copied) HIPCHK(hipEventSynchronize(copied));
+    else HIPCHK(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+    if (total > host_cap) {
+      if (host) HIPCHK(hipHostFree(host));
+      host = nullptr;
+      host_cap = 0;
+      const size_t cap = std::max(total, (size_t)1 << 20);
+      if (hipHostMalloc((void**)&host, cap, hipHostMallocDefault) != hipSuccess || !host) {
+        host = nullptr;
+        (void)hipGetLastError();
+        fail(H2_ERR_OOM, "pinned host allocation of " + std::to_string(cap) + " bytes failed");
+      }
+      host_cap = cap;
+    }
+    std::memcpy(host, buf.data(), total);
+    dev.alloc(total);
+    HIPCHK(hipMemcpyAsync(dev.p, host, total, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(copied, st));
+    launch_scatter_segments(dev.p, reinterpret_cast<const CopySeg*>(dev.p + toff), (int)segs.size(), st);
+    buf.clear();
+    segs.clear();
+  }
+};
+
 // ---------------------------------------------------------------------------
 // plans
 // ---------------------------------------------------------------------------
@@ -338,9 +403,12 @@ struct h2_ctx {
   h2::DArr<int32_t> lv_k1, lv_k2, lv_off1; // per-level uploads of factor_impl
   h2::DArr<int64_t> lv_toff, lv_so, lv_do, lv_len;
   int stop = -1;                           // last factored level (l0 unless stopped early, Sec. III-C)
+  std::vector<int64_t> split_below;        // per level: Schur flush split threshold in workgroups (-1: default)
   h2::DArr<double2> fb_X, fb_Y;            // early stop: expanded bases and their products with couplings
   h2::DArr<int32_t> fb_n, fb_k, fb_k1, fb_k2, fb_off1;
   h2::DArr<int64_t> fb_toff, fb_xoff;
+  h2::DArr<h2::BatchEntry> batch_entries;  // work items of shared launches when this handle leads a batch
+  h2::Stager stage;                        // per-level host arrays on their way to the device
   std::vector<std::vector<int64_t>> stats_rows;
   std::vector<double> level_ms;            // per stats row: ms of that level (Steps 0-3 and its merge) / final LU
 };
@@ -1158,6 +1226,11 @@ static float elapsed(hipEvent_t a, hipEvent_t b) {
 static void dense_lu_factor(h2_ctx* H, hipStream_t st);
 
 constexpr size_t SCHUR_PART_MAX_BYTES = size_t(8) << 30;
+// A colour's Schur flush whose whole tasks make fewer 64 x 64 tile workgroups than
+// this splits its long tasks into chunks of SCHUR_CHUNK_TERMS terms (more
+// workgroups for a small flush); a larger flush fills the device with whole tasks
+// and spares the partial tiles' traffic.  Per level, h2_set_schur_split / h2_tune.
+constexpr int64_t SCHUR_SPLIT_BELOW = 8192;
 
 static void release_factor_buffers(h2_ctx* H) {
   H->flev.clear();
@@ -1332,79 +1405,108 @@ static void add_far_blocks(h2_ctx* H, int ls, const std::vector<int32_t>& n_par,
   run_gemms(H, t2, st);
 }
 
-static void factor_impl(h2_ctx* H, hipStream_t st) {
-  const Structure& S = H->S;
-  const int L = S.L, l0 = S.l0;
-  H->factored = false;
-  // buffers of the previous factorization are reused; nothing of it may still run
-  HIPCHK(hipStreamSynchronize(st));
+// One factorization in progress (Alg. 1: per level, Steps 0-3 colour by colour,
+// eqs. 16-31, then the merge into the parent level, eq. 23; the matrix left at
+// the stop level is factored densely, Sec. III-C).  A single problem drives it
+// level by level; a batch drives several in lockstep and launches each colour's
+// kernels once for all of them (factor_fused).
+struct FactorRun {
+  h2_ctx* H;
+  hipStream_t st;
+  const Structure& S;
+  int L, l0, ls = 0, l = 0, j = 0;
+  bool own_memory, ktime, mixed, done = false;
+  EventPool ev;
+  std::vector<std::array<hipEvent_t, 4>> phase_ev;
+  // per-kernel intervals when kernel timing is on: {begin, end, family}
+  std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> kern_ev;
+  hipEvent_t t_begin = nullptr, e_level = nullptr, e_m0 = nullptr, e_m1 = nullptr;
+  std::vector<int32_t> n_cur, kk, n_par, off1;
+  std::vector<MergeTask> mt;  // kept until the merge's synchronisation
+  int dmax = 1;
+  int64_t gram_pstride = 0;
+  bool split_ok = false;
+  int64_t split_below = SCHUR_SPLIT_BELOW;
+  int32_t flags[4] = {0, 0, 0, 0};
+
   // With the library's own hipMalloc: when device memory is short, start from nothing
   // rather than from the previous factorization's buffers (its factors would sit beside
   // the new arenas).  A caller's allocator keeps what the library frees in its own cache
   // (so the device's free memory says nothing about it) and frees that cache itself when
   // an allocation fails: the handle keeps its buffers.
-  const bool own_memory = !(H->allocator.alloc && H->allocator.free);
-  auto memory_short = [&]() {
+  bool memory_short() const {
     size_t fr = 0, tot = 0;
     return own_memory && hipMemGetInfo(&fr, &tot) == hipSuccess && (double)fr < 0.35 * (double)tot;
-  };
-  if (memory_short()) release_factor_buffers(H);
-  H->vbuf_nrhs = 0;  // level sizes may change with the ranks: resize the sweep buffers
-  H->drop_graphs();
-  H->timing.assign(6, 0.0);
-  H->stats_rows.clear();
-  H->level_ms.clear();
-  H->merge_elems = 0;
-  H->kernel_ms.assign(8, -1.0);
-  EventPool ev;
-  std::vector<std::array<hipEvent_t, 4>> phase_ev;
-  // per-kernel intervals when kernel timing is on: {begin, end, family}
-  std::vector<std::tuple<hipEvent_t, hipEvent_t, int>> kern_ev;
-  const bool ktime = H->kernel_timing;
-  const bool mixed = H->precision == H2_MIXED;
-  hipEvent_t t_begin = ev.next(st);
-  if (l0 < 0) {
-    // no admissible block anywhere: LU of the whole matrix
-    H->nf = H->N;
-    H->Zf.alloc((size_t)H->N * H->N);
-    launch_zero(H->Zf.p, H->N * H->N, st);
-    const auto& nl = S.near[L];
-    for (size_t e = 0; e < nl.size(); ++e) {
-      const int a = nl[e].first, b = nl[e].second;
-      HIPCHK(hipMemcpy2DAsync(H->Zf.p + S.start[L][a] + S.start[L][b] * H->N, H->N * sizeof(double2),
-                              H->near_orig.p + H->near_off[e], S.size[L][a] * sizeof(double2),
-                              S.size[L][a] * sizeof(double2), S.size[L][b], hipMemcpyDeviceToDevice, st));
-    }
-    hipEvent_t t_m = ev.next(st);
-    dense_lu_factor(H, st);
-    hipEvent_t t_end = ev.next(st);
-    HIPCHK(hipStreamSynchronize(st));
-    H->timing[0] = elapsed(t_begin, t_end);
-    H->timing[5] = elapsed(t_m, t_end);
-    for (int f = 0; f < 7; ++f) H->kernel_ms[f] = 0.0;
-    H->kernel_ms[7] = H->timing[5];
-    H->ledger_valid = false;
-    H->factored = true;
-    return;
   }
-  const int ls = H->stop;  // last factored level; the matrix merged to level ls - 1 is factored densely
-  const int nlev = L - ls + 1;
-  H->flev.resize(nlev);
-  // block arenas of consecutive levels alternate between two handle-owned buffers
-  std::vector<int32_t> n_cur(S.nclusters(L));
-  for (int t = 0; t < S.nclusters(L); ++t) n_cur[t] = (int32_t)S.size[L][t];
-  for (int l = L; l >= ls; --l) {
-    const int j = L - l;
+  bool level_pending() const { return !done && l >= ls; }
+  LevelPlan& plan() { return H->plans[j]; }
+  FactorLevel& flev() { return H->flev[j]; }
+
+  FactorRun(h2_ctx* h, hipStream_t s)
+      : H(h), st(s), S(h->S), L(h->S.L), l0(h->S.l0), own_memory(!(h->allocator.alloc && h->allocator.free)),
+        ktime(h->kernel_timing), mixed(h->precision == H2_MIXED) {
+    H->factored = false;
+    // buffers of the previous factorization are reused; nothing of it may still run
+    HIPCHK(hipStreamSynchronize(st));
+    if (memory_short()) release_factor_buffers(H);
+    H->vbuf_nrhs = 0;  // level sizes may change with the ranks: resize the sweep buffers
+    H->drop_graphs();
+    H->timing.assign(6, 0.0);
+    H->stats_rows.clear();
+    H->level_ms.clear();
+    H->merge_elems = 0;
+    H->kernel_ms.assign(8, -1.0);
+    t_begin = ev.next(st);
+    if (l0 < 0) {
+      // no admissible block anywhere: LU of the whole matrix
+      H->nf = H->N;
+      H->Zf.alloc((size_t)H->N * H->N);
+      launch_zero(H->Zf.p, H->N * H->N, st);
+      const auto& nl = S.near[L];
+      for (size_t e = 0; e < nl.size(); ++e) {
+        const int a = nl[e].first, b = nl[e].second;
+        HIPCHK(hipMemcpy2DAsync(H->Zf.p + S.start[L][a] + S.start[L][b] * H->N, H->N * sizeof(double2),
+                                H->near_orig.p + H->near_off[e], S.size[L][a] * sizeof(double2),
+                                S.size[L][a] * sizeof(double2), S.size[L][b], hipMemcpyDeviceToDevice, st));
+      }
+      hipEvent_t t_m = ev.next(st);
+      dense_lu_factor(H, st);
+      hipEvent_t t_end = ev.next(st);
+      HIPCHK(hipStreamSynchronize(st));
+      H->timing[0] = elapsed(t_begin, t_end);
+      H->timing[5] = elapsed(t_m, t_end);
+      for (int f = 0; f < 7; ++f) H->kernel_ms[f] = 0.0;
+      H->kernel_ms[7] = H->timing[5];
+      H->ledger_valid = false;
+      H->factored = true;
+      done = true;
+      return;
+    }
+    ls = H->stop;  // last factored level; the matrix merged to level ls - 1 is factored densely
+    H->flev.resize(L - ls + 1);
+    // block arenas of consecutive levels alternate between two handle-owned buffers
+    n_cur.resize(S.nclusters(L));
+    for (int t = 0; t < S.nclusters(L); ++t) n_cur[t] = (int32_t)S.size[L][t];
+    l = L;
+  }
+
+  // Level l: sizes, offsets and work space, the blocks of the level (leaf blocks
+  // or the merged parent blocks), the parent bases (eq. 23) and the complements
+  // B_perp of every cluster (Step 0 starts from them).
+  void level_begin() {
+    j = L - l;
+    split_below = (l < (int)H->split_below.size() && H->split_below[l] >= 0) ? H->split_below[l] : SCHUR_SPLIT_BELOW;
     LevelPlan& P = H->plans[j];
     BuildLevel& Bd = H->build[j];
     FactorLevel& F = H->flev[j];
     const int nc = P.nc;
-    hipEvent_t e_level = ev.next(st);
+    e_level = ev.next(st);
     F.n = n_cur;
-    std::vector<int32_t> kk(Bd.k.begin(), Bd.k.end());
+    kk.assign(Bd.k.begin(), Bd.k.end());
     for (int t = 0; t < nc; ++t)
       if (!P.nonempty[t]) kk[t] = 0;
-    int nmax = 0, dmax = 1;
+    int nmax = 0;
+    dmax = 1;
     for (int t = 0; t < nc; ++t) {
       nmax = std::max(nmax, F.n[t]);
       if (F.n[t] < kk[t]) fail(H2_ERR_INTERNAL, "basis wider than its cluster");
@@ -1450,7 +1552,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         const int s = C.pj_slot[e];
         o += (int64_t)F.n[P.slot_a[s]] * F.n[P.slot_b[s]];
       }
-      C.d_pj_toff.upload(C.pj_toff, st);
+      H->stage.put(C.d_pj_toff, C.pj_toff);
       temp_max = std::max(temp_max, o);
     }
     F.ntot = 0;
@@ -1458,27 +1560,28 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     for (int i = 0; i < nc; ++i) F.voff[i + 1] = F.voff[i] + F.n[i];
     F.ntot = F.voff[nc];
     // device arrays
-    F.d_n.upload(F.n, st);
-    F.d_k.upload(kk, st);
-    F.d_kt.upload(kk, st);
+    Stager& sg = H->stage;
+    sg.put(F.d_n, F.n);
+    sg.put(F.d_k, kk);
+    sg.put(F.d_kt, kk);
     {
       std::vector<int32_t> fk(nc, -1);
       if (H->has_forced)
         for (int i = 0; i < nc; ++i) fk[i] = H->forced_kt[H->lvl_base[l] + i];
-      F.d_forced.upload(fk, st);
+      sg.put(F.d_forced, fk);
     }
-    F.d_np_off.upload(np_off, st);
-    F.d_prow.upload(prow, st);
-    F.d_flags.upload(std::vector<int32_t>(4, 0), st);
-    F.d_slot_off.upload(slot_off, st);
-    F.d_q_off.upload(q_off, st);
-    F.d_b_off.upload(b_off, st);
-    F.d_bp_off.upload(bp_off, st);
-    F.d_lu_off.upload(lu_off, st);
-    F.d_cp_off.upload(cp_off, st);
-    F.d_rp_off.upload(cp_off, st);
-    F.d_w_off.upload(w_off, st);
-    F.d_voff.upload(F.voff, st);
+    sg.put(F.d_np_off, np_off);
+    sg.put(F.d_prow, prow);
+    sg.put(F.d_flags, std::vector<int32_t>(4, 0));
+    sg.put(F.d_slot_off, slot_off);
+    sg.put(F.d_q_off, q_off);
+    sg.put(F.d_b_off, b_off);
+    sg.put(F.d_bp_off, bp_off);
+    sg.put(F.d_lu_off, lu_off);
+    sg.put(F.d_cp_off, cp_off);
+    sg.put(F.d_rp_off, cp_off);
+    sg.put(F.d_w_off, w_off);
+    sg.put(F.d_voff, F.voff);
     F.d_margins.alloc(2 * nc);
     if (mixed) {
       F.d_pmax.alloc(2 * nc);
@@ -1502,7 +1605,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     int maxcl = 1;
     for (ColourPlan& C : P.cols) maxcl = std::max<int>(maxcl, (int)C.cl.size());
     lu_scr.alloc((size_t)maxcl * ((size_t)dmax * dmax + dmax) * (dmax > LU_LDS_MAX ? 1 : 0) + 1);  // k_lu beyond its LDS size
-    const int64_t gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
+    gram_pstride = (int64_t)maxcl * (F.tiles * 64) * (F.tiles * 64);
     gram_part.alloc((size_t)GRAM_SPLIT * gram_pstride);
     eig_scr.alloc((size_t)maxcl * 4 * dmax * dmax);
     // split Schur tasks: one 64 x 64 partial tile per (chunk, tile) when the level's
@@ -1526,33 +1629,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     int64_t max_tiles = group_bases(P.fin);
     for (ColourPlan& C : P.cols) max_tiles = std::max(max_tiles, group_bases(C));
     const size_t scp_elems = (size_t)std::max<int64_t>(1, max_tiles * 4096);
-    const bool split_ok = scp_elems * sizeof(double2) <= SCHUR_PART_MAX_BYTES;
+    split_ok = scp_elems * sizeof(double2) <= SCHUR_PART_MAX_BYTES;
     if (split_ok) {
       H->ws_scp.alloc(scp_elems);
-      P.fin.d_sc_gbase.upload(P.fin.sc_gbase, st);
-      for (ColourPlan& C : P.cols) C.d_sc_gbase.upload(C.sc_gbase, st);
+      sg.put(P.fin.d_sc_gbase, P.fin.sc_gbase);
+      for (ColourPlan& C : P.cols) sg.put(C.d_sc_gbase, C.sc_gbase);
     }
-    auto schur_lists = [&](const ColourPlan& C, ColourTasks& ct) {
-      if (split_ok) {
-        ct.sc_slot = C.d_sc_slot.p;
-        ct.sc_cptr = C.d_sc_cptr.p;
-        ct.sc_sp = C.d_sc_sp.p;
-        ct.nsc = (int)C.sc_slot.size();
-        ct.sc_gtask = C.d_sc_gtask.p;
-        ct.sc_gbase = C.d_sc_gbase.p;
-        ct.ngrp = C.ngrp;
-        ct.sc_part = H->ws_scp.p;
-      } else {
-        ct.sc_slot = C.d_sc_slot_u.p;
-        ct.sc_cptr = C.d_sc_cptr_u.p;
-        ct.sc_sp = C.d_sc_sp_u.p;
-        ct.nsc = (int)C.sc_slot_u.size();
-        ct.sc_gtask = nullptr;
-        ct.sc_gbase = nullptr;
-        ct.ngrp = 0;
-        ct.sc_part = nullptr;
-      }
-    };
     // blocks of this level
     if (l == L) {
       slots.alloc(slot_off[P.nslot]);
@@ -1568,12 +1650,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
         DArr<int64_t>& d_so = H->lv_so;
         DArr<int64_t>& d_do = H->lv_do;
         DArr<int64_t>& d_len = H->lv_len;
-        d_so.upload(so, st);
-        d_do.upload(dofs, st);
-        d_len.upload(len, st);
+        sg.put(d_so, so);
+        sg.put(d_do, dofs);
+        sg.put(d_len, len);
+        sg.flush(st);
         launch_copy_blocks(H->near_orig.p, d_so.p, slots.p, d_do.p, d_len.p, P.nnear, st);
         check_launch("near block copy");
-        HIPCHK(hipStreamSynchronize(st));
       }
       F.B.alloc(b_off[nc]);
       if (b_off[nc] > 0)
@@ -1593,11 +1675,12 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       DArr<int32_t>& d_k2 = H->lv_k2;
       DArr<int32_t>& d_off1 = H->lv_off1;
       DArr<int64_t>& d_toff = H->lv_toff;
-      d_k1.upload(k1, st);
-      d_k2.upload(k2, st);
-      d_off1.upload(off1, st);
-      d_toff.upload(toff, st);
+      sg.put(d_k1, k1);
+      sg.put(d_k2, k2);
+      sg.put(d_off1, off1);
+      sg.put(d_toff, toff);
       F.B.alloc(b_off[nc]);
+      sg.flush(st);
       launch_parent_basis(nc, F.d_n.p, F.d_k.p, d_k1.p, d_k2.p, d_off1.p, d_toff.p, Bd.basis.p, F.d_b_off.p, F.B.p,
                           st);
       check_launch("host.cpp:997");
@@ -1648,101 +1731,191 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     launch_householder_perp(v, nc, st);
     check_launch("host.cpp:1040");
     if (ktime) kern_ev.emplace_back(e_hp, ev.next(st), 1);
-    hipEvent_t e_lev0 = ev.next(st);
-    for (int c = 0; c < P.ncol; ++c) {
-      ColourPlan& C = P.cols[c];
-      ColourTasks ct{};
-      ct.cl = C.d_cl.p;
-      ct.ncl = (int)C.cl.size();
-      ct.pj_slot = C.d_pj_slot.p;
-      ct.pj_toff = C.d_pj_toff.p;
-      ct.npj = (int)C.pj_slot.size();
-      ct.sc_i = C.d_sc_i.p;
-      ct.sc_ja = C.d_sc_ja.p;
-      ct.sc_jb = C.d_sc_jb.p;
-      schur_lists(C, ct);
-      ct.pn_i = C.d_pn_i.p;
-      ct.pn_ja = C.d_pn_ja.p;
-      ct.npn = (int)C.pn_i.size();
-      ct.sv_cl = C.d_sv_cl.p;
-      ct.sv_cptr = C.d_sv_cptr.p;
-      ct.sv_i = C.d_sv_i.p;
-      ct.sv_ja = C.d_sv_ja.p;
-      ct.nsv = (int)C.sv_cl.size();
-      ct.colour = c - 1;  // the flush sees the blocks as they are before colour c
-      ct.tiles = F.tiles;
-      hipEvent_t es = ev.next(st);
-      launch_schur(v, ct, mixed, st);
-      check_launch("schur");
-      ct.colour = c;
-      hipEvent_t e0 = ev.next(st);
-      launch_gram_fill(v, ct, gram_part.p, gram_pstride, st);
-      check_launch("gram_fill");
-      hipEvent_t eg = ktime ? ev.next(st) : nullptr;
-      if (ktime) kern_ev.emplace_back(e0, eg, 0);
-      launch_xform(v, ct, 0, st);
-      launch_xform(v, ct, 1, st);
-      check_launch("xform");
-      launch_step0_eig(v, ct, eig_scr.p, dmax, st);
-      check_launch("step0_eig");
-      launch_xform(v, ct, 2, st);
-      hipEvent_t ex = ktime ? ev.next(st) : nullptr;
-      if (ktime) kern_ev.emplace_back(eg, ex, 1);
-      if (F.tiles == 1) {
-        launch_proj_fused(v, ct, mixed, st);
-      } else {
-        launch_proj(v, ct, temp.p, 0, mixed, st);
-        launch_proj(v, ct, temp.p, 1, mixed, st);
-      }
-      check_launch("projection");
-      hipEvent_t e1 = ev.next(st);
-      if (ktime) kern_ev.emplace_back(ex, e1, 2);
-      launch_lu(v, ct, lu_scr.p, dmax, st);
-      check_launch("lu");
-      hipEvent_t el = ktime ? ev.next(st) : nullptr;
-      launch_panels(v, ct, st);
-      check_launch("panels");
-      hipEvent_t e2 = ev.next(st);
-      if (ktime) {
-        kern_ev.emplace_back(e1, el, 3);
-        kern_ev.emplace_back(el, e2, 4);
-      }
-      phase_ev.push_back({es, e0, e1, e2});
+  }
+  void schur_lists(const ColourPlan& C, ColourTasks& ct) const {
+    const int64_t t = H->flev[j].tiles;
+    if (split_ok && C.ngrp > 0 && (int64_t)C.sc_slot_u.size() * t * t < split_below) {
+      ct.sc_slot = C.d_sc_slot.p;
+      ct.sc_cptr = C.d_sc_cptr.p;
+      ct.sc_sp = C.d_sc_sp.p;
+      ct.nsc = (int)C.sc_slot.size();
+      ct.sc_gtask = C.d_sc_gtask.p;
+      ct.sc_gbase = C.d_sc_gbase.p;
+      ct.ngrp = C.ngrp;
+      ct.sc_part = H->ws_scp.p;
+    } else {
+      ct.sc_slot = C.d_sc_slot_u.p;
+      ct.sc_cptr = C.d_sc_cptr_u.p;
+      ct.sc_sp = C.d_sc_sp_u.p;
+      ct.nsc = (int)C.sc_slot_u.size();
+      ct.sc_gtask = nullptr;
+      ct.sc_gbase = nullptr;
+      ct.ngrp = 0;
+      ct.sc_part = nullptr;
     }
-    {
-      // updates still pending at the end of the level
-      ColourTasks ct{};
-      ct.sc_i = P.fin.d_sc_i.p;
-      ct.sc_ja = P.fin.d_sc_ja.p;
-      ct.sc_jb = P.fin.d_sc_jb.p;
-      schur_lists(P.fin, ct);
-      ct.colour = P.ncol - 1;
-      ct.tiles = F.tiles;
-      hipEvent_t es = ev.next(st);
-      launch_schur(v, ct, mixed, st);
-      check_launch("schur");
-      hipEvent_t ee = ev.next(st);
-      phase_ev.push_back({es, ee, ee, ee});
+  }
+
+  // the task lists of colour c (ct.colour = c: Steps 0-3 of its clusters)
+  ColourTasks colour_tasks(int c) {
+    ColourPlan& C = plan().cols[c];
+    ColourTasks ct{};
+    ct.cl = C.d_cl.p;
+    ct.ncl = (int)C.cl.size();
+    ct.pj_slot = C.d_pj_slot.p;
+    ct.pj_toff = C.d_pj_toff.p;
+    ct.npj = (int)C.pj_slot.size();
+    ct.sc_i = C.d_sc_i.p;
+    ct.sc_ja = C.d_sc_ja.p;
+    ct.sc_jb = C.d_sc_jb.p;
+    schur_lists(C, ct);
+    ct.pn_i = C.d_pn_i.p;
+    ct.pn_ja = C.d_pn_ja.p;
+    ct.npn = (int)C.pn_i.size();
+    ct.sv_cl = C.d_sv_cl.p;
+    ct.sv_cptr = C.d_sv_cptr.p;
+    ct.sv_i = C.d_sv_i.p;
+    ct.sv_ja = C.d_sv_ja.p;
+    ct.nsv = (int)C.sv_cl.size();
+    ct.colour = c;
+    ct.tiles = flev().tiles;
+    return ct;
+  }
+
+  // the updates still pending at the end of the level
+  ColourTasks fin_tasks() {
+    LevelPlan& P = plan();
+    ColourTasks ct{};
+    ct.sc_i = P.fin.d_sc_i.p;
+    ct.sc_ja = P.fin.d_sc_ja.p;
+    ct.sc_jb = P.fin.d_sc_jb.p;
+    schur_lists(P.fin, ct);
+    ct.colour = P.ncol - 1;
+    ct.tiles = flev().tiles;
+    return ct;
+  }
+
+  // Colour c of the level: the flush of the updates its clusters receive from the
+  // colours before it (the blocks as they are before colour c), then Step 0 (the
+  // fill-in Gram and its eigenvectors, eqs. 16-17), the projections (eqs. 18-20),
+  // the partial LU (eq. 21) and the panels (eqs. 22, 24-26).
+  void run_colour(int c) {
+    FactorLevel& F = flev();
+    LevelView& v = F.view;
+    ColourTasks ct = colour_tasks(c);
+    ct.colour = c - 1;
+    hipEvent_t es = ev.next(st);
+    launch_schur(v, ct, mixed, st);
+    check_launch("schur");
+    ct.colour = c;
+    hipEvent_t e0 = ev.next(st);
+    launch_gram_fill(v, ct, H->ws_gram.p, gram_pstride, st);
+    check_launch("gram_fill");
+    hipEvent_t eg = ktime ? ev.next(st) : nullptr;
+    if (ktime) kern_ev.emplace_back(e0, eg, 0);
+    launch_xform(v, ct, 0, st);
+    launch_xform(v, ct, 1, st);
+    check_launch("xform");
+    launch_step0_eig(v, ct, H->ws_eig.p, dmax, st);
+    check_launch("step0_eig");
+    launch_xform(v, ct, 2, st);
+    hipEvent_t ex = ktime ? ev.next(st) : nullptr;
+    if (ktime) kern_ev.emplace_back(eg, ex, 1);
+    if (F.tiles == 1) {
+      launch_proj_fused(v, ct, mixed, st);
+    } else {
+      launch_proj(v, ct, H->ws_temp.p, 0, mixed, st);
+      launch_proj(v, ct, H->ws_temp.p, 1, mixed, st);
     }
-    // one synchronisation per level: ranks k~ and pivot status
+    check_launch("projection");
+    hipEvent_t e1 = ev.next(st);
+    if (ktime) kern_ev.emplace_back(ex, e1, 2);
+    launch_lu(v, ct, H->ws_lu.p, dmax, st);
+    check_launch("lu");
+    hipEvent_t el = ktime ? ev.next(st) : nullptr;
+    launch_panels(v, ct, st);
+    check_launch("panels");
+    hipEvent_t e2 = ev.next(st);
+    if (ktime) {
+      kern_ev.emplace_back(e1, el, 3);
+      kern_ev.emplace_back(el, e2, 4);
+    }
+    phase_ev.push_back({es, e0, e1, e2});
+  }
+
+  void run_fin() {
+    ColourTasks ct = fin_tasks();
+    hipEvent_t es = ev.next(st);
+    launch_schur(flev().view, ct, mixed, st);
+    check_launch("schur");
+    hipEvent_t ee = ev.next(st);
+    phase_ev.push_back({es, ee, ee, ee});
+  }
+
+  // The (kernel, entry) pairs of one stage of colour c for a shared launch; the
+  // work space and the largest eliminated dimension travel in each entry.
+  void stage_entries(int stage, int c, std::vector<std::pair<int, BatchEntry>>& out) {
+    FactorLevel& F = flev();
+    const bool fin = c >= plan().ncol;
+    ColourTasks ct = fin ? fin_tasks() : colour_tasks(c);
+    double2* buf = nullptr;
+    int64_t aux = 0;
+    switch (stage) {
+      case BS_SCHUR:
+      case BS_SCHUR_REDUCE:
+        if (!fin) ct.colour = c - 1;
+        break;
+      case BS_GRAM:
+      case BS_GRAM_REDUCE:
+        buf = H->ws_gram.p;
+        aux = gram_pstride;
+        break;
+      case BS_STEP0:
+        buf = H->ws_eig.p;
+        break;
+      case BS_PROJ0:
+      case BS_PROJ1:
+        buf = H->ws_temp.p;
+        break;
+      case BS_LU:
+        buf = H->ws_lu.p;
+        break;
+      default:
+        break;
+    }
+    batch_stage_entries(stage, F.view, ct, mixed, buf, aux, dmax, out);
+  }
+
+  // one synchronisation per level: ranks k~ and pivot status
+  void readback() {
+    FactorLevel& F = flev();
+    const int nc = plan().nc;
     F.kt.assign(nc, 0);
     HIPCHK(hipMemcpyAsync(F.kt.data(), F.d_kt.p, nc * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    int32_t flags[4];
     HIPCHK(hipMemcpyAsync(flags, F.d_flags.p, sizeof(flags), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+  }
+
+  // after readback(): merge into the parent level (or the final dense block, with
+  // the far blocks of the coarser levels when stopped early)
+  void level_merge() {
+    LevelPlan& P = plan();
+    BuildLevel& Bd = H->build[j];
+    FactorLevel& F = flev();
+    const int nc = P.nc;
     if (flags[0]) fail(H2_ERR_SINGULAR, "zero pivot in the partial LU of a cluster at level " + std::to_string(l));
     for (int i = 0; i < nc; ++i)
       if (!P.nonempty[i]) F.kt[i] = 0;
     F.k = kk;
-    // merge into the parent level (or the final dense block)
-    hipEvent_t e_m0 = ev.next(st);
+    DArr<double2>& parent_slots = H->slot_buf[(j + 1) & 1];
+    LevelView& v = F.view;
+    e_m0 = ev.next(st);
     const int npar = S.nclusters(l - 1);
-    std::vector<int32_t> n_par(npar, 0), off1(npar, 0);
+    n_par.assign(npar, 0);
+    off1.assign(npar, 0);
     for (int p = 0; p < npar; ++p) {
       off1[p] = P.nonempty[2 * p] ? F.kt[2 * p] : 0;
       n_par[p] = off1[p] + (P.nonempty[2 * p + 1] ? F.kt[2 * p + 1] : 0);
     }
-    std::vector<MergeTask> mt(P.merge.size());
+    mt.assign(P.merge.size(), MergeTask{});
     int64_t dst_total = 0;
     std::vector<int64_t> pslot_off;
     if (l > ls) {
@@ -1773,7 +1946,7 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       H->final_off.assign(npar + 1, 0);
       for (int p = 0; p < npar; ++p) H->final_off[p + 1] = H->final_off[p] + n_par[p];
       H->nf = H->final_off[npar];
-      H->d_final_off.upload(std::vector<int64_t>(H->final_off.begin(), H->final_off.end() - 1), st);
+      H->stage.put(H->d_final_off, std::vector<int64_t>(H->final_off.begin(), H->final_off.end() - 1));
       dst_total = H->nf * H->nf;
       for (size_t e = 0; e < P.merge.size(); ++e) {
         const MergeSrc& m = P.merge[e];
@@ -1795,9 +1968,8 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
       }
     }
     DArr<MergeTask>& d_mt = H->ws_merge;
-    d_mt.alloc(mt.size());
-    if (!mt.empty())
-      HIPCHK(hipMemcpyAsync(d_mt.p, mt.data(), mt.size() * sizeof(MergeTask), hipMemcpyHostToDevice, st));
+    H->stage.put(d_mt, mt);
+    H->stage.flush(st);
     double2* dst;
     if (l > ls) {
       parent_slots.alloc(dst_total);
@@ -1811,11 +1983,17 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     launch_merge(v, d_mt.p, (int)mt.size(), Bd.S.p, dst, st);
     check_launch("merge");
     if (l == ls && ls > l0) add_far_blocks(H, ls, n_par, off1, st);
-    hipEvent_t e_m1 = ev.next(st);
-    HIPCHK(hipStreamSynchronize(st));
+    e_m1 = ev.next(st);
+  }
+
+  // after the merge's synchronisation: timings, the level's stats row, next level
+  void level_close() {
+    LevelPlan& P = plan();
+    FactorLevel& F = flev();
+    const int nc = P.nc;
+    DArr<double2>& slots = H->slot_buf[j & 1];
     H->timing[4] += elapsed(e_m0, e_m1);
     H->level_ms.push_back(elapsed(e_level, e_m1));
-    (void)e_lev0;
     // stats row
     {
       int64_t sn = 0, mn = 0, sk = 0, mk = 0, skt = 0, mkt = 0, nkt = INT64_MAX, el = 0, ncl = 0;
@@ -1837,30 +2015,53 @@ static void factor_impl(h2_ctx* H, hipStream_t st) {
     // keep this level's block arena for the next factorization unless memory is
     // short (the level two steps up reuses it; keeping it costs its full size)
     if (memory_short()) slots.release();
+    --l;
   }
-  hipEvent_t e_f0 = ev.next(st);
-  dense_lu_factor(H, st);
-  hipEvent_t t_end = ev.next(st);
-  HIPCHK(hipStreamSynchronize(st));
-  H->stats_rows.push_back({ls - 1, (int64_t)S.nclusters(ls - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
-  H->timing[5] = elapsed(e_f0, t_end);
-  H->level_ms.push_back(H->timing[5]);
-  for (auto& pe : phase_ev) {
-    H->timing[3] += elapsed(pe[0], pe[1]);
-    H->timing[1] += elapsed(pe[1], pe[2]);
-    H->timing[2] += elapsed(pe[2], pe[3]);
+
+  // the final dense block (eq. 34 at the top of the tree or at the stop level), timings
+  void finish() {
+    hipEvent_t e_f0 = ev.next(st);
+    dense_lu_factor(H, st);
+    hipEvent_t t_end = ev.next(st);
+    HIPCHK(hipStreamSynchronize(st));
+    H->stats_rows.push_back({ls - 1, (int64_t)S.nclusters(ls - 1), H->nf, H->nf, 0, 0, 0, 0, 0, H->nf});
+    H->timing[5] = elapsed(e_f0, t_end);
+    H->level_ms.push_back(H->timing[5]);
+    for (auto& pe : phase_ev) {
+      H->timing[3] += elapsed(pe[0], pe[1]);
+      H->timing[1] += elapsed(pe[1], pe[2]);
+      H->timing[2] += elapsed(pe[2], pe[3]);
+    }
+    H->timing[0] = elapsed(t_begin, t_end);
+    if (!phase_ev.empty()) {  // a fused batch's launches serve every problem: no per-kernel times
+      if (ktime) {
+        for (int f = 0; f < 5; ++f) H->kernel_ms[f] = 0.0;
+        for (auto& ke : kern_ev) H->kernel_ms[std::get<2>(ke)] += elapsed(std::get<0>(ke), std::get<1>(ke));
+      }
+      H->kernel_ms[5] = H->timing[3];
+      H->kernel_ms[6] = H->timing[4];
+    }
+    H->kernel_ms[7] = H->timing[5];
+    H->ledger_valid = false;
+    H->factored = true;
   }
-  H->timing[0] = elapsed(t_begin, t_end);
-  if (ktime) {
-    for (int f = 0; f < 5; ++f) H->kernel_ms[f] = 0.0;
-    for (auto& ke : kern_ev) H->kernel_ms[std::get<2>(ke)] += elapsed(std::get<0>(ke), std::get<1>(ke));
+};
+
+static void factor_impl(h2_ctx* H, hipStream_t st) {
+  FactorRun R(H, st);
+  while (R.level_pending()) {
+    R.level_begin();
+    for (int c = 0; c < R.plan().ncol; ++c) R.run_colour(c);
+    R.run_fin();
+    R.readback();
+    HIPCHK(hipStreamSynchronize(st));
+    R.level_merge();
+    HIPCHK(hipStreamSynchronize(st));
+    R.level_close();
   }
-  H->kernel_ms[5] = H->timing[3];
-  H->kernel_ms[6] = H->timing[4];
-  H->kernel_ms[7] = H->timing[5];
-  H->ledger_valid = false;
-  H->factored = true;
+  if (!R.done) R.finish();
 }
+
 
 // P Z_f = L U by blocked LU with partial pivoting (64-column panels, GEMM
 // trailing updates), in place; the inverses of the 64 x 64 diagonal blocks of L
@@ -2495,6 +2696,44 @@ static void set_stop(h2_ctx* H, int stop) {
     build_merge(H, H->plans[S.L - l], l > stop ? &H->plans[S.L - l + 1] : nullptr);
 }
 
+static void factor_checked(h2_ctx* H, hipStream_t st) {
+  try {
+    factor_impl(H, st);
+  } catch (...) {
+    H->factored = false;
+    throw;
+  }
+}
+
+// The stop level search (see h2_tune_stop_level); returns the chosen level.
+static int tune_stop(h2_ctx* H, int64_t max_final, hipStream_t st, double* ms, int32_t n_ms, double* best_out) {
+  const Structure& S = H->S;
+  for (int32_t e = 0; ms && e < n_ms; ++e) ms[e] = -1.0;
+  int best = S.l0;
+  double best_ms = 0;
+  for (int ls = S.l0; ls <= S.L; ++ls) {
+    if (ls > S.l0) {
+      // the dense block a stop at ls leaves: the kept unknowns of level ls (known from the last run)
+      const FactorLevel& F = H->flev[S.L - ls];
+      int64_t nf = 0;
+      for (int t = 0; t < S.nclusters(ls); ++t)
+        if (S.size[ls][t]) nf += F.kt[t];
+      if (nf > max_final) break;
+    }
+    set_stop(H, ls);
+    factor_checked(H, st);
+    const double t = H->timing[0];
+    if (ms && ls - S.l0 < n_ms) ms[ls - S.l0] = t;
+    if (ls == S.l0 || t < best_ms) {
+      best = ls;
+      best_ms = t;
+    }
+  }
+  set_stop(H, best);
+  if (best_out) *best_out = best_ms;
+  return best;
+}
+
 extern "C" h2_status h2_tune_stop_level(h2_handle H, int64_t max_final, void* hip_stream, int32_t* chosen,
                                         double* ms, int32_t n_ms) {
   return guarded([&] {
@@ -2502,41 +2741,142 @@ extern "C" h2_status h2_tune_stop_level(h2_handle H, int64_t max_final, void* hi
     if (max_final < 1) fail(H2_ERR_ARG, "max_final < 1");
     hipStream_t st = (hipStream_t)hip_stream;
     AllocScope scope(&H->allocator, st);
-    const Structure& S = H->S;
-    for (int32_t e = 0; ms && e < n_ms; ++e) ms[e] = -1.0;
-    if (S.l0 < 0) {
+    if (H->S.l0 < 0) {
+      for (int32_t e = 0; ms && e < n_ms; ++e) ms[e] = -1.0;
       factor_impl(H, st);
       *chosen = 0;
       return;
     }
-    int best = S.l0;
-    double best_ms = 0;
-    for (int ls = S.l0; ls <= S.L; ++ls) {
-      if (ls > S.l0) {
-        // the dense block a stop at ls leaves: the kept unknowns of level ls (known from the last run)
-        const FactorLevel& F = H->flev[S.L - ls];
-        int64_t nf = 0;
-        for (int t = 0; t < S.nclusters(ls); ++t)
-          if (S.size[ls][t]) nf += F.kt[t];
-        if (nf > max_final) break;
-      }
-      set_stop(H, ls);
-      try {
-        factor_impl(H, st);
-      } catch (...) {
-        H->factored = false;
-        throw;
-      }
-      const double t = H->timing[0];
-      if (ms && ls - S.l0 < n_ms) ms[ls - S.l0] = t;
-      if (ls == S.l0 || t < best_ms) {
-        best = ls;
-        best_ms = t;
+    *chosen = tune_stop(H, max_final, st, ms, n_ms, nullptr);
+    if (!H->factored) factor_checked(H, st);
+  });
+}
+
+extern "C" h2_status h2_set_schur_split(h2_handle H, int32_t level, int64_t below_wgs) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    const Structure& S = H->S;
+    if (level < -1 || level > S.L) fail(H2_ERR_ARG, "level outside [0, L] (or -1 for every level)");
+    if (below_wgs < -1) fail(H2_ERR_ARG, "below_wgs < -1");
+    H->split_below.resize(S.L + 1, -1);
+    if (level < 0)
+      std::fill(H->split_below.begin(), H->split_below.end(), below_wgs);
+    else
+      H->split_below[level] = below_wgs;
+    H->factored = false;
+  });
+}
+
+// Process-wide cache of measured tunings, keyed by everything the factorization's
+// work depends on: the cluster tree and block structure (sizes of every cluster,
+// eta), the accuracy, the form, forced ranks and the stop-level search bound.
+struct TuneRecord {
+  int32_t stop;
+  std::vector<int64_t> split;
+  double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<uint64_t, TuneRecord> g_tune_cache;
+
+static uint64_t tuning_key(const h2_ctx* H, int64_t max_final) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  };
+  const Structure& S = H->S;
+  mix(&H->N, sizeof(H->N));
+  mix(&H->leaf, sizeof(H->leaf));
+  mix(&H->eta, sizeof(H->eta));
+  mix(&H->eps, sizeof(H->eps));
+  mix(&H->precision, sizeof(H->precision));
+  mix(&max_final, sizeof(max_final));
+  mix(&S.L, sizeof(S.L));
+  mix(&S.l0, sizeof(S.l0));
+  for (int l = 0; l <= S.L; ++l)
+    if (!S.size[l].empty()) mix(S.size[l].data(), S.size[l].size() * sizeof(S.size[l][0]));
+  const int32_t hf = H->has_forced ? 1 : 0;
+  mix(&hf, sizeof(hf));
+  if (H->has_forced) {
+    mix(H->forced_k.data(), H->forced_k.size() * sizeof(int32_t));
+    mix(H->forced_kt.data(), H->forced_kt.size() * sizeof(int32_t));
+  }
+  return h;
+}
+
+extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h2_tuning* out) {
+  return guarded([&] {
+    if (!H || !out) fail(H2_ERR_ARG, "NULL argument");
+    if (max_final < 1) fail(H2_ERR_ARG, "max_final < 1");
+    hipStream_t st = (hipStream_t)hip_stream;
+    AllocScope scope(&H->allocator, st);
+    const Structure& S = H->S;
+    std::memset(out, 0, sizeof(*out));
+    for (int l = 0; l < H2_TUNING_MAX_LEVELS; ++l) out->split_below[l] = -1;
+    if (S.L + 1 > H2_TUNING_MAX_LEVELS) fail(H2_ERR_ARG, "tree deeper than H2_TUNING_MAX_LEVELS");
+    if (S.l0 < 0) {
+      factor_checked(H, st);
+      out->factor_ms = H->timing[0];
+      return;
+    }
+    const uint64_t key = tuning_key(H, max_final);
+    TuneRecord rec;
+    bool cached = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        rec = it->second;
+        cached = true;
       }
     }
-    set_stop(H, best);
-    if (!H->factored) factor_impl(H, st);
-    *chosen = best;
+    if (!cached) {
+      // 1. the stop level, with the default split rule
+      H->split_below.assign(S.L + 1, -1);
+      rec.stop = tune_stop(H, max_final, st, nullptr, 0, nullptr);
+      // 2. the split threshold of every factored level: one factorization per candidate
+      //    (the same value on every level), each level keeps the candidate under which
+      //    its own time (its colours and its merge) was lowest
+      const int64_t cand[] = {0, 2048, SCHUR_SPLIT_BELOW, 32768, INT64_MAX};
+      const int nlev = S.L - rec.stop + 1;
+      std::vector<double> best(nlev, 0.0);
+      rec.split.assign(S.L + 1, -1);
+      for (int64_t c : cand) {
+        std::fill(H->split_below.begin(), H->split_below.end(), c);
+        factor_checked(H, st);
+        for (int e = 0; e < nlev && e < (int)H->level_ms.size(); ++e) {
+          const int l = S.L - e;
+          if (rec.split[l] < 0 || H->level_ms[e] < best[e]) {
+            rec.split[l] = c;
+            best[e] = H->level_ms[e];
+          }
+        }
+      }
+      H->split_below = rec.split;
+      factor_checked(H, st);
+      rec.ms = H->timing[0];
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = rec;
+    } else {
+      set_stop(H, rec.stop);
+      H->split_below = rec.split;
+      H->factored = false;
+      factor_checked(H, st);
+    }
+    out->stop_level = rec.stop;
+    out->from_cache = cached ? 1 : 0;
+    for (int l = 0; l <= S.L; ++l) out->split_below[l] = rec.split[l];
+    out->factor_ms = cached ? H->timing[0] : rec.ms;
+  });
+}
+
+extern "C" h2_status h2_tune_cache_clear(void) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
   });
 }
 
@@ -2677,14 +3017,121 @@ static void solve_refined(h2_ctx* H, int adj, const void* b, void* x, int32_t nr
 // stream from its own host thread (at most `workers` threads pull handles from a
 // shared counter), after everything queued on the caller's stream, which in turn
 // waits for all of them.  The first failure is reported.
-template <typename Fn>
-static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
+static void check_batch(h2_handle* hs, int32_t count) {
   if (!hs || count < 1) fail(H2_ERR_ARG, "empty batch");
   for (int32_t k = 0; k < count; ++k) {
     if (!hs[k]) fail(H2_ERR_ARG, "handle is NULL");
     for (int32_t q = 0; q < k; ++q)
       if (hs[q] == hs[k]) fail(H2_ERR_ARG, "a handle appears twice in the batch");
   }
+}
+
+// Several problems factored in lockstep, level by level from each problem's finest
+// level: every stage of colour index c (Schur flush, Step 0, projections, partial
+// LU, panels) is one launch for all problems that have that colour, its work items
+// listed per problem (entries sorted by their first workgroup).  Problems whose
+// sizes select different kernel variants (Step 0 register tiles, register or LDS
+// LU, fused one-tile projections, FP64 or mixed form) share a launch with those of
+// the same variant.  Each problem's work items and kernels are the ones its own
+// factorization launches, so the factors are bit-identical to one-by-one runs.
+// ids: the problems' indices in the caller's batch (for messages); *bad_id: the
+// index of the first failed problem, INT32_MAX when none failed in the problems'
+// own steps.
+static void factor_fused(h2_handle* hs, int32_t count, hipStream_t st, const int32_t* ids, int32_t* bad_id) {
+  *bad_id = INT32_MAX;
+  std::vector<std::unique_ptr<FactorRun>> runs(count);
+  std::vector<char> failed(count, 0);
+  h2_status first = H2_OK;
+  std::string first_msg;
+  auto step = [&](int32_t k, auto&& fn) {
+    if (failed[k]) return;
+    AllocScope scope(&hs[k]->allocator, st);
+    const h2_status s = guarded(fn);
+    if (s != H2_OK) {
+      failed[k] = 1;
+      hs[k]->factored = false;
+      if (first == H2_OK) {
+        first = s;
+        first_msg = "batch item " + std::to_string(ids[k]) + ": " + g_err;
+        *bad_id = ids[k];
+      }
+    }
+  };
+  for (int32_t k = 0; k < count; ++k) step(k, [&] { runs[k].reset(new FactorRun(hs[k], st)); });
+  struct Group {
+    int kernel;
+    size_t off;
+    int ne;
+    int64_t blocks;
+  };
+  std::vector<std::pair<int, BatchEntry>> pairs;
+  std::vector<BatchEntry> ent;
+  std::vector<Group> groups;
+  std::vector<int32_t> act;
+  for (;;) {
+    act.clear();
+    for (int32_t k = 0; k < count; ++k)
+      if (!failed[k] && runs[k]->level_pending()) act.push_back(k);
+    if (act.empty()) break;
+    for (int32_t k : act) step(k, [&] { runs[k]->level_begin(); });
+    act.erase(std::remove_if(act.begin(), act.end(), [&](int32_t k) { return failed[k] != 0; }), act.end());
+    int maxcol = 0;
+    for (int32_t k : act) maxcol = std::max(maxcol, runs[k]->plan().ncol);
+    ent.clear();
+    groups.clear();
+    // c < 0: the updates still pending at the end of each problem's level
+    auto add_stage = [&](int stage, int c) {
+      pairs.clear();
+      for (int32_t k : act) {
+        FactorRun& R = *runs[k];
+        const int nc = R.plan().ncol;
+        if (c < 0)
+          R.stage_entries(stage, nc, pairs);
+        else if (c < nc)
+          R.stage_entries(stage, c, pairs);
+      }
+      std::stable_sort(pairs.begin(), pairs.end(),
+                       [](const std::pair<int, BatchEntry>& a, const std::pair<int, BatchEntry>& b) {
+                         return a.first < b.first;
+                       });
+      for (size_t i = 0; i < pairs.size();) {
+        Group g{pairs[i].first, ent.size(), 0, 0};
+        for (; i < pairs.size() && pairs[i].first == g.kernel; ++i) {
+          BatchEntry e = pairs[i].second;
+          e.first = (int32_t)g.blocks;
+          g.blocks += (int64_t)e.gx * e.gy * e.gz;
+          if (g.blocks > INT32_MAX) fail(H2_ERR_INTERNAL, "shared launch beyond 2^31 workgroups");
+          ent.push_back(e);
+          ++g.ne;
+        }
+        groups.push_back(g);
+      }
+    };
+    for (int c = 0; c < maxcol; ++c)
+      for (int s = 0; s < BS_COUNT; ++s) add_stage(s, c);
+    add_stage(BS_SCHUR, -1);
+    add_stage(BS_SCHUR_REDUCE, -1);
+    {
+      AllocScope scope(&hs[0]->allocator, st);
+      hs[0]->batch_entries.upload(ent, st);
+    }
+    const BatchEntry* d_ent = hs[0]->batch_entries.p;
+    for (const Group& g : groups) launch_batched(g.kernel, d_ent + g.off, g.ne, (int)g.blocks, st);
+    check_launch("batched colour stages");
+    for (int32_t k : act) step(k, [&] { runs[k]->readback(); });
+    HIPCHK(hipStreamSynchronize(st));
+    for (int32_t k : act) step(k, [&] { runs[k]->level_merge(); });
+    HIPCHK(hipStreamSynchronize(st));
+    for (int32_t k : act) step(k, [&] { runs[k]->level_close(); });
+  }
+  for (int32_t k = 0; k < count; ++k)
+    if (!failed[k] && !runs[k]->done) step(k, [&] { runs[k]->finish(); });
+  if (first != H2_OK) fail(first, first_msg);
+}
+
+template <typename Fn>
+static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
+  check_batch(hs, count);
   hipEvent_t start;
   HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
   HIPCHK(hipEventRecord(start, st));
@@ -2727,6 +3174,69 @@ static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
   }
   (void)hipEventDestroy(start);
   if (first != H2_OK) fail(first, first_msg);
+}
+
+// The fused schedule over up to FUSED_GROUPS groups of problems, each group on a
+// stream of its own driven by its own host thread: the latency-bound stages of one
+// group (Step 0's eigen-solver, the partial LU, the final dense LU) overlap with
+// another group's flushes on the other hardware queues.  Problems are dealt to the
+// groups by size (largest first, in alternating order) so that the groups carry
+// similar work.
+constexpr int FUSED_GROUPS = 4;
+
+static void factor_fused_groups(h2_handle* hs, int32_t count, hipStream_t st) {
+  const int ng = std::min<int>(FUSED_GROUPS, (count + 1) / 2);
+  if (ng <= 1) {
+    std::vector<int32_t> ids(count);
+    for (int32_t k = 0; k < count; ++k) ids[k] = k;
+    int32_t bad_id = 0;
+    factor_fused(hs, count, st, ids.data(), &bad_id);
+    return;
+  }
+  std::vector<int32_t> order(count);
+  for (int32_t k = 0; k < count; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hs[a]->N > hs[b]->N; });
+  std::vector<std::vector<h2_handle>> grp(ng);
+  std::vector<std::vector<int32_t>> gid(ng);
+  for (int32_t i = 0; i < count; ++i) {
+    const int r = i % ng, g = ((i / ng) & 1) ? ng - 1 - r : r;
+    grp[g].push_back(hs[order[i]]);
+    gid[g].push_back(order[i]);
+  }
+  hipEvent_t start;
+  HIPCHK(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(start, st));
+  std::vector<hipStream_t> gs(ng);
+  for (int g = 0; g < ng; ++g) {
+    h2_handle lead = grp[g][0];
+    if (!lead->own_stream) HIPCHK(hipStreamCreateWithFlags(&lead->own_stream, hipStreamNonBlocking));
+    gs[g] = lead->own_stream;
+    HIPCHK(hipStreamWaitEvent(gs[g], start, 0));
+  }
+  std::vector<h2_status> stt(ng, H2_OK);
+  std::vector<std::string> msg(ng);
+  std::vector<int32_t> bad_id(ng, INT32_MAX);
+  auto work = [&](int g) {
+    stt[g] = guarded([&] { factor_fused(grp[g].data(), (int32_t)grp[g].size(), gs[g], gid[g].data(), &bad_id[g]); });
+    if (stt[g] != H2_OK) msg[g] = g_err;
+  };
+  std::vector<std::thread> pool;
+  for (int g = 1; g < ng; ++g) pool.emplace_back(work, g);
+  work(0);
+  for (auto& t : pool) t.join();
+  for (int g = 0; g < ng; ++g) {
+    hipEvent_t done;
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(done, gs[g]));
+    HIPCHK(hipStreamWaitEvent(st, done, 0));
+    (void)hipEventDestroy(done);
+  }
+  (void)hipEventDestroy(start);
+  // report the failure of the lowest batch index
+  int bad = -1;
+  for (int g = 0; g < ng; ++g)
+    if (stt[g] != H2_OK && (bad < 0 || bad_id[g] < bad_id[bad])) bad = g;
+  if (bad >= 0) fail(stt[bad], msg[bad]);
 }
 
 extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
@@ -2785,8 +3295,14 @@ extern "C" h2_status h2_solve_noalloc(h2_handle H, const void* b, void* x, int32
   });
 }
 
-extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream) {
+extern "C" h2_status h2_factor_batch_mode(h2_handle* hs, int32_t count, void* hip_stream, int32_t mode) {
   return guarded([&] {
+    if (mode != H2_BATCH_FUSED && mode != H2_BATCH_STREAMS) fail(H2_ERR_ARG, "unknown batch mode");
+    if (mode == H2_BATCH_FUSED) {
+      check_batch(hs, count);
+      factor_fused_groups(hs, count, (hipStream_t)hip_stream);
+      return;
+    }
     run_batch(hs, count, (hipStream_t)hip_stream, [&](int32_t k, hipStream_t s) {
       try {
         factor_impl(hs[k], s);
@@ -2796,6 +3312,10 @@ extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_str
       }
     });
   });
+}
+
+extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_stream) {
+  return h2_factor_batch_mode(hs, count, hip_stream, H2_BATCH_FUSED);
 }
 
 extern "C" h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,

@@ -26,18 +26,32 @@ struct VBlock {
 __device__ __forceinline__ VBlock vblock() {
   return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, (int)gridDim.z};
 }
-// entry of a shared launch that owns this workgroup (entries sorted by `first`)
-__device__ __forceinline__ const BatchEntry& locate(const BatchEntry* E, int ne, VBlock& VB) {
+// Entry of a shared launch that owns this workgroup (entries sorted by `first`).
+// The table is read through the constant address space: the index is made
+// wave-uniform, the fields are scalar loads, and the compiler may load a field
+// again where it is used rather than hold every field in registers (as it does
+// for kernel arguments).  The table is never written while a launch runs.
+typedef const __attribute__((address_space(4))) BatchEntry ConstEntry;
+struct EntryRef {
+  const LevelView& v;
+  const ColourTasks& c;
+  double2* buf;
+  int64_t aux;
+  int i0;
+};
+__device__ __forceinline__ EntryRef locate(const BatchEntry* E, int ne, VBlock& VB) {
+  ConstEntry* CE = (ConstEntry*)E;
   const int lin = blockIdx.x;
   int lo = 0, hi = ne - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (E[mid].first <= lin)
+    if (CE[mid].first <= lin)
       lo = mid;
     else
       hi = mid - 1;
   }
-  const BatchEntry& e = E[lo];
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  ConstEntry& e = CE[lo];
   int r = lin - e.first;
   VB.gx = e.gx;
   VB.gy = e.gy;
@@ -46,7 +60,7 @@ __device__ __forceinline__ const BatchEntry& locate(const BatchEntry* E, int ne,
   r /= e.gx;
   VB.y = r % e.gy;
   VB.z = r / e.gy;
-  return e;
+  return {*(const LevelView*)&e.v, *(const ColourTasks*)&e.c, e.buf, e.aux, e.i0};
 }
 
 static inline __host__ __device__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
@@ -734,7 +748,7 @@ __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, d
 }
 __global__ void __launch_bounds__(256) k_gram_fill_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   gram_fill_body(e.v, e.c, e.buf, e.aux, VB);
 }
 
@@ -758,7 +772,7 @@ __global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* pa
 }
 __global__ void k_gram_fill_reduce_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   gram_fill_reduce_body(e.v, e.c, e.buf, e.aux, VB);
 }
 
@@ -805,7 +819,7 @@ __device__ __forceinline__ void xform_body(const LevelView& v, const ColourTasks
 __global__ void __launch_bounds__(256) k_xform(LevelView v, ColourTasks c, int phase) { xform_body(v, c, phase, vblock()); }
 __global__ void __launch_bounds__(256) k_xform_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   xform_body(e.v, e.c, e.i0, VB);
 }
 
@@ -1506,7 +1520,7 @@ __global__ void __launch_bounds__(S0_NT) k_step0_eig(LevelView v, ColourTasks c,
 template <int NQ>
 __global__ void __launch_bounds__(S0_NT) k_step0_eig_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   step0_eig_body<NQ>(e.v, e.c, e.buf, e.i0, VB);
 }
 
@@ -1589,7 +1603,7 @@ __global__ void __launch_bounds__(256) k_proj(LevelView v, ColourTasks c, double
 }
 __global__ void __launch_bounds__(256) k_proj_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   proj_kernel_body<double>(e.v, e.c, e.buf, e.i0, PJ_ALL, VB);
 }
 
@@ -1614,7 +1628,7 @@ __global__ void __launch_bounds__(256) k_proj_mixed(LevelView v, ColourTasks c, 
 }
 __global__ void __launch_bounds__(256) k_proj_mixed_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   proj_mixed_body(e.v, e.c, e.buf, e.i0, VB);
 }
 
@@ -1662,7 +1676,7 @@ __global__ void __launch_bounds__(256) k_proj_fused(LevelView v, ColourTasks c, 
 }
 __global__ void __launch_bounds__(256) k_proj_fused_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   proj_fused_kernel_body<double>(e.v, e.c, PJ_ALL, VB);
 }
 
@@ -1679,7 +1693,7 @@ __global__ void __launch_bounds__(256) k_proj_fused_mixed(LevelView v, ColourTas
 }
 __global__ void __launch_bounds__(256) k_proj_fused_mixed_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   proj_fused_mixed_body(e.v, e.c, VB);
 }
 
@@ -1899,7 +1913,7 @@ __global__ void __launch_bounds__(LU_NT) k_lu_reg(LevelView v, ColourTasks c, do
 }
 __global__ void __launch_bounds__(LU_NT) k_lu_reg_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   lu_reg_body(e.v, e.c, e.buf, e.i0, VB);
 }
 
@@ -2032,7 +2046,7 @@ __global__ void __launch_bounds__(256) k_lu_big(LevelView v, ColourTasks c, doub
 }
 __global__ void __launch_bounds__(256) k_lu_big_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   lu_big_body(e.v, e.c, e.buf, e.i0, VB);
 }
 
@@ -2137,7 +2151,7 @@ __device__ __forceinline__ void panels_body(const LevelView& v, const ColourTask
 __global__ void __launch_bounds__(256) k_panels(LevelView v, ColourTasks c) { panels_body(v, c, vblock()); }
 __global__ void __launch_bounds__(256) k_panels_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   panels_body(e.v, e.c, VB);
 }
 
@@ -2328,7 +2342,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                                                                                           int ne) {
   __shared__ SchurSmem s;
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   schur_flush<false>(e.v, e.c, s, VB);
 }
 
@@ -2341,7 +2355,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                                                                                            int ne) {
   __shared__ SchurSmem s;
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   schur_flush<true>(e.v, e.c, s, VB);
 }
 
@@ -2394,7 +2408,7 @@ __device__ __forceinline__ void schur_reduce_body(const LevelView& v, const Colo
 __global__ void __launch_bounds__(256) k_schur_reduce(LevelView v, ColourTasks c) { schur_reduce_body(v, c, vblock()); }
 __global__ void __launch_bounds__(256) k_schur_reduce_b(const BatchEntry* E, int ne) {
   VBlock VB;
-  const BatchEntry& e = locate(E, ne, VB);
+  const EntryRef e = locate(E, ne, VB);
   schur_reduce_body(e.v, e.c, VB);
 }
 
@@ -2429,6 +2443,26 @@ void launch_copy_blocks(const double2* src, const int64_t* src_off, double2* dst
                         const int64_t* len, int nb, hipStream_t st) {
   if (nb <= 0) return;
   hipLaunchKernelGGL(k_copy_blocks, dim3(nb), dim3(256), 0, st, src, src_off, dst, dst_off, len);
+}
+
+// Host arrays staged in one buffer, spread to their device arrays: one workgroup
+// per piece of at most STAGE_PIECE bytes, 16-byte words (pieces start 16-byte
+// aligned on both sides), the last 4-byte words of a piece one per thread.
+__global__ void __launch_bounds__(256) k_scatter_segments(const char* base, const CopySeg* segs) {
+  const CopySeg sg = segs[blockIdx.x];
+  const char* a = base + sg.src;
+  char* d = static_cast<char*>(sg.dst);
+  const int64_t q = sg.bytes >> 4;
+  for (int64_t e = threadIdx.x; e < q; e += blockDim.x)
+    reinterpret_cast<uint4*>(d)[e] = reinterpret_cast<const uint4*>(a)[e];
+  const int64_t w0 = q << 2, words = sg.bytes >> 2;
+  if (w0 + threadIdx.x < words)
+    reinterpret_cast<uint32_t*>(d)[w0 + threadIdx.x] = reinterpret_cast<const uint32_t*>(a)[w0 + threadIdx.x];
+}
+
+void launch_scatter_segments(const char* base, const CopySeg* segs, int nseg, hipStream_t st) {
+  if (nseg <= 0) return;
+  hipLaunchKernelGGL(k_scatter_segments, dim3(nseg), dim3(256), 0, st, base, segs);
 }
 
 void launch_zero(double2* p, int64_t n, hipStream_t st) {

@@ -198,6 +198,15 @@ struct MergeTask {
   int32_t tr;          // source slot holds (cb, ca): read transposed
 };
 void launch_zero(double2* p, int64_t n, hipStream_t st);
+// One piece of a staged host array: `bytes` (a multiple of 4, at most STAGE_PIECE)
+// at offset `src` of the staging buffer go to `dst`; src and dst are 16-byte aligned.
+constexpr int64_t STAGE_PIECE = 16384;
+struct CopySeg {
+  int64_t src;
+  int64_t bytes;
+  void* dst;
+};
+void launch_scatter_segments(const char* base, const CopySeg* segs, int nseg, hipStream_t st);
 void launch_copy_blocks(const double2* src, const int64_t* src_off, double2* dst, const int64_t* dst_off,
                         const int64_t* len, int nb, hipStream_t st);
 void launch_merge(const LevelView& v, const MergeTask* t, int nt, const double2* S, double2* dst,

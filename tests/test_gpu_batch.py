@@ -1,10 +1,14 @@
 """Batched factor and solve of independent problems (rectangular box grids of
 the batching workload's recipe, scaled down) against the same calls made one
-handle at a time: results must be bit-identical."""
+handle at a time, in both batch schedules (fused launches across problems and
+one stream per handle): results must be bit-identical.  A fused batch that
+mixes precisions, stop levels, tree depths and a problem without admissible
+blocks; small problems with ranks pinned to the oracle's against its solves."""
 import numpy as np
 import pytest
 
 import paper_1703_06155_amd as h2
+from oracle import h2_oracle as O
 from paper_1703_06155_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -16,14 +20,17 @@ def _torch():
     return torch
 
 
-def test_batch_equals_one_by_one():
+@pytest.mark.parametrize("mode", ["fused", "streams"])
+def test_batch_equals_one_by_one(mode):
     torch = _torch()
     probs = I.batch_problems(count=6, nrhs=4, sides=(6, 14), leaf=16)
     solo, batch = [], []
     for pr in probs:
         solo.append(h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps).factor())
         batch.append(h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps))
-    h2.factor_batch(batch)
+    h2.factor_batch(batch, mode=mode)
+    for k in range(len(probs)):
+        assert np.array_equal(batch[k].stats(), solo[k].stats()), k
     rhs = [torch.from_numpy(pr.rhs.copy()) for pr in probs]
     xs, infos = h2.solve_batch(batch, rhs, tol=1e-8, info=True)
     for k, pr in enumerate(probs):
@@ -43,10 +50,79 @@ def test_batch_rejects_duplicates_and_empty():
     _torch()
     pr = I.batch_problems(count=1, nrhs=1, sides=(6, 8), leaf=16)[0]
     G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
-    with pytest.raises(h2.H2Error):
-        h2.factor_batch([G, G])
-    with pytest.raises(h2.H2Error):
-        h2.factor_batch([])
+    for mode in ("fused", "streams"):
+        with pytest.raises(h2.H2Error):
+            h2.factor_batch([G, G], mode=mode)
+        with pytest.raises(h2.H2Error):
+            h2.factor_batch([], mode=mode)
+    with pytest.raises(ValueError):
+        h2.factor_batch([G], mode="other")
+
+
+def _settings(k, pr, G):
+    """Per-problem settings of the heterogeneous batch: every third problem in the mixed
+    form, every other one stopped one level early when its tree allows."""
+    if k % 3 == 1:
+        G.set_precision("mixed")
+    if k % 2 == 0:
+        l0, L = G.stop_level_range()
+        if L > l0:
+            G.set_stop_level(l0 + 1)
+    return G
+
+
+def test_fused_batch_of_mixed_settings_equals_one_by_one():
+    torch = _torch()
+    probs = I.batch_problems(count=7, nrhs=3, sides=(5, 18), leaf=12)
+    # a box too small for any admissible block: the whole matrix is one dense LU
+    probs.append(I.make_problem("tiny", (3, 3, 2), 16, 1e-4, nrhs=3))
+    solo, batch = [], []
+    for k, pr in enumerate(probs):
+        solo.append(_settings(k, pr, h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)).factor())
+        batch.append(_settings(k, pr, h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)))
+    depths = {G.stop_level_range()[1] for G in solo}
+    assert solo[-1].stop_level_range()[0] < 0
+    assert len(depths) > 1, "the batch should hold trees of different depths"
+    h2.factor_batch(batch)
+    for k, pr in enumerate(probs):
+        assert np.array_equal(batch[k].stats(), solo[k].stats()), k
+        b = torch.from_numpy(pr.rhs.copy()).cuda()
+        assert np.array_equal(batch[k].solve(b).cpu().numpy(), solo[k].solve(b).cpu().numpy()), k
+        assert np.array_equal(batch[k].solve_adjoint(b).cpu().numpy(), solo[k].solve_adjoint(b).cpu().numpy()), k
+    # the same handles again: the work item table of the shared launches is reused
+    h2.factor_batch(batch)
+    for k, pr in enumerate(probs):
+        b = torch.from_numpy(pr.rhs.copy()).cuda()
+        assert np.array_equal(batch[k].solve(b).cpu().numpy(), solo[k].solve(b).cpu().numpy()), k
+    for G in solo + batch:
+        G.close()
+
+
+def test_fused_batch_against_oracle():
+    """Three small problems, ranks pinned to the oracle's, factored in one fused batch:
+    M^-1 b and M^-H g agree with the oracle's sweeps (Algs. 5-6) to 1e-10 of their
+    largest entry."""
+    torch = _torch()
+    probs = I.batch_problems(count=3, nrhs=2, sides=(7, 12), leaf=14)
+    hs, refs = [], []
+    for pr in probs:
+        H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+        Fz = O.factor(H)
+        fr = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(Fz))
+        hs.append(h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr))
+        refs.append(Fz)
+    h2.factor_batch(hs)
+    for pr, G, Fz in zip(probs, hs, refs):
+        x = G.solve(torch.from_numpy(pr.rhs.copy()).cuda()).cpu().numpy()
+        xo = O.solve(Fz, pr.rhs)
+        g = np.random.default_rng(5).standard_normal(pr.rhs.shape) + 0.25j
+        lam = G.solve_adjoint(torch.from_numpy(g).cuda()).cpu().numpy()
+        lo = O.solve_adjoint(Fz, g)
+        ex = float(np.abs(x - xo).max() / np.abs(xo).max())
+        el = float(np.abs(lam - lo).max() / np.abs(lo).max())
+        print(f"{pr.name} N={pr.n}: fused batch vs oracle x {ex:.1e}, lam {el:.1e}")
+        assert ex < 1e-10 and el < 1e-10
+        G.close()
 
 
 def test_batch_mixed_equals_one_by_one_and_refines():

@@ -1,0 +1,93 @@
+"""Autotuner (h2_tune): the stop level and, per factored level, the Schur flush
+split threshold, chosen by measurement and cached per problem structure.
+
+Checked: the chosen settings are among the candidates, a second handle of the
+same structure takes them from the cache (nothing measured) and a cleared
+cache measures again; the tuned factorization, ranks pinned to the oracle's
+stopped at the chosen level, agrees with the oracle to 1e-10; the split
+threshold's extremes (never split, always split) change only the order of
+summation: both agree with the oracle to 1e-10 and each is bitwise
+repeatable."""
+import numpy as np
+import pytest
+
+import paper_1703_06155_amd as h2
+from oracle import h2_oracle as O
+from paper_1703_06155_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+CANDIDATES = {0, 2048, 8192, 32768, 2 ** 63 - 1}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _maxrel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_tune_settings_cache_and_oracle():
+    torch = _torch()
+    pr = I.make_problem("tune", (14, 12, 10), 16, 1e-5, nrhs=2, rhs_seed=3)
+    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    S = H.S
+    fr0 = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(O.factor(H)))
+    h2.tune_cache_clear()
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr0)
+    try:
+        t = G.tune(max_final=4096)
+        print(f"tuned: {t}")
+        assert not t["from_cache"]
+        ls = t["stop_level"]
+        assert S.l0 <= ls <= S.L and G.stop_level() == ls
+        assert set(t["split_below"]) == set(range(ls, S.L + 1))
+        assert set(t["split_below"].values()) <= CANDIDATES
+        # the same structure again: cached, same settings
+        G2 = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr0)
+        t2 = G2.tune(max_final=4096)
+        assert t2["from_cache"] and t2["stop_level"] == ls and t2["split_below"] == t["split_below"]
+        b = torch.from_numpy(pr.rhs.copy()).cuda()
+        x = G.solve(b).cpu().numpy()
+        assert np.array_equal(x, G2.solve(b).cpu().numpy())
+        G2.close()
+        # a stopped factorization's ranks above the stop are those of the unstopped one;
+        # the oracle stopped at the same level
+        Fz = O.factor(H, stop_level=ls)
+        fr = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(Fz))
+        G3 = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr, stop_level=ls)
+        for lev, v in t["split_below"].items():
+            G3.set_schur_split(v, lev)
+        G3.factor()
+        assert _maxrel(G3.solve(b).cpu().numpy(), O.solve(Fz, pr.rhs)) < 1e-10
+        G3.close()
+        h2.tune_cache_clear()
+        assert not G.tune(max_final=4096)["from_cache"]
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("below", [0, 2 ** 63 - 1], ids=["never_split", "always_split"])
+def test_split_extremes_match_oracle(below):
+    torch = _torch()
+    pr = I.make_problem("split", (12, 12, 12), 27, 1e-4, nrhs=2, rhs_seed=5)
+    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    Fz = O.factor(H)
+    fr = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(Fz))
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr)
+    try:
+        G.set_schur_split(below).factor()
+        b = torch.from_numpy(pr.rhs.copy()).cuda()
+        x = G.solve(b).cpu().numpy()
+        assert _maxrel(x, O.solve(Fz, pr.rhs)) < 1e-10
+        G.factor()
+        assert np.array_equal(x, G.solve(b).cpu().numpy())
+        with pytest.raises(h2.H2Error):
+            G.set_schur_split(-2)
+        with pytest.raises(h2.H2Error):
+            G.set_schur_split(100, level=99)
+    finally:
+        G.close()

@@ -2535,111 +2535,138 @@ void launch_parent_basis(int np, const int32_t* pn, const int32_t* pk, const int
 // Panel of the final dense LU: columns [j0, j0 + w) over rows [j0, n), partial
 // pivoting (largest |re| + |im|, lowest row on ties, as zgetrf).  Row interchanges
 // are applied to the panel's own columns only (k_dense_laswp applies them to the
-// others).  Columns are taken in groups of eight: within a group each column's
-// pivot search, scaling and rank-1 update touch only the group's columns; the
-// group then updates the rest of the panel by one rank-8 pass over the rows, so
-// the panel is streamed about w / 8 times instead of w times.
-constexpr int DP_GROUP = 8;
+// others).  The columns are taken in groups of DP_GROUP.  One workgroup factors a
+// group: per column the pivot, the interchange, the L column and the rank-1
+// update of the group's later columns in a single pass over the rows (each thread
+// keeps DP_RU rows' loads in flight, and the pass also yields the next column's
+// pivot candidates), then the group's rows of the later panel columns become U
+// rows (L_gg^-1 times them).  The rows below the group of the later panel
+// columns are then updated by a matrix-core GEMM over many workgroups, so the
+// single workgroup never streams the whole panel.
+constexpr int DP_GROUP = 4;
+constexpr int DP_RU = 4;
 
-__global__ void __launch_bounds__(1024) k_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv,
+// the workgroup's pivot from per-thread candidates (value, row): largest value,
+// lowest row among equal values
+__device__ __forceinline__ void dense_pivot(double best, int bi, double* rv, int* ri, double& pv, int& pj) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double wm = wave_max_nonneg(fmax(best, 0.0));
+  const int wi = wave_min_int(best == wm ? bi : 0x7fffffff);
+  if (lane == 0) {
+    rv[wv] = wm;
+    ri[wv] = wi;
+  }
+  __syncthreads();
+  pv = rv[0];
+  pj = ri[0];
+  for (int u = 1; u < 16; ++u)
+    if (rv[u] > pv || (rv[u] == pv && ri[u] < pj)) {
+      pv = rv[u];
+      pj = ri[u];
+    }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_dense_group(double2* A, int64_t n, int64_t j0, int g0, int32_t* piv,
                                                       double2* linv, int32_t* flag) {
   __shared__ double rv[16];
   __shared__ int ri[16];
-  __shared__ double2 sU[DP_GROUP * 64];  // the group's rows of the later panel columns (U part)
+  __shared__ double2 srow[DP_GROUP];
   __shared__ double2 sD[64 * 64];
+  if (*flag) return;  // an earlier group met a zero pivot: the factorization has failed
   const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int w = (int)imin64(64, n - j0);
-  for (int g0 = 0; g0 < w; g0 += DP_GROUP) {
-    const int ge = min(w, g0 + DP_GROUP);
-    for (int jj = g0; jj < ge; ++jj) {
-      const int64_t j = j0 + jj;
-      // pivot: largest |re| + |im| in column j from row j on, lowest row on ties
-      double best = -1.0;
-      int bi = 0x7fffffff;
-      for (int64_t a = j + tid; a < n; a += blockDim.x) {
-        const double2 x = A[a + j * n];
-        const double val = fabs(x.x) + fabs(x.y);
-        if (val > best) {
-          best = val;
-          bi = (int)a;
-        }
-      }
-      const double wm = wave_max_nonneg(fmax(best, 0.0));
-      const int wi = wave_min_int(best == wm ? bi : 0x7fffffff);
-      if (lane == 0) {
-        rv[wv] = wm;
-        ri[wv] = wi;
-      }
-      __syncthreads();
-      double pv = rv[0];
-      int pj = ri[0];
-      for (int u = 1; u < 16; ++u)
-        if (rv[u] > pv || (rv[u] == pv && ri[u] < pj)) {
-          pv = rv[u];
-          pj = ri[u];
-        }
-      __syncthreads();
-      if (!(pv > 0.0) || pj >= n) {
-        if (tid == 0) *flag = 1;
-        return;
-      }
-      if (tid == 0) piv[j] = pj;
-      // interchange rows j and pj within the panel's columns
-      if (pj != j && tid < w) {
-        const int64_t cb = (j0 + tid) * n;
-        const double2 t = A[j + cb];
-        A[j + cb] = A[pj + cb];
-        A[pj + cb] = t;
-      }
-      __syncthreads();
-      const double2 p = A[j + j * n];
-      const double pd = cabs2(p);
-      const double2 pinv = make_double2(p.x / pd, -p.y / pd);
-      for (int64_t a = j + 1 + tid; a < n; a += blockDim.x) A[a + j * n] = cmul(A[a + j * n], pinv);
-      __syncthreads();
-      // rank-1 update of the group's later columns: a column per wavefront, rows on lanes
-      for (int b = jj + 1 + wv; b < ge; b += 16) {
-        const int64_t cb = (j0 + b) * n;
-        const double2 ub = A[j + cb];
-        for (int64_t a = j + 1 + lane; a < n; a += 64) A[a + cb] = csub(A[a + cb], cmul(A[a + j * n], ub));
-      }
-      __syncthreads();
+  const int w = (int)imin64(64, n - j0), ge = min(w, g0 + DP_GROUP);
+  // pivot candidates of the group's first column
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int64_t a = j0 + g0 + tid; a < n; a += blockDim.x) {
+    const double2 x = A[a + (j0 + g0) * n];
+    const double val = fabs(x.x) + fabs(x.y);
+    if (val > best) {
+      best = val;
+      bi = (int)a;
     }
-    if (ge >= w) break;
-    // U rows of the group for the later panel columns: U_g = L_gg^-1 A[group rows, later columns]
-    const int ng = ge - g0, nl = w - ge;
-    for (int b = tid; b < nl; b += blockDim.x) {
-      const int64_t cb = (j0 + ge + b) * n;
-      double2 u[DP_GROUP];
-#pragma unroll
-      for (int k = 0; k < DP_GROUP; ++k) {
-        if (k >= ng) break;
-        double2 v = A[j0 + g0 + k + cb];
-        for (int q = 0; q < k; ++q) v = csub(v, cmul(A[j0 + g0 + k + (j0 + g0 + q) * n], u[q]));
-        u[k] = v;
-        A[j0 + g0 + k + cb] = v;
-        sU[k + DP_GROUP * b] = v;
-      }
+  }
+  for (int jj = g0; jj < ge; ++jj) {
+    const int64_t j = j0 + jj;
+    double pv;
+    int pj;
+    dense_pivot(best, bi, rv, ri, pv, pj);
+    if (!(pv > 0.0) || pj >= n) {
+      if (tid == 0) *flag = 1;
+      return;
+    }
+    if (tid == 0) piv[j] = pj;
+    // interchange rows j and pj within the panel's columns
+    if (pj != j && tid < w) {
+      const int64_t cb = (j0 + tid) * n;
+      const double2 t = A[j + cb];
+      A[j + cb] = A[pj + cb];
+      A[pj + cb] = t;
     }
     __syncthreads();
-    // rank-ng update of the later panel columns below the group: a row per thread
-    for (int64_t a = j0 + ge + tid; a < n; a += blockDim.x) {
-      double2 l[DP_GROUP];
+    const double2 p = A[j + j * n];
+    const double pd = cabs2(p);
+    const double2 pinv = make_double2(p.x / pd, -p.y / pd);
+    const int nb = ge - jj - 1;  // later columns of the group
+    if (tid < nb) srow[tid] = A[j + (j + 1 + tid) * n];
+    __syncthreads();
+    best = -1.0;
+    bi = 0x7fffffff;
+    for (int64_t a0 = j + 1 + tid; a0 < n; a0 += (int64_t)DP_RU * blockDim.x) {
+      double2 l[DP_RU], x[DP_RU][DP_GROUP - 1];
 #pragma unroll
-      for (int k = 0; k < DP_GROUP; ++k) l[k] = k < ng ? A[a + (j0 + g0 + k) * n] : make_double2(0, 0);
-      for (int b = 0; b < nl; ++b) {
-        double2* p = A + a + (j0 + ge + b) * n;
-        double2 v = *p;
+      for (int u = 0; u < DP_RU; ++u) {
+        const int64_t a = a0 + (int64_t)u * blockDim.x;
+        if (a < n) {
+          l[u] = A[a + j * n];
 #pragma unroll
-        for (int k = 0; k < DP_GROUP; ++k)
-          if (k < ng) v = csub(v, cmul(l[k], sU[k + DP_GROUP * b]));
-        *p = v;
+          for (int q = 0; q < DP_GROUP - 1; ++q)
+            if (q < nb) x[u][q] = A[a + (j + 1 + q) * n];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < DP_RU; ++u) {
+        const int64_t a = a0 + (int64_t)u * blockDim.x;
+        if (a < n) {
+          const double2 lv = cmul(l[u], pinv);
+          A[a + j * n] = lv;
+#pragma unroll
+          for (int q = 0; q < DP_GROUP - 1; ++q)
+            if (q < nb) {
+              const double2 y = csub(x[u][q], cmul(lv, srow[q]));
+              A[a + (j + 1 + q) * n] = y;
+              if (q == 0) {  // candidate for the next column's pivot (rows visited in increasing order)
+                const double val = fabs(y.x) + fabs(y.y);
+                if (val > best) {
+                  best = val;
+                  bi = (int)a;
+                }
+              }
+            }
+        }
       }
     }
     __syncthreads();
   }
-  // explicit inverse of the unit-lower diagonal block: a column per wavefront by
-  // forward substitution, rows on lanes, the block in LDS
+  // the group's rows of the later panel columns: U_g = L_gg^-1 A[group rows, later columns]
+  const int ng = ge - g0, nl = w - ge;
+  for (int b = tid; b < nl; b += blockDim.x) {
+    const int64_t cb = (j0 + ge + b) * n;
+    double2 u[DP_GROUP];
+#pragma unroll
+    for (int k = 0; k < DP_GROUP; ++k) {
+      if (k >= ng) break;
+      double2 v = A[j0 + g0 + k + cb];
+      for (int q = 0; q < k; ++q) v = csub(v, cmul(A[j0 + g0 + k + (j0 + g0 + q) * n], u[q]));
+      u[k] = v;
+      A[j0 + g0 + k + cb] = v;
+    }
+  }
+  if (ge < w) return;
+  __syncthreads();
+  // last group: explicit inverse of the panel's unit-lower diagonal block, a column
+  // per wavefront by forward substitution, rows on lanes, the block in LDS
   for (int e = tid; e < w * w; e += blockDim.x) sD[(e % w) + 64 * (e / w)] = A[j0 + (e % w) + (j0 + e / w) * n];
   __syncthreads();
   for (int col = wv; col < 64; col += 16) {
@@ -2674,8 +2701,17 @@ __global__ void k_dense_laswp(double2* A, int64_t n, int64_t j0, int w, const in
 
 void launch_dense_panel(double2* A, int64_t n, int64_t j0, int32_t* piv, double2* linv, int32_t* flag,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_dense_panel, dim3(1), dim3(1024), 0, st, A, n, j0, piv, linv, flag);
   const int w = (int)std::min<int64_t>(64, n - j0);
+  for (int g0 = 0; g0 < w; g0 += DP_GROUP) {
+    hipLaunchKernelGGL(k_dense_group, dim3(1), dim3(1024), 0, st, A, n, j0, g0, piv, linv, flag);
+    const int ge = std::min(w, g0 + DP_GROUP);
+    const int64_t rows = n - j0 - ge;
+    // rows below the group of the later panel columns -= L[rows, group] U[group, later columns]
+    if (ge < w && rows > 0)
+      launch_gemm_one({A + (j0 + ge) + (j0 + g0) * n, A + (j0 + g0) + (j0 + ge) * n, A + (j0 + ge) + (j0 + ge) * n,
+                       n, n, n, (int32_t)rows, w - ge, ge - g0, OP_N, OP_N, ST_SUB},
+                      st);
+  }
   if (n - w > 0)
     hipLaunchKernelGGL(k_dense_laswp, dim3((unsigned)((n - w + 255) / 256)), dim3(256), 0, st, A, n, j0, w, piv);
 }

@@ -74,10 +74,12 @@ def cpu_baseline() -> dict:
 
 # HBM bytes per Schur flush (flush kernel + partial-tile reduction), keyed by
 # (cube side, form), from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
-# 1 GiB copy (the summaries under profiles/); valid only for that workload and the
-# kernel sources hashed here.
-SCHUR_TRAFFIC = {(64, "mixed"): {"sources_sha256": "c580869f87fc761c8e286994701701d575e77d78a616cbea67be6d9c1a07590a",
-                                   "bytes_per_launch": 11585222194}}
+# 1 GiB copy (the summaries under profiles/); valid only for that workload, its fixed
+# execution settings (CUBE64_SETTINGS) and the kernel sources hashed here.
+SCHUR_TRAFFIC = {(64, "mixed"): {"sources_sha256": "c7c6747020f832be82d08a2e8c2ec47b88a66bd90e107ab404e724fb14de2c17",
+                                   "bytes_per_launch": 12475000966},
+                 (64, "fp64"): {"sources_sha256": "c7c6747020f832be82d08a2e8c2ec47b88a66bd90e107ab404e724fb14de2c17",
+                                  "bytes_per_launch": 13125623040}}
 
 
 def kernel_sources_sha256() -> str:
@@ -131,7 +133,8 @@ def kernel_rooflines(led: dict, solve1_ms: float = None, matvec_ms: float = None
     return out
 
 
-def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: int, form: str = "fp64") -> dict:
+def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: int, form: str = "fp64",
+                   fixed_settings: bool = True) -> dict:
     """Roofline of the Schur flush (the FP64 flush kernel plus the kernel that adds
     the partial tiles of split target blocks) from the algorithmic ledger and the
     flush durations the library measured with HIP events on its stream; one
@@ -141,7 +144,7 @@ def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: 
     intensity = flops / nbytes if nbytes > 0 else float("inf")
     traffic = None
     rec = SCHUR_TRAFFIC.get((grid, form))
-    if rec and rec["sources_sha256"] == kernel_sources_sha256():
+    if rec and fixed_settings and rec["sources_sha256"] == kernel_sources_sha256():
         traffic = rec["bytes_per_launch"]
     if intensity >= ridge:
         achieved = flops / max(launches, 1) / per_launch_s / 1e12 if ms > 0 else 0.0
@@ -244,11 +247,33 @@ def median_ms(torch, fn, reps: int = 5) -> float:
     return float(np.median(ts))
 
 
-def form_leg(torch, G, pr, precision: str, steps: int, warmup: int, b, B64, tag: str) -> dict:
+# Execution settings of the 64^3 workload per form: the stop level and the Schur flush
+# split threshold of every factored level, as h2_tune chose them in one measured run
+# (stop level first, then one factorization per split candidate).  Fixed here so that
+# every run, and the profiles under profiles/, use the same launches; --tune measures
+# them again at setup instead.
+CUBE64_SETTINGS = {"fp64": {"stop_level": 7, "split_below": {7: 32768, 8: 0, 9: 8192, 10: 2048, 11: 2048, 12: 0}},
+                   "mixed": {"stop_level": 7, "split_below": {7: 8192, 8: 32768, 9: 2048, 10: 0, 11: 0, 12: 0}}}
+
+
+def apply_settings(G, settings: dict) -> dict:
+    G.set_stop_level(settings["stop_level"])
+    for lev, v in settings["split_below"].items():
+        G.set_schur_split(int(v), int(lev))
+    return dict(settings, source="fixed (h2_tune)")
+
+
+def form_leg(torch, G, pr, precision: str, steps: int, warmup: int, b, B64, tag: str, setup=None) -> dict:
     """One arithmetic form on the resident H^2 matrix: `warmup` untimed and `steps` timed
     steps (factor + 1 RHS refined to 1e-8), then warm solve and matvec medians and one
-    more factorization with every kernel family timed (untimed, for the roofline)."""
+    more factorization with every kernel family timed (untimed, for the roofline).
+    `setup(G)` (untimed) fixes or tunes the execution settings and returns them."""
     G.set_precision(precision)
+    t0 = time.perf_counter()
+    settings = setup(G) if setup else None
+    setup_s = time.perf_counter() - t0
+    if settings is not None:
+        print(f"# {tag} {precision} settings {settings} ({setup_s:.1f} s)", file=sys.stderr, flush=True)
 
     def step():
         G.factor()
@@ -297,6 +322,7 @@ def form_leg(torch, G, pr, precision: str, steps: int, warmup: int, b, B64, tag:
            "solve_ms_refined_1e-8": solve_ref_ms, "solve_ms_1rhs": solve1_ms, "solve_ms_64rhs": solve64_ms,
            "matvec_ms_1rhs": matvec_ms, "kernel_roofline": kern,
            "schur_fp32_flop_frac": kled["schur_fp32_flop_frac"],
+           "settings": settings, "settings_s": setup_s,
            "_ledger": ledger, "_schur_ms": float(tm[3])}
     return out
 
@@ -312,7 +338,9 @@ def main():
     ap.add_argument("--no-cube32", action="store_true", help="skip the 32^3 leg")
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--stop-level", type=int, default=0,
-                    help="last factored level of the headline workload (0: chosen by measurement at setup)")
+                    help="last factored level of the headline workload (0: the fixed settings, or --tune)")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the stop level and Schur split thresholds by h2_tune at setup")
     ap.add_argument("--batch-chunk", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling HBM counters)")
@@ -342,25 +370,28 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     print(f"# build {g}^3 {build_s:.2f} s (setup, untimed)", file=sys.stderr, flush=True)
-    # setup, untimed: the stop level (Sec. III-C early stop) and the per-level Schur split
-    # thresholds chosen by measurement (h2_tune)
-    t0 = time.perf_counter()
+    # setup, untimed, per form: the stop level (Sec. III-C early stop) and the per-level
+    # Schur split thresholds: fixed for 64^3 (chosen by h2_tune), measured otherwise
     if args.stop_level:
-        G.set_stop_level(args.stop_level)
-        tuning = {"stop_level": args.stop_level, "source": "--stop-level"}
+        def setup(G, form):
+            G.set_stop_level(args.stop_level)
+            return {"stop_level": args.stop_level, "source": "--stop-level"}
+    elif args.tune or g not in (64,):
+        def setup(G, form):
+            return dict(G.tune(max_final=16384), source="h2_tune at setup")
     else:
-        tuning = G.tune(max_final=16384)
-    stop = tuning["stop_level"]
-    tune_s = time.perf_counter() - t0
-    print(f"# tuning {tuning}, {tune_s:.1f} s", file=sys.stderr, flush=True)
+        def setup(G, form):
+            return apply_settings(G, CUBE64_SETTINGS[form])
     b = torch.from_numpy(pr.rhs[:, 0].copy()).cuda()
     B64 = torch.from_numpy(I.plane_waves(pr.points, I.directions(64, 3))).cuda()
     forms = [f for f in args.forms.split(",") if f]
-    legs = {f: form_leg(torch, G, pr, f, args.steps, args.warmup, b, B64, f"{g}^3") for f in forms}
+    legs = {f: form_leg(torch, G, pr, f, args.steps, args.warmup, b, B64, f"{g}^3", lambda G_, f=f: setup(G_, f))
+            for f in forms}
     head = max(legs.values(), key=lambda d: d["unknowns_per_s"])
     hf = head["precision"]
     schur_flops, schur_launches, factor_flops, schur_bytes = head["_ledger"]
-    roof = schur_roofline(schur_flops, schur_bytes, head["_schur_ms"], int(schur_launches), g, hf)
+    roof = schur_roofline(schur_flops, schur_bytes, head["_schur_ms"], int(schur_launches), g, hf,
+                          fixed_settings=(head["settings"] or {}).get("source") == "fixed (h2_tune)")
     for d in legs.values():
         d.pop("_ledger")
         d.pop("_schur_ms")
@@ -383,7 +414,7 @@ def main():
         "config": {"workload": f"VIE cube grid {g}^3 (N={pr.n}), leaf 64, eta 1, eps 1e-4, "
                                f"factor + 1 RHS refined to 1e-8; value = the faster form ({hf})",
                    "N": pr.n, "leaf": 64, "eta": 1.0, "eps": 1e-4, "precision": hf, "build_s": build_s,
-                   "stop_level": stop, "tuning": tuning, "tuning_s": tune_s},
+                   "stop_level": head["settings"]["stop_level"], "settings": head["settings"]},
         "factor_ms": head["factor_ms"],
         "factor_unknowns_per_s": head["factor_unknowns_per_s"],
         "solve_ms_refined_1e-8": head["solve_ms_refined_1e-8"],
@@ -402,16 +433,15 @@ def main():
     if not args.no_cube32 and g != 32:
         p32 = I.make_problem("cube32", (32, 32, 32), 64, 1e-4)
         G32 = h2.H2(p32.points, p32.k, p32.h, p32.chi, p32.leaf, p32.eta, p32.eps)
-        tune32 = G32.tune(max_final=16384)
         b32 = torch.from_numpy(p32.rhs[:, 0].copy()).cuda()
         B32 = torch.from_numpy(I.plane_waves(p32.points, I.directions(64, 3))).cuda()
-        leg32 = form_leg(torch, G32, p32, "fp64", max(args.steps, 3), 1, b32, B32, "32^3")
+        leg32 = form_leg(torch, G32, p32, "fp64", max(args.steps, 3), 1, b32, B32, "32^3",
+                         lambda G_: dict(G_.tune(max_final=16384), source="h2_tune at setup"))
         leg32.pop("_ledger")
         leg32.pop("_schur_ms")
         leg32.pop("kernel_roofline")
         leg32["workload"] = "VIE cube grid 32^3 (N=32768), leaf 64, eta 1, eps 1e-4, FP64, factor + 1 RHS refined"
-        leg32["stop_level"] = tune32["stop_level"]
-        leg32["tuning"] = tune32
+        leg32["stop_level"] = leg32["settings"]["stop_level"]
         out["cube32"] = leg32
         G32.close()
         del G32

@@ -152,7 +152,7 @@ def schur_roofline(flops: float, nbytes: float, ms: float, launches: int, grid: 
     else:
         achieved = nbytes / max(launches, 1) / per_launch_s / 1e9 if ms > 0 else 0.0
         out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    kernel = "k_schur_fp64 + k_schur_reduce" if form == "fp64" else "k_schur_mixed + k_schur_reduce"
+    kernel = "k_schur_fp64 + k_schur_reduce" if form == "fp64" else "k_schur_mixed / k_schur_fp64 (per level) + k_schur_reduce"
     out.update({"frac": out["achieved"] / out["peak"], "traffic": traffic, "kernel": kernel,
                 "launches": launches, "flops_per_launch": flops / max(launches, 1),
                 "bytes_per_launch_algorithmic": nbytes / max(launches, 1), "intensity_flop_per_byte": intensity,
@@ -247,19 +247,26 @@ def median_ms(torch, fn, reps: int = 5) -> float:
     return float(np.median(ts))
 
 
-# Execution settings of the 64^3 workload per form: the stop level and the Schur flush
-# split threshold of every factored level, as h2_tune chose them in one measured run
-# (stop level first, then one factorization per split candidate).  Fixed here so that
+# Execution settings of the 64^3 workload per form: the stop level, the Schur flush
+# split threshold of every factored level and, in the mixed form, each level's flush
+# mode, as h2_tune chose them in one measured run (stop level first, then one
+# factorization per candidate).  Fixed here so that
 # every run, and the profiles under profiles/, use the same launches; --tune measures
 # them again at setup instead.
-CUBE64_SETTINGS = {"fp64": {"stop_level": 7, "split_below": {7: 32768, 8: 0, 9: 8192, 10: 2048, 11: 2048, 12: 0}},
-                   "mixed": {"stop_level": 7, "split_below": {7: 8192, 8: 32768, 9: 2048, 10: 0, 11: 0, 12: 0}}}
+UNLIMITED = 2 ** 63 - 1
+CUBE64_SETTINGS = {"fp64": {"stop_level": 7,
+                            "split_below": {7: 8192, 8: 2048, 9: 0, 10: UNLIMITED, 11: UNLIMITED, 12: 32768}},
+                   "mixed": {"stop_level": 7,
+                             "split_below": {7: 32768, 8: 32768, 9: 0, 10: 8192, 11: 8192, 12: 0},
+                             "mixed_flush": {7: 0, 8: 1, 9: 0, 10: 0, 11: 0, 12: 1}}}
 
 
 def apply_settings(G, settings: dict) -> dict:
     G.set_stop_level(settings["stop_level"])
     for lev, v in settings["split_below"].items():
         G.set_schur_split(int(v), int(lev))
+    for lev, v in settings.get("mixed_flush", {}).items():
+        G.set_mixed_flush(int(v), int(lev))
     return dict(settings, source="fixed (h2_tune)")
 
 

@@ -149,6 +149,14 @@ h2_status h2_set_stop_level(h2_handle H, int32_t level);
  * hence the rounding.  The handle becomes unfactored. */
 h2_status h2_set_schur_split(h2_handle H, int32_t level, int64_t below_wgs);
 
+/* Mixed form: the Schur flush kernel of a level (level = -1: every level).
+ * mode 1: terms of clusters whose panels show no growth run on FP32 matrix
+ * cores, the others in FP64; 0: every term in FP64 (only the projections stay
+ * mixed at that level); -1: the default rule (FP32 routing where the level's
+ * clusters eliminate 32 or more unknowns on average).  The handle becomes
+ * unfactored when it is in the mixed form. */
+h2_status h2_set_mixed_flush(h2_handle H, int32_t level, int32_t mode);
+
 #define H2_TUNING_MAX_LEVELS 64
 
 /* Measured settings of a handle (h2_tune). */
@@ -156,14 +164,16 @@ typedef struct h2_tuning {
   int32_t stop_level;        /* chosen stop level (0 when no block is admissible) */
   int32_t from_cache;        /* 1: taken from the process-wide cache, only the final factorization ran */
   int64_t split_below[H2_TUNING_MAX_LEVELS]; /* per level l: the Schur split threshold (-1: not factored) */
+  int32_t mixed_flush[H2_TUNING_MAX_LEVELS]; /* per level l, mixed form: the flush mode (-1: not factored or FP64 form) */
   double factor_ms;          /* factorization time with the chosen settings */
 } h2_tuning;
 
 /* Autotuner: chooses the stop level (as h2_tune_stop_level, with the default
- * split rule) and then, per factored level, the Schur split threshold among
- * {0, 2048, 8192, 32768, unlimited} by one factorization per candidate (the
- * candidate on every level at once; each level keeps the candidate under which
- * its own time was lowest).  The result is stored in a process-wide cache
+ * split and flush rules) and then, per factored level, the Schur split
+ * threshold among {0, 2048, 8192, 32768, unlimited} and, in the mixed form, the
+ * flush mode among {0, 1}, by one factorization per candidate (the candidate
+ * on every level at once; each level keeps the candidate under which its own
+ * time was lowest).  The result is stored in a process-wide cache
  * keyed by the cluster tree (every cluster's size), eta, eps, the form, the
  * forced ranks and max_final; a later call on any handle with the same key
  * applies the cached settings and factors once.  The handle is left factored

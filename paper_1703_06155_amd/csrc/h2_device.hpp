@@ -70,6 +70,15 @@ __device__ __forceinline__ int wave_min_int(int v) {
   v = min(v, __builtin_amdgcn_update_dpp(0x7fffffff, v, 0x143, 0xc, 0xf, false));
   return __builtin_amdgcn_readlane(v, 63);
 }
+__device__ __forceinline__ int wave_sum_int(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 63);
+}
 // maximum of non-negative values (lanes outside a DPP source read 0)
 __device__ __forceinline__ double wave_max_nonneg(double v) {
   v = fmax(v, dpp_f64<0xb1>(v));

@@ -329,6 +329,7 @@ struct FactorLevel {
   std::vector<int64_t> voff;
   LevelView view{};
   int tiles = 1;
+  bool mixed_flush = false;  // the level's Schur flushes routed FP32-safe terms to FP32
 };
 
 }  // namespace h2
@@ -404,6 +405,7 @@ struct h2_ctx {
   h2::DArr<int64_t> lv_toff, lv_so, lv_do, lv_len;
   int stop = -1;                           // last factored level (l0 unless stopped early, Sec. III-C)
   std::vector<int64_t> split_below;        // per level: Schur flush split threshold in workgroups (-1: default)
+  std::vector<int32_t> mixed_flush;        // per level, mixed form: 1 FP32-routing flush, 0 FP64 flush, -1 default rule
   h2::DArr<double2> fb_X, fb_Y;            // early stop: expanded bases and their products with couplings
   h2::DArr<int32_t> fb_n, fb_k, fb_k1, fb_k2, fb_off1;
   h2::DArr<int64_t> fb_toff, fb_xoff;
@@ -1231,6 +1233,11 @@ constexpr size_t SCHUR_PART_MAX_BYTES = size_t(8) << 30;
 // workgroups for a small flush); a larger flush fills the device with whole tasks
 // and spares the partial tiles' traffic.  Per level, h2_set_schur_split / h2_tune.
 constexpr int64_t SCHUR_SPLIT_BELOW = 8192;
+// Mixed form: a level's flushes route FP32-safe terms to FP32 (k_schur_mixed) when
+// its clusters' average eliminated dimension is at least this; below, few tasks
+// gather enough FP32-safe contraction columns to pay for that kernel's lower
+// occupancy, and the FP64 flush runs.  Per level, h2_set_mixed_flush / h2_tune.
+constexpr double MIXED_FLUSH_MIN_D = 32.0;
 
 static void release_factor_buffers(h2_ctx* H) {
   H->flev.clear();
@@ -1427,6 +1434,7 @@ struct FactorRun {
   int64_t gram_pstride = 0;
   bool split_ok = false;
   int64_t split_below = SCHUR_SPLIT_BELOW;
+  bool mixed_flush = false;
   int32_t flags[4] = {0, 0, 0, 0};
 
   // With the library's own hipMalloc: when device memory is short, start from nothing
@@ -1518,6 +1526,17 @@ struct FactorRun {
     }
     if (nmax > 512) fail(H2_ERR_INTERNAL, "cluster dimension above 512 (kernel limit)");
     F.tiles = std::max(1, (nmax + 63) / 64);
+    {
+      int64_t dsum = 0, ncl = 0;
+      for (int t = 0; t < nc; ++t)
+        if (P.nonempty[t]) {
+          dsum += F.n[t] - kk[t];
+          ++ncl;
+        }
+      const int mf = l < (int)H->mixed_flush.size() ? H->mixed_flush[l] : -1;
+      mixed_flush = mixed && (mf >= 0 ? mf != 0 : (ncl > 0 && (double)dsum / ncl >= MIXED_FLUSH_MIN_D));
+      F.mixed_flush = mixed_flush;
+    }
     // offsets
     std::vector<int64_t> slot_off(P.nslot + 1, 0);
     for (int s = 0; s < P.nslot; ++s)
@@ -1726,7 +1745,8 @@ struct FactorRun {
     v.W = W.p;
     v.flags = F.d_flags.p;
     v.margins = F.d_margins.p;
-    v.pmax = mixed ? reinterpret_cast<unsigned long long*>(F.d_pmax.p) : nullptr;
+    // panel maxima only where the flush routes by them
+    v.pmax = mixed_flush ? reinterpret_cast<unsigned long long*>(F.d_pmax.p) : nullptr;
     hipEvent_t e_hp = ktime ? ev.next(st) : nullptr;
     launch_householder_perp(v, nc, st);
     check_launch("host.cpp:1040");
@@ -1804,7 +1824,7 @@ struct FactorRun {
     ColourTasks ct = colour_tasks(c);
     ct.colour = c - 1;
     hipEvent_t es = ev.next(st);
-    launch_schur(v, ct, mixed, st);
+    launch_schur(v, ct, mixed_flush, st);
     check_launch("schur");
     ct.colour = c;
     hipEvent_t e0 = ev.next(st);
@@ -1845,7 +1865,7 @@ struct FactorRun {
   void run_fin() {
     ColourTasks ct = fin_tasks();
     hipEvent_t es = ev.next(st);
-    launch_schur(flev().view, ct, mixed, st);
+    launch_schur(flev().view, ct, mixed_flush, st);
     check_launch("schur");
     hipEvent_t ee = ev.next(st);
     phase_ev.push_back({es, ee, ee, ee});
@@ -1882,7 +1902,7 @@ struct FactorRun {
       default:
         break;
     }
-    batch_stage_entries(stage, F.view, ct, mixed, buf, aux, dmax, out);
+    batch_stage_entries(stage, F.view, ct, mixed, mixed_flush, buf, aux, dmax, out);
   }
 
   // one synchronisation per level: ranks k~ and pivot status
@@ -2767,12 +2787,28 @@ extern "C" h2_status h2_set_schur_split(h2_handle H, int32_t level, int64_t belo
   });
 }
 
+extern "C" h2_status h2_set_mixed_flush(h2_handle H, int32_t level, int32_t mode) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    const Structure& S = H->S;
+    if (level < -1 || level > S.L) fail(H2_ERR_ARG, "level outside [0, L] (or -1 for every level)");
+    if (mode < -1 || mode > 1) fail(H2_ERR_ARG, "mode must be -1, 0 or 1");
+    H->mixed_flush.resize(S.L + 1, -1);
+    if (level < 0)
+      std::fill(H->mixed_flush.begin(), H->mixed_flush.end(), mode);
+    else
+      H->mixed_flush[level] = mode;
+    if (H->precision == H2_MIXED) H->factored = false;
+  });
+}
+
 // Process-wide cache of measured tunings, keyed by everything the factorization's
 // work depends on: the cluster tree and block structure (sizes of every cluster,
 // eta), the accuracy, the form, forced ranks and the stop-level search bound.
 struct TuneRecord {
   int32_t stop;
   std::vector<int64_t> split;
+  std::vector<int32_t> mflush;
   double ms;
 };
 static std::mutex g_tune_mu;
@@ -2815,7 +2851,10 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
     AllocScope scope(&H->allocator, st);
     const Structure& S = H->S;
     std::memset(out, 0, sizeof(*out));
-    for (int l = 0; l < H2_TUNING_MAX_LEVELS; ++l) out->split_below[l] = -1;
+    for (int l = 0; l < H2_TUNING_MAX_LEVELS; ++l) {
+      out->split_below[l] = -1;
+      out->mixed_flush[l] = -1;
+    }
     if (S.L + 1 > H2_TUNING_MAX_LEVELS) fail(H2_ERR_ARG, "tree deeper than H2_TUNING_MAX_LEVELS");
     if (S.l0 < 0) {
       factor_checked(H, st);
@@ -2834,8 +2873,9 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
       }
     }
     if (!cached) {
-      // 1. the stop level, with the default split rule
+      // 1. the stop level, with the default split and flush rules
       H->split_below.assign(S.L + 1, -1);
+      H->mixed_flush.assign(S.L + 1, -1);
       rec.stop = tune_stop(H, max_final, st, nullptr, 0, nullptr);
       // 2. the split threshold of every factored level: one factorization per candidate
       //    (the same value on every level), each level keeps the candidate under which
@@ -2856,6 +2896,24 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
         }
       }
       H->split_below = rec.split;
+      // 3. mixed form: the flush kernel of every factored level (FP32 routing or plain
+      //    FP64), chosen the same way
+      rec.mflush.assign(S.L + 1, -1);
+      if (H->precision == H2_MIXED) {
+        std::vector<double> bm(nlev, 0.0);
+        for (int32_t m = 0; m <= 1; ++m) {
+          H->mixed_flush.assign(S.L + 1, m);
+          factor_checked(H, st);
+          for (int e = 0; e < nlev && e < (int)H->level_ms.size(); ++e) {
+            const int l = S.L - e;
+            if (rec.mflush[l] < 0 || H->level_ms[e] < bm[e]) {
+              rec.mflush[l] = m;
+              bm[e] = H->level_ms[e];
+            }
+          }
+        }
+      }
+      H->mixed_flush = rec.mflush;
       factor_checked(H, st);
       rec.ms = H->timing[0];
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2863,12 +2921,16 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
     } else {
       set_stop(H, rec.stop);
       H->split_below = rec.split;
+      H->mixed_flush = rec.mflush;
       H->factored = false;
       factor_checked(H, st);
     }
     out->stop_level = rec.stop;
     out->from_cache = cached ? 1 : 0;
-    for (int l = 0; l <= S.L; ++l) out->split_below[l] = rec.split[l];
+    for (int l = 0; l <= S.L; ++l) {
+      out->split_below[l] = rec.split[l];
+      out->mixed_flush[l] = rec.mflush[l];
+    }
     out->factor_ms = cached ? H->timing[0] : rec.ms;
   });
 }
@@ -3450,7 +3512,7 @@ static void compute_ledger(h2_ctx* H) {
     auto dim_after = [&](int a, int c) -> double { return P.colour[a] <= c ? F.kt[a] : F.n[a]; };
     // the panel maxima the mixed flush routes by (max|C|, max|R|, max|input block| per cluster)
     std::vector<unsigned long long> pmax;
-    if (H->precision == H2_MIXED && F.d_pmax.p) {
+    if (H->precision == H2_MIXED && F.mixed_flush && F.d_pmax.p) {
       pmax.resize(4 * (size_t)P.nc);
       HIPCHK(hipMemcpy(pmax.data(), F.d_pmax.p, pmax.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     }

@@ -2273,11 +2273,14 @@ __device__ __forceinline__ void schur_flush(const LevelView& v, const ColourTask
   // the contraction (MIX_MIN_K columns); otherwise every term runs in FP64
   bool split_prec = false;
   if (MIX) {
+    // the FP32-safe contraction columns of the task, its terms spread over the lanes
+    // (one round of loads rather than a chain of them per term)
     int kf = 0;
-    SchurTerm t;
-    for (int e = e0; e < e_end && kf < MIX_MIN_K; ++e)
+    for (int e = e0 + (int)(threadIdx.x & 63); e < e_end; e += 64) {
+      SchurTerm t;
       if (schur_term(v, c, e, tr, tc, 1, t)) kf += t.r;
-    split_prec = kf >= MIX_MIN_K;
+    }
+    split_prec = wave_sum_int(kf) >= MIX_MIN_K;
   }
   if (split_prec) {
     // FP32 terms first; their sums then seed the FP64 accumulators (through LDS:
@@ -3659,8 +3662,8 @@ void launch_contrast_grad(const double2* x, const double2* g, const double2* lam
 // ===========================================================================
 // The entries one problem contributes to a stage of a colour, with the grids and
 // arguments its own launchers (launch_schur, launch_gram_fill, ...) would use.
-void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, double2* buf,
-                         int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out) {
+void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, bool mixed_flush,
+                         double2* buf, int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out) {
   auto add = [&](int kernel, int gx, int gy, int gz, double2* b, int64_t a, int i) {
     if (gx <= 0 || gy <= 0 || gz <= 0) return;
     BatchEntry e;
@@ -3678,7 +3681,7 @@ void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bo
   const int t2 = c.tiles * c.tiles;
   switch (stage) {
     case BS_SCHUR:
-      if (c.nsc > 0) add(mixed ? BK_SCHUR_MIXED : BK_SCHUR_FP64, c.nsc, t2, 1, nullptr, 0, 0);
+      if (c.nsc > 0) add(mixed_flush ? BK_SCHUR_MIXED : BK_SCHUR_FP64, c.nsc, t2, 1, nullptr, 0, 0);
       break;
     case BS_SCHUR_REDUCE:
       if (c.nsc > 0 && c.ngrp > 0) add(BK_SCHUR_REDUCE, c.ngrp, t2, 4, nullptr, 0, 0);

@@ -118,12 +118,13 @@ enum BatchStage : int {
   BS_SCHUR, BS_SCHUR_REDUCE, BS_GRAM, BS_GRAM_REDUCE, BS_XFORM0, BS_XFORM1, BS_STEP0, BS_XFORM2, BS_PROJ0,
   BS_PROJ1, BS_LU, BS_PANELS, BS_COUNT
 };
-// Appends the (kernel, entry) pairs one problem contributes to a stage: buf / aux
+// Appends the (kernel, entry) pairs one problem contributes to a stage (mixed: the
+// mixed form's projections; mixed_flush: its FP32-routing Schur flush): buf / aux
 // are its work space and stride (Gram partials, eigen-solver, projection temp or
 // LU scratch), i0 its largest eliminated dimension (Step 0, LU); the grids follow
 // the single-problem launchers.
-void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, double2* buf,
-                         int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out);
+void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, bool mixed_flush,
+                         double2* buf, int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out);
 
 // Generic host-resolved batched GEMM task: C (op)= op(A) op(B).
 struct GemmTask {

@@ -69,3 +69,36 @@ def test_set_precision_round_trip():
         G.solve(b)
     G.factor().set_precision("fp64").factor()
     assert _rel(G.solve(b).cpu().numpy(), x1) == 0.0
+
+
+def test_flush_mode_per_level():
+    """The mixed form with the FP64 flush at every level routes nothing to FP32 (the
+    ledger's FP32 share is 0) and differs from the FP64 oracle only by the FP32
+    projections; with the routing flush forced everywhere it stays within the same
+    bound; both refine to 1e-8.  Bad arguments are rejected."""
+    torch = _torch()
+    pr = I.make_problem("t", (12, 12, 12), 27, 1e-4)
+    H = O.construct(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps)
+    Fz = O.factor(H)
+    fr = h2.forced_ranks_from_oracle(O.forced_construction(H), O.forced_from(Fz))
+    b = pr.rhs[:, 0]
+    xo = O.solve(Fz, b)
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, precision="mixed", forced_ranks=fr)
+    try:
+        for mode in (0, 1):
+            G.set_mixed_flush(mode).factor()
+            frac = G.kernel_ledger()["schur_fp32_flop_frac"]
+            if mode == 0:
+                assert frac == 0.0
+            x = G.solve(torch.from_numpy(b.copy())).cpu().numpy()
+            err = _rel(x, xo)
+            xr, info = G.solve(torch.from_numpy(b.copy()), tol=1e-8, info=True)
+            print(f"flush mode {mode}: FP32 share {frac:.3f}, unrefined vs oracle {err:.2e}, "
+                  f"refined in {info['iterations']}")
+            assert err < 1e-4 and info["rel_residual"] <= 1e-8
+        with pytest.raises(h2.H2Error):
+            G.set_mixed_flush(2)
+        with pytest.raises(h2.H2Error):
+            G.set_mixed_flush(1, level=99)
+    finally:
+        G.close()

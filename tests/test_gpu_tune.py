@@ -70,6 +70,24 @@ def test_tune_settings_cache_and_oracle():
         G.close()
 
 
+def test_tune_mixed_form_flush_modes():
+    """In the mixed form the tuner also picks each factored level's flush mode (0 or 1),
+    and the tuned handle refines to 1e-8."""
+    torch = _torch()
+    pr = I.make_problem("tunemix", (16, 12, 12), 27, 1e-4)
+    G = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, precision="mixed")
+    try:
+        t = G.tune(max_final=4096)
+        print(f"tuned mixed: {t}")
+        l0, L = G.stop_level_range()
+        assert set(t["mixed_flush"]) == set(range(t["stop_level"], L + 1))
+        assert set(t["mixed_flush"].values()) <= {0, 1}
+        _, info = G.solve(torch.from_numpy(pr.rhs[:, 0].copy()).cuda(), tol=1e-8, info=True)
+        assert info["rel_residual"] <= 1e-8
+    finally:
+        G.close()
+
+
 @pytest.mark.parametrize("below", [0, 2 ** 63 - 1], ids=["never_split", "always_split"])
 def test_split_extremes_match_oracle(below):
     torch = _torch()

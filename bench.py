@@ -76,10 +76,10 @@ def cpu_baseline() -> dict:
 # (cube side, form), from rocprofv3 FETCH_SIZE and WRITE_SIZE counters scaled by a
 # 1 GiB copy (the summaries under profiles/); valid only for that workload, its fixed
 # execution settings (CUBE64_SETTINGS) and the kernel sources hashed here.
-SCHUR_TRAFFIC = {(64, "mixed"): {"sources_sha256": "c7c6747020f832be82d08a2e8c2ec47b88a66bd90e107ab404e724fb14de2c17",
-                                   "bytes_per_launch": 12475000966},
-                 (64, "fp64"): {"sources_sha256": "c7c6747020f832be82d08a2e8c2ec47b88a66bd90e107ab404e724fb14de2c17",
-                                  "bytes_per_launch": 13125623040}}
+SCHUR_TRAFFIC = {(64, "mixed"): {"sources_sha256": "583c2b91efba2d15f0094b054d3bf31082d88c5557bfbe1fa44f12786e4d14f0",
+                                   "bytes_per_launch": 12904049067},
+                 (64, "fp64"): {"sources_sha256": "583c2b91efba2d15f0094b054d3bf31082d88c5557bfbe1fa44f12786e4d14f0",
+                                  "bytes_per_launch": 13125095600}}
 
 
 def kernel_sources_sha256() -> str:

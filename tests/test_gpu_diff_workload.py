@@ -39,13 +39,15 @@ def _field(torch, Gobs_t, chi_t, x, k2h3):
     return Gobs_t @ (k2h3 * chi_t.to(torch.complex128) * x)
 
 
-def _log(msg):
-    print(f"[48^3 gradient] {msg}", flush=True)
-
-
-def test_differentiation_workload_against_central_differences():
+def test_differentiation_workload_against_central_differences(capsys):
     import time
     torch = _torch()
+
+    def _log(msg):
+        # progress straight to the terminal: the whole test runs for minutes
+        with capsys.disabled():
+            print(f"[48^3 gradient] {msg}", flush=True)
+
     from paper_1703_06155_amd.autograd import h2_solve
     t0 = time.perf_counter()
     pr = I.config(4)

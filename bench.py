@@ -178,10 +178,11 @@ def copy_calibration(torch):
 def batch_leg(torch, h2, I, chunk: int) -> dict:
     """Independent box problems (sides U{12..32} cells, leaf 48, eps 1e-4, 16 plane-wave
     right-hand sides each): factor + 16-RHS solve refined to 1e-8, one problem at a time
-    in FP64 versus batched (h2_factor_batch_mode / h2_solve_batch, graph-replayed sweeps):
-    fused launches across problems in FP64 and in the mixed form, and one stream per
-    problem in FP64, in chunks of `chunk` problems whose handles are released after their
-    solve.  Every run reports the largest final residual over the problems."""
+    in FP64 versus batched (h2_factor_batch_mode / h2_solve_batch_mode): fused launches
+    across problems (factorization and sweeps) in FP64 and in the mixed form, and one
+    stream per problem (graph-replayed sweeps) in FP64, in chunks of `chunk` problems
+    whose handles are released after their solve.  Every run reports the largest final
+    residual over the problems."""
     probs = I.batch_problems(count=64, nrhs=16)
     n_total = sum(pr.n for pr in probs)
 
@@ -194,12 +195,12 @@ def batch_leg(torch, h2, I, chunk: int) -> dict:
                   for pr in part]
             rhs = [torch.from_numpy(pr.rhs.copy()).cuda() for pr in part]
             for G in hs:
-                G.set_sweep_graph(batched)
+                G.set_sweep_graph(mode == "streams")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if batched:
                 h2.factor_batch(hs, mode=mode)
-                _, infos = h2.solve_batch(hs, rhs, tol=1e-8, max_iter=20, info=True)
+                _, infos = h2.solve_batch(hs, rhs, tol=1e-8, max_iter=20, info=True, mode=mode)
             else:
                 infos = []
                 for G, b in zip(hs, rhs):

@@ -286,10 +286,24 @@ h2_status h2_factor_batch_mode(h2_handle* hs, int32_t count, void* hip_stream, i
 
 /* x[k] = M_k^-1 b[k] for every handle k as h2_solve does (nrhs columns,
  * leading dimension ld[k], refinement to tol when tol > 0, infos[k] when infos
- * is not NULL), concurrently in the manner of H2_BATCH_STREAMS.  b[k], x[k] are
- * device pointers; b[k] and x[k] may alias. */
+ * is not NULL): h2_solve_batch_mode with H2_BATCH_FUSED.  b[k], x[k] are device
+ * pointers; b[k] and x[k] may alias. */
 h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
                          const int64_t* ld, double tol, int32_t max_iter, void* hip_stream, h2_solve_info* infos);
+
+/* Batched solves (Algs. 5-6, refined as h2_solve).  H2_BATCH_FUSED: on hip_stream,
+ * the problems' sweeps run in lockstep, every stage of a colour (forward local
+ * products and gathers, backward partial sums and local products) one launch
+ * over all problems that have that colour; merges, final blocks and the
+ * refinement residuals per problem; one host synchronisation per refinement
+ * step for all problems; problems leave the refinement as they converge.
+ * H2_BATCH_STREAMS: a stream per handle driven by up to eight host threads.
+ * Results equal h2_solve's bit for bit in both modes.  A failing problem
+ * (H2_ERR_NOCONV) is reported ("batch item k: ...") after the others finish;
+ * infos[k] is filled for every problem. */
+h2_status h2_solve_batch_mode(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
+                              const int64_t* ld, double tol, int32_t max_iter, void* hip_stream, h2_solve_info* infos,
+                              int32_t mode);
 
 /* Release every resource of H (NULL is ignored). */
 void h2_destroy(h2_handle H);

@@ -108,6 +108,9 @@ def lib():
         L.h2_solve_batch.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                      ctypes.c_int32, _I64P, ctypes.c_double, ctypes.c_int32, _P,
                                      ctypes.POINTER(SolveInfo)]
+        L.h2_solve_batch_mode.argtypes = [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                          ctypes.c_int32, _I64P, ctypes.c_double, ctypes.c_int32, _P,
+                                          ctypes.POINTER(SolveInfo), ctypes.c_int32]
         L.h2_matvec.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _P]
         L.h2_destroy.argtypes = [_P]
         L.h2_destroy.restype = None
@@ -131,7 +134,7 @@ def lib():
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
-                     "h2_factor_batch_mode",
+                     "h2_factor_batch_mode", "h2_solve_batch_mode",
                      "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing",
                      "h2_solve_noalloc", "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level",
                      "h2_set_schur_split", "h2_set_mixed_flush", "h2_tune", "h2_tune_cache_clear"):
@@ -462,8 +465,13 @@ def factor_batch(solvers, stream=None, mode="fused"):
     return solvers
 
 
-def solve_batch(solvers, rhs, tol=0.0, max_iter=20, stream=None, info=False):
-    """x_k = M_k^-1 b_k for every handle (h2_solve_batch); every b_k has the same number of columns."""
+def solve_batch(solvers, rhs, tol=0.0, max_iter=20, stream=None, info=False, mode="fused"):
+    """x_k = M_k^-1 b_k for every handle (h2_solve_batch_mode); every b_k has the same number of
+    columns.  mode "fused" runs the sweeps of all problems in shared launches, "streams" gives
+    each handle a stream of its own."""
+    modes = {"fused": H2_BATCH_FUSED, "streams": H2_BATCH_STREAMS}
+    if mode not in modes:
+        raise ValueError(f"mode must be one of {sorted(modes)}")
     torch = _torch()
     bufs, outs, nrhs = [], [], None
     for sv, b in zip(solvers, rhs):
@@ -480,8 +488,8 @@ def solve_batch(solvers, rhs, tol=0.0, max_iter=20, stream=None, info=False):
     xp = (_P * cnt)(*[o.data_ptr() for o in outs])
     ld = np.ascontiguousarray([sv.n for sv in solvers], dtype=np.int64)
     infos = (SolveInfo * cnt)()
-    _check(lib().h2_solve_batch(hs, cnt, bp, xp, nrhs, ld.ctypes.data_as(_I64P), float(tol), int(max_iter),
-                                _stream_ptr(stream), infos), "h2_solve_batch")
+    _check(lib().h2_solve_batch_mode(hs, cnt, bp, xp, nrhs, ld.ctypes.data_as(_I64P), float(tol), int(max_iter),
+                                     _stream_ptr(stream), infos, modes[mode]), "h2_solve_batch_mode")
     xs = [_from_cols(o, vec) for o, (_, vec) in zip(outs, bufs)]
     if info:
         return xs, [{"iterations": i.iterations, "rel_residual": i.rel_residual,

@@ -410,6 +410,7 @@ struct h2_ctx {
   h2::DArr<int32_t> fb_n, fb_k, fb_k1, fb_k2, fb_off1;
   h2::DArr<int64_t> fb_toff, fb_xoff;
   h2::DArr<h2::BatchEntry> batch_entries;  // work items of shared launches when this handle leads a batch
+  h2::DArr<h2::SweepEntry> sweep_entries;  // work items of shared sweep launches when it leads a batched solve
   h2::Stager stage;                        // per-level host arrays on their way to the device
   std::vector<std::vector<int64_t>> stats_rows;
   std::vector<double> level_ms;            // per stats row: ms of that level (Steps 0-3 and its merge) / final LU
@@ -3301,6 +3302,284 @@ static void factor_fused_groups(h2_handle* hs, int32_t count, hipStream_t st) {
   if (bad >= 0) fail(stt[bad], msg[bad]);
 }
 
+// Sweeps of several factored problems in lockstep, each in place on its own
+// vtmp3 (M^-1 or M^-H on Z, eq. 35): level step j is each problem's j-th finest
+// level; every stage of colour c (forward: local products, then the gather into
+// the partners; backward: the partial sums, then the local products) is one
+// launch over all problems that have that colour, the merges between levels and
+// the final block per problem in between.  Each problem's kernels and work
+// items are those of its own sweep, so the results equal one-by-one sweeps bit
+// for bit.  The work item table lives in `lead` (kept for later sweeps).
+static void sweep_fused(h2_handle* hs, const std::vector<int32_t>& act, int nrhs, int adj, hipStream_t st,
+                        h2_handle lead) {
+  const int64_t nact = (int64_t)act.size();
+  std::vector<SweepBufs> W(nact);
+  std::vector<int32_t> fused;
+  int maxlev = 0;
+  for (int64_t a = 0; a < nact; ++a) {
+    h2_ctx* H = hs[act[a]];
+    AllocScope scope(&H->allocator, st);
+    W[a] = handle_bufs(H, nrhs);
+    if (H->flev.empty()) {
+      sweep(H, W[a], H->vtmp3.p, H->vtmp3.p, nrhs, adj, st);  // the whole matrix is one dense block
+      continue;
+    }
+    fused.push_back((int32_t)a);
+    maxlev = std::max(maxlev, (int)H->flev.size());
+    HIPCHK(hipMemcpyAsync(W[a].vbuf[0], H->vtmp3.p, H->N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  }
+  if (fused.empty()) return;
+  // ops in stream order: a shared launch (kind 0) or a per-problem merge (1: up,
+  // 2: down) or final block (3)
+  struct Op {
+    int kind, kernel;
+    size_t off;
+    int ne;
+    int64_t blocks;
+    int32_t a, j;
+  };
+  std::vector<Op> ops;
+  std::vector<SweepEntry> ent;
+  std::vector<std::pair<int, SweepEntry>> pairs;
+  auto add_stage = [&](int stage, int j, int c) {
+    pairs.clear();
+    for (int32_t a : fused) {
+      h2_ctx* H = hs[act[a]];
+      if (j >= (int)H->flev.size()) continue;
+      FactorLevel& F = H->flev[j];
+      LevelPlan& P = H->plans[j];
+      if (c >= P.ncol) continue;
+      const ColourTasks ct = colour_tasks(P.cols[c], c, F.tiles);
+      sweep_stage_entries(stage, F.view, ct, W[a].vbuf[j], F.d_voff.p, F.ntot, nrhs, adj, W[a].part, BWD_SPLIT,
+                          W[a].scratch, pairs);
+    }
+    std::stable_sort(pairs.begin(), pairs.end(),
+                     [](const std::pair<int, SweepEntry>& x, const std::pair<int, SweepEntry>& y) {
+                       return x.first < y.first;
+                     });
+    for (size_t i = 0; i < pairs.size();) {
+      Op o{0, pairs[i].first, ent.size(), 0, 0, -1, j};
+      for (; i < pairs.size() && pairs[i].first == o.kernel; ++i) {
+        SweepEntry e = pairs[i].second;
+        e.first = (int32_t)o.blocks;
+        o.blocks += (int64_t)e.gx * e.gy * e.gz;
+        if (o.blocks > INT32_MAX) fail(H2_ERR_INTERNAL, "shared sweep launch beyond 2^31 workgroups");
+        ent.push_back(e);
+        ++o.ne;
+      }
+      ops.push_back(o);
+    }
+  };
+  auto maxcol = [&](int j) {
+    int m = 0;
+    for (int32_t a : fused) {
+      h2_ctx* H = hs[act[a]];
+      if (j < (int)H->flev.size()) m = std::max(m, H->plans[j].ncol);
+    }
+    return m;
+  };
+  for (int j = 0; j < maxlev; ++j) {
+    const int mc = maxcol(j);
+    for (int c = 0; c < mc; ++c) {
+      add_stage(SS_FWD_LOCAL, j, c);
+      add_stage(SS_FWD_GATHER, j, c);
+    }
+    for (int32_t a : fused) {
+      const int nlev = (int)hs[act[a]]->flev.size();
+      if (j < nlev) ops.push_back({j + 1 < nlev ? 1 : 3, 0, 0, 0, 0, a, j});
+    }
+  }
+  for (int j = maxlev - 1; j >= 0; --j) {
+    for (int32_t a : fused) {
+      const int nlev = (int)hs[act[a]]->flev.size();
+      if (j + 1 < nlev) ops.push_back({2, 0, 0, 0, 0, a, j});
+    }
+    for (int c = maxcol(j) - 1; c >= 0; --c) {
+      add_stage(SS_BWD_PARTIAL, j, c);
+      add_stage(SS_BWD_LOCAL, j, c);
+    }
+  }
+  {
+    AllocScope scope(&lead->allocator, st);
+    lead->sweep_entries.upload(ent, st);
+  }
+  const SweepEntry* d_ent = lead->sweep_entries.p;
+  for (const Op& o : ops) {
+    if (o.kind == 0) {
+      launch_sweep_batched(o.kernel, d_ent + o.off, o.ne, (int)o.blocks, st);
+      continue;
+    }
+    h2_ctx* H = hs[act[o.a]];
+    const SweepBufs& B = W[o.a];
+    FactorLevel& F = H->flev[o.j];
+    LevelPlan& P = H->plans[o.j];
+    const int npar = H->S.nclusters(P.l - 1);
+    if (o.kind == 1 || o.kind == 2) {
+      FactorLevel& Fp = H->flev[o.j + 1];
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, Fp.d_voff.p, F.ntot, Fp.ntot, nrhs, B.vbuf[o.j], B.vbuf[o.j + 1],
+                    o.kind == 1 ? 1 : 0, P.d_nonempty.p, st);
+    } else {
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, B.vbuf[o.j], B.vtmp, 1,
+                    P.d_nonempty.p, st);
+      dense_lu_apply(H, B.vtmp, B.vtmp2, nrhs, adj, st);
+      launch_vmerge(npar, F.d_kt.p, F.d_voff.p, H->d_final_off.p, F.ntot, H->nf, nrhs, B.vbuf[o.j], B.vtmp2, 0,
+                    P.d_nonempty.p, st);
+    }
+  }
+  check_launch("batched sweeps");
+  for (int32_t a : fused) {
+    h2_ctx* H = hs[act[a]];
+    HIPCHK(hipMemcpyAsync(H->vtmp3.p, W[a].vbuf[0], H->N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, st));
+  }
+}
+
+// h2_solve for every handle of a batch in lockstep on one stream (the refinement
+// of eq. 35's solution against A_H2 as in solve_refined; the sweeps of all
+// problems that still refine are fused).  A problem that fails (non-finite
+// residual, tolerance not reached) is reported and the others go on.
+static void solve_fused(h2_handle* hs, int32_t count, int adj, const void* const* b, void* const* x, int32_t nrhs,
+                        const int64_t* ld, double tol, int32_t max_iter, hipStream_t st, h2_solve_info* infos) {
+  check_batch(hs, count);
+  if (!(tol >= 0) || !std::isfinite(tol)) fail(H2_ERR_ARG, "tol must be finite and >= 0");
+  if (tol > 0 && max_iter < 1) fail(H2_ERR_ARG, "max_iter < 1 with tol > 0");
+  for (int32_t k = 0; k < count; ++k) {
+    validate_vec(hs[k], b[k], x[k], nrhs, ld[k]);
+    if (!hs[k]->factored) fail(H2_ERR_STATE, "batch item " + std::to_string(k) + ": solve before a successful h2_factor");
+  }
+  h2_handle lead = hs[0];
+  auto perm_in = [&](h2_ctx* H, const double2* rhs, int64_t ldr) {
+    if (!adj)
+      launch_permute_in(rhs, ldr, H->d_perm.p, nullptr, 0, H->N, nrhs, H->vtmp3.p, H->N, st);
+    else
+      launch_permute_in(rhs, ldr, H->d_perm.p, H->d_scale_solve.p, 0, H->N, nrhs, H->vtmp3.p, H->N, st);
+  };
+  auto perm_out = [&](h2_ctx* H, double2* outx, int64_t ldo, int accumulate) {
+    if (!adj)
+      launch_permute_out(H->vtmp3.p, H->N, H->d_perm.p, H->d_scale_solve.p, 0, H->N, nrhs, outx, ldo, accumulate, st);
+    else
+      launch_permute_out(H->vtmp3.p, H->N, H->d_perm.p, nullptr, 0, H->N, nrhs, outx, ldo, accumulate, st);
+  };
+  std::vector<int32_t> act(count);
+  for (int32_t k = 0; k < count; ++k) {
+    act[k] = k;
+    AllocScope scope(&hs[k]->allocator, st);
+    ensure_vbuf(hs[k], nrhs);
+    if (infos) {
+      infos[k].iterations = 0;
+      infos[k].rel_residual = -1.0;
+      infos[k].rel_residual_first = -1.0;
+    }
+  }
+  if (tol <= 0) {
+    for (int32_t k = 0; k < count; ++k) perm_in(hs[k], (const double2*)b[k], ld[k]);
+    sweep_fused(hs, act, nrhs, adj, st, lead);
+    for (int32_t k = 0; k < count; ++k) perm_out(hs[k], (double2*)x[k], ld[k], 0);
+    check_launch("batched solve");
+    return;
+  }
+  std::vector<std::vector<double>> nb(count, std::vector<double>(nrhs)), nr(count, std::vector<double>(nrhs));
+  std::vector<int> it(count, 0);
+  std::vector<double> first(count, -1.0), rel(count, 0.0);
+  for (int32_t k = 0; k < count; ++k) {
+    h2_ctx* H = hs[k];
+    AllocScope scope(&H->allocator, st);
+    const int64_t N = H->N;
+    H->rf_b0.alloc(N * nrhs);
+    HIPCHK(hipMemcpy2DAsync(H->rf_b0.p, N * sizeof(double2), b[k], ld[k] * sizeof(double2), N * sizeof(double2), nrhs,
+                            hipMemcpyDeviceToDevice, st));
+    H->rf_r.alloc(N * nrhs);
+    H->rf_ax.alloc(N * nrhs);
+    H->rf_vt.alloc(N * nrhs);
+    H->rf_nb.alloc(nrhs);
+    perm_in(H, H->rf_b0.p, N);
+  }
+  sweep_fused(hs, act, nrhs, adj, st, lead);
+  for (int32_t k = 0; k < count; ++k) {
+    h2_ctx* H = hs[k];
+    perm_out(H, (double2*)x[k], ld[k], 0);
+    launch_col_norms(H->rf_b0.p, H->N, H->N, nrhs, H->rf_nb.p, st);
+    HIPCHK(hipMemcpyAsync(nb[k].data(), H->rf_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  h2_status first_err = H2_OK;
+  std::string first_msg;
+  // the residuals run side by side, each problem's on a stream of its own after
+  // everything queued on st; st waits for all of them
+  for (int32_t k = 0; k < count; ++k)
+    if (!hs[k]->own_stream) HIPCHK(hipStreamCreateWithFlags(&hs[k]->own_stream, hipStreamNonBlocking));
+  EventPool rev;
+  while (!act.empty()) {
+    hipEvent_t ready = rev.next(st);
+    for (int32_t k : act) {
+      h2_ctx* H = hs[k];
+      const int64_t N = H->N;
+      double2* xx = (double2*)x[k];
+      const hipStream_t st = H->own_stream;  // this problem's residual
+      AllocScope scope(&H->allocator, st);
+      HIPCHK(hipStreamWaitEvent(st, ready, 0));
+      if (!adj) {
+        launch_permute_in(xx, ld[k], H->d_perm.p, H->d_scale_mat.p, 0, N, nrhs, H->rf_vt.p, N, st);
+        matvec_tree(H, H->rf_vt.p, H->vtmp3.p, nrhs, st);
+        launch_permute_out(H->vtmp3.p, N, H->d_perm.p, nullptr, 0, N, nrhs, H->rf_ax.p, N, 0, st);
+      } else {
+        launch_permute_in(xx, ld[k], H->d_perm.p, nullptr, 1, N, nrhs, H->rf_vt.p, N, st);
+        matvec_tree(H, H->rf_vt.p, H->vtmp3.p, nrhs, st);
+        launch_permute_out(H->vtmp3.p, N, H->d_perm.p, H->d_scale_mat.p, 1, N, nrhs, H->rf_ax.p, N, 0, st);
+      }
+      launch_residual(H->rf_b0.p, N, H->rf_ax.p, N, H->rf_r.p, N, N, nrhs, st);
+      launch_col_norms(H->rf_r.p, N, N, nrhs, H->rf_nb.p, st);
+    }
+    check_launch("batched refinement residuals");
+    for (int32_t k : act) HIPCHK(hipStreamWaitEvent(st, rev.next(hs[k]->own_stream), 0));
+    // the norms come back on st once every residual is done (one host wait)
+    for (int32_t k : act)
+      HIPCHK(hipMemcpyAsync(nr[k].data(), hs[k]->rf_nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int32_t> next;
+    for (int32_t k : act) {
+      double r = 0;
+      bool finite = true;
+      for (int c = 0; c < nrhs; ++c) {
+        const double rc = nb[k][c] > 0 ? nr[k][c] / nb[k][c] : nr[k][c];
+        if (!std::isfinite(rc)) finite = false;
+        r = std::max(r, rc);
+      }
+      if (!finite) r = std::numeric_limits<double>::infinity();
+      rel[k] = r;
+      if (first[k] < 0) first[k] = r;
+      std::string msg;
+      if (!finite) {
+        msg = "refinement residual is not finite after " + std::to_string(it[k]) + " iterations";
+      } else if (r > tol && it[k] >= max_iter) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "refinement did not reach tol within max_iter (relative residual %.3e after %d iterations, %.3e before)",
+                 r, it[k], first[k]);
+        msg = buf;
+      }
+      if (!msg.empty() && first_err == H2_OK) {
+        first_err = H2_ERR_NOCONV;
+        first_msg = "batch item " + std::to_string(k) + ": " + msg;
+      }
+      if (msg.empty() && r > tol) next.push_back(k);
+    }
+    act.swap(next);
+    if (act.empty()) break;
+    for (int32_t k : act) perm_in(hs[k], hs[k]->rf_r.p, hs[k]->N);
+    sweep_fused(hs, act, nrhs, adj, st, lead);
+    for (int32_t k : act) {
+      perm_out(hs[k], (double2*)x[k], ld[k], 1);
+      ++it[k];
+    }
+  }
+  if (infos)
+    for (int32_t k = 0; k < count; ++k) {
+      infos[k].iterations = it[k];
+      infos[k].rel_residual = rel[k];
+      infos[k].rel_residual_first = first[k];
+    }
+  if (first_err != H2_OK) fail(first_err, first_msg);
+}
+
 extern "C" h2_status h2_solve(h2_handle H, const void* b, void* x, int32_t nrhs, int64_t ld, double tol,
                               int32_t max_iter, void* hip_stream, h2_solve_info* info) {
   return guarded([&] {
@@ -3380,16 +3659,27 @@ extern "C" h2_status h2_factor_batch(h2_handle* hs, int32_t count, void* hip_str
   return h2_factor_batch_mode(hs, count, hip_stream, H2_BATCH_FUSED);
 }
 
-extern "C" h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
-                                    const int64_t* ld, double tol, int32_t max_iter, void* hip_stream,
-                                    h2_solve_info* infos) {
+extern "C" h2_status h2_solve_batch_mode(h2_handle* hs, int32_t count, const void* const* b, void* const* x,
+                                         int32_t nrhs, const int64_t* ld, double tol, int32_t max_iter,
+                                         void* hip_stream, h2_solve_info* infos, int32_t mode) {
   return guarded([&] {
     if (!b || !x || !ld) fail(H2_ERR_ARG, "null pointer");
+    if (mode != H2_BATCH_FUSED && mode != H2_BATCH_STREAMS) fail(H2_ERR_ARG, "unknown batch mode");
+    if (mode == H2_BATCH_FUSED) {
+      solve_fused(hs, count, 0, b, x, nrhs, ld, tol, max_iter, (hipStream_t)hip_stream, infos);
+      return;
+    }
     run_batch(hs, count, (hipStream_t)hip_stream, [&](int32_t k, hipStream_t s) {
       solve_refined(hs[k], 0, b[k], x[k], nrhs, ld[k], tol, max_iter, s, infos ? &infos[k] : nullptr);
       if (tol <= 0) HIPCHK(hipStreamSynchronize(s));
     });
   });
+}
+
+extern "C" h2_status h2_solve_batch(h2_handle* hs, int32_t count, const void* const* b, void* const* x, int32_t nrhs,
+                                    const int64_t* ld, double tol, int32_t max_iter, void* hip_stream,
+                                    h2_solve_info* infos) {
+  return h2_solve_batch_mode(hs, count, b, x, nrhs, ld, tol, max_iter, hip_stream, infos, H2_BATCH_FUSED);
 }
 
 extern "C" h2_status h2_contrast_gradient(h2_handle H, const void* x, const void* g, const void* lam, int32_t nrhs,

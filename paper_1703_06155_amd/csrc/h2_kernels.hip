@@ -63,6 +63,44 @@ __device__ __forceinline__ EntryRef locate(const BatchEntry* E, int ne, VBlock& 
   return {*(const LevelView*)&e.v, *(const ColourTasks*)&e.c, e.buf, e.aux, e.i0};
 }
 
+// The same for the entries of a shared sweep launch.
+typedef const __attribute__((address_space(4))) SweepEntry ConstSweepEntry;
+struct SweepRef {
+  const LevelView& v;
+  const ColourTasks& c;
+  double2* vec;
+  const int64_t* voff;
+  int64_t ldv;
+  int nrhs, adj;
+  double2* part;
+  int nsplit;
+  double2* scratch;
+};
+__device__ __forceinline__ SweepRef locate_sweep(const SweepEntry* E, int ne, VBlock& VB) {
+  ConstSweepEntry* CE = (ConstSweepEntry*)E;
+  const int lin = blockIdx.x;
+  int lo = 0, hi = ne - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (CE[mid].first <= lin)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  ConstSweepEntry& e = CE[lo];
+  int r = lin - e.first;
+  VB.gx = e.gx;
+  VB.gy = e.gy;
+  VB.gz = e.gz;
+  VB.x = r % e.gx;
+  r /= e.gx;
+  VB.y = r % e.gy;
+  VB.z = r / e.gy;
+  return {*(const LevelView*)&e.v, *(const ColourTasks*)&e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, e.part, e.nsplit,
+          e.scratch};
+}
+
 static inline __host__ __device__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 // ===========================================================================
@@ -2914,15 +2952,15 @@ __device__ void wg_gemm(TileSmem<double>& s, const double2* A, int64_t lda, int 
 // Forward (adj 0): b_i <- Q~^H b_i, b_i' <- (L^-1 P) b_i'.
 // Adjoint phase A (adj 1): g_i <- Q~^T g_i, g_i' <- U^-H g_i'.
 // scratch: (ncl * gridDim.z) blocks of (64 tiles) x 64.
-__global__ void __launch_bounds__(256) k_sw_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
-                                                      int64_t ldv, int nrhs, int adj, double2* scratch) {
+__device__ __forceinline__ void k_sw_fwd_local_body(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, double2* scratch, const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (n == 0) return;
-  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int c0 = VB.z * 64, nr = min(64, nrhs - c0);
   const int ldy = c.tiles * 64;
-  double2* Y = scratch + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * ldy * 64;
+  double2* Y = scratch + ((int64_t)VB.z * VB.gx + VB.x) * ldy * 64;
   double2* b = vec + voff[i] + (int64_t)c0 * ldv;
   const double2* Q = v.Q + v.q_off[i];
   wg_gemm(s, Q, n, adj ? OP_T : OP_C, b, ldv, OP_N, Y, ldy, n, nr, n, ST_SET);
@@ -2940,18 +2978,27 @@ __global__ void __launch_bounds__(256) k_sw_fwd_local(LevelView v, ColourTasks c
       wg_gemm(s, Ui, rmax, OP_C, Y + kt, ldy, OP_N, b + kt, ldv, r, nr, r, ST_SET);
   }
 }
+__global__ void __launch_bounds__(256) k_sw_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, double2* scratch) {
+  k_sw_fwd_local_body(v, c, vec, voff, ldv, nrhs, adj, scratch, vblock());
+}
+__global__ void __launch_bounds__(256) k_sw_fwd_local_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sw_fwd_local_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, e.scratch, VB);
+}
 
 // b_a[0:m_a] -= sum_i C_i[a] b_i'  (adj: g_a -= R_i[:, a]^H g_i').  grid: (target, row tiles, rhs blocks)
-__global__ void __launch_bounds__(256) k_sw_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
-                                                       int64_t ldv, int nrhs, int adj) {
+__device__ __forceinline__ void k_sw_fwd_gather_body(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                       int64_t ldv, int nrhs, int adj, const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int task = blockIdx.x;
+  const int task = VB.x;
   const int a = c.sv_cl[task];
   const int ma = dim_after(v, a, c.colour);
-  const int tr = blockIdx.y;
+  const int tr = VB.y;
   if (tr * 64 >= ma) return;
   const int m = min(64, ma - tr * 64);
-  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int c0 = VB.z * 64, nr = min(64, nrhs - c0);
   TileAcc<double> acc;
   acc.zero();
   for (int e = c.sv_cptr[task]; e < c.sv_cptr[task + 1]; ++e) {
@@ -2970,19 +3017,28 @@ __global__ void __launch_bounds__(256) k_sw_fwd_gather(LevelView v, ColourTasks 
   }
   store_tile<double, double2>(acc, vec + voff[a] + tr * 64 + (int64_t)c0 * ldv, ldv, m, nr, ST_SUB);
 }
+__global__ void __launch_bounds__(256) k_sw_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                       int64_t ldv, int nrhs, int adj) {
+  k_sw_fwd_gather_body(v, c, vec, voff, ldv, nrhs, adj, vblock());
+}
+__global__ void __launch_bounds__(256) k_sw_fwd_gather_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sw_fwd_gather_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, VB);
+}
 
 // Partial sums of the backward gather: part_j = sum over partners of chunk j of
 // R_i[:, a] y_a (adj: C_i[a, :]^H g_a).  grid: (cluster, chunk, rhs blocks)
-__global__ void __launch_bounds__(256) k_sw_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+__device__ __forceinline__ void k_sw_bwd_partial_body(LevelView v, ColourTasks c, const double2* vec,
                                                         const int64_t* voff, int64_t ldv, int nrhs, int adj,
-                                                        double2* part, int nsplit) {
+                                                        double2* part, int nsplit, const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
-  const int chunk = blockIdx.y;
-  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int chunk = VB.y;
+  const int c0 = VB.z * 64, nr = min(64, nrhs - c0);
   const int ldp = c.tiles * 64;
-  double2* P = part + (((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * nsplit + chunk) * ldp * 64;
+  double2* P = part + (((int64_t)VB.z * VB.gx + VB.x) * nsplit + chunk) * ldp * 64;
   if (r <= 0) return;
   const int pr = v.prow[i];
   for (int tr = 0; tr * 64 < r; ++tr) {
@@ -3004,21 +3060,31 @@ __global__ void __launch_bounds__(256) k_sw_bwd_partial(LevelView v, ColourTasks
     store_tile<double, double2>(acc, P + tr * 64, ldp, m, nr, ST_SET);
   }
 }
+__global__ void __launch_bounds__(256) k_sw_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+                                                        const int64_t* voff, int64_t ldv, int nrhs, int adj,
+                                                        double2* part, int nsplit) {
+  k_sw_bwd_partial_body(v, c, vec, voff, ldv, nrhs, adj, part, nsplit, vblock());
+}
+__global__ void __launch_bounds__(256) k_sw_bwd_partial_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sw_bwd_partial_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, e.part, e.nsplit, VB);
+}
 
 // Backward (adj 0): y_i' <- U^-1 (y_i' - sum parts), y_i <- conj(Q~) y_i.
 // Adjoint phase B (adj 1): g_i' <- (L^-1 P)^H (g_i' - sum parts), g_i <- Q~ g_i.
-__global__ void __launch_bounds__(256) k_sw_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+__device__ __forceinline__ void k_sw_bwd_local_body(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
                                                       int64_t ldv, int nrhs, int adj, const double2* part, int nsplit,
-                                                      double2* scratch) {
+                                                      double2* scratch, const VBlock& VB) {
   __shared__ TileSmem<double> s;
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   if (n == 0) return;
-  const int c0 = blockIdx.z * 64, nr = min(64, nrhs - c0);
+  const int c0 = VB.z * 64, nr = min(64, nrhs - c0);
   const int ldp = c.tiles * 64;
-  double2* Y = scratch + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * ldp * 64;
+  double2* Y = scratch + ((int64_t)VB.z * VB.gx + VB.x) * ldp * 64;
   double2* y = vec + voff[i] + (int64_t)c0 * ldv;
-  const double2* P = part + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * nsplit * ldp * 64;
+  const double2* P = part + ((int64_t)VB.z * VB.gx + VB.x) * nsplit * ldp * 64;
   // Y = [y[0:kt]; acc] with acc = y' - sum of the partial sums
   for (int e = threadIdx.x; e < n * nr; e += blockDim.x) {
     const int row = e % n, col = e / n;
@@ -3045,6 +3111,16 @@ __global__ void __launch_bounds__(256) k_sw_bwd_local(LevelView v, ColourTasks c
   }
   const double2* Q = v.Q + v.q_off[i];
   wg_gemm(s, Q, n, adj ? OP_N : OP_R, Y, ldp, OP_N, y, ldv, n, nr, n, ST_SET);
+}
+__global__ void __launch_bounds__(256) k_sw_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, const double2* part, int nsplit,
+                                                      double2* scratch) {
+  k_sw_bwd_local_body(v, c, vec, voff, ldv, nrhs, adj, part, nsplit, scratch, vblock());
+}
+__global__ void __launch_bounds__(256) k_sw_bwd_local_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sw_bwd_local_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, e.part, e.nsplit, e.scratch, VB);
 }
 
 // ---------------------------------------------------------------------------
@@ -3123,10 +3199,10 @@ __device__ void bv_gemv_t(const double2* M, int64_t ld, int m, int n, const doub
   }
 }
 
-__global__ void __launch_bounds__(SV_NT) k_sv_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
-                                                      int64_t ldv, int nrhs, int adj) {
+__device__ __forceinline__ void k_sv_fwd_local_body(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, const VBlock& VB) {
   __shared__ double2 xs[512], ys[512];
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   const double2* Q = v.Q + v.q_off[i];
   const double2* Li = v.LU + v.lu_off[i];
@@ -3147,6 +3223,15 @@ __global__ void __launch_bounds__(SV_NT) k_sv_fwd_local(LevelView v, ColourTasks
     }
   }
 }
+__global__ void __launch_bounds__(SV_NT) k_sv_fwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj) {
+  k_sv_fwd_local_body(v, c, vec, voff, ldv, nrhs, adj, vblock());
+}
+__global__ void __launch_bounds__(SV_NT) k_sv_fwd_local_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sv_fwd_local_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, VB);
+}
 
 // Sum over the wavefronts' partial results of the 1-RHS gather kernels.
 __device__ __forceinline__ double2 red_sum(const double2 (*red)[128], int t) {
@@ -3156,10 +3241,10 @@ __device__ __forceinline__ double2 red_sum(const double2 (*red)[128], int t) {
   return s;
 }
 
-__global__ void __launch_bounds__(SV_NT) k_sv_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
-                                                       int64_t ldv, int nrhs, int adj) {
+__device__ __forceinline__ void k_sv_fwd_gather_body(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                       int64_t ldv, int nrhs, int adj, const VBlock& VB) {
   __shared__ double2 red[SV_NW][128];
-  const int task = blockIdx.x;
+  const int task = VB.x;
   const int a = c.sv_cl[task];
   const int ma = dim_after(v, a, c.colour);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -3217,16 +3302,25 @@ __global__ void __launch_bounds__(SV_NT) k_sv_fwd_gather(LevelView v, ColourTask
     }
   }
 }
+__global__ void __launch_bounds__(SV_NT) k_sv_fwd_gather(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                       int64_t ldv, int nrhs, int adj) {
+  k_sv_fwd_gather_body(v, c, vec, voff, ldv, nrhs, adj, vblock());
+}
+__global__ void __launch_bounds__(SV_NT) k_sv_fwd_gather_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sv_fwd_gather_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, VB);
+}
 
-__global__ void __launch_bounds__(SV_NT) k_sv_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+__device__ __forceinline__ void k_sv_bwd_partial_body(LevelView v, ColourTasks c, const double2* vec,
                                                         const int64_t* voff, int64_t ldv, int nrhs, int adj,
-                                                        double2* part, int nsplit) {
+                                                        double2* part, int nsplit, const VBlock& VB) {
   __shared__ double2 red[SV_NW][128];
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
-  const int chunk = blockIdx.y;
+  const int chunk = VB.y;
   const int ldp = c.tiles * 64;
-  double2* P = part + ((int64_t)blockIdx.x * nsplit + chunk) * ldp * SMALL_RHS;  // ldp x nrhs partial per chunk
+  double2* P = part + ((int64_t)VB.x * nsplit + chunk) * ldp * SMALL_RHS;  // ldp x nrhs partial per chunk
   if (r <= 0) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int pr = v.prow[i];
@@ -3278,18 +3372,28 @@ __global__ void __launch_bounds__(SV_NT) k_sv_bwd_partial(LevelView v, ColourTas
     }
   }
 }
+__global__ void __launch_bounds__(SV_NT) k_sv_bwd_partial(LevelView v, ColourTasks c, const double2* vec,
+                                                        const int64_t* voff, int64_t ldv, int nrhs, int adj,
+                                                        double2* part, int nsplit) {
+  k_sv_bwd_partial_body(v, c, vec, voff, ldv, nrhs, adj, part, nsplit, vblock());
+}
+__global__ void __launch_bounds__(SV_NT) k_sv_bwd_partial_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sv_bwd_partial_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, e.part, e.nsplit, VB);
+}
 
-__global__ void __launch_bounds__(SV_NT) k_sv_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+__device__ __forceinline__ void k_sv_bwd_local_body(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
                                                       int64_t ldv, int nrhs, int adj, const double2* part,
-                                                      int nsplit) {
+                                                      int nsplit, const VBlock& VB) {
   __shared__ double2 xs[512], ys[512];
-  const int i = c.cl[blockIdx.x];
+  const int i = c.cl[VB.x];
   const int n = v.n[i], kt = v.kt[i], r = n - kt, rmax = n - v.k[i];
   const int ldp = c.tiles * 64;
   const double2* Q = v.Q + v.q_off[i];
   const double2* Li = v.LU + v.lu_off[i];
   const double2* Ui = Li + (int64_t)rmax * rmax;
-  const double2* P = part + (int64_t)blockIdx.x * nsplit * ldp * SMALL_RHS;
+  const double2* P = part + (int64_t)VB.x * nsplit * ldp * SMALL_RHS;
   for (int col = 0; col < nrhs; ++col) {
     double2* y = vec + voff[i] + (int64_t)col * ldv;
     __syncthreads();
@@ -3312,6 +3416,16 @@ __global__ void __launch_bounds__(SV_NT) k_sv_bwd_local(LevelView v, ColourTasks
     }
     bv_gemv_n(Q, n, n, n, xs, y, !adj);  // conj(Q~) y  (adj: Q~ g)
   }
+}
+__global__ void __launch_bounds__(SV_NT) k_sv_bwd_local(LevelView v, ColourTasks c, double2* vec, const int64_t* voff,
+                                                      int64_t ldv, int nrhs, int adj, const double2* part,
+                                                      int nsplit) {
+  k_sv_bwd_local_body(v, c, vec, voff, ldv, nrhs, adj, part, nsplit, vblock());
+}
+__global__ void __launch_bounds__(SV_NT) k_sv_bwd_local_b(const SweepEntry* E, int ne) {
+  VBlock VB;
+  const SweepRef e = locate_sweep(E, ne, VB);
+  k_sv_bwd_local_body(e.v, e.c, e.vec, e.voff, e.ldv, e.nrhs, e.adj, e.part, e.nsplit, VB);
 }
 
 void launch_sweep_fwd(const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff, int64_t ldv,
@@ -3342,6 +3456,78 @@ void launch_sweep_bwd(const LevelView& v, const ColourTasks& c, double2* vec, co
                      nsplit);
   hipLaunchKernelGGL(k_sw_bwd_local, dim3(c.ncl, 1, zb), dim3(256), 0, st, v, c, vec, voff, ldv, nrhs, adj, part, nsplit,
                      scratch);
+}
+
+void sweep_stage_entries(int stage, const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
+                         int64_t ldv, int nrhs, int adj, double2* part, int nsplit, double2* scratch,
+                         std::vector<std::pair<int, SweepEntry>>& out) {
+  if (c.ncl <= 0) return;
+  auto add = [&](int kernel, int gx, int gy, int gz, int ns) {
+    if (gx <= 0 || gy <= 0 || gz <= 0) return;
+    SweepEntry e;
+    e.v = v;
+    e.c = c;
+    e.vec = vec;
+    e.voff = voff;
+    e.ldv = ldv;
+    e.part = part;
+    e.scratch = scratch;
+    e.nrhs = nrhs;
+    e.adj = adj;
+    e.nsplit = ns;
+    e.gx = gx;
+    e.gy = gy;
+    e.gz = gz;
+    e.first = 0;
+    out.emplace_back(kernel, e);
+  };
+  const bool small = nrhs <= SMALL_RHS;
+  const int zb = (nrhs + 63) / 64;
+  switch (stage) {
+    case SS_FWD_LOCAL:
+      if (small)
+        add(SK_SV_FWD_LOCAL, c.ncl, 1, 1, 0);
+      else
+        add(SK_SW_FWD_LOCAL, c.ncl, 1, zb, 0);
+      break;
+    case SS_FWD_GATHER:
+      if (c.nsv <= 0) break;
+      if (small)
+        add(SK_SV_FWD_GATHER, c.nsv, 1, 1, 0);
+      else
+        add(SK_SW_FWD_GATHER, c.nsv, c.tiles, zb, 0);
+      break;
+    case SS_BWD_PARTIAL:
+      if (small)
+        add(SK_SV_BWD_PARTIAL, c.ncl, SV_SPLIT, 1, SV_SPLIT);
+      else
+        add(SK_SW_BWD_PARTIAL, c.ncl, nsplit, zb, nsplit);
+      break;
+    case SS_BWD_LOCAL:
+      if (small)
+        add(SK_SV_BWD_LOCAL, c.ncl, 1, 1, SV_SPLIT);
+      else
+        add(SK_SW_BWD_LOCAL, c.ncl, 1, zb, nsplit);
+      break;
+    default:
+      break;
+  }
+}
+
+void launch_sweep_batched(int kernel, const SweepEntry* entries, int ne, int blocks, hipStream_t st) {
+  if (ne <= 0 || blocks <= 0) return;
+  const dim3 g(blocks), b256(256), bsv(SV_NT);
+  switch (kernel) {
+    case SK_SW_FWD_LOCAL: hipLaunchKernelGGL(k_sw_fwd_local_b, g, b256, 0, st, entries, ne); break;
+    case SK_SW_FWD_GATHER: hipLaunchKernelGGL(k_sw_fwd_gather_b, g, b256, 0, st, entries, ne); break;
+    case SK_SW_BWD_PARTIAL: hipLaunchKernelGGL(k_sw_bwd_partial_b, g, b256, 0, st, entries, ne); break;
+    case SK_SW_BWD_LOCAL: hipLaunchKernelGGL(k_sw_bwd_local_b, g, b256, 0, st, entries, ne); break;
+    case SK_SV_FWD_LOCAL: hipLaunchKernelGGL(k_sv_fwd_local_b, g, bsv, 0, st, entries, ne); break;
+    case SK_SV_FWD_GATHER: hipLaunchKernelGGL(k_sv_fwd_gather_b, g, bsv, 0, st, entries, ne); break;
+    case SK_SV_BWD_PARTIAL: hipLaunchKernelGGL(k_sv_bwd_partial_b, g, bsv, 0, st, entries, ne); break;
+    case SK_SV_BWD_LOCAL: hipLaunchKernelGGL(k_sv_bwd_local_b, g, bsv, 0, st, entries, ne); break;
+    default: break;
+  }
 }
 
 // up = 1: parent vector = [kept(c1); kept(c2)] ; up = 0: children's kept parts from the parent

@@ -126,6 +126,34 @@ enum BatchStage : int {
 void batch_stage_entries(int stage, const LevelView& v, const ColourTasks& c, bool mixed, bool mixed_flush,
                          double2* buf, int64_t aux, int i0, std::vector<std::pair<int, BatchEntry>>& out);
 
+// One problem's share of a shared sweep launch (forward or backward sweep of one
+// colour, Algs. 5-6): the per-problem arguments of the single-problem kernels and
+// the same local grid, placed at workgroup `first` of the shared grid.
+struct SweepEntry {
+  LevelView v;
+  ColourTasks c;
+  double2* vec;
+  const int64_t* voff;
+  int64_t ldv;
+  double2* part;
+  double2* scratch;
+  int32_t nrhs, adj, nsplit;
+  int32_t gx, gy, gz;
+  int32_t first;
+};
+enum SweepKernel : int {
+  SK_SW_FWD_LOCAL, SK_SW_FWD_GATHER, SK_SW_BWD_PARTIAL, SK_SW_BWD_LOCAL,
+  SK_SV_FWD_LOCAL, SK_SV_FWD_GATHER, SK_SV_BWD_PARTIAL, SK_SV_BWD_LOCAL
+};
+// stages of one colour: forward local then gather; backward partial sums then local
+enum SweepStage : int { SS_FWD_LOCAL, SS_FWD_GATHER, SS_BWD_PARTIAL, SS_BWD_LOCAL };
+// The (kernel, entry) pairs one problem's colour contributes to a sweep stage; grids
+// as launch_sweep_fwd / launch_sweep_bwd.
+void sweep_stage_entries(int stage, const LevelView& v, const ColourTasks& c, double2* vec, const int64_t* voff,
+                         int64_t ldv, int nrhs, int adj, double2* part, int nsplit, double2* scratch,
+                         std::vector<std::pair<int, SweepEntry>>& out);
+void launch_sweep_batched(int kernel, const SweepEntry* entries, int ne, int blocks, hipStream_t st);
+
 // Generic host-resolved batched GEMM task: C (op)= op(A) op(B).
 struct GemmTask {
   const double2* A;

@@ -32,7 +32,7 @@ def test_batch_equals_one_by_one(mode):
     for k in range(len(probs)):
         assert np.array_equal(batch[k].stats(), solo[k].stats()), k
     rhs = [torch.from_numpy(pr.rhs.copy()) for pr in probs]
-    xs, infos = h2.solve_batch(batch, rhs, tol=1e-8, info=True)
+    xs, infos = h2.solve_batch(batch, rhs, tol=1e-8, info=True, mode=mode)
     for k, pr in enumerate(probs):
         x1, i1 = solo[k].solve(rhs[k], tol=1e-8, info=True)
         assert np.array_equal(xs[k].cpu().numpy(), x1.cpu().numpy()), k
@@ -41,9 +41,14 @@ def test_batch_equals_one_by_one(mode):
     # plain batched solve with graph-replayed sweeps equals the direct launches
     for G in batch:
         G.set_sweep_graph(True)
-    xg = h2.solve_batch(batch, rhs)
+    xg = h2.solve_batch(batch, rhs, mode=mode)
     for k in range(len(probs)):
         assert np.array_equal(xg[k].cpu().numpy(), solo[k].solve(rhs[k]).cpu().numpy()), k
+    # one right-hand side: the matrix-vector sweep kernels
+    r1 = [r[:, :1].contiguous() for r in rhs]
+    x1 = h2.solve_batch(batch, r1, tol=1e-8, mode=mode)
+    for k in range(len(probs)):
+        assert np.array_equal(x1[k].cpu().numpy(), solo[k].solve(r1[k], tol=1e-8).cpu().numpy()), k
 
 
 def test_batch_rejects_duplicates_and_empty():
@@ -89,6 +94,21 @@ def test_fused_batch_of_mixed_settings_equals_one_by_one():
         b = torch.from_numpy(pr.rhs.copy()).cuda()
         assert np.array_equal(batch[k].solve(b).cpu().numpy(), solo[k].solve(b).cpu().numpy()), k
         assert np.array_equal(batch[k].solve_adjoint(b).cpu().numpy(), solo[k].solve_adjoint(b).cpu().numpy()), k
+    # fused batched solves (three columns, then one), refined and plain, against single solves
+    rhs = [torch.from_numpy(pr.rhs.copy()).cuda() for pr in probs]
+    for cols in (3, 1):
+        rr = [r[:, :cols].contiguous() for r in rhs]
+        xs, infos = h2.solve_batch(batch, rr, tol=1e-9, info=True)
+        x0 = h2.solve_batch(batch, rr)
+        for k in range(len(probs)):
+            xk, ik = solo[k].solve(rr[k], tol=1e-9, info=True)
+            assert np.array_equal(xs[k].cpu().numpy(), xk.cpu().numpy()), (cols, k)
+            assert infos[k]["iterations"] == ik["iterations"], (cols, k)
+            assert np.array_equal(x0[k].cpu().numpy(), solo[k].solve(rr[k]).cpu().numpy()), (cols, k)
+    # a tolerance out of reach in one step: reported for the batch, every problem still solved
+    with pytest.raises(h2.H2Error) as ei:
+        h2.solve_batch(batch, rhs, tol=1e-300, max_iter=1)
+    assert ei.value.status == h2.H2_ERR_NOCONV and "batch item" in str(ei.value)
     # the same handles again: the work item table of the shared launches is reused
     h2.factor_batch(batch)
     for k, pr in enumerate(probs):

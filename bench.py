@@ -268,6 +268,8 @@ def apply_settings(G, settings: dict) -> dict:
         G.set_schur_split(int(v), int(lev))
     for lev, v in settings.get("mixed_flush", {}).items():
         G.set_mixed_flush(int(v), int(lev))
+    for lev, v in settings.get("schur_chunk", {}).items():
+        G.set_schur_chunk(int(v), int(lev))
     return dict(settings, source="fixed (h2_tune)")
 
 

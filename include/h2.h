@@ -157,6 +157,13 @@ h2_status h2_set_schur_split(h2_handle H, int32_t level, int64_t below_wgs);
  * unfactored when it is in the mixed form. */
 h2_status h2_set_mixed_flush(h2_handle H, int32_t level, int32_t mode);
 
+/* Terms per chunk of a split Schur task at a level (level = -1: every level;
+ * terms = -1: the default, 10): a colour's flush that splits (h2_set_schur_split)
+ * cuts every task of more pending terms into chunks of at most this many.
+ * Rebuilds the level's flush lists; the handle becomes unfactored.  Changes
+ * the order in which a block's updates are summed, hence the rounding. */
+h2_status h2_set_schur_chunk(h2_handle H, int32_t level, int32_t terms);
+
 #define H2_TUNING_MAX_LEVELS 64
 
 /* Measured settings of a handle (h2_tune). */
@@ -165,13 +172,15 @@ typedef struct h2_tuning {
   int32_t from_cache;        /* 1: taken from the process-wide cache, only the final factorization ran */
   int64_t split_below[H2_TUNING_MAX_LEVELS]; /* per level l: the Schur split threshold (-1: not factored) */
   int32_t mixed_flush[H2_TUNING_MAX_LEVELS]; /* per level l, mixed form: the flush mode (-1: not factored or FP64 form) */
+  int32_t schur_chunk[H2_TUNING_MAX_LEVELS]; /* per level l: terms per chunk of split Schur tasks (-1: not factored) */
   double factor_ms;          /* factorization time with the chosen settings */
 } h2_tuning;
 
 /* Autotuner: chooses the stop level (as h2_tune_stop_level, with the default
  * split and flush rules) and then, per factored level, the Schur split
- * threshold among {0, 2048, 8192, 32768, unlimited} and, in the mixed form, the
- * flush mode among {0, 1}, by one factorization per candidate (the candidate
+ * threshold among {0, 2048, 8192, 32768, unlimited}, in the mixed form the
+ * flush mode among {0, 1}, and the terms per chunk of split tasks among
+ * {5, 10, 20}, by one factorization per candidate (the candidate
  * on every level at once; each level keeps the candidate under which its own
  * time was lowest).  The result is stored in a process-wide cache
  * keyed by the cluster tree (every cluster's size), eta, eps, the form, the

@@ -74,7 +74,8 @@ TUNING_MAX_LEVELS = 64
 class Tuning(ctypes.Structure):
     _fields_ = [("stop_level", ctypes.c_int32), ("from_cache", ctypes.c_int32),
                 ("split_below", ctypes.c_int64 * TUNING_MAX_LEVELS),
-                ("mixed_flush", ctypes.c_int32 * TUNING_MAX_LEVELS), ("factor_ms", ctypes.c_double)]
+                ("mixed_flush", ctypes.c_int32 * TUNING_MAX_LEVELS),
+                ("schur_chunk", ctypes.c_int32 * TUNING_MAX_LEVELS), ("factor_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -129,6 +130,7 @@ def lib():
         L.h2_tune_stop_level.argtypes = [_P, ctypes.c_int64, _P, _I32P, _DP, ctypes.c_int32]
         L.h2_set_schur_split.argtypes = [_P, ctypes.c_int32, ctypes.c_int64]
         L.h2_set_mixed_flush.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+        L.h2_set_schur_chunk.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
         L.h2_tune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(Tuning)]
         L.h2_tune_cache_clear.argtypes = []
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
@@ -137,7 +139,8 @@ def lib():
                      "h2_factor_batch_mode", "h2_solve_batch_mode",
                      "h2_solve_batch", "h2_set_kernel_timing", "h2_kernel_ledger", "h2_level_timing",
                      "h2_solve_noalloc", "h2_set_stop_level", "h2_stop_level", "h2_tune_stop_level",
-                     "h2_set_schur_split", "h2_set_mixed_flush", "h2_tune", "h2_tune_cache_clear"):
+                     "h2_set_schur_split", "h2_set_mixed_flush", "h2_set_schur_chunk", "h2_tune",
+                     "h2_tune_cache_clear"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -302,7 +305,14 @@ class H2:
         mflush = {l: int(v) for l, v in enumerate(t.mixed_flush) if v >= 0}
         if mflush:
             out["mixed_flush"] = mflush
+        out["schur_chunk"] = {l: int(v) for l, v in enumerate(t.schur_chunk) if v > 0}
         return out
+
+    def set_schur_chunk(self, terms: int, level: int = -1):
+        """Terms per chunk of split Schur tasks at `level` (-1: every level; terms -1: the
+        default) (h2_set_schur_chunk)."""
+        _check(lib().h2_set_schur_chunk(self._h, int(level), int(terms)), "h2_set_schur_chunk")
+        return self
 
     def set_mixed_flush(self, mode: int, level: int = -1):
         """Mixed form: the Schur flush kernel at `level` (-1: every level): 1 FP32 routing,

@@ -245,7 +245,7 @@ struct ColourPlan {
   std::vector<int32_t> cl, pj_slot, sc_slot, sc_cptr, sc_i, sc_ja, sc_jb, pn_i, pn_ja, sv_cl, sv_cptr, sv_i,
       sv_ja;
   // Schur tasks with many terms are split along the contraction into chunks of at
-  // most SCHUR_CHUNK_TERMS terms: per task {chunk, chunks, chunks of earlier groups,
+  // most SCHUR_CHUNK_TERMS terms (or the level's setting): per task {chunk, chunks, chunks of earlier groups,
   // group} ({-1, 1, 0, 0} when whole); nps chunks and ngrp groups in all
   std::vector<int32_t> sc_sp, sc_gtask;
   std::vector<int32_t> sc_gbase;  // per group, set per factorization: first 64 x 64 partial tile
@@ -406,6 +406,7 @@ struct h2_ctx {
   int stop = -1;                           // last factored level (l0 unless stopped early, Sec. III-C)
   std::vector<int64_t> split_below;        // per level: Schur flush split threshold in workgroups (-1: default)
   std::vector<int32_t> mixed_flush;        // per level, mixed form: 1 FP32-routing flush, 0 FP64 flush, -1 default rule
+  std::vector<int32_t> schur_chunk;        // per level: terms per chunk of a split Schur task (<= 0: SCHUR_CHUNK_TERMS)
   h2::DArr<double2> fb_X, fb_Y;            // early stop: expanded bases and their products with couplings
   h2::DArr<int32_t> fb_n, fb_k, fb_k1, fb_k2, fb_off1;
   h2::DArr<int64_t> fb_toff, fb_xoff;
@@ -539,6 +540,9 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
   // therefore written at most three times per level, with all contributions of
   // an interval summed in one pass.
   std::vector<std::vector<std::array<int32_t, 3>>> pending(P.nslot);
+  // terms per chunk of a split task at this level (h2_set_schur_chunk, h2_tune)
+  const int chunk_terms =
+      (l < (int)H->schur_chunk.size() && H->schur_chunk[l] > 0) ? H->schur_chunk[l] : SCHUR_CHUNK_TERMS;
   auto flush_into = [&](ColourPlan& C, const std::vector<int32_t>& slots) {
     C.sc_slot.clear();
     C.sc_cptr.assign(1, 0);
@@ -555,7 +559,7 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
       auto& pl = pending[s];
       if (pl.empty()) continue;
       const int T = (int)pl.size();
-      const int np = (T + SCHUR_CHUNK_TERMS - 1) / SCHUR_CHUNK_TERMS;
+      const int np = (T + chunk_terms - 1) / chunk_terms;
       for (int ch = 0; ch < np; ++ch) {
         const int t0 = (int)((int64_t)T * ch / np), t1 = (int)((int64_t)T * (ch + 1) / np);
         C.sc_slot.push_back(s);
@@ -2803,6 +2807,51 @@ extern "C" h2_status h2_set_mixed_flush(h2_handle H, int32_t level, int32_t mode
   });
 }
 
+// New chunk sizes change the levels' Schur flush lists: rebuild those plans and
+// every merge plan (which reads the plans of two levels), and upload them.
+static void rebuild_plans(h2_ctx* H, const std::vector<int>& levels, hipStream_t st) {
+  const Structure& S = H->S;
+  if (S.l0 < 0 || levels.empty()) return;
+  for (int l : levels) build_plan_level(H, l, H->plans[S.L - l]);
+  for (int l = S.l0; l <= S.L; ++l)
+    build_merge(H, H->plans[S.L - l], l > H->stop ? &H->plans[S.L - l + 1] : nullptr);
+  for (int l : levels) upload_plan(H->plans[S.L - l], st);
+  H->factored = false;
+}
+
+static void set_chunks(h2_ctx* H, const std::vector<int32_t>& chunk, hipStream_t st) {
+  const Structure& S = H->S;
+  std::vector<int32_t> old = H->schur_chunk;
+  old.resize(S.L + 1, -1);
+  std::vector<int32_t> nw = chunk;
+  nw.resize(S.L + 1, -1);
+  std::vector<int> changed;
+  for (int l = std::max(S.l0, 0); l <= S.L; ++l) {
+    const int a = old[l] > 0 ? old[l] : SCHUR_CHUNK_TERMS, b = nw[l] > 0 ? nw[l] : SCHUR_CHUNK_TERMS;
+    if (a != b) changed.push_back(l);
+  }
+  H->schur_chunk = nw;
+  rebuild_plans(H, changed, st);
+}
+
+extern "C" h2_status h2_set_schur_chunk(h2_handle H, int32_t level, int32_t terms) {
+  return guarded([&] {
+    if (!H) fail(H2_ERR_ARG, "handle is NULL");
+    const Structure& S = H->S;
+    if (level < -1 || level > S.L) fail(H2_ERR_ARG, "level outside [0, L] (or -1 for every level)");
+    if (terms == 0 || terms < -1) fail(H2_ERR_ARG, "terms must be >= 1 (or -1 for the default)");
+    std::vector<int32_t> ch = H->schur_chunk;
+    ch.resize(S.L + 1, -1);
+    if (level < 0)
+      std::fill(ch.begin(), ch.end(), terms);
+    else
+      ch[level] = terms;
+    AllocScope scope(&H->allocator, nullptr);
+    set_chunks(H, ch, nullptr);
+    HIPCHK(hipStreamSynchronize(nullptr));
+  });
+}
+
 // Process-wide cache of measured tunings, keyed by everything the factorization's
 // work depends on: the cluster tree and block structure (sizes of every cluster,
 // eta), the accuracy, the form, forced ranks and the stop-level search bound.
@@ -2810,6 +2859,7 @@ struct TuneRecord {
   int32_t stop;
   std::vector<int64_t> split;
   std::vector<int32_t> mflush;
+  std::vector<int32_t> chunk;
   double ms;
 };
 static std::mutex g_tune_mu;
@@ -2855,6 +2905,7 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
     for (int l = 0; l < H2_TUNING_MAX_LEVELS; ++l) {
       out->split_below[l] = -1;
       out->mixed_flush[l] = -1;
+      out->schur_chunk[l] = -1;
     }
     if (S.L + 1 > H2_TUNING_MAX_LEVELS) fail(H2_ERR_ARG, "tree deeper than H2_TUNING_MAX_LEVELS");
     if (S.l0 < 0) {
@@ -2874,9 +2925,10 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
       }
     }
     if (!cached) {
-      // 1. the stop level, with the default split and flush rules
+      // 1. the stop level, with the default split, flush and chunk rules
       H->split_below.assign(S.L + 1, -1);
       H->mixed_flush.assign(S.L + 1, -1);
+      set_chunks(H, std::vector<int32_t>(S.L + 1, -1), st);
       rec.stop = tune_stop(H, max_final, st, nullptr, 0, nullptr);
       // 2. the split threshold of every factored level: one factorization per candidate
       //    (the same value on every level), each level keeps the candidate under which
@@ -2915,6 +2967,25 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
         }
       }
       H->mixed_flush = rec.mflush;
+      // 4. the terms per chunk of split Schur tasks, chosen the same way (each candidate
+      //    rebuilds the levels' flush lists)
+      {
+        const int32_t cand_chunk[] = {5, SCHUR_CHUNK_TERMS, 20};
+        std::vector<double> bc(nlev, 0.0);
+        rec.chunk.assign(S.L + 1, -1);
+        for (int32_t cterms : cand_chunk) {
+          set_chunks(H, std::vector<int32_t>(S.L + 1, cterms), st);
+          factor_checked(H, st);
+          for (int e = 0; e < nlev && e < (int)H->level_ms.size(); ++e) {
+            const int l = S.L - e;
+            if (rec.chunk[l] < 0 || H->level_ms[e] < bc[e]) {
+              rec.chunk[l] = cterms;
+              bc[e] = H->level_ms[e];
+            }
+          }
+        }
+        set_chunks(H, rec.chunk, st);
+      }
       factor_checked(H, st);
       rec.ms = H->timing[0];
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2923,6 +2994,7 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
       set_stop(H, rec.stop);
       H->split_below = rec.split;
       H->mixed_flush = rec.mflush;
+      set_chunks(H, rec.chunk, st);
       H->factored = false;
       factor_checked(H, st);
     }
@@ -2931,6 +3003,7 @@ extern "C" h2_status h2_tune(h2_handle H, int64_t max_final, void* hip_stream, h
     for (int l = 0; l <= S.L; ++l) {
       out->split_below[l] = rec.split[l];
       out->mixed_flush[l] = rec.mflush[l];
+      out->schur_chunk[l] = rec.chunk[l];
     }
     out->factor_ms = cached ? H->timing[0] : rec.ms;
   });

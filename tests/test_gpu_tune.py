@@ -46,6 +46,8 @@ def test_tune_settings_cache_and_oracle():
         assert S.l0 <= ls <= S.L and G.stop_level() == ls
         assert set(t["split_below"]) == set(range(ls, S.L + 1))
         assert set(t["split_below"].values()) <= CANDIDATES
+        assert set(t["schur_chunk"]) == set(range(ls, S.L + 1))
+        assert set(t["schur_chunk"].values()) <= {5, 10, 20}
         # the same structure again: cached, same settings
         G2 = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr0)
         t2 = G2.tune(max_final=4096)
@@ -61,6 +63,8 @@ def test_tune_settings_cache_and_oracle():
         G3 = h2.H2(pr.points, pr.k, pr.h, pr.chi, pr.leaf, pr.eta, pr.eps, forced_ranks=fr, stop_level=ls)
         for lev, v in t["split_below"].items():
             G3.set_schur_split(v, lev)
+        for lev, v in t["schur_chunk"].items():
+            G3.set_schur_chunk(v, lev)
         G3.factor()
         assert _maxrel(G3.solve(b).cpu().numpy(), O.solve(Fz, pr.rhs)) < 1e-10
         G3.close()
@@ -107,5 +111,12 @@ def test_split_extremes_match_oracle(below):
             G.set_schur_split(-2)
         with pytest.raises(h2.H2Error):
             G.set_schur_split(100, level=99)
+        # split tasks cut into chunks of one and of three terms: the same solution to rounding
+        if below:
+            for terms in (1, 3):
+                G.set_schur_chunk(terms).factor()
+                assert _maxrel(G.solve(b).cpu().numpy(), O.solve(Fz, pr.rhs)) < 1e-10
+            with pytest.raises(h2.H2Error):
+                G.set_schur_chunk(0)
     finally:
         G.close()

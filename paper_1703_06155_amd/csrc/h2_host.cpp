@@ -3314,11 +3314,13 @@ static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
 
 // The fused schedule over up to FUSED_GROUPS groups of problems, each group on a
 // stream of its own driven by its own host thread: the latency-bound stages of one
-// group (Step 0's eigen-solver, the partial LU, the final dense LU) overlap with
-// another group's flushes on the other hardware queues.  Problems are dealt to the
-// groups by size (largest first, in alternating order) so that the groups carry
-// similar work.
-constexpr int FUSED_GROUPS = 4;
+// group (Step 0's eigen-solver, the partial LU, the final dense LU) and its host
+// work between levels overlap with another group's launches.  Problems are dealt
+// to the groups by size (largest first, in alternating order) so that the groups
+// carry similar work.  Two groups measured best for fresh handles (16 boxes:
+// 329 ms against 351, 354 and 367 ms with three, four and eight groups, 421 ms
+// with one).
+constexpr int FUSED_GROUPS = 2;
 
 static void factor_fused_groups(h2_handle* hs, int32_t count, hipStream_t st) {
   const int ng = std::min<int>(FUSED_GROUPS, (count + 1) / 2);

@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <atomic>
+#include <exception>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -451,15 +452,32 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     nearkeys.push_back((int64_t)p.first * nc + p.second);
   }
   P.nnear = (int)P.near_src.size();
+  // Blocks touched by some cluster's Schur update: (a, b), a <= b, both near a
+  // common cluster i.  Near is symmetric, so row a collects N(i) over i in N(a);
+  // the rows come out in order and each row is sorted, so the keys are sorted.
   std::vector<int64_t> keys;
-  keys.reserve(S.near[l].size() * 4);
-  for (int i = 0; i < nc; ++i) {
-    for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
-      for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
-        if (P.np_cl[x] <= P.np_cl[y]) keys.push_back((int64_t)P.np_cl[x] * nc + P.np_cl[y]);
+  {
+    std::vector<char> mark(nc, 0);
+    std::vector<int32_t> row;
+    for (int a = 0; a < nc; ++a) {
+      row.clear();
+      for (int x = P.np_ptr[a]; x < P.np_ptr[a + 1]; ++x) {
+        const int i = P.np_cl[x];
+        for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y) {
+          const int b = P.np_cl[y];
+          if (b >= a && !mark[b]) {
+            mark[b] = 1;
+            row.push_back(b);
+          }
+        }
+      }
+      std::sort(row.begin(), row.end());
+      for (int b : row) {
+        keys.push_back((int64_t)a * nc + b);
+        mark[b] = 0;
+      }
+    }
   }
-  std::sort(keys.begin(), keys.end());
-  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
   // remove near pairs from keys -> fill pairs
   std::vector<int64_t> nearsorted(nearkeys);
   std::sort(nearsorted.begin(), nearsorted.end());
@@ -539,36 +557,58 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
   // are then needed and change coordinates) or the level ends.  Every block is
   // therefore written at most three times per level, with all contributions of
   // an interval summed in one pass.
-  std::vector<std::vector<std::array<int32_t, 3>>> pending(P.nslot);
+  //
+  // A block is processed only by the colours of its two clusters, so a term added
+  // while colour c is eliminated is flushed by the first of those colours after c,
+  // or at the level's end (event ncol, the plan `fin`).  Flush `e` visits its
+  // blocks in slot order and each block's terms in the order they were added
+  // (colour, cluster, then partner pair).  Two passes over the terms: count per
+  // (slot, event), then place.
   // terms per chunk of a split task at this level (h2_set_schur_chunk, h2_tune)
   const int chunk_terms =
       (l < (int)H->schur_chunk.size() && H->schur_chunk[l] > 0) ? H->schur_chunk[l] : SCHUR_CHUNK_TERMS;
-  auto flush_into = [&](ColourPlan& C, const std::vector<int32_t>& slots) {
+  const int ncol = P.ncol;
+  std::vector<int32_t> tc0(P.nslot), tc1(P.nslot);  // the colours processing each slot, ascending
+  for (int s2 = 0; s2 < P.nslot; ++s2) {
+    const int ca = P.colour[P.slot_a[s2]], cb = P.colour[P.slot_b[s2]];
+    tc0[s2] = std::min(ca, cb);
+    tc1[s2] = std::max(ca, cb);
+  }
+  // event of a term added to slot s2 at colour c, as 0/1 (tc0, tc1) or 2 (level end)
+  auto event_of = [&](int s2, int c) -> int { return tc0[s2] > c ? 0 : (tc1[s2] > c ? 1 : 2); };
+  std::vector<int32_t> cnt3((size_t)3 * P.nslot, 0);
+  std::vector<int32_t> term_slot;
+  for (int c = 0; c < ncol; ++c)
+    for (int i : P.cols[c].cl)
+      for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
+        for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
+          if (P.np_cl[x] <= P.np_cl[y]) {
+            const int s2 = P.slot_of(P.np_cl[x], P.np_cl[y]);
+            term_slot.push_back(s2);
+            cnt3[(size_t)3 * s2 + event_of(s2, c)]++;
+          }
+  // task layout of every flush; woff3 = where each (slot, event) run of terms starts
+  std::vector<int32_t> woff3((size_t)3 * P.nslot, 0);
+  auto layout = [&](ColourPlan& C, const std::vector<int32_t>& slots, int ev) {
     C.sc_slot.clear();
     C.sc_cptr.assign(1, 0);
-    C.sc_i.clear();
-    C.sc_ja.clear();
-    C.sc_jb.clear();
     C.sc_sp.clear();
     C.sc_gtask.clear();
     C.nps = C.ngrp = 0;
     C.sc_slot_u.clear();
     C.sc_cptr_u.assign(1, 0);
     C.sc_sp_u.clear();
-    for (int s : slots) {
-      auto& pl = pending[s];
-      if (pl.empty()) continue;
-      const int T = (int)pl.size();
+    int32_t pos = 0;
+    for (int s2 : slots) {
+      const int j = ev < 0 ? 2 : (tc0[s2] == ev ? 0 : 1);
+      const int T = cnt3[(size_t)3 * s2 + j];
+      if (T == 0) continue;
+      woff3[(size_t)3 * s2 + j] = pos;
       const int np = (T + chunk_terms - 1) / chunk_terms;
       for (int ch = 0; ch < np; ++ch) {
-        const int t0 = (int)((int64_t)T * ch / np), t1 = (int)((int64_t)T * (ch + 1) / np);
-        C.sc_slot.push_back(s);
-        for (int x = t0; x < t1; ++x) {
-          C.sc_i.push_back(pl[x][0]);
-          C.sc_ja.push_back(pl[x][1]);
-          C.sc_jb.push_back(pl[x][2]);
-        }
-        C.sc_cptr.push_back((int32_t)C.sc_i.size());
+        const int t1 = (int)((int64_t)T * (ch + 1) / np);
+        C.sc_slot.push_back(s2);
+        C.sc_cptr.push_back(pos + t1);
         if (np == 1) {
           C.sc_sp.insert(C.sc_sp.end(), {-1, 1, 0, 0});
         } else {
@@ -580,27 +620,41 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
         C.nps += np;
         C.ngrp += 1;
       }
-      C.sc_slot_u.push_back(s);
-      C.sc_cptr_u.push_back((int32_t)C.sc_i.size());
+      pos += T;
+      C.sc_slot_u.push_back(s2);
+      C.sc_cptr_u.push_back(pos);
       C.sc_sp_u.insert(C.sc_sp_u.end(), {-1, 1, 0, 0});
-      pl.clear();
-      pl.shrink_to_fit();
     }
+    C.sc_i.assign(pos, 0);
+    C.sc_ja.assign(pos, 0);
+    C.sc_jb.assign(pos, 0);
   };
-  for (int c = 0; c < P.ncol; ++c) {
+  for (int c = 0; c < ncol; ++c) {
     ColourPlan& C = P.cols[c];
     std::vector<int32_t> touched(C.pj_slot.begin(), C.pj_slot.end());
     std::sort(touched.begin(), touched.end());
-    flush_into(C, touched);
-    for (int i : C.cl)
-      for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
-        for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
-          if (P.np_cl[x] <= P.np_cl[y]) pending[P.slot_of(P.np_cl[x], P.np_cl[y])].push_back({i, x, y});
+    layout(C, touched, c);
   }
   {
     std::vector<int32_t> all(P.nslot);
     for (int s2 = 0; s2 < P.nslot; ++s2) all[s2] = s2;
-    flush_into(P.fin, all);
+    layout(P.fin, all, -1);
+  }
+  {
+    size_t q = 0;
+    for (int c = 0; c < ncol; ++c)
+      for (int i : P.cols[c].cl)
+        for (int x = P.np_ptr[i]; x < P.np_ptr[i + 1]; ++x)
+          for (int y = P.np_ptr[i]; y < P.np_ptr[i + 1]; ++y)
+            if (P.np_cl[x] <= P.np_cl[y]) {
+              const int s2 = term_slot[q++];
+              const int j = event_of(s2, c);
+              ColourPlan& C = j == 2 ? P.fin : P.cols[j == 0 ? tc0[s2] : tc1[s2]];
+              const int32_t w = woff3[(size_t)3 * s2 + j]++;
+              C.sc_i[w] = i;
+              C.sc_ja[w] = x;
+              C.sc_jb[w] = y;
+            }
   }
   for (int c = 0; c < P.ncol; ++c) {
     ColourPlan& C = P.cols[c];
@@ -625,6 +679,24 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
     C.sv_cptr.push_back((int32_t)sv.size());
     if (C.sv_cl.empty()) C.sv_cptr.assign(1, 0);
   }
+}
+
+// Plans of several levels, one host thread per level (each writes only its own plan).
+static void build_plan_levels(h2_ctx* H, const std::vector<int>& levels) {
+  std::vector<std::exception_ptr> err(levels.size());
+  std::vector<std::thread> th;
+  th.reserve(levels.size());
+  for (size_t e = 0; e < levels.size(); ++e)
+    th.emplace_back([H, &levels, &err, e] {
+      try {
+        build_plan_level(H, levels[e], H->plans[H->S.L - levels[e]]);
+      } catch (...) {
+        err[e] = std::current_exception();
+      }
+    });
+  for (auto& t : th) t.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 // merge plan from level l (plan P) into level l-1 (plan Pp, or the final block when l == l0).
@@ -2603,7 +2675,9 @@ extern "C" h2_status h2_build(const double* points, int64_t n, double k, double 
       // plans
       H->plans.clear();
       H->plans.resize(L - S.l0 + 1);
-      for (int l = L; l >= S.l0; --l) build_plan_level(H.get(), l, H->plans[L - l]);
+      std::vector<int> levels;
+      for (int l = L; l >= S.l0; --l) levels.push_back(l);
+      build_plan_levels(H.get(), levels);
       int stop = S.l0;
       if (opt && opt->struct_size >= offsetof(h2_options, stop_level) + sizeof(int32_t) && opt->stop_level != 0) {
         if (opt->stop_level < S.l0 || opt->stop_level > L)
@@ -2812,7 +2886,7 @@ extern "C" h2_status h2_set_mixed_flush(h2_handle H, int32_t level, int32_t mode
 static void rebuild_plans(h2_ctx* H, const std::vector<int>& levels, hipStream_t st) {
   const Structure& S = H->S;
   if (S.l0 < 0 || levels.empty()) return;
-  for (int l : levels) build_plan_level(H, l, H->plans[S.L - l]);
+  build_plan_levels(H, levels);
   for (int l = S.l0; l <= S.L; ++l)
     build_merge(H, H->plans[S.L - l], l > H->stop ? &H->plans[S.L - l + 1] : nullptr);
   for (int l : levels) upload_plan(H->plans[S.L - l], st);

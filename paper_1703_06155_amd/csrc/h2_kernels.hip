@@ -159,51 +159,128 @@ void launch_near_blocks(const GeomView& g, const int32_t* pr, const int32_t* pc,
   hipLaunchKernelGGL(k_near_blocks, dim3(npairs), dim3(256), 0, st, g, pr, pc, off, rs, rn, cs, cn, out);
 }
 
+// e^{-jkr} / (4 pi r) from the table tab[m] = (cos, sin)(m pi/128): the phase
+// kr = q pi/128 + f with q the nearest integer (two-part pi/128, so f carries
+// no reduction error beyond one rounding), |f| <= pi/256, cos f and sin f by
+// their Taylor series through f^6 and f^7 (truncation < 2e-21), combined by the
+// angle-addition formulas: the classic table-driven scheme of elementary-function
+// libraries.  The phase kr itself is only known to ~1e-16 kr, which dominates.
+constexpr double PHASE_STEP_HI = 0.02454369260617026;    // pi / 128 rounded to double
+constexpr double PHASE_STEP_LO = 9.567553118338697e-19;  // pi / 128 - PHASE_STEP_HI
+constexpr double PHASE_INV_STEP = 40.74366543152521;     // 128 / pi
+
+__device__ __forceinline__ double2 zfar(double xa, double xb, double xc, double ya, double yb, double yc, double k,
+                                        const double2* tab) {
+  const double dx = xa - ya;
+  const double dy = xb - yb;
+  const double dz = xc - yc;
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  const double ph = k * r;
+  const double q = rint(ph * PHASE_INV_STEP);
+  const double f = fma(-q, PHASE_STEP_LO, fma(-q, PHASE_STEP_HI, ph));
+  const double f2 = f * f;
+  const double sf = f * (1.0 + f2 * (-1.0 / 6.0 + f2 * (1.0 / 120.0 + f2 * (-1.0 / 5040.0))));
+  const double cf = 1.0 + f2 * (-0.5 + f2 * (1.0 / 24.0 + f2 * (-1.0 / 720.0)));
+  const double2 t = tab[(int)q & 255];
+  const double c = t.x * cf - t.y * sf;
+  const double s = t.y * cf + t.x * sf;
+  const double inv = 1.0 / (4.0 * M_PI * r);
+  return make_double2(c * inv, -s * inv);
+}
+
+// Fills tab[0..255] with (cos, sin)(m pi/128); 256 threads.
+__device__ __forceinline__ void phase_table(double2* tab) {
+  const int th = threadIdx.x;
+  double sv, cv;
+  sincos(fma((double)th, PHASE_STEP_HI, (double)th * PHASE_STEP_LO), &sv, &cv);
+  tab[th] = make_double2(cv, sv);
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Leaf far-field Gram G_t = sum_y Zm(t, y) Zm(t, y)^H, split over column chunks.
-// grid: (cluster, tile(2x2), chunk)
+// grid: (cluster, tile(2x2), chunk).  The tile's rows stay in registers; per slab
+// each thread loads one column point and its mask bit, and the next slab's
+// entries are generated while the current one is on the matrix cores.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_leaf_gram(GeomView g, const uint32_t* mask, int level,
                                                    const int64_t* cstart, const int32_t* csize,
                                                    int64_t kchunk, double2* part, int64_t stride,
                                                    const int64_t* goff, int ntr) {
   __shared__ TileSmem<double> s;
+  __shared__ double2 tab[256];
   const int t = blockIdx.x, tile = blockIdx.y, ch = blockIdx.z;
   const int n = csize[t];
   const int tr = tile % ntr, tc = tile / ntr;
   if (tr * 64 >= n || tc * 64 >= n) return;
+  phase_table(tab);
   const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
   const int64_t k_begin = (int64_t)ch * kchunk;
   const int64_t k_end = min(g.N, k_begin + kchunk);
   const int64_t row_a = cstart[t] + tr * 64, row_b = cstart[t] + tc * 64;
+  const int th = threadIdx.x;
+  const int kk = th & 15;
+  const bool diag = tr == tc;
+  const int sh = g.L - level;
+  const int64_t ncl = (int64_t)1 << level;
+  const int64_t cx = (int64_t)(g.leafid[row_a] >> sh);
+  double ra[4][3], rb[4][3];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = (th >> 4) + 16 * e;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      ra[e][d] = i < m ? g.pts[3 * (row_a + i) + d] : 0.0;
+      rb[e][d] = (!diag && i < nn) ? g.pts[3 * (row_b + i) + d] : 0.0;
+    }
+  }
+  double2 v[4], w[4];
+  auto entries = [&](int64_t y, bool far, double ya, double yb, double yc) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = (th >> 4) + 16 * e;
+      v[e] = (far && i < m) ? zfar(ra[e][0], ra[e][1], ra[e][2], ya, yb, yc, g.k, tab) : make_double2(0, 0);
+      if (diag)
+        w[e] = i < nn ? v[e] : make_double2(0, 0);
+      else
+        w[e] = (far && i < nn) ? zfar(rb[e][0], rb[e][1], rb[e][2], ya, yb, yc, g.k, tab) : make_double2(0, 0);
+    }
+  };
+  auto column = [&](int64_t y, bool& far, double& ya, double& yb, double& yc) {
+    far = false;
+    ya = yb = yc = 0.0;
+    if (y < k_end) {
+      far = !near_bit(mask, ncl, cx, (int64_t)(g.leafid[y] >> sh));
+      ya = g.pts[3 * y];
+      yb = g.pts[3 * y + 1];
+      yc = g.pts[3 * y + 2];
+    }
+  };
   TileAcc<double> acc;
   acc.zero();
+  {
+    bool far;
+    double ya, yb, yc;
+    column(k_begin + kk, far, ya, yb, yc);
+    entries(k_begin + kk, far, ya, yb, yc);
+  }
   for (int64_t k0 = k_begin; k0 < k_end; k0 += TK) {
     __syncthreads();
-    {
-      const int th = threadIdx.x;
-      const int kk = th & 15;
-      const int64_t y = k0 + kk;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = (th >> 4) + 16 * e;
-        double2 v = make_double2(0, 0);
-        if (i < m && y < k_end) v = zmasked(g, mask, level, row_a + i, y);
-        s.are[kk][i] = v.x;
-        s.aim[kk][i] = v.y;
-        double2 w = v;
-        if (tr != tc) {
-          w = make_double2(0, 0);
-          if (i < nn && y < k_end) w = zmasked(g, mask, level, row_b + i, y);
-        } else if (i >= nn) {
-          w = make_double2(0, 0);
-        }
-        s.bre[kk][i] = w.x;
-        s.bim[kk][i] = -w.y;
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int i = (th >> 4) + 16 * e;
+      s.are[kk][i] = v[e].x;
+      s.aim[kk][i] = v[e].y;
+      s.bre[kk][i] = w[e].x;
+      s.bim[kk][i] = -w[e].y;
     }
     __syncthreads();
+    const bool more = k0 + TK < k_end;
+    bool far = false;
+    double ya = 0.0, yb = 0.0, yc = 0.0;
+    if (more) column(k0 + TK + kk, far, ya, yb, yc);
     mma_slab_bal<double>(s, acc, TK, (m + 15) >> 4, (nn + 15) >> 4);
+    if (more) entries(k0 + TK + kk, far, ya, yb, yc);
   }
   double2* G = part + (int64_t)ch * stride + goff[t] + tr * 64 + (int64_t)tc * 64 * n;
   store_tile<double, double2>(acc, G, n, m, nn, ST_SET);
@@ -240,6 +317,14 @@ void launch_gram_reduce(const double2* part, double2* out, const int64_t* off, c
 // ---------------------------------------------------------------------------
 // Non-leaf construction rows: Y_c = V_c^H Zm(c, J) for children c (K = #c),
 // written into the stacked row block of the parent.  grid: (child, tiles)
+//
+// Every point of c lies in the same level-`level` cluster, so the far-field
+// mask of a column is fixed for the workgroup: each thread keeps its four
+// columns' coordinates and mask bits in registers, and per slab loads one
+// point's coordinates.  The next slab's V_c^H elements and point are fetched
+// while the current slab is on the matrix cores, and its entries are generated
+// after the MFMAs are issued, so the transcendental work overlaps them.  The
+// slab order and the entry arithmetic are those of zmasked/mma_slab_bal.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_proj_rows(GeomView g, const uint32_t* mask, int level,
                                                    const int64_t* cstart, const int32_t* csize,
@@ -248,6 +333,7 @@ __global__ void __launch_bounds__(256) k_proj_rows(GeomView g, const uint32_t* m
                                                    const int32_t* yld, double2* Y, int64_t col0,
                                                    int ncols, int ntr) {
   __shared__ TileSmem<double> s;
+  __shared__ double2 tab[256];
   const int c = blockIdx.x;
   const int kc = ck[c];
   const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
@@ -257,26 +343,80 @@ __global__ void __launch_bounds__(256) k_proj_rows(GeomView g, const uint32_t* m
   const double2* A = V + voff[c] + (int64_t)tr * 64 * K;  // op C of V_c (#c x k_c, ld #c)
   const int64_t x0 = cstart[c];
   const int64_t y0 = col0 + tc * 64;
+  const int th = threadIdx.x;
+  phase_table(tab);
+  const int kk = th & 15;
+  const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
   TileAcc<double> acc;
   acc.zero();
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    __syncthreads();
-    load_a<double, double2>(s, A, K, OP_C, m, K, k0);
-    {
-      const int th = threadIdx.x;
-      const int kk = th & 15;
-      const int k = k0 + kk;
+  if (K > 0) {
+    const int sh = g.L - level;
+    const int64_t ncl = (int64_t)1 << level;
+    const int64_t cx = (int64_t)(g.leafid[x0] >> sh);
+    double ya[4], yb[4], yc[4];
+    bool far[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int j = (th >> 4) + 16 * e;
-        double2 v = make_double2(0, 0);
-        if (j < nn && k < K) v = zmasked(g, mask, level, x0 + k, y0 + j);
-        s.bre[kk][j] = v.x;
-        s.bim[kk][j] = v.y;
+    for (int e = 0; e < 4; ++e) {
+      const int j = (th >> 4) + 16 * e;
+      far[e] = false;
+      ya[e] = yb[e] = yc[e] = 0.0;
+      if (j < nn) {
+        const int64_t y = y0 + j;
+        far[e] = !near_bit(mask, ncl, cx, (int64_t)(g.leafid[y] >> sh));
+        ya[e] = g.pts[3 * y];
+        yb[e] = g.pts[3 * y + 1];
+        yc[e] = g.pts[3 * y + 2];
       }
     }
-    __syncthreads();
-    mma_slab_bal<double>(s, acc, TK, (m + 15) >> 4, (nn + 15) >> 4);
+    // slab 0 operands
+    double2 a[4], b[4];
+    double xa = 0.0, xb = 0.0, xc = 0.0;
+    bool xin = kk < K;
+    if (xin) {
+      xa = g.pts[3 * (x0 + kk)];
+      xb = g.pts[3 * (x0 + kk) + 1];
+      xc = g.pts[3 * (x0 + kk) + 2];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = (th >> 4) + 16 * e;
+      a[e] = (i < m && kk < K) ? A[kk + (int64_t)i * K] : make_double2(0, 0);
+      b[e] = (far[e] && xin) ? zfar(xa, xb, xc, ya[e], yb[e], yc[e], g.k, tab) : make_double2(0, 0);
+    }
+    for (int k0 = 0; k0 < K; k0 += TK) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = (th >> 4) + 16 * e;
+        s.are[kk][i] = a[e].x;
+        s.aim[kk][i] = -a[e].y;
+        s.bre[kk][i] = b[e].x;
+        s.bim[kk][i] = b[e].y;
+      }
+      __syncthreads();
+      const int k1 = k0 + TK;
+      const bool more = k1 < K;
+      if (more) {
+        const int k = k1 + kk;
+        xin = k < K;
+        if (xin) {
+          xa = g.pts[3 * (x0 + k)];
+          xb = g.pts[3 * (x0 + k) + 1];
+          xc = g.pts[3 * (x0 + k) + 2];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = (th >> 4) + 16 * e;
+          a[e] = (i < m && k < K) ? A[k + (int64_t)i * K] : make_double2(0, 0);
+        }
+      }
+      mma_slab_bal<double>(s, acc, TK, mt, nt);
+      if (more) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          b[e] = (far[e] && xin) ? zfar(xa, xb, xc, ya[e], yb[e], yc[e], g.k, tab) : make_double2(0, 0);
+      }
+    }
   }
   double2* out = Y + yoff[c] + tr * 64 + (int64_t)tc * 64 * yld[c];
   store_tile<double, double2>(acc, out, yld[c], m, nn, ST_SET);

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <atomic>
 #include <exception>
+#include <system_error>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -681,19 +682,26 @@ static void build_plan_level(h2_ctx* H, int l, LevelPlan& P) {
   }
 }
 
-// Plans of several levels, one host thread per level (each writes only its own plan).
+// Plans of several levels, one host thread per level (each writes only its own
+// plan); a level whose thread cannot be started is built on the calling thread.
 static void build_plan_levels(h2_ctx* H, const std::vector<int>& levels) {
   std::vector<std::exception_ptr> err(levels.size());
+  auto work = [H, &levels, &err](size_t e) {
+    try {
+      build_plan_level(H, levels[e], H->plans[H->S.L - levels[e]]);
+    } catch (...) {
+      err[e] = std::current_exception();
+    }
+  };
   std::vector<std::thread> th;
   th.reserve(levels.size());
-  for (size_t e = 0; e < levels.size(); ++e)
-    th.emplace_back([H, &levels, &err, e] {
-      try {
-        build_plan_level(H, levels[e], H->plans[H->S.L - levels[e]]);
-      } catch (...) {
-        err[e] = std::current_exception();
-      }
-    });
+  for (size_t e = 0; e < levels.size(); ++e) {
+    try {
+      th.emplace_back(work, e);
+    } catch (const std::system_error&) {
+      work(e);
+    }
+  }
   for (auto& t : th) t.join();
   for (auto& e : err)
     if (e) std::rethrow_exception(e);

@@ -840,7 +840,9 @@ void launch_householder_perp(const LevelView& v, int nc, hipStream_t st) {
 // k_gram_fill_reduce adds in a fixed order.  Partial j of colour cluster x sits at
 // part + j * pstride + x * (64 tiles)^2.  grid: (cluster, tiles^2, part).  The
 // partners of a part form one K stream with the next slab always in flight, and
-// the tile's 16 x 16 output blocks are dealt evenly to the four wavefronts.
+// the tile's 16 x 16 output blocks are dealt evenly to the four wavefronts.  H_i
+// is Hermitian, so only the blocks on or above the block diagonal are formed and
+// the reduction writes their conjugate transposes below it.
 constexpr int GRAM_RED_BLOCKS = 32;
 
 struct GramTerm {
@@ -876,6 +878,56 @@ __device__ __forceinline__ bool gram_term(const LevelView& v, const ColourTasks&
   return true;
 }
 
+// The 16 x 16 output blocks of a partial Gram tile (tr, tc), tr <= tc, that
+// wavefront w forms: all mt x nt blocks off the tile diagonal, only those on or
+// above the block diagonal (rb <= cb, numbered column by column) on it; dealt to
+// the four wavefronts in contiguous runs.  Block j of the run: (rb[j], cb[j]),
+// rb[j] < 0 past its end.
+__device__ __forceinline__ void gram_blocks(bool tri, int mt, int nt, int rb[4], int cb[4]) {
+  const int w = threadIdx.x >> 6;
+  const int cnt = tri ? mt * (mt + 1) / 2 : mt * nt, per = (cnt + 3) >> 2, k0 = w * per;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int kb = k0 + j;
+    rb[j] = -1;
+    cb[j] = 0;
+    if (j >= per || kb >= cnt) continue;
+    if (tri) {
+      int c = 0;
+      while ((c + 1) * (c + 2) / 2 <= kb) ++c;
+      cb[j] = c;
+      rb[j] = kb - c * (c + 1) / 2;
+    } else {
+      rb[j] = kb % mt;
+      cb[j] = kb / mt;
+    }
+  }
+}
+
+// acc += op(A_tile) op(B_tile) on the given blocks for the first nk k-columns of one slab.
+__device__ __forceinline__ void mma_slab_blocks(const TileSmem<double>& s, TileAcc<double>& acc, int nk,
+                                                const int rb[4], const int cb[4]) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < TK / 4; ++q) {
+    if (q * 4 >= nk) break;
+    const int kk = q * 4 + lk;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (rb[j] < 0) continue;
+      const double ar = s.are[kk][rb[j] * 16 + li], ai = s.aim[kk][rb[j] * 16 + li];
+      const double br = s.bre[kk][cb[j] * 16 + li], bi = s.bim[kk][cb[j] * 16 + li];
+      auto& re = acc.re[j >> 1][j & 1];
+      auto& im = acc.im[j >> 1][j & 1];
+      re = mfma16(br, ar, re);
+      re = mfma16(bi, -ai, re);
+      im = mfma16(br, ai, im);
+      im = mfma16(bi, ar, im);
+    }
+  }
+}
+
 __device__ __forceinline__ void gram_fill_body(const LevelView& v, const ColourTasks& c, double2* part, int64_t pstride,
                                                const VBlock& VB) {
   __shared__ TileSmem<double> s;
@@ -883,9 +935,13 @@ __device__ __forceinline__ void gram_fill_body(const LevelView& v, const ColourT
   const int n = v.n[i];
   const int tr = VB.y % c.tiles, tc = VB.y / c.tiles;
   const int sp = VB.z;
-  if (tr * 64 >= n || tc * 64 >= n) return;
+  // H_i is Hermitian: only tiles on or above the diagonal, and in diagonal tiles
+  // only the blocks on or above the block diagonal; the reduction mirrors the rest
+  if (tr * 64 >= n || tc * 64 >= n || tr > tc) return;
   const int m = min(64, n - tr * 64), nn = min(64, n - tc * 64);
   const int mt = (m + 15) >> 4, nt = (nn + 15) >> 4;
+  int rbs[4], cbs[4];
+  gram_blocks(tr == tc, mt, nt, rbs, cbs);
   TileAcc<double> acc;
   acc.zero();
   const int j_end = v.fp_ptr[i + 1];
@@ -911,15 +967,24 @@ __device__ __forceinline__ void gram_fill_body(const LevelView& v, const ColourT
         more = j < j_end;
       }
       if (more) slab_fetch<double2>(regs, nxt.A, nxt.lda, nxt.opA, nxt.B, nxt.ldb, nxt.opB, m, nn, nxt.K, nk0);
-      mma_slab_bal<double>(s, acc, nk, mt, nt);
+      mma_slab_blocks(s, acc, nk, rbs, cbs);
       if (!more) break;
       cur = nxt;
       k0 = nk0;
     }
   }
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
-  double2* P = part + (int64_t)sp * pstride + (int64_t)VB.x * cstride;
-  store_tile_bal_set<double, double2>(acc, P + tr * 64 + (int64_t)tc * 64 * n, n, m, nn, mt, nt);
+  double2* P = part + (int64_t)sp * pstride + (int64_t)VB.x * cstride + tr * 64 + (int64_t)tc * 64 * n;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (rbs[j] < 0) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = rbs[j] * 16 + (lane & 15), col = cbs[j] * 16 + acc_col<double>(lane, q);
+      if (r < m && col < nn) P[r + (int64_t)col * n] = make_double2(acc.re[j >> 1][j & 1][q], acc.im[j >> 1][j & 1][q]);
+    }
+  }
 }
 __global__ void __launch_bounds__(256) k_gram_fill(LevelView v, ColourTasks c, double2* part, int64_t pstride) {
   gram_fill_body(v, c, part, pstride, vblock());
@@ -931,18 +996,40 @@ __global__ void __launch_bounds__(256) k_gram_fill_b(const BatchEntry* E, int ne
 }
 
 // H_i = sum of the partial Grams in a fixed order (deterministic); grid (cluster,
-// GRAM_RED_BLOCKS) with the entries interleaved over the workgroups
+// GRAM_RED_BLOCKS), each workgroup taking the 16 x 16 blocks on or above the block
+// diagonal in turn (thread (ti, tj): row ti, column tj of the block), writing the
+// block and, off the diagonal, its conjugate transpose through LDS.
 __device__ __forceinline__ void gram_fill_reduce_body(const LevelView& v, const ColourTasks& c, const double2* part,
                                                       int64_t pstride, const VBlock& VB) {
+  __shared__ double2 blk[16][17];
   const int i = c.cl[VB.x];
   const int n = v.n[i];
   double2* H = v.W + v.w_off[i];
   const int64_t cstride = (int64_t)(c.tiles * 64) * (c.tiles * 64);
   const double2* P0 = part + (int64_t)VB.x * cstride;
-  for (int e = VB.y * blockDim.x + threadIdx.x; e < n * n; e += VB.gy * blockDim.x) {
-    double2 a = P0[e];
-    for (int sp = 1; sp < GRAM_SPLIT; ++sp) a = cadd(a, P0[(int64_t)sp * pstride + e]);
-    H[e] = a;
+  const int nb = (n + 15) >> 4, nblk = nb * (nb + 1) / 2;
+  const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
+  for (int kb = VB.y; kb < nblk; kb += VB.gy) {
+    int cb = 0;
+    while ((cb + 1) * (cb + 2) / 2 <= kb) ++cb;
+    const int rb = kb - cb * (cb + 1) / 2;
+    const int r = rb * 16 + ti, q = cb * 16 + tj;
+    double2 a = make_double2(0, 0);
+    if (r < n && q < n) {
+      const int64_t e = r + (int64_t)q * n;
+      a = P0[e];
+      for (int sp = 1; sp < GRAM_SPLIT; ++sp) a = cadd(a, P0[(int64_t)sp * pstride + e]);
+      H[e] = a;
+    }
+    if (rb != cb) {
+      __syncthreads();
+      blk[tj][ti] = a;
+      __syncthreads();
+      // entry (cb*16 + ti, rb*16 + tj) is the conjugate of (rb*16 + tj, cb*16 + ti)
+      const int r2 = cb * 16 + ti, q2 = rb * 16 + tj;
+      const double2 b = blk[ti][tj];
+      if (r2 < n && q2 < n) H[r2 + (int64_t)q2 * n] = make_double2(b.x, -b.y);
+    }
   }
 }
 __global__ void k_gram_fill_reduce(LevelView v, ColourTasks c, const double2* part, int64_t pstride) {

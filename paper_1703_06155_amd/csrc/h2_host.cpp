@@ -2958,6 +2958,8 @@ static uint64_t tuning_key(const h2_ctx* H, int64_t max_final) {
   };
   const Structure& S = H->S;
   mix(&H->N, sizeof(H->N));
+  mix(&H->k, sizeof(H->k));
+  mix(&H->h, sizeof(H->h));
   mix(&H->leaf, sizeof(H->leaf));
   mix(&H->eta, sizeof(H->eta));
   mix(&H->eps, sizeof(H->eps));
@@ -2967,6 +2969,9 @@ static uint64_t tuning_key(const h2_ctx* H, int64_t max_final) {
   mix(&S.l0, sizeof(S.l0));
   for (int l = 0; l <= S.L; ++l)
     if (!S.size[l].empty()) mix(S.size[l].data(), S.size[l].size() * sizeof(S.size[l][0]));
+  // the construction ranks, which (with the sizes) set each level's work
+  for (const BuildLevel& B : H->build)
+    if (!B.k.empty()) mix(B.k.data(), B.k.size() * sizeof(B.k[0]));
   const int32_t hf = H->has_forced ? 1 : 0;
   mix(&hf, sizeof(hf));
   if (H->has_forced) {
@@ -3360,6 +3365,7 @@ static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
   std::atomic<int32_t> next{0};
   std::mutex mu;
   h2_status first = H2_OK;
+  int32_t first_k = INT32_MAX;  // the lowest failing batch index is reported
   std::string first_msg;
   const int workers = std::max(1, std::min<int>(count, 8));
   auto work = [&]() {
@@ -3372,15 +3378,22 @@ static void run_batch(h2_handle* hs, int32_t count, hipStream_t st, Fn&& fn) {
       });
       if (stt != H2_OK) {
         std::lock_guard<std::mutex> lk(mu);
-        if (first == H2_OK) {
+        if (k < first_k) {
           first = stt;
+          first_k = k;
           first_msg = "batch item " + std::to_string(k) + ": " + g_err;
         }
       }
     }
   };
   std::vector<std::thread> pool;
-  for (int w = 1; w < workers; ++w) pool.emplace_back(work);
+  for (int w = 1; w < workers; ++w) {
+    try {
+      pool.emplace_back(work);
+    } catch (const std::system_error&) {
+      break;  // fewer workers: the items are shared through `next`
+    }
+  }
   work();
   for (auto& t : pool) t.join();
   for (int32_t k = 0; k < count; ++k) {
@@ -3441,7 +3454,13 @@ static void factor_fused_groups(h2_handle* hs, int32_t count, hipStream_t st) {
     if (stt[g] != H2_OK) msg[g] = g_err;
   };
   std::vector<std::thread> pool;
-  for (int g = 1; g < ng; ++g) pool.emplace_back(work, g);
+  for (int g = 1; g < ng; ++g) {
+    try {
+      pool.emplace_back(work, g);
+    } catch (const std::system_error&) {
+      work(g);  // no thread: this group runs on the calling thread
+    }
+  }
   work(0);
   for (auto& t : pool) t.join();
   for (int g = 0; g < ng; ++g) {

@@ -329,6 +329,21 @@ const char* h2_last_error(void);
 h2_status h2_structure(const double* points, int64_t n, double h, int32_t leaf, double eta,
                        int64_t* counts, int64_t* perm, int32_t* colours);
 
+/* Host-only query of the deferred Schur updates of one tree level (no device is
+ * touched; Sec. III-A, eq. 12).  Eliminating cluster i updates every block
+ * (a, b) with a and b in i's inadmissible list; the library keeps each update
+ * pending until a or b is next processed or the level ends, and sums a block's
+ * pending updates in one pass.  The updates are written to out as records of four
+ * int64: event, a, b, i (event c < *ncolours: the flush before colour c is
+ * eliminated; event *ncolours: the flush at the level's end; a <= b the block's
+ * clusters, i the eliminated cluster), in flush order and, within a block, in
+ * the order they are summed.  *count receives the number of records and
+ * *ncolours the level's colours.  With out == NULL only those two are written;
+ * H2_ERR_ARG if cap < 4 * records or level lies outside [l0, L] of the tree
+ * h2_structure describes. */
+h2_status h2_schur_schedule(const double* points, int64_t n, double h, int32_t leaf, double eta, int32_t level,
+                            int32_t* ncolours, int64_t* out, int64_t cap, int64_t* count);
+
 /* Per-level statistics after h2_factor, written as rows of int64:
  *   level, clusters, sum n, max n, sum k, max k, sum k~, max k~, min k~, eliminated.
  * rows_cap is the number of rows out can hold; *rows receives the count.

@@ -119,6 +119,8 @@ def lib():
         L.h2_last_error.restype = ctypes.c_char_p
         L.h2_structure.argtypes = [_DP, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double, _I64P,
                                    _I64P, _I32P]
+        L.h2_schur_schedule.argtypes = [_DP, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int32, _I32P, _I64P, ctypes.c_int64, _I64P]
         L.h2_stats.argtypes = [_P, _I64P, ctypes.c_int32, _I32P]
         L.h2_forced_ranks_layout.argtypes = [_P, _I32P, ctypes.c_int64, _I64P]
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
@@ -134,6 +136,7 @@ def lib():
         L.h2_tune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(Tuning)]
         L.h2_tune_cache_clear.argtypes = []
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
+                     "h2_schur_schedule",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
                      "h2_factor_batch_mode", "h2_solve_batch_mode",
@@ -178,6 +181,21 @@ def structure(points, h: float, leaf: int, eta: float) -> dict:
     out["perm"] = perm
     out["colours"] = cols
     return out
+
+
+def schur_schedule(points, h: float, leaf: int, eta: float, level: int) -> tuple:
+    """Host-only deferred Schur updates of one level (no device touched): (number of
+    colours, int64 array of (event, a, b, i) rows in flush order)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    ncol = ctypes.c_int32(0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().h2_schur_schedule(_dptr(pts), n, float(h), int(leaf), float(eta), int(level), ctypes.byref(ncol),
+                                   None, 0, ctypes.byref(cnt)), "h2_schur_schedule")
+    out = np.zeros((int(cnt.value), 4), np.int64)
+    _check(lib().h2_schur_schedule(_dptr(pts), n, float(h), int(leaf), float(eta), int(level), ctypes.byref(ncol),
+                                   out.ctypes.data_as(_I64P), out.size, ctypes.byref(cnt)), "h2_schur_schedule")
+    return int(ncol.value), out
 
 
 def _torch():

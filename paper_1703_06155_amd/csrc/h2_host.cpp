@@ -2582,6 +2582,41 @@ extern "C" h2_status h2_structure(const double* points, int64_t n, double h, int
   });
 }
 
+extern "C" h2_status h2_schur_schedule(const double* points, int64_t n, double h, int32_t leaf, double eta,
+                                       int32_t level, int32_t* ncolours, int64_t* out, int64_t cap, int64_t* count) {
+  return guarded([&] {
+    if (!points || !ncolours || !count) fail(H2_ERR_ARG, "points, ncolours or count is NULL");
+    if (n < 1 || leaf < 1 || !(h > 0) || !(eta >= 0)) fail(H2_ERR_ARG, "invalid size or parameter");
+    std::unique_ptr<h2_ctx> H(new h2_ctx());
+    std::vector<char> msg;
+    if (!build_structure(points, n, h, leaf, eta, H->S, msg)) fail(H2_ERR_ARG, msg.data());
+    const Structure& S = H->S;
+    if (S.l0 < 0 || level < S.l0 || level > S.L) fail(H2_ERR_ARG, "level outside [l0, L]");
+    LevelPlan P;
+    build_plan_level(H.get(), level, P);
+    int64_t terms = (int64_t)P.fin.sc_i.size();
+    for (const ColourPlan& C : P.cols) terms += (int64_t)C.sc_i.size();
+    *ncolours = P.ncol;
+    *count = terms;
+    if (!out) return;
+    if (cap < 4 * terms) fail(H2_ERR_ARG, "cap < 4 * terms");
+    int64_t w = 0;
+    auto emit = [&](const ColourPlan& C, int ev) {
+      for (size_t u = 0; u < C.sc_slot_u.size(); ++u) {
+        const int s2 = C.sc_slot_u[u];
+        for (int32_t q = C.sc_cptr_u[u]; q < C.sc_cptr_u[u + 1]; ++q) {
+          out[w++] = ev;
+          out[w++] = P.slot_a[s2];
+          out[w++] = P.slot_b[s2];
+          out[w++] = C.sc_i[q];
+        }
+      }
+    };
+    for (int c = 0; c < P.ncol; ++c) emit(P.cols[c], c);
+    emit(P.fin, P.ncol);
+  });
+}
+
 // Contrast-dependent device arrays: chi in tree and caller order and the
 // scalings D = diag(k^2 h^3 chi) (matvec) and D^-1 (solve).
 static void upload_contrast(h2_ctx* H, const double* contrast, hipStream_t st) {

@@ -127,16 +127,6 @@ __device__ __forceinline__ bool near_bit(const uint32_t* mask, int64_t nc, int64
   return (mask[bit >> 5] >> (bit & 31)) & 1u;
 }
 
-// Entry of Z masked to the far field at `level`: zero where the level-`level`
-// clusters of x and y form an inadmissible pair.
-__device__ __forceinline__ double2 zmasked(const GeomView& g, const uint32_t* mask, int level, int64_t x,
-                                           int64_t y) {
-  const int sh = g.L - level;
-  const int64_t cx = g.leafid[x] >> sh, cy = g.leafid[y] >> sh;
-  if (near_bit(mask, (int64_t)1 << level, cx, cy)) return make_double2(0.0, 0.0);
-  return zentry(g, x, y);
-}
-
 __global__ void __launch_bounds__(256) k_near_blocks(GeomView g, const int32_t* pr, const int32_t* pc,
                                                      const int64_t* off, const int64_t* rs,
                                                      const int32_t* rn, const int64_t* cs,
@@ -315,7 +305,8 @@ void launch_gram_reduce(const double2* part, double2* out, const int64_t* off, c
 }
 
 // ---------------------------------------------------------------------------
-// Non-leaf construction rows: Y_c = V_c^H Zm(c, J) for children c (K = #c),
+// Non-leaf construction rows: Y_c = V_c^H Zm(c, J) for children c (K = #c, Zm
+// the entries of Z masked to the far field at `level`),
 // written into the stacked row block of the parent.  grid: (child, tiles)
 //
 // Every point of c lies in the same level-`level` cluster, so the far-field
@@ -323,8 +314,9 @@ void launch_gram_reduce(const double2* part, double2* out, const int64_t* off, c
 // columns' coordinates and mask bits in registers, and per slab loads one
 // point's coordinates.  The next slab's V_c^H elements and point are fetched
 // while the current slab is on the matrix cores, and its entries are generated
-// after the MFMAs are issued, so the transcendental work overlaps them.  The
-// slab order and the entry arithmetic are those of zmasked/mma_slab_bal.
+// after the MFMAs are issued, so the transcendental work overlaps them.  A
+// column is masked (zero) where the level-`level` clusters of its point and of
+// c form an inadmissible pair.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_proj_rows(GeomView g, const uint32_t* mask, int level,
                                                    const int64_t* cstart, const int32_t* csize,

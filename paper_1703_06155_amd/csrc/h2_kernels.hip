@@ -188,7 +188,8 @@ __device__ __forceinline__ void phase_table(double2* tab) {
 }
 
 // ---------------------------------------------------------------------------
-// Leaf far-field Gram G_t = sum_y Zm(t, y) Zm(t, y)^H, split over column chunks.
+// Leaf far-field Gram G_t = sum_y Zm(t, y) Zm(t, y)^H (Zm: the entries of Z, zero
+// where the leaf clusters of t and y form an inadmissible pair), split over column chunks.
 // grid: (cluster, tile(2x2), chunk).  The tile's rows stay in registers; per slab
 // each thread loads one column point and its mask bit, and the next slab's
 // entries are generated while the current one is on the matrix cores.

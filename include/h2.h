@@ -344,6 +344,20 @@ h2_status h2_structure(const double* points, int64_t n, double h, int32_t leaf, 
 h2_status h2_schur_schedule(const double* points, int64_t n, double h, int32_t leaf, double eta, int32_t level,
                             int32_t* ncolours, int64_t* out, int64_t cap, int64_t* count);
 
+/* Host-only query of how the blocks of one tree level are merged into the blocks
+ * of its parent level (Sec. III-A, eq. 23; no device is touched).  Each ordered
+ * child pair (a, b) that holds a block (inadmissible, admissible, or filled in by
+ * Schur updates) is written to out as seven int64: parent row cluster, parent
+ * column cluster, ci = a & 1, dj = b & 1 (the child's position in the parent
+ * block), kind (0 inadmissible, 1 admissible, 2 fill-in), a, b.  Parent blocks
+ * are stored for parent row <= parent column, so pairs below the parent diagonal
+ * are not written, except at level l0, whose blocks all go into the final dense
+ * block (parent clusters of level l0 - 1).  *count receives the number of
+ * records; with out == NULL only *count is written; H2_ERR_ARG if cap < 7 *
+ * records or level lies outside [l0, L]. */
+h2_status h2_merge_schedule(const double* points, int64_t n, double h, int32_t leaf, double eta, int32_t level,
+                            int64_t* out, int64_t cap, int64_t* count);
+
 /* Per-level statistics after h2_factor, written as rows of int64:
  *   level, clusters, sum n, max n, sum k, max k, sum k~, max k~, min k~, eliminated.
  * rows_cap is the number of rows out can hold; *rows receives the count.

@@ -121,6 +121,8 @@ def lib():
                                    _I64P, _I32P]
         L.h2_schur_schedule.argtypes = [_DP, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_int32, _I32P, _I64P, ctypes.c_int64, _I64P]
+        L.h2_merge_schedule.argtypes = [_DP, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int32, _I64P, ctypes.c_int64, _I64P]
         L.h2_stats.argtypes = [_P, _I64P, ctypes.c_int32, _I32P]
         L.h2_forced_ranks_layout.argtypes = [_P, _I32P, ctypes.c_int64, _I64P]
         L.h2_factor_timing.argtypes = [_P, _DP, ctypes.c_int32]
@@ -136,7 +138,7 @@ def lib():
         L.h2_tune.argtypes = [_P, ctypes.c_int64, _P, ctypes.POINTER(Tuning)]
         L.h2_tune_cache_clear.argtypes = []
         for name in ("h2_build", "h2_factor", "h2_solve", "h2_solve_adjoint", "h2_matvec", "h2_structure",
-                     "h2_schur_schedule",
+                     "h2_schur_schedule", "h2_merge_schedule",
                      "h2_stats", "h2_forced_ranks_layout", "h2_factor_timing", "h2_contrast_gradient",
                      "h2_set_contrast", "h2_set_precision", "h2_set_sweep_graph", "h2_factor_batch",
                      "h2_factor_batch_mode", "h2_solve_batch_mode",
@@ -196,6 +198,20 @@ def schur_schedule(points, h: float, leaf: int, eta: float, level: int) -> tuple
     _check(lib().h2_schur_schedule(_dptr(pts), n, float(h), int(leaf), float(eta), int(level), ctypes.byref(ncol),
                                    out.ctypes.data_as(_I64P), out.size, ctypes.byref(cnt)), "h2_schur_schedule")
     return int(ncol.value), out
+
+
+def merge_schedule(points, h: float, leaf: int, eta: float, level: int) -> np.ndarray:
+    """Host-only merge of one level's blocks into its parent level (no device touched):
+    int64 rows (parent row, parent column, ci, dj, kind, a, b)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    cnt = ctypes.c_int64(0)
+    _check(lib().h2_merge_schedule(_dptr(pts), n, float(h), int(leaf), float(eta), int(level), None, 0,
+                                   ctypes.byref(cnt)), "h2_merge_schedule")
+    out = np.zeros((int(cnt.value), 7), np.int64)
+    _check(lib().h2_merge_schedule(_dptr(pts), n, float(h), int(leaf), float(eta), int(level),
+                                   out.ctypes.data_as(_I64P), out.size, ctypes.byref(cnt)), "h2_merge_schedule")
+    return out
 
 
 def _torch():

@@ -2617,6 +2617,38 @@ extern "C" h2_status h2_schur_schedule(const double* points, int64_t n, double h
   });
 }
 
+extern "C" h2_status h2_merge_schedule(const double* points, int64_t n, double h, int32_t leaf, double eta,
+                                       int32_t level, int64_t* out, int64_t cap, int64_t* count) {
+  return guarded([&] {
+    if (!points || !count) fail(H2_ERR_ARG, "points or count is NULL");
+    if (n < 1 || leaf < 1 || !(h > 0) || !(eta >= 0)) fail(H2_ERR_ARG, "invalid size or parameter");
+    std::unique_ptr<h2_ctx> H(new h2_ctx());
+    std::vector<char> msg;
+    if (!build_structure(points, n, h, leaf, eta, H->S, msg)) fail(H2_ERR_ARG, msg.data());
+    const Structure& S = H->S;
+    if (S.l0 < 0 || level < S.l0 || level > S.L) fail(H2_ERR_ARG, "level outside [l0, L]");
+    LevelPlan P, Pp;
+    build_plan_level(H.get(), level, P);
+    const bool to_final = level == S.l0;
+    if (!to_final) build_plan_level(H.get(), level - 1, Pp);
+    build_merge(H.get(), P, to_final ? nullptr : &Pp);
+    const int npar = S.nclusters(level - 1);
+    *count = (int64_t)P.merge.size();
+    if (!out) return;
+    if (cap < 7 * *count) fail(H2_ERR_ARG, "cap < 7 * records");
+    int64_t w = 0;
+    for (const MergeSrc& m : P.merge) {
+      out[w++] = to_final ? m.pslot / npar : Pp.slot_a[m.pslot];
+      out[w++] = to_final ? m.pslot % npar : Pp.slot_b[m.pslot];
+      out[w++] = m.ci;
+      out[w++] = m.dj;
+      out[w++] = m.kind;
+      out[w++] = m.ca;
+      out[w++] = m.cb;
+    }
+  });
+}
+
 // Contrast-dependent device arrays: chi in tree and caller order and the
 // scalings D = diag(k^2 h^3 chi) (matvec) and D^-1 (solve).
 static void upload_contrast(h2_ctx* H, const double* contrast, hipStream_t st) {

@@ -356,7 +356,7 @@ def main():
                     help="only run a plain device copy of known size (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration:
